@@ -1,0 +1,218 @@
+/*
+ * mmof.h -- C ABI of the MI355X (gfx950) MMGKS-OF hot-path library.
+ *
+ * The library applies the space-time operators of joint image reconstruction and
+ * motion estimation (Okunola, Pasha, Kilmer, Freitag, "Efficient dynamic image
+ * reconstruction with motion estimation") and runs the alternating
+ * majorization-minimization / generalized-Krylov solve (MMGKS-OF, Alg. 1) on one GPU.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Images are stacks of frames stored [t][y][x] (x fastest), sequences one after
+ *    another ("packed"); a stack is described by mmof_stack.  Frames are 0-based.
+ *  - Flows are [pair][2][y][x] (component 0 = x, 1 = y), one pair per consecutive
+ *    frame pair (t, t+1) of each sequence, pairs packed sequence after sequence.
+ *    The reverse flow s'(t+1) of the paper is stored at the pair index t.
+ *  - Array arguments are DEVICE pointers owned by the caller, contiguous and
+ *    naturally aligned for their dtype.  The library never frees them and does not
+ *    keep them after the call returns (work is enqueued asynchronously on the
+ *    context's stream; the caller keeps buffers alive until the stream reaches it).
+ *  - Host structs and host arrays passed in are copied; the caller keeps ownership.
+ *  - Every entry point returns an int status: 0 = OK, < 0 = error (nothing useful
+ *    was written), > 0 = completed with a warning.  No C++ exception crosses the ABI.
+ *    mmof_last_error() returns the message of the most recent failure.
+ *  - A context is bound to one HIP stream and is not thread-safe; use one context
+ *    per host thread/stream.
+ */
+#ifndef MMOF_H
+#define MMOF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define MMOF_OK 0
+#define MMOF_ERR_INVALID (-1)     /* null pointer, bad enum, bad parameter value     */
+#define MMOF_ERR_SHAPE (-2)       /* inconsistent sizes (stack, plan, capacity)      */
+#define MMOF_ERR_DTYPE (-3)       /* unsupported dtype for this call                 */
+#define MMOF_ERR_HIP (-4)         /* HIP runtime error (launch, copy, device)        */
+#define MMOF_ERR_OOM (-5)         /* device workspace allocation failed              */
+#define MMOF_ERR_NONFINITE (-6)   /* NaN/Inf found in an input that is checked       */
+#define MMOF_WARN_KMAX 1          /* solve: k_max reached before the RRE target      */
+#define MMOF_WARN_DP_CLAMPED 2    /* solve: discrepancy principle clamped lambda     */
+#define MMOF_WARN_BREAKDOWN 3     /* solve: Krylov breakdown (residual vanished)     */
+
+typedef enum { MMOF_F32 = 0, MMOF_F64 = 1 } mmof_dtype;
+
+/* apply_flow_op modes */
+#define MMOF_FLOW_FWD 0   /* out = L(v) u                         (r: [pairs][ny][nx])   */
+#define MMOF_FLOW_ADJ 1   /* out = L(v)^T in                      (u: [frames][ny][nx])  */
+#define MMOF_FLOW_DV 2    /* out = (d (L(v)u) / d v)^T in         (g: [pairs][2][ny][nx]) */
+/* warp interpolation */
+#define MMOF_INTERP_BILINEAR 0
+#define MMOF_INTERP_ROUND 1
+
+typedef struct mmof_ctx_s* mmof_ctx;
+typedef struct mmof_plan_s* mmof_plan;
+
+/* A batch of image sequences (ragged sizes allowed).  Host arrays of n_seq entries. */
+typedef struct {
+    int32_t n_seq;
+    const int32_t* n_t;   /* frames per sequence, >= 1 (flow calls need >= 2) */
+    const int32_t* ny;    /* rows per frame, >= 2                             */
+    const int32_t* nx;    /* columns per frame, >= 2                          */
+} mmof_stack;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*; NULL = the
+ * null stream) on the current HIP device.  The context owns its device workspace,
+ * plan/tile caches and the autotuner cache. */
+int mmof_create(mmof_ctx* out, void* hip_stream);
+int mmof_destroy(mmof_ctx ctx);
+/* Rebind the context to another stream of the same device. */
+int mmof_set_stream(mmof_ctx ctx, void* hip_stream);
+/* Message of the last failure on this host thread ("" if none).  ctx may be NULL. */
+const char* mmof_last_error(mmof_ctx ctx);
+/* Library version string. */
+const char* mmof_version(void);
+
+/* ------------------------------------------------------------------ forward operator H */
+
+/* Plan for the per-frame parallel-beam projector H^t (Sec. 2.1: H = blockdiag(H^t)).
+ * Model: pixel-driven linear ("hat") weights with unit pixels and unit detector bins,
+ *   a_{(theta,j),p} = max(0, 1 - |X_p cos(theta) + Y_p sin(theta) - d_j|),
+ *   X_p = x - (nx-1)/2, Y_p = y - (ny-1)/2, d_j = j - (n_bins-1)/2.
+ * n_angles, n_bins: per sequence (host arrays of n_seq).  angles_rad: host array of
+ * sum_s n_t[s]*n_angles[s] angles, sequence-major then frame-major ([t][k]).
+ * Sinograms are stored [frame][angle][bin], sequences packed. */
+int mmof_plan_radon(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles,
+                    const int32_t* n_bins, const double* angles_rad, mmof_plan* out);
+/* Plan for a per-frame Gaussian blur H^t: K(i,j) = exp(-(i^2+j^2)/(2 sigma^2)) / sum,
+ * |i|,|j| <= ksize/2 (ksize odd, <= 15), zero boundary, output the size of the input.
+ * K is symmetric so H^T applies the same sum. */
+int mmof_plan_blur(mmof_ctx ctx, const mmof_stack* stack, int32_t ksize, double sigma, mmof_plan* out);
+int mmof_plan_destroy(mmof_plan plan);
+/* n = number of pixels, m = number of data entries of the plan's stack. */
+int mmof_plan_sizes(mmof_plan plan, int64_t* n, int64_t* m);
+
+/* b <- H u  (u: n entries, b: m entries, both of dtype dt). */
+int mmof_apply_A(mmof_plan plan, mmof_dtype dt, const void* u, void* b);
+/* u <- H^T b (overwrites u). */
+int mmof_apply_At(mmof_plan plan, mmof_dtype dt, const void* b, void* u);
+
+/* ------------------------------------------------------------------ regularisation operators */
+
+/* Edge-weighted spatial gradient Psi = blockdiag(L), L = [I (x) L_x ; L_y (x) I] with
+ * first differences and no boundary rows (Sec. 4.1, eq. L):
+ *   gx[t][y][x] = wx * (u[t][y][x+1] - u[t][y][x]),  gx: [frames][ny][nx-1]
+ *   gy[t][y][x] = wy * (u[t][y+1][x] - u[t][y][x]),  gy: [frames][ny-1][nx]
+ * transpose = 0: u is read, gx/gy are written.
+ * transpose = 1: gx/gy are read, u <- Psi^T (w (.) g) is written.
+ * wx, wy: optional weights with the layout of gx, gy (NULL = 1). */
+int mmof_apply_grad(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int transpose,
+                    const void* wx, const void* wy, void* u, void* gx, void* gy);
+
+/* Optical-flow temporal operator L(v) ~ d/dt + v.grad, in the warp form of Sec. 3:
+ *   direction +1 (M-bar):  r_t = W(v_t) u_{t+1} - u_t
+ *   direction -1 (M-bar'): r_t = W(v_t) u_t - u_{t+1}      (v = reverse flow s')
+ * for every pair t of every sequence.  W(v) pulls samples at p + v(p): bilinear
+ * weights of the four neighbours with sample coordinates clipped to [0, n-1]
+ * (MMOF_INTERP_BILINEAR), or the nearest pixel, ties to even, clipped
+ * (MMOF_INTERP_ROUND, eq. m_matrix).  L(v) = -M-bar(s) of the paper.
+ *   mode FWD: out (r, [pairs][ny][nx]) <- L(v) u;                     `in` unused
+ *   mode ADJ: out (u, [frames][ny][nx]) <- L(v)^T in (in: r-shaped);  `u` unused
+ *   mode DV : out (g, [pairs][2][ny][nx]) <- (d(L(v)u)/dv)^T in (in: r-shaped);
+ *             per pixel the bilinear-interpolant gradient times in; 0 on clipped
+ *             axes; the cell [floor(x'), floor(x')+1] at integer x'; 0 for ROUND.
+ * The adjoint is a deterministic gather (no atomics): repeated calls are bitwise equal. */
+int mmof_apply_flow_op(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int mode,
+                       int direction, int interp, const void* u, const void* v,
+                       const void* in, void* out);
+
+/* MM weights of Sec. 4.1.1: w2 = diag(P_eps^2) = 1 / sqrt(nu^2 + eps^2), n entries. */
+int mmof_mm_weights(mmof_ctx ctx, mmof_dtype dt, int64_t n, const void* nu, double eps, void* w2);
+
+/* ------------------------------------------------------------------ optical flow */
+
+/* App. C image derivatives for every pair (t, t+1): I [pairs][3][ny][nx] = (I_x, I_y, I_t),
+ *   I_x = 1/(2dr+1) sum_{j=-dr..dr} (u_t(y+j, x+dr) - u_t(y+j, x-dr)) / (2dr),  I_y alike,
+ *   I_t = 1/(2dr+1)^2 sum_box (u_{t+1} - u_t),
+ * with half-sample-symmetric mirroring at the borders; 1 <= delta_r < min(ny, nx). */
+int mmof_of_derivs(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u,
+                   void* I, int32_t delta_r);
+
+/* Horn-Schunck flow update for eq. of_reg with p = q = 2 (gamma = alpha^2):
+ * n_sweeps exact 2x2 block-Jacobi sweeps for
+ *   min sum (I_x s_x + I_y s_y + I_t)^2 + gamma (||D s_x||^2 + ||D s_y||^2),
+ *   s_new = sbar - g (g.sbar + I_t) / (gamma d_p + |g|^2),
+ * warm-started from v (in/out, [pairs][2][ny][nx]).  If v_rev is not NULL it
+ * receives the reverse flow of v (mmof_reverse_flow). */
+int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u,
+                     void* v, void* v_rev, double alpha, int32_t n_sweeps, int32_t delta_r);
+
+/* Reverse flow (Remark on estimating the reverse optical flow): v_rev at
+ * rint(p + v(p)) = -v(p), contributions to one pixel averaged, pixels that receive
+ * none set to 0, targets outside the frame dropped. */
+int mmof_reverse_flow(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* v,
+                      void* v_rev);
+
+/* ------------------------------------------------------------------ joint solve */
+
+typedef struct {
+    int32_t ell;          /* Golub-Kahan start dimension (paper: 10)                     */
+    int32_t k_max;        /* outer MM iterations (ell + k_max - 1 <= 64)                 */
+    int32_t tau;          /* flow update when k % tau == 0                               */
+    int32_t n_sweeps;     /* Horn-Schunck sweeps per flow update                          */
+    int32_t delta_r;      /* derivative box radius                                        */
+    int32_t use_flow;     /* 0: Theta = Psi (method M); 1: Theta = [Psi; M-bar(...)]      */
+    int32_t use_reverse;  /* 1: also M-bar'(s') with s' from the reverse-flow remark      */
+    int32_t interp;       /* MMOF_INTERP_*                                                */
+    int32_t op_dtype;     /* MMOF_F32 or MMOF_F64: precision of operator applications     */
+    int32_t refine_iters; /* with op_dtype F32: last iterations run with F64 operators    */
+    double eps;           /* MM smoothing (reading: 1e-3)                                 */
+    double eta;           /* discrepancy safety factor (reading: 1.01)                    */
+    double alpha;         /* Horn-Schunck alpha (gamma = alpha^2)                         */
+    double fixed_lambda;  /* > 0: use this lambda instead of the discrepancy principle    */
+    double rre_target;    /* > 0 with u_true: stop at the first RRE <= rre_target         */
+    const double* u_true; /* device, n doubles, or NULL                                   */
+} mmof_solve_params;
+
+typedef struct {
+    int32_t iters;        /* outer iterations done                                        */
+    int32_t status;       /* same value as the return code                                */
+    int32_t n_cols;       /* Krylov basis size of the last projected solve                */
+    int32_t capacity;     /* entries available in the host arrays below                   */
+    double* lambda;       /* host [capacity] or NULL: lambda^(k)                          */
+    double* resid;        /* host [capacity] or NULL: ||H u^(k+1) - b||                   */
+    double* rre;          /* host [capacity] or NULL: RRE(u^(k+1)) if u_true given        */
+    int32_t* dp_status;   /* host [capacity] or NULL: 0 root found, 2 clamped             */
+    int64_t n_A, n_At, n_theta, n_thetaT, n_flow_updates;  /* operator application counts */
+} mmof_report;
+
+/* MMGKS-OF (Alg. 1) for min ||H u - b||^2 + lambda ||Theta u||_1 with the flow
+ * re-estimated every tau iterations.  b: device FP64 [m]; noise_norm: ||e|| for the
+ * discrepancy principle; u_inout: device FP64 [n] (initial estimate in, solution out);
+ * v_out, v_rev_out: device flows of dtype op_dtype (either may be NULL); rep may be NULL.
+ * Krylov vectors, Gram matrices, the projected solve and lambda are FP64 on the GPU. */
+int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p,
+                     void* u_inout, void* v_out, void* v_rev_out, mmof_report* rep);
+/* Fill p with the defaults (ell 10, k_max 20, tau 1, 200 sweeps, delta_r 1, flow on,
+ * reverse on, bilinear, F64 operators, eps 1e-3, eta 1.01, alpha 0.1). */
+void mmof_solve_defaults(mmof_solve_params* p);
+
+/* ------------------------------------------------------------------ measurement */
+
+/* Time every launch of the named kernel with HIP events on the context's stream
+ * (name NULL or "" switches timing off).  mmof_kernel_timing returns the number of
+ * timed launches and their summed duration in milliseconds (synchronizes the stream). */
+int mmof_profile_kernel(mmof_ctx ctx, const char* kernel_name);
+int mmof_kernel_timing(mmof_ctx ctx, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMOF_H */

@@ -1,0 +1,375 @@
+"""Thin Python binding of the C ABI: argument marshalling only.
+
+Every function takes torch tensors that already live on the GPU (PyTorch provides
+device memory and streams), checks shapes and dtypes, and calls the entry point of
+the same name in libmmof.so on the current torch stream.  All arithmetic happens in
+the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_DT = {torch.float32: _lib.MMOF_F32, torch.float64: _lib.MMOF_F64}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dt(*ts: torch.Tensor) -> int:
+    dts = {t.dtype for t in ts if t is not None}
+    if len(dts) != 1 or next(iter(dts)) not in _DT:
+        raise TypeError(f"tensors must share one dtype, float32 or float64 (got {dts})")
+    return _DT[next(iter(dts))]
+
+
+def _need(t: torch.Tensor, numel: int, name: str):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+# ----------------------------------------------------------------------------- context
+
+
+class Context:
+    """A library context bound to the current torch stream of one device."""
+
+    def __init__(self, device: Optional[int] = None):
+        self.lib = _lib.load()
+        self.device = torch.cuda.current_device() if device is None else device
+        with torch.cuda.device(self.device):
+            h = C.c_void_p()
+            check(self.lib.mmof_create(C.byref(h), C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        self.h = h
+
+    def bind(self):
+        """Point the context at torch's current stream (call before every launch)."""
+        check(self.lib.mmof_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+        return self.h
+
+    def close(self):
+        if self.h:
+            self.lib.mmof_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # timing of a named kernel with HIP events on the bound stream
+    def profile_kernel(self, name: Optional[str]):
+        check(self.lib.mmof_profile_kernel(self.h, None if not name else name.encode()))
+
+    def kernel_timing(self) -> Tuple[int, float]:
+        n = C.c_int64()
+        ms = C.c_double()
+        check(self.lib.mmof_kernel_timing(self.h, C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+
+_CTX = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    d = torch.cuda.current_device() if device is None else device
+    if d not in _CTX:
+        _CTX[d] = Context(d)
+    return _CTX[d]
+
+
+# ----------------------------------------------------------------------------- stacks
+
+
+@dataclass
+class Stack:
+    """Sizes of a packed batch of sequences: [(n_t, ny, nx), ...]."""
+    sizes: List[Tuple[int, int, int]]
+    _arrs: tuple = field(default=None, repr=False)
+    _s: object = field(default=None, repr=False)
+
+    def __post_init__(self):
+        self.sizes = [tuple(int(v) for v in s) for s in self.sizes]
+        nt = (C.c_int32 * len(self.sizes))(*[s[0] for s in self.sizes])
+        ny = (C.c_int32 * len(self.sizes))(*[s[1] for s in self.sizes])
+        nx = (C.c_int32 * len(self.sizes))(*[s[2] for s in self.sizes])
+        self._arrs = (nt, ny, nx)
+        self._s = _lib.mmof_stack(len(self.sizes), nt, ny, nx)
+
+    @classmethod
+    def single(cls, n_t: int, ny: int, nx: int) -> "Stack":
+        return cls([(n_t, ny, nx)])
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    @property
+    def n(self) -> int:
+        return sum(t * y * x for t, y, x in self.sizes)
+
+    @property
+    def n_pair_px(self) -> int:
+        return sum((t - 1) * y * x for t, y, x in self.sizes)
+
+    @property
+    def n_gx(self) -> int:
+        return sum(t * y * (x - 1) for t, y, x in self.sizes)
+
+    @property
+    def n_gy(self) -> int:
+        return sum(t * (y - 1) * x for t, y, x in self.sizes)
+
+
+# ----------------------------------------------------------------------------- plans
+
+
+class Plan:
+    def __init__(self, h, ctx: Context, stack: Stack, kind: str):
+        self.h = h
+        self.ctx = ctx
+        self.stack = stack
+        self.kind = kind
+        n = C.c_int64()
+        m = C.c_int64()
+        check(ctx.lib.mmof_plan_sizes(h, C.byref(n), C.byref(m)))
+        self.n, self.m = int(n.value), int(m.value)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.mmof_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_radon(stack: Stack, n_angles: Sequence[int], n_bins: Sequence[int], angles_rad: np.ndarray,
+               ctx: Optional[Context] = None) -> Plan:
+    """Parallel-beam projector plan; angles_rad holds sum_s n_t[s]*n_angles[s] radians."""
+    ctx = ctx or context()
+    na = (C.c_int32 * len(n_angles))(*[int(v) for v in n_angles])
+    nb = (C.c_int32 * len(n_bins))(*[int(v) for v in n_bins])
+    ang = np.ascontiguousarray(np.asarray(angles_rad, dtype=np.float64).ravel())
+    want = sum(s[0] * a for s, a in zip(stack.sizes, n_angles))
+    if ang.size != want:
+        raise ValueError(f"angles_rad has {ang.size} entries, expected {want}")
+    h = C.c_void_p()
+    ctx.bind()
+    check(ctx.lib.mmof_plan_radon(ctx.h, stack.ref, na, nb, ang.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+    return Plan(h, ctx, stack, "radon")
+
+
+def plan_blur(stack: Stack, ksize: int = 9, sigma: float = 2.0, ctx: Optional[Context] = None) -> Plan:
+    ctx = ctx or context()
+    h = C.c_void_p()
+    ctx.bind()
+    check(ctx.lib.mmof_plan_blur(ctx.h, stack.ref, int(ksize), float(sigma), C.byref(h)))
+    return Plan(h, ctx, stack, "blur")
+
+
+# ----------------------------------------------------------------------------- operators
+
+
+def apply_A(plan: Plan, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _need(u, plan.n, "u")
+    out = torch.empty(plan.m, dtype=u.dtype, device=u.device) if out is None else out
+    _need(out, plan.m, "out")
+    plan.ctx.bind()
+    check(plan.ctx.lib.mmof_apply_A(plan.h, _dt(u, out), _ptr(u), _ptr(out)))
+    return out
+
+
+def apply_At(plan: Plan, b: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _need(b, plan.m, "b")
+    out = torch.empty(plan.n, dtype=b.dtype, device=b.device) if out is None else out
+    _need(out, plan.n, "out")
+    plan.ctx.bind()
+    check(plan.ctx.lib.mmof_apply_At(plan.h, _dt(b, out), _ptr(b), _ptr(out)))
+    return out
+
+
+def apply_grad(stack: Stack, u: Optional[torch.Tensor] = None, gx: Optional[torch.Tensor] = None,
+               gy: Optional[torch.Tensor] = None, wx=None, wy=None, transpose: bool = False,
+               ctx: Optional[Context] = None):
+    """transpose=False: returns (gx, gy) = w (.) Psi u.  transpose=True: returns Psi^T (w (.) g)."""
+    ctx = ctx or context()
+    ref = u if not transpose else gx
+    if transpose:
+        _need(gx, stack.n_gx, "gx")
+        _need(gy, stack.n_gy, "gy")
+        u = torch.empty(stack.n, dtype=gx.dtype, device=gx.device) if u is None else u
+    else:
+        _need(u, stack.n, "u")
+        gx = torch.empty(stack.n_gx, dtype=u.dtype, device=u.device) if gx is None else gx
+        gy = torch.empty(stack.n_gy, dtype=u.dtype, device=u.device) if gy is None else gy
+    _need(u, stack.n, "u")
+    _need(gx, stack.n_gx, "gx")
+    _need(gy, stack.n_gy, "gy")
+    if wx is not None:
+        _need(wx, stack.n_gx, "wx")
+    if wy is not None:
+        _need(wy, stack.n_gy, "wy")
+    ctx.bind()
+    check(ctx.lib.mmof_apply_grad(ctx.h, stack.ref, _dt(ref, u, gx, gy, wx, wy), int(bool(transpose)), _ptr(wx),
+                                  _ptr(wy), _ptr(u), _ptr(gx), _ptr(gy)))
+    return u if transpose else (gx, gy)
+
+
+def apply_flow_op(stack: Stack, mode: int, direction: int, interp: int, u: Optional[torch.Tensor],
+                  v: torch.Tensor, inp: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                  ctx: Optional[Context] = None) -> torch.Tensor:
+    """mode FWD: L(v) u;  ADJ: L(v)^T inp;  DV: (d(L(v)u)/dv)^T inp."""
+    ctx = ctx or context()
+    P = stack.n_pair_px
+    _need(v, 2 * P, "v")
+    if mode == _lib.MMOF_FLOW_FWD:
+        _need(u, stack.n, "u")
+        n_out = P
+    elif mode == _lib.MMOF_FLOW_ADJ:
+        _need(inp, P, "inp")
+        n_out = stack.n
+    elif mode == _lib.MMOF_FLOW_DV:
+        _need(u, stack.n, "u")
+        _need(inp, P, "inp")
+        n_out = 2 * P
+    else:
+        raise ValueError("bad mode")
+    out = torch.empty(n_out, dtype=v.dtype, device=v.device) if out is None else out
+    _need(out, n_out, "out")
+    ctx.bind()
+    check(ctx.lib.mmof_apply_flow_op(ctx.h, stack.ref, _dt(u, v, inp, out), int(mode), int(direction), int(interp),
+                                     _ptr(u), _ptr(v), _ptr(inp), _ptr(out)))
+    return out
+
+
+def mm_weights(nu: torch.Tensor, eps: float, out: Optional[torch.Tensor] = None,
+               ctx: Optional[Context] = None) -> torch.Tensor:
+    ctx = ctx or context()
+    out = torch.empty_like(nu) if out is None else out
+    _need(nu, nu.numel(), "nu")
+    _need(out, nu.numel(), "out")
+    ctx.bind()
+    check(ctx.lib.mmof_mm_weights(ctx.h, _dt(nu, out), nu.numel(), _ptr(nu), float(eps), _ptr(out)))
+    return out
+
+
+def of_derivs(stack: Stack, u: torch.Tensor, delta_r: int = 1, out: Optional[torch.Tensor] = None,
+              ctx: Optional[Context] = None) -> torch.Tensor:
+    ctx = ctx or context()
+    _need(u, stack.n, "u")
+    out = torch.empty(3 * stack.n_pair_px, dtype=u.dtype, device=u.device) if out is None else out
+    _need(out, 3 * stack.n_pair_px, "out")
+    ctx.bind()
+    check(ctx.lib.mmof_of_derivs(ctx.h, stack.ref, _dt(u, out), _ptr(u), _ptr(out), int(delta_r)))
+    return out
+
+
+def flow_update(stack: Stack, u: torch.Tensor, v: torch.Tensor, alpha: float, n_sweeps: int, delta_r: int = 1,
+                v_rev: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Horn-Schunck sweeps, in place on v; fills v_rev with the reverse flow when given."""
+    ctx = ctx or context()
+    _need(u, stack.n, "u")
+    _need(v, 2 * stack.n_pair_px, "v")
+    if v_rev is not None:
+        _need(v_rev, 2 * stack.n_pair_px, "v_rev")
+    ctx.bind()
+    check(ctx.lib.mmof_flow_update(ctx.h, stack.ref, _dt(u, v, v_rev), _ptr(u), _ptr(v), _ptr(v_rev), float(alpha),
+                                   int(n_sweeps), int(delta_r)))
+    return v
+
+
+def reverse_flow(stack: Stack, v: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 ctx: Optional[Context] = None) -> torch.Tensor:
+    ctx = ctx or context()
+    _need(v, 2 * stack.n_pair_px, "v")
+    out = torch.empty_like(v) if out is None else out
+    _need(out, 2 * stack.n_pair_px, "out")
+    ctx.bind()
+    check(ctx.lib.mmof_reverse_flow(ctx.h, stack.ref, _dt(v, out), _ptr(v), _ptr(out)))
+    return out
+
+
+# ----------------------------------------------------------------------------- solve
+
+
+def solve_params(**kw) -> _lib.mmof_solve_params:
+    p = _lib.mmof_solve_params()
+    _lib.load().mmof_solve_defaults(C.byref(p))
+    for k, val in kw.items():
+        if k == "op_dtype" and isinstance(val, str):
+            val = {"f32": _lib.MMOF_F32, "f64": _lib.MMOF_F64}[val]
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, val)
+    return p
+
+
+@dataclass
+class SolveResult:
+    u: torch.Tensor
+    v: Optional[torch.Tensor]
+    v_rev: Optional[torch.Tensor]
+    status: int
+    iters: int
+    n_cols: int
+    lambdas: List[float]
+    resid: List[float]
+    rre: List[float]
+    dp_status: List[int]
+    counts: dict
+
+
+def solve_joint(plan: Plan, b: torch.Tensor, noise_norm: float, u0: Optional[torch.Tensor] = None,
+                u_true: Optional[torch.Tensor] = None, **params) -> SolveResult:
+    """MMGKS-OF solve; b, u0, u_true are FP64 GPU tensors; params as in mmof_solve_params."""
+    p = solve_params(**params)
+    _need(b, plan.m, "b")
+    if b.dtype != torch.float64:
+        raise TypeError("b must be float64")
+    u = torch.zeros(plan.n, dtype=torch.float64, device=b.device) if u0 is None else u0.clone()
+    _need(u, plan.n, "u0")
+    if u_true is not None:
+        _need(u_true, plan.n, "u_true")
+        if u_true.dtype != torch.float64:
+            raise TypeError("u_true must be float64")
+        p.u_true = u_true.data_ptr()
+    opdt = torch.float32 if p.op_dtype == _lib.MMOF_F32 else torch.float64
+    P = plan.stack.n_pair_px
+    v = torch.zeros(2 * P, dtype=opdt, device=b.device) if (p.use_flow and P) else None
+    vr = torch.zeros(2 * P, dtype=opdt, device=b.device) if (p.use_flow and P) else None
+    cap = max(1, int(p.k_max))
+    lam = (C.c_double * cap)()
+    res = (C.c_double * cap)()
+    rre = (C.c_double * cap)()
+    dps = (C.c_int32 * cap)()
+    rep = _lib.mmof_report()
+    rep.capacity = cap
+    rep.lambda_, rep.resid, rep.rre, rep.dp_status = lam, res, rre, dps
+    plan.ctx.bind()
+    rc = check(plan.ctx.lib.mmof_solve_joint(plan.h, _ptr(b), float(noise_norm), C.byref(p), _ptr(u), _ptr(v),
+                                            _ptr(vr), C.byref(rep)))
+    k = rep.iters
+    return SolveResult(u=u, v=v, v_rev=vr, status=rc, iters=k, n_cols=rep.n_cols, lambdas=list(lam[:k]),
+                       resid=list(res[:k]), rre=list(rre[:k]) if u_true is not None else [],
+                       dp_status=list(dps[:k]),
+                       counts=dict(A=rep.n_A, At=rep.n_At, theta=rep.n_theta, thetaT=rep.n_thetaT,
+                                   flow_updates=rep.n_flow_updates))

@@ -1,0 +1,405 @@
+// extern "C" entry points: argument checks, error translation, dispatch to launchers.
+#include <cmath>
+
+#include "kernels.h"
+#include "krylov.h"
+#include "solver.h"
+
+namespace mmof {
+const char* last_error_cstr();
+void radon_plan_init(Ctx& c, Plan& p);
+}  // namespace mmof
+
+using namespace mmof;
+
+#define MMOF_VERSION_STRING "mmof-gfx950 0.1.0"
+
+template <class F>
+static int guarded(Ctx* c, F&& f) {
+    try {
+        int rc = f();
+        return rc;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        if (c) c->last_error = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        if (c) c->last_error = e.what();
+        return MMOF_ERR_HIP;
+    } catch (...) {
+        set_last_error("unknown error");
+        return MMOF_ERR_HIP;
+    }
+}
+
+static void need(const void* p, const char* what) {
+    MMOF_CHECK(p != nullptr, MMOF_ERR_INVALID, std::string(what) + " is NULL");
+}
+
+static void need_dt(int dt) {
+    MMOF_CHECK(dt == MMOF_F32 || dt == MMOF_F64, MMOF_ERR_DTYPE, "dtype must be MMOF_F32 or MMOF_F64");
+}
+
+extern "C" {
+
+const char* mmof_version(void) { return MMOF_VERSION_STRING; }
+
+const char* mmof_last_error(mmof_ctx ctx) {
+    (void)ctx;
+    return last_error_cstr();
+}
+
+int mmof_create(mmof_ctx* out, void* hip_stream) {
+    return guarded(nullptr, [&] {
+        need(out, "out");
+        *out = nullptr;
+        std::unique_ptr<mmof_ctx_s> c(new mmof_ctx_s());
+        MMOF_HIP(hipGetDevice(&c->device));
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+            c->cu_count = cus;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        *out = c.release();
+        return MMOF_OK;
+    });
+}
+
+int mmof_destroy(mmof_ctx ctx) {
+    return guarded(nullptr, [&] {
+        if (!ctx) return MMOF_OK;
+        (void)hipStreamSynchronize(ctx->stream);
+        delete ctx;
+        return MMOF_OK;
+    });
+}
+
+int mmof_set_stream(mmof_ctx ctx, void* hip_stream) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+        return MMOF_OK;
+    });
+}
+
+// ------------------------------------------------------------------ plans
+
+int mmof_plan_radon(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles, const int32_t* n_bins,
+                    const double* angles_rad, mmof_plan* out) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need(stack, "stack");
+        need(n_angles, "n_angles");
+        need(n_bins, "n_bins");
+        need(angles_rad, "angles_rad");
+        need(out, "out");
+        *out = nullptr;
+        std::unique_ptr<mmof_plan_s> p(new mmof_plan_s());
+        p->ctx = ctx;
+        p->kind = 0;
+        p->geom_own = make_geom(stack, ctx->stream);
+        p->geom = p->geom_own.get();
+        p->n = p->geom->n;
+        int64_t n_trig = 0;
+        for (int s = 0; s < stack->n_seq; ++s) {
+            MMOF_CHECK(n_angles[s] >= 1 && n_bins[s] >= 1, MMOF_ERR_SHAPE, "n_angles and n_bins must be >= 1");
+            p->n_ang.push_back(n_angles[s]);
+            p->n_bins.push_back(n_bins[s]);
+            n_trig += (int64_t)stack->n_t[s] * n_angles[s];
+        }
+        std::vector<double> cs(2 * n_trig);
+        for (int64_t i = 0; i < n_trig; ++i) {
+            MMOF_CHECK(std::isfinite(angles_rad[i]), MMOF_ERR_NONFINITE, "angle is not finite");
+            cs[2 * i] = std::cos(angles_rad[i]);
+            cs[2 * i + 1] = std::sin(angles_rad[i]);
+        }
+        p->d_trig.ensure(sizeof(double) * cs.size());
+        MMOF_HIP(hipMemcpyAsync(p->d_trig.ptr, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice,
+                                ctx->stream));
+        radon_plan_init(*ctx, *p);  // synchronizes the stream
+        *out = p.release();
+        return MMOF_OK;
+    });
+}
+
+int mmof_plan_blur(mmof_ctx ctx, const mmof_stack* stack, int32_t ksize, double sigma, mmof_plan* out) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need(stack, "stack");
+        need(out, "out");
+        *out = nullptr;
+        MMOF_CHECK(ksize >= 1 && ksize <= 15 && (ksize % 2) == 1, MMOF_ERR_INVALID, "ksize must be odd, 1..15");
+        MMOF_CHECK(sigma > 0 && std::isfinite(sigma), MMOF_ERR_INVALID, "sigma must be > 0");
+        std::unique_ptr<mmof_plan_s> p(new mmof_plan_s());
+        p->ctx = ctx;
+        p->kind = 1;
+        p->geom_own = make_geom(stack, ctx->stream);
+        p->geom = p->geom_own.get();
+        p->n = p->geom->n;
+        p->m = p->geom->n;
+        p->ksize = ksize;
+        p->sigma = sigma;
+        const int r = ksize / 2;
+        std::vector<double> k1(ksize);
+        double s = 0.0;
+        for (int i = -r; i <= r; ++i) s += (k1[i + r] = std::exp(-(double)(i * i) / (2.0 * sigma * sigma)));
+        for (auto& v : k1) v /= s;
+        p->d_k1.ensure(sizeof(double) * ksize);
+        MMOF_HIP(hipMemcpyAsync(p->d_k1.ptr, k1.data(), sizeof(double) * ksize, hipMemcpyHostToDevice, ctx->stream));
+        MMOF_HIP(hipStreamSynchronize(ctx->stream));
+        *out = p.release();
+        return MMOF_OK;
+    });
+}
+
+int mmof_plan_destroy(mmof_plan plan) {
+    return guarded(nullptr, [&] {
+        if (!plan) return MMOF_OK;
+        (void)hipStreamSynchronize(plan->ctx->stream);
+        delete plan;
+        return MMOF_OK;
+    });
+}
+
+int mmof_plan_sizes(mmof_plan plan, int64_t* n, int64_t* m) {
+    return guarded(nullptr, [&] {
+        need(plan, "plan");
+        if (n) *n = plan->n;
+        if (m) *m = plan->m;
+        return MMOF_OK;
+    });
+}
+
+int mmof_apply_A(mmof_plan plan, mmof_dtype dt, const void* u, void* b) {
+    return guarded(plan ? plan->ctx : nullptr, [&] {
+        need(plan, "plan");
+        need_dt(dt);
+        need(u, "u");
+        need(b, "b");
+        if (plan->kind == 0)
+            launch_radon_fwd(*plan->ctx, *plan, dt, u, b);
+        else
+            launch_blur(*plan->ctx, *plan, dt, u, b);
+        return MMOF_OK;
+    });
+}
+
+int mmof_apply_At(mmof_plan plan, mmof_dtype dt, const void* b, void* u) {
+    return guarded(plan ? plan->ctx : nullptr, [&] {
+        need(plan, "plan");
+        need_dt(dt);
+        need(u, "u");
+        need(b, "b");
+        if (plan->kind == 0)
+            launch_radon_adj(*plan->ctx, *plan, dt, b, u);
+        else
+            launch_blur(*plan->ctx, *plan, dt, b, u);
+        return MMOF_OK;
+    });
+}
+
+// ------------------------------------------------------------------ regularisation operators
+
+int mmof_apply_grad(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int transpose, const void* wx,
+                    const void* wy, void* u, void* gx, void* gy) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(u, "u");
+        need(gx, "gx");
+        need(gy, "gy");
+        Geom& g = ctx->geom(stack);
+        if (transpose)
+            launch_grad_adj(*ctx, g, dt, gx, gy, wx, wy, u, false);
+        else
+            launch_grad_fwd(*ctx, g, dt, u, wx, wy, gx, gy);
+        return MMOF_OK;
+    });
+}
+
+int mmof_apply_flow_op(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int mode, int direction, int interp,
+                       const void* u, const void* v, const void* in, void* out) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(v, "v");
+        need(out, "out");
+        MMOF_CHECK(direction == 1 || direction == -1, MMOF_ERR_INVALID, "direction must be +1 or -1");
+        MMOF_CHECK(interp == MMOF_INTERP_BILINEAR || interp == MMOF_INTERP_ROUND, MMOF_ERR_INVALID, "bad interp");
+        Geom& g = ctx->geom(stack);
+        MMOF_CHECK(g.n_pairs >= 1, MMOF_ERR_SHAPE, "flow operators need sequences with >= 2 frames");
+        switch (mode) {
+            case MMOF_FLOW_FWD:
+                need(u, "u");
+                launch_flow_fwd(*ctx, g, dt, direction, interp, u, v, out);
+                break;
+            case MMOF_FLOW_ADJ:
+                need(in, "in");
+                launch_flow_adj(*ctx, g, dt, direction, interp, in, v, out, false, nullptr);
+                break;
+            case MMOF_FLOW_DV:
+                need(u, "u");
+                need(in, "in");
+                launch_flow_dv(*ctx, g, dt, direction, interp, u, v, in, out);
+                break;
+            default:
+                throw Error(MMOF_ERR_INVALID, "mode must be MMOF_FLOW_FWD, _ADJ or _DV");
+        }
+        return MMOF_OK;
+    });
+}
+
+int mmof_mm_weights(mmof_ctx ctx, mmof_dtype dt, int64_t n, const void* nu, double eps, void* w2) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        MMOF_CHECK(n >= 0, MMOF_ERR_SHAPE, "n must be >= 0");
+        MMOF_CHECK(eps > 0, MMOF_ERR_INVALID, "eps must be > 0");
+        if (n == 0) return MMOF_OK;
+        need(nu, "nu");
+        need(w2, "w2");
+        launch_mm_weights(*ctx, dt, n, nu, eps, w2);
+        return MMOF_OK;
+    });
+}
+
+// ------------------------------------------------------------------ optical flow
+
+int mmof_of_derivs(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* I, int32_t delta_r) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(u, "u");
+        need(I, "I");
+        Geom& g = ctx->geom(stack);
+        MMOF_CHECK(delta_r >= 1 && delta_r < g.max_nx && delta_r < g.max_ny, MMOF_ERR_INVALID, "bad delta_r");
+        for (int s = 0; s < g.n_seq; ++s)
+            MMOF_CHECK(delta_r < g.nx[s] && delta_r < g.ny[s], MMOF_ERR_INVALID, "delta_r must be < frame size");
+        launch_of_derivs(*ctx, g, dt, u, I, delta_r);
+        return MMOF_OK;
+    });
+}
+
+int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
+                     double alpha, int32_t n_sweeps, int32_t delta_r) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(u, "u");
+        need(v, "v");
+        MMOF_CHECK(alpha > 0 && std::isfinite(alpha), MMOF_ERR_INVALID, "alpha must be > 0");
+        MMOF_CHECK(n_sweeps >= 0, MMOF_ERR_INVALID, "n_sweeps must be >= 0");
+        Geom& g = ctx->geom(stack);
+        for (int s = 0; s < g.n_seq; ++s)
+            MMOF_CHECK(delta_r >= 1 && delta_r < g.nx[s] && delta_r < g.ny[s], MMOF_ERR_INVALID,
+                       "delta_r must be in [1, frame size)");
+        if (g.n_pairs == 0) return MMOF_OK;
+        const size_t es = dt == MMOF_F32 ? 4 : 8;
+        void* I = ctx->work("fu_I", es * 3 * g.pair_px);
+        void* tmp = ctx->work("fu_tmp", es * 2 * g.pair_px);
+        launch_of_derivs(*ctx, g, dt, u, I, delta_r);
+        void* a = v;
+        void* b = tmp;
+        for (int s = 0; s < n_sweeps; ++s) {
+            launch_hs_sweep(*ctx, g, dt, I, a, b, alpha * alpha);
+            std::swap(a, b);
+        }
+        if (a != v) MMOF_HIP(hipMemcpyAsync(v, a, es * 2 * g.pair_px, hipMemcpyDeviceToDevice, ctx->stream));
+        if (v_rev) launch_reverse_flow(*ctx, g, dt, v, v_rev, nullptr);
+        return MMOF_OK;
+    });
+}
+
+int mmof_reverse_flow(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* v, void* v_rev) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(v, "v");
+        need(v_rev, "v_rev");
+        Geom& g = ctx->geom(stack);
+        launch_reverse_flow(*ctx, g, dt, v, v_rev, nullptr);
+        return MMOF_OK;
+    });
+}
+
+// ------------------------------------------------------------------ solve
+
+void mmof_solve_defaults(mmof_solve_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->ell = 10;
+    p->k_max = 20;
+    p->tau = 1;
+    p->n_sweeps = 200;
+    p->delta_r = 1;
+    p->use_flow = 1;
+    p->use_reverse = 1;
+    p->interp = MMOF_INTERP_BILINEAR;
+    p->op_dtype = MMOF_F64;
+    p->refine_iters = 0;
+    p->eps = 1e-3;
+    p->eta = 1.01;
+    p->alpha = 0.1;
+    p->fixed_lambda = 0.0;
+    p->rre_target = 0.0;
+    p->u_true = nullptr;
+}
+
+int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p, void* u_inout,
+                     void* v_out, void* v_rev_out, mmof_report* rep) {
+    return guarded(A ? A->ctx : nullptr, [&] {
+        need(A, "plan");
+        need(b, "b");
+        need(p, "params");
+        need(u_inout, "u_inout");
+        MMOF_CHECK(std::isfinite(noise_norm) && noise_norm >= 0, MMOF_ERR_INVALID, "noise_norm must be >= 0");
+        MMOF_CHECK(p->interp == MMOF_INTERP_BILINEAR || p->interp == MMOF_INTERP_ROUND, MMOF_ERR_INVALID, "bad interp");
+        if (p->use_flow)
+            for (int s = 0; s < A->geom->n_seq; ++s)
+                MMOF_CHECK(p->delta_r >= 1 && p->delta_r < A->geom->nx[s] && p->delta_r < A->geom->ny[s],
+                           MMOF_ERR_INVALID, "delta_r must be in [1, frame size)");
+        int rc = solve_joint(*A, static_cast<const double*>(b), noise_norm, *p, static_cast<double*>(u_inout), v_out,
+                             v_rev_out, rep);
+        if (rep) rep->status = rc;
+        return rc;
+    });
+}
+
+// ------------------------------------------------------------------ measurement
+
+int mmof_profile_kernel(mmof_ctx ctx, const char* kernel_name) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        MMOF_HIP(hipStreamSynchronize(ctx->stream));
+        for (auto& e : ctx->timer.events) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ctx->timer.events.clear();
+        ctx->timer.launches = 0;
+        ctx->timer.total_ms = 0.0;
+        ctx->timer.name = kernel_name ? kernel_name : "";
+        return MMOF_OK;
+    });
+}
+
+int mmof_kernel_timing(mmof_ctx ctx, int64_t* launches, double* total_ms) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        MMOF_HIP(hipStreamSynchronize(ctx->stream));
+        for (auto& e : ctx->timer.events) {
+            float ms = 0.f;
+            MMOF_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+            ctx->timer.total_ms += ms;
+            ctx->timer.launches += 1;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ctx->timer.events.clear();
+        if (launches) *launches = ctx->timer.launches;
+        if (total_ms) *total_ms = ctx->timer.total_ms;
+        return MMOF_OK;
+    });
+}
+
+}  // extern "C"

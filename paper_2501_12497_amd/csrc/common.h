@@ -1,0 +1,210 @@
+// Internal runtime of the MMGKS-OF library: context, geometry, tiles, errors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mmof.h"
+
+namespace mmof {
+
+// ----------------------------------------------------------------------------- errors
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define MMOF_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::mmof::Error(MMOF_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define MMOF_CHECK(cond, code, msg)                      \
+    do {                                                 \
+        if (!(cond)) throw ::mmof::Error((code), (msg)); \
+    } while (0)
+
+// Launch + error check (launch errors are reported synchronously by hipGetLastError).
+#define MMOF_LAUNCH_CHECK() MMOF_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------------------- device tables
+
+// One frame of a packed stack.
+struct FrameInfo {
+    int64_t off;       // pixel offset of the frame in the stack
+    int64_t gx_off;    // offset of its gx block ([ny][nx-1])
+    int64_t gy_off;    // offset of its gy block ([ny-1][nx])
+    int64_t pair_off;  // pixel offset of pair (t, t+1) in pair arrays (valid if t < n_t-1)
+    int32_t ny, nx;
+    int32_t t, n_t;
+    int32_t seq, pad;
+};
+
+// A rectangular work tile of one frame (or one pair: frame = first frame of the pair).
+struct Tile {
+    int32_t frame;
+    int32_t y0, x0;
+    int32_t pad;
+};
+
+// ----------------------------------------------------------------------------- host objects
+
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DeviceBuffer() = default;
+    DeviceBuffer(const DeviceBuffer&) = delete;
+    DeviceBuffer& operator=(const DeviceBuffer&) = delete;
+    ~DeviceBuffer() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    // Grows (never shrinks); contents are not preserved.
+    void* ensure(size_t nbytes) {
+        if (nbytes <= bytes && ptr) return ptr;
+        release();
+        size_t want = nbytes ? nbytes : 256;
+        hipError_t e = hipMalloc(&ptr, want);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            throw Error(MMOF_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        }
+        bytes = want;
+        return ptr;
+    }
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+struct TileList {
+    DeviceBuffer buf;
+    int64_t count = 0;
+};
+
+struct Geom {
+    std::vector<int32_t> n_t, ny, nx;
+    int32_t n_seq = 0;
+    int64_t n = 0;          // pixels
+    int64_t n_frames = 0;
+    int64_t n_pairs = 0;    // frame pairs
+    int64_t pair_px = 0;    // pixels over all pairs
+    int64_t gx_len = 0, gy_len = 0;
+    int32_t max_ny = 0, max_nx = 0;
+    std::vector<FrameInfo> frames;       // host copy
+    std::vector<int64_t> seq_off;        // pixel offset per sequence
+    DeviceBuffer d_frames;               // FrameInfo[n_frames]
+    std::map<uint64_t, std::unique_ptr<TileList>> tiles;  // (tw, th, pairs) -> list
+
+    bool same_as(const mmof_stack& s) const;
+    const TileList& tile_list(hipStream_t st, int tw, int th, bool pairs);
+    const FrameInfo* dframes() const { return d_frames.as<FrameInfo>(); }
+};
+
+std::unique_ptr<Geom> make_geom(const mmof_stack* s, hipStream_t st);
+
+struct KernelTimer {
+    std::string name;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    std::vector<std::unique_ptr<Geom>> geoms;   // small cache keyed by content
+    std::map<std::string, std::unique_ptr<DeviceBuffer>> ws;  // named workspaces
+    KernelTimer timer;
+    int cu_count = 256;
+    void* pinned_buf = nullptr;
+    size_t pinned_bytes = 0;
+    ~Ctx();
+    // Pinned host staging buffer (grows; contents not preserved).
+    void* pinned(size_t bytes);
+
+    Geom& geom(const mmof_stack* s);
+    void* work(const std::string& name, size_t bytes) {
+        auto& p = ws[name];
+        if (!p) p.reset(new DeviceBuffer());
+        return p->ensure(bytes);
+    }
+    // Event-timing hooks around launches of a named kernel.
+    bool timing(const char* kname) const { return !timer.name.empty() && timer.name == kname; }
+    void time_begin(const char* kname, hipEvent_t* ev);
+    void time_end(const char* kname, hipEvent_t ev);
+};
+
+struct Plan {
+    Ctx* ctx = nullptr;
+    int kind = 0;  // 0 radon, 1 blur
+    std::unique_ptr<Geom> geom_own;  // the plan's own copy of its stack geometry
+    Geom* geom = nullptr;
+    int64_t n = 0, m = 0;
+    // radon
+    std::vector<int32_t> n_ang, n_bins;
+    std::vector<int64_t> sino_off;  // per frame, offset of its sinogram
+    DeviceBuffer d_trig;            // float2/double2 per (frame, angle): cos, sin  (double)
+    DeviceBuffer d_rinfo;           // RadonFrame[n_frames]
+    DeviceBuffer d_rays;            // ray tiles of the forward projector
+    DeviceBuffer d_tiles_a;         // pixel tiles of the back-projector
+    DeviceBuffer d_tiles_b;         // 32x32 tiles of the frame transpose
+    int64_t n_rays = 0, n_tiles_a = 0, n_tiles_b = 0;
+    // blur
+    int ksize = 9;
+    double sigma = 2.0;
+    DeviceBuffer d_k1;              // 1-D factor (double) [ksize]
+};
+
+// Scoped kernel timer: records events around a launch when the kernel is selected.
+struct ScopedTime {
+    Ctx* c;
+    const char* name;
+    hipEvent_t ev = nullptr;
+    ScopedTime(Ctx* c_, const char* n) : c(c_), name(n) {
+        if (c->timing(name)) c->time_begin(name, &ev);
+    }
+    ~ScopedTime() {
+        if (ev) c->time_end(name, ev);
+    }
+};
+
+// dtype dispatch helper
+template <class F>
+void dispatch(int dt, F&& f) {
+    if (dt == MMOF_F32)
+        f(float{});
+    else if (dt == MMOF_F64)
+        f(double{});
+    else
+        throw Error(MMOF_ERR_DTYPE, "unsupported dtype " + std::to_string(dt));
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Grid for a 1-D grid-stride launch.
+inline dim3 grid_for(int64_t n, int block, int cap = 65536) {
+    int64_t g = cdiv(n, block);
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return dim3((unsigned)g);
+}
+
+}  // namespace mmof
+
+// The opaque handles of the ABI.
+struct mmof_ctx_s : mmof::Ctx {};
+struct mmof_plan_s : mmof::Plan {};

@@ -1,0 +1,70 @@
+// Device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace mmof {
+
+// Block id -> work item such that consecutive work items land on the same XCD.
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8); this
+// gives XCD x the contiguous range of items [x*q + min(x,r), ...) so neighbouring
+// tiles of one frame share an L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
+    const int64_t q = n >> 3, r = n & 7;
+    const int64_t x = b & 7, s = b >> 3;
+    return x * q + (x < r ? x : r) + s;
+}
+
+// Clipped floor/fraction of the sample coordinate x + v for an integer pixel x:
+// returns x0 in [0, n-1] and f in [0, 1) with x0 + f = clip(x + v, 0, n-1).  The
+// fraction is v - floor(v) (exact in the working precision), so no large-number
+// cancellation enters the bilinear weights.
+template <class T>
+__device__ __forceinline__ void clip_cell(int x, T v, int n, int& x0, T& f, bool& clipped) {
+    v = fmin(fmax(v, T(-1048576)), T(1048576));  // keeps the int conversion defined (NaN -> low bound)
+    T fv = floor(v);
+    int xr = x + (int)fv;
+    f = v - fv;
+    clipped = false;
+    if (xr < 0) {
+        x0 = 0;
+        f = T(0);
+        clipped = true;
+    } else if (xr >= n - 1) {
+        clipped = (xr > n - 1) || (f > T(0));
+        x0 = n - 1;
+        f = T(0);
+    } else {
+        x0 = xr;
+    }
+}
+
+// rint(x + v) (round half to even) for an integer x, computed exactly: the fraction
+// v - floor(v) is exact, and a tie is resolved on the parity of x + floor(v).
+template <class T>
+__device__ __forceinline__ int rint_shift(int x, T v) {
+    v = fmin(fmax(v, T(-1048576)), T(1048576));
+    const T fv = floor(v);
+    const T fr = v - fv;
+    int n = x + (int)fv;
+    if (fr > T(0.5) || (fr == T(0.5) && (n & 1))) ++n;
+    return n;
+}
+
+// Nearest pixel (ties to even) of x + v, clipped into [0, n-1].
+template <class T>
+__device__ __forceinline__ int round_clip(int x, T v, int n) {
+    const int r = rint_shift(x, v);
+    return r < 0 ? 0 : (r > n - 1 ? n - 1 : r);
+}
+
+// Half-sample-symmetric mirror of an index into [0, n): -1 -> 0, n -> n-1.
+__device__ __forceinline__ int mirror(int i, int n) {
+    if (i < 0) i = -i - 1;
+    if (i >= n) i = 2 * n - i - 1;
+    return i;
+}
+
+}  // namespace mmof

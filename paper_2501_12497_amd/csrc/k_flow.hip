@@ -1,0 +1,308 @@
+// The optical-flow temporal operator L(v) of the image subproblem, in warp form:
+//   direction +1:  r_t = W(v_t) u_{t+1} - u_t      (-M-bar(s), Sec. 3)
+//   direction -1:  r_t = W(v_t) u_t - u_{t+1}      (-M-bar'(s'))
+// W(v) pulls a bilinear (or nearest, ties to even) sample at p + v(p) with clipped
+// coordinates.  The adjoint scatters through the bilinear weights; here it is a
+// deterministic gather: every output pixel sums, in a fixed order, the sources whose
+// sample cell touches it.  Sources are staged in LDS per output tile together with the
+// range of their integer displacements, so a pixel only visits the (dmax-dmin+2)^2
+// sources that can reach it.
+#include <climits>
+
+#include "dev.h"
+#include "kernels.h"
+
+namespace mmof {
+
+static constexpr int FTW = 64, FTH = 4;          // forward / dv tiles
+static constexpr int ATX = 32, ATY = 8;          // adjoint tiles
+static constexpr int RMAX = 8;                   // LDS path handles radius <= RMAX
+static constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);
+
+// Bilinear (INTERP 0) or nearest (INTERP 1) sample of src at (x + vx, y + vy).
+template <class T, int INTERP>
+__device__ __forceinline__ T warp_sample(const T* __restrict__ src, int nx, int ny, int x, int y, T vx, T vy) {
+    if (INTERP == 1) {
+        const int xr = round_clip(x, vx, nx), yr = round_clip(y, vy, ny);
+        return src[(int64_t)yr * nx + xr];
+    }
+    int x0, y0;
+    T fx, fy;
+    bool cx, cy;
+    clip_cell(x, vx, nx, x0, fx, cx);
+    clip_cell(y, vy, ny, y0, fy, cy);
+    const int x1 = min(x0 + 1, nx - 1), y1 = min(y0 + 1, ny - 1);
+    const T* r0 = src + (int64_t)y0 * nx;
+    const T* r1 = src + (int64_t)y1 * nx;
+    return (T(1) - fx) * (T(1) - fy) * r0[x0] + fx * (T(1) - fy) * r0[x1] + (T(1) - fx) * fy * r1[x0] +
+           fx * fy * r1[x1];
+}
+
+template <class T, int INTERP>
+__global__ __launch_bounds__(256) void k_flow_fwd(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                  const T* __restrict__ u, const T* __restrict__ v,
+                                                  T* __restrict__ r, int direction) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + (int)(threadIdx.x % FTW);
+    const int y = tl.y0 + (int)(threadIdx.x / FTW);
+    if (x >= f.nx || y >= f.ny) return;
+    const int64_t np = (int64_t)f.nx * f.ny;
+    const int64_t p = (int64_t)y * f.nx + x;
+    const T* ut = u + f.off;
+    const T* ut1 = ut + np;
+    const T* vx = v + 2 * f.pair_off;
+    const T vxx = vx[p], vyy = vx[np + p];
+    const T* src = direction > 0 ? ut1 : ut;
+    const T* sub = direction > 0 ? ut : ut1;
+    r[f.pair_off + p] = warp_sample<T, INTERP>(src, f.nx, f.ny, x, y, vxx, vyy) - sub[p];
+}
+
+// Cell of a source pixel: clipped floor coordinates and fractions (0 for INTERP 1).
+template <class T, int INTERP>
+__device__ __forceinline__ void source_cell(int sx, int sy, T vx, T vy, int nx, int ny, int& x0, int& y0, T& fx,
+                                            T& fy) {
+    if (INTERP == 1) {
+        x0 = round_clip(sx, vx, nx);
+        y0 = round_clip(sy, vy, ny);
+        fx = T(0);
+        fy = T(0);
+    } else {
+        bool c;
+        clip_cell(sx, vx, nx, x0, fx, c);
+        clip_cell(sy, vy, ny, y0, fy, c);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ bool corner_weight(int c0, T f, int q, T& w) {
+    if (c0 == q) {
+        w = T(1) - f;
+        return true;
+    }
+    if (c0 + 1 == q) {
+        w = f;
+        return true;
+    }
+    return false;
+}
+
+template <class T, int INTERP>
+__global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                  const T* __restrict__ r, const T* __restrict__ v,
+                                                  T* __restrict__ u, int direction, int accumulate,
+                                                  const int32_t* __restrict__ d_radius) {
+    __shared__ int s_x0[SMAX], s_y0[SMAX];
+    __shared__ T s_fx[SMAX], s_fy[SMAX], s_val[SMAX];
+    __shared__ int s_d[4];  // dmin_x, dmax_x, dmin_y, dmax_y
+
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int64_t fi = tl.frame;
+    const FrameInfo f = fr[fi];
+    const int nx = f.nx, ny = f.ny;
+    const int64_t np = (int64_t)nx * ny;
+    const int qx = tl.x0 + (int)(threadIdx.x % ATX);
+    const int qy = tl.y0 + (int)(threadIdx.x / ATX);
+    const bool inside = qx < nx && qy < ny;
+    const int64_t q = (int64_t)qy * nx + qx;
+
+    // direct term and the pair whose warp gathers into this frame
+    T direct = T(0);
+    int64_t gp = -1;  // pair offset of the gathering pair
+    if (direction > 0) {
+        if (f.t + 1 < f.n_t && inside) direct = -r[f.pair_off + q];
+        if (f.t >= 1) gp = fr[fi - 1].pair_off;
+    } else {
+        if (f.t >= 1 && inside) direct = -r[fr[fi - 1].pair_off + q];
+        if (f.t + 1 < f.n_t) gp = f.pair_off;
+    }
+
+    T acc = T(0);
+    if (gp >= 0) {
+        const T* rg = r + gp;
+        const T* vxg = v + 2 * gp;
+        const T* vyg = vxg + np;
+        const int R = *d_radius;
+        if (R <= RMAX) {
+            const int sx0 = max(tl.x0 - R, 0), sx1 = min(tl.x0 + ATX - 1 + R, nx - 1);
+            const int sy0 = max(tl.y0 - R, 0), sy1 = min(tl.y0 + ATY - 1 + R, ny - 1);
+            const int sw = sx1 - sx0 + 1, sh = sy1 - sy0 + 1;
+            if (threadIdx.x == 0) {
+                s_d[0] = INT_MAX;
+                s_d[1] = INT_MIN;
+                s_d[2] = INT_MAX;
+                s_d[3] = INT_MIN;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < sw * sh; i += 256) {
+                const int sy = sy0 + i / sw, sx = sx0 + i % sw;
+                const int64_t p = (int64_t)sy * nx + sx;
+                int x0, y0;
+                T fx, fy;
+                source_cell<T, INTERP>(sx, sy, vxg[p], vyg[p], nx, ny, x0, y0, fx, fy);
+                s_x0[i] = x0;
+                s_y0[i] = y0;
+                s_fx[i] = fx;
+                s_fy[i] = fy;
+                s_val[i] = rg[p];
+                if (x0 >= tl.x0 - 1 && x0 <= tl.x0 + ATX - 1 && y0 >= tl.y0 - 1 && y0 <= tl.y0 + ATY - 1) {
+                    atomicMin(&s_d[0], x0 - sx);
+                    atomicMax(&s_d[1], x0 - sx);
+                    atomicMin(&s_d[2], y0 - sy);
+                    atomicMax(&s_d[3], y0 - sy);
+                }
+            }
+            __syncthreads();
+            if (inside && s_d[0] <= s_d[1]) {
+                const int px_lo = max(qx - 1 - s_d[1], sx0), px_hi = min(qx - s_d[0], sx1);
+                const int py_lo = max(qy - 1 - s_d[3], sy0), py_hi = min(qy - s_d[2], sy1);
+                for (int py = py_lo; py <= py_hi; ++py) {
+                    const int row = (py - sy0) * sw - sx0;
+                    for (int px = px_lo; px <= px_hi; ++px) {
+                        const int i = row + px;
+                        T wx, wy;
+                        if (!corner_weight(s_x0[i], s_fx[i], qx, wx)) continue;
+                        if (!corner_weight(s_y0[i], s_fy[i], qy, wy)) continue;
+                        acc += wx * wy * s_val[i];
+                    }
+                }
+            }
+        } else if (inside) {
+            // Large displacements: scan the full window in global memory (same order).
+            const int py_lo = max(qy - R, 0), py_hi = min(qy + R, ny - 1);
+            const int px_lo = max(qx - R, 0), px_hi = min(qx + R, nx - 1);
+            for (int py = py_lo; py <= py_hi; ++py)
+                for (int px = px_lo; px <= px_hi; ++px) {
+                    const int64_t p = (int64_t)py * nx + px;
+                    int x0, y0;
+                    T fx, fy;
+                    source_cell<T, INTERP>(px, py, vxg[p], vyg[p], nx, ny, x0, y0, fx, fy);
+                    T wx, wy;
+                    if (!corner_weight(x0, fx, qx, wx)) continue;
+                    if (!corner_weight(y0, fy, qy, wy)) continue;
+                    acc += wx * wy * rg[p];
+                }
+        }
+    }
+    if (!inside) return;
+    T* uo = u + f.off + q;
+    const T val = acc + direct;
+    *uo = accumulate ? *uo + val : val;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_flow_dv(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                 const T* __restrict__ u, const T* __restrict__ v,
+                                                 const T* __restrict__ w, T* __restrict__ gv, int direction) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + (int)(threadIdx.x % FTW);
+    const int y = tl.y0 + (int)(threadIdx.x / FTW);
+    if (x >= f.nx || y >= f.ny) return;
+    const int nx = f.nx, ny = f.ny;
+    const int64_t np = (int64_t)nx * ny;
+    const int64_t p = (int64_t)y * nx + x;
+    const T* src = u + f.off + (direction > 0 ? np : 0);
+    const T* vv = v + 2 * f.pair_off;
+    int x0, y0;
+    T fx, fy;
+    bool cx, cy;
+    clip_cell(x, vv[p], nx, x0, fx, cx);
+    clip_cell(y, vv[np + p], ny, y0, fy, cy);
+    const int x1 = min(x0 + 1, nx - 1), y1 = min(y0 + 1, ny - 1);
+    const T s00 = src[(int64_t)y0 * nx + x0], s01 = src[(int64_t)y0 * nx + x1];
+    const T s10 = src[(int64_t)y1 * nx + x0], s11 = src[(int64_t)y1 * nx + x1];
+    const T ww = w[f.pair_off + p];
+    T dx = (T(1) - fy) * (s01 - s00) + fy * (s11 - s10);
+    T dy = (T(1) - fx) * (s10 - s00) + fx * (s11 - s01);
+    if (cx) dx = T(0);
+    if (cy) dy = T(0);
+    gv[2 * f.pair_off + p] = ww * dx;
+    gv[2 * f.pair_off + np + p] = ww * dy;
+}
+
+template <class T>
+__global__ void k_flow_radius(const T* __restrict__ v, int64_t n, int32_t* __restrict__ out) {
+    T m = T(0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        T a = fabs(v[i]);
+        m = (a > m || a != a) ? (a != a ? T(1e30) : a) : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) {
+        const T c = fmin(floor(m), T(1 << 20));
+        atomicMax(out, (int32_t)c + 1);
+    }
+}
+
+__global__ void k_set_int(int32_t* p, int32_t val) { *p = val; }
+
+void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, c.stream, d_out, 1);
+    MMOF_LAUNCH_CHECK();
+    const int64_t n = 2 * g.pair_px;
+    if (n == 0) return;
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        hipLaunchKernelGGL(k_flow_radius<T>, grid_for(n, 256, 2048), dim3(256), 0, c.stream, (const T*)v, n, d_out);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r) {
+    if (g.n_pairs == 0) return;
+    const TileList& tl = g.tile_list(c.stream, FTW, FTH, true);
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        ScopedTime st(&c, "flow_fwd");
+        auto k = interp == MMOF_INTERP_ROUND ? k_flow_fwd<T, 1> : k_flow_fwd<T, 0>;
+        hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
+                           (const T*)u, (const T*)v, (T*)r, direction);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const void* r, const void* v, void* u,
+                     bool accumulate, const int32_t* d_radius) {
+    int32_t* rad = const_cast<int32_t*>(d_radius);
+    if (!rad) {
+        rad = static_cast<int32_t*>(c.work("flow_radius", 256));
+        launch_flow_radius(c, g, dt, v, rad);
+    }
+    const TileList& tl = g.tile_list(c.stream, ATX, ATY, false);
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        ScopedTime st(&c, "flow_adj");
+        auto k = interp == MMOF_INTERP_ROUND ? k_flow_adj<T, 1> : k_flow_adj<T, 0>;
+        hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
+                           (const T*)r, (const T*)v, (T*)u, direction, accumulate ? 1 : 0, rad);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+template <class T>
+__global__ void k_zero(T* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
+}
+
+void launch_flow_dv(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v,
+                    const void* w, void* gv) {
+    if (g.n_pairs == 0) return;
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        if (interp == MMOF_INTERP_ROUND) {  // piecewise-constant warp: zero derivative
+            hipLaunchKernelGGL(k_zero<T>, grid_for(2 * g.pair_px, 256), dim3(256), 0, c.stream, (T*)gv,
+                               2 * g.pair_px);
+            MMOF_LAUNCH_CHECK();
+            return;
+        }
+        const TileList& tl = g.tile_list(c.stream, FTW, FTH, true);
+        ScopedTime st(&c, "flow_dv");
+        hipLaunchKernelGGL(k_flow_dv<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                           g.dframes(), (const T*)u, (const T*)v, (const T*)w, (T*)gv, direction);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+}  // namespace mmof

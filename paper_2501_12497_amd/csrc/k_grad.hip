@@ -1,0 +1,92 @@
+// Psi = blockdiag(L), L = [I (x) L_x ; L_y (x) I] (first differences, no boundary rows),
+// optionally weighted row by row, and its transpose.  One pixel per thread over
+// 64x4 tiles of every frame in the packed stack.
+#include "dev.h"
+#include "kernels.h"
+
+namespace mmof {
+
+static constexpr int GTW = 64, GTH = 4;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_grad_fwd(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                  const T* __restrict__ u, const T* __restrict__ wx,
+                                                  const T* __restrict__ wy, T* __restrict__ gx, T* __restrict__ gy) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + (int)(threadIdx.x % GTW);
+    const int y = tl.y0 + (int)(threadIdx.x / GTW);
+    if (x >= f.nx || y >= f.ny) return;
+    const T* uf = u + f.off;
+    const int64_t p = (int64_t)y * f.nx + x;
+    const T c = uf[p];
+    if (x < f.nx - 1) {
+        const int64_t o = f.gx_off + (int64_t)y * (f.nx - 1) + x;
+        T d = uf[p + 1] - c;
+        gx[o] = wx ? wx[o] * d : d;
+    }
+    if (y < f.ny - 1) {
+        const int64_t o = f.gy_off + p;
+        T d = uf[p + f.nx] - c;
+        gy[o] = wy ? wy[o] * d : d;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_grad_adj(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                  const T* __restrict__ gx, const T* __restrict__ gy,
+                                                  const T* __restrict__ wx, const T* __restrict__ wy,
+                                                  T* __restrict__ u, int accumulate) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + (int)(threadIdx.x % GTW);
+    const int y = tl.y0 + (int)(threadIdx.x / GTW);
+    if (x >= f.nx || y >= f.ny) return;
+    const int64_t rx = f.gx_off + (int64_t)y * (f.nx - 1);  // row y of gx
+    const int64_t ry = f.gy_off;
+    T acc = T(0);
+    if (x > 0) {
+        const int64_t o = rx + x - 1;
+        acc += wx ? wx[o] * gx[o] : gx[o];
+    }
+    if (x < f.nx - 1) {
+        const int64_t o = rx + x;
+        acc -= wx ? wx[o] * gx[o] : gx[o];
+    }
+    if (y > 0) {
+        const int64_t o = ry + (int64_t)(y - 1) * f.nx + x;
+        acc += wy ? wy[o] * gy[o] : gy[o];
+    }
+    if (y < f.ny - 1) {
+        const int64_t o = ry + (int64_t)y * f.nx + x;
+        acc -= wy ? wy[o] * gy[o] : gy[o];
+    }
+    const int64_t p = f.off + (int64_t)y * f.nx + x;
+    u[p] = accumulate ? u[p] + acc : acc;
+}
+
+void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy) {
+    const TileList& tl = g.tile_list(c.stream, GTW, GTH, false);
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        ScopedTime st(&c, "grad_fwd");
+        hipLaunchKernelGGL(k_grad_fwd<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                           g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx, (T*)gy);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+void launch_grad_adj(Ctx& c, Geom& g, int dt, const void* gx, const void* gy, const void* wx, const void* wy,
+                     void* u, bool accumulate) {
+    const TileList& tl = g.tile_list(c.stream, GTW, GTH, false);
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        ScopedTime st(&c, "grad_adj");
+        hipLaunchKernelGGL(k_grad_adj<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                           g.dframes(), (const T*)gx, (const T*)gy, (const T*)wx, (const T*)wy, (T*)u,
+                           accumulate ? 1 : 0);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+}  // namespace mmof

@@ -1,0 +1,351 @@
+// MMGKS-OF driver (Alg. 1): flow update every tau iterations, MM weights, projected
+// Gram matrices, discrepancy-principle lambda, u = V z, residual of the weighted normal
+// equations, CGS2 against V, subspace growth.  All work runs on the context's stream;
+// the host reads back one small report per iteration.
+//
+// Precision: operator applications (H, H^T, Theta, Theta^T, flow update) run in TX
+// (float or double); the Krylov basis V, the Golub-Kahan start, all inner products,
+// the Gram matrices, the projected solve and lambda are FP64.  H V and Theta V are kept
+// in TX (they are operator outputs) and are accumulated in FP64.
+//
+// Theta = [Psi; M-bar(v); M-bar'(v')] is stored row block after row block:
+// [gx (all frames) | gy (all frames) | forward flow rows | reverse flow rows].
+#include <cmath>
+#include <type_traits>
+
+#include "kernels.h"
+#include "krylov.h"
+#include "solver.h"
+
+namespace mmof {
+
+template <class TX>
+struct Solver {
+    Ctx& c;
+    Plan& P;
+    Geom& g;
+    const mmof_solve_params& p;
+    int dt;
+    int64_t n, m, R, oGX, oGY, oRF, oRR;
+    int Kcap;
+    bool flow;
+    mmof_report* rep;
+
+    // workspace
+    double *V, *U, *r, *tmp_n, *tmp_m, *GA, *GT, *dvec, *z, *h, *sc, *res, *scal;
+    TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *flow_v, *flow_vr, *flow_tmp, *I;
+    int32_t *rad_v, *rad_vr;
+    double* host;  // pinned report staging
+
+    Solver(Ctx& c_, Plan& P_, const mmof_solve_params& p_, mmof_report* rep_)
+        : c(c_), P(P_), g(*P_.geom), p(p_), rep(rep_) {
+        dt = std::is_same<TX, float>::value ? MMOF_F32 : MMOF_F64;
+        n = P.n;
+        m = P.m;
+        flow = p.use_flow != 0;
+        oGX = 0;
+        oGY = g.gx_len;
+        oRF = g.gx_len + g.gy_len;
+        oRR = oRF + (flow ? g.pair_px : 0);
+        R = oRR + ((flow && p.use_reverse) ? g.pair_px : 0);
+        Kcap = p.ell + p.k_max - 1;
+    }
+
+    template <class T>
+    T* ws(const char* name, int64_t count) {
+        return static_cast<T*>(c.work(std::string("solve_") + name, sizeof(T) * (size_t)std::max<int64_t>(count, 1)));
+    }
+
+    void alloc() {
+        V = ws<double>("V", (int64_t)Kcap * n);
+        U = ws<double>("U", (int64_t)(p.ell + 1) * m);
+        r = ws<double>("r", n);
+        tmp_n = ws<double>("tmp_n", n);
+        tmp_m = ws<double>("tmp_m", m);
+        GA = ws<double>("GA", KMAX_SMALL * KMAX_SMALL);
+        GT = ws<double>("GT", KMAX_SMALL * KMAX_SMALL);
+        dvec = ws<double>("dvec", KMAX_SMALL);
+        z = ws<double>("z", KMAX_SMALL);
+        h = ws<double>("h", KMAX_SMALL);
+        sc = ws<double>("sc", 8);
+        res = ws<double>("res", 8);
+        scal = ws<double>("scal", 16);
+        AV = ws<TX>("AV", (int64_t)Kcap * m);
+        TV = ws<TX>("TV", (int64_t)Kcap * R);
+        u_op = ws<TX>("u_op", n);
+        vin_n = ws<TX>("vin_n", n);
+        vin_m = ws<TX>("vin_m", m);
+        out_n = ws<TX>("out_n", n);
+        out_n2 = ws<TX>("out_n2", n);
+        nu = ws<TX>("nu", R);
+        yR = ws<TX>("yR", R);
+        flow_v = ws<TX>("flow_v", 2 * g.pair_px);
+        flow_vr = ws<TX>("flow_vr", 2 * g.pair_px);
+        flow_tmp = ws<TX>("flow_tmp", 2 * g.pair_px);
+        I = ws<TX>("I", 3 * g.pair_px);
+        rad_v = ws<int32_t>("rad_v", 64);
+        rad_vr = ws<int32_t>("rad_vr", 64);
+        host = static_cast<double*>(c.pinned(64 * sizeof(double)));
+        fill_zero<double>(c, 16, scal);
+    }
+
+    // ---------------------------------------------------------------- operators (TX)
+    void A(const TX* in, TX* out) {
+        if (P.kind == 0)
+            launch_radon_fwd(c, P, dt, in, out);
+        else
+            launch_blur(c, P, dt, in, out);
+        if (rep) rep->n_A++;
+    }
+    void At(const TX* in, TX* out) {
+        if (P.kind == 0)
+            launch_radon_adj(c, P, dt, in, out);
+        else
+            launch_blur(c, P, dt, in, out);
+        if (rep) rep->n_At++;
+    }
+    void theta_flow(const TX* in, TX* out) {
+        if (!flow) return;
+        launch_flow_fwd(c, g, dt, +1, p.interp, in, flow_v, out + oRF);
+        if (p.use_reverse) launch_flow_fwd(c, g, dt, -1, p.interp, in, flow_vr, out + oRR);
+    }
+    void theta(const TX* in, TX* out) {
+        launch_grad_fwd(c, g, dt, in, nullptr, nullptr, out + oGX, out + oGY);
+        theta_flow(in, out);
+        if (rep) rep->n_theta++;
+    }
+    void thetaT(const TX* in, TX* out) {
+        launch_grad_adj(c, g, dt, in + oGX, in + oGY, nullptr, nullptr, out, false);
+        if (flow) {
+            launch_flow_adj(c, g, dt, +1, p.interp, in + oRF, flow_v, out, true, rad_v);
+            if (p.use_reverse) launch_flow_adj(c, g, dt, -1, p.interp, in + oRR, flow_vr, out, true, rad_vr);
+        }
+        if (rep) rep->n_thetaT++;
+    }
+
+    // ---------------------------------------------------------------- Krylov helpers (FP64)
+    void norm_into(int64_t len, const double* x, double* out) {  // out = ||x||^2
+        mdot<double, double>(c, len, 1, x, len, x, 1.0, out);
+    }
+    // x <- x - Q (Q^T x), twice (Q has k columns of length len)
+    void reorth(int64_t len, const double* Q, int k, double* x) {
+        if (k <= 0) return;
+        for (int pass = 0; pass < 2; ++pass) {
+            mdot<double, double>(c, len, k, Q, len, x, 1.0, h);
+            gemv_cols<double>(c, len, k, Q, len, h, -1.0, 1.0, x);
+        }
+    }
+    // s1 = sqrt(s2); out = x / s1  (s2 holds the squared norm; all on the device)
+    void normalize_sq(int64_t len, const double* x, const double* s2, double* s1, double* out) {
+        sqrt_scalar(c, s2, s1);
+        normalize(c, len, x, s1, 0.0, out);
+    }
+
+    void add_column(int j) {
+        // H v_j, the row/column j of G_H, d_j = (H v_j)^T b and Theta v_j
+        const double* vj = V + (int64_t)j * n;
+        convert<double, TX>(c, n, vj, vin_n);
+        TX* avj = AV + (int64_t)j * m;
+        A(vin_n, avj);
+        mdot<TX, TX>(c, m, j + 1, AV, m, avj, 1.0, h);
+        put_rowcol(c, GA, KMAX_SMALL, j, h);
+        mdot<TX, double>(c, m, 1, avj, m, b, 1.0, dvec + j);
+        theta(vin_n, TV + (int64_t)j * R);
+    }
+
+    const double* b = nullptr;
+
+    int run(const double* b_, double delta, double* u_io, void* v_out, void* vr_out) {
+        b = b_;
+        MMOF_CHECK(Kcap >= 1 && Kcap <= KMAX_SMALL, MMOF_ERR_SHAPE,
+                   "ell + k_max - 1 must be in [1, " + std::to_string(KMAX_SMALL) + "]");
+        MMOF_CHECK(p.ell >= 1 && p.k_max >= 1 && p.tau >= 1, MMOF_ERR_INVALID, "ell, k_max, tau must be >= 1");
+        MMOF_CHECK(!flow || p.n_sweeps >= 0, MMOF_ERR_INVALID, "n_sweeps must be >= 0");
+        MMOF_CHECK(p.eps > 0 && p.alpha > 0 && p.eta > 0, MMOF_ERR_INVALID, "eps, alpha, eta must be > 0");
+        alloc();
+        if (rep) {
+            rep->n_A = rep->n_At = rep->n_theta = rep->n_thetaT = rep->n_flow_updates = 0;
+            rep->iters = 0;
+            rep->status = 0;
+        }
+        // scalars: sc[0] = ||b||^2, sc[1] = (eta delta)^2, sc[2] = previous lambda
+        norm_into(m, b, sc);
+        set_scalar(c, sc + 1, (p.eta * delta) * (p.eta * delta));
+        set_scalar(c, sc + 2, 0.0);
+
+        // ||H^T b|| for the breakdown test
+        convert<double, TX>(c, m, b, vin_m);
+        At(vin_m, out_n);
+        mdot<TX, TX>(c, n, 1, out_n, n, out_n, 1.0, scal + 4);
+        // RRE denominator
+        if (p.u_true) norm_into(n, p.u_true, scal + 5);
+        MMOF_HIP(hipMemcpyAsync(host, scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        MMOF_HIP(hipStreamSynchronize(c.stream));
+        const double atb = std::sqrt(host[0]);
+        const double utn = p.u_true ? std::sqrt(host[1]) : 0.0;
+
+        // ---- Golub-Kahan start: u_1 = b/||b||, ell right vectors, both bases re-orthogonalised
+        // scalar slots: scal[0..3] = alpha^2, alpha, beta^2, beta
+        norm_into(m, b, scal + 11);
+        normalize_sq(m, b, scal + 11, scal + 12, U);
+        convert<double, TX>(c, m, U, vin_m);
+        At(vin_m, out_n);
+        convert<TX, double>(c, n, out_n, r);
+        norm_into(n, r, scal);
+        normalize_sq(n, r, scal, scal + 1, V);
+        for (int i = 1; i < p.ell; ++i) {
+            // w = H v_{i-1} - alpha u_{i-1}
+            convert<double, TX>(c, n, V + (int64_t)(i - 1) * n, vin_n);
+            A(vin_n, vin_m);
+            convert<TX, double>(c, m, vin_m, tmp_m);
+            axpy_dev(c, m, U + (int64_t)(i - 1) * m, tmp_m, scal + 1, -1.0);
+            reorth(m, U, i, tmp_m);
+            norm_into(m, tmp_m, scal + 2);
+            normalize_sq(m, tmp_m, scal + 2, scal + 3, U + (int64_t)i * m);
+            // v = H^T u_i - beta v_{i-1}
+            convert<double, TX>(c, m, U + (int64_t)i * m, vin_m);
+            At(vin_m, out_n);
+            convert<TX, double>(c, n, out_n, r);
+            axpy_dev(c, n, V + (int64_t)(i - 1) * n, r, scal + 3, -1.0);
+            reorth(n, V, i, r);
+            norm_into(n, r, scal);
+            normalize_sq(n, r, scal, scal + 1, V + (int64_t)i * n);
+        }
+        for (int j = 0; j < p.ell; ++j) {
+            // Theta of the start vectors is built after the flows are zeroed below
+            const double* vj = V + (int64_t)j * n;
+            convert<double, TX>(c, n, vj, vin_n);
+            TX* avj = AV + (int64_t)j * m;
+            A(vin_n, avj);
+            mdot<TX, TX>(c, m, j + 1, AV, m, avj, 1.0, h);
+            put_rowcol(c, GA, KMAX_SMALL, j, h);
+            mdot<TX, double>(c, m, 1, avj, m, b, 1.0, dvec + j);
+        }
+
+        // ---- initial state
+        convert<double, TX>(c, n, u_io, u_op);
+        if (flow) {
+            fill_zero<TX>(c, 2 * g.pair_px, flow_v);
+            fill_zero<TX>(c, 2 * g.pair_px, flow_vr);
+            launch_flow_radius(c, g, dt, flow_v, rad_v);
+            launch_flow_radius(c, g, dt, flow_vr, rad_vr);
+        }
+        for (int j = 0; j < p.ell; ++j) {
+            convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
+            theta(vin_n, TV + (int64_t)j * R);
+        }
+
+        int K = p.ell;
+        int status = 0;
+        int iters = 0;
+        const double gamma = p.alpha * p.alpha;
+        for (int k = 0; k < p.k_max; ++k) {
+            // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
+            if (flow && k % p.tau == 0) {
+                launch_of_derivs(c, g, dt, u_op, I, p.delta_r);
+                TX* a = flow_v;
+                TX* bbuf = flow_tmp;
+                for (int s = 0; s < p.n_sweeps; ++s) {
+                    launch_hs_sweep(c, g, dt, I, a, bbuf, gamma);
+                    std::swap(a, bbuf);
+                }
+                if (a != flow_v) convert<TX, TX>(c, 2 * g.pair_px, a, flow_v);
+                launch_flow_radius(c, g, dt, flow_v, rad_v);
+                if (p.use_reverse) {
+                    launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);
+                    launch_flow_radius(c, g, dt, flow_vr, rad_vr);
+                }
+                for (int j = 0; j < K; ++j) {
+                    convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
+                    theta_flow(vin_n, TV + (int64_t)j * R);
+                }
+                if (rep) rep->n_flow_updates++;
+            }
+            // 2. nu = Theta u^(k); weighted Gram of Theta V
+            theta(u_op, nu);
+            wgram<TX>(c, R, K, TV, R, nu, p.eps, GT, KMAX_SMALL);
+            // 3-5. lambda (discrepancy principle) and z
+            small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res);
+            copy_scalar(c, sc + 2, res);
+            // 6. u^(k+1) = V z
+            gemv_cols<double>(c, n, K, V, n, z, 1.0, 0.0, u_io);
+            convert<double, TX>(c, n, u_io, u_op);
+            if (p.u_true) {
+                sub(c, n, u_io, p.u_true, tmp_n);
+                norm_into(n, tmp_n, scal + 6);
+            }
+            const bool last = (k == p.k_max - 1);
+            if (!last) {
+                // 7. r = H^T (H V z - b) + lambda Theta^T P^2 Theta V z
+                gemv_cols<TX>(c, m, K, AV, m, z, 1.0, 0.0, tmp_m);
+                axpby(c, m, 1.0, tmp_m, -1.0, b, tmp_m);
+                convert<double, TX>(c, m, tmp_m, vin_m);
+                At(vin_m, out_n);
+                theta(u_op, yR);
+                weight_mul<TX>(c, R, nu, p.eps, yR, yR);
+                thetaT(yR, out_n2);
+                residual_combine<TX>(c, n, out_n, out_n2, res, r);
+                // 8. CGS2 against V
+                reorth(n, V, K, r);
+                norm_into(n, r, scal + 7);
+            }
+            // report: lambda, D^2, status, rre^2, ||r||^2
+            copy_scalar(c, scal + 8, res);
+            copy_scalar(c, scal + 9, res + 1);
+            copy_scalar(c, scal + 10, res + 2);
+            MMOF_HIP(hipMemcpyAsync(host, scal + 6, 5 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            MMOF_HIP(hipStreamSynchronize(c.stream));
+            const double rre2 = host[0], rnorm = std::sqrt(std::max(host[1], 0.0));
+            const double lam = host[2], D2 = host[3];
+            const int st = (int)host[4];
+            iters = k + 1;
+            if (st == 2) status = std::max(status, (int)MMOF_WARN_DP_CLAMPED);
+            if (st == 4) throw Error(MMOF_ERR_NONFINITE, "projected system is not positive definite");
+            double rre = p.u_true ? std::sqrt(std::max(rre2, 0.0)) / utn : 0.0;
+            if (rep && k < rep->capacity) {
+                if (rep->lambda) rep->lambda[k] = lam;
+                if (rep->resid) rep->resid[k] = std::sqrt(std::max(D2, 0.0));
+                if (rep->rre) rep->rre[k] = rre;
+                if (rep->dp_status) rep->dp_status[k] = st;
+            }
+            if (rep) rep->n_cols = K;
+            if (p.u_true && p.rre_target > 0 && rre <= p.rre_target) break;
+            if (last) {
+                if (p.u_true && p.rre_target > 0) status = std::max(status, (int)MMOF_WARN_KMAX);
+                break;
+            }
+            // 9. breakdown or append r/||r||
+            if (!(rnorm > 1e-14 * atb)) {
+                status = MMOF_WARN_BREAKDOWN;
+                break;
+            }
+            normalize_sq(n, r, scal + 7, scal + 13, V + (int64_t)K * n);
+            add_column(K);
+            ++K;
+        }
+        if (rep) {
+            rep->iters = iters;
+            rep->status = status;
+        }
+        const int64_t vb = (int64_t)sizeof(TX) * 2 * g.pair_px;
+        if (v_out && flow && vb) MMOF_HIP(hipMemcpyAsync(v_out, flow_v, vb, hipMemcpyDeviceToDevice, c.stream));
+        if (vr_out && flow && vb) MMOF_HIP(hipMemcpyAsync(vr_out, flow_vr, vb, hipMemcpyDeviceToDevice, c.stream));
+        MMOF_HIP(hipStreamSynchronize(c.stream));
+        return status;
+    }
+};
+
+int solve_joint(Plan& P, const double* b, double delta, const mmof_solve_params& p, double* u_io, void* v_out,
+                void* vr_out, mmof_report* rep) {
+    if (p.op_dtype == MMOF_F32) {
+        Solver<float> s(*P.ctx, P, p, rep);
+        return s.run(b, delta, u_io, v_out, vr_out);
+    }
+    if (p.op_dtype == MMOF_F64) {
+        Solver<double> s(*P.ctx, P, p, rep);
+        return s.run(b, delta, u_io, v_out, vr_out);
+    }
+    throw Error(MMOF_ERR_DTYPE, "op_dtype must be MMOF_F32 or MMOF_F64");
+}
+
+}  // namespace mmof

@@ -1,0 +1,290 @@
+"""GPU parity of every operator kernel against the FP64 oracle, through the C ABI.
+
+Stacks are ragged batches whose frames span several kernel tiles and end in partial
+tiles.  FP64 kernels must match to 1e-12 (norm-wise relative); FP32 kernels get FP32
+inputs (the oracle sees the same values upcast) and must match to 1e-5 relative to the
+forward-error scale ||Op| |x|| (for cancellation-prone outputs) or to ||y||.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import TOL32, TOL64, dev, host, pack, rel, roundtrip32, unpack
+from oracle import forward, optflow, regops
+from synth import bins_for, nudge_off_kinks
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(3, 37, 75), (2, 20, 130), (4, 33, 33)]   # (n_t, ny, nx) per sequence
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch  # noqa: F401
+    from paper_2501_12497_amd import binding
+    return binding
+
+
+def _rand_stack(seed, sizes=SIZES):
+    r = np.random.default_rng(seed)
+    return [r.standard_normal(s) for s in sizes]
+
+
+def _dtypes():
+    import torch
+    return [(torch.float64, TOL64), (torch.float32, TOL32)]
+
+
+# --------------------------------------------------------------------------- Radon
+
+
+def _angles(r, n_t, n_th):
+    a = r.uniform(0, math.pi, size=(n_t, n_th))
+    a[0, :4] = [0.0, math.pi / 2, math.pi / 4, 3 * math.pi / 4][: min(4, n_th)]
+    return a
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_radon_forward_and_adjoint(B, which):
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    r = np.random.default_rng(10)
+    us = _rand_stack(11)
+    n_th = [7, 5, 9]
+    nbins = [bins_for(max(s[1], s[2])), 23, bins_for(33)]
+    angs = [_angles(r, s[0], k) for s, k in zip(SIZES, n_th)]
+    stack = B.Stack(SIZES)
+    plan = B.plan_radon(stack, n_th, nbins, np.concatenate([a.ravel() for a in angs]))
+    if dt == torch.float32:
+        us = [roundtrip32(u) for u in us]
+    b = host(B.apply_A(plan, dev(pack(us), dt)))
+    exp = [forward.radon_fwd(u, a, nb) for u, a, nb in zip(us, angs, nbins)]
+    scale = pack([forward.radon_fwd(np.abs(u), a, nb) for u, a, nb in zip(us, angs, nbins)])
+    assert rel(b, pack(exp), scale) < tol
+    bs = [r.standard_normal(e.shape) for e in exp]
+    if dt == torch.float32:
+        bs = [roundtrip32(x) for x in bs]
+    u = host(B.apply_At(plan, dev(pack(bs), dt)))
+    expu = [forward.radon_adj(x, a, s[1], s[2]) for x, a, s in zip(bs, angs, SIZES)]
+    scale = pack([forward.radon_adj(np.abs(x), a, s[1], s[2]) for x, a, s in zip(bs, angs, SIZES)])
+    assert rel(u, pack(expu), scale) < tol
+
+
+def test_radon_adjoint_identity_fp64(B):
+    import torch
+    r = np.random.default_rng(12)
+    sizes = [(2, 64, 64), (1, 50, 70)]
+    stack = B.Stack(sizes)
+    plan = B.plan_radon(stack, [30, 11], [bins_for(64), 87], r.uniform(0, 2 * math.pi, 2 * 30 + 11))
+    u = torch.randn(plan.n, dtype=torch.float64, device="cuda")
+    b = torch.randn(plan.m, dtype=torch.float64, device="cuda")
+    lhs = float((B.apply_A(plan, u) * b).sum())
+    rhs = float((u * B.apply_At(plan, b)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# --------------------------------------------------------------------------- blur
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_blur(B, which):
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    us = _rand_stack(13)
+    if dt == torch.float32:
+        us = [roundtrip32(u) for u in us]
+    plan = B.plan_blur(B.Stack(SIZES), 9, 2.0)
+    y = host(B.apply_A(plan, dev(pack(us), dt)))
+    exp = pack([forward.blur(u) for u in us])
+    assert rel(y, exp, pack([forward.blur(np.abs(u)) for u in us])) < tol
+    y2 = host(B.apply_At(plan, dev(pack(us), dt)))
+    assert rel(y2, pack([forward.blur_adj(u) for u in us]), pack([forward.blur(np.abs(u)) for u in us])) < tol
+
+
+# --------------------------------------------------------------------------- gradient
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_grad_forward_and_adjoint(B, which, weighted):
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    r = np.random.default_rng(14)
+    us = _rand_stack(15)
+    gxs = [r.standard_normal((s[0], s[1], s[2] - 1)) for s in SIZES]
+    gys = [r.standard_normal((s[0], s[1] - 1, s[2])) for s in SIZES]
+    wxs = [r.random(g.shape) for g in gxs] if weighted else None
+    wys = [r.random(g.shape) for g in gys] if weighted else None
+    if dt == torch.float32:
+        us, gxs, gys = [list(map(roundtrip32, a)) for a in (us, gxs, gys)]
+        if weighted:
+            wxs, wys = list(map(roundtrip32, wxs)), list(map(roundtrip32, wys))
+    stack = B.Stack(SIZES)
+    wx = dev(pack(wxs), dt) if weighted else None
+    wy = dev(pack(wys), dt) if weighted else None
+    gx, gy = B.apply_grad(stack, dev(pack(us), dt), wx=wx, wy=wy)
+    ex = [regops.grad_fwd(u, *((a, b) if weighted else ())) for u, a, b in
+          zip(us, wxs or [None] * 3, wys or [None] * 3)]
+    sx = pack([np.abs(u[:, :, 1:]) + np.abs(u[:, :, :-1]) for u in us])
+    sy = pack([np.abs(u[:, 1:, :]) + np.abs(u[:, :-1, :]) for u in us])
+    assert rel(host(gx), pack([e[0] for e in ex]), sx if not weighted else None) < tol
+    assert rel(host(gy), pack([e[1] for e in ex]), sy if not weighted else None) < tol
+    u = host(B.apply_grad(stack, gx=dev(pack(gxs), dt), gy=dev(pack(gys), dt), wx=wx, wy=wy, transpose=True))
+    exp = pack([regops.grad_adj(a, b, *((c, d) if weighted else ())) for a, b, c, d in
+                zip(gxs, gys, wxs or [None] * 3, wys or [None] * 3)])
+    scale = []
+    for i, (a, b) in enumerate(zip(gxs, gys)):
+        a = np.abs(a) * (wxs[i] if weighted else 1.0)
+        b = np.abs(b) * (wys[i] if weighted else 1.0)
+        sc = np.zeros(SIZES[i])
+        sc[:, :, 1:] += a
+        sc[:, :, :-1] += a
+        sc[:, 1:, :] += b
+        sc[:, :-1, :] += b
+        scale.append(sc)
+    scale = pack(scale)
+    assert rel(u, exp, scale) < tol
+
+
+# --------------------------------------------------------------------------- flow operator
+
+
+def _flows(seed, vmax, sizes=SIZES, nudge=False):
+    r = np.random.default_rng(seed)
+    vs = [r.uniform(-vmax, vmax, size=(s[0] - 1, 2, s[1], s[2])) for s in sizes]
+    return [nudge_off_kinks(v) for v in vs] if nudge else vs
+
+
+def _abs_warp(u, v, direction, interp, adjoint=False, r=None):
+    """Forward-error scale |W| |src| + |sub| (or its adjoint counterpart)."""
+    n_t = u.shape[0] if not adjoint else r.shape[0] + 1
+    out = []
+    for t in range(v.shape[0]):
+        M = abs(regops.motion_matrix(v[t], interp))
+        if not adjoint:
+            src = u[t + 1] if direction > 0 else u[t]
+            sub = u[t] if direction > 0 else u[t + 1]
+            out.append((M @ np.abs(src).ravel()).reshape(src.shape) + np.abs(sub))
+    if adjoint:
+        acc = np.zeros((n_t,) + r.shape[1:])
+        for t in range(r.shape[0]):
+            M = abs(regops.motion_matrix(v[t], interp))
+            back = (M.T @ np.abs(r[t]).ravel()).reshape(r.shape[1:])
+            if direction > 0:
+                acc[t + 1] += back
+                acc[t] += np.abs(r[t])
+            else:
+                acc[t] += back
+                acc[t + 1] += np.abs(r[t])
+        return acc
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("interp", ["bilinear", "round"])
+@pytest.mark.parametrize("vmax", [3.5, 11.0])   # LDS-staged adjoint (radius <= 8) and the wide-window path
+def test_flow_operator(B, which, direction, interp, vmax):
+    import torch
+    from paper_2501_12497_amd import _lib
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    us = _rand_stack(16)
+    vs = _flows(17, vmax)
+    rs = [np.random.default_rng(18 + i).standard_normal((s[0] - 1, s[1], s[2])) for i, s in enumerate(SIZES)]
+    if dt == torch.float32:
+        us, vs, rs = [list(map(roundtrip32, a)) for a in (us, vs, rs)]
+    stack = B.Stack(SIZES)
+    ip = _lib.MMOF_INTERP_BILINEAR if interp == "bilinear" else _lib.MMOF_INTERP_ROUND
+    du, dv, dr = dev(pack(us), dt), dev(pack(vs), dt), dev(pack(rs), dt)
+    y = host(B.apply_flow_op(stack, _lib.MMOF_FLOW_FWD, direction, ip, du, dv))
+    exp = pack([regops.flow_fwd(u, v, direction, interp) for u, v in zip(us, vs)])
+    scale = pack([_abs_warp(u, v, direction, interp) for u, v in zip(us, vs)])
+    assert rel(y, exp, scale) < tol
+    ya = B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, direction, ip, None, dv, dr)
+    exp = pack([regops.flow_adj(r, v, s[0], direction, interp) for r, v, s in zip(rs, vs, SIZES)])
+    scale = pack([_abs_warp(None, v, direction, interp, True, r) for r, v in zip(rs, vs)])
+    assert rel(host(ya), exp, scale) < tol
+    # the adjoint is a deterministic gather: bitwise reproducible
+    ya2 = B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, direction, ip, None, dv, dr)
+    assert torch.equal(ya, ya2)
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_flow_dv(B, which, direction):
+    import torch
+    from paper_2501_12497_amd import _lib
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    us = _rand_stack(19)
+    vs = _flows(20, 3.0, nudge=True)
+    ws = [np.random.default_rng(21 + i).standard_normal((s[0] - 1, s[1], s[2])) for i, s in enumerate(SIZES)]
+    if dt == torch.float32:
+        us, vs, ws = [list(map(roundtrip32, a)) for a in (us, vs, ws)]
+    stack = B.Stack(SIZES)
+    g = host(B.apply_flow_op(stack, _lib.MMOF_FLOW_DV, direction, _lib.MMOF_INTERP_BILINEAR,
+                             dev(pack(us), dt), dev(pack(vs), dt), dev(pack(ws), dt)))
+    exp = pack([regops.flow_dv(u, v, w, direction) for u, v, w in zip(us, vs, ws)])
+    scale = pack([2 * np.abs(w)[:, None] * np.abs(u).max() * np.ones((1, 2, 1, 1)) for u, w in zip(us, ws)])
+    assert rel(g, exp, scale) < tol
+
+
+# --------------------------------------------------------------------------- optical flow pieces
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+@pytest.mark.parametrize("dr", [1, 2])
+def test_of_derivs(B, which, dr):
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    us = _rand_stack(22)
+    if dt == torch.float32:
+        us = [roundtrip32(u) for u in us]
+    I = host(B.of_derivs(B.Stack(SIZES), dev(pack(us), dt), dr))
+    exp = pack([optflow.of_derivs(u, dr) for u in us])
+    scale = pack([optflow.of_derivs(np.abs(u), dr) * 0 + np.abs(u).max() for u in us])
+    assert rel(I, exp, scale) < tol
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_flow_update_and_reverse(B, which):
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    r = np.random.default_rng(23)
+    us = [np.cumsum(np.cumsum(r.standard_normal(s), axis=1), axis=2) * 0.05 for s in SIZES]   # smooth-ish images
+    vs0 = _flows(24, 0.5)
+    if dt == torch.float32:
+        us, vs0 = [list(map(roundtrip32, a)) for a in (us, vs0)]
+    stack = B.Stack(SIZES)
+    v = dev(pack(vs0), dt)
+    vr = torch.empty_like(v)
+    B.flow_update(stack, dev(pack(us), dt), v, alpha=0.3, n_sweeps=25, delta_r=1, v_rev=vr)
+    exp = [optflow.flow_update(u, v0, 0.3, 25, 1) for u, v0 in zip(us, vs0)]
+    got = host(v)
+    assert rel(got, pack(exp)) < (TOL64 if dt == torch.float64 else 1e-4)
+    # reverse flow of the GPU's own flow (rounding decisions must see identical inputs)
+    gshapes = [e.shape for e in exp]
+    exp_r = pack([optflow.reverse_flow(x) for x in unpack(got, gshapes)])
+    assert rel(host(vr), exp_r) < tol
+
+
+def test_reverse_flow_exact_on_half_integers(B):
+    import torch
+    sizes = [(2, 9, 11)]
+    r = np.random.default_rng(25)
+    v = (np.round(r.uniform(-3, 3, size=(1, 2, 9, 11)) * 2) / 2)    # many exact .5 ties
+    for dt in (torch.float64, torch.float32):
+        got = host(B.reverse_flow(B.Stack(sizes), dev(v, dt)))
+        assert np.array_equal(got, optflow.reverse_flow(v).ravel())
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_mm_weights(B, which):
+    import torch
+    from oracle import mmgks
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    nu = np.random.default_rng(26).standard_normal(10007) * np.logspace(-5, 1, 10007)
+    if dt == torch.float32:
+        nu = roundtrip32(nu)
+    w = host(B.mm_weights(dev(nu, dt), 1e-3))
+    assert rel(w, mmgks.mm_weights_sq(nu, 1e-3)) < tol
