@@ -52,7 +52,7 @@ def test_radon_forward_and_adjoint(B, which):
     r = np.random.default_rng(10)
     us = _rand_stack(11)
     n_th = [7, 5, 9]
-    nbins = [bins_for(max(s[1], s[2])), 23, bins_for(33)]
+    nbins = [bins_for(max(SIZES[0][1], SIZES[0][2])), 23, bins_for(33)]
     angs = [_angles(r, s[0], k) for s, k in zip(SIZES, n_th)]
     stack = B.Stack(SIZES)
     plan = B.plan_radon(stack, n_th, nbins, np.concatenate([a.ravel() for a in angs]))
@@ -273,9 +273,12 @@ def test_reverse_flow_exact_on_half_integers(B):
     sizes = [(2, 9, 11)]
     r = np.random.default_rng(25)
     v = (np.round(r.uniform(-3, 3, size=(1, 2, 9, 11)) * 2) / 2)    # many exact .5 ties
-    for dt in (torch.float64, torch.float32):
-        got = host(B.reverse_flow(B.Stack(sizes), dev(v, dt)))
-        assert np.array_equal(got, optflow.reverse_flow(v).ravel())
+    exp = optflow.reverse_flow(v).ravel()
+    got = host(B.reverse_flow(B.Stack(sizes), dev(v, torch.float64)))
+    assert np.array_equal(got, exp)
+    # FP32: identical rounding decisions; the averages differ only by FP32 rounding
+    got = host(B.reverse_flow(B.Stack(sizes), dev(v, torch.float32)))
+    np.testing.assert_allclose(got, exp, rtol=1e-6, atol=0)
 
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
