@@ -1,0 +1,240 @@
+"""Benchmark of the MMGKS-OF hot path on one MI355X.
+
+Workload: 128x128 pixels x 16 frames, three ellipses translating with integer
+velocities in [-2, 2] px/frame, 30 parallel-beam angles per frame rotated 6 deg per
+frame, 181 detector bins, 2% Gaussian noise (synthetic, seeded).  One step is one
+complete joint solve (MMGKS-OF, Alg. 1): Golub-Kahan start (ell = 10), 30 outer
+MM iterations, Horn-Schunck flow update (200 sweeps) every 10 iterations, with FP32
+operator applications and the FP64 generalized-Krylov projection, Gram matrices,
+projected solve and discrepancy principle.  Inputs are resident on the GPU before
+the timed region starts.
+
+Printed JSON fields beyond the driver's contract:
+  roofline         the dominant kernel's algorithmic bytes / its mean launch time
+                   (HIP events on the library's stream over the timed region)
+  time_to_solution FP32-operator vs FP64-operator solve to the same RRE target
+  cpu_baseline     the FP64 oracle on the host cores, on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per launch of the kernels that can dominate (FP32 operands):
+# per pixel (or pair-pixel) the bytes the method must read and write once.
+ALGO_BYTES = {
+    # HS sweep: read s (2 x 4 B) and I (3 x 4 B), write s (2 x 4 B) per pair-pixel
+    "hs_sweep": lambda s: 28 * s["pair_px"],
+    # weighted Gram: read K columns of Theta V (4 B each) and nu (4 B) per Theta row
+    "wgram": lambda s: s["rows_theta"] * (4 * s["K_mean"] + 4),
+    # flow adjoint (one direction): read r (4 B) and v (8 B), read/write u (8 B) per pair-pixel
+    "flow_adj": lambda s: 20 * s["pair_px"],
+    # flow forward: read u_t, u_t+1 (8 B), v (8 B), write r (4 B) per pair-pixel
+    "flow_fwd": lambda s: 20 * s["pair_px"],
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload():
+    from synth import cfg_ellipse128
+    return cfg_ellipse128()
+
+
+def gpu_data(wl, B, torch):
+    s = wl.seqs[0]
+    stack = B.Stack.single(s.n_t, s.ny, s.nx)
+    plan = B.plan_radon(stack, [s.angles.shape[1]], [s.n_bins], s.angles.ravel())
+    u_true = torch.as_tensor(s.u_true.ravel(), dtype=torch.float64, device="cuda")
+    clean = B.apply_A(plan, u_true)          # data synthesis on the GPU (FP64)
+    g = torch.as_tensor(s.noise_g.ravel(), dtype=torch.float64, device="cuda")
+    e = wl.noise_level * torch.linalg.vector_norm(clean) * g / torch.linalg.vector_norm(g)
+    b = (clean + e).contiguous()
+    delta = float(torch.linalg.vector_norm(e))
+    return stack, plan, u_true, b, delta
+
+
+def solve_params(wl, op):
+    p = wl.params
+    return dict(ell=p["ell"], k_max=p["k_max"], tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
+                eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"], op_dtype=op)
+
+
+def cpu_baseline(wl, k_iters: int = 3):
+    """The FP64 oracle's solve on the same workload, stopped after k_iters outer iterations
+    (one flow update included); matvecs counted by wrapping the oracle's operators."""
+    from oracle import mmgks
+    from synth import noisy
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    s = wl.seqs[0]
+    g = mmgks.SeqGeom(s.n_t, s.ny, s.nx, s.angles, s.n_bins)
+    ops = mmgks.StackOps([g], "radon")
+    clean = ops.A(s.u_true.ravel())
+    b = noisy(clean, s.noise_g, wl.noise_level)
+    delta = float(np.linalg.norm(b - clean))
+    cnt = dict(A=0, At=0, L=0)
+    fA, fAt, fT, fTT = ops.A, ops.At, ops.theta, ops.thetaT
+
+    def A(x):
+        cnt["A"] += 1
+        return fA(x)
+
+    def At(x):
+        cnt["At"] += 1
+        return fAt(x)
+
+    def T(x, f):
+        cnt["L"] += 2
+        return fT(x, f)
+
+    def TT(x, f):
+        cnt["L"] += 2
+        return fTT(x, f)
+
+    ops.A, ops.At, ops.theta, ops.thetaT = A, At, T, TT
+    p = wl.params
+    prm = mmgks.SolveParams(ell=p["ell"], k_max=k_iters, tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
+                            eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"])
+    t0 = time.perf_counter()
+    mmgks.mmgks_of(ops, b, delta, prm, u_true=s.u_true.ravel())
+    dt = time.perf_counter() - t0
+    n = cnt["A"] + cnt["At"] + cnt["L"]
+    return {"value": n / dt, "unit": "matvecs/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 oracle MMGKS-OF on the same 128x128x16 data, {k_iters} outer iterations "
+                      f"(1 flow update of {p['n_sweeps']} sweeps), {n} A/At/L(v) applications in {dt:.1f} s; "
+                      f"sparse products single-threaded, dense QR/solves on {threads} BLAS threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--profile-kernel", default="hs_sweep")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tts", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2501_12497_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = make_workload()
+    stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
+    ctx = plan.ctx
+    prm = solve_params(wl, "f32")
+    log(f"workload {wl.name}: n={plan.n} m={plan.m} params={prm}")
+
+    def step():
+        return B.solve_joint(plan, b, delta, u_true=u_true, **prm)
+
+    for i in range(a.warmup):
+        r = step()
+        log(f"warmup {i}: iters={r.iters} rre={r.rre[-1]:.5f}")
+    ctx.profile_kernel(a.profile_kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for i in range(a.steps):
+        res.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_launch, k_ms = ctx.kernel_timing()
+    ctx.profile_kernel(None)
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    r = res[-1]
+    mv = r.counts["A"] + r.counts["At"] + r.counts["L"]
+    value = mv * a.steps / (t1 - t0)
+    log(f"timed {a.steps} solves: {ms_step:.2f} ms/solve, {mv} matvecs/solve, rre={r.rre[-1]:.5f}, "
+        f"{a.profile_kernel}: {n_launch} launches {k_ms:.2f} ms")
+
+    # roofline of the profiled kernel
+    P = stack.n_pair_px
+    Ks = list(range(prm["ell"], prm["ell"] + prm["k_max"]))
+    sz = {"pair_px": P, "rows_theta": stack.n_gx + stack.n_gy + 2 * P, "K_mean": float(np.mean(Ks))}
+    roof = None
+    if n_launch and a.profile_kernel in ALGO_BYTES:
+        avg_s = k_ms / n_launch * 1e-3
+        bytes_ = ALGO_BYTES[a.profile_kernel](sz)
+        ach = bytes_ / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": a.profile_kernel, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(bytes_), "avg_launch_us": round(avg_s * 1e6, 3),
+                "launches": n_launch}
+
+    # time to solution at a fixed relative error: FP32 operators vs FP64 operators
+    tts = None
+    if not a.no_tts:
+        ref = B.solve_joint(plan, b, delta, u_true=u_true, **solve_params(wl, "f64"))
+        target = ref.rre[-1] * 1.001
+        tts = {"rre_target": target, "k_max": prm["k_max"] + 15}
+        for op in ("f64", "f32"):
+            kw = solve_params(wl, op)
+            kw["k_max"] = prm["k_max"] + 15
+            kw["rre_target"] = target
+            B.solve_joint(plan, b, delta, u_true=u_true, **kw)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                rr = B.solve_joint(plan, b, delta, u_true=u_true, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            tts[op] = {"seconds": float(np.median(ts)), "iters": rr.iters, "rre": rr.rre[-1],
+                       "reached": bool(rr.rre[-1] <= target)}
+        log(f"time to solution: {tts}")
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(wl)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "A+At+L(v) matvecs/s in the MMGKS-OF joint solve (FP32 operators, FP64 Krylov)",
+        "value": round(value, 1),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 operators + f64 krylov",
+        "data": "synthetic",
+        "config": {"workload": "ellipse128x128x16: 3 translating ellipses, 30 angles/frame (+6 deg/frame), "
+                               "181 bins, 2% noise; solve ell=10, 30 MM iterations, flow every 10 (200 HS sweeps)",
+                   "n_pixels": plan.n, "n_data": plan.m, "matvecs_per_step": mv, "rre": r.rre[-1]},
+        "roofline": roof,
+        "time_to_solution": tts,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

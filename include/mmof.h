@@ -191,6 +191,7 @@ typedef struct {
     double* rre;          /* host [capacity] or NULL: RRE(u^(k+1)) if u_true given        */
     int32_t* dp_status;   /* host [capacity] or NULL: 0 root found, 2 clamped             */
     int64_t n_A, n_At, n_theta, n_thetaT, n_flow_updates;  /* operator application counts */
+    int64_t n_L;          /* applications of L(v) or L(v)^T, one per flow direction      */
 } mmof_report;
 
 /* MMGKS-OF (Alg. 1) for min ||H u - b||^2 + lambda ||Theta u||_1 with the flow
@@ -203,6 +204,25 @@ int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_s
 /* Fill p with the defaults (ell 10, k_max 20, tau 1, 200 sweeps, delta_r 1, flow on,
  * reverse on, bilinear, F64 operators, eps 1e-3, eta 1.01, alpha 0.1). */
 void mmof_solve_defaults(mmof_solve_params* p);
+
+/* ------------------------------------------------------------------ projected-problem steps */
+
+/* Weighted Gram matrix of a block of K columns (Sec. 4.1.1: R^T R of the thin QR of
+ * P Theta V, eq. QR):  G = X^T diag(w2) X with w2 = 1/sqrt(nu^2 + eps^2) (nu NULL: w2 = 1).
+ * X: device, K columns of length n in dtype dt, column j at X + j*ld; nu: device, n entries
+ * of dtype dt or NULL.  G: device FP64, K x K row-major with leading dimension ldg.
+ * 1 <= K <= 64.  Accumulation is FP64 on the matrix cores. */
+int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
+                       const void* nu, double eps, double* G, int32_t ldg);
+
+/* Projected solve of MMGKS (eq. minKryov2) with the discrepancy principle (Sec. 4.1.3):
+ * (G_H + lambda G_T) z = d, lambda such that ||b||^2 - d^T z - lambda z^T G_T z = target.
+ * GA, GT: device FP64 K x K (leading dimension 64); d: device FP64 [K];
+ * sc: device FP64 {||b||^2, target = (eta delta)^2, previous lambda or 0};
+ * fixed_lambda > 0 skips the root search.  Writes z (device FP64 [K]) and
+ * res (device FP64 [3]) = {lambda, discrepancy^2, status 0 root / 2 clamped / 4 failure}. */
+int mmof_projected_solve(mmof_ctx ctx, int32_t K, const double* GA, const double* GT, const double* d,
+                         const double* sc, double fixed_lambda, double* z, double* res);
 
 /* ------------------------------------------------------------------ measurement */
 

@@ -36,7 +36,7 @@ class mmof_report(C.Structure):
                 ("lambda_", C.POINTER(C.c_double)), ("resid", C.POINTER(C.c_double)),
                 ("rre", C.POINTER(C.c_double)), ("dp_status", C.POINTER(C.c_int32)),
                 ("n_A", C.c_int64), ("n_At", C.c_int64), ("n_theta", C.c_int64), ("n_thetaT", C.c_int64),
-                ("n_flow_updates", C.c_int64)]
+                ("n_flow_updates", C.c_int64), ("n_L", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -63,6 +63,8 @@ _SIGS = {
     "mmof_solve_defaults": (None, [C.POINTER(mmof_solve_params)]),
     "mmof_solve_joint": (_I, [_P, _P, C.c_double, C.POINTER(mmof_solve_params), _P, _P, _P,
                               C.POINTER(mmof_report)]),
+    "mmof_weighted_gram": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_int32]),
+    "mmof_projected_solve": (_I, [_P, C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
     "mmof_profile_kernel": (_I, [_P, C.c_char_p]),
     "mmof_kernel_timing": (_I, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }

@@ -308,6 +308,41 @@ def reverse_flow(stack: Stack, v: torch.Tensor, out: Optional[torch.Tensor] = No
     return out
 
 
+# ----------------------------------------------------------------------------- projected steps
+
+
+def weighted_gram(X: torch.Tensor, nu: Optional[torch.Tensor] = None, eps: float = 1e-3,
+                  ctx: Optional[Context] = None) -> torch.Tensor:
+    """G = X^T diag(1/sqrt(nu^2+eps^2)) X for X of shape [K, n] (K columns, each contiguous)."""
+    ctx = ctx or context()
+    K, n = X.shape
+    _need(X, K * n, "X")
+    if nu is not None:
+        _need(nu, n, "nu")
+    G = torch.empty((K, K), dtype=torch.float64, device=X.device)
+    ctx.bind()
+    check(ctx.lib.mmof_weighted_gram(ctx.h, _dt(X, nu), n, K, _ptr(X), n, _ptr(nu), float(eps), _ptr(G), K))
+    return G
+
+
+def projected_solve(GA: torch.Tensor, GT: torch.Tensor, d: torch.Tensor, bnorm2: float, target: float,
+                    prev_lambda: float = 0.0, fixed_lambda: float = 0.0, ctx: Optional[Context] = None):
+    """(G_H + lambda G_T) z = d with lambda from the discrepancy principle; returns (z, lambda, D^2, status)."""
+    ctx = ctx or context()
+    K = d.numel()
+    pad = lambda M: torch.nn.functional.pad(M.to(torch.float64), (0, 64 - K, 0, 64 - K)).contiguous()
+    A64, T64 = pad(GA), pad(GT)
+    sc = torch.tensor([bnorm2, target, prev_lambda], dtype=torch.float64, device=d.device)
+    z = torch.empty(K, dtype=torch.float64, device=d.device)
+    res = torch.empty(3, dtype=torch.float64, device=d.device)
+    dd = d.to(torch.float64).contiguous()
+    ctx.bind()
+    check(ctx.lib.mmof_projected_solve(ctx.h, K, _ptr(A64), _ptr(T64), _ptr(dd), _ptr(sc), float(fixed_lambda),
+                                       _ptr(z), _ptr(res)))
+    r = res.cpu().tolist()
+    return z, r[0], r[1], int(r[2])
+
+
 # ----------------------------------------------------------------------------- solve
 
 
@@ -372,4 +407,4 @@ def solve_joint(plan: Plan, b: torch.Tensor, noise_norm: float, u0: Optional[tor
                        resid=list(res[:k]), rre=list(rre[:k]) if u_true is not None else [],
                        dp_status=list(dps[:k]),
                        counts=dict(A=rep.n_A, At=rep.n_At, theta=rep.n_theta, thetaT=rep.n_thetaT,
-                                   flow_updates=rep.n_flow_updates))
+                                   flow_updates=rep.n_flow_updates, L=rep.n_L))

@@ -365,6 +365,40 @@ int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_s
     });
 }
 
+// ------------------------------------------------------------------ projected-problem steps
+
+int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld, const void* nu,
+                       double eps, double* G, int32_t ldg) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(X, "X");
+        need(G, "G");
+        MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX_SMALL && ld >= n && ldg >= K, MMOF_ERR_SHAPE, "bad Gram sizes");
+        MMOF_CHECK(!nu || eps > 0, MMOF_ERR_INVALID, "eps must be > 0");
+        if (dt == MMOF_F32)
+            wgram<float>(*ctx, n, K, (const float*)X, ld, (const float*)nu, eps, G, ldg);
+        else
+            wgram<double>(*ctx, n, K, (const double*)X, ld, (const double*)nu, eps, G, ldg);
+        return MMOF_OK;
+    });
+}
+
+int mmof_projected_solve(mmof_ctx ctx, int32_t K, const double* GA, const double* GT, const double* d,
+                         const double* sc, double fixed_lambda, double* z, double* res) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need(GA, "GA");
+        need(GT, "GT");
+        need(d, "d");
+        need(sc, "sc");
+        need(z, "z");
+        need(res, "res");
+        small_solve(*ctx, K, GA, GT, d, sc, fixed_lambda, z, res);
+        return MMOF_OK;
+    });
+}
+
 // ------------------------------------------------------------------ measurement
 
 int mmof_profile_kernel(mmof_ctx ctx, const char* kernel_name) {

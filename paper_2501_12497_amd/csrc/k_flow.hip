@@ -222,16 +222,20 @@ __global__ __launch_bounds__(256) void k_flow_dv(const Tile* __restrict__ tiles,
 }
 
 template <class T>
-__global__ void k_flow_radius(const T* __restrict__ v, int64_t n, int32_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_flow_radius(const T* __restrict__ v, int64_t n, int32_t* __restrict__ out) {
+    __shared__ T s4[4];
     T m = T(0);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        T a = fabs(v[i]);
-        m = (a > m || a != a) ? (a != a ? T(1e30) : a) : m;
+        const T a = fabs(v[i]);
+        m = (a != a) ? T(1e30) : fmax(m, a);
     }
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) {
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(s4[0], s4[1]), fmax(s4[2], s4[3]));
         const T c = fmin(floor(m), T(1 << 20));
-        atomicMax(out, (int32_t)c + 1);
+        atomicMax(out, (int32_t)c + 1);  // integer max: order-independent
     }
 }
 
@@ -244,7 +248,7 @@ void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out) 
     if (n == 0) return;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        hipLaunchKernelGGL(k_flow_radius<T>, grid_for(n, 256, 2048), dim3(256), 0, c.stream, (const T*)v, n, d_out);
+        hipLaunchKernelGGL(k_flow_radius<T>, grid_for(n, 256, 256), dim3(256), 0, c.stream, (const T*)v, n, d_out);
         MMOF_LAUNCH_CHECK();
     });
 }

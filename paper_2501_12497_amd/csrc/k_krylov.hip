@@ -36,20 +36,37 @@ __global__ void k_convert(int64_t n, const TI* __restrict__ in, TO* __restrict__
         out[i] = (TO)in[i];
 }
 
-// part[b][j] = sum_{i in chunk b} X_j[i] * y[i]
+// part[b][j] = sum_{i in chunk b} X_j[i] * y[i]; eight columns per pass over the chunk.
 template <class TX, class TY>
 __global__ __launch_bounds__(KB) void k_mdot_part(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                                   const TY* __restrict__ y, double* __restrict__ part) {
-    __shared__ double s4[4];
+    __shared__ double s8[4][8];
     const int64_t nb = gridDim.x;
     const int64_t chunk = (n + nb - 1) / nb;
     const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    for (int j = 0; j < K; ++j) {
-        const TX* xj = X + (int64_t)j * ld;
-        double acc = 0.0;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += KB) acc += (double)xj[i] * (double)y[i];
-        const double s = block_sum(acc, s4);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * K + j] = s;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < K; j0 += 8) {
+        const int nj = min(8, K - j0);
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += KB) {
+            const double yi = (double)y[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nj) acc[q] += (double)X[(int64_t)(j0 + q) * ld + i] * yi;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s8[w][q] = acc[q];
+        }
+        __syncthreads();
+        if (threadIdx.x < nj)
+            part[(int64_t)blockIdx.x * K + j0 + threadIdx.x] =
+                (s8[0][threadIdx.x] + s8[1][threadIdx.x]) + (s8[2][threadIdx.x] + s8[3][threadIdx.x]);
     }
 }
 
@@ -79,110 +96,96 @@ __global__ __launch_bounds__(KB) void k_gemv_cols(int64_t n, int K, const TX* __
     }
 }
 
-// Weighted Gram, stage 1: part[b] (K x K, upper blocks) = X^T diag(w2) X over chunk b,
-// w2 = 1/sqrt(nu^2 + eps^2) (or 1 when nu is null).  Rows are staged in LDS as double;
-// each thread owns a 4x4 block of the Gram for a slice of the staged rows.
-static constexpr int GCH = 32;  // rows staged per step
+// Weighted Gram G = X^T diag(w2) X (K <= 64), w2 = 1/sqrt(nu^2 + eps^2) (1 when nu is null),
+// on the FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16x4 block of X^T by a
+// 4x16 block of diag(w2) X.  Lane l supplies A[l%16][l/16] and B[l/16][l%16], which here
+// are the same entry X[16g + l%16][r0 + l/16] (times w2 for B); the 16x16 result sits in
+// four doubles per lane, D[l/16 + 4v][l%16] (layout checked on the device).  Each wave keeps the upper blocks of the
+// (K/16)^2 block grid for its rows; stage 1 writes one partial Gram per workgroup.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 template <class TX>
 __global__ __launch_bounds__(KB) void k_wgram_part(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                                    const TX* __restrict__ nu, double eps2,
                                                    double* __restrict__ part) {
-    __shared__ double sx[GCH][KMAX_SMALL + 1];
-    __shared__ double sred[(KMAX_SMALL / 4) * (KMAX_SMALL / 4 + 1) / 2 * 16];
-    const int nb4 = (K + 3) / 4;
-    const int npairs = nb4 * (nb4 + 1) / 2;
-    const int groups = max(1, KB / npairs);
-    const int tid = threadIdx.x;
-    const int pair = tid % npairs, grp = tid / npairs;
-    const bool active = tid < npairs * groups;
-    // block pair -> (bi, bj), bi <= bj
-    int bi = 0, bj = 0;
-    {
-        int p = pair, row = 0;
-        while (p >= nb4 - row) {
-            p -= nb4 - row;
-            ++row;
-        }
-        bi = row;
-        bj = row + p;
-    }
-    double acc[4][4];
+    __shared__ double sred[4][10][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int G = (K + 15) >> 4;
+    dbl4 acc[10];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-
+    for (int p = 0; p < 10; ++p) acc[p] = dbl4{0.0, 0.0, 0.0, 0.0};
     const int64_t nbk = gridDim.x;
-    const int64_t chunk = ((n + nbk - 1) / nbk + GCH - 1) / GCH * GCH;
+    const int64_t chunk = ((n + nbk - 1) / nbk + 15) / 16 * 16;
     const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    for (int64_t r0 = lo; r0 < hi; r0 += GCH) {
-        __syncthreads();
-        // stage rows r0..r0+GCH of every column (weights folded into a copy below)
-        for (int e = tid; e < GCH * K; e += KB) {
-            const int j = e / GCH, r = e % GCH;
-            const int64_t i = r0 + r;
-            sx[r][j] = (i < hi) ? (double)X[(int64_t)j * ld + i] : 0.0;
-        }
-        for (int j = K + tid; j < 4 * nb4; j += KB)
-            for (int r = 0; r < GCH; ++r) sx[r][j] = 0.0;
-        __syncthreads();
-        if (active) {
-            for (int r = grp; r < GCH; r += groups) {
-                const int64_t i = r0 + r;
-                if (i >= hi) break;
-                double w = 1.0;
-                if (nu) {
-                    const double a = (double)nu[i];
-                    w = 1.0 / sqrt(a * a + eps2);
-                }
-                double xa[4], xb[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    xa[a] = sx[r][4 * bi + a] * w;
-                    xb[a] = sx[r][4 * bj + a];
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += xa[a] * xb[b];
+    const int c = lane & 15;
+    for (int64_t r0 = lo + 4 * wave; r0 < hi; r0 += 16) {
+        const int64_t r = r0 + (lane >> 4);
+        const bool inr = r < hi;
+        double w = 0.0;
+        if (inr) {
+            if (nu) {
+                const double t = (double)nu[r];
+                w = 1.0 / sqrt(t * t + eps2);
+            } else {
+                w = 1.0;
             }
         }
-    }
-    // reduce the row groups into group 0 through LDS, highest group first (fixed order)
-    for (int g = groups - 1; g >= 1; --g) {
-        __syncthreads();
-        if (active && grp == g) {
+        double a[4], bw[4];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) sred[pair * 16 + e] = acc[e / 4][e % 4];
+        for (int g = 0; g < 4; ++g) {
+            const int col = 16 * g + c;
+            a[g] = (g < G && col < K && inr) ? (double)X[(int64_t)col * ld + r] : 0.0;
+            bw[g] = a[g] * w;
         }
-        __syncthreads();
-        if (active && grp == 0) {
+        int p = 0;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[e / 4][e % 4] += sred[pair * 16 + e];
-        }
+        for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+            for (int gj = gi; gj < 4; ++gj, ++p)
+                if (gj < G) acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[gi], bw[gj], acc[p], 0, 0, 0);
     }
-    if (active && grp == 0) {
-        double* out = part + (int64_t)blockIdx.x * KMAX_SMALL * KMAX_SMALL;
+    // combine the four waves in a fixed order and store the upper blocks
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+    for (int p = 0; p < 10; ++p)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int ii = 4 * bi + a, jj = 4 * bj + b;
-                if (ii < K && jj < K) out[(int64_t)ii * KMAX_SMALL + jj] = acc[a][b];
-            }
+        for (int v = 0; v < 4; ++v) sred[wave][p][v][lane] = acc[p][v];
+    __syncthreads();
+    double* out = part + (int64_t)blockIdx.x * KMAX_SMALL * KMAX_SMALL;
+    for (int e = threadIdx.x; e < 10 * 4 * 64; e += KB) {
+        const int p = e / 256, v = (e / 64) % 4, l = e % 64;
+        int gi = 0, gj = 0, q = p;
+        while (q >= 4 - gi) {
+            q -= 4 - gi;
+            ++gi;
+        }
+        gj = gi + q;
+        if (gj >= G) continue;
+        const int ii = 16 * gi + (l >> 4) + 4 * v, jj = 16 * gj + (l & 15);
+        if (ii >= K || jj >= K) continue;
+        const double val = (sred[0][p][v][l] + sred[1][p][v][l]) + (sred[2][p][v][l] + sred[3][p][v][l]);
+        out[(int64_t)ii * KMAX_SMALL + jj] = val;
     }
 }
 
-// Weighted Gram, stage 2: G[i][j] = sum_b part[b][i][j] for i <= j (block order), mirrored.
+// Weighted Gram, stage 2: G[i][j] = sum_b part[b][min(i,j)-block entry] in block order,
+// four partial sums per entry combined in a fixed order.
 __global__ __launch_bounds__(KB) void k_wgram_final(int nb, int K, const double* __restrict__ part,
                                                     double* __restrict__ G, int ldg) {
-    for (int e = blockIdx.x * KB + threadIdx.x; e < K * K; e += gridDim.x * KB) {
-        const int i = e / K, j = e % K;
-        if (i > j) continue;
-        double acc = 0.0;
-        for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * KMAX_SMALL * KMAX_SMALL + (int64_t)i * KMAX_SMALL + j];
-        G[(int64_t)i * ldg + j] = acc;
-        G[(int64_t)j * ldg + i] = acc;
+    __shared__ double s4[4][64];
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+    const int i = e / K, j = e % K;
+    double acc = 0.0;
+    if (e < K * K) {
+        // upper-block storage: the entry lives at (i, j) if its block is upper, else at (j, i)
+        const bool up = (i >> 4) <= (j >> 4);
+        const int ii = up ? i : j, jj = up ? j : i;
+        for (int b = grp; b < nb; b += 4) acc += part[(int64_t)b * KMAX_SMALL * KMAX_SMALL + (int64_t)ii * KMAX_SMALL + jj];
+    }
+    s4[grp][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (grp == 0 && e < K * K) {
+        const int t = threadIdx.x;
+        G[(int64_t)i * ldg + j] = (s4[0][t] + s4[1][t]) + (s4[2][t] + s4[3][t]);
     }
 }
 
@@ -302,7 +305,7 @@ template void weight_mul<float>(Ctx&, int64_t, const float*, double, const float
 template void weight_mul<double>(Ctx&, int64_t, const double*, double, const double*, double*);
 
 
-int mdot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 2048))); }
+int mdot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 1024))); }
 
 template <class TX, class TY>
 void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double alpha, double* out) {
@@ -340,15 +343,15 @@ template void gemv_cols<double>(Ctx&, int64_t, int, const double*, int64_t, cons
 
 template <class TX>
 void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TX* nu, double eps, double* G, int ldg) {
-    MMOF_CHECK(K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(512, cdiv(n, 4096)));
+    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(512, cdiv(n, 2048)));
     double* part = static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)512 * KMAX_SMALL * KMAX_SMALL));
     {
         ScopedTime st(&c, "wgram");
         hipLaunchKernelGGL(k_wgram_part<TX>, dim3(nb), dim3(KB), 0, c.stream, n, K, X, ld, nu, eps * eps, part);
         MMOF_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_wgram_final, dim3((unsigned)cdiv((int64_t)K * K, KB)), dim3(KB), 0, c.stream, nb, K, part,
+    hipLaunchKernelGGL(k_wgram_final, dim3((unsigned)cdiv((int64_t)K * K, 64)), dim3(KB), 0, c.stream, nb, K, part,
                        G, ldg);
     MMOF_LAUNCH_CHECK();
 }

@@ -7,11 +7,20 @@
 // lambda solves D(lambda) = eta*delta.  D^2 increases with lambda; its derivative is
 //   dD^2/dlambda = 2 lambda w^T (G_H + lambda G_T)^{-1} w,   w = G_T z.
 // The root is bracketed in mu = log10(lambda) on [-12, 12] + log10(tr G_H / tr G_T)
-// (the ends are taken when the root lies outside) and found by Newton steps in mu,
-// safeguarded by bisection of the bracket.  Each evaluation factors
-// G_H + lambda G_T by Cholesky in LDS.
+// (an end is taken when the root lies beyond it) and found by Newton steps in mu,
+// safeguarded by bisection of the bracket, starting from the previous lambda.
+//
+// One lane owns one row (K <= 64).  Each evaluation factors M = G_H + lambda G_T with a
+// left-looking Cholesky (the inner products only read LDS, so they pipeline) and solves
+// with the factor held in LDS and the right-hand side in registers, broadcasting the
+// pivot entries with readlane.
 #include "dev.h"
 #include "krylov.h"
+
+// Optional per-iteration trace (a probe build can define it; no-op in the library).
+#ifndef MMOF_SMALL_TRACE
+#define MMOF_SMALL_TRACE(it, mu, e, f, lo, hi)
+#endif
 
 namespace mmof {
 
@@ -20,89 +29,97 @@ static constexpr int KP = KMAX_SMALL + 1;  // padded row length (odd: no LDS ban
 struct SmallLds {
     double A[KMAX_SMALL][KP];
     double T[KMAX_SMALL][KP];
-    double M[KMAX_SMALL][KP];
-    double d[KMAX_SMALL], z[KMAX_SMALL], w[KMAX_SMALL], y[KMAX_SMALL];
+    double L[KMAX_SMALL][KP];
+    double invd[KMAX_SMALL];
 };
 
-// Cholesky of M (lower, in place); returns false on a non-positive pivot.
-__device__ bool chol(SmallLds& s, int K) {
-    const int lane = threadIdx.x;
+__device__ __forceinline__ double bcast(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave sum whose result is bitwise identical in every lane: the root finder branches on
+// it, and a butterfly alone is not lane-symmetric once the compiler fuses the first add
+// with the product that feeds it.  Lane 0's sum is broadcast.
+__device__ __forceinline__ double wave_sum64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return bcast(v, 0);
+}
+
+// Left-looking Cholesky of M = A + lam T into s.L (lower) and s.invd; false on a
+// non-positive pivot (uniform across the wave).
+__device__ bool chol(SmallLds& s, int K, double lam) {
+    const int i = threadIdx.x;
     for (int k = 0; k < K; ++k) {
-        const double piv = s.M[k][k];
+        double dot = 0.0;
+        if (i >= k && i < K) {
+#pragma unroll 8
+            for (int j = 0; j < k; ++j) dot += s.L[i][j] * s.L[k][j];
+        }
+        const double mik = (i < K) ? s.A[i][k] + lam * s.T[i][k] - dot : 0.0;
+        const double piv = bcast(mik, k);
         if (!(piv > 0.0)) return false;
         const double lkk = sqrt(piv);
-        __syncthreads();
-        for (int i = k + lane; i < K; i += 64) s.M[i][k] = (i == k) ? lkk : s.M[i][k] / lkk;
-        __syncthreads();
-        for (int i = k + 1 + lane; i < K; i += 64) {
-            const double lik = s.M[i][k];
-            for (int j = k + 1; j <= i; ++j) s.M[i][j] -= lik * s.M[j][k];
+        const double inv = 1.0 / lkk;
+        if (i > k && i < K) s.L[i][k] = mik * inv;
+        if (i == k) {
+            s.L[k][k] = lkk;
+            s.invd[k] = inv;
         }
         __syncthreads();
     }
     return true;
 }
 
-// Solve L L^T x = b with the factor in s.M; b is read from `in`, x is written to `out`
-// (both LDS vectors, may alias).
-__device__ void chol_solve(SmallLds& s, int K, const double* in, double* out) {
-    const int lane = threadIdx.x;
-    for (int i = lane; i < K; i += 64) s.y[i] = in[i];
-    __syncthreads();
-    for (int k = 0; k < K; ++k) {
-        const double yk = s.y[k] / s.M[k][k];
-        __syncthreads();
-        for (int i = k + 1 + lane; i < K; i += 64) s.y[i] -= s.M[i][k] * yk;
-        if (lane == 0) s.y[k] = yk;
-        __syncthreads();
+// x = M^{-1} b with the factor in s.L; b and x are per-lane registers (row i = lane).
+__device__ double chol_solve(SmallLds& s, int K, double b) {
+    const int i = threadIdx.x;
+    double y = b;
+    for (int k = 0; k < K; ++k) {  // L y = b
+        const double yk = bcast(y, k) * s.invd[k];
+        if (i == k) y = yk;
+        if (i > k && i < K) y -= s.L[i][k] * yk;
     }
-    for (int k = K - 1; k >= 0; --k) {
-        const double xk = s.y[k] / s.M[k][k];
-        __syncthreads();
-        for (int i = lane; i < k; i += 64) s.y[i] -= s.M[k][i] * xk;
-        if (lane == 0) s.y[k] = xk;
-        __syncthreads();
+    for (int k = K - 1; k >= 0; --k) {  // L^T x = y
+        const double xk = bcast(y, k) * s.invd[k];
+        if (i == k) y = xk;
+        if (i < k) y -= s.L[k][i] * xk;
     }
-    for (int i = lane; i < K; i += 64) out[i] = s.y[i];
-    __syncthreads();
+    return i < K ? y : 0.0;
 }
 
-__device__ double dot_lds(const double* a, const double* b, int K) {
+// (T z)_i for the lane's row, z distributed one entry per lane.
+__device__ double matvec_T(SmallLds& s, int K, double z) {
+    const int i = threadIdx.x;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < K; i += 64) acc += a[i] * b[i];
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    return acc;  // all lanes hold the same value
+    for (int j = 0; j < K; ++j) {
+        const double zj = bcast(z, j);
+        if (i < K) acc += s.T[i][j] * zj;
+    }
+    return acc;
 }
 
-// One evaluation at lambda: z, D^2 and (optionally) dD^2/dmu.  Returns false if the
-// Cholesky factorization failed.
-__device__ bool evaluate(SmallLds& s, int K, double lam, double bb, bool deriv, double& D2, double& dD2) {
-    const int lane = threadIdx.x;
-    for (int i = lane; i < K; i += 64)
-        for (int j = 0; j <= i; ++j) s.M[i][j] = s.A[i][j] + lam * s.T[i][j];
-    __syncthreads();
-    if (!chol(s, K)) return false;
-    chol_solve(s, K, s.d, s.z);
-    for (int i = lane; i < K; i += 64) {
-        double acc = 0.0;
-        for (int j = 0; j < K; ++j) acc += s.T[i][j] * s.z[j];
-        s.w[i] = acc;
-    }
-    __syncthreads();
-    const double dz = dot_lds(s.d, s.z, K);
-    const double zTz = dot_lds(s.z, s.w, K);
-    D2 = bb - dz - lam * zTz;
-    dD2 = 0.0;
+struct Eval {
+    bool ok;
+    double D2, dD2, z;  // z: this lane's entry
+};
+
+__device__ Eval evaluate(SmallLds& s, int K, double lam, double bb, double d, bool deriv) {
+    Eval e{false, 0.0, 0.0, 0.0};
+    if (!chol(s, K, lam)) return e;
+    e.ok = true;
+    e.z = chol_solve(s, K, d);
+    const double w = matvec_T(s, K, e.z);
+    const double dz = wave_sum64(d * e.z);
+    const double zw = wave_sum64(e.z * w);
+    e.D2 = bb - dz - lam * zw;
     if (deriv) {
-        // dD^2/dmu = ln(10) * lambda * 2 lambda w^T M^{-1} w
-        __shared__ double sv[KMAX_SMALL];
-        for (int i = lane; i < K; i += 64) sv[i] = s.w[i];
-        __syncthreads();
-        chol_solve(s, K, sv, sv);
-        const double wMw = dot_lds(s.w, sv, K);
-        dD2 = 2.302585092994046 * 2.0 * lam * lam * wMw;
+        const double q = chol_solve(s, K, w);
+        e.dD2 = 2.302585092994046 * 2.0 * lam * lam * wave_sum64(w * q);
     }
-    return true;
+    return e;
 }
 
 __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restrict__ GA, const double* __restrict__ GT,
@@ -110,70 +127,81 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
                                                     double fixed_lambda, double* __restrict__ zout,
                                                     double* __restrict__ res) {
     __shared__ SmallLds s;
-    const int lane = threadIdx.x;
-    for (int i = lane; i < K; i += 64) {
+    const int i = threadIdx.x;
+    if (i < K) {
         for (int j = 0; j < K; ++j) {
             s.A[i][j] = GA[(int64_t)i * KMAX_SMALL + j];
             s.T[i][j] = GT[(int64_t)i * KMAX_SMALL + j];
         }
-        s.d[i] = dvec[i];
     }
+    const double d = i < K ? dvec[i] : 0.0;
     __syncthreads();
     const double bb = sc[0], target = sc[1];
-    double D2 = 0.0, dD2 = 0.0;
-    double lam;
+    double lam = fixed_lambda;
     int status = 0;
+    Eval e{false, 0.0, 0.0, 0.0};
     if (fixed_lambda > 0.0) {
-        lam = fixed_lambda;
-        if (!evaluate(s, K, lam, bb, false, D2, dD2)) status = 4;
+        e = evaluate(s, K, lam, bb, d, false);
     } else {
-        double trA = 0.0, trT = 0.0;
-        for (int i = 0; i < K; ++i) {
-            trA += s.A[i][i];
-            trT += s.T[i][i];
-        }
+        const double trA = wave_sum64(i < K ? s.A[i][i] : 0.0);
+        const double trT = wave_sum64(i < K ? s.T[i][i] : 0.0);
         const double shift = log10(trA / fmax(trT, 1e-300));
-        double lo = -12.0 + shift, hi = 12.0 + shift;
-        bool ok_lo = evaluate(s, K, pow(10.0, lo), bb, false, D2, dD2);
-        if (ok_lo && D2 > target) {
-            lam = pow(10.0, lo);
-            status = 2;
-        } else {
-            bool ok_hi = evaluate(s, K, pow(10.0, hi), bb, false, D2, dD2);
-            if (ok_hi && D2 < target) {
-                lam = pow(10.0, hi);
-                status = 2;
-            } else {
-                double mu = 0.5 * (lo + hi);
-                const double prev = sc[2];
-                if (prev > 0.0) {
-                    const double m = log10(prev);
-                    if (m > lo && m < hi) mu = m;
-                }
-                for (int it = 0; it < 200; ++it) {
-                    const bool ok = evaluate(s, K, pow(10.0, mu), bb, true, D2, dD2);
-                    const double f = ok ? D2 - target : -target;
-                    if (f < 0.0)
-                        lo = mu;
-                    else
-                        hi = mu;
-                    // stop at the rounding level of D^2 or of mu
-                    if (ok && fabs(f) <= 1e-14 * bb) break;
-                    if (hi - lo <= 1e-14 * fmax(1.0, fabs(mu))) break;
-                    double nmu = (ok && dD2 > 0.0) ? mu - f / dD2 : 0.5 * (lo + hi);
-                    if (!(nmu > lo && nmu < hi)) nmu = 0.5 * (lo + hi);
-                    if (fabs(nmu - mu) <= 1e-14 * fmax(1.0, fabs(mu))) break;
-                    mu = nmu;
-                }
-                lam = pow(10.0, mu);
-                if (!evaluate(s, K, lam, bb, false, D2, dD2)) status = 4;
-            }
+        const double LO = -12.0 + shift, HI = 12.0 + shift;
+        double lo = LO, hi = HI;
+        bool lo_checked = false, hi_checked = false;
+        double mu = 0.5 * (lo + hi);
+        const double prev = sc[2];
+        if (prev > 0.0) {
+            const double m = log10(prev);
+            if (m > lo && m < hi) mu = m;
         }
+        bool done = false;
+        for (int it = 0; it < 200 && !done; ++it) {
+            e = evaluate(s, K, pow(10.0, mu), bb, d, true);
+            const double f = e.ok ? e.D2 - target : -target;
+            MMOF_SMALL_TRACE(it, mu, e, f, lo, hi);
+            if (f < 0.0) {
+                lo = mu;
+                if (!hi_checked) {  // the root may lie beyond the upper end
+                    hi_checked = true;
+                    // (e keeps z, D^2 and the derivative at mu in registers)
+                    const Eval eh = evaluate(s, K, pow(10.0, HI), bb, d, false);
+                    if (eh.ok && eh.D2 < target) {
+                        e = eh;
+                        mu = HI;
+                        status = 2;
+                        break;
+                    }
+                }
+            } else {
+                hi = mu;
+                if (!lo_checked) {  // the root may lie below the lower end
+                    lo_checked = true;
+                    const Eval el = evaluate(s, K, pow(10.0, LO), bb, d, false);
+                    if (el.ok && el.D2 > target) {
+                        e = el;
+                        mu = LO;
+                        status = 2;
+                        break;
+                    }
+                }
+            }
+            // stop at the rounding level of D^2 or of mu
+            if (e.ok && fabs(f) <= 1e-14 * bb) break;
+            if (hi - lo <= 1e-14 * fmax(1.0, fabs(mu))) break;
+            double nmu = (e.ok && e.dD2 > 0.0) ? mu - f / e.dD2 : 0.5 * (lo + hi);
+            if (!(nmu > lo && nmu < hi)) nmu = 0.5 * (lo + hi);
+            if (fabs(nmu - mu) <= 1e-14 * fmax(1.0, fabs(mu))) done = true;
+            mu = nmu;
+            if (done) e = evaluate(s, K, pow(10.0, mu), bb, d, false);
+        }
+        lam = pow(10.0, mu);
     }
-    for (int i = lane; i < K; i += 64) zout[i] = status == 4 ? 0.0 : s.z[i];
-    if (lane == 0) {
+    if (!e.ok) status = 4;
+    if (i < K) zout[i] = e.ok ? e.z : 0.0;
+    if (i == 0) {
         res[0] = lam;
-        res[1] = D2;
+        res[1] = e.D2;
         res[2] = (double)status;
     }
 }

@@ -11,6 +11,8 @@
 // Theta = [Psi; M-bar(v); M-bar'(v')] is stored row block after row block:
 // [gx (all frames) | gy (all frames) | forward flow rows | reverse flow rows].
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.h"
@@ -108,6 +110,7 @@ struct Solver {
         if (!flow) return;
         launch_flow_fwd(c, g, dt, +1, p.interp, in, flow_v, out + oRF);
         if (p.use_reverse) launch_flow_fwd(c, g, dt, -1, p.interp, in, flow_vr, out + oRR);
+        if (rep) rep->n_L += p.use_reverse ? 2 : 1;
     }
     void theta(const TX* in, TX* out) {
         launch_grad_fwd(c, g, dt, in, nullptr, nullptr, out + oGX, out + oGY);
@@ -119,6 +122,7 @@ struct Solver {
         if (flow) {
             launch_flow_adj(c, g, dt, +1, p.interp, in + oRF, flow_v, out, true, rad_v);
             if (p.use_reverse) launch_flow_adj(c, g, dt, -1, p.interp, in + oRR, flow_vr, out, true, rad_vr);
+            if (rep) rep->n_L += p.use_reverse ? 2 : 1;
         }
         if (rep) rep->n_thetaT++;
     }
@@ -155,6 +159,28 @@ struct Solver {
 
     const double* b = nullptr;
 
+    // With MMOF_DUMP_PROJECTED=<path>, a failed projected solve writes K, G_H, G_T, d and the
+    // scalars (binary doubles) for offline inspection.
+    void dump_projected(int K) {
+        const char* path = std::getenv("MMOF_DUMP_PROJECTED");
+        if (!path) return;
+        std::vector<double> buf(2 * KMAX_SMALL * KMAX_SMALL + KMAX_SMALL + 8);
+        (void)hipStreamSynchronize(c.stream);
+        (void)hipMemcpy(buf.data(), GA, sizeof(double) * KMAX_SMALL * KMAX_SMALL, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(buf.data() + KMAX_SMALL * KMAX_SMALL, GT, sizeof(double) * KMAX_SMALL * KMAX_SMALL,
+                        hipMemcpyDeviceToHost);
+        (void)hipMemcpy(buf.data() + 2 * KMAX_SMALL * KMAX_SMALL, dvec, sizeof(double) * KMAX_SMALL,
+                        hipMemcpyDeviceToHost);
+        (void)hipMemcpy(buf.data() + 2 * KMAX_SMALL * KMAX_SMALL + KMAX_SMALL, sc, sizeof(double) * 3,
+                        hipMemcpyDeviceToHost);
+        if (FILE* f = std::fopen(path, "wb")) {
+            const double kk = K;
+            std::fwrite(&kk, sizeof(double), 1, f);
+            std::fwrite(buf.data(), sizeof(double), buf.size(), f);
+            std::fclose(f);
+        }
+    }
+
     int run(const double* b_, double delta, double* u_io, void* v_out, void* vr_out) {
         b = b_;
         MMOF_CHECK(Kcap >= 1 && Kcap <= KMAX_SMALL, MMOF_ERR_SHAPE,
@@ -164,7 +190,7 @@ struct Solver {
         MMOF_CHECK(p.eps > 0 && p.alpha > 0 && p.eta > 0, MMOF_ERR_INVALID, "eps, alpha, eta must be > 0");
         alloc();
         if (rep) {
-            rep->n_A = rep->n_At = rep->n_theta = rep->n_thetaT = rep->n_flow_updates = 0;
+            rep->n_A = rep->n_At = rep->n_theta = rep->n_thetaT = rep->n_flow_updates = rep->n_L = 0;
             rep->iters = 0;
             rep->status = 0;
         }
@@ -300,7 +326,11 @@ struct Solver {
             const int st = (int)host[4];
             iters = k + 1;
             if (st == 2) status = std::max(status, (int)MMOF_WARN_DP_CLAMPED);
-            if (st == 4) throw Error(MMOF_ERR_NONFINITE, "projected system is not positive definite");
+            if (st == 4) {
+                dump_projected(K);
+                throw Error(MMOF_ERR_NONFINITE, "projected system is not positive definite (iteration " +
+                                                    std::to_string(k) + ", " + std::to_string(K) + " columns)");
+            }
             double rre = p.u_true ? std::sqrt(std::max(rre2, 0.0)) / utn : 0.0;
             if (rep && k < rep->capacity) {
                 if (rep->lambda) rep->lambda[k] = lam;

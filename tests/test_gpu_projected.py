@@ -1,0 +1,71 @@
+"""GPU parity of the projected-problem steps of MMGKS (FP64 Krylov side) at every basis size.
+
+* weighted Gram X^T diag(w2) X on the matrix cores vs numpy, K = 1..64 (all block-grid shapes);
+* projected solve + discrepancy principle vs the oracle's bisection on the same Grams.
+"""
+import numpy as np
+import pytest
+
+from oracle import mmgks
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch  # noqa: F401
+    from paper_2501_12497_amd import binding
+    return binding
+
+
+@pytest.mark.parametrize("K", [1, 5, 16, 17, 31, 33, 40, 48, 63, 64])
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_weighted_gram(B, K, which):
+    import torch
+    dt = torch.float64 if which == "f64" else torch.float32
+    r = np.random.default_rng(K)
+    n = 50000 + 37 * K
+    X = r.standard_normal((K, n))
+    nu = r.standard_normal(n) * np.logspace(-4, 0, n)
+    if dt == torch.float32:
+        X = X.astype(np.float32).astype(np.float64)
+        nu = nu.astype(np.float32).astype(np.float64)
+    G = B.weighted_gram(torch.as_tensor(X, dtype=dt, device="cuda"), torch.as_tensor(nu, dtype=dt, device="cuda"),
+                        1e-3).cpu().numpy()
+    w = mmgks.mm_weights_sq(nu, 1e-3)
+    exp = X @ (w[:, None] * X.T)
+    assert np.abs(G - exp).max() <= 1e-12 * np.abs(exp).max()
+    G1 = B.weighted_gram(torch.as_tensor(X, dtype=dt, device="cuda")).cpu().numpy()
+    assert np.abs(G1 - X @ X.T).max() <= 1e-12 * np.abs(X @ X.T).max()
+
+
+@pytest.mark.parametrize("K", [3, 20, 39, 64])
+def test_projected_solve_matches_oracle_dp(B, K):
+    import torch
+    r = np.random.default_rng(100 + K)
+    m, n = 3 * K + 50, 2 * K + 40
+    RA = r.standard_normal((m, K))
+    RT = r.standard_normal((n, K)) * r.uniform(0.1, 10, size=K)
+    b = r.standard_normal(m) * 3 + RA @ r.standard_normal(K)
+    QA, RAq = np.linalg.qr(RA)
+    _, RTq = np.linalg.qr(RT)
+    QAtb = QA.T @ b
+    bb = float(b @ b)
+    # a target between the two ends so that a root exists
+    lo_d = mmgks.discrepancy(RAq, QAtb, RTq, 1e-8, bb)[0]
+    hi_d = mmgks.discrepancy(RAq, QAtb, RTq, 1e8, bb)[0]
+    target = 0.5 * (lo_d + hi_d)
+    lam_or, st_or = mmgks.dp_lambda(RAq, QAtb, RTq, bb, target)
+    z_or = mmgks.projected_solve(RAq, QAtb, RTq, lam_or)
+    GA, GT, d = RA.T @ RA, RT.T @ RT, RA.T @ b
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+    z, lam, D2, st = B.projected_solve(dev(GA), dev(GT), dev(d), bb, target * target)
+    assert st == st_or == 0
+    assert abs(lam - lam_or) <= 1e-9 * lam_or
+    np.testing.assert_allclose(z.cpu().numpy(), z_or, rtol=1e-7, atol=1e-9 * np.abs(z_or).max())
+    assert abs(np.sqrt(D2) - target) <= 1e-10 * target
+    # clamped ends
+    z, lam, D2, st = B.projected_solve(dev(GA), dev(GT), dev(d), bb, (0.1 * lo_d) ** 2)
+    assert st == 2
+    z, lam, D2, st = B.projected_solve(dev(GA), dev(GT), dev(d), bb, (10 * hi_d) ** 2)
+    assert st == 2
