@@ -376,10 +376,18 @@ int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const 
         need(G, "G");
         MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX_SMALL && ld >= n && ldg >= K, MMOF_ERR_SHAPE, "bad Gram sizes");
         MMOF_CHECK(!nu || eps > 0, MMOF_ERR_INVALID, "eps must be > 0");
+        double* w = nullptr;
+        if (nu) {
+            w = static_cast<double*>(ctx->work("gram_w", sizeof(double) * (size_t)n));
+            if (dt == MMOF_F32)
+                mm_weights_f64<float>(*ctx, n, (const float*)nu, eps, w);
+            else
+                mm_weights_f64<double>(*ctx, n, (const double*)nu, eps, w);
+        }
         if (dt == MMOF_F32)
-            wgram<float>(*ctx, n, K, (const float*)X, ld, (const float*)nu, eps, G, ldg);
+            wgram<float>(*ctx, n, K, (const float*)X, ld, w, G, ldg);
         else
-            wgram<double>(*ctx, n, K, (const double*)X, ld, (const double*)nu, eps, G, ldg);
+            wgram<double>(*ctx, n, K, (const double*)X, ld, w, G, ldg);
         return MMOF_OK;
     });
 }

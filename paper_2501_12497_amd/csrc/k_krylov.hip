@@ -30,6 +30,15 @@ __device__ __forceinline__ double block_sum(double v, double* s4) {
     return r;
 }
 
+// FP64 MM weights w2 = 1/sqrt(nu^2 + eps^2) of the rows of Theta.
+template <class TX>
+__global__ void k_mm_weights_f64(int64_t n, const TX* __restrict__ nu, double eps2, double* __restrict__ w) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)nu[i];
+        w[i] = 1.0 / sqrt(a * a + eps2);
+    }
+}
+
 template <class TI, class TO>
 __global__ void k_convert(int64_t n, const TI* __restrict__ in, TO* __restrict__ out) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -105,88 +114,119 @@ __global__ __launch_bounds__(KB) void k_gemv_cols(int64_t n, int K, const TX* __
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <class TX>
+struct GramStep {
+    TX x[4][4];   // [row group u][column group g]
+    double w[4];  // row weights
+};
+
+template <class TX>
+__device__ __forceinline__ void gram_load(GramStep<TX>& st, const TX* __restrict__ X, int64_t ld,
+                                          const double* __restrict__ w, int64_t r0, int64_t hi, int K, int G,
+                                          int lane) {
+    const int c = lane & 15;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t r = r0 + 4 * u + (lane >> 4);
+        const bool inr = r < hi;
+        st.w[u] = inr ? (w ? w[r] : 1.0) : 0.0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int col = 16 * g + c;
+            st.x[u][g] = (g < G && col < K && inr) ? X[(int64_t)col * ld + r] : TX(0);
+        }
+    }
+}
+
+template <class TX>
 __global__ __launch_bounds__(KB) void k_wgram_part(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
-                                                   const TX* __restrict__ nu, double eps2,
-                                                   double* __restrict__ part) {
-    __shared__ double sred[4][10][4][64];
+                                                   const double* __restrict__ w, double* __restrict__ part) {
+    __shared__ double sred[2][10][4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int G = (K + 15) >> 4;
     dbl4 acc[10];
 #pragma unroll
     for (int p = 0; p < 10; ++p) acc[p] = dbl4{0.0, 0.0, 0.0, 0.0};
     const int64_t nbk = gridDim.x;
-    const int64_t chunk = ((n + nbk - 1) / nbk + 15) / 16 * 16;
+    const int64_t chunk = ((n + nbk - 1) / nbk + 63) / 64 * 64;
     const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    const int c = lane & 15;
-    for (int64_t r0 = lo + 4 * wave; r0 < hi; r0 += 16) {
-        const int64_t r = r0 + (lane >> 4);
-        const bool inr = r < hi;
-        double w = 0.0;
-        if (inr) {
-            if (nu) {
-                const double t = (double)nu[r];
-                w = 1.0 / sqrt(t * t + eps2);
-            } else {
-                w = 1.0;
-            }
-        }
-        double a[4], bw[4];
+    // Each wave takes 4 groups of 4 rows per step (16 rows), the block 64 rows per step.
+    // The next step's loads are issued before the current step's MFMAs.
+    GramStep<TX> cur, nxt;
+    int64_t r0 = lo + 16 * wave;
+    if (r0 < hi) gram_load(cur, X, ld, w, r0, hi, K, G, lane);
+    for (; r0 < hi; r0 += 64) {
+        if (r0 + 64 < hi) gram_load(nxt, X, ld, w, r0 + 64, hi, K, G, lane);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int col = 16 * g + c;
-            a[g] = (g < G && col < K && inr) ? (double)X[(int64_t)col * ld + r] : 0.0;
-            bw[g] = a[g] * w;
+        for (int u = 0; u < 4; ++u) {
+            const double wu = cur.w[u];
+            double a[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) a[g] = (double)cur.x[u][g];
+            int p = 0;
+#pragma unroll
+            for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+                for (int gj = gi; gj < 4; ++gj, ++p)
+                    if (gj < G) acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[gi], a[gj] * wu, acc[p], 0, 0, 0);
         }
+        cur = nxt;
+    }
+    // combine the four waves in a fixed order: (w2, w3) into (w0, w1), then w1 into w0
+    if (wave >= 2) {
+#pragma unroll
+        for (int p = 0; p < 10; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sred[wave - 2][p][v][lane] = acc[p][v];
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+        for (int p = 0; p < 10; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[p][v] += sred[wave][p][v][lane];
+    }
+    __syncthreads();
+    if (wave == 1) {
+#pragma unroll
+        for (int p = 0; p < 10; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sred[0][p][v][lane] = acc[p][v];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double* out = part + (int64_t)blockIdx.x * KMAX_SMALL * KMAX_SMALL;
         int p = 0;
 #pragma unroll
         for (int gi = 0; gi < 4; ++gi)
 #pragma unroll
-            for (int gj = gi; gj < 4; ++gj, ++p)
-                if (gj < G) acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[gi], bw[gj], acc[p], 0, 0, 0);
-    }
-    // combine the four waves in a fixed order and store the upper blocks
+            for (int gj = gi; gj < 4; ++gj, ++p) {
+                if (gj >= G) continue;
 #pragma unroll
-    for (int p = 0; p < 10; ++p)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sred[wave][p][v][lane] = acc[p][v];
-    __syncthreads();
-    double* out = part + (int64_t)blockIdx.x * KMAX_SMALL * KMAX_SMALL;
-    for (int e = threadIdx.x; e < 10 * 4 * 64; e += KB) {
-        const int p = e / 256, v = (e / 64) % 4, l = e % 64;
-        int gi = 0, gj = 0, q = p;
-        while (q >= 4 - gi) {
-            q -= 4 - gi;
-            ++gi;
-        }
-        gj = gi + q;
-        if (gj >= G) continue;
-        const int ii = 16 * gi + (l >> 4) + 4 * v, jj = 16 * gj + (l & 15);
-        if (ii >= K || jj >= K) continue;
-        const double val = (sred[0][p][v][l] + sred[1][p][v][l]) + (sred[2][p][v][l] + sred[3][p][v][l]);
-        out[(int64_t)ii * KMAX_SMALL + jj] = val;
+                for (int v = 0; v < 4; ++v) {
+                    const int ii = 16 * gi + (lane >> 4) + 4 * v, jj = 16 * gj + (lane & 15);
+                    if (ii < K && jj < K) out[(int64_t)ii * KMAX_SMALL + jj] = acc[p][v] + sred[0][p][v][lane];
+                }
+            }
     }
 }
 
-// Weighted Gram, stage 2: G[i][j] = sum_b part[b][min(i,j)-block entry] in block order,
-// four partial sums per entry combined in a fixed order.
+// Weighted Gram, stage 2: G[i][j] = sum_b part[b][entry].  Four entries per workgroup, one
+// wavefront per entry: lane l sums partials l, l+64, ... and the wave combines them with a
+// fixed butterfly.
 __global__ __launch_bounds__(KB) void k_wgram_final(int nb, int K, const double* __restrict__ part,
                                                     double* __restrict__ G, int ldg) {
-    __shared__ double s4[4][64];
-    const int e = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= K * K) return;
     const int i = e / K, j = e % K;
+    // upper-block storage: the entry lives at (i, j) if its block is upper, else at (j, i)
+    const bool up = (i >> 4) <= (j >> 4);
+    const int ii = up ? i : j, jj = up ? j : i;
+    const double* src = part + (int64_t)ii * KMAX_SMALL + jj;
     double acc = 0.0;
-    if (e < K * K) {
-        // upper-block storage: the entry lives at (i, j) if its block is upper, else at (j, i)
-        const bool up = (i >> 4) <= (j >> 4);
-        const int ii = up ? i : j, jj = up ? j : i;
-        for (int b = grp; b < nb; b += 4) acc += part[(int64_t)b * KMAX_SMALL * KMAX_SMALL + (int64_t)ii * KMAX_SMALL + jj];
-    }
-    s4[grp][threadIdx.x & 63] = acc;
-    __syncthreads();
-    if (grp == 0 && e < K * K) {
-        const int t = threadIdx.x;
-        G[(int64_t)i * ldg + j] = (s4[0][t] + s4[1][t]) + (s4[2][t] + s4[3][t]);
-    }
+    for (int b = lane; b < nb; b += 64) acc += src[(int64_t)b * KMAX_SMALL * KMAX_SMALL];
+    acc = wave_sum(acc);
+    if (lane == 0) G[(int64_t)i * ldg + j] = acc;
 }
 
 // Scale x by 1/s[0] when s[0] > thr, else leave a zero column; s holds ||x||.
@@ -255,14 +295,11 @@ __global__ void k_put_rowcol(double* __restrict__ G, int ldg, int j, const doubl
     }
 }
 
-// y = w2(nu) * x in TX
+// y = w * x in TX (w: FP64 MM weights)
 template <class TX>
-__global__ void k_weight_mul(int64_t n, const TX* __restrict__ nu, double eps2, const TX* __restrict__ x,
-                             TX* __restrict__ y) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double a = (double)nu[i];
-        y[i] = (TX)((double)x[i] / sqrt(a * a + eps2));
-    }
+__global__ void k_weight_mul(int64_t n, const double* __restrict__ w, const TX* __restrict__ x, TX* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (TX)((double)x[i] * w[i]);
 }
 
 // ------------------------------------------------------------------------ host launchers
@@ -297,12 +334,12 @@ void put_rowcol(Ctx& c, double* G, int ldg, int j, const double* h) {
     MMOF_LAUNCH_CHECK();
 }
 template <class TX>
-void weight_mul(Ctx& c, int64_t n, const TX* nu, double eps, const TX* x, TX* y) {
-    hipLaunchKernelGGL(k_weight_mul<TX>, grid_for(n, KB, 8192), dim3(KB), 0, c.stream, n, nu, eps * eps, x, y);
+void weight_mul(Ctx& c, int64_t n, const double* w, const TX* x, TX* y) {
+    hipLaunchKernelGGL(k_weight_mul<TX>, grid_for(n, KB, 8192), dim3(KB), 0, c.stream, n, w, x, y);
     MMOF_LAUNCH_CHECK();
 }
-template void weight_mul<float>(Ctx&, int64_t, const float*, double, const float*, float*);
-template void weight_mul<double>(Ctx&, int64_t, const double*, double, const double*, double*);
+template void weight_mul<float>(Ctx&, int64_t, const double*, const float*, float*);
+template void weight_mul<double>(Ctx&, int64_t, const double*, const double*, double*);
 
 
 int mdot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 1024))); }
@@ -342,21 +379,29 @@ template void gemv_cols<float>(Ctx&, int64_t, int, const float*, int64_t, const 
 template void gemv_cols<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double, double, double*);
 
 template <class TX>
-void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TX* nu, double eps, double* G, int ldg) {
+void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w) {
+    hipLaunchKernelGGL(k_mm_weights_f64<TX>, grid_for(n, KB, 8192), dim3(KB), 0, c.stream, n, nu, eps * eps, w);
+    MMOF_LAUNCH_CHECK();
+}
+template void mm_weights_f64<float>(Ctx&, int64_t, const float*, double, double*);
+template void mm_weights_f64<double>(Ctx&, int64_t, const double*, double, double*);
+
+template <class TX>
+void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg) {
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(512, cdiv(n, 2048)));
-    double* part = static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)512 * KMAX_SMALL * KMAX_SMALL));
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(n, 1024)));
+    double* part = static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)256 * KMAX_SMALL * KMAX_SMALL));
     {
         ScopedTime st(&c, "wgram");
-        hipLaunchKernelGGL(k_wgram_part<TX>, dim3(nb), dim3(KB), 0, c.stream, n, K, X, ld, nu, eps * eps, part);
+        hipLaunchKernelGGL(k_wgram_part<TX>, dim3(nb), dim3(KB), 0, c.stream, n, K, X, ld, w, part);
         MMOF_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_wgram_final, dim3((unsigned)cdiv((int64_t)K * K, 64)), dim3(KB), 0, c.stream, nb, K, part,
+    hipLaunchKernelGGL(k_wgram_final, dim3((unsigned)cdiv((int64_t)K * K, 4)), dim3(KB), 0, c.stream, nb, K, part,
                        G, ldg);
     MMOF_LAUNCH_CHECK();
 }
-template void wgram<float>(Ctx&, int64_t, int, const float*, int64_t, const float*, double, double*, int);
-template void wgram<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double, double*, int);
+template void wgram<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int);
+template void wgram<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double*, int);
 
 template <class TI, class TO>
 void convert(Ctx& c, int64_t n, const TI* in, TO* out) {

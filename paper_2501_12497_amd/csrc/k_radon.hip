@@ -48,17 +48,19 @@ __global__ __launch_bounds__(256) void k_transpose_frames(const Tile* __restrict
     }
 }
 
+// One workgroup per (frame, angle, 64 bins): lane = bin, the four waves walk disjoint
+// quarters of the rows and their partial sums are added in a fixed order.
 template <class T>
 __global__ __launch_bounds__(256) void k_radon_fwd(const RayTile* __restrict__ rays, int64_t n_rays,
                                                    const RadonFrame* __restrict__ rf, const double2* __restrict__ trig,
                                                    const T* __restrict__ u, const T* __restrict__ ut,
                                                    T* __restrict__ b) {
-    const int64_t wid = xcd_remap(blockIdx.x, gridDim.x) * 4 + threadIdx.x / 64;
-    if (wid >= n_rays) return;
+    __shared__ T part[4][64];
+    const int64_t wid = xcd_remap(blockIdx.x, gridDim.x);
     const RayTile rt = rays[wid];
     const RadonFrame f = rf[rt.frame];
-    const int j = rt.bin0 + (int)(threadIdx.x % 64);
-    if (j >= f.n_bins) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = rt.bin0 + lane;
     const double2 cs = trig[f.trig_off + rt.angle];
     const double c = cs.x, s = cs.y;
     const double cx = 0.5 * (f.nx - 1), cy = 0.5 * (f.ny - 1);
@@ -74,22 +76,29 @@ __global__ __launch_bounds__(256) void k_radon_fwd(const RayTile* __restrict__ r
     const double xs0 = ccol + (dj + crow * bb) / a;
     const double step = -bb / a;
     const T aa = (T)fabs(a);
+    const int q = (nrow + 3) >> 2;
+    const int r_lo = wave * q, r_hi = min(nrow, r_lo + q);
     T acc = T(0);
-    for (int r = 0; r < nrow; ++r) {
-        const double xs = fma((double)r, step, xs0);
-        const double fl = floor(xs);
-        const int xi = (int)fl;
-        const T fr = (T)(xs - fl);
-        const T* row = img + (int64_t)r * ncol;
+    if (j < f.n_bins) {
+        for (int r = r_lo; r < r_hi; ++r) {
+            const double xs = fma((double)r, step, xs0);
+            const double fl = floor(xs);
+            const int xi = (int)fl;
+            const T fr = (T)(xs - fl);
+            const T* row = img + (int64_t)r * ncol;
 #pragma unroll
-        for (int k = -1; k <= 2; ++k) {
-            const int x = xi + k;
-            if (x < 0 || x >= ncol) continue;
-            const T w = T(1) - aa * fabs((T)k - fr);
-            if (w > T(0)) acc += w * row[x];
+            for (int k = -1; k <= 2; ++k) {
+                const int x = xi + k;
+                if (x < 0 || x >= ncol) continue;
+                const T w = T(1) - aa * fabs((T)k - fr);
+                if (w > T(0)) acc += w * row[x];
+            }
         }
     }
-    b[f.sino_off + (int64_t)rt.angle * f.n_bins + j] = acc;
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && j < f.n_bins)
+        b[f.sino_off + (int64_t)rt.angle * f.n_bins + j] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 template <class T>
@@ -173,7 +182,7 @@ void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
                            p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), (const T*)u, ut);
         MMOF_LAUNCH_CHECK();
         ScopedTime st(&c, "radon_fwd");
-        hipLaunchKernelGGL(k_radon_fwd<T>, dim3((unsigned)cdiv(p.n_rays, 4)), dim3(256), 0, c.stream,
+        hipLaunchKernelGGL(k_radon_fwd<T>, dim3((unsigned)p.n_rays), dim3(256), 0, c.stream,
                            p.d_rays.as<RayTile>(), p.n_rays, p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(),
                            (const T*)u, (const T*)ut, (T*)b);
         MMOF_LAUNCH_CHECK();

@@ -128,10 +128,13 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
                                                     double* __restrict__ res) {
     __shared__ SmallLds s;
     const int i = threadIdx.x;
-    if (i < K) {
-        for (int j = 0; j < K; ++j) {
-            s.A[i][j] = GA[(int64_t)i * KMAX_SMALL + j];
-            s.T[i][j] = GT[(int64_t)i * KMAX_SMALL + j];
+    // coalesced loads: each instruction moves one contiguous row of the 64-wide matrices
+    for (int r = 0; r < K; ++r) {
+        const double ga = GA[(int64_t)r * KMAX_SMALL + i];
+        const double gt = GT[(int64_t)r * KMAX_SMALL + i];
+        if (i < K) {
+            s.A[r][i] = ga;
+            s.T[r][i] = gt;
         }
     }
     const double d = i < K ? dvec[i] : 0.0;
@@ -155,16 +158,22 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
             const double m = log10(prev);
             if (m > lo && m < hi) mu = m;
         }
-        bool done = false;
-        for (int it = 0; it < 200 && !done; ++it) {
+        // Newton in mu inside the bracket [lo, hi].  An end of the search interval is only
+        // evaluated when a step would leave through it: an interior root proves, by
+        // monotonicity of D^2, that neither end needs clamping.
+        for (int it = 0; it < 200; ++it) {
             e = evaluate(s, K, pow(10.0, mu), bb, d, true);
             const double f = e.ok ? e.D2 - target : -target;
             MMOF_SMALL_TRACE(it, mu, e, f, lo, hi);
-            if (f < 0.0) {
+            if (f < 0.0)
                 lo = mu;
-                if (!hi_checked) {  // the root may lie beyond the upper end
+            else
+                hi = mu;
+            if (e.ok && fabs(f) <= 1e-13 * bb) break;  // rounding level of D^2
+            double nmu = (e.ok && e.dD2 > 0.0) ? mu - f / e.dD2 : 0.5 * (lo + hi);
+            if (!(nmu > lo && nmu < hi)) {
+                if (f < 0.0 && !hi_checked && hi == HI) {
                     hi_checked = true;
-                    // (e keeps z, D^2 and the derivative at mu in registers)
                     const Eval eh = evaluate(s, K, pow(10.0, HI), bb, d, false);
                     if (eh.ok && eh.D2 < target) {
                         e = eh;
@@ -173,9 +182,7 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
                         break;
                     }
                 }
-            } else {
-                hi = mu;
-                if (!lo_checked) {  // the root may lie below the lower end
+                if (f > 0.0 && !lo_checked && lo == LO) {
                     lo_checked = true;
                     const Eval el = evaluate(s, K, pow(10.0, LO), bb, d, false);
                     if (el.ok && el.D2 > target) {
@@ -185,15 +192,14 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
                         break;
                     }
                 }
+                nmu = 0.5 * (lo + hi);
             }
-            // stop at the rounding level of D^2 or of mu
-            if (e.ok && fabs(f) <= 1e-14 * bb) break;
-            if (hi - lo <= 1e-14 * fmax(1.0, fabs(mu))) break;
-            double nmu = (e.ok && e.dD2 > 0.0) ? mu - f / e.dD2 : 0.5 * (lo + hi);
-            if (!(nmu > lo && nmu < hi)) nmu = 0.5 * (lo + hi);
-            if (fabs(nmu - mu) <= 1e-14 * fmax(1.0, fabs(mu))) done = true;
+            if (fabs(nmu - mu) <= 1e-11 * fmax(1.0, fabs(mu)) || hi - lo <= 1e-14 * fmax(1.0, fabs(mu))) {
+                mu = nmu;
+                e = evaluate(s, K, pow(10.0, mu), bb, d, false);
+                break;
+            }
             mu = nmu;
-            if (done) e = evaluate(s, K, pow(10.0, mu), bb, d, false);
         }
         lam = pow(10.0, mu);
     }

@@ -14,9 +14,12 @@ void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double
 template <class TX>
 void gemv_cols(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, double beta,
                double* out);
-// G (K x K, leading dim ldg) = X^T diag(1/sqrt(nu^2+eps^2)) X   (nu == null: unweighted)
+// w[i] = 1/sqrt(nu[i]^2 + eps^2) in FP64
 template <class TX>
-void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TX* nu, double eps, double* G, int ldg);
+void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w);
+// G (K x K, leading dim ldg) = X^T diag(w) X   (w == null: unweighted), FP64 on the matrix cores
+template <class TX>
+void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg);
 template <class TI, class TO>
 void convert(Ctx& c, int64_t n, const TI* in, TO* out);
 void normalize(Ctx& c, int64_t n, const double* x, const double* nrm, double thr, double* out);
@@ -35,9 +38,9 @@ void sqrt_scalar(Ctx& c, const double* in, double* out);
 void axpy_dev(Ctx& c, int64_t n, const double* x, double* y, const double* s, double sign);
 // G[j][0..j] and G[0..j][j] <- h[0..j]
 void put_rowcol(Ctx& c, double* G, int ldg, int j, const double* h);
-// y = x / sqrt(nu^2 + eps^2)
+// y = w * x
 template <class TX>
-void weight_mul(Ctx& c, int64_t n, const TX* nu, double eps, const TX* x, TX* y);
+void weight_mul(Ctx& c, int64_t n, const double* w, const TX* x, TX* y);
 
 // Small projected solve (one wavefront).  Inputs on the device: GA, GT (K x K, ld KMAX_SMALL),
 // d (K), and the scalars bb = ||b||^2 and target = (eta*delta)^2 in sc[0..1].

@@ -36,6 +36,7 @@ struct Solver {
     // workspace
     double *V, *U, *r, *tmp_n, *tmp_m, *GA, *GT, *dvec, *z, *h, *sc, *res, *scal;
     TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *flow_v, *flow_vr, *flow_tmp, *I;
+    double* w2;  // FP64 MM weights of the rows of Theta
     int32_t *rad_v, *rad_vr;
     double* host;  // pinned report staging
 
@@ -81,6 +82,7 @@ struct Solver {
         out_n2 = ws<TX>("out_n2", n);
         nu = ws<TX>("nu", R);
         yR = ws<TX>("yR", R);
+        w2 = ws<double>("w2", R);
         flow_v = ws<TX>("flow_v", 2 * g.pair_px);
         flow_vr = ws<TX>("flow_vr", 2 * g.pair_px);
         flow_tmp = ws<TX>("flow_tmp", 2 * g.pair_px);
@@ -289,7 +291,8 @@ struct Solver {
             }
             // 2. nu = Theta u^(k); weighted Gram of Theta V
             theta(u_op, nu);
-            wgram<TX>(c, R, K, TV, R, nu, p.eps, GT, KMAX_SMALL);
+            mm_weights_f64<TX>(c, R, nu, p.eps, w2);
+            wgram<TX>(c, R, K, TV, R, w2, GT, KMAX_SMALL);
             // 3-5. lambda (discrepancy principle) and z
             small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res);
             copy_scalar(c, sc + 2, res);
@@ -308,7 +311,7 @@ struct Solver {
                 convert<double, TX>(c, m, tmp_m, vin_m);
                 At(vin_m, out_n);
                 theta(u_op, yR);
-                weight_mul<TX>(c, R, nu, p.eps, yR, yR);
+                weight_mul<TX>(c, R, w2, yR, yR);
                 thetaT(yR, out_n2);
                 residual_combine<TX>(c, n, out_n, out_n2, res, r);
                 // 8. CGS2 against V
