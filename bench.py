@@ -46,6 +46,10 @@ ALGO_BYTES = {
 }
 
 
+# FP32+FP64-refined solves: the last outer iterations run with FP64 operators
+REFINE_ITERS = 10
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -192,10 +196,12 @@ def main():
         ref = B.solve_joint(plan, b, delta, u_true=u_true, **solve_params(wl, "f64"))
         target = ref.rre[-1] * 1.001
         tts = {"rre_target": target, "k_max": prm["k_max"] + 15}
-        for op in ("f64", "f32"):
-            kw = solve_params(wl, op)
+        for op in ("f64", "f32", "f32+refine"):
+            kw = solve_params(wl, op.split("+")[0])
             kw["k_max"] = prm["k_max"] + 15
             kw["rre_target"] = target
+            if op.endswith("refine"):
+                kw["refine_iters"] = REFINE_ITERS
             B.solve_joint(plan, b, delta, u_true=u_true, **kw)
             torch.cuda.synchronize()
             ts = []

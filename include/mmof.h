@@ -172,7 +172,9 @@ typedef struct {
     int32_t use_reverse;  /* 1: also M-bar'(s') with s' from the reverse-flow remark      */
     int32_t interp;       /* MMOF_INTERP_*                                                */
     int32_t op_dtype;     /* MMOF_F32 or MMOF_F64: precision of operator applications     */
-    int32_t refine_iters; /* with op_dtype F32: last iterations run with F64 operators    */
+    int32_t refine_iters; /* with op_dtype F32: the last refine_iters outer iterations run  */
+                          /* with F64 operators on the basis the F32 iterations built      */
+                          /* (H V, G_H, d and Theta V recomputed in F64); 0: F32 throughout */
     double eps;           /* MM smoothing (reading: 1e-3)                                 */
     double eta;           /* discrepancy safety factor (reading: 1.01)                    */
     double alpha;         /* Horn-Schunck alpha (gamma = alpha^2)                         */

@@ -7,7 +7,9 @@ the HIP kernels.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -18,6 +20,21 @@ from . import _lib
 from ._lib import check
 
 _DT = {torch.float32: _lib.MMOF_F32, torch.float64: _lib.MMOF_F64}
+
+# Library objects still alive at interpreter exit are released while the HIP runtime is
+# still up (plans before contexts); later finalizers then do nothing.
+_LIVE_PLANS = weakref.WeakSet()
+_LIVE_CTX = weakref.WeakSet()
+_SHUTDOWN = [False]
+
+
+@atexit.register
+def _release_all():
+    for p in list(_LIVE_PLANS):
+        p.close()
+    for c in list(_LIVE_CTX):
+        c.close()
+    _SHUTDOWN[0] = True
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -55,6 +72,7 @@ class Context:
             h = C.c_void_p()
             check(self.lib.mmof_create(C.byref(h), C.c_void_p(torch.cuda.current_stream().cuda_stream)))
         self.h = h
+        _LIVE_CTX.add(self)
 
     def bind(self):
         """Point the context at torch's current stream (call before every launch)."""
@@ -62,9 +80,9 @@ class Context:
         return self.h
 
     def close(self):
-        if self.h:
+        if self.h and not _SHUTDOWN[0]:
             self.lib.mmof_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -149,11 +167,12 @@ class Plan:
         m = C.c_int64()
         check(ctx.lib.mmof_plan_sizes(h, C.byref(n), C.byref(m)))
         self.n, self.m = int(n.value), int(m.value)
+        _LIVE_PLANS.add(self)
 
     def close(self):
-        if self.h:
+        if self.h and not _SHUTDOWN[0]:
             self.ctx.lib.mmof_plan_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:

@@ -21,6 +21,27 @@
 
 namespace mmof {
 
+// One phase of a solve: outer iterations [k_begin, k_end) in one operator precision.
+// A phase that starts from a previous one takes over its Krylov basis (K_in columns of the
+// shared FP64 workspace) and its flows (converted to this phase's precision).
+struct Phase {
+    int k_begin = 0, k_end = 0;
+    bool final = true;             // the last phase: no subspace growth after its last iteration
+    int K_in = 0;                  // 0: start with Golub-Kahan
+    bool start_only = false;       // build the Golub-Kahan basis V and return
+    const void* v_in = nullptr;    // flows of the previous phase (NULL: zero flows)
+    const void* vr_in = nullptr;
+    int in_dt = MMOF_F32;
+    int out_dt = MMOF_F32;         // dtype of v_out / v_rev_out
+};
+
+struct PhaseOut {
+    int status = 0, K = 0, iters = 0;
+    bool stopped = false;          // RRE target reached or breakdown
+    const void* flow_v = nullptr;
+    const void* flow_vr = nullptr;
+};
+
 template <class TX>
 struct Solver {
     Ctx& c;
@@ -54,43 +75,53 @@ struct Solver {
         Kcap = p.ell + p.k_max - 1;
     }
 
+    // FP64 buffers (the Krylov state) are shared by both operator precisions, so an FP32
+    // phase can hand its basis to an FP64 refinement phase; operator-precision buffers are
+    // kept apart per precision.
     template <class T>
     T* ws(const char* name, int64_t count) {
-        return static_cast<T*>(c.work(std::string("solve_") + name, sizeof(T) * (size_t)std::max<int64_t>(count, 1)));
+        const char* tag = std::is_same<T, TX>::value && !std::is_same<TX, double>::value ? "solve_f_" : "solve_";
+        return static_cast<T*>(c.work(std::string(tag) + name, sizeof(T) * (size_t)std::max<int64_t>(count, 1)));
+    }
+    TX* wsx(const char* name, int64_t count) {
+        return static_cast<TX*>(c.work(std::string(std::is_same<TX, float>::value ? "solve_f_" : "solve_d_") + name,
+                                       sizeof(TX) * (size_t)std::max<int64_t>(count, 1)));
     }
 
-    void alloc() {
+    // full = false: only what the Golub-Kahan start needs
+    void alloc(bool full) {
         V = ws<double>("V", (int64_t)Kcap * n);
         U = ws<double>("U", (int64_t)(p.ell + 1) * m);
         r = ws<double>("r", n);
-        tmp_n = ws<double>("tmp_n", n);
         tmp_m = ws<double>("tmp_m", m);
+        h = ws<double>("h", KMAX_SMALL);
+        sc = ws<double>("sc", 8);
+        scal = ws<double>("scal", 16);
+        vin_n = wsx("vin_n", n);
+        vin_m = wsx("vin_m", m);
+        out_n = wsx("out_n", n);
+        host = static_cast<double*>(c.pinned(64 * sizeof(double)));
+        fill_zero<double>(c, 16, scal);
+        if (!full) return;
+        tmp_n = ws<double>("tmp_n", n);
         GA = ws<double>("GA", KMAX_SMALL * KMAX_SMALL);
         GT = ws<double>("GT", KMAX_SMALL * KMAX_SMALL);
         dvec = ws<double>("dvec", KMAX_SMALL);
         z = ws<double>("z", KMAX_SMALL);
-        h = ws<double>("h", KMAX_SMALL);
-        sc = ws<double>("sc", 8);
         res = ws<double>("res", 8);
-        scal = ws<double>("scal", 16);
-        AV = ws<TX>("AV", (int64_t)Kcap * m);
-        TV = ws<TX>("TV", (int64_t)Kcap * R);
-        u_op = ws<TX>("u_op", n);
-        vin_n = ws<TX>("vin_n", n);
-        vin_m = ws<TX>("vin_m", m);
-        out_n = ws<TX>("out_n", n);
-        out_n2 = ws<TX>("out_n2", n);
-        nu = ws<TX>("nu", R);
-        yR = ws<TX>("yR", R);
+        AV = wsx("AV", (int64_t)Kcap * m);
+        TV = wsx("TV", (int64_t)Kcap * R);
+        u_op = wsx("u_op", n);
+        out_n2 = wsx("out_n2", n);
+        nu = wsx("nu", R);
+        yR = wsx("yR", R);
         w2 = ws<double>("w2", R);
-        flow_v = ws<TX>("flow_v", 2 * g.pair_px);
-        flow_vr = ws<TX>("flow_vr", 2 * g.pair_px);
-        flow_tmp = ws<TX>("flow_tmp", 2 * g.pair_px);
-        I = ws<TX>("I", 3 * g.pair_px);
+        flow_v = wsx("flow_v", 2 * g.pair_px);
+        flow_vr = wsx("flow_vr", 2 * g.pair_px);
+        flow_tmp = wsx("flow_tmp", 2 * g.pair_px);
+        I = wsx("I", 3 * g.pair_px);
         rad_v = ws<int32_t>("rad_v", 64);
         rad_vr = ws<int32_t>("rad_vr", 64);
-        host = static_cast<double*>(c.pinned(64 * sizeof(double)));
-        fill_zero<double>(c, 16, scal);
     }
 
     // ---------------------------------------------------------------- operators (TX)
@@ -183,23 +214,18 @@ struct Solver {
         }
     }
 
-    int run(const double* b_, double delta, double* u_io, void* v_out, void* vr_out) {
+    PhaseOut run(const double* b_, double delta, double* u_io, void* v_out, void* vr_out, const Phase& ph) {
         b = b_;
         MMOF_CHECK(Kcap >= 1 && Kcap <= KMAX_SMALL, MMOF_ERR_SHAPE,
                    "ell + k_max - 1 must be in [1, " + std::to_string(KMAX_SMALL) + "]");
         MMOF_CHECK(p.ell >= 1 && p.k_max >= 1 && p.tau >= 1, MMOF_ERR_INVALID, "ell, k_max, tau must be >= 1");
         MMOF_CHECK(!flow || p.n_sweeps >= 0, MMOF_ERR_INVALID, "n_sweeps must be >= 0");
         MMOF_CHECK(p.eps > 0 && p.alpha > 0 && p.eta > 0, MMOF_ERR_INVALID, "eps, alpha, eta must be > 0");
-        alloc();
-        if (rep) {
-            rep->n_A = rep->n_At = rep->n_theta = rep->n_thetaT = rep->n_flow_updates = rep->n_L = 0;
-            rep->iters = 0;
-            rep->status = 0;
-        }
+        alloc(!ph.start_only);
         // scalars: sc[0] = ||b||^2, sc[1] = (eta delta)^2, sc[2] = previous lambda
         norm_into(m, b, sc);
         set_scalar(c, sc + 1, (p.eta * delta) * (p.eta * delta));
-        set_scalar(c, sc + 2, 0.0);
+        if (ph.k_begin == 0) set_scalar(c, sc + 2, 0.0);  // a later phase keeps the previous lambda
 
         // ||H^T b|| for the breakdown test
         convert<double, TX>(c, m, b, vin_m);
@@ -212,62 +238,66 @@ struct Solver {
         const double atb = std::sqrt(host[0]);
         const double utn = p.u_true ? std::sqrt(host[1]) : 0.0;
 
-        // ---- Golub-Kahan start: u_1 = b/||b||, ell right vectors, both bases re-orthogonalised
-        // scalar slots: scal[0..3] = alpha^2, alpha, beta^2, beta
-        norm_into(m, b, scal + 11);
-        normalize_sq(m, b, scal + 11, scal + 12, U);
-        convert<double, TX>(c, m, U, vin_m);
-        At(vin_m, out_n);
-        convert<TX, double>(c, n, out_n, r);
-        norm_into(n, r, scal);
-        normalize_sq(n, r, scal, scal + 1, V);
-        for (int i = 1; i < p.ell; ++i) {
-            // w = H v_{i-1} - alpha u_{i-1}
-            convert<double, TX>(c, n, V + (int64_t)(i - 1) * n, vin_n);
-            A(vin_n, vin_m);
-            convert<TX, double>(c, m, vin_m, tmp_m);
-            axpy_dev(c, m, U + (int64_t)(i - 1) * m, tmp_m, scal + 1, -1.0);
-            reorth(m, U, i, tmp_m);
-            norm_into(m, tmp_m, scal + 2);
-            normalize_sq(m, tmp_m, scal + 2, scal + 3, U + (int64_t)i * m);
-            // v = H^T u_i - beta v_{i-1}
-            convert<double, TX>(c, m, U + (int64_t)i * m, vin_m);
+        int K = ph.K_in;
+        if (K == 0) {
+            // ---- Golub-Kahan start: u_1 = b/||b||, ell right vectors, both bases re-orthogonalised
+            // scalar slots: scal[0..3] = alpha^2, alpha, beta^2, beta
+            norm_into(m, b, scal + 11);
+            normalize_sq(m, b, scal + 11, scal + 12, U);
+            convert<double, TX>(c, m, U, vin_m);
             At(vin_m, out_n);
             convert<TX, double>(c, n, out_n, r);
-            axpy_dev(c, n, V + (int64_t)(i - 1) * n, r, scal + 3, -1.0);
-            reorth(n, V, i, r);
             norm_into(n, r, scal);
-            normalize_sq(n, r, scal, scal + 1, V + (int64_t)i * n);
-        }
-        for (int j = 0; j < p.ell; ++j) {
-            // Theta of the start vectors is built after the flows are zeroed below
-            const double* vj = V + (int64_t)j * n;
-            convert<double, TX>(c, n, vj, vin_n);
-            TX* avj = AV + (int64_t)j * m;
-            A(vin_n, avj);
-            mdot<TX, TX>(c, m, j + 1, AV, m, avj, 1.0, h);
-            put_rowcol(c, GA, KMAX_SMALL, j, h);
-            mdot<TX, double>(c, m, 1, avj, m, b, 1.0, dvec + j);
+            normalize_sq(n, r, scal, scal + 1, V);
+            for (int i = 1; i < p.ell; ++i) {
+                // w = H v_{i-1} - alpha u_{i-1}
+                convert<double, TX>(c, n, V + (int64_t)(i - 1) * n, vin_n);
+                A(vin_n, vin_m);
+                convert<TX, double>(c, m, vin_m, tmp_m);
+                axpy_dev(c, m, U + (int64_t)(i - 1) * m, tmp_m, scal + 1, -1.0);
+                reorth(m, U, i, tmp_m);
+                norm_into(m, tmp_m, scal + 2);
+                normalize_sq(m, tmp_m, scal + 2, scal + 3, U + (int64_t)i * m);
+                // v = H^T u_i - beta v_{i-1}
+                convert<double, TX>(c, m, U + (int64_t)i * m, vin_m);
+                At(vin_m, out_n);
+                convert<TX, double>(c, n, out_n, r);
+                axpy_dev(c, n, V + (int64_t)(i - 1) * n, r, scal + 3, -1.0);
+                reorth(n, V, i, r);
+                norm_into(n, r, scal);
+                normalize_sq(n, r, scal, scal + 1, V + (int64_t)i * n);
+            }
+            K = p.ell;
+            if (ph.start_only) {
+                MMOF_HIP(hipStreamSynchronize(c.stream));
+                PhaseOut out;
+                out.K = K;
+                return out;
+            }
         }
 
-        // ---- initial state
+        // ---- state: u^(k), the flows (zero at the start), then H V, G_H, d and Theta V
         convert<double, TX>(c, n, u_io, u_op);
         if (flow) {
-            fill_zero<TX>(c, 2 * g.pair_px, flow_v);
-            fill_zero<TX>(c, 2 * g.pair_px, flow_vr);
+            if (!ph.v_in) {
+                fill_zero<TX>(c, 2 * g.pair_px, flow_v);
+                fill_zero<TX>(c, 2 * g.pair_px, flow_vr);
+            } else if (ph.in_dt == MMOF_F32) {
+                convert<float, TX>(c, 2 * g.pair_px, (const float*)ph.v_in, flow_v);
+                convert<float, TX>(c, 2 * g.pair_px, (const float*)ph.vr_in, flow_vr);
+            } else {
+                convert<double, TX>(c, 2 * g.pair_px, (const double*)ph.v_in, flow_v);
+                convert<double, TX>(c, 2 * g.pair_px, (const double*)ph.vr_in, flow_vr);
+            }
             launch_flow_radius(c, g, dt, flow_v, rad_v);
             launch_flow_radius(c, g, dt, flow_vr, rad_vr);
         }
-        for (int j = 0; j < p.ell; ++j) {
-            convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
-            theta(vin_n, TV + (int64_t)j * R);
-        }
-
-        int K = p.ell;
+        for (int j = 0; j < K; ++j) add_column(j);
         int status = 0;
         int iters = 0;
         const double gamma = p.alpha * p.alpha;
-        for (int k = 0; k < p.k_max; ++k) {
+        bool stopped = false;
+        for (int k = ph.k_begin; k < ph.k_end; ++k) {
             // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
             if (flow && k % p.tau == 0) {
                 launch_of_derivs(c, g, dt, u_op, I, p.delta_r);
@@ -303,7 +333,7 @@ struct Solver {
                 sub(c, n, u_io, p.u_true, tmp_n);
                 norm_into(n, tmp_n, scal + 6);
             }
-            const bool last = (k == p.k_max - 1);
+            const bool last = ph.final && (k == ph.k_end - 1);
             if (!last) {
                 // 7. r = H^T (H V z - b) + lambda Theta^T P^2 Theta V z
                 gemv_cols<TX>(c, m, K, AV, m, z, 1.0, 0.0, tmp_m);
@@ -342,7 +372,10 @@ struct Solver {
                 if (rep->dp_status) rep->dp_status[k] = st;
             }
             if (rep) rep->n_cols = K;
-            if (p.u_true && p.rre_target > 0 && rre <= p.rre_target) break;
+            if (p.u_true && p.rre_target > 0 && rre <= p.rre_target) {
+                stopped = true;
+                break;
+            }
             if (last) {
                 if (p.u_true && p.rre_target > 0) status = std::max(status, (int)MMOF_WARN_KMAX);
                 break;
@@ -350,6 +383,7 @@ struct Solver {
             // 9. breakdown or append r/||r||
             if (!(rnorm > 1e-14 * atb)) {
                 status = MMOF_WARN_BREAKDOWN;
+                stopped = true;
                 break;
             }
             normalize_sq(n, r, scal + 7, scal + 13, V + (int64_t)K * n);
@@ -357,28 +391,77 @@ struct Solver {
             ++K;
         }
         if (rep) {
-            rep->iters = iters;
-            rep->status = status;
+            rep->iters = std::max(rep->iters, iters);
+            rep->status = std::max(rep->status, status);
         }
-        const int64_t vb = (int64_t)sizeof(TX) * 2 * g.pair_px;
-        if (v_out && flow && vb) MMOF_HIP(hipMemcpyAsync(v_out, flow_v, vb, hipMemcpyDeviceToDevice, c.stream));
-        if (vr_out && flow && vb) MMOF_HIP(hipMemcpyAsync(vr_out, flow_vr, vb, hipMemcpyDeviceToDevice, c.stream));
+        if (ph.final || stopped) {
+            const int64_t nv = 2 * g.pair_px;
+            for (int q = 0; q < 2 && flow && nv; ++q) {
+                void* dst = q == 0 ? v_out : vr_out;
+                const TX* src = q == 0 ? flow_v : flow_vr;
+                if (!dst) continue;
+                if (ph.out_dt == MMOF_F32)
+                    convert<TX, float>(c, nv, src, static_cast<float*>(dst));
+                else
+                    convert<TX, double>(c, nv, src, static_cast<double*>(dst));
+            }
+        }
         MMOF_HIP(hipStreamSynchronize(c.stream));
-        return status;
+        PhaseOut out;
+        out.status = status;
+        out.K = K;
+        out.iters = iters;
+        out.stopped = stopped;
+        out.flow_v = flow_v;
+        out.flow_vr = flow_vr;
+        return out;
     }
 };
 
 int solve_joint(Plan& P, const double* b, double delta, const mmof_solve_params& p, double* u_io, void* v_out,
                 void* vr_out, mmof_report* rep) {
-    if (p.op_dtype == MMOF_F32) {
-        Solver<float> s(*P.ctx, P, p, rep);
-        return s.run(b, delta, u_io, v_out, vr_out);
+    MMOF_CHECK(p.op_dtype == MMOF_F32 || p.op_dtype == MMOF_F64, MMOF_ERR_DTYPE, "op_dtype must be F32 or F64");
+    MMOF_CHECK(p.refine_iters >= 0, MMOF_ERR_INVALID, "refine_iters must be >= 0");
+    if (rep) {
+        rep->n_A = rep->n_At = rep->n_theta = rep->n_thetaT = rep->n_flow_updates = rep->n_L = 0;
+        rep->iters = 0;
+        rep->status = 0;
     }
-    if (p.op_dtype == MMOF_F64) {
+    Phase ph;
+    ph.k_end = p.k_max;
+    ph.out_dt = p.op_dtype;
+    const int k_sw = std::max(0, p.k_max - p.refine_iters);
+    if (p.op_dtype == MMOF_F64 || k_sw == 0) {
         Solver<double> s(*P.ctx, P, p, rep);
-        return s.run(b, delta, u_io, v_out, vr_out);
+        return s.run(b, delta, u_io, v_out, vr_out, ph).status;
     }
-    throw Error(MMOF_ERR_DTYPE, "op_dtype must be MMOF_F32 or MMOF_F64");
+    // FP32 operators in the MM iterations.  The Golub-Kahan start runs with FP64 operators:
+    // its recurrence loses accuracy in the later start vectors in proportion to the operator
+    // rounding, and the discrepancy-principle lambda amplifies a perturbed start subspace,
+    // while the residual directions appended later are computed afresh in every iteration.
+    {
+        Phase p0 = ph;
+        p0.start_only = true;
+        Solver<double> s0(*P.ctx, P, p, rep);
+        s0.run(b, delta, u_io, nullptr, nullptr, p0);
+    }
+    Phase p1 = ph;
+    p1.K_in = p.ell;
+    p1.k_end = k_sw;
+    p1.final = p.refine_iters == 0;
+    Solver<float> s1(*P.ctx, P, p, rep);
+    const PhaseOut o1 = s1.run(b, delta, u_io, v_out, vr_out, p1);
+    if (p1.final || o1.stopped) return o1.status;
+    // FP64 refinement for iterations [k_sw, k_max), starting from the FP32 phase's basis
+    Phase p2 = ph;
+    p2.k_begin = k_sw;
+    p2.K_in = o1.K;
+    p2.v_in = o1.flow_v;
+    p2.vr_in = o1.flow_vr;
+    p2.in_dt = MMOF_F32;
+    Solver<double> s2(*P.ctx, P, p, rep);
+    const PhaseOut o2 = s2.run(b, delta, u_io, v_out, vr_out, p2);
+    return std::max(o1.status, o2.status);
 }
 
 }  // namespace mmof

@@ -17,6 +17,7 @@ from .workloads import (  # noqa: F401
     noisy,
     random_field,
     smooth_flow,
+    smooth_flow_coarse,
     nudge_off_kinks,
     GOLDEN_ANGLE_180,
 )

@@ -92,18 +92,23 @@ def paint_ellipses(ny: int, nx: int, ells: List[dict], t: float) -> np.ndarray:
     px), phi (rad), val, vx, vy (px/frame) and om (rad/frame).  A pixel belongs to an
     ellipse when its centre satisfies the implicit inequality.
     """
-    x, y = _pixel_grid(ny, nx)
     img = np.zeros((ny, nx))
     for e in ells:
         cx = e["cx"] + e.get("vx", 0.0) * t
         cy = e["cy"] + e.get("vy", 0.0) * t
         ph = e["phi"] + e.get("om", 0.0) * t
         c, s = math.cos(ph), math.sin(ph)
+        R = max(e["a"], e["b"]) + 1.0
+        x0, x1 = max(0, int(math.floor(cx - R))), min(nx, int(math.ceil(cx + R)) + 1)
+        y0, y1 = max(0, int(math.floor(cy - R))), min(ny, int(math.ceil(cy + R)) + 1)
+        if x0 >= x1 or y0 >= y1:
+            continue
+        y, x = np.mgrid[y0:y1, x0:x1]
         dx, dy = x - cx, y - cy
         xr = c * dx + s * dy
         yr = -s * dx + c * dy
         inside = (xr / e["a"]) ** 2 + (yr / e["b"]) ** 2 <= 1.0
-        img[inside] = e["val"]
+        img[y0:y1, x0:x1][inside] = e["val"]
     return img
 
 
@@ -164,6 +169,19 @@ def smooth_flow(n_pairs: int, n: int, seed: int, sigma: float = 16.0, vmax: floa
     for p in range(n_pairs):
         for c in range(2):
             out[p, c] = gaussian_filter(g[p, c], sigma=sigma, mode="reflect")
+    return out * (vmax / np.abs(out).max())
+
+
+def smooth_flow_coarse(n_pairs: int, n: int, seed: int, coarse: int = 16, vmax: float = 3.0) -> np.ndarray:
+    """Smooth random flow [n_pairs, 2, n, n]: N(0,1) on a coarse grid, bilinearly upsampled,
+    rescaled so that max |v| = vmax (cheap at large n)."""
+    from scipy.ndimage import zoom
+
+    g = np.random.default_rng(seed).standard_normal((n_pairs, 2, coarse, coarse))
+    out = np.empty((n_pairs, 2, n, n))
+    for p in range(n_pairs):
+        for c in range(2):
+            out[p, c] = zoom(g[p, c], n / coarse, order=1, mode="nearest")[:n, :n]
     return out * (vmax / np.abs(out).max())
 
 

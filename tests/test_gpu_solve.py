@@ -103,6 +103,31 @@ def test_solve_disk32_workload(B, op):
         assert np.linalg.norm(got - ref.u) <= 1e-6 * np.linalg.norm(ref.u)
 
 
+def test_solve_disk32_refined(B):
+    """FP32 operators with the last outer iterations on FP64 operators (the FP64 phase takes
+    over the FP32 phase's basis and flows and continues the iteration count)."""
+    import torch
+    wl, s, g, b, delta = _disk32_data()
+    prm = dict(ell=10, k_max=20, tau=1, n_sweeps=200, alpha=0.1, eps=1e-3, eta=1.01, delta_r=1)
+    ref, res = _run_both(B, s.u_true, s.angles, s.n_bins, g, b, delta, op="f32", refine_iters=5, **prm)
+    assert res.iters == ref.iters == 20
+    assert abs(res.rre[-1] - ref.rre[-1]) <= 1e-4, (res.rre[-1], ref.rre[-1])
+    assert res.v.dtype == torch.float32 and res.n_cols == ref.n_cols
+    # refinement over the whole solve is the FP64 solve
+    stack = B.Stack.single(g.n_t, g.ny, g.nx)
+    plan = B.plan_radon(stack, [s.angles.shape[1]], [s.n_bins], s.angles.ravel())
+    bt = torch.as_tensor(b, device="cuda")
+    ut = torch.as_tensor(s.u_true.ravel(), device="cuda")
+    full = B.solve_joint(plan, bt, delta, u_true=ut, op_dtype="f32", refine_iters=20, **prm)
+    f64 = B.solve_joint(plan, bt, delta, u_true=ut, op_dtype="f64", **prm)
+    assert full.rre == f64.rre and full.lambdas == f64.lambdas
+    assert torch.equal(full.u, f64.u)
+    # a target reached during the FP32 phase ends the solve there
+    tgt = res.rre[4]
+    early = B.solve_joint(plan, bt, delta, u_true=ut, op_dtype="f32", refine_iters=5, rre_target=tgt, **prm)
+    assert early.iters <= 15 and early.rre[-1] <= tgt and early.status == 0
+
+
 def test_solve_blur_ragged_fp64(B):
     import torch
     r = np.random.default_rng(5)
@@ -137,4 +162,7 @@ def test_solve_rejects_bad_arguments(B):
     assert e.value.code == -2
     with pytest.raises(MMOFError) as e:
         B.solve_joint(plan, b, 0.1, eps=-1.0)
+    assert e.value.code == -1
+    with pytest.raises(MMOFError) as e:
+        B.solve_joint(plan, b, 0.1, op_dtype="f32", refine_iters=-1)
     assert e.value.code == -1
