@@ -105,128 +105,175 @@ __global__ __launch_bounds__(KB) void k_gemv_cols(int64_t n, int K, const TX* __
     }
 }
 
-// Weighted Gram G = X^T diag(w2) X (K <= 64), w2 = 1/sqrt(nu^2 + eps^2) (1 when nu is null),
-// on the FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16x4 block of X^T by a
-// 4x16 block of diag(w2) X.  Lane l supplies A[l%16][l/16] and B[l/16][l%16], which here
-// are the same entry X[16g + l%16][r0 + l/16] (times w2 for B); the 16x16 result sits in
-// four doubles per lane, D[l/16 + 4v][l%16] (layout checked on the device).  Each wave keeps the upper blocks of the
-// (K/16)^2 block grid for its rows; stage 1 writes one partial Gram per workgroup.
+// Weighted Gram G = X^T diag(w) X (K <= 64; w = 1 when null) on the FP64 matrix cores.
+// v_mfma_f64_16x16x4f64 multiplies a 16x4 block A by a 4x16 block B: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16], and the 16x16 result sits in four doubles per lane,
+// D[l/16 + 4v][l%16].  Here A[i][k] = X[row_k][16gi + i] and B[k][j] = w[row_k] X[row_k][16gj + j]
+// for the column blocks gi <= gj, so one instruction adds four rows to a 16x16 block.
+//
+// A wave takes 16 rows per step: lane group q = l/16 owns rows r0 + 4q .. r0 + 4q + 3 and
+// reads them with one 16-byte (float) or two 16-byte (double) loads per column block,
+// so a load instruction covers 64 contiguous bytes of each of 16 columns; the k-th MFMA
+// of the step uses row r0 + 4q + k in lane group q.  The next step's loads are issued
+// before the current step's MFMAs.  Stage 1 leaves one partial per workgroup (the waves
+// are combined in LDS in a fixed order); stage 2 sums the partials in a fixed order.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-template <class TX>
-struct GramStep {
-    TX x[4][4];   // [row group u][column group g]
-    double w[4];  // row weights
+static constexpr int GRAM_WAVES = 8;       // waves per stage-1 workgroup
+static constexpr int GRAM_BLOCKS = 256;    // stage-1 workgroups (partials)
+static constexpr int GRAM_PAIRS = 10;      // upper blocks of a 4x4 block grid
+static constexpr int GRAM_SLAB = 64;       // partial entries per stage-2 workgroup
+
+template <class TX, int G>
+struct GramRows {
+    TX x[G][4];    // [column block][row k]
+    double w[4];
 };
 
-template <class TX>
-__device__ __forceinline__ void gram_load(GramStep<TX>& st, const TX* __restrict__ X, int64_t ld,
-                                          const double* __restrict__ w, int64_t r0, int64_t hi, int K, int G,
-                                          int lane) {
+// Rows r0 + 4q + k (k < 4) of column blocks g < G for this lane; rows at or beyond n and
+// columns at or beyond K read as zero.  VEC: the four rows are loaded with vector loads
+// (requires ld % 4 == 0, 16-byte aligned X and rows r0 + 4q + 3 < n).
+template <class TX, int G, bool VEC>
+__device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restrict__ X, int64_t ld,
+                                          const double* __restrict__ w, int64_t n, int K, int64_t r0, int lane) {
     const int c = lane & 15;
+    const int64_t rb = r0 + 4 * (lane >> 4);
+    if (VEC && rb + 3 < n) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t r = r0 + 4 * u + (lane >> 4);
-        const bool inr = r < hi;
-        st.w[u] = inr ? (w ? w[r] : 1.0) : 0.0;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < G; ++g) {
             const int col = 16 * g + c;
-            st.x[u][g] = (g < G && col < K && inr) ? X[(int64_t)col * ld + r] : TX(0);
+            if (col < K) {
+                const TX* src = X + (int64_t)col * ld + rb;
+                if constexpr (sizeof(TX) == 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(src);
+                    st.x[g][0] = v.x;
+                    st.x[g][1] = v.y;
+                    st.x[g][2] = v.z;
+                    st.x[g][3] = v.w;
+                } else {
+                    const double2 v0 = *reinterpret_cast<const double2*>(src);
+                    const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+                    st.x[g][0] = v0.x;
+                    st.x[g][1] = v0.y;
+                    st.x[g][2] = v1.x;
+                    st.x[g][3] = v1.y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) st.x[g][k] = TX(0);
+            }
+        }
+        if (w) {
+            const double2 w0 = *reinterpret_cast<const double2*>(w + rb);
+            const double2 w1 = *reinterpret_cast<const double2*>(w + rb + 2);
+            st.w[0] = w0.x;
+            st.w[1] = w0.y;
+            st.w[2] = w1.x;
+            st.w[3] = w1.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) st.w[k] = 1.0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t r = rb + k;
+        const bool in = r < n;
+        st.w[k] = in ? (w ? w[r] : 1.0) : 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int col = 16 * g + c;
+            st.x[g][k] = (in && col < K) ? X[(int64_t)col * ld + r] : TX(0);
         }
     }
 }
 
-template <class TX>
-__global__ __launch_bounds__(KB) void k_wgram_part(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
-                                                   const double* __restrict__ w, double* __restrict__ part) {
-    __shared__ double sred[2][10][4][64];
+template <class TX, int G, bool VEC>
+__global__ __launch_bounds__(64 * GRAM_WAVES) void k_wgram_part(int64_t n, int K, const TX* __restrict__ X,
+                                                                int64_t ld, const double* __restrict__ w,
+                                                                double* __restrict__ part) {
+    constexpr int NP = G * (G + 1) / 2;
+    __shared__ double sred[GRAM_WAVES][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int G = (K + 15) >> 4;
-    dbl4 acc[10];
+    dbl4 acc[NP];
 #pragma unroll
-    for (int p = 0; p < 10; ++p) acc[p] = dbl4{0.0, 0.0, 0.0, 0.0};
-    const int64_t nbk = gridDim.x;
-    const int64_t chunk = ((n + nbk - 1) / nbk + 63) / 64 * 64;
-    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    // Each wave takes 4 groups of 4 rows per step (16 rows), the block 64 rows per step.
-    // The next step's loads are issued before the current step's MFMAs.
-    GramStep<TX> cur, nxt;
-    int64_t r0 = lo + 16 * wave;
-    if (r0 < hi) gram_load(cur, X, ld, w, r0, hi, K, G, lane);
-    for (; r0 < hi; r0 += 64) {
-        if (r0 + 64 < hi) gram_load(nxt, X, ld, w, r0 + 64, hi, K, G, lane);
+    for (int p = 0; p < NP; ++p) acc[p] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // contiguous 16-row steps per wave
+    const int64_t steps = (n + 15) / 16;
+    const int64_t nw = (int64_t)gridDim.x * GRAM_WAVES;
+    const int64_t gw = (int64_t)blockIdx.x * GRAM_WAVES + wave;
+    const int64_t s_lo = steps * gw / nw, s_hi = steps * (gw + 1) / nw;
+    GramRows<TX, G> cur, nxt;
+    if (s_lo < s_hi) gram_rows<TX, G, VEC>(cur, X, ld, w, n, K, 16 * s_lo, lane);
+    for (int64_t st = s_lo; st < s_hi; ++st) {
+        if (st + 1 < s_hi) gram_rows<TX, G, VEC>(nxt, X, ld, w, n, K, 16 * (st + 1), lane);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double wu = cur.w[u];
-            double a[4];
+        for (int k = 0; k < 4; ++k) {
+            double a[G], bw[G];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) a[g] = (double)cur.x[u][g];
+            for (int g = 0; g < G; ++g) {
+                a[g] = (double)cur.x[g][k];
+                bw[g] = a[g] * cur.w[k];
+            }
             int p = 0;
 #pragma unroll
-            for (int gi = 0; gi < 4; ++gi)
+            for (int gi = 0; gi < G; ++gi)
 #pragma unroll
-                for (int gj = gi; gj < 4; ++gj, ++p)
-                    if (gj < G) acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[gi], a[gj] * wu, acc[p], 0, 0, 0);
+                for (int gj = gi; gj < G; ++gj, ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[gi], bw[gj], acc[p], 0, 0, 0);
         }
         cur = nxt;
     }
-    // combine the four waves in a fixed order: (w2, w3) into (w0, w1), then w1 into w0
-    if (wave >= 2) {
+    // combine the waves pair by pair: thread t < 256 sums entry t over the waves in order
+    double* out = part + (int64_t)blockIdx.x * (GRAM_PAIRS * 256);
 #pragma unroll
-        for (int p = 0; p < 10; ++p)
+    for (int p = 0; p < NP; ++p) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sred[wave - 2][p][v][lane] = acc[p][v];
-    }
-    __syncthreads();
-    if (wave < 2) {
+        for (int v = 0; v < 4; ++v) sred[wave][v * 64 + lane] = acc[p][v];
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            double sum = 0.0;
 #pragma unroll
-        for (int p = 0; p < 10; ++p)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[p][v] += sred[wave][p][v][lane];
-    }
-    __syncthreads();
-    if (wave == 1) {
-#pragma unroll
-        for (int p = 0; p < 10; ++p)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sred[0][p][v][lane] = acc[p][v];
-    }
-    __syncthreads();
-    if (wave == 0) {
-        double* out = part + (int64_t)blockIdx.x * KMAX_SMALL * KMAX_SMALL;
-        int p = 0;
-#pragma unroll
-        for (int gi = 0; gi < 4; ++gi)
-#pragma unroll
-            for (int gj = gi; gj < 4; ++gj, ++p) {
-                if (gj >= G) continue;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int ii = 16 * gi + (lane >> 4) + 4 * v, jj = 16 * gj + (lane & 15);
-                    if (ii < K && jj < K) out[(int64_t)ii * KMAX_SMALL + jj] = acc[p][v] + sred[0][p][v][lane];
-                }
-            }
+            for (int q = 0; q < GRAM_WAVES; ++q) sum += sred[q][threadIdx.x];
+            out[p * 256 + threadIdx.x] = sum;
+        }
+        __syncthreads();
     }
 }
 
-// Weighted Gram, stage 2: G[i][j] = sum_b part[b][entry].  Four entries per workgroup, one
-// wavefront per entry: lane l sums partials l, l+64, ... and the wave combines them with a
-// fixed butterfly.
-__global__ __launch_bounds__(KB) void k_wgram_final(int nb, int K, const double* __restrict__ part,
-                                                    double* __restrict__ G, int ldg) {
-    const int lane = threadIdx.x & 63;
-    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (e >= K * K) return;
-    const int i = e / K, j = e % K;
-    // upper-block storage: the entry lives at (i, j) if its block is upper, else at (j, i)
-    const bool up = (i >> 4) <= (j >> 4);
-    const int ii = up ? i : j, jj = up ? j : i;
-    const double* src = part + (int64_t)ii * KMAX_SMALL + jj;
+// Stage 2: entry e (pair p = e / 256, register slot e % 256) summed over the partials.
+// A workgroup takes GRAM_SLAB consecutive entries; its 16 waves split the partials and
+// are combined in a fixed order; the upper triangle's entry is written to both triangles.
+__global__ __launch_bounds__(1024) void k_wgram_final(int nb, int K, int G, const double* __restrict__ part,
+                                                      double* __restrict__ Gm, int ldg) {
+    __shared__ double s[16][GRAM_SLAB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = blockIdx.x * GRAM_SLAB + lane;
     double acc = 0.0;
-    for (int b = lane; b < nb; b += 64) acc += src[(int64_t)b * KMAX_SMALL * KMAX_SMALL];
-    acc = wave_sum(acc);
-    if (lane == 0) G[(int64_t)i * ldg + j] = acc;
+    for (int b = wave; b < nb; b += 16) acc += part[(int64_t)b * (GRAM_PAIRS * 256) + e];
+    s[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sum += s[q][lane];
+    // map (pair, slot) to (i, j)
+    const int p = e >> 8, slot = e & 255, v = slot >> 6, l = slot & 63;
+    int gi = 0, base = 0;
+    while (gi < G && p >= base + (G - gi)) {
+        base += G - gi;
+        ++gi;
+    }
+    if (gi >= G) return;
+    const int gj = gi + (p - base);
+    const int i = 16 * gi + (l >> 4) + 4 * v, j = 16 * gj + (l & 15);
+    // a diagonal block holds both (i, j) and (j, i), which round differently: the upper one
+    // is written to both triangles, so G is exactly symmetric and every entry has one writer
+    if (i <= j && j < K) {
+        Gm[(int64_t)i * ldg + j] = sum;
+        Gm[(int64_t)j * ldg + i] = sum;
+    }
 }
 
 // Scale x by 1/s[0] when s[0] > thr, else leave a zero column; s holds ||x||.
@@ -386,18 +433,45 @@ void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w) {
 template void mm_weights_f64<float>(Ctx&, int64_t, const float*, double, double*);
 template void mm_weights_f64<double>(Ctx&, int64_t, const double*, double, double*);
 
+template <class TX, int G, bool VEC>
+static void wgram_launch(Ctx& c, int nb, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* part) {
+    hipLaunchKernelGGL((k_wgram_part<TX, G, VEC>), dim3(nb), dim3(64 * GRAM_WAVES), 0, c.stream, n, K, X, ld, w,
+                       part);
+}
+
+template <class TX, int G>
+static void wgram_launch_g(Ctx& c, int nb, bool vec, int64_t n, int K, const TX* X, int64_t ld, const double* w,
+                           double* part) {
+    if (vec)
+        wgram_launch<TX, G, true>(c, nb, n, K, X, ld, w, part);
+    else
+        wgram_launch<TX, G, false>(c, nb, n, K, X, ld, w, part);
+}
+
 template <class TX>
 void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg) {
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(n, 1024)));
-    double* part = static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)256 * KMAX_SMALL * KMAX_SMALL));
+    const int Gb = (K + 15) / 16;
+    const int np = Gb * (Gb + 1) / 2;
+    // enough 16-row steps per wave to amortise the partial, at most GRAM_BLOCKS partials
+    const int64_t steps = (n + 15) / 16;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 8 * GRAM_WAVES)));
+    const bool vec = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                     (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
+    double* part =
+        static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * GRAM_PAIRS * 256));
     {
         ScopedTime st(&c, "wgram");
-        hipLaunchKernelGGL(k_wgram_part<TX>, dim3(nb), dim3(KB), 0, c.stream, n, K, X, ld, w, part);
+        switch (Gb) {
+            case 1: wgram_launch_g<TX, 1>(c, nb, vec, n, K, X, ld, w, part); break;
+            case 2: wgram_launch_g<TX, 2>(c, nb, vec, n, K, X, ld, w, part); break;
+            case 3: wgram_launch_g<TX, 3>(c, nb, vec, n, K, X, ld, w, part); break;
+            default: wgram_launch_g<TX, 4>(c, nb, vec, n, K, X, ld, w, part); break;
+        }
         MMOF_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_wgram_final, dim3((unsigned)cdiv((int64_t)K * K, 4)), dim3(KB), 0, c.stream, nb, K, part,
-                       G, ldg);
+    hipLaunchKernelGGL(k_wgram_final, dim3((unsigned)cdiv((int64_t)np * 256, GRAM_SLAB)), dim3(1024), 0, c.stream,
+                       nb, K, Gb, part, G, ldg);
     MMOF_LAUNCH_CHECK();
 }
 template void wgram<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int);
