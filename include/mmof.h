@@ -194,6 +194,7 @@ typedef struct {
     int32_t* dp_status;   /* host [capacity] or NULL: 0 root found, 2 clamped             */
     int64_t n_A, n_At, n_theta, n_thetaT, n_flow_updates;  /* operator application counts */
     int64_t n_L;          /* applications of L(v) or L(v)^T, one per flow direction      */
+    int64_t n_factorizations; /* Cholesky factorizations in the projected solves          */
 } mmof_report;
 
 /* MMGKS-OF (Alg. 1) for min ||H u - b||^2 + lambda ||Theta u||_1 with the flow
@@ -222,7 +223,8 @@ int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const 
  * GA, GT: device FP64 K x K (leading dimension 64); d: device FP64 [K];
  * sc: device FP64 {||b||^2, target = (eta delta)^2, previous lambda or 0};
  * fixed_lambda > 0 skips the root search.  Writes z (device FP64 [K]) and
- * res (device FP64 [3]) = {lambda, discrepancy^2, status 0 root / 2 clamped / 4 failure}. */
+ * res (device FP64 [4]) = {lambda, discrepancy^2, status 0 root / 2 clamped / 4 failure,
+ * number of Cholesky factorizations}. */
 int mmof_projected_solve(mmof_ctx ctx, int32_t K, const double* GA, const double* GT, const double* d,
                          const double* sc, double fixed_lambda, double* z, double* res);
 

@@ -36,7 +36,8 @@ class mmof_report(C.Structure):
                 ("lambda_", C.POINTER(C.c_double)), ("resid", C.POINTER(C.c_double)),
                 ("rre", C.POINTER(C.c_double)), ("dp_status", C.POINTER(C.c_int32)),
                 ("n_A", C.c_int64), ("n_At", C.c_int64), ("n_theta", C.c_int64), ("n_thetaT", C.c_int64),
-                ("n_flow_updates", C.c_int64), ("n_L", C.c_int64)]
+                ("n_flow_updates", C.c_int64), ("n_L", C.c_int64),
+                ("n_factorizations", C.c_int64)]
 
 
 _P = C.c_void_p

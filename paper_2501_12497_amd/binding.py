@@ -353,7 +353,7 @@ def projected_solve(GA: torch.Tensor, GT: torch.Tensor, d: torch.Tensor, bnorm2:
     A64, T64 = pad(GA), pad(GT)
     sc = torch.tensor([bnorm2, target, prev_lambda], dtype=torch.float64, device=d.device)
     z = torch.empty(K, dtype=torch.float64, device=d.device)
-    res = torch.empty(3, dtype=torch.float64, device=d.device)
+    res = torch.empty(4, dtype=torch.float64, device=d.device)
     dd = d.to(torch.float64).contiguous()
     ctx.bind()
     check(ctx.lib.mmof_projected_solve(ctx.h, K, _ptr(A64), _ptr(T64), _ptr(dd), _ptr(sc), float(fixed_lambda),
@@ -426,4 +426,5 @@ def solve_joint(plan: Plan, b: torch.Tensor, noise_norm: float, u0: Optional[tor
                        resid=list(res[:k]), rre=list(rre[:k]) if u_true is not None else [],
                        dp_status=list(dps[:k]),
                        counts=dict(A=rep.n_A, At=rep.n_At, theta=rep.n_theta, thetaT=rep.n_thetaT,
-                                   flow_updates=rep.n_flow_updates, L=rep.n_L))
+                                   flow_updates=rep.n_flow_updates, L=rep.n_L,
+                                   factorizations=rep.n_factorizations))

@@ -133,7 +133,9 @@ __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles
                 s_d[2] = INT_MAX;
                 s_d[3] = INT_MIN;
             }
-            __syncthreads();
+            // displacement range of the sources whose cell touches the tile: per-thread
+            // bounds, then one LDS atomic per wave
+            int dxn = INT_MAX, dxx = INT_MIN, dyn = INT_MAX, dyx = INT_MIN;
             for (int i = threadIdx.x; i < sw * sh; i += 256) {
                 const int sy = sy0 + i / sw, sx = sx0 + i % sw;
                 const int64_t p = (int64_t)sy * nx + sx;
@@ -146,11 +148,24 @@ __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles
                 s_fy[i] = fy;
                 s_val[i] = rg[p];
                 if (x0 >= tl.x0 - 1 && x0 <= tl.x0 + ATX - 1 && y0 >= tl.y0 - 1 && y0 <= tl.y0 + ATY - 1) {
-                    atomicMin(&s_d[0], x0 - sx);
-                    atomicMax(&s_d[1], x0 - sx);
-                    atomicMin(&s_d[2], y0 - sy);
-                    atomicMax(&s_d[3], y0 - sy);
+                    dxn = min(dxn, x0 - sx);
+                    dxx = max(dxx, x0 - sx);
+                    dyn = min(dyn, y0 - sy);
+                    dyx = max(dyx, y0 - sy);
                 }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                dxn = min(dxn, __shfl_xor(dxn, o));
+                dxx = max(dxx, __shfl_xor(dxx, o));
+                dyn = min(dyn, __shfl_xor(dyn, o));
+                dyx = max(dyx, __shfl_xor(dyx, o));
+            }
+            __syncthreads();  // s_d initialised
+            if ((threadIdx.x & 63) == 0) {
+                atomicMin(&s_d[0], dxn);
+                atomicMax(&s_d[1], dxx);
+                atomicMin(&s_d[2], dyn);
+                atomicMax(&s_d[3], dyx);
             }
             __syncthreads();
             if (inside && s_d[0] <= s_d[1]) {

@@ -45,49 +45,68 @@ __global__ void k_convert(int64_t n, const TI* __restrict__ in, TO* __restrict__
         out[i] = (TO)in[i];
 }
 
-// part[b][j] = sum_{i in chunk b} X_j[i] * y[i]; eight columns per pass over the chunk.
+// Inner products of K columns (and of one extra FP64 column xe, when given) with y.
+// Grid: x = row chunks, y = groups of 8 columns; part[b][j] receives chunk b's sum for
+// column j.  (A single-launch completion by the last workgroup would need a device-scope
+// release per workgroup, which writes back the XCD's L2; a second small launch is cheaper.)
 template <class TX, class TY>
-__global__ __launch_bounds__(KB) void k_mdot_part(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
-                                                  const TY* __restrict__ y, double* __restrict__ part) {
+__global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
+                                             const TY* __restrict__ y, const double* __restrict__ xe,
+                                             double* __restrict__ part) {
     __shared__ double s8[4][8];
+    const int Kt = K + (xe ? 1 : 0);
     const int64_t nb = gridDim.x;
     const int64_t chunk = (n + nb - 1) / nb;
     const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int j0 = 0; j0 < K; j0 += 8) {
-        const int nj = min(8, K - j0);
-        double acc[8];
+    const int j0 = blockIdx.y * 8;
+    const int nj = min(8, Kt - j0);
+    double acc[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += KB) {
-            const double yi = (double)y[i];
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += KB) {
+        const double yi = (double)y[i];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (q < nj) acc[q] += (double)X[(int64_t)(j0 + q) * ld + i] * yi;
+        for (int q = 0; q < 8; ++q) {
+            const int j = j0 + q;
+            if (q < nj) acc[q] += (j < K ? (double)X[(int64_t)j * ld + i] : xe[i]) * yi;
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
-        __syncthreads();
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) s8[w][q] = acc[q];
-        }
-        __syncthreads();
-        if (threadIdx.x < nj)
-            part[(int64_t)blockIdx.x * K + j0 + threadIdx.x] =
-                (s8[0][threadIdx.x] + s8[1][threadIdx.x]) + (s8[2][threadIdx.x] + s8[3][threadIdx.x]);
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s8[w][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < nj)
+        part[(int64_t)blockIdx.x * Kt + j0 + threadIdx.x] =
+            (s8[0][threadIdx.x] + s8[1][threadIdx.x]) + (s8[2][threadIdx.x] + s8[3][threadIdx.x]);
 }
 
-// out[j] = alpha * sum_b part[b][j]  (fixed-order tree over b); one block per j.
-__global__ __launch_bounds__(KB) void k_mdot_final(int nb, int K, const double* __restrict__ part, double alpha,
-                                                   double* __restrict__ out) {
-    __shared__ double s4[4];
-    const int j = blockIdx.x;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += KB) acc += part[(int64_t)b * K + j];
-    const double s = block_sum(acc, s4);
-    if (threadIdx.x == 0) out[j] = alpha * s;
+// Sums of the chunk partials in a fixed order (wave w takes columns w, w+4, ...; lane l sums
+// chunks l, l+64, ...; then a fixed butterfly):
+//   G == null: out[j] = alpha * s_j (j < Kt)
+//   G != null: G[row][j] = G[j][row] = s_j for j < Kt - 1 and dj[0] = s_{Kt-1}.
+__global__ __launch_bounds__(KB) void k_mdot_final(int nb, int Kt, const double* __restrict__ part, double alpha,
+                                                   double* __restrict__ out, double* __restrict__ G, int ldg,
+                                                   int row, double* __restrict__ dj) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int j = w; j < Kt; j += 4) {
+        double a = 0.0;
+        for (int b = lane; b < nb; b += 64) a += part[(int64_t)b * Kt + j];
+        a = wave_sum(a);
+        if (lane == 0) {
+            if (!G)
+                out[j] = alpha * a;
+            else if (j < Kt - 1) {
+                G[(int64_t)row * ldg + j] = a;
+                G[(int64_t)j * ldg + row] = a;
+            } else {
+                dj[0] = a;
+            }
+        }
+    }
 }
 
 // out[i] = beta * out[i] + alpha * sum_j X_j[i] * h[j]   (h on the device)
@@ -103,6 +122,66 @@ __global__ __launch_bounds__(KB) void k_gemv_cols(int64_t n, int K, const TX* __
         for (int j = 0; j < K; ++j) acc += (double)X[(int64_t)j * ld + i] * sh[j];
         out[i] = (beta == 0.0 ? 0.0 : beta * out[i]) + alpha * acc;
     }
+}
+
+// v_i = alpha * sum_j X_j[i] h[j] + beta * y[i]; stores v (FP64) and/or its rounding to TO,
+// and optionally the workgroup's partial of sum (v_i - cv_i)^2 (sum v_i^2 without cv) in
+// part[blockIdx.x].  y and out_d may alias.
+template <class TX, class TO>
+__global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
+                                                   const double* __restrict__ h, double alpha, const double* y,
+                                                   double beta, double* out_d, TO* __restrict__ out_t,
+                                                   const double* __restrict__ cv, double* __restrict__ part) {
+    __shared__ double sh[KMAX_SMALL];
+    __shared__ double s4[4];
+    for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
+    __syncthreads();
+    double e2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+        double acc = 0.0;
+        for (int j = 0; j < K; ++j) acc += (double)X[(int64_t)j * ld + i] * sh[j];
+        const double v = alpha * acc + (y ? beta * y[i] : 0.0);
+        if (out_d) out_d[i] = v;
+        if (out_t) out_t[i] = (TO)v;
+        if (part) {
+            const double e = cv ? v - cv[i] : v;
+            e2 += e * e;
+        }
+    }
+    if (!part) return;
+    const double bs = block_sum(e2, s4);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// out[0] = sum of nb partials in a fixed order (one wavefront)
+__global__ __launch_bounds__(64) void k_sum_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64) a += part[b];
+    a = wave_sum(a);
+    if (threadIdx.x == 0) out[0] = a;
+}
+
+// s = sqrt(s2[0]); out_d = x / s, out_t = (TO)(x / s) (zero when s = 0); s1[0] = s.
+template <class TO>
+__global__ void k_normalize2(int64_t n, const double* x, const double* __restrict__ s2, double* __restrict__ s1,
+                             double* out_d, TO* __restrict__ out_t) {
+    const double s = sqrt(fmax(s2[0], 0.0));
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    if (s1 && blockIdx.x == 0 && threadIdx.x == 0) s1[0] = s;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = x[i] * inv;
+        if (out_d) out_d[i] = v;
+        if (out_t) out_t[i] = (TO)v;
+    }
+}
+
+// out = (double)in + sign * s[0] * q
+template <class TX>
+__global__ void k_axpy_conv(int64_t n, const TX* __restrict__ in, const double* __restrict__ q,
+                            const double* __restrict__ s, double sign, double* __restrict__ out) {
+    const double a = sign * s[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (double)in[i] + a * q[i];
 }
 
 // Weighted Gram G = X^T diag(w) X (K <= 64; w = 1 when null) on the FP64 matrix cores.
@@ -396,15 +475,76 @@ void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double
     if (K <= 0) return;
     const int nb = mdot_blocks(n);
     MMOF_CHECK(K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for a block inner product");
-    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * KMAX_SMALL));
-    hipLaunchKernelGGL((k_mdot_part<TX, TY>), dim3(nb), dim3(KB), 0, c.stream, n, K, X, ld, y, part);
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
+    hipLaunchKernelGGL((k_mdot<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld, y,
+                       (const double*)nullptr, part);
     MMOF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mdot_final, dim3(K), dim3(KB), 0, c.stream, nb, K, part, alpha, out);
+    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(KB), 0, c.stream, nb, K, part, alpha, out, (double*)nullptr, 0, 0,
+                       (double*)nullptr);
     MMOF_LAUNCH_CHECK();
 }
 template void mdot<float, double>(Ctx&, int64_t, int, const float*, int64_t, const double*, double, double*);
 template void mdot<double, double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double, double*);
 template void mdot<float, float>(Ctx&, int64_t, int, const float*, int64_t, const float*, double, double*);
+
+template <class TX>
+void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e, double* G, int ldg, double* dj) {
+    MMOF_CHECK(j >= 0 && j < KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    const int nb = mdot_blocks(n);
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
+    const TX* xj = X + (int64_t)j * ld;
+    hipLaunchKernelGGL((k_mdot<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1, X,
+                       ld, xj, e, part);
+    MMOF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(KB), 0, c.stream, nb, j + 2, part, 1.0, (double*)nullptr, G, ldg,
+                       j, dj);
+    MMOF_LAUNCH_CHECK();
+}
+template void gram_row<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int, double*);
+template void gram_row<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double*, int, double*);
+
+template <class TX, class TO>
+void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, const double* y,
+                double beta, double* out_d, TO* out_t, const double* cv, double* sq) {
+    MMOF_CHECK(K >= 0 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    if (n == 0) {
+        if (sq) set_scalar(c, sq, 0.0);
+        return;
+    }
+    const dim3 grid = grid_for(n, KB, 2048);
+    double* part = sq ? static_cast<double*>(c.work("gemv_part", sizeof(double) * 2048)) : nullptr;
+    hipLaunchKernelGGL((k_gemv_fused<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta, out_d,
+                       out_t, cv, part);
+    MMOF_LAUNCH_CHECK();
+    if (sq) {
+        hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c.stream, (int)grid.x, (const double*)part, sq);
+        MMOF_LAUNCH_CHECK();
+    }
+}
+template void gemv_fused<double, float>(Ctx&, int64_t, int, const double*, int64_t, const double*, double,
+                                        const double*, double, double*, float*, const double*, double*);
+template void gemv_fused<double, double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double,
+                                         const double*, double, double*, double*, const double*, double*);
+template void gemv_fused<float, float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double,
+                                       const double*, double, double*, float*, const double*, double*);
+
+template <class TO>
+void normalize2(Ctx& c, int64_t n, const double* x, const double* s2, double* s1, double* out_d, TO* out_t) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_normalize2<TO>, grid_for(n, KB, 8192), dim3(KB), 0, c.stream, n, x, s2, s1, out_d, out_t);
+    MMOF_LAUNCH_CHECK();
+}
+template void normalize2<float>(Ctx&, int64_t, const double*, const double*, double*, double*, float*);
+template void normalize2<double>(Ctx&, int64_t, const double*, const double*, double*, double*, double*);
+
+template <class TX>
+void axpy_conv(Ctx& c, int64_t n, const TX* in, const double* q, const double* s, double sign, double* out) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_axpy_conv<TX>, grid_for(n, KB, 8192), dim3(KB), 0, c.stream, n, in, q, s, sign, out);
+    MMOF_LAUNCH_CHECK();
+}
+template void axpy_conv<float>(Ctx&, int64_t, const float*, const double*, const double*, double, double*);
+template void axpy_conv<double>(Ctx&, int64_t, const double*, const double*, const double*, double, double*);
 
 template <class TX>
 void gemv_cols(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, double beta,

@@ -106,8 +106,9 @@ struct Eval {
     double D2, dD2, z;  // z: this lane's entry
 };
 
-__device__ Eval evaluate(SmallLds& s, int K, double lam, double bb, double d, bool deriv) {
+__device__ Eval evaluate(SmallLds& s, int K, double lam, double bb, double d, bool deriv, int& nfac) {
     Eval e{false, 0.0, 0.0, 0.0};
+    ++nfac;
     if (!chol(s, K, lam)) return e;
     e.ok = true;
     e.z = chol_solve(s, K, d);
@@ -125,7 +126,7 @@ __device__ Eval evaluate(SmallLds& s, int K, double lam, double bb, double d, bo
 __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restrict__ GA, const double* __restrict__ GT,
                                                     const double* __restrict__ dvec, const double* __restrict__ sc,
                                                     double fixed_lambda, double* __restrict__ zout,
-                                                    double* __restrict__ res) {
+                                                    double* __restrict__ res, double* __restrict__ lam_out) {
     __shared__ SmallLds s;
     const int i = threadIdx.x;
     // coalesced loads: each instruction moves one contiguous row of the 64-wide matrices
@@ -142,9 +143,10 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
     const double bb = sc[0], target = sc[1];
     double lam = fixed_lambda;
     int status = 0;
+    int nfac = 0;
     Eval e{false, 0.0, 0.0, 0.0};
     if (fixed_lambda > 0.0) {
-        e = evaluate(s, K, lam, bb, d, false);
+        e = evaluate(s, K, lam, bb, d, false, nfac);
     } else {
         const double trA = wave_sum64(i < K ? s.A[i][i] : 0.0);
         const double trT = wave_sum64(i < K ? s.T[i][i] : 0.0);
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
         // evaluated when a step would leave through it: an interior root proves, by
         // monotonicity of D^2, that neither end needs clamping.
         for (int it = 0; it < 200; ++it) {
-            e = evaluate(s, K, pow(10.0, mu), bb, d, true);
+            e = evaluate(s, K, pow(10.0, mu), bb, d, true, nfac);
             const double f = e.ok ? e.D2 - target : -target;
             MMOF_SMALL_TRACE(it, mu, e, f, lo, hi);
             if (f < 0.0)
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
             if (!(nmu > lo && nmu < hi)) {
                 if (f < 0.0 && !hi_checked && hi == HI) {
                     hi_checked = true;
-                    const Eval eh = evaluate(s, K, pow(10.0, HI), bb, d, false);
+                    const Eval eh = evaluate(s, K, pow(10.0, HI), bb, d, false, nfac);
                     if (eh.ok && eh.D2 < target) {
                         e = eh;
                         mu = HI;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
                 }
                 if (f > 0.0 && !lo_checked && lo == LO) {
                     lo_checked = true;
-                    const Eval el = evaluate(s, K, pow(10.0, LO), bb, d, false);
+                    const Eval el = evaluate(s, K, pow(10.0, LO), bb, d, false, nfac);
                     if (el.ok && el.D2 > target) {
                         e = el;
                         mu = LO;
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
             }
             if (fabs(nmu - mu) <= 1e-11 * fmax(1.0, fabs(mu)) || hi - lo <= 1e-14 * fmax(1.0, fabs(mu))) {
                 mu = nmu;
-                e = evaluate(s, K, pow(10.0, mu), bb, d, false);
+                e = evaluate(s, K, pow(10.0, mu), bb, d, false, nfac);
                 break;
             }
             mu = nmu;
@@ -209,14 +211,17 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
         res[0] = lam;
         res[1] = e.D2;
         res[2] = (double)status;
+        res[3] = (double)nfac;
+        if (lam_out) lam_out[0] = lam;
     }
 }
 
 void small_solve(Ctx& c, int K, const double* GA, const double* GT, const double* d, const double* sc,
-                 double fixed_lambda, double* z, double* res) {
+                 double fixed_lambda, double* z, double* res, double* lam_out) {
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "Krylov basis size out of range");
     ScopedTime st(&c, "small_solve");
-    hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(64), 0, c.stream, K, GA, GT, d, sc, fixed_lambda, z, res);
+    hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(64), 0, c.stream, K, GA, GT, d, sc, fixed_lambda, z, res,
+                       lam_out);
     MMOF_LAUNCH_CHECK();
 }
 

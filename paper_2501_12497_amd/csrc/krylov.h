@@ -7,13 +7,30 @@ namespace mmof {
 
 static constexpr int KMAX_SMALL = 64;  // largest Krylov basis handled by the small solve
 
-// out[j] = alpha * X_j^T y for j < K (X column-major [K][ld]).
+// out[j] = alpha * X_j^T y for j < K (X column-major [K][ld]); one launch.
 template <class TX, class TY>
 void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double alpha, double* out);
+// Row and column j of a Gram matrix and one more inner product, in one launch:
+// G[j][k] = G[k][j] = X_k^T X_j (k <= j), dj[0] = X_j^T e.
+template <class TX>
+void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e, double* G, int ldg, double* dj);
 // out = beta*out + alpha * X h
 template <class TX>
 void gemv_cols(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, double beta,
                double* out);
+// v = alpha * X h + beta * y (y may be null, and may alias out_d), in one launch:
+// out_d = v (FP64, may be null), out_t = v rounded to TO (may be null), and, when sq is not
+// null, sq[0] = sum_i (v_i - cv_i)^2 (cv may be null: sum of v_i^2).
+template <class TX, class TO>
+void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, const double* y,
+                double beta, double* out_d, TO* out_t, const double* cv, double* sq);
+// s = sqrt(s2[0]) (written to s1 when not null); out_d = x / s and out_t = (TO)(x / s)
+// (a zero vector when s = 0).
+template <class TO>
+void normalize2(Ctx& c, int64_t n, const double* x, const double* s2, double* s1, double* out_d, TO* out_t);
+// out = (double)in + sign * s[0] * q
+template <class TX>
+void axpy_conv(Ctx& c, int64_t n, const TX* in, const double* q, const double* s, double sign, double* out);
 // w[i] = 1/sqrt(nu[i]^2 + eps^2) in FP64
 template <class TX>
 void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w);
@@ -45,8 +62,10 @@ void weight_mul(Ctx& c, int64_t n, const double* w, const TX* x, TX* y);
 // Small projected solve (one wavefront).  Inputs on the device: GA, GT (K x K, ld KMAX_SMALL),
 // d (K), and the scalars bb = ||b||^2 and target = (eta*delta)^2 in sc[0..1].
 // Writes z (K), and res[0] = lambda, res[1] = discrepancy^2, res[2] = status (0 root, 2 clamped,
-// 4 factorization failure).  fixed_lambda > 0 skips the discrepancy principle.
+// 4 factorization failure), res[3] = factorizations done.  fixed_lambda > 0 skips the
+// discrepancy principle.  sc[2] is the warm start (previous lambda, 0: none); when
+// lam_out is not null the chosen lambda is also written there.
 void small_solve(Ctx& c, int K, const double* GA, const double* GT, const double* d, const double* sc,
-                 double fixed_lambda, double* z, double* res);
+                 double fixed_lambda, double* z, double* res, double* lam_out = nullptr);
 
 }  // namespace mmof

@@ -56,7 +56,7 @@ struct Solver {
 
     // workspace
     double *V, *U, *r, *tmp_n, *tmp_m, *GA, *GT, *dvec, *z, *h, *sc, *res, *scal;
-    TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *flow_v, *flow_vr, *flow_tmp, *I;
+    TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *yW, *flow_v, *flow_vr, *flow_tmp, *I;
     double* w2;  // FP64 MM weights of the rows of Theta
     int32_t *rad_v, *rad_vr;
     double* host;  // pinned report staging
@@ -96,12 +96,12 @@ struct Solver {
         tmp_m = ws<double>("tmp_m", m);
         h = ws<double>("h", KMAX_SMALL);
         sc = ws<double>("sc", 8);
-        scal = ws<double>("scal", 16);
+        scal = ws<double>("scal", 24);
         vin_n = wsx("vin_n", n);
         vin_m = wsx("vin_m", m);
         out_n = wsx("out_n", n);
         host = static_cast<double*>(c.pinned(64 * sizeof(double)));
-        fill_zero<double>(c, 16, scal);
+        fill_zero<double>(c, 24, scal);
         if (!full) return;
         tmp_n = ws<double>("tmp_n", n);
         GA = ws<double>("GA", KMAX_SMALL * KMAX_SMALL);
@@ -115,6 +115,7 @@ struct Solver {
         out_n2 = wsx("out_n2", n);
         nu = wsx("nu", R);
         yR = wsx("yR", R);
+        yW = wsx("yW", R);
         w2 = ws<double>("w2", R);
         flow_v = wsx("flow_v", 2 * g.pair_px);
         flow_vr = wsx("flow_vr", 2 * g.pair_px);
@@ -164,29 +165,26 @@ struct Solver {
     void norm_into(int64_t len, const double* x, double* out) {  // out = ||x||^2
         mdot<double, double>(c, len, 1, x, len, x, 1.0, out);
     }
-    // x <- x - Q (Q^T x), twice (Q has k columns of length len)
-    void reorth(int64_t len, const double* Q, int k, double* x) {
-        if (k <= 0) return;
+    // x <- x - Q (Q^T x), twice (Q has k columns of length len); sq[0] = ||x||^2 afterwards
+    void reorth(int64_t len, const double* Q, int k, double* x, double* sq) {
+        if (k <= 0) {
+            norm_into(len, x, sq);
+            return;
+        }
         for (int pass = 0; pass < 2; ++pass) {
             mdot<double, double>(c, len, k, Q, len, x, 1.0, h);
-            gemv_cols<double>(c, len, k, Q, len, h, -1.0, 1.0, x);
+            gemv_fused<double, double>(c, len, k, Q, len, h, -1.0, x, 1.0, x, nullptr, nullptr,
+                                       pass == 1 ? sq : nullptr);
         }
     }
-    // s1 = sqrt(s2); out = x / s1  (s2 holds the squared norm; all on the device)
-    void normalize_sq(int64_t len, const double* x, const double* s2, double* s1, double* out) {
-        sqrt_scalar(c, s2, s1);
-        normalize(c, len, x, s1, 0.0, out);
-    }
 
-    void add_column(int j) {
-        // H v_j, the row/column j of G_H, d_j = (H v_j)^T b and Theta v_j
-        const double* vj = V + (int64_t)j * n;
-        convert<double, TX>(c, n, vj, vin_n);
+    // H v_j, the row/column j of G_H, d_j = (H v_j)^T b and Theta v_j; vin_n already holds
+    // v_j in TX when have_vin
+    void add_column(int j, bool have_vin) {
+        if (!have_vin) convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
         TX* avj = AV + (int64_t)j * m;
         A(vin_n, avj);
-        mdot<TX, TX>(c, m, j + 1, AV, m, avj, 1.0, h);
-        put_rowcol(c, GA, KMAX_SMALL, j, h);
-        mdot<TX, double>(c, m, 1, avj, m, b, 1.0, dvec + j);
+        gram_row<TX>(c, m, j, AV, m, b, GA, KMAX_SMALL, dvec + j);
         theta(vin_n, TV + (int64_t)j * R);
     }
 
@@ -241,31 +239,25 @@ struct Solver {
         int K = ph.K_in;
         if (K == 0) {
             // ---- Golub-Kahan start: u_1 = b/||b||, ell right vectors, both bases re-orthogonalised
-            // scalar slots: scal[0..3] = alpha^2, alpha, beta^2, beta
-            norm_into(m, b, scal + 11);
-            normalize_sq(m, b, scal + 11, scal + 12, U);
-            convert<double, TX>(c, m, U, vin_m);
+            // scalar slots: scal[0..3] = alpha^2, alpha, beta^2, beta; the normalisations also
+            // leave the new vector in the operator precision for the next product
+            norm_into(m, b, scal + 12);
+            normalize2<TX>(c, m, b, scal + 12, scal + 13, U, vin_m);
             At(vin_m, out_n);
             convert<TX, double>(c, n, out_n, r);
             norm_into(n, r, scal);
-            normalize_sq(n, r, scal, scal + 1, V);
+            normalize2<TX>(c, n, r, scal, scal + 1, V, vin_n);
             for (int i = 1; i < p.ell; ++i) {
                 // w = H v_{i-1} - alpha u_{i-1}
-                convert<double, TX>(c, n, V + (int64_t)(i - 1) * n, vin_n);
                 A(vin_n, vin_m);
-                convert<TX, double>(c, m, vin_m, tmp_m);
-                axpy_dev(c, m, U + (int64_t)(i - 1) * m, tmp_m, scal + 1, -1.0);
-                reorth(m, U, i, tmp_m);
-                norm_into(m, tmp_m, scal + 2);
-                normalize_sq(m, tmp_m, scal + 2, scal + 3, U + (int64_t)i * m);
+                axpy_conv<TX>(c, m, vin_m, U + (int64_t)(i - 1) * m, scal + 1, -1.0, tmp_m);
+                reorth(m, U, i, tmp_m, scal + 2);
+                normalize2<TX>(c, m, tmp_m, scal + 2, scal + 3, U + (int64_t)i * m, vin_m);
                 // v = H^T u_i - beta v_{i-1}
-                convert<double, TX>(c, m, U + (int64_t)i * m, vin_m);
                 At(vin_m, out_n);
-                convert<TX, double>(c, n, out_n, r);
-                axpy_dev(c, n, V + (int64_t)(i - 1) * n, r, scal + 3, -1.0);
-                reorth(n, V, i, r);
-                norm_into(n, r, scal);
-                normalize_sq(n, r, scal, scal + 1, V + (int64_t)i * n);
+                axpy_conv<TX>(c, n, out_n, V + (int64_t)(i - 1) * n, scal + 3, -1.0, r);
+                reorth(n, V, i, r, scal);
+                normalize2<TX>(c, n, r, scal, scal + 1, V + (int64_t)i * n, vin_n);
             }
             K = p.ell;
             if (ph.start_only) {
@@ -292,11 +284,15 @@ struct Solver {
             launch_flow_radius(c, g, dt, flow_v, rad_v);
             launch_flow_radius(c, g, dt, flow_vr, rad_vr);
         }
-        for (int j = 0; j < K; ++j) add_column(j);
+        for (int j = 0; j < K; ++j) add_column(j, false);
         int status = 0;
         int iters = 0;
         const double gamma = p.alpha * p.alpha;
         bool stopped = false;
+        bool nu_fresh = false;  // nu already holds Theta u^(k) (from the previous residual)
+        // report slots: scal[6] = ||u - u_true||^2, scal[7] = ||r||^2, scal[8..11] = lambda,
+        // D^2, status, factorizations (written by the projected solve)
+        double* res = scal + 8;
         for (int k = ph.k_begin; k < ph.k_end; ++k) {
             // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
             if (flow && k % p.tau == 0) {
@@ -318,45 +314,38 @@ struct Solver {
                     theta_flow(vin_n, TV + (int64_t)j * R);
                 }
                 if (rep) rep->n_flow_updates++;
+                nu_fresh = false;
             }
-            // 2. nu = Theta u^(k); weighted Gram of Theta V
-            theta(u_op, nu);
+            // 2. nu = Theta u^(k); FP64 weights; weighted Gram of Theta V
+            if (!nu_fresh) theta(u_op, nu);
             mm_weights_f64<TX>(c, R, nu, p.eps, w2);
             wgram<TX>(c, R, K, TV, R, w2, GT, KMAX_SMALL);
-            // 3-5. lambda (discrepancy principle) and z
-            small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res);
-            copy_scalar(c, sc + 2, res);
-            // 6. u^(k+1) = V z
-            gemv_cols<double>(c, n, K, V, n, z, 1.0, 0.0, u_io);
-            convert<double, TX>(c, n, u_io, u_op);
-            if (p.u_true) {
-                sub(c, n, u_io, p.u_true, tmp_n);
-                norm_into(n, tmp_n, scal + 6);
-            }
+            // 3-5. lambda (discrepancy principle) and z; lambda is kept in sc[2] as the next warm start
+            small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
+            // 6. u^(k+1) = V z (FP64 and operator copies, and ||u - u_true||^2)
+            gemv_fused<double, TX>(c, n, K, V, n, z, 1.0, nullptr, 0.0, u_io, u_op, p.u_true,
+                                   p.u_true ? scal + 6 : nullptr);
             const bool last = ph.final && (k == ph.k_end - 1);
             if (!last) {
                 // 7. r = H^T (H V z - b) + lambda Theta^T P^2 Theta V z
-                gemv_cols<TX>(c, m, K, AV, m, z, 1.0, 0.0, tmp_m);
-                axpby(c, m, 1.0, tmp_m, -1.0, b, tmp_m);
-                convert<double, TX>(c, m, tmp_m, vin_m);
+                gemv_fused<TX, TX>(c, m, K, AV, m, z, 1.0, b, -1.0, nullptr, vin_m, nullptr, nullptr);
                 At(vin_m, out_n);
                 theta(u_op, yR);
-                weight_mul<TX>(c, R, w2, yR, yR);
-                thetaT(yR, out_n2);
+                weight_mul<TX>(c, R, w2, yR, yW);
+                thetaT(yW, out_n2);
                 residual_combine<TX>(c, n, out_n, out_n2, res, r);
-                // 8. CGS2 against V
-                reorth(n, V, K, r);
-                norm_into(n, r, scal + 7);
+                // 8. CGS2 against V, ||r||^2
+                reorth(n, V, K, r, scal + 7);
+                // Theta u^(k+1) is the next iteration's nu unless the flow changes first
+                std::swap(nu, yR);
+                nu_fresh = true;
             }
-            // report: lambda, D^2, status, rre^2, ||r||^2
-            copy_scalar(c, scal + 8, res);
-            copy_scalar(c, scal + 9, res + 1);
-            copy_scalar(c, scal + 10, res + 2);
-            MMOF_HIP(hipMemcpyAsync(host, scal + 6, 5 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            MMOF_HIP(hipMemcpyAsync(host, scal + 6, 6 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
             MMOF_HIP(hipStreamSynchronize(c.stream));
             const double rre2 = host[0], rnorm = std::sqrt(std::max(host[1], 0.0));
             const double lam = host[2], D2 = host[3];
             const int st = (int)host[4];
+            if (rep) rep->n_factorizations += (int64_t)host[5];
             iters = k + 1;
             if (st == 2) status = std::max(status, (int)MMOF_WARN_DP_CLAMPED);
             if (st == 4) {
@@ -386,8 +375,8 @@ struct Solver {
                 stopped = true;
                 break;
             }
-            normalize_sq(n, r, scal + 7, scal + 13, V + (int64_t)K * n);
-            add_column(K);
+            normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
+            add_column(K, true);
             ++K;
         }
         if (rep) {
@@ -424,6 +413,7 @@ int solve_joint(Plan& P, const double* b, double delta, const mmof_solve_params&
     MMOF_CHECK(p.refine_iters >= 0, MMOF_ERR_INVALID, "refine_iters must be >= 0");
     if (rep) {
         rep->n_A = rep->n_At = rep->n_theta = rep->n_thetaT = rep->n_flow_updates = rep->n_L = 0;
+        rep->n_factorizations = 0;
         rep->iters = 0;
         rep->status = 0;
     }
