@@ -298,13 +298,8 @@ int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const
         void* I = ctx->work("fu_I", es * 3 * g.pair_px);
         void* tmp = ctx->work("fu_tmp", es * 2 * g.pair_px);
         launch_of_derivs(*ctx, g, dt, u, I, delta_r);
-        void* a = v;
-        void* b = tmp;
-        for (int s = 0; s < n_sweeps; ++s) {
-            launch_hs_sweep(*ctx, g, dt, I, a, b, alpha * alpha);
-            std::swap(a, b);
-        }
-        if (a != v) MMOF_HIP(hipMemcpyAsync(v, a, es * 2 * g.pair_px, hipMemcpyDeviceToDevice, ctx->stream));
+        if (launch_hs_sweeps(*ctx, g, dt, I, v, tmp, alpha * alpha, n_sweeps))
+            MMOF_HIP(hipMemcpyAsync(v, tmp, es * 2 * g.pair_px, hipMemcpyDeviceToDevice, ctx->stream));
         if (v_rev) launch_reverse_flow(*ctx, g, dt, v, v_rev, nullptr);
         return MMOF_OK;
     });

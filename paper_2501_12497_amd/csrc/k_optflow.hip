@@ -41,38 +41,103 @@ __global__ __launch_bounds__(256) void k_of_derivs(const Tile* __restrict__ tile
     Ip[2 * np + p] = It / (box * box);
 }
 
-// One exact 2x2 block-Jacobi sweep: sbar = mean of in-image 4-neighbours,
-// s = sbar - g (g.sbar + I_t) / (gamma d + |g|^2).
+// Exact 2x2 block-Jacobi sweeps for the p = q = 2 flow energy: per pixel,
+// sbar = mean of the in-image 4-neighbours, s = sbar - g (g.sbar + I_t) / (gamma d + |g|^2).
+// Up to HS_MAX block-Jacobi sweeps per launch (temporal blocking).  A workgroup owns an
+// HTW x HTH tile of a pair and loads the tile with a halo of HS_MAX pixels into LDS; after q
+// sweeps the values within q pixels of the halo's outer edge are stale (their outside
+// neighbours were not loaded), so the tile itself is exact after up to HS_MAX sweeps.  Each
+// thread keeps, for its HPT halo pixels, the derivatives, 1/d and 1/(gamma d + |g|^2) in
+// registers, so a sweep is a few LDS reads and multiply-adds per pixel.  (Reciprocals
+// replace the divisions of the sweep formula: the values differ from it by rounding only.)
+static constexpr int HTW = 64, HTH = 16, HS_MAX = 8;
+static constexpr int HRW = HTW + 2 * HS_MAX, HRH = HTH + 2 * HS_MAX;  // 80 x 32 halo region
+static constexpr int HS_THREADS = 640;
+static constexpr int HPT = HRW * HRH / HS_THREADS;                   // pixels per thread (4)
+static_assert(HRW * HRH == HS_THREADS * HPT, "halo region must split evenly over the workgroup");
+
 template <class T>
-__global__ __launch_bounds__(256) void k_hs_sweep(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
-                                                  const T* __restrict__ I, const T* __restrict__ vin,
-                                                  T* __restrict__ vout, T gamma) {
+__global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict__ tiles,
+                                                         const FrameInfo* __restrict__ fr, const T* __restrict__ I,
+                                                         const T* __restrict__ vin, T* __restrict__ vout, T gamma,
+                                                         int nsw) {
+    __shared__ T sv[2][2][HRH * HRW];  // [buffer][component][pixel]
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
-    const int x = tl.x0 + (int)(threadIdx.x % OTW);
-    const int y = tl.y0 + (int)(threadIdx.x / OTW);
-    if (x >= f.nx || y >= f.ny) return;
     const int nx = f.nx, ny = f.ny;
     const int64_t np = (int64_t)nx * ny;
-    const int64_t p = (int64_t)y * nx + x;
+    const int ox = tl.x0 - HS_MAX, oy = tl.y0 - HS_MAX;  // image coordinates of the region origin
     const T* sx = vin + 2 * f.pair_off;
-    const T* sy = sx + np;
-    T ax = T(0), ay = T(0);
-    int d = 0;
-    // neighbour order: y-1, y+1, x-1, x+1
-    if (y > 0) { ax += sx[p - nx]; ay += sy[p - nx]; ++d; }
-    if (y < ny - 1) { ax += sx[p + nx]; ay += sy[p + nx]; ++d; }
-    if (x > 0) { ax += sx[p - 1]; ay += sy[p - 1]; ++d; }
-    if (x < nx - 1) { ax += sx[p + 1]; ay += sy[p + 1]; ++d; }
-    const T dd = T(d);
-    ax /= dd;
-    ay /= dd;
     const T* Ip = I + 3 * f.pair_off;
-    const T gx = Ip[p], gy = Ip[np + p], gt = Ip[2 * np + p];
-    const T k = (gx * ax + gy * ay + gt) / (gamma * dd + gx * gx + gy * gy);
+    T gx[HPT], gy[HPT], gt[HPT], rden[HPT], rd[HPT];
+    int nbr[HPT][4];  // LDS index of the y-1, y+1, x-1, x+1 neighbours, -1 outside the image
+    bool live[HPT];
+#pragma unroll
+    for (int r = 0; r < HPT; ++r) {
+        const int idx = threadIdx.x + HS_THREADS * r;
+        const int ry = idx / HRW, rx = idx % HRW;
+        const int x = ox + rx, y = oy + ry;
+        const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
+        live[r] = in;
+        T a = T(0), b = T(0);
+        gx[r] = gy[r] = gt[r] = T(0);
+        rden[r] = rd[r] = T(0);
+        // neighbours outside the loaded region read the pixel itself (stale halo only)
+        nbr[r][0] = (in && y > 0) ? (ry > 0 ? idx - HRW : idx) : -1;
+        nbr[r][1] = (in && y < ny - 1) ? (ry < HRH - 1 ? idx + HRW : idx) : -1;
+        nbr[r][2] = (in && x > 0) ? (rx > 0 ? idx - 1 : idx) : -1;
+        nbr[r][3] = (in && x < nx - 1) ? (rx < HRW - 1 ? idx + 1 : idx) : -1;
+        if (in) {
+            const int64_t p = (int64_t)y * nx + x;
+            a = sx[p];
+            b = sx[np + p];
+            gx[r] = Ip[p];
+            gy[r] = Ip[np + p];
+            gt[r] = Ip[2 * np + p];
+            const int d = (nbr[r][0] >= 0) + (nbr[r][1] >= 0) + (nbr[r][2] >= 0) + (nbr[r][3] >= 0);
+            rd[r] = T(1) / T(d);
+            rden[r] = T(1) / (gamma * T(d) + gx[r] * gx[r] + gy[r] * gy[r]);
+        }
+        sv[0][0][idx] = a;
+        sv[0][1][idx] = b;
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int q = 0; q < nsw; ++q) {
+        const T* cx = sv[cur][0];
+        const T* cy = sv[cur][1];
+#pragma unroll
+        for (int r = 0; r < HPT; ++r) {
+            if (!live[r]) continue;
+            const int idx = threadIdx.x + HS_THREADS * r;
+            T ax = T(0), ay = T(0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {  // neighbour order: y-1, y+1, x-1, x+1
+                const int j = nbr[r][e];
+                if (j >= 0) {
+                    ax += cx[j];
+                    ay += cy[j];
+                }
+            }
+            ax *= rd[r];
+            ay *= rd[r];
+            const T k = (gx[r] * ax + gy[r] * ay + gt[r]) * rden[r];
+            sv[cur ^ 1][0][idx] = ax - gx[r] * k;
+            sv[cur ^ 1][1][idx] = ay - gy[r] * k;
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
     T* o = vout + 2 * f.pair_off;
-    o[p] = ax - gx * k;
-    o[np + p] = ay - gy * k;
+#pragma unroll
+    for (int r = 0; r < HPT; ++r) {
+        const int idx = threadIdx.x + HS_THREADS * r;
+        const int ry = idx / HRW, rx = idx % HRW;
+        if (rx < HS_MAX || rx >= HS_MAX + HTW || ry < HS_MAX || ry >= HS_MAX + HTH || !live[r]) continue;
+        const int64_t p = (int64_t)(oy + ry) * nx + (ox + rx);
+        o[p] = sv[cur][0][idx];
+        o[np + p] = sv[cur][1][idx];
+    }
 }
 
 // Reverse flow: target q gathers, in raster order of the sources p, every p with
@@ -131,16 +196,26 @@ void launch_of_derivs(Ctx& c, Geom& g, int dt, const void* u, void* I, int dr) {
     });
 }
 
-void launch_hs_sweep(Ctx& c, Geom& g, int dt, const void* I, const void* vin, void* vout, double gamma) {
-    if (g.n_pairs == 0) return;
-    const TileList& tl = g.tile_list(c.stream, OTW, OTH, true);
+int launch_hs_sweeps(Ctx& c, Geom& g, int dt, const void* I, void* v, void* tmp, double gamma, int n_sweeps) {
+    if (g.n_pairs == 0 || n_sweeps <= 0) return 0;
+    const TileList& tl = g.tile_list(c.stream, HTW, HTH, true);
+    int done = 0, parity = 0;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "hs_sweep");
-        hipLaunchKernelGGL(k_hs_sweep<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), (const T*)I, (const T*)vin, (T*)vout, (T)gamma);
-        MMOF_LAUNCH_CHECK();
+        T* a = (T*)v;
+        T* b = (T*)tmp;
+        while (done < n_sweeps) {
+            const int q = std::min(HS_MAX, n_sweeps - done);
+            ScopedTime st(&c, "hs_multi");
+            hipLaunchKernelGGL(k_hs_multi<T>, dim3((unsigned)tl.count), dim3(HS_THREADS), 0, c.stream, tl.buf.as<Tile>(),
+                               g.dframes(), (const T*)I, (const T*)a, b, (T)gamma, q);
+            MMOF_LAUNCH_CHECK();
+            std::swap(a, b);
+            parity ^= 1;
+            done += q;
+        }
     });
+    return parity;
 }
 
 void launch_reverse_flow(Ctx& c, Geom& g, int dt, const void* v, void* vr, const int32_t* d_radius) {

@@ -21,7 +21,9 @@ void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out);
 
 // App. C derivatives, Horn-Schunck sweeps, reverse flow.
 void launch_of_derivs(Ctx& c, Geom& g, int dt, const void* u, void* I, int dr);
-void launch_hs_sweep(Ctx& c, Geom& g, int dt, const void* I, const void* vin, void* vout, double gamma);
+// n_sweeps Horn-Schunck sweeps starting from v, several per launch, ping-ponging between
+// v and tmp; returns 1 when the result is in tmp, 0 when it is in v.
+int launch_hs_sweeps(Ctx& c, Geom& g, int dt, const void* I, void* v, void* tmp, double gamma, int n_sweeps);
 void launch_reverse_flow(Ctx& c, Geom& g, int dt, const void* v, void* vr, const int32_t* d_radius);
 
 // Elementwise.

@@ -297,13 +297,8 @@ struct Solver {
             // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
             if (flow && k % p.tau == 0) {
                 launch_of_derivs(c, g, dt, u_op, I, p.delta_r);
-                TX* a = flow_v;
-                TX* bbuf = flow_tmp;
-                for (int s = 0; s < p.n_sweeps; ++s) {
-                    launch_hs_sweep(c, g, dt, I, a, bbuf, gamma);
-                    std::swap(a, bbuf);
-                }
-                if (a != flow_v) convert<TX, TX>(c, 2 * g.pair_px, a, flow_v);
+                if (launch_hs_sweeps(c, g, dt, I, flow_v, flow_tmp, gamma, p.n_sweeps))
+                    convert<TX, TX>(c, 2 * g.pair_px, flow_tmp, flow_v);
                 launch_flow_radius(c, g, dt, flow_v, rad_v);
                 if (p.use_reverse) {
                     launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);

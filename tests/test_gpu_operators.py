@@ -268,6 +268,21 @@ def test_flow_update_and_reverse(B, which):
     assert rel(host(vr), exp_r) < tol
 
 
+@pytest.mark.parametrize("n_sweeps", [0, 1, 8, 9, 40])
+def test_flow_update_sweep_counts_small_frames(B, n_sweeps):
+    """Sweep counts around the per-launch block of sweeps, on frames smaller than one tile
+    and its halo (2x2, 5x3, 3x70 frames in one ragged stack), FP64 against the oracle."""
+    import torch
+    sizes = [(2, 2, 2), (3, 5, 3), (2, 3, 70)]
+    r = np.random.default_rng(26)
+    us = [r.standard_normal(sz) for sz in sizes]
+    vs0 = [r.uniform(-1, 1, (sz[0] - 1, 2, sz[1], sz[2])) for sz in sizes]
+    v = dev(pack(vs0), torch.float64)
+    B.flow_update(B.Stack(sizes), dev(pack(us), torch.float64), v, alpha=0.2, n_sweeps=n_sweeps, delta_r=1)
+    exp = pack([optflow.flow_update(u, v0, 0.2, n_sweeps, 1) for u, v0 in zip(us, vs0)])
+    assert rel(host(v), exp) < TOL64
+
+
 def test_reverse_flow_exact_on_half_integers(B):
     import torch
     sizes = [(2, 9, 11)]
