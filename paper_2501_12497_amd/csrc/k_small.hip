@@ -10,10 +10,11 @@
 // (an end is taken when the root lies beyond it) and found by Newton steps in mu,
 // safeguarded by bisection of the bracket, starting from the previous lambda.
 //
-// One lane owns one row (K <= 64).  Each evaluation factors M = G_H + lambda G_T with a
-// left-looking Cholesky (the inner products only read LDS, so they pipeline) and solves
-// with the factor held in LDS and the right-hand side in registers, broadcasting the
-// pivot entries with readlane.
+// One wavefront; K <= 64.  Each evaluation factors M = G_H + lambda G_T with a blocked
+// Cholesky (registers and matrix cores), then solves with the factor: the right-hand side is one entry
+// per lane and each step broadcasts the finished entry with readlane.  D^2 and its
+// derivative only need forward solves (d^T z = ||L^{-1} d||^2, w^T M^{-1} w = ||L^{-1} w||^2)
+// plus one backward solve for z.
 #include "dev.h"
 #include "krylov.h"
 
@@ -30,7 +31,6 @@ struct SmallLds {
     double A[KMAX_SMALL][KP];
     double T[KMAX_SMALL][KP];
     double L[KMAX_SMALL][KP];
-    double invd[KMAX_SMALL];
 };
 
 __device__ __forceinline__ double bcast(double v, int lane) {
@@ -48,57 +48,116 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return bcast(v, 0);
 }
 
-// Left-looking Cholesky of M = A + lam T into s.L (lower) and s.invd; false on a
-// non-positive pivot (uniform across the wave).
-__device__ bool chol(SmallLds& s, int K, double lam) {
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps r <- r (3 - x r^2) / 2
+// (each step squares the relative error), a short dependency chain on the pivot path.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    return r;
+}
+
+// Blocked Cholesky of M = A + lam T into the lower triangle of s.L, in 16-column block
+// columns (rows and columns K..16*ceil(K/16)-1 are padded with the identity).  Lane i owns
+// row i.  A block column is loaded into registers and factored right-looking there (the
+// pivot and the finished column entries are broadcast with readlane), written back, and
+// the trailing lower blocks are updated on the FP64 matrix cores:
+// M_{I,J'} -= L_{I,J} L_{J',J}^T with v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; the 16x16 result is D[l/16 + 4v][l%16] in four doubles per lane).
+// Returns false on a non-positive pivot (uniform across the wave); on success *inv holds
+// 1 / L[lane][lane].
+__device__ bool chol(SmallLds& s, int K, double lam, double* inv) {
     const int i = threadIdx.x;
-    for (int k = 0; k < K; ++k) {
-        double dot = 0.0;
-        if (i >= k && i < K) {
-#pragma unroll 8
-            for (int j = 0; j < k; ++j) dot += s.L[i][j] * s.L[k][j];
+    const int nbk = (K + 15) >> 4;
+    const int KP = nbk << 4;
+    for (int c = 0; c < KP; ++c)
+        if (c <= i && i < KP) s.L[i][c] = (i < K && c < K) ? s.A[i][c] + lam * s.T[i][c] : (i == c ? 1.0 : 0.0);
+    __syncthreads();
+    double my_inv = 0.0;
+    for (int J = 0; J < nbk; ++J) {
+        const int c0 = J << 4;
+        double a[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = (i >= c0 + c && i < KP) ? s.L[i][c0 + c] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const double piv = bcast(a[c], c0 + c);
+            if (!(piv > 0.0)) return false;
+            const double r = rsqrt_nr(piv);
+            const double l = a[c] * r;  // L[i][c0+c] for rows below the pivot, L[c0+c][c0+c] on its lane
+            a[c] = l;
+            if (i == c0 + c) my_inv = r;
+#pragma unroll
+            for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= l * bcast(l, c0 + c2);
         }
-        const double mik = (i < K) ? s.A[i][k] + lam * s.T[i][k] - dot : 0.0;
-        const double piv = bcast(mik, k);
-        if (!(piv > 0.0)) return false;
-        const double lkk = sqrt(piv);
-        const double inv = 1.0 / lkk;
-        if (i > k && i < K) s.L[i][k] = mik * inv;
-        if (i == k) {
-            s.L[k][k] = lkk;
-            s.invd[k] = inv;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (i >= c0 + c && i < KP) s.L[i][c0 + c] = a[c];
+        __syncthreads();
+        // trailing update of the lower blocks (I, J'), J < J' <= I
+        const int lr = i & 15, lk = i >> 4;
+        for (int Jp = J + 1; Jp < nbk; ++Jp) {
+            for (int I = Jp; I < nbk; ++I) {
+                dbl4 acc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = s.L[(I << 4) + lk + 4 * v][(Jp << 4) + lr];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double av = -s.L[(I << 4) + lr][c0 + 4 * q + lk];
+                    const double bv = s.L[(Jp << 4) + lr][c0 + 4 * q + lk];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) s.L[(I << 4) + lk + 4 * v][(Jp << 4) + lr] = acc[v];
+            }
         }
         __syncthreads();
     }
+    *inv = my_inv;
     return true;
 }
 
-// x = M^{-1} b with the factor in s.L; b and x are per-lane registers (row i = lane).
-__device__ double chol_solve(SmallLds& s, int K, double b) {
+// y = L^{-1} b (one entry per lane)
+__device__ double fwd_solve(const SmallLds& s, int K, double inv, double b) {
     const int i = threadIdx.x;
-    double y = b;
-    for (int k = 0; k < K; ++k) {  // L y = b
-        const double yk = bcast(y, k) * s.invd[k];
-        if (i == k) y = yk;
-        if (i > k && i < K) y -= s.L[i][k] * yk;
-    }
-    for (int k = K - 1; k >= 0; --k) {  // L^T x = y
-        const double xk = bcast(y, k) * s.invd[k];
-        if (i == k) y = xk;
-        if (i < k) y -= s.L[k][i] * xk;
+    double y = i < K ? b : 0.0;
+    for (int j = 0; j < K; ++j) {
+        const double lij = s.L[min(i, KMAX_SMALL - 1)][j];
+        const double yj = bcast(y * inv, j);
+        const double upd = fma(-lij, yj, y);
+        y = (i == j) ? yj : ((i > j && i < K) ? upd : y);
     }
     return i < K ? y : 0.0;
 }
 
+// z = L^{-T} y
+__device__ double bwd_solve(const SmallLds& s, int K, double inv, double y) {
+    const int i = threadIdx.x;
+    double z = i < K ? y : 0.0;
+    for (int j = K - 1; j >= 0; --j) {
+        const double lji = s.L[j][min(i, KMAX_SMALL - 1)];
+        const double zj = bcast(z * inv, j);
+        const double upd = fma(-lji, zj, z);
+        z = (i == j) ? zj : (i < j ? upd : z);
+    }
+    return i < K ? z : 0.0;
+}
+
 // (T z)_i for the lane's row, z distributed one entry per lane.
-__device__ double matvec_T(SmallLds& s, int K, double z) {
+__device__ double matvec_T(const SmallLds& s, int K, double z) {
     const int i = threadIdx.x;
     double acc = 0.0;
     for (int j = 0; j < K; ++j) {
+        const double tij = s.T[min(i, KMAX_SMALL - 1)][j];
         const double zj = bcast(z, j);
-        if (i < K) acc += s.T[i][j] * zj;
+        acc += tij * zj;
     }
-    return acc;
+    return i < K ? acc : 0.0;
 }
 
 struct Eval {
@@ -109,16 +168,18 @@ struct Eval {
 __device__ Eval evaluate(SmallLds& s, int K, double lam, double bb, double d, bool deriv, int& nfac) {
     Eval e{false, 0.0, 0.0, 0.0};
     ++nfac;
-    if (!chol(s, K, lam)) return e;
+    double inv;
+    if (!chol(s, K, lam, &inv)) return e;
     e.ok = true;
-    e.z = chol_solve(s, K, d);
+    const double y = fwd_solve(s, K, inv, d);
+    e.z = bwd_solve(s, K, inv, y);
     const double w = matvec_T(s, K, e.z);
-    const double dz = wave_sum64(d * e.z);
+    const double dz = wave_sum64(y * y);  // d^T z = ||L^{-1} d||^2
     const double zw = wave_sum64(e.z * w);
     e.D2 = bb - dz - lam * zw;
     if (deriv) {
-        const double q = chol_solve(s, K, w);
-        e.dD2 = 2.302585092994046 * 2.0 * lam * lam * wave_sum64(w * q);
+        const double q = fwd_solve(s, K, inv, w);  // w^T M^{-1} w = ||L^{-1} w||^2
+        e.dD2 = 2.302585092994046 * 2.0 * lam * lam * wave_sum64(q * q);
     }
     return e;
 }
