@@ -31,19 +31,46 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-# Algorithmic HBM bytes per launch of the kernels that can dominate (FP32 operands):
-# per pixel (or pair-pixel) the bytes the method must read and write once.
-ALGO_BYTES = {
-    # HS sweep: read s (2 x 4 B) and I (3 x 4 B), write s (2 x 4 B) per pair-pixel
-    "hs_sweep": lambda s: 28 * s["pair_px"],
-    # weighted Gram: read K columns of Theta V (4 B each) and nu (4 B) per Theta row
-    "wgram": lambda s: s["rows_theta"] * (4 * s["K_mean"] + 4),
-    # flow adjoint (one direction): read r (4 B) and v (8 B), read/write u (8 B) per pair-pixel
-    "flow_adj": lambda s: 20 * s["pair_px"],
-    # flow forward: read u_t, u_t+1 (8 B), v (8 B), write r (4 B) per pair-pixel
-    "flow_fwd": lambda s: 20 * s["pair_px"],
+# Published MI355X compute peaks (TFLOP/s) of the unit each profiled kernel computes on.
+COMPUTE = {
+    "wgram": ("mfma", 78.6),        # FP64 matrix cores (FP32 operands widened to FP64)
+    "radon_fwd": ("alu", 157.3),    # FP32 vector ALU
+    "radon_adj": ("alu", 157.3),
+    "blur": ("alu", 157.3),
+    "flow_fwd": ("alu", 157.3),
+    "flow_adj": ("alu", 157.3),
+    "grad_fwd": ("alu", 157.3),
+    "grad_adj": ("alu", 157.3),
+    "hs_multi": ("alu", 157.3),
+    "mdot": ("alu", 78.6),          # FP64 vector ALU
 }
+# The committed HBM-traffic summary of a kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) and
+# the source file it was measured on: traffic is reported only while that source is unchanged.
+TRAFFIC = {
+    "wgram": ("profiles/wgram_ellipse128_traffic.md", "paper_2501_12497_amd/csrc/k_krylov.hip"),
+}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    import hashlib
+    if kernel not in TRAFFIC:
+        return None
+    summ, src = (os.path.join(ROOT, x) for x in TRAFFIC[kernel])
+    if not (os.path.exists(summ) and os.path.exists(src)):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(summ):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source sha256") != digest:
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 # FP32+FP64-refined solves: the last outer iterations run with FP64 operators
@@ -136,6 +163,8 @@ def main():
     ap.add_argument("--profile-kernel", default="wgram")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no multi-GPU path.",
@@ -156,6 +185,13 @@ def main():
     def step():
         return B.solve_joint(plan, b, delta, u_true=u_true, **prm)
 
+    if a.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
     for i in range(a.warmup):
         r = step()
         log(f"warmup {i}: iters={r.iters} rre={r.rre[-1]:.5f}")
@@ -167,7 +203,7 @@ def main():
         res.append(step())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    n_launch, k_ms = ctx.kernel_timing()
+    n_launch, k_ms, k_bytes, k_flops = ctx.kernel_timing()
     ctx.profile_kernel(None)
     ms_step = (t1 - t0) * 1e3 / a.steps
     r = res[-1]
@@ -176,19 +212,28 @@ def main():
     log(f"timed {a.steps} solves: {ms_step:.2f} ms/solve, {mv} matvecs/solve, rre={r.rre[-1]:.5f}, "
         f"{a.profile_kernel}: {n_launch} launches {k_ms:.2f} ms")
 
-    # roofline of the profiled kernel
-    P = stack.n_pair_px
-    Ks = list(range(prm["ell"], prm["ell"] + prm["k_max"]))
-    sz = {"pair_px": P, "rows_theta": stack.n_gx + stack.n_gy + 2 * P, "K_mean": float(np.mean(Ks))}
+    # roofline of the profiled kernel: its algorithmic work over its launches in the timed
+    # region (HIP events on the library's stream), against the bound its arithmetic
+    # intensity selects
     roof = None
-    if n_launch and a.profile_kernel in ALGO_BYTES:
-        avg_s = k_ms / n_launch * 1e-3
-        bytes_ = ALGO_BYTES[a.profile_kernel](sz)
-        ach = bytes_ / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": a.profile_kernel, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": int(bytes_), "avg_launch_us": round(avg_s * 1e6, 3),
-                "launches": n_launch}
+    if n_launch and k_ms > 0 and a.profile_kernel in COMPUTE:
+        unit, peak_tf = COMPUTE[a.profile_kernel]
+        sec = k_ms * 1e-3
+        intensity = k_flops / max(k_bytes, 1.0)
+        ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+        traffic = measured_traffic(a.profile_kernel)
+        common = {"kernel": a.profile_kernel, "launches": n_launch, "avg_launch_us": round(k_ms * 1e3 / n_launch, 3),
+                  "bytes_per_launch": round(k_bytes / n_launch), "flops_per_launch": round(k_flops / n_launch),
+                  "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(ridge, 2),
+                  "traffic": traffic}
+        if intensity < ridge:
+            ach = k_bytes / sec / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), **common}
+        else:
+            ach = k_flops / sec / 1e12
+            roof = {"bound": unit, "achieved": round(ach, 2), "peak": peak_tf, "unit": "TFLOP/s",
+                    "frac": round(ach / peak_tf, 4), **common}
 
     # time to solution at a fixed relative error: FP32 operators vs FP64 operators
     tts = None

@@ -231,10 +231,14 @@ int mmof_projected_solve(mmof_ctx ctx, int32_t K, const double* GA, const double
 /* ------------------------------------------------------------------ measurement */
 
 /* Time every launch of the named kernel with HIP events on the context's stream
- * (name NULL or "" switches timing off).  mmof_kernel_timing returns the number of
- * timed launches and their summed duration in milliseconds (synchronizes the stream). */
+ * (name NULL or "" switches timing off; names: radon_fwd, radon_adj, blur, grad_fwd,
+ * grad_adj, flow_fwd, flow_adj, flow_dv, of_derivs, hs_multi, reverse_flow, mdot, wgram,
+ * small_solve).  mmof_kernel_timing returns the number of timed launches, their summed
+ * duration in milliseconds and their summed algorithmic work (bytes that must move, each
+ * input read and each output written once; flops the method needs), and synchronizes the
+ * stream.  Any output pointer may be NULL. */
 int mmof_profile_kernel(mmof_ctx ctx, const char* kernel_name);
-int mmof_kernel_timing(mmof_ctx ctx, int64_t* launches, double* total_ms);
+int mmof_kernel_timing(mmof_ctx ctx, int64_t* launches, double* total_ms, double* alg_bytes, double* alg_flops);
 
 #ifdef __cplusplus
 }

@@ -67,7 +67,8 @@ _SIGS = {
     "mmof_weighted_gram": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_int32]),
     "mmof_projected_solve": (_I, [_P, C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
     "mmof_profile_kernel": (_I, [_P, C.c_char_p]),
-    "mmof_kernel_timing": (_I, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "mmof_kernel_timing": (_I, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]),
 }
 
 _lib = None

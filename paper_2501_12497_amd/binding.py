@@ -94,11 +94,12 @@ class Context:
     def profile_kernel(self, name: Optional[str]):
         check(self.lib.mmof_profile_kernel(self.h, None if not name else name.encode()))
 
-    def kernel_timing(self) -> Tuple[int, float]:
+    def kernel_timing(self) -> Tuple[int, float, float, float]:
+        """(launches, total ms, algorithmic bytes, algorithmic flops) of the profiled kernel."""
         n = C.c_int64()
-        ms = C.c_double()
-        check(self.lib.mmof_kernel_timing(self.h, C.byref(n), C.byref(ms)))
-        return int(n.value), float(ms.value)
+        ms, by, fl = C.c_double(), C.c_double(), C.c_double()
+        check(self.lib.mmof_kernel_timing(self.h, C.byref(n), C.byref(ms), C.byref(by), C.byref(fl)))
+        return int(n.value), float(ms.value), float(by.value), float(fl.value)
 
 
 _CTX = {}

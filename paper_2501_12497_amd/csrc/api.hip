@@ -415,12 +415,13 @@ int mmof_profile_kernel(mmof_ctx ctx, const char* kernel_name) {
         ctx->timer.events.clear();
         ctx->timer.launches = 0;
         ctx->timer.total_ms = 0.0;
+        ctx->timer.bytes = ctx->timer.flops = 0.0;
         ctx->timer.name = kernel_name ? kernel_name : "";
         return MMOF_OK;
     });
 }
 
-int mmof_kernel_timing(mmof_ctx ctx, int64_t* launches, double* total_ms) {
+int mmof_kernel_timing(mmof_ctx ctx, int64_t* launches, double* total_ms, double* alg_bytes, double* alg_flops) {
     return guarded(ctx, [&] {
         need(ctx, "ctx");
         MMOF_HIP(hipStreamSynchronize(ctx->stream));
@@ -435,6 +436,8 @@ int mmof_kernel_timing(mmof_ctx ctx, int64_t* launches, double* total_ms) {
         ctx->timer.events.clear();
         if (launches) *launches = ctx->timer.launches;
         if (total_ms) *total_ms = ctx->timer.total_ms;
+        if (alg_bytes) *alg_bytes = ctx->timer.bytes;
+        if (alg_flops) *alg_flops = ctx->timer.flops;
         return MMOF_OK;
     });
 }

@@ -120,6 +120,7 @@ struct KernelTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     int64_t launches = 0;
     double total_ms = 0.0;
+    double bytes = 0.0, flops = 0.0;  // algorithmic work of the timed launches
 };
 
 struct Ctx {
@@ -156,6 +157,7 @@ struct Plan {
     int64_t n = 0, m = 0;
     // radon
     std::vector<int32_t> n_ang, n_bins;
+    double radon_flops = 0.0;       // 2 hat weights x (multiply + add) per pixel and angle
     std::vector<int64_t> sino_off;  // per frame, offset of its sinogram
     DeviceBuffer d_trig;            // float2/double2 per (frame, angle): cos, sin  (double)
     DeviceBuffer d_rinfo;           // RadonFrame[n_frames]
@@ -174,8 +176,14 @@ struct ScopedTime {
     Ctx* c;
     const char* name;
     hipEvent_t ev = nullptr;
-    ScopedTime(Ctx* c_, const char* n) : c(c_), name(n) {
-        if (c->timing(name)) c->time_begin(name, &ev);
+    // bytes / flops: the launch's algorithmic work (each input read once, each output written
+    // once; the arithmetic the method needs), accumulated while the kernel is being timed
+    ScopedTime(Ctx* c_, const char* n, double bytes = 0.0, double flops = 0.0) : c(c_), name(n) {
+        if (c->timing(name)) {
+            c->time_begin(name, &ev);
+            c->timer.bytes += bytes;
+            c->timer.flops += flops;
+        }
     }
     ~ScopedTime() {
         if (ev) c->time_end(name, ev);

@@ -50,7 +50,7 @@ void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out) {
     const TileList& tl = g.tile_list(c.stream, BTX, BTY, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "blur");
+        ScopedTime st(&c, "blur", 2.0 * sizeof(T) * g.n, 4.0 * p.ksize * g.n);
         hipLaunchKernelGGL(k_blur<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
                            g.dframes(), p.d_k1.as<double>(), p.ksize / 2, (const T*)in, (T*)out);
         MMOF_LAUNCH_CHECK();

@@ -273,7 +273,7 @@ void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const v
     const TileList& tl = g.tile_list(c.stream, FTW, FTH, true);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "flow_fwd");
+        ScopedTime st(&c, "flow_fwd", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
         auto k = interp == MMOF_INTERP_ROUND ? k_flow_fwd<T, 1> : k_flow_fwd<T, 0>;
         hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
                            (const T*)u, (const T*)v, (T*)r, direction);
@@ -291,7 +291,7 @@ void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const v
     const TileList& tl = g.tile_list(c.stream, ATX, ATY, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "flow_adj");
+        ScopedTime st(&c, "flow_adj", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
         auto k = interp == MMOF_INTERP_ROUND ? k_flow_adj<T, 1> : k_flow_adj<T, 0>;
         hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
                            (const T*)r, (const T*)v, (T*)u, direction, accumulate ? 1 : 0, rad);

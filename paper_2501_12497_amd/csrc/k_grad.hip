@@ -69,7 +69,7 @@ void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, con
     const TileList& tl = g.tile_list(c.stream, GTW, GTH, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "grad_fwd");
+        ScopedTime st(&c, "grad_fwd", 3.0 * sizeof(T) * g.n, 2.0 * g.n);
         hipLaunchKernelGGL(k_grad_fwd<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
                            g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx, (T*)gy);
         MMOF_LAUNCH_CHECK();
@@ -81,7 +81,7 @@ void launch_grad_adj(Ctx& c, Geom& g, int dt, const void* gx, const void* gy, co
     const TileList& tl = g.tile_list(c.stream, GTW, GTH, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "grad_adj");
+        ScopedTime st(&c, "grad_adj", 3.0 * sizeof(T) * g.n, 3.0 * g.n);
         hipLaunchKernelGGL(k_grad_adj<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
                            g.dframes(), (const T*)gx, (const T*)gy, (const T*)wx, (const T*)wy, (T*)u,
                            accumulate ? 1 : 0);

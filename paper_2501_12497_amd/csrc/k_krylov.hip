@@ -476,9 +476,12 @@ void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double
     const int nb = mdot_blocks(n);
     MMOF_CHECK(K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for a block inner product");
     double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
-    hipLaunchKernelGGL((k_mdot<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld, y,
-                       (const double*)nullptr, part);
-    MMOF_LAUNCH_CHECK();
+    {
+        ScopedTime st(&c, "mdot", (double)n * ((double)sizeof(TX) * K + sizeof(TY)), 2.0 * n * K);
+        hipLaunchKernelGGL((k_mdot<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld, y,
+                           (const double*)nullptr, part);
+        MMOF_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(KB), 0, c.stream, nb, K, part, alpha, out, (double*)nullptr, 0, 0,
                        (double*)nullptr);
     MMOF_LAUNCH_CHECK();
@@ -601,7 +604,7 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
     double* part =
         static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * GRAM_PAIRS * 256));
     {
-        ScopedTime st(&c, "wgram");
+        ScopedTime st(&c, "wgram", (double)n * ((double)sizeof(TX) * K + 8.0), (double)n * K * (K + 1));
         switch (Gb) {
             case 1: wgram_launch_g<TX, 1>(c, nb, vec, n, K, X, ld, w, part); break;
             case 2: wgram_launch_g<TX, 2>(c, nb, vec, n, K, X, ld, w, part); break;

@@ -206,7 +206,7 @@ int launch_hs_sweeps(Ctx& c, Geom& g, int dt, const void* I, void* v, void* tmp,
         T* b = (T*)tmp;
         while (done < n_sweeps) {
             const int q = std::min(HS_MAX, n_sweeps - done);
-            ScopedTime st(&c, "hs_multi");
+            ScopedTime st(&c, "hs_multi", 7.0 * sizeof(T) * g.pair_px, 16.0 * q * g.pair_px);
             hipLaunchKernelGGL(k_hs_multi<T>, dim3((unsigned)tl.count), dim3(HS_THREADS), 0, c.stream, tl.buf.as<Tile>(),
                                g.dframes(), (const T*)I, (const T*)a, b, (T)gamma, q);
             MMOF_LAUNCH_CHECK();

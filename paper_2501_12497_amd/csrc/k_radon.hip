@@ -155,6 +155,7 @@ void radon_plan_init(Ctx& c, Plan& p) {
             for (int x0 = 0; x0 < fr.nx; x0 += 32) tr.push_back(Tile{(int32_t)fi, y0, x0, 0});
         sino += (int64_t)r.n_ang * r.n_bins;
         trig += r.n_ang;
+        p.radon_flops += 4.0 * (double)fr.ny * fr.nx * r.n_ang;
     }
     p.m = sino;
     p.d_rinfo.ensure(sizeof(RadonFrame) * rfs.size());
@@ -181,7 +182,7 @@ void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
         hipLaunchKernelGGL(k_transpose_frames<T>, dim3((unsigned)p.n_tiles_b), dim3(256), 0, c.stream,
                            p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), (const T*)u, ut);
         MMOF_LAUNCH_CHECK();
-        ScopedTime st(&c, "radon_fwd");
+        ScopedTime st(&c, "radon_fwd", (double)sizeof(T) * (p.n + p.m), p.radon_flops);
         hipLaunchKernelGGL(k_radon_fwd<T>, dim3((unsigned)p.n_rays), dim3(256), 0, c.stream,
                            p.d_rays.as<RayTile>(), p.n_rays, p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(),
                            (const T*)u, (const T*)ut, (T*)b);
@@ -192,7 +193,7 @@ void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
 void launch_radon_adj(Ctx& c, Plan& p, int dt, const void* b, void* u) {
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "radon_adj");
+        ScopedTime st(&c, "radon_adj", (double)sizeof(T) * (p.n + p.m), p.radon_flops);
         hipLaunchKernelGGL(k_radon_adj<T>, dim3((unsigned)p.n_tiles_a), dim3(256), 0, c.stream,
                            p.d_tiles_a.as<Tile>(), p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), (const T*)b,
                            (T*)u);
