@@ -99,10 +99,10 @@ def gpu_data(wl, B, torch):
     return stack, plan, u_true, b, delta
 
 
-def solve_params(wl, op):
+def solve_params(wl, op, graph=True):
     p = wl.params
     return dict(ell=p["ell"], k_max=p["k_max"], tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
-                eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"], op_dtype=op)
+                eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"], op_dtype=op, use_graph=1 if graph else 0)
 
 
 def cpu_baseline(wl, k_iters: int = 3):
@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--profile-kernel", default="wgram")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the fixed launch sequences of each iteration from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
     a = ap.parse_args()
@@ -179,7 +181,7 @@ def main():
     wl = make_workload()
     stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
     ctx = plan.ctx
-    prm = solve_params(wl, "f32")
+    prm = solve_params(wl, "f32", graph=a.graph)
     log(f"workload {wl.name}: n={plan.n} m={plan.m} params={prm}")
 
     def step():
@@ -238,11 +240,11 @@ def main():
     # time to solution at a fixed relative error: FP32 operators vs FP64 operators
     tts = None
     if not a.no_tts:
-        ref = B.solve_joint(plan, b, delta, u_true=u_true, **solve_params(wl, "f64"))
+        ref = B.solve_joint(plan, b, delta, u_true=u_true, **solve_params(wl, "f64", graph=a.graph))
         target = ref.rre[-1] * 1.001
         tts = {"rre_target": target, "k_max": prm["k_max"] + 15}
         for op in ("f64", "f32", "f32+refine"):
-            kw = solve_params(wl, op.split("+")[0])
+            kw = solve_params(wl, op.split("+")[0], graph=a.graph)
             kw["k_max"] = prm["k_max"] + 15
             kw["rre_target"] = target
             if op.endswith("refine"):

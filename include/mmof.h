@@ -99,6 +99,19 @@ int mmof_plan_destroy(mmof_plan plan);
 /* n = number of pixels, m = number of data entries of the plan's stack. */
 int mmof_plan_sizes(mmof_plan plan, int64_t* n, int64_t* m);
 
+/* Tile-shape autotuner of the plan's stencil kernels (blur for blur plans, Psi, Psi^T,
+ * L(v), L(v)^T): every candidate shape is timed on the plan's stack in dtype dt (HIP
+ * events on the context's stream) and the fastest is used by later launches of the plan
+ * (apply_A/At, solve_joint) in that dtype.  All candidates compute identical values.
+ * report: host buffer of report_len bytes (or NULL) that receives a NUL-terminated line
+ * "kernel=TWxTH(mean us) ..." (a trailing "p" marks a persistent launch).  Allocates
+ * scratch in the context; synchronizes the stream. */
+int mmof_autotune(mmof_plan plan, mmof_dtype dt, char* report, int32_t report_len);
+/* Forces tile candidate `choice` (0-based, in the order the autotuner tries them) of a
+ * tunable kernel ("blur", "grad_fwd", "grad_adj", "flow_fwd", "flow_adj") for the plan
+ * in dtype dt.  MMOF_ERR_INVALID for an unknown kernel or an out-of-range choice. */
+int mmof_set_tile(mmof_plan plan, const char* kernel, mmof_dtype dt, int32_t choice);
+
 /* b <- H u  (u: n entries, b: m entries, both of dtype dt). */
 int mmof_apply_A(mmof_plan plan, mmof_dtype dt, const void* u, void* b);
 /* u <- H^T b (overwrites u). */
@@ -181,6 +194,9 @@ typedef struct {
     double fixed_lambda;  /* > 0: use this lambda instead of the discrepancy principle    */
     double rre_target;    /* > 0 with u_true: stop at the first RRE <= rre_target         */
     const double* u_true; /* device, n doubles, or NULL                                   */
+    int32_t use_graph;    /* 1: replay the fixed launch sequences of an iteration (the flow  */
+                          /* update and the residual's operator applications) from HIP      */
+                          /* graphs captured on their second use and kept in the context    */
 } mmof_solve_params;
 
 typedef struct {

@@ -28,7 +28,7 @@ class mmof_solve_params(C.Structure):
                 ("delta_r", C.c_int32), ("use_flow", C.c_int32), ("use_reverse", C.c_int32),
                 ("interp", C.c_int32), ("op_dtype", C.c_int32), ("refine_iters", C.c_int32),
                 ("eps", C.c_double), ("eta", C.c_double), ("alpha", C.c_double), ("fixed_lambda", C.c_double),
-                ("rre_target", C.c_double), ("u_true", C.c_void_p)]
+                ("rre_target", C.c_double), ("u_true", C.c_void_p), ("use_graph", C.c_int32)]
 
 
 class mmof_report(C.Structure):
@@ -67,6 +67,8 @@ _SIGS = {
     "mmof_weighted_gram": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_int32]),
     "mmof_projected_solve": (_I, [_P, C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
     "mmof_profile_kernel": (_I, [_P, C.c_char_p]),
+    "mmof_autotune": (_I, [_P, C.c_int32, C.c_char_p, C.c_int32]),
+    "mmof_set_tile": (_I, [_P, C.c_char_p, C.c_int32, C.c_int32]),
     "mmof_kernel_timing": (_I, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double)]),
 }

@@ -48,6 +48,14 @@ def _dt(*ts: torch.Tensor) -> int:
     return _DT[next(iter(dts))]
 
 
+def _dtcode(dtype) -> int:
+    if isinstance(dtype, str):
+        dtype = {"f32": torch.float32, "f64": torch.float64}[dtype]
+    if dtype not in _DT:
+        raise TypeError(f"dtype must be float32 or float64 (got {dtype})")
+    return _DT[dtype]
+
+
 def _need(t: torch.Tensor, numel: int, name: str):
     if t is None:
         raise ValueError(f"{name} is required")
@@ -169,6 +177,17 @@ class Plan:
         check(ctx.lib.mmof_plan_sizes(h, C.byref(n), C.byref(m)))
         self.n, self.m = int(n.value), int(m.value)
         _LIVE_PLANS.add(self)
+
+    def autotune(self, dtype=torch.float32) -> str:
+        """Times the tile-shape candidates of this plan's stencil kernels; returns the report."""
+        buf = C.create_string_buffer(1024)
+        self.ctx.bind()
+        check(self.ctx.lib.mmof_autotune(self.h, _dtcode(dtype), buf, 1024))
+        return buf.value.decode()
+
+    def set_tile(self, kernel: str, choice: int, dtype=torch.float32):
+        """Forces tile candidate `choice` of a tunable kernel for this plan."""
+        check(self.ctx.lib.mmof_set_tile(self.h, kernel.encode(), _dtcode(dtype), int(choice)))
 
     def close(self):
         if self.h and not _SHUTDOWN[0]:

@@ -1,9 +1,11 @@
 // extern "C" entry points: argument checks, error translation, dispatch to launchers.
 #include <cmath>
+#include <cstring>
 
 #include "kernels.h"
 #include "krylov.h"
 #include "solver.h"
+#include "tune.h"
 
 namespace mmof {
 const char* last_error_cstr();
@@ -22,6 +24,7 @@ static int guarded(Ctx* c, F&& f) {
     } catch (const Error& e) {
         set_last_error(e.what());
         if (c) c->last_error = e.what();
+        if (e.code == MMOF_ERR_HIP) (void)hipGetLastError();  // do not leave it for the next call
         return e.code;
     } catch (const std::exception& e) {
         set_last_error(e.what());
@@ -166,6 +169,30 @@ int mmof_plan_sizes(mmof_plan plan, int64_t* n, int64_t* m) {
         need(plan, "plan");
         if (n) *n = plan->n;
         if (m) *m = plan->m;
+        return MMOF_OK;
+    });
+}
+
+int mmof_autotune(mmof_plan plan, mmof_dtype dt, char* report, int32_t report_len) {
+    return guarded(plan ? plan->ctx : nullptr, [&] {
+        need(plan, "plan");
+        need_dt(dt);
+        const std::string rep = autotune(*plan, dt);
+        if (report && report_len > 0) {
+            const size_t k = std::min<size_t>(rep.size(), (size_t)report_len - 1);
+            std::memcpy(report, rep.data(), k);
+            report[k] = 0;
+        }
+        return MMOF_OK;
+    });
+}
+
+int mmof_set_tile(mmof_plan plan, const char* kernel, mmof_dtype dt, int32_t choice) {
+    return guarded(plan ? plan->ctx : nullptr, [&] {
+        need(plan, "plan");
+        need(kernel, "kernel");
+        need_dt(dt);
+        set_tile(*plan, kernel, dt, choice);
         return MMOF_OK;
     });
 }
@@ -338,6 +365,7 @@ void mmof_solve_defaults(mmof_solve_params* p) {
     p->fixed_lambda = 0.0;
     p->rre_target = 0.0;
     p->u_true = nullptr;
+    p->use_graph = 0;
 }
 
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p, void* u_inout,

@@ -94,6 +94,12 @@ struct TileList {
     int64_t count = 0;
 };
 
+// Output tile of a stencil kernel: tw x th pixels per workgroup; persistent: the grid is a
+// few workgroups per CU that loop over the tile list.
+struct TileShape {
+    int tw, th, persistent;
+};
+
 struct Geom {
     std::vector<int32_t> n_t, ny, nx;
     int32_t n_seq = 0;
@@ -107,6 +113,12 @@ struct Geom {
     std::vector<int64_t> seq_off;        // pixel offset per sequence
     DeviceBuffer d_frames;               // FrameInfo[n_frames]
     std::map<uint64_t, std::unique_ptr<TileList>> tiles;  // (tw, th, pairs) -> list
+    // Tile-shape candidate chosen by the autotuner per "kernel/dtype" (absent: candidate 0).
+    std::map<std::string, int> tuned;
+    int choice(const char* kernel, int dt) const {
+        auto it = tuned.find(std::string(kernel) + (dt == MMOF_F32 ? "/f32" : "/f64"));
+        return it == tuned.end() ? 0 : it->second;
+    }
 
     bool same_as(const mmof_stack& s) const;
     const TileList& tile_list(hipStream_t st, int tw, int th, bool pairs);
@@ -123,6 +135,13 @@ struct KernelTimer {
     double bytes = 0.0, flops = 0.0;  // algorithmic work of the timed launches
 };
 
+// An instantiated HIP graph of a launch sequence and the operator-application counts one
+// replay adds to a solve report.
+struct CachedGraph {
+    hipGraphExec_t exec = nullptr;
+    int64_t dA = 0, dAt = 0, dTheta = 0, dThetaT = 0, dL = 0;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -131,6 +150,13 @@ struct Ctx {
     std::map<std::string, std::unique_ptr<DeviceBuffer>> ws;  // named workspaces
     KernelTimer timer;
     int cu_count = 256;
+    // launch sequences captured as graphs, keyed by everything their launches depend on
+    std::map<std::string, CachedGraph> graphs;
+    std::map<std::string, int> graph_seen;
+    // private stream the sequences are captured on (capture is not possible on the legacy
+    // default stream); the graphs are launched on `stream`
+    hipStream_t capture_stream = nullptr;
+    bool capturing = false;  // launches are being recorded into a graph (no event timing)
     void* pinned_buf = nullptr;
     size_t pinned_bytes = 0;
     ~Ctx();
@@ -144,7 +170,7 @@ struct Ctx {
         return p->ensure(bytes);
     }
     // Event-timing hooks around launches of a named kernel.
-    bool timing(const char* kname) const { return !timer.name.empty() && timer.name == kname; }
+    bool timing(const char* kname) const { return !capturing && !timer.name.empty() && timer.name == kname; }
     void time_begin(const char* kname, hipEvent_t* ev);
     void time_end(const char* kname, hipEvent_t ev);
 };

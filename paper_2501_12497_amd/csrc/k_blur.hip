@@ -1,57 +1,76 @@
 // Per-frame Gaussian blur with zero boundary, K = k1 k1^T (k1 normalised to unit sum, so
 // sum K = 1).  Because K(i,j) = K(-i,-j) the transpose applies the same sum, so one
 // kernel serves H and H^T.  Separable: a horizontal then a vertical pass over an LDS
-// tile of 64x16 outputs plus a halo of ksize/2 on every side.
+// tile of outputs plus a halo of ksize/2 on every side (tile shape chosen per geometry).
 #include "dev.h"
 #include "kernels.h"
 
 namespace mmof {
 
-static constexpr int BTX = 64, BTY = 16, BRMAX = 7;
+static constexpr int BRMAX = 7;
 
-template <class T>
-__global__ __launch_bounds__(256) void k_blur(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
-                                              const double* __restrict__ k1d, int r, const T* __restrict__ in,
-                                              T* __restrict__ out) {
-    __shared__ T s_in[BTY + 2 * BRMAX][BTX + 2 * BRMAX];
-    __shared__ T s_h[BTY + 2 * BRMAX][BTX];
+// TW x TH output tile per workgroup of 256 threads.  PERS: a grid of a few workgroups per
+// CU loops over the tile list (persistent launch); otherwise one workgroup per tile.
+template <class T, int TW, int TH, bool PERS>
+__global__ __launch_bounds__(256) void k_blur(const Tile* __restrict__ tiles, int64_t n_tiles,
+                                              const FrameInfo* __restrict__ fr, const double* __restrict__ k1d,
+                                              int r, const T* __restrict__ in, T* __restrict__ out) {
+    __shared__ T s_in[TH + 2 * BRMAX][TW + 2 * BRMAX];
+    __shared__ T s_h[TH + 2 * BRMAX][TW];
     __shared__ T s_k[2 * BRMAX + 1];
-    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
-    const FrameInfo f = fr[tl.frame];
-    const int nx = f.nx, ny = f.ny;
-    const T* src = in + f.off;
     if (threadIdx.x < 2 * r + 1) s_k[threadIdx.x] = (T)k1d[threadIdx.x];
-    const int hw = BTX + 2 * r, hh = BTY + 2 * r;
-    for (int i = threadIdx.x; i < hw * hh; i += 256) {
-        const int ly = i / hw, lx = i % hw;
-        const int y = tl.y0 - r + ly, x = tl.x0 - r + lx;
-        s_in[ly][lx] = (y >= 0 && y < ny && x >= 0 && x < nx) ? src[(int64_t)y * nx + x] : T(0);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < BTX * hh; i += 256) {
-        const int ly = i / BTX, lx = i % BTX;
-        T acc = T(0);
-        for (int j = 0; j <= 2 * r; ++j) acc += s_k[j] * s_in[ly][lx + j];
-        s_h[ly][lx] = acc;
-    }
-    __syncthreads();
-    const int lx = threadIdx.x % BTX;
-    for (int ly = threadIdx.x / BTX; ly < BTY; ly += 256 / BTX) {
-        const int y = tl.y0 + ly, x = tl.x0 + lx;
-        if (y >= ny || x >= nx) continue;
-        T acc = T(0);
-        for (int i = 0; i <= 2 * r; ++i) acc += s_k[i] * s_h[ly + i][lx];
-        out[f.off + (int64_t)y * nx + x] = acc;
+    const int64_t step = PERS ? gridDim.x : n_tiles;
+    for (int64_t ti = PERS ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x); ti < n_tiles; ti += step) {
+        const Tile tl = tiles[ti];
+        const FrameInfo f = fr[tl.frame];
+        const int nx = f.nx, ny = f.ny;
+        const T* src = in + f.off;
+        const int hw = TW + 2 * r, hh = TH + 2 * r;
+        __syncthreads();  // LDS of the previous tile is free
+        for (int i = threadIdx.x; i < hw * hh; i += 256) {
+            const int ly = i / hw, lx = i % hw;
+            const int y = tl.y0 - r + ly, x = tl.x0 - r + lx;
+            s_in[ly][lx] = (y >= 0 && y < ny && x >= 0 && x < nx) ? src[(int64_t)y * nx + x] : T(0);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < TW * hh; i += 256) {
+            const int ly = i / TW, lx = i % TW;
+            T acc = T(0);
+            for (int j = 0; j <= 2 * r; ++j) acc += s_k[j] * s_in[ly][lx + j];
+            s_h[ly][lx] = acc;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < TW * TH; i += 256) {
+            const int ly = i / TW, lx = i % TW;
+            const int y = tl.y0 + ly, x = tl.x0 + lx;
+            if (y >= ny || x >= nx) continue;
+            T acc = T(0);
+            for (int k = 0; k <= 2 * r; ++k) acc += s_k[k] * s_h[ly + k][lx];
+            out[f.off + (int64_t)y * nx + x] = acc;
+        }
     }
 }
 
-void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out) {
+const TileShape kBlurShapes[] = {{64, 16, 0}, {32, 32, 0}, {128, 8, 0}, {32, 16, 0}, {64, 16, 1}};
+const int kBlurCandidates = sizeof(kBlurShapes) / sizeof(kBlurShapes[0]);
+
+void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out, int choice) {
     Geom& g = *p.geom;
-    const TileList& tl = g.tile_list(c.stream, BTX, BTY, false);
+    if (choice < 0) choice = g.choice("blur", dt);
+    MMOF_CHECK(choice >= 0 && choice < kBlurCandidates, MMOF_ERR_INVALID, "blur tile candidate out of range");
+    const TileShape sh = kBlurShapes[choice];
+    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
+    if (tl.count == 0) return;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "blur", 2.0 * sizeof(T) * g.n, 4.0 * p.ksize * g.n);
-        hipLaunchKernelGGL(k_blur<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+        auto k = choice == 0 ? k_blur<T, 64, 16, false>
+                 : choice == 1 ? k_blur<T, 32, 32, false>
+                 : choice == 2 ? k_blur<T, 128, 8, false>
+                 : choice == 3 ? k_blur<T, 32, 16, false>
+                               : k_blur<T, 64, 16, true>;
+        const int64_t grid = sh.persistent ? std::min<int64_t>(tl.count, (int64_t)c.cu_count * 4) : tl.count;
+        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, c.stream, tl.buf.as<Tile>(), tl.count,
                            g.dframes(), p.d_k1.as<double>(), p.ksize / 2, (const T*)in, (T*)out);
         MMOF_LAUNCH_CHECK();
     });

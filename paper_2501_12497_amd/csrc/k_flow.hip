@@ -8,23 +8,23 @@
 // range of their integer displacements, so a pixel only visits the (dmax-dmin+2)^2
 // sources that can reach it.
 #include <climits>
+#include <type_traits>
 
 #include "dev.h"
 #include "kernels.h"
 
 namespace mmof {
 
-static constexpr int FTW = 64, FTH = 4;          // forward / dv tiles
-static constexpr int ATX = 32, ATY = 8;          // adjoint tiles
-static constexpr int RMAX = 8;                   // LDS path handles radius <= RMAX
-static constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);
+static constexpr int FTW = 64, FTH = 4;          // dv tiles
+static constexpr int RMAX = 8;                   // LDS path of the adjoint handles radius <= RMAX
 
-// Bilinear (INTERP 0) or nearest (INTERP 1) sample of src at (x + vx, y + vy).
-template <class T, int INTERP>
-__device__ __forceinline__ T warp_sample(const T* __restrict__ src, int nx, int ny, int x, int y, T vx, T vy) {
+// Bilinear (INTERP 0) or nearest (INTERP 1) sample of src at (x + vx, y + vy), computed in T
+// (source values of type S are rounded to T first).
+template <class T, int INTERP, class S = T>
+__device__ __forceinline__ T warp_sample(const S* __restrict__ src, int nx, int ny, int x, int y, T vx, T vy) {
     if (INTERP == 1) {
         const int xr = round_clip(x, vx, nx), yr = round_clip(y, vy, ny);
-        return src[(int64_t)yr * nx + xr];
+        return (T)src[(int64_t)yr * nx + xr];
     }
     int x0, y0;
     T fx, fy;
@@ -32,13 +32,13 @@ __device__ __forceinline__ T warp_sample(const T* __restrict__ src, int nx, int 
     clip_cell(x, vx, nx, x0, fx, cx);
     clip_cell(y, vy, ny, y0, fy, cy);
     const int x1 = min(x0 + 1, nx - 1), y1 = min(y0 + 1, ny - 1);
-    const T* r0 = src + (int64_t)y0 * nx;
-    const T* r1 = src + (int64_t)y1 * nx;
-    return (T(1) - fx) * (T(1) - fy) * r0[x0] + fx * (T(1) - fy) * r0[x1] + (T(1) - fx) * fy * r1[x0] +
-           fx * fy * r1[x1];
+    const S* r0 = src + (int64_t)y0 * nx;
+    const S* r1 = src + (int64_t)y1 * nx;
+    return (T(1) - fx) * (T(1) - fy) * (T)r0[x0] + fx * (T(1) - fy) * (T)r0[x1] + (T(1) - fx) * fy * (T)r1[x0] +
+           fx * fy * (T)r1[x1];
 }
 
-template <class T, int INTERP>
+template <class T, int INTERP, int FTW, int FTH>
 __global__ __launch_bounds__(256) void k_flow_fwd(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ u, const T* __restrict__ v,
                                                   T* __restrict__ r, int direction) {
@@ -56,6 +56,35 @@ __global__ __launch_bounds__(256) void k_flow_fwd(const Tile* __restrict__ tiles
     const T* src = direction > 0 ? ut1 : ut;
     const T* sub = direction > 0 ? ut : ut1;
     r[f.pair_off + p] = warp_sample<T, INTERP>(src, f.nx, f.ny, x, y, vxx, vyy) - sub[p];
+}
+
+// Forward and (when vr is not null) reverse flow rows of Theta for K columns at once:
+// column j of U (FP64, leading dimension ldu) is rounded to T and mapped to
+// out[j*ldo + oF + pair pixel] (forward) and out[j*ldo + oR + pair pixel] (reverse).  The
+// values equal those of k_flow_fwd applied to the rounded column.
+template <class T, int INTERP, int FTW, int FTH>
+__global__ __launch_bounds__(256) void k_flow_fwd_cols(const Tile* __restrict__ tiles,
+                                                       const FrameInfo* __restrict__ fr,
+                                                       const double* __restrict__ U, int64_t ldu,
+                                                       const T* __restrict__ v, const T* __restrict__ vr,
+                                                       T* __restrict__ out, int64_t ldo, int64_t oF, int64_t oR) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + (int)(threadIdx.x % FTW);
+    const int y = tl.y0 + (int)(threadIdx.x / FTW);
+    if (x >= f.nx || y >= f.ny) return;
+    const int64_t np = (int64_t)f.nx * f.ny;
+    const int64_t p = (int64_t)y * f.nx + x;
+    const double* ut = U + (int64_t)blockIdx.y * ldu + f.off;
+    const double* ut1 = ut + np;
+    T* o = out + (int64_t)blockIdx.y * ldo;
+    const T* vf = v + 2 * f.pair_off;
+    o[oF + f.pair_off + p] = warp_sample<T, INTERP, double>(ut1, f.nx, f.ny, x, y, vf[p], vf[np + p]) - (T)ut[p];
+    if (vr) {
+        const T* vb = vr + 2 * f.pair_off;
+        o[oR + f.pair_off + p] =
+            warp_sample<T, INTERP, double>(ut, f.nx, f.ny, x, y, vb[p], vb[np + p]) - (T)ut1[p];
+    }
 }
 
 // Cell of a source pixel: clipped floor coordinates and fractions (0 for INTERP 1).
@@ -87,11 +116,12 @@ __device__ __forceinline__ bool corner_weight(int c0, T f, int q, T& w) {
     return false;
 }
 
-template <class T, int INTERP>
+template <class T, int INTERP, int ATX, int ATY>
 __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ r, const T* __restrict__ v,
                                                   T* __restrict__ u, int direction, int accumulate,
                                                   const int32_t* __restrict__ d_radius) {
+    constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);
     __shared__ int s_x0[SMAX], s_y0[SMAX];
     __shared__ T s_fx[SMAX], s_fy[SMAX], s_val[SMAX];
     __shared__ int s_d[4];  // dmin_x, dmax_x, dmin_y, dmax_y
@@ -268,31 +298,82 @@ void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out) 
     });
 }
 
-void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r) {
+const TileShape kFlowShapes[] = {{64, 4, 0}, {32, 8, 0}, {128, 2, 0}, {16, 16, 0}};
+const int kFlowCandidates = sizeof(kFlowShapes) / sizeof(kFlowShapes[0]);
+const TileShape kFlowAdjShapes[] = {{32, 8, 0}, {64, 4, 0}, {16, 16, 0}};
+const int kFlowAdjCandidates = sizeof(kFlowAdjShapes) / sizeof(kFlowAdjShapes[0]);
+
+template <class T, int INTERP>
+static auto flow_fwd_kernel(int choice) {
+    return choice == 0 ? k_flow_fwd<T, INTERP, 64, 4>
+           : choice == 1 ? k_flow_fwd<T, INTERP, 32, 8>
+           : choice == 2 ? k_flow_fwd<T, INTERP, 128, 2>
+                         : k_flow_fwd<T, INTERP, 16, 16>;
+}
+template <class T, int INTERP>
+static auto flow_adj_kernel(int choice) {
+    return choice == 0 ? k_flow_adj<T, INTERP, 32, 8>
+           : choice == 1 ? k_flow_adj<T, INTERP, 64, 4>
+                         : k_flow_adj<T, INTERP, 16, 16>;
+}
+
+void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r,
+                     int choice) {
     if (g.n_pairs == 0) return;
-    const TileList& tl = g.tile_list(c.stream, FTW, FTH, true);
+    if (choice < 0) choice = g.choice("flow_fwd", dt);
+    MMOF_CHECK(choice >= 0 && choice < kFlowCandidates, MMOF_ERR_INVALID, "flow tile candidate out of range");
+    const TileShape sh = kFlowShapes[choice];
+    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_fwd", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
-        auto k = interp == MMOF_INTERP_ROUND ? k_flow_fwd<T, 1> : k_flow_fwd<T, 0>;
+        auto k = interp == MMOF_INTERP_ROUND ? flow_fwd_kernel<T, 1>(choice) : flow_fwd_kernel<T, 0>(choice);
         hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
                            (const T*)u, (const T*)v, (T*)r, direction);
         MMOF_LAUNCH_CHECK();
     });
 }
 
+void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const double* U, int64_t ldu, int K, const void* v,
+                          const void* vr, void* out, int64_t ldo, int64_t oF, int64_t oR) {
+    if (g.n_pairs == 0 || K <= 0) return;
+    const int choice = g.choice("flow_fwd", dt);
+    const TileShape sh = kFlowShapes[choice];
+    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        ScopedTime st(&c, "flow_fwd_cols", (vr ? 2.0 : 1.0) * K * (4.0 * sizeof(T) + 16.0) * g.pair_px,
+                      (vr ? 2.0 : 1.0) * K * 12.0 * g.pair_px);
+        auto pick = [&](auto interp_tag) {
+            constexpr int I = decltype(interp_tag)::value;
+            return choice == 0 ? k_flow_fwd_cols<T, I, 64, 4>
+                   : choice == 1 ? k_flow_fwd_cols<T, I, 32, 8>
+                   : choice == 2 ? k_flow_fwd_cols<T, I, 128, 2>
+                                 : k_flow_fwd_cols<T, I, 16, 16>;
+        };
+        auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
+                                             : pick(std::integral_constant<int, 0>{});
+        hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                           g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo, oF, oR);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
 void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const void* r, const void* v, void* u,
-                     bool accumulate, const int32_t* d_radius) {
+                     bool accumulate, const int32_t* d_radius, int choice) {
     int32_t* rad = const_cast<int32_t*>(d_radius);
     if (!rad) {
         rad = static_cast<int32_t*>(c.work("flow_radius", 256));
         launch_flow_radius(c, g, dt, v, rad);
     }
-    const TileList& tl = g.tile_list(c.stream, ATX, ATY, false);
+    if (choice < 0) choice = g.choice("flow_adj", dt);
+    MMOF_CHECK(choice >= 0 && choice < kFlowAdjCandidates, MMOF_ERR_INVALID, "flow adjoint tile candidate out of range");
+    const TileShape sh = kFlowAdjShapes[choice];
+    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_adj", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
-        auto k = interp == MMOF_INTERP_ROUND ? k_flow_adj<T, 1> : k_flow_adj<T, 0>;
+        auto k = interp == MMOF_INTERP_ROUND ? flow_adj_kernel<T, 1>(choice) : flow_adj_kernel<T, 0>(choice);
         hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
                            (const T*)r, (const T*)v, (T*)u, direction, accumulate ? 1 : 0, rad);
         MMOF_LAUNCH_CHECK();

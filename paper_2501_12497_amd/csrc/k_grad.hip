@@ -1,14 +1,12 @@
 // Psi = blockdiag(L), L = [I (x) L_x ; L_y (x) I] (first differences, no boundary rows),
 // optionally weighted row by row, and its transpose.  One pixel per thread over
-// 64x4 tiles of every frame in the packed stack.
+// TW x TH tiles (TW * TH = 256) of every frame in the packed stack.
 #include "dev.h"
 #include "kernels.h"
 
 namespace mmof {
 
-static constexpr int GTW = 64, GTH = 4;
-
-template <class T>
+template <class T, int GTW, int GTH>
 __global__ __launch_bounds__(256) void k_grad_fwd(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ u, const T* __restrict__ wx,
                                                   const T* __restrict__ wy, T* __restrict__ gx, T* __restrict__ gy) {
@@ -32,7 +30,7 @@ __global__ __launch_bounds__(256) void k_grad_fwd(const Tile* __restrict__ tiles
     }
 }
 
-template <class T>
+template <class T, int GTW, int GTH>
 __global__ __launch_bounds__(256) void k_grad_adj(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ gx, const T* __restrict__ gy,
                                                   const T* __restrict__ wx, const T* __restrict__ wy,
@@ -65,26 +63,51 @@ __global__ __launch_bounds__(256) void k_grad_adj(const Tile* __restrict__ tiles
     u[p] = accumulate ? u[p] + acc : acc;
 }
 
-void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy) {
-    const TileList& tl = g.tile_list(c.stream, GTW, GTH, false);
+const TileShape kGradShapes[] = {{64, 4, 0}, {32, 8, 0}, {128, 2, 0}, {16, 16, 0}};
+const int kGradCandidates = sizeof(kGradShapes) / sizeof(kGradShapes[0]);
+
+template <class T>
+static auto grad_fwd_kernel(int choice) {
+    return choice == 0 ? k_grad_fwd<T, 64, 4>
+           : choice == 1 ? k_grad_fwd<T, 32, 8>
+           : choice == 2 ? k_grad_fwd<T, 128, 2>
+                         : k_grad_fwd<T, 16, 16>;
+}
+template <class T>
+static auto grad_adj_kernel(int choice) {
+    return choice == 0 ? k_grad_adj<T, 64, 4>
+           : choice == 1 ? k_grad_adj<T, 32, 8>
+           : choice == 2 ? k_grad_adj<T, 128, 2>
+                         : k_grad_adj<T, 16, 16>;
+}
+
+void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy,
+                     int choice) {
+    if (choice < 0) choice = g.choice("grad_fwd", dt);
+    MMOF_CHECK(choice >= 0 && choice < kGradCandidates, MMOF_ERR_INVALID, "grad tile candidate out of range");
+    const TileShape sh = kGradShapes[choice];
+    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "grad_fwd", 3.0 * sizeof(T) * g.n, 2.0 * g.n);
-        hipLaunchKernelGGL(k_grad_fwd<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx, (T*)gy);
+        hipLaunchKernelGGL(grad_fwd_kernel<T>(choice), dim3((unsigned)tl.count), dim3(256), 0, c.stream,
+                           tl.buf.as<Tile>(), g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx, (T*)gy);
         MMOF_LAUNCH_CHECK();
     });
 }
 
 void launch_grad_adj(Ctx& c, Geom& g, int dt, const void* gx, const void* gy, const void* wx, const void* wy,
-                     void* u, bool accumulate) {
-    const TileList& tl = g.tile_list(c.stream, GTW, GTH, false);
+                     void* u, bool accumulate, int choice) {
+    if (choice < 0) choice = g.choice("grad_adj", dt);
+    MMOF_CHECK(choice >= 0 && choice < kGradCandidates, MMOF_ERR_INVALID, "grad tile candidate out of range");
+    const TileShape sh = kGradShapes[choice];
+    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "grad_adj", 3.0 * sizeof(T) * g.n, 3.0 * g.n);
-        hipLaunchKernelGGL(k_grad_adj<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), (const T*)gx, (const T*)gy, (const T*)wx, (const T*)wy, (T*)u,
-                           accumulate ? 1 : 0);
+        hipLaunchKernelGGL(grad_adj_kernel<T>(choice), dim3((unsigned)tl.count), dim3(256), 0, c.stream,
+                           tl.buf.as<Tile>(), g.dframes(), (const T*)gx, (const T*)gy, (const T*)wx, (const T*)wy,
+                           (T*)u, accumulate ? 1 : 0);
         MMOF_LAUNCH_CHECK();
     });
 }

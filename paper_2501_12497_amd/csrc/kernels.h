@@ -5,15 +5,27 @@
 
 namespace mmof {
 
+// Tunable stencil kernels take a tile-shape candidate index; -1 uses the geometry's tuned
+// choice (candidate 0 until the autotuner has run).
+extern const TileShape kBlurShapes[], kGradShapes[], kFlowShapes[], kFlowAdjShapes[];
+extern const int kBlurCandidates, kGradCandidates, kFlowCandidates, kFlowAdjCandidates;
+
 // Psi and Psi^T (eq. L); weights optional.
-void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy);
+void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy,
+                     int choice = -1);
 void launch_grad_adj(Ctx& c, Geom& g, int dt, const void* gx, const void* gy, const void* wx, const void* wy,
-                     void* u, bool accumulate);
+                     void* u, bool accumulate, int choice = -1);
 
 // L(v) = -M-bar (direction +1) / -M-bar' (direction -1) and relatives.
-void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r);
+void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r,
+                     int choice = -1);
 void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const void* r, const void* v, void* u,
-                     bool accumulate, const int32_t* d_radius /* device int: floor(max|v|)+1, or null */);
+                     bool accumulate, const int32_t* d_radius /* device int: floor(max|v|)+1, or null */,
+                     int choice = -1);
+// Forward (v) and, when vr is not null, reverse (vr) flow rows of Theta for K FP64 columns U
+// (leading dimension ldu) in one launch: out[j*ldo + oF ...] and out[j*ldo + oR ...], dtype dt.
+void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const double* U, int64_t ldu, int K, const void* v,
+                          const void* vr, void* out, int64_t ldo, int64_t oF, int64_t oR);
 void launch_flow_dv(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v,
                     const void* w, void* gv);
 // Device int *d_out = floor(max |v|) + 1 over all pairs (saturating at 1<<20, NaN -> saturate).
@@ -32,6 +44,6 @@ void launch_mm_weights(Ctx& c, int dt, int64_t n, const void* nu, double eps, vo
 // Forward operators.
 void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b);
 void launch_radon_adj(Ctx& c, Plan& p, int dt, const void* b, void* u);
-void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out);
+void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out, int choice = -1);
 
 }  // namespace mmof

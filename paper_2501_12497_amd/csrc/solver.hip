@@ -161,6 +161,80 @@ struct Solver {
         if (rep) rep->n_thetaT++;
     }
 
+    // ---------------------------------------------------------------- graphs
+    // Runs body, a launch sequence whose launches depend only on `key`: eagerly on its first
+    // use (which also creates its tile lists and workspaces), captured into a graph and
+    // launched on its second, replayed from the context's cache afterwards.  The report
+    // counters the body increments are added again on every replay; kernels inside a graph
+    // are not event-timed.
+    template <class F>
+    void replayable(const std::string& key, F&& body) {
+        if (!p.use_graph) {
+            body();
+            return;
+        }
+        auto it = c.graphs.find(key);
+        if (it != c.graphs.end()) {
+            MMOF_HIP(hipGraphLaunch(it->second.exec, c.stream));
+            if (rep) {
+                rep->n_A += it->second.dA;
+                rep->n_At += it->second.dAt;
+                rep->n_theta += it->second.dTheta;
+                rep->n_thetaT += it->second.dThetaT;
+                rep->n_L += it->second.dL;
+            }
+            return;
+        }
+        if (c.graph_seen[key]++ == 0) {
+            body();
+            return;
+        }
+        mmof_report before{};
+        if (rep) before = *rep;
+        if (!c.capture_stream) MMOF_HIP(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+        // the launchers use c.stream: point it at the capture stream while the body records
+        hipGraph_t gr = nullptr;
+        const hipStream_t launch_stream = c.stream;
+        MMOF_HIP(hipStreamBeginCapture(c.capture_stream, hipStreamCaptureModeThreadLocal));
+        c.stream = c.capture_stream;
+        c.capturing = true;
+        try {
+            body();
+        } catch (...) {
+            c.capturing = false;
+            c.stream = launch_stream;
+            (void)hipStreamEndCapture(c.capture_stream, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            (void)hipGetLastError();
+            throw;
+        }
+        c.capturing = false;
+        c.stream = launch_stream;
+        MMOF_HIP(hipStreamEndCapture(c.capture_stream, &gr));
+        CachedGraph cg;
+        const hipError_t e = hipGraphInstantiate(&cg.exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        MMOF_CHECK(e == hipSuccess, MMOF_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        if (rep) {
+            cg.dA = rep->n_A - before.n_A;
+            cg.dAt = rep->n_At - before.n_At;
+            cg.dTheta = rep->n_theta - before.n_theta;
+            cg.dThetaT = rep->n_thetaT - before.n_thetaT;
+            cg.dL = rep->n_L - before.n_L;
+        }
+        c.graphs[key] = cg;
+        MMOF_HIP(hipGraphLaunch(cg.exec, c.stream));
+    }
+    std::string graph_key(const char* what) const {
+        char buf[512];
+        std::snprintf(buf, sizeof buf, "%s|%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%lld|%lld", what,
+                      dt, (void*)&P, (void*)u_op, (void*)I, (void*)flow_v, (void*)flow_tmp, (void*)flow_vr,
+                      (void*)rad_v, (void*)rad_vr, (void*)vin_m, (void*)out_n, (void*)out_n2, (void*)w2, (void*)r,
+                      (void*)scal, p.interp, p.use_reverse, p.n_sweeps, p.delta_r, p.alpha, (long long)n,
+                      (long long)R);
+        return std::string(buf);
+    }
+
     // ---------------------------------------------------------------- Krylov helpers (FP64)
     void norm_into(int64_t len, const double* x, double* out) {  // out = ||x||^2
         mdot<double, double>(c, len, 1, x, len, x, 1.0, out);
@@ -296,18 +370,19 @@ struct Solver {
         for (int k = ph.k_begin; k < ph.k_end; ++k) {
             // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
             if (flow && k % p.tau == 0) {
-                launch_of_derivs(c, g, dt, u_op, I, p.delta_r);
-                if (launch_hs_sweeps(c, g, dt, I, flow_v, flow_tmp, gamma, p.n_sweeps))
-                    convert<TX, TX>(c, 2 * g.pair_px, flow_tmp, flow_v);
-                launch_flow_radius(c, g, dt, flow_v, rad_v);
-                if (p.use_reverse) {
-                    launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);
-                    launch_flow_radius(c, g, dt, flow_vr, rad_vr);
-                }
-                for (int j = 0; j < K; ++j) {
-                    convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
-                    theta_flow(vin_n, TV + (int64_t)j * R);
-                }
+                replayable(graph_key("flow"), [&] {
+                    launch_of_derivs(c, g, dt, u_op, I, p.delta_r);
+                    if (launch_hs_sweeps(c, g, dt, I, flow_v, flow_tmp, gamma, p.n_sweeps))
+                        convert<TX, TX>(c, 2 * g.pair_px, flow_tmp, flow_v);
+                    launch_flow_radius(c, g, dt, flow_v, rad_v);
+                    if (p.use_reverse) {
+                        launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);
+                        launch_flow_radius(c, g, dt, flow_vr, rad_vr);
+                    }
+                });
+                launch_flow_fwd_cols(c, g, dt, p.interp, V, n, K, flow_v, p.use_reverse ? flow_vr : nullptr, TV, R,
+                                     oRF, oRR);
+                if (rep) rep->n_L += (int64_t)K * (p.use_reverse ? 2 : 1);
                 if (rep) rep->n_flow_updates++;
                 nu_fresh = false;
             }
@@ -324,11 +399,16 @@ struct Solver {
             if (!last) {
                 // 7. r = H^T (H V z - b) + lambda Theta^T P^2 Theta V z
                 gemv_fused<TX, TX>(c, m, K, AV, m, z, 1.0, b, -1.0, nullptr, vin_m, nullptr, nullptr);
-                At(vin_m, out_n);
-                theta(u_op, yR);
-                weight_mul<TX>(c, R, w2, yR, yW);
-                thetaT(yW, out_n2);
-                residual_combine<TX>(c, n, out_n, out_n2, res, r);
+                std::string key = graph_key("residual");
+                key += "|" + std::to_string(reinterpret_cast<uintptr_t>(yR)) + "|" +
+                       std::to_string(reinterpret_cast<uintptr_t>(yW));
+                replayable(key, [&] {
+                    At(vin_m, out_n);
+                    theta(u_op, yR);
+                    weight_mul<TX>(c, R, w2, yR, yW);
+                    thetaT(yW, out_n2);
+                    residual_combine<TX>(c, n, out_n, out_n2, res, r);
+                });
                 // 8. CGS2 against V, ||r||^2
                 reorth(n, V, K, r, scal + 7);
                 // Theta u^(k+1) is the next iteration's nu unless the flow changes first
