@@ -99,16 +99,19 @@ int mmof_plan_destroy(mmof_plan plan);
 /* n = number of pixels, m = number of data entries of the plan's stack. */
 int mmof_plan_sizes(mmof_plan plan, int64_t* n, int64_t* m);
 
-/* Tile-shape autotuner of the plan's stencil kernels (blur for blur plans, Psi, Psi^T,
- * L(v), L(v)^T): every candidate shape is timed on the plan's stack in dtype dt (HIP
- * events on the context's stream) and the fastest is used by later launches of the plan
- * (apply_A/At, solve_joint) in that dtype.  All candidates compute identical values.
+/* Tile-shape autotuner of the plan's stencil kernels (blur for blur plans, the angle
+ * grouping of the projector for Radon plans, Psi, Psi^T, L(v), L(v)^T): every candidate
+ * is timed on the plan's stack in dtype dt (HIP events on the context's stream) and the
+ * fastest is used by later launches of the plan (apply_A/At, solve_joint) in that dtype.
+ * The stencil candidates compute identical values; the projector's angle groups split the
+ * rows of a ray differently, which changes its sums by rounding only.
  * report: host buffer of report_len bytes (or NULL) that receives a NUL-terminated line
- * "kernel=TWxTH(mean us) ..." (a trailing "p" marks a persistent launch).  Allocates
- * scratch in the context; synchronizes the stream. */
+ * "kernel=AxB(mean us) ..." (tile width x height, or angles x row blocks for radon_fwd; a
+ * trailing "p" marks a persistent launch).  Allocates scratch in the context; synchronizes
+ * the stream. */
 int mmof_autotune(mmof_plan plan, mmof_dtype dt, char* report, int32_t report_len);
 /* Forces tile candidate `choice` (0-based, in the order the autotuner tries them) of a
- * tunable kernel ("blur", "grad_fwd", "grad_adj", "flow_fwd", "flow_adj") for the plan
+ * tunable kernel ("blur", "radon_fwd", "grad_fwd", "grad_adj", "flow_fwd", "flow_adj") for the plan
  * in dtype dt.  MMOF_ERR_INVALID for an unknown kernel or an out-of-range choice. */
 int mmof_set_tile(mmof_plan plan, const char* kernel, mmof_dtype dt, int32_t choice);
 

@@ -150,10 +150,7 @@ struct Ctx {
     std::map<std::string, std::unique_ptr<DeviceBuffer>> ws;  // named workspaces
     KernelTimer timer;
     int cu_count = 256;
-    // launch sequences captured as graphs, keyed by everything their launches depend on
-    std::map<std::string, CachedGraph> graphs;
-    std::map<std::string, int> graph_seen;
-    // private stream the sequences are captured on (capture is not possible on the legacy
+    // private stream the launch sequences of a solve are captured on (capture is not possible on the legacy
     // default stream); the graphs are launched on `stream`
     hipStream_t capture_stream = nullptr;
     bool capturing = false;  // launches are being recorded into a graph (no event timing)
@@ -187,14 +184,25 @@ struct Plan {
     std::vector<int64_t> sino_off;  // per frame, offset of its sinogram
     DeviceBuffer d_trig;            // float2/double2 per (frame, angle): cos, sin  (double)
     DeviceBuffer d_rinfo;           // RadonFrame[n_frames]
-    DeviceBuffer d_rays;            // ray tiles of the forward projector
+    DeviceBuffer d_rays[4];         // ray tiles of the forward projector (angle groups 1, 2, 4, 8)
     DeviceBuffer d_tiles_a;         // pixel tiles of the back-projector
     DeviceBuffer d_tiles_b;         // 32x32 tiles of the frame transpose
-    int64_t n_rays = 0, n_tiles_a = 0, n_tiles_b = 0;
+    int64_t n_rays[4] = {0, 0, 0, 0}, n_tiles_a = 0, n_tiles_b = 0;
     // blur
     int ksize = 9;
     double sigma = 2.0;
     DeviceBuffer d_k1;              // 1-D factor (double) [ksize]
+    // launch sequences of solves on this plan captured as graphs, keyed by every pointer and
+    // choice their launches depend on; they die with the plan (and its tile lists)
+    std::map<std::string, CachedGraph> graphs;
+    std::map<std::string, int> graph_seen;
+    Plan() = default;
+    Plan(const Plan&) = delete;
+    Plan& operator=(const Plan&) = delete;
+    ~Plan() {
+        for (auto& g : graphs)
+            if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+    }
 };
 
 // Scoped kernel timer: records events around a launch when the kernel is selected.

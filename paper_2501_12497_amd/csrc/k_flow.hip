@@ -293,7 +293,7 @@ void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out) 
     if (n == 0) return;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        hipLaunchKernelGGL(k_flow_radius<T>, grid_for(n, 256, 256), dim3(256), 0, c.stream, (const T*)v, n, d_out);
+        hipLaunchKernelGGL(k_flow_radius<T>, grid_for(n, 256, 4096), dim3(256), 0, c.stream, (const T*)v, n, d_out);
         MMOF_LAUNCH_CHECK();
     });
 }

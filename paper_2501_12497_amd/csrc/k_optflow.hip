@@ -41,6 +41,52 @@ __global__ __launch_bounds__(256) void k_of_derivs(const Tile* __restrict__ tile
     Ip[2 * np + p] = It / (box * box);
 }
 
+// The same derivatives from an LDS tile: a workgroup of 512 threads owns 64 x 8 outputs of a
+// pair and stages both frames over the tile plus a halo of dr <= DTR_MAX (mirrored indices
+// resolved while staging), then forms the sums in the order of k_of_derivs, so the values are
+// identical.
+static constexpr int DTW = 64, DTH = 8, DTR_MAX = 4;
+
+template <class T>
+__global__ __launch_bounds__(512) void k_of_derivs_lds(const Tile* __restrict__ tiles,
+                                                       const FrameInfo* __restrict__ fr, const T* __restrict__ u,
+                                                       T* __restrict__ I, int dr) {
+    constexpr int LW = DTW + 2 * DTR_MAX, LH = DTH + 2 * DTR_MAX;
+    __shared__ T sa[LH][LW], sb[LH][LW];
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int nx = f.nx, ny = f.ny;
+    const int64_t np = (int64_t)nx * ny;
+    const T* a = u + f.off;  // frame t
+    const T* b = a + np;     // frame t+1
+    const int hw = DTW + 2 * dr, hh = DTH + 2 * dr;
+    for (int i = threadIdx.x; i < hw * hh; i += 512) {
+        const int ly = i / hw, lx = i % hw;
+        const int yy = tl.y0 - dr + ly, xx = tl.x0 - dr + lx;
+        if (yy >= ny + dr || xx >= nx + dr) continue;  // beyond the frame's own halo
+        const int64_t o = (int64_t)mirror(yy, ny) * nx + mirror(xx, nx);
+        sa[ly][lx] = a[o];
+        sb[ly][lx] = b[o];
+    }
+    __syncthreads();
+    const int tx = (int)(threadIdx.x % DTW), ty = (int)(threadIdx.x / DTW);
+    const int x = tl.x0 + tx, y = tl.y0 + ty;
+    if (x >= nx || y >= ny) return;
+    const int cx = tx + dr, cy = ty + dr;  // the output's position in the tile
+    T Ix = T(0), Iy = T(0), It = T(0);
+    for (int j = -dr; j <= dr; ++j) {
+        Ix += sa[cy + j][cx + dr] - sa[cy + j][cx - dr];
+        Iy += sa[cy + dr][cx + j] - sa[cy - dr][cx + j];
+        for (int k = -dr; k <= dr; ++k) It += sb[cy + j][cx + k] - sa[cy + j][cx + k];
+    }
+    const T box = T(2 * dr + 1);
+    const int64_t p = (int64_t)y * nx + x;
+    T* Ip = I + 3 * f.pair_off;
+    Ip[p] = Ix / (box * T(2 * dr));
+    Ip[np + p] = Iy / (box * T(2 * dr));
+    Ip[2 * np + p] = It / (box * box);
+}
+
 // Exact 2x2 block-Jacobi sweeps for the p = q = 2 flow energy: per pixel,
 // sbar = mean of the in-image 4-neighbours, s = sbar - g (g.sbar + I_t) / (gamma d + |g|^2).
 // Up to HS_MAX block-Jacobi sweeps per launch (temporal blocking).  A workgroup owns an
@@ -186,12 +232,18 @@ __global__ void k_mm_weights(int64_t n, const T* __restrict__ nu, T eps2, T* __r
 
 void launch_of_derivs(Ctx& c, Geom& g, int dt, const void* u, void* I, int dr) {
     if (g.n_pairs == 0) return;
-    const TileList& tl = g.tile_list(c.stream, OTW, OTH, true);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "of_derivs");
-        hipLaunchKernelGGL(k_of_derivs<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), (const T*)u, (T*)I, dr);
+        ScopedTime st(&c, "of_derivs", 5.0 * sizeof(T) * g.pair_px, (4.0 * (2 * dr + 1) + 2.0 * (2 * dr + 1) * (2 * dr + 1)) * g.pair_px);
+        if (dr <= DTR_MAX) {
+            const TileList& tl = g.tile_list(c.stream, DTW, DTH, true);
+            hipLaunchKernelGGL(k_of_derivs_lds<T>, dim3((unsigned)tl.count), dim3(512), 0, c.stream,
+                               tl.buf.as<Tile>(), g.dframes(), (const T*)u, (T*)I, dr);
+        } else {
+            const TileList& tl = g.tile_list(c.stream, OTW, OTH, true);
+            hipLaunchKernelGGL(k_of_derivs<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                               g.dframes(), (const T*)u, (T*)I, dr);
+        }
         MMOF_LAUNCH_CHECK();
     });
 }

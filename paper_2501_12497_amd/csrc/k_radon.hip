@@ -26,7 +26,7 @@ struct RayTile {
     int32_t frame, angle, bin0, pad;
 };
 
-static constexpr int RTW = 64, RTH = 4;  // pixel tiles of the transpose
+static constexpr int RTW = 16, RTH = 16;  // pixel tiles of the transpose (backprojection)
 
 // Per-frame transpose uT[f][x][y] = u[f][y][x] through a 32x33 LDS tile.
 template <class T>
@@ -48,83 +48,176 @@ __global__ __launch_bounds__(256) void k_transpose_frames(const Tile* __restrict
     }
 }
 
-// One workgroup per (frame, angle, 64 bins): lane = bin, the four waves walk disjoint
-// quarters of the rows and their partial sums are added in a fixed order.
+// Sum over the (at most three) pixels of one row with non-zero hat weight for a ray whose
+// centre crosses the row at xs: weights 1 - |a| |x - xs| with |a| >= 1/sqrt(2), so the
+// pixels are floor(xs) - 1 .. floor(xs) + 1 when the fraction is below 1/2, else
+// floor(xs) .. floor(xs) + 2.
 template <class T>
-__global__ __launch_bounds__(256) void k_radon_fwd(const RayTile* __restrict__ rays, int64_t n_rays,
-                                                   const RadonFrame* __restrict__ rf, const double2* __restrict__ trig,
-                                                   const T* __restrict__ u, const T* __restrict__ ut,
-                                                   T* __restrict__ b) {
-    __shared__ T part[4][64];
-    const int64_t wid = xcd_remap(blockIdx.x, gridDim.x);
-    const RayTile rt = rays[wid];
+__device__ __forceinline__ T hat_row(const T* __restrict__ row, int ncol, double xs, T aa) {
+    const double fl = floor(xs);
+    const int xi = (int)fl;
+    const T fr = (T)(xs - fl);
+    const int k0 = fr < T(0.5) ? -1 : 0;
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int x = xi + k0 + k;
+        const T w = T(1) - aa * fabs(T(k0 + k) - fr);
+        if (x >= 0 && x < ncol && w > T(0)) acc += w * row[x];
+    }
+    return acc;
+}
+
+// The same sum for a row where all three candidates lie inside the row (xs in [1, ncol - 2)):
+// pixels floor(xs) and floor(xs) + 1 with weights 1 - |a| f and 1 - |a| (1 - f), and the
+// outer neighbour on the nearer side with weight max(0, 1 - |a| (1 + min(f, 1 - f))).
+template <class T>
+__device__ __forceinline__ T hat_row_inner(const T* __restrict__ row, int ncol, double xs, T aa) {
+    // xs >= 1: truncation is the floor; the clamp keeps every access inside the row even if
+    // rounding puts xs a hair outside the interior (the weights then still match xs)
+    const int xi = min(max((int)xs, 1), ncol - 3);
+    const T fr = (T)(xs - (double)xi);
+    const bool lo = fr < T(0.5);
+    const T w0 = T(1) - aa * fr;
+    const T w1 = T(1) - aa * (T(1) - fr);
+    const T w2 = fmax(T(1) - aa * (T(1) + (lo ? fr : T(1) - fr)), T(0));
+    return w0 * row[xi] + w1 * row[xi + 1] + w2 * row[lo ? xi - 1 : xi + 2];
+}
+
+// One workgroup of 8 waves per (frame, ANG consecutive angles, 64 bins): lane = bin, wave
+// w takes angle w / (8/ANG) and the (w % (8/ANG))-th block of rows, walking four rows per
+// step so that their loads are in flight together.  The waves of one workgroup read
+// overlapping spans of the same rows, so a wider angle group reuses the image through the
+// cache; partial sums are added in a fixed order.
+template <class T, int ANG>
+__global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ rays, const RadonFrame* __restrict__ rf,
+                                                   const double2* __restrict__ trig, const T* __restrict__ u,
+                                                   const T* __restrict__ ut, T* __restrict__ b) {
+    constexpr int RSL = 8 / ANG;
+    __shared__ T part[8][64];
+    const RayTile rt = rays[xcd_remap(blockIdx.x, gridDim.x)];
     const RadonFrame f = rf[rt.frame];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ang = rt.angle + wave / RSL, sl = wave % RSL;
     const int j = rt.bin0 + lane;
-    const double2 cs = trig[f.trig_off + rt.angle];
-    const double c = cs.x, s = cs.y;
-    const double cx = 0.5 * (f.nx - 1), cy = 0.5 * (f.ny - 1);
-    const double dj = (double)j - 0.5 * (f.n_bins - 1);
-    // Row walk over (rows, cols) = (ny, nx) of u, or over (nx, ny) of the transpose.
-    const bool steep = fabs(s) > fabs(c);
-    const double a = steep ? s : c;              // coefficient of the in-row coordinate
-    const double bb = steep ? c : s;             // coefficient of the row coordinate
-    const int nrow = steep ? f.nx : f.ny, ncol = steep ? f.ny : f.nx;
-    const double crow = steep ? cx : cy, ccol = steep ? cy : cx;
-    const T* img = (steep ? ut : u) + f.u_off;
-    // position of the ray centre in row r: xs(r) = ccol + (dj - (r - crow) bb) / a
-    const double xs0 = ccol + (dj + crow * bb) / a;
-    const double step = -bb / a;
-    const T aa = (T)fabs(a);
-    const int q = (nrow + 3) >> 2;
-    const int r_lo = wave * q, r_hi = min(nrow, r_lo + q);
     T acc = T(0);
-    if (j < f.n_bins) {
-        for (int r = r_lo; r < r_hi; ++r) {
-            const double xs = fma((double)r, step, xs0);
-            const double fl = floor(xs);
-            const int xi = (int)fl;
-            const T fr = (T)(xs - fl);
-            const T* row = img + (int64_t)r * ncol;
-#pragma unroll
-            for (int k = -1; k <= 2; ++k) {
-                const int x = xi + k;
-                if (x < 0 || x >= ncol) continue;
-                const T w = T(1) - aa * fabs((T)k - fr);
-                if (w > T(0)) acc += w * row[x];
-            }
+    if (ang < f.n_ang && j < f.n_bins) {
+        const double2 cs = trig[f.trig_off + ang];
+        const double c = cs.x, s = cs.y;
+        const double cx = 0.5 * (f.nx - 1), cy = 0.5 * (f.ny - 1);
+        const double dj = (double)j - 0.5 * (f.n_bins - 1);
+        // row walk over (rows, cols) = (ny, nx) of u, or over (nx, ny) of the transpose
+        const bool steep = fabs(s) > fabs(c);
+        const double a = steep ? s : c;   // coefficient of the in-row coordinate
+        const double bb = steep ? c : s;  // coefficient of the row coordinate
+        const int nrow = steep ? f.nx : f.ny, ncol = steep ? f.ny : f.nx;
+        const double crow = steep ? cx : cy, ccol = steep ? cy : cx;
+        const T* img = (steep ? ut : u) + f.u_off;
+        // ray centre in row r: xs(r) = ccol + (dj - (r - crow) bb) / a
+        const double xs0 = ccol + (dj + crow * bb) / a;
+        const double step = -bb / a;
+        const double inv_step = 1.0 / step;  // inf for step 0 (that case is handled apart)
+        const T aa = (T)fabs(a);
+        const int q = (nrow + RSL - 1) / RSL;
+        int r_lo = sl * q, r_hi = min(nrow, r_lo + q);
+        // rows where the ray can touch the image (xs in (-1.5, ncol + 0.5)), and among them
+        // the rows where every candidate is inside (xs in [1, ncol - 2)), from xs linear in r
+        auto row_of = [&](double x) { return (x - xs0) * inv_step; };
+        int in_lo = r_lo, in_hi = r_lo;  // [in_lo, in_hi): interior rows
+        // (bounds are clamped to [0, nrow] in double before the conversion, so near-axis
+        // angles, whose tiny slope puts the crossings far away, give in-range integers)
+        const double dn = (double)nrow;
+        auto clamp_row = [&](double x) { return (int)fmin(fmax(x, 0.0), dn); };
+        if (step != 0.0) {
+            const double ra = row_of(-1.5), rb = row_of((double)ncol + 0.5);
+            const double t_lo = fmin(ra, rb), t_hi = fmax(ra, rb);
+            r_lo = max(r_lo, clamp_row(floor(t_lo) - 1.0));
+            r_hi = min(r_hi, clamp_row(ceil(t_hi) + 2.0));
+            const double ia = row_of(1.0), ib = row_of((double)ncol - 2.0);
+            in_lo = max(r_lo, clamp_row(ceil(fmin(ia, ib)) + 1.0));
+            in_hi = min(r_hi, clamp_row(floor(fmax(ia, ib)) - 1.0));
+        } else if (xs0 >= 1.0 && xs0 < (double)ncol - 2.0) {
+            in_lo = r_lo;
+            in_hi = r_hi;
         }
+        if (in_hi < in_lo || ncol < 4) in_hi = in_lo = r_lo;  // no interior (also for rows shorter than 4)
+        int r = r_lo;
+        for (; r < min(in_lo, r_hi); ++r) acc += hat_row(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+        for (; r < in_hi - 3; r += 4) {
+            const T a0 = hat_row_inner(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+            const T a1 = hat_row_inner(img + (int64_t)(r + 1) * ncol, ncol, fma((double)(r + 1), step, xs0), aa);
+            const T a2 = hat_row_inner(img + (int64_t)(r + 2) * ncol, ncol, fma((double)(r + 2), step, xs0), aa);
+            const T a3 = hat_row_inner(img + (int64_t)(r + 3) * ncol, ncol, fma((double)(r + 3), step, xs0), aa);
+            acc += (a0 + a1) + (a2 + a3);
+        }
+        for (; r < in_hi; ++r) acc += hat_row_inner(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+        for (; r < r_hi; ++r) acc += hat_row(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
     }
     part[wave][lane] = acc;
     __syncthreads();
-    if (wave == 0 && j < f.n_bins)
-        b[f.sino_off + (int64_t)rt.angle * f.n_bins + j] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (sl == 0 && ang < f.n_ang && j < f.n_bins) {
+        T sum = T(0);
+#pragma unroll
+        for (int k = 0; k < RSL; ++k) sum += part[wave + k][lane];
+        b[f.sino_off + (int64_t)ang * f.n_bins + j] = sum;
+    }
 }
+
+// Transpose: one workgroup per 16 x 16 pixel tile.  For each angle the tile projects onto
+// fewer than AW consecutive bins; those sinogram windows are staged in LDS, AC angles at a
+// time (zeros outside the detector), and every pixel then gathers its two hat weights per
+// angle from LDS.
+static constexpr int AW = 32, AC = 32;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tiles, const RadonFrame* __restrict__ rf,
                                                    const double2* __restrict__ trig, const T* __restrict__ b,
                                                    T* __restrict__ u) {
+    __shared__ T win[AC][AW];
+    __shared__ int jlo[AC];
+    __shared__ double2 scs[AC];
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const RadonFrame f = rf[tl.frame];
     const int x = tl.x0 + (int)(threadIdx.x % RTW);
     const int y = tl.y0 + (int)(threadIdx.x / RTW);
-    if (x >= f.nx || y >= f.ny) return;
-    const double X = x - 0.5 * (f.nx - 1), Y = y - 0.5 * (f.ny - 1);
+    const bool inside = x < f.nx && y < f.ny;
+    const double hx = 0.5 * (f.nx - 1), hy = 0.5 * (f.ny - 1);
+    const double X = x - hx, Y = y - hy;
     const double cd = 0.5 * (f.n_bins - 1);
+    // tile corners (clipped to the frame) for the window bounds
+    const double X0 = tl.x0 - hx, X1 = min(tl.x0 + RTW, f.nx) - 1 - hx;
+    const double Y0 = tl.y0 - hy, Y1 = min(tl.y0 + RTH, f.ny) - 1 - hy;
     const T* sino = b + f.sino_off;
     T acc = T(0);
-    for (int k = 0; k < f.n_ang; ++k) {
-        const double2 cs = trig[f.trig_off + k];
-        const double pos = fma(X, cs.x, fma(Y, cs.y, cd));
-        const double fl = floor(pos);
-        const int j0 = (int)fl;
-        const T fr = (T)(pos - fl);
-        const T* row = sino + (int64_t)k * f.n_bins;
-        if (j0 >= 0 && j0 < f.n_bins) acc += (T(1) - fr) * row[j0];
-        if (j0 + 1 >= 0 && j0 + 1 < f.n_bins) acc += fr * row[j0 + 1];
+    for (int k0 = 0; k0 < f.n_ang; k0 += AC) {
+        const int nk = min(AC, f.n_ang - k0);
+        __syncthreads();  // the previous chunk's windows are no longer read
+        if (threadIdx.x < nk) {
+            const double2 cs = trig[f.trig_off + k0 + threadIdx.x];
+            const double pmin = cd + fmin(X0 * cs.x, X1 * cs.x) + fmin(Y0 * cs.y, Y1 * cs.y);
+            jlo[threadIdx.x] = (int)floor(pmin) - 1;
+            scs[threadIdx.x] = cs;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nk * AW; i += 256) {
+            const int kk = i / AW, w = i % AW;
+            const int j = jlo[kk] + w;
+            win[kk][w] = (j >= 0 && j < f.n_bins) ? sino[(int64_t)(k0 + kk) * f.n_bins + j] : T(0);
+        }
+        __syncthreads();
+        if (inside) {
+#pragma unroll 4
+            for (int kk = 0; kk < nk; ++kk) {
+                const double2 cs = scs[kk];
+                const double pos = fma(X, cs.x, fma(Y, cs.y, cd));
+                const double fl = floor(pos);
+                const int w0 = (int)fl - jlo[kk];
+                const T fr = (T)(pos - fl);
+                acc += (T(1) - fr) * win[kk][w0] + fr * win[kk][w0 + 1];
+            }
+        }
     }
-    u[f.u_off + (int64_t)y * f.nx + x] = acc;
+    if (inside) u[f.u_off + (int64_t)y * f.nx + x] = acc;
 }
 
 // ----------------------------------------------------------------------------- host side
@@ -132,7 +225,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tile
 void radon_plan_init(Ctx& c, Plan& p) {
     Geom& g = *p.geom;
     std::vector<RadonFrame> rfs;
-    std::vector<RayTile> rays;
+    std::vector<RayTile> rays[4];  // angle groups of 1, 2, 4, 8
     std::vector<Tile> px, tr;
     int64_t sino = 0, trig = 0;
     for (int64_t fi = 0; fi < g.n_frames; ++fi) {
@@ -147,8 +240,11 @@ void radon_plan_init(Ctx& c, Plan& p) {
         r.nx = fr.nx;
         rfs.push_back(r);
         p.sino_off.push_back(sino);
-        for (int k = 0; k < r.n_ang; ++k)
-            for (int j0 = 0; j0 < r.n_bins; j0 += 64) rays.push_back(RayTile{(int32_t)fi, k, j0, 0});
+        for (int gi = 0; gi < 4; ++gi) {
+            const int ag = 1 << gi;
+            for (int k = 0; k < r.n_ang; k += ag)
+                for (int j0 = 0; j0 < r.n_bins; j0 += 64) rays[gi].push_back(RayTile{(int32_t)fi, k, j0, 0});
+        }
         for (int y0 = 0; y0 < fr.ny; y0 += RTH)
             for (int x0 = 0; x0 < fr.nx; x0 += RTW) px.push_back(Tile{(int32_t)fi, y0, x0, 0});
         for (int y0 = 0; y0 < fr.ny; y0 += 32)
@@ -160,11 +256,13 @@ void radon_plan_init(Ctx& c, Plan& p) {
     p.m = sino;
     p.d_rinfo.ensure(sizeof(RadonFrame) * rfs.size());
     MMOF_HIP(hipMemcpyAsync(p.d_rinfo.ptr, rfs.data(), sizeof(RadonFrame) * rfs.size(), hipMemcpyHostToDevice, c.stream));
-    p.n_rays = (int64_t)rays.size();
-    p.d_rays.ensure(sizeof(RayTile) * std::max<size_t>(rays.size(), 1));
-    if (!rays.empty())
-        MMOF_HIP(hipMemcpyAsync(p.d_rays.ptr, rays.data(), sizeof(RayTile) * rays.size(), hipMemcpyHostToDevice,
-                                c.stream));
+    for (int gi = 0; gi < 4; ++gi) {
+        p.n_rays[gi] = (int64_t)rays[gi].size();
+        p.d_rays[gi].ensure(sizeof(RayTile) * std::max<size_t>(rays[gi].size(), 1));
+        if (!rays[gi].empty())
+            MMOF_HIP(hipMemcpyAsync(p.d_rays[gi].ptr, rays[gi].data(), sizeof(RayTile) * rays[gi].size(),
+                                    hipMemcpyHostToDevice, c.stream));
+    }
     p.n_tiles_a = (int64_t)px.size();
     p.d_tiles_a.ensure(sizeof(Tile) * px.size());
     MMOF_HIP(hipMemcpyAsync(p.d_tiles_a.ptr, px.data(), sizeof(Tile) * px.size(), hipMemcpyHostToDevice, c.stream));
@@ -174,8 +272,19 @@ void radon_plan_init(Ctx& c, Plan& p) {
     MMOF_HIP(hipStreamSynchronize(c.stream));
 }
 
-void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
-    if (p.n_rays == 0) return;
+const int kRadonCandidates = 4;  // angle groups of 1, 2, 4, 8 per workgroup
+
+int radon_fwd_choice(Plan& p, int dt) {
+    auto it = p.geom->tuned.find(std::string("radon_fwd") + (dt == MMOF_F32 ? "/f32" : "/f64"));
+    if (it != p.geom->tuned.end()) return it->second;
+    // untuned: wide angle groups once a frame no longer fits the cache of one angle's pass
+    return p.geom->max_ny >= 512 ? 3 : 1;
+}
+
+void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b, int choice) {
+    if (choice < 0) choice = radon_fwd_choice(p, dt);
+    MMOF_CHECK(choice >= 0 && choice < kRadonCandidates, MMOF_ERR_INVALID, "radon_fwd candidate out of range");
+    if (p.n_rays[choice] == 0) return;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         T* ut = static_cast<T*>(c.work("radon_transpose", sizeof(T) * p.n));
@@ -183,9 +292,10 @@ void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
                            p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), (const T*)u, ut);
         MMOF_LAUNCH_CHECK();
         ScopedTime st(&c, "radon_fwd", (double)sizeof(T) * (p.n + p.m), p.radon_flops);
-        hipLaunchKernelGGL(k_radon_fwd<T>, dim3((unsigned)p.n_rays), dim3(256), 0, c.stream,
-                           p.d_rays.as<RayTile>(), p.n_rays, p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(),
-                           (const T*)u, (const T*)ut, (T*)b);
+        auto k = choice == 0 ? k_radon_fwd<T, 1> : choice == 1 ? k_radon_fwd<T, 2> : choice == 2 ? k_radon_fwd<T, 4>
+                                                                                                 : k_radon_fwd<T, 8>;
+        hipLaunchKernelGGL(k, dim3((unsigned)p.n_rays[choice]), dim3(512), 0, c.stream, p.d_rays[choice].as<RayTile>(),
+                           p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), (const T*)u, (const T*)ut, (T*)b);
         MMOF_LAUNCH_CHECK();
     });
 }

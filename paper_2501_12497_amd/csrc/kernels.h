@@ -42,7 +42,9 @@ void launch_reverse_flow(Ctx& c, Geom& g, int dt, const void* v, void* vr, const
 void launch_mm_weights(Ctx& c, int dt, int64_t n, const void* nu, double eps, void* w2);
 
 // Forward operators.
-void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b);
+// choice: angle-group candidate (0..3 = 1, 2, 4, 8 angles per workgroup), -1 = tuned/default
+extern const int kRadonCandidates;
+void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b, int choice = -1);
 void launch_radon_adj(Ctx& c, Plan& p, int dt, const void* b, void* u);
 void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out, int choice = -1);
 

@@ -108,8 +108,6 @@ Geom& Ctx::geom(const mmof_stack* s) {
 }
 
 Ctx::~Ctx() {
-    for (auto& g : graphs)
-        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     if (pinned_buf) (void)hipHostFree(pinned_buf);
     for (auto& e : timer.events) {

@@ -164,7 +164,7 @@ struct Solver {
     // ---------------------------------------------------------------- graphs
     // Runs body, a launch sequence whose launches depend only on `key`: eagerly on its first
     // use (which also creates its tile lists and workspaces), captured into a graph and
-    // launched on its second, replayed from the context's cache afterwards.  The report
+    // launched on its second, replayed from the plan's cache afterwards.  The report
     // counters the body increments are added again on every replay; kernels inside a graph
     // are not event-timed.
     template <class F>
@@ -173,8 +173,8 @@ struct Solver {
             body();
             return;
         }
-        auto it = c.graphs.find(key);
-        if (it != c.graphs.end()) {
+        auto it = P.graphs.find(key);
+        if (it != P.graphs.end()) {
             MMOF_HIP(hipGraphLaunch(it->second.exec, c.stream));
             if (rep) {
                 rep->n_A += it->second.dA;
@@ -185,7 +185,7 @@ struct Solver {
             }
             return;
         }
-        if (c.graph_seen[key]++ == 0) {
+        if (P.graph_seen[key]++ == 0) {
             body();
             return;
         }
@@ -222,17 +222,18 @@ struct Solver {
             cg.dThetaT = rep->n_thetaT - before.n_thetaT;
             cg.dL = rep->n_L - before.n_L;
         }
-        c.graphs[key] = cg;
+        P.graphs[key] = cg;
         MMOF_HIP(hipGraphLaunch(cg.exec, c.stream));
     }
     std::string graph_key(const char* what) const {
         char buf[512];
-        std::snprintf(buf, sizeof buf, "%s|%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%lld|%lld", what,
-                      dt, (void*)&P, (void*)u_op, (void*)I, (void*)flow_v, (void*)flow_tmp, (void*)flow_vr,
-                      (void*)rad_v, (void*)rad_vr, (void*)vin_m, (void*)out_n, (void*)out_n2, (void*)w2, (void*)r,
-                      (void*)scal, p.interp, p.use_reverse, p.n_sweeps, p.delta_r, p.alpha, (long long)n,
-                      (long long)R);
-        return std::string(buf);
+        std::snprintf(buf, sizeof buf, "%s|%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%lld|%lld", what, dt,
+                      (void*)u_op, (void*)I, (void*)flow_v, (void*)flow_tmp, (void*)flow_vr, (void*)rad_v,
+                      (void*)rad_vr, (void*)vin_m, (void*)out_n, (void*)out_n2, (void*)w2, (void*)r, (void*)scal,
+                      p.interp, p.use_reverse, p.n_sweeps, p.delta_r, p.alpha, (long long)n, (long long)R);
+        std::string key(buf);
+        for (const auto& t : g.tuned) key += "|" + t.first + "=" + std::to_string(t.second);  // tile lists used
+        return key;
     }
 
     // ---------------------------------------------------------------- Krylov helpers (FP64)

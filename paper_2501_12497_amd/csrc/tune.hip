@@ -1,9 +1,11 @@
 // Tile-shape autotuner of the stencil kernels.  For a plan's stack and a dtype it times every
-// tile-shape candidate of blur (blur plans), Psi, Psi^T, L(v) and L(v)^T on scratch buffers of
-// the stack's sizes (HIP events on the context's stream, a warm-up launch then TUNE_REPS
-// timed launches per candidate) and records the fastest candidate in the geometry, where the
-// launchers find it.  All candidates compute the same values (the per-pixel arithmetic and
-// summation order do not depend on the tile shape), so tuning changes only speed.
+// candidate of blur (blur plans), the projector's angle grouping (Radon plans), Psi, Psi^T,
+// L(v) and L(v)^T on scratch buffers of the stack's sizes (HIP events on the context's
+// stream, a warm-up launch then TUNE_REPS timed launches per candidate) and records the
+// fastest candidate in the plan's geometry, where the launchers find it.  The stencil
+// candidates compute the same values (the per-pixel arithmetic and summation order do not
+// depend on the tile shape); the projector's angle groups split a ray's rows differently,
+// which changes its sum by rounding only.
 #include <cstdio>
 #include <string>
 
@@ -74,6 +76,13 @@ std::string autotune(Plan& P, int dt) {
     std::string rep;
     if (P.kind == 1)
         pick(c, g, "blur", dt, kBlurCandidates, kBlurShapes, [&](int k) { launch_blur(c, P, dt, u, o, k); }, rep);
+    if (P.kind == 0) {
+        // angle groups of 1, 2, 4, 8 per workgroup, reported as "<angles>x<row blocks>"
+        static const TileShape groups[] = {{1, 8, 0}, {2, 4, 0}, {4, 2, 0}, {8, 1, 0}};
+        void* sino = c.work("tune_b", es * (size_t)std::max<int64_t>(P.m, 1));
+        pick(c, g, "radon_fwd", dt, kRadonCandidates, groups,
+             [&](int k) { launch_radon_fwd(c, P, dt, u, sino, k); }, rep);
+    }
     pick(c, g, "grad_fwd", dt, kGradCandidates, kGradShapes,
          [&](int k) { launch_grad_fwd(c, g, dt, u, nullptr, nullptr, gx, gy, k); }, rep);
     pick(c, g, "grad_adj", dt, kGradCandidates, kGradShapes,
@@ -92,6 +101,7 @@ std::string autotune(Plan& P, int dt) {
 
 void set_tile(Plan& P, const std::string& kernel, int dt, int choice) {
     int n = kernel == "blur" ? kBlurCandidates
+            : kernel == "radon_fwd" ? kRadonCandidates
             : (kernel == "grad_fwd" || kernel == "grad_adj") ? kGradCandidates
             : kernel == "flow_fwd" ? kFlowCandidates
             : kernel == "flow_adj" ? kFlowAdjCandidates
