@@ -42,6 +42,7 @@ COMPUTE = {
     "grad_fwd": ("alu", 157.3),
     "grad_adj": ("alu", 157.3),
     "hs_multi": ("alu", 157.3),
+    "of_derivs": ("alu", 157.3),
     "mdot": ("alu", 78.6),          # FP64 vector ALU
 }
 # The committed HBM-traffic summary of a kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) and
@@ -97,6 +98,57 @@ def gpu_data(wl, B, torch):
     b = (clean + e).contiguous()
     delta = float(torch.linalg.vector_norm(e))
     return stack, plan, u_true, b, delta
+
+
+def operators_large(B, torch, reps=5):
+    """Per-kernel rates of the operators on the 1024x1024x64 workload (FP32; 90 angles per
+    frame shifted by the golden angle, 1449 bins; a smooth flow of up to 3 px): HIP-event
+    mean over `reps` launches, algorithmic bytes and flops as the library counts them."""
+    from paper_2501_12497_amd import _lib
+    from synth import cfg_large1024, smooth_flow_coarse
+    wl = cfg_large1024()
+    s = wl.seqs[0]
+    stack = B.Stack.single(s.n_t, s.ny, s.nx)
+    plan = B.plan_radon(stack, [s.angles.shape[1]], [s.n_bins], s.angles.ravel())
+    ctx = plan.ctx
+    u = torch.as_tensor(s.u_true.ravel(), dtype=torch.float32, device="cuda")
+    v = torch.as_tensor(smooth_flow_coarse(s.n_t - 1, s.nx, seed=11, coarse=16, vmax=3.0).ravel(),
+                        dtype=torch.float32, device="cuda")
+    b = B.apply_A(plan, u)
+    gx, gy = B.apply_grad(stack, u)
+    r = B.apply_flow_op(stack, _lib.MMOF_FLOW_FWD, 1, 0, u, v)
+    w = torch.zeros_like(v)
+    ops = {
+        "radon_fwd": lambda: B.apply_A(plan, u, out=b),
+        "radon_adj": lambda: B.apply_At(plan, b),
+        "grad_fwd": lambda: B.apply_grad(stack, u),
+        "grad_adj": lambda: B.apply_grad(stack, gx=gx, gy=gy, transpose=True),
+        "flow_fwd": lambda: B.apply_flow_op(stack, _lib.MMOF_FLOW_FWD, 1, 0, u, v),
+        "flow_adj": lambda: B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, 1, 0, None, v, r),
+        "of_derivs": lambda: B.of_derivs(stack, u, 1),
+        "hs_multi": lambda: B.flow_update(stack, u, w, alpha=0.1, n_sweeps=8, delta_r=1),
+    }
+    table = {}
+    for name, f in ops.items():
+        f()
+        torch.cuda.synchronize()
+        ctx.profile_kernel(name)
+        for _ in range(reps):
+            f()
+        n, ms, by, fl = ctx.kernel_timing()
+        ctx.profile_kernel(None)
+        if not n:
+            continue
+        sec = ms * 1e-3
+        unit, peak = COMPUTE[name]
+        ent = {"us": round(ms * 1e3 / n, 1), "GB/s": round(by / sec / 1e9, 1), "hbm_frac": round(by / sec / 1e9 / HBM_PEAK_GBS, 3),
+               "TFLOP/s": round(fl / sec / 1e12, 2), "compute_frac": round(fl / sec / 1e12 / peak, 3)}
+        if name == "hs_multi":
+            ent["sweeps_per_launch"] = 8
+        table[name] = ent
+    del plan
+    return {"workload": "large1024x1024x64: 12 moving/rotating ellipses, 90 golden-angle-shifted angles/frame, "
+                        "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "kernels": table}
 
 
 def solve_params(wl, op, graph=True):
@@ -163,6 +215,7 @@ def main():
     ap.add_argument("--profile-kernel", default="wgram")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the operator table at 1024x1024x64")
     ap.add_argument("--graph", action="store_true",
                     help="replay the fixed launch sequences of each iteration from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -261,6 +314,11 @@ def main():
                        "reached": bool(rr.rre[-1] <= target)}
         log(f"time to solution: {tts}")
 
+    large = None
+    if not a.no_large:
+        large = operators_large(B, torch)
+        log(f"operators at 1024x1024x64: {large['kernels']}")
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(wl)
@@ -285,6 +343,7 @@ def main():
         "roofline": roof,
         "time_to_solution": tts,
         "cpu_baseline": cpu,
+        "operators_large": large,
     }
     print(json.dumps(out))
 

@@ -62,8 +62,8 @@ typedef struct mmof_plan_s* mmof_plan;
 typedef struct {
     int32_t n_seq;
     const int32_t* n_t;   /* frames per sequence, >= 1 (flow calls need >= 2) */
-    const int32_t* ny;    /* rows per frame, >= 2                             */
-    const int32_t* nx;    /* columns per frame, >= 2                          */
+    const int32_t* ny;    /* rows per frame, 2 .. 65535                       */
+    const int32_t* nx;    /* columns per frame, 2 .. 65535                    */
 } mmof_stack;
 
 /* ------------------------------------------------------------------ context */

@@ -113,11 +113,14 @@ struct Geom {
     std::vector<int64_t> seq_off;        // pixel offset per sequence
     DeviceBuffer d_frames;               // FrameInfo[n_frames]
     std::map<uint64_t, std::unique_ptr<TileList>> tiles;  // (tw, th, pairs) -> list
-    // Tile-shape candidate chosen by the autotuner per "kernel/dtype" (absent: candidate 0).
+    // Tile-shape candidate chosen by the autotuner per "kernel/dtype".  Untuned kernels use
+    // candidate 0 (tiles of 1024 outputs) on frames of at least 512 x 512 pixels and
+    // `small` (tiles of 256 outputs, more workgroups) on smaller frames.
     std::map<std::string, int> tuned;
-    int choice(const char* kernel, int dt) const {
+    int choice(const char* kernel, int dt, int small = 0) const {
         auto it = tuned.find(std::string(kernel) + (dt == MMOF_F32 ? "/f32" : "/f64"));
-        return it == tuned.end() ? 0 : it->second;
+        if (it != tuned.end()) return it->second;
+        return (int64_t)max_nx * max_ny >= 512 * 512 ? 0 : small;
     }
 
     bool same_as(const mmof_stack& s) const;

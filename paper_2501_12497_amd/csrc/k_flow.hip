@@ -116,13 +116,20 @@ __device__ __forceinline__ bool corner_weight(int c0, T f, int q, T& w) {
     return false;
 }
 
+// Adjoint over an ATX x ATY output tile per workgroup of 256 threads; each thread owns
+// RPT = ATX * ATY / 256 consecutive rows of one column.  The sources of the tile's
+// neighbourhood are staged in LDS with their sample cell packed into one word, and a
+// thread scans the window of sources that can reach any of its rows once, in raster order,
+// adding each match to the row it lands in (so every output sums its sources in raster
+// order, whatever the tile shape).
 template <class T, int INTERP, int ATX, int ATY>
 __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ r, const T* __restrict__ v,
                                                   T* __restrict__ u, int direction, int accumulate,
                                                   const int32_t* __restrict__ d_radius) {
+    constexpr int RPT = ATX * ATY / 256;
     constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);
-    __shared__ int s_x0[SMAX], s_y0[SMAX];
+    __shared__ unsigned s_cell[SMAX];  // x0 | y0 << 16 of the source's sample cell
     __shared__ T s_fx[SMAX], s_fy[SMAX], s_val[SMAX];
     __shared__ int s_d[4];  // dmin_x, dmax_x, dmin_y, dmax_y
 
@@ -132,22 +139,22 @@ __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles
     const int nx = f.nx, ny = f.ny;
     const int64_t np = (int64_t)nx * ny;
     const int qx = tl.x0 + (int)(threadIdx.x % ATX);
-    const int qy = tl.y0 + (int)(threadIdx.x / ATX);
-    const bool inside = qx < nx && qy < ny;
-    const int64_t q = (int64_t)qy * nx + qx;
+    const int qy0 = tl.y0 + (int)(threadIdx.x / ATX) * RPT;
+    const bool col_in = qx < nx;
 
-    // direct term and the pair whose warp gathers into this frame
-    T direct = T(0);
-    int64_t gp = -1;  // pair offset of the gathering pair
+    // direct terms and the pair whose warp gathers into this frame
+    int64_t dp = -1, gp = -1;  // pair offsets of the direct term and of the gathering pair
     if (direction > 0) {
-        if (f.t + 1 < f.n_t && inside) direct = -r[f.pair_off + q];
+        if (f.t + 1 < f.n_t) dp = f.pair_off;
         if (f.t >= 1) gp = fr[fi - 1].pair_off;
     } else {
-        if (f.t >= 1 && inside) direct = -r[fr[fi - 1].pair_off + q];
+        if (f.t >= 1) dp = fr[fi - 1].pair_off;
         if (f.t + 1 < f.n_t) gp = f.pair_off;
     }
+    T acc[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) acc[k] = T(0);
 
-    T acc = T(0);
     if (gp >= 0) {
         const T* rg = r + gp;
         const T* vxg = v + 2 * gp;
@@ -172,8 +179,7 @@ __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles
                 int x0, y0;
                 T fx, fy;
                 source_cell<T, INTERP>(sx, sy, vxg[p], vyg[p], nx, ny, x0, y0, fx, fy);
-                s_x0[i] = x0;
-                s_y0[i] = y0;
+                s_cell[i] = (unsigned)x0 | ((unsigned)y0 << 16);
                 s_fx[i] = fx;
                 s_fy[i] = fy;
                 s_val[i] = rg[p];
@@ -198,41 +204,62 @@ __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles
                 atomicMax(&s_d[3], dyx);
             }
             __syncthreads();
-            if (inside && s_d[0] <= s_d[1]) {
+            if (col_in && qy0 < ny && s_d[0] <= s_d[1]) {
+                const int qy_last = min(qy0 + RPT - 1, ny - 1);
                 const int px_lo = max(qx - 1 - s_d[1], sx0), px_hi = min(qx - s_d[0], sx1);
-                const int py_lo = max(qy - 1 - s_d[3], sy0), py_hi = min(qy - s_d[2], sy1);
+                const int py_lo = max(qy0 - 1 - s_d[3], sy0), py_hi = min(qy_last - s_d[2], sy1);
                 for (int py = py_lo; py <= py_hi; ++py) {
                     const int row = (py - sy0) * sw - sx0;
                     for (int px = px_lo; px <= px_hi; ++px) {
                         const int i = row + px;
-                        T wx, wy;
-                        if (!corner_weight(s_x0[i], s_fx[i], qx, wx)) continue;
-                        if (!corner_weight(s_y0[i], s_fy[i], qy, wy)) continue;
-                        acc += wx * wy * s_val[i];
+                        const unsigned cell = s_cell[i];
+                        const int cx = (int)(cell & 0xffffu), cy = (int)(cell >> 16);
+                        if ((unsigned)(cx - (qx - 1)) > 1u) continue;
+                        const int ky = cy - qy0;  // row offset of the cell's upper corner
+                        if (ky < -1 || ky >= RPT) continue;
+                        const T wx = cx == qx ? T(1) - s_fx[i] : s_fx[i];
+                        const T fy = s_fy[i], val = s_val[i];
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) {
+                            if (cy == qy0 + k) acc[k] += wx * (T(1) - fy) * val;
+                            else if (cy + 1 == qy0 + k) acc[k] += wx * fy * val;
+                        }
                     }
                 }
             }
-        } else if (inside) {
+        } else if (col_in) {
             // Large displacements: scan the full window in global memory (same order).
-            const int py_lo = max(qy - R, 0), py_hi = min(qy + R, ny - 1);
-            const int px_lo = max(qx - R, 0), px_hi = min(qx + R, nx - 1);
-            for (int py = py_lo; py <= py_hi; ++py)
-                for (int px = px_lo; px <= px_hi; ++px) {
-                    const int64_t p = (int64_t)py * nx + px;
-                    int x0, y0;
-                    T fx, fy;
-                    source_cell<T, INTERP>(px, py, vxg[p], vyg[p], nx, ny, x0, y0, fx, fy);
-                    T wx, wy;
-                    if (!corner_weight(x0, fx, qx, wx)) continue;
-                    if (!corner_weight(y0, fy, qy, wy)) continue;
-                    acc += wx * wy * rg[p];
-                }
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const int qy = qy0 + k;
+                if (qy >= ny) break;
+                const int py_lo = max(qy - R, 0), py_hi = min(qy + R, ny - 1);
+                const int px_lo = max(qx - R, 0), px_hi = min(qx + R, nx - 1);
+                for (int py = py_lo; py <= py_hi; ++py)
+                    for (int px = px_lo; px <= px_hi; ++px) {
+                        const int64_t p = (int64_t)py * nx + px;
+                        int x0, y0;
+                        T fx, fy;
+                        source_cell<T, INTERP>(px, py, vxg[p], vyg[p], nx, ny, x0, y0, fx, fy);
+                        T wx, wy;
+                        if (!corner_weight(x0, fx, qx, wx)) continue;
+                        if (!corner_weight(y0, fy, qy, wy)) continue;
+                        acc[k] += wx * wy * rg[p];
+                    }
+            }
         }
     }
-    if (!inside) return;
-    T* uo = u + f.off + q;
-    const T val = acc + direct;
-    *uo = accumulate ? *uo + val : val;
+    if (!col_in) return;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int qy = qy0 + k;
+        if (qy >= ny) break;
+        const int64_t q = (int64_t)qy * nx + qx;
+        const T direct = dp >= 0 ? -r[dp + q] : T(0);
+        T* uo = u + f.off + q;
+        const T val = acc[k] + direct;
+        *uo = accumulate ? *uo + val : val;
+    }
 }
 
 template <class T>
@@ -300,7 +327,7 @@ void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out) 
 
 const TileShape kFlowShapes[] = {{64, 4, 0}, {32, 8, 0}, {128, 2, 0}, {16, 16, 0}};
 const int kFlowCandidates = sizeof(kFlowShapes) / sizeof(kFlowShapes[0]);
-const TileShape kFlowAdjShapes[] = {{32, 8, 0}, {64, 4, 0}, {16, 16, 0}};
+const TileShape kFlowAdjShapes[] = {{64, 16, 0}, {32, 32, 0}, {64, 8, 0}, {32, 8, 0}};
 const int kFlowAdjCandidates = sizeof(kFlowAdjShapes) / sizeof(kFlowAdjShapes[0]);
 
 template <class T, int INTERP>
@@ -312,9 +339,10 @@ static auto flow_fwd_kernel(int choice) {
 }
 template <class T, int INTERP>
 static auto flow_adj_kernel(int choice) {
-    return choice == 0 ? k_flow_adj<T, INTERP, 32, 8>
-           : choice == 1 ? k_flow_adj<T, INTERP, 64, 4>
-                         : k_flow_adj<T, INTERP, 16, 16>;
+    return choice == 0 ? k_flow_adj<T, INTERP, 64, 16>
+           : choice == 1 ? k_flow_adj<T, INTERP, 32, 32>
+           : choice == 2 ? k_flow_adj<T, INTERP, 64, 8>
+                         : k_flow_adj<T, INTERP, 32, 8>;
 }
 
 void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r,
@@ -366,7 +394,7 @@ void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const v
         rad = static_cast<int32_t*>(c.work("flow_radius", 256));
         launch_flow_radius(c, g, dt, v, rad);
     }
-    if (choice < 0) choice = g.choice("flow_adj", dt);
+    if (choice < 0) choice = g.choice("flow_adj", dt, 3);
     MMOF_CHECK(choice >= 0 && choice < kFlowAdjCandidates, MMOF_ERR_INVALID, "flow adjoint tile candidate out of range");
     const TileShape sh = kFlowAdjShapes[choice];
     const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);

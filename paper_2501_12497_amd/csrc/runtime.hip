@@ -29,7 +29,8 @@ static void build_geom(Geom& g, const mmof_stack* s, hipStream_t st) {
     for (int i = 0; i < g.n_seq; ++i) {
         MMOF_CHECK(g.n_t[i] >= 1 && g.ny[i] >= 2 && g.nx[i] >= 2, MMOF_ERR_SHAPE,
                    "sequence " + std::to_string(i) + " needs n_t >= 1, ny >= 2, nx >= 2");
-        MMOF_CHECK(g.ny[i] <= (1 << 20) && g.nx[i] <= (1 << 20), MMOF_ERR_SHAPE, "frame too large");
+        // (the flow adjoint packs a pixel's two coordinates into 16 bits each)
+        MMOF_CHECK(g.ny[i] <= 65535 && g.nx[i] <= 65535, MMOF_ERR_SHAPE, "frame too large (at most 65535 pixels a side)");
         g.seq_off.push_back(off);
         g.max_ny = std::max(g.max_ny, g.ny[i]);
         g.max_nx = std::max(g.max_nx, g.nx[i]);

@@ -83,7 +83,7 @@ def test_every_tile_candidate_gives_the_same_solve():
     ref = _solve(B, plan, b, delta, ut, "f64", 0)
     x = torch.as_tensor(np.random.default_rng(5).standard_normal(plan.n), device="cuda")
     ax0 = B.apply_A(plan, x)
-    n_cand = {"blur": 5, "grad_fwd": 4, "grad_adj": 4, "flow_fwd": 4, "flow_adj": 3}
+    n_cand = {"blur": 5, "grad_fwd": 4, "grad_adj": 4, "flow_fwd": 4, "flow_adj": 4}
     for c in range(1, 5):
         for k, nc in n_cand.items():
             plan.set_tile(k, min(c, nc - 1), torch.float64)
