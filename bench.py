@@ -216,6 +216,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the operator table at 1024x1024x64")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default tile shapes")
     ap.add_argument("--graph", action="store_true",
                     help="replay the fixed launch sequences of each iteration from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -236,6 +237,9 @@ def main():
     ctx = plan.ctx
     prm = solve_params(wl, "f32", graph=a.graph)
     log(f"workload {wl.name}: n={plan.n} m={plan.m} params={prm}")
+    if not a.no_autotune:  # tile shapes of this plan's stencil kernels, once, before any timing
+        for dt in (torch.float32, torch.float64):
+            log(f"autotune {dt}: {plan.autotune(dt)}")
 
     def step():
         return B.solve_joint(plan, b, delta, u_true=u_true, **prm)

@@ -128,7 +128,9 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
         // angles, whose tiny slope puts the crossings far away, give in-range integers)
         const double dn = (double)nrow;
         auto clamp_row = [&](double x) { return (int)fmin(fmax(x, 0.0), dn); };
-        if (step != 0.0) {
+        if (r_hi - r_lo < 48) {
+            // short row blocks: the bookkeeping below would cost more than it saves
+        } else if (step != 0.0) {
             const double ra = row_of(-1.5), rb = row_of((double)ncol + 0.5);
             const double t_lo = fmin(ra, rb), t_hi = fmax(ra, rb);
             r_lo = max(r_lo, clamp_row(floor(t_lo) - 1.0));
@@ -151,6 +153,13 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
             acc += (a0 + a1) + (a2 + a3);
         }
         for (; r < in_hi; ++r) acc += hat_row_inner(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+        for (; r < r_hi - 3; r += 4) {
+            const T a0 = hat_row(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+            const T a1 = hat_row(img + (int64_t)(r + 1) * ncol, ncol, fma((double)(r + 1), step, xs0), aa);
+            const T a2 = hat_row(img + (int64_t)(r + 2) * ncol, ncol, fma((double)(r + 2), step, xs0), aa);
+            const T a3 = hat_row(img + (int64_t)(r + 3) * ncol, ncol, fma((double)(r + 3), step, xs0), aa);
+            acc += (a0 + a1) + (a2 + a3);
+        }
         for (; r < r_hi; ++r) acc += hat_row(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
     }
     part[wave][lane] = acc;
