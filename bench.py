@@ -118,6 +118,8 @@ def operators_large(B, torch, reps=5):
     gx, gy = B.apply_grad(stack, u)
     r = B.apply_flow_op(stack, _lib.MMOF_FLOW_FWD, 1, 0, u, v)
     w = torch.zeros_like(v)
+    tuned = plan.autotune(torch.float32)
+    log(f"large autotune: {tuned}")
     ops = {
         "radon_fwd": lambda: B.apply_A(plan, u, out=b),
         "radon_adj": lambda: B.apply_At(plan, b),
@@ -148,7 +150,38 @@ def operators_large(B, torch, reps=5):
         table[name] = ent
     del plan
     return {"workload": "large1024x1024x64: 12 moving/rotating ellipses, 90 golden-angle-shifted angles/frame, "
-                        "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "kernels": table}
+                        "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "tiles": tuned, "kernels": table}
+
+
+def large_solve(B, torch):
+    """Time to solution on the 1024x1024x64 workload: the FP64-operator solve's RRE after its
+    k_max iterations (x 1.01) is the target; FP64, FP32 and FP32 + FP64-refined solves are
+    timed to it (wall clock of solve_joint, inputs resident)."""
+    from synth import cfg_large1024
+    wl = cfg_large1024()
+    stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
+    p = wl.params
+    prm = dict(ell=p["ell"], k_max=p["k_max"], tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
+               eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"])
+    for dt in (torch.float32, torch.float64):
+        log(f"large autotune {dt}: {plan.autotune(dt)}")
+    out = {"workload": "large1024x1024x64", "n_pixels": plan.n, "n_data": plan.m, "params": prm}
+    t0 = time.perf_counter()
+    ref = B.solve_joint(plan, b, delta, u_true=u_true, op_dtype="f64", **prm)
+    torch.cuda.synchronize()
+    out["f64_full"] = {"seconds": time.perf_counter() - t0, "iters": ref.iters, "rre": ref.rre[-1]}
+    target = ref.rre[-1] * 1.01
+    out["rre_target"] = target
+    for name, kw in (("f64", dict(op_dtype="f64")), ("f32", dict(op_dtype="f32")),
+                     ("f32+refine", dict(op_dtype="f32", refine_iters=REFINE_ITERS))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = B.solve_joint(plan, b, delta, u_true=u_true, rre_target=target, **dict(prm, **kw))
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "iters": r.iters, "rre": r.rre[-1],
+                     "reached": bool(r.rre[-1] <= target)}
+        log(f"large {name}: {out[name]}")
+    return out
 
 
 def solve_params(wl, op, graph=True):
@@ -217,6 +250,8 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the operator table at 1024x1024x64")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tile shapes")
+    ap.add_argument("--large-solve", action="store_true",
+                    help="also time FP64 / FP32 / FP32+refined solves of the 1024x1024x64 workload")
     ap.add_argument("--graph", action="store_true",
                     help="replay the fixed launch sequences of each iteration from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -323,6 +358,10 @@ def main():
         large = operators_large(B, torch)
         log(f"operators at 1024x1024x64: {large['kernels']}")
 
+    big = None
+    if a.large_solve:
+        big = large_solve(B, torch)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(wl)
@@ -349,6 +388,8 @@ def main():
         "cpu_baseline": cpu,
         "operators_large": large,
     }
+    if big is not None:
+        out["time_to_solution_large"] = big
     print(json.dumps(out))
 
 

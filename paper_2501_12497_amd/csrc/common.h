@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -109,6 +110,9 @@ struct Geom {
     int64_t pair_px = 0;    // pixels over all pairs
     int64_t gx_len = 0, gy_len = 0;
     int32_t max_ny = 0, max_nx = 0;
+    // every frame width is a multiple of 4, so frame, pair and row starts (and those of the
+    // gy blocks) fall on 4-element boundaries: the stencil kernels may move 4 pixels at once
+    bool vec4 = false;
     std::vector<FrameInfo> frames;       // host copy
     std::vector<int64_t> seq_off;        // pixel offset per sequence
     DeviceBuffer d_frames;               // FrameInfo[n_frames]
@@ -239,6 +243,13 @@ void dispatch(int dt, F&& f) {
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// All pointers aligned to `bytes` (null pointers pass).
+inline bool aligned_to(size_t bytes, std::initializer_list<const void*> ptrs) {
+    for (const void* p : ptrs)
+        if (reinterpret_cast<uintptr_t>(p) % bytes) return false;
+    return true;
+}
 
 // Grid for a 1-D grid-stride launch.
 inline dim3 grid_for(int64_t n, int block, int cap = 65536) {

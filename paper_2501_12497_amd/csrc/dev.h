@@ -60,6 +60,25 @@ __device__ __forceinline__ int round_clip(int x, T v, int n) {
     return r < 0 ? 0 : (r > n - 1 ? n - 1 : r);
 }
 
+// Four consecutive values moved as one 16-byte (FP32) or two 16-byte (FP64) accesses; the
+// address must be aligned to 4 elements.
+template <class T>
+struct alignas(4 * sizeof(T)) Quad {
+    T v[4];
+};
+template <class T>
+__device__ __forceinline__ Quad<T> ld4(const T* p) {
+    return *reinterpret_cast<const Quad<T>*>(p);
+}
+template <class T>
+__device__ __forceinline__ void st4(T* p, const Quad<T>& q) {
+    *reinterpret_cast<Quad<T>*>(p) = q;
+}
+template <class T>
+__device__ __forceinline__ Quad<T> zero4() {
+    return Quad<T>{{T(0), T(0), T(0), T(0)}};
+}
+
 // Half-sample-symmetric mirror of an index into [0, n): -1 -> 0, n -> n-1.
 __device__ __forceinline__ int mirror(int i, int n) {
     if (i < 0) i = -i - 1;

@@ -87,6 +87,71 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols(const Tile* __restrict__ 
     }
 }
 
+// Vector forms of the two kernels above, for stacks whose frame widths are multiples of 4:
+// each thread owns 4 consecutive pixels of one row of a (4*LW)-pixel-wide tile, so flows,
+// the subtracted frame and the output move as 4-element vectors (16 bytes per FP32 access);
+// the bilinear samples stay single loads.  Values equal those of the scalar kernels.
+template <class T, int INTERP, int LW>
+__global__ __launch_bounds__(256) void k_flow_fwd4(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                   const T* __restrict__ u, const T* __restrict__ v,
+                                                   T* __restrict__ r, int direction) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + 4 * (int)(threadIdx.x % LW);
+    const int y = tl.y0 + (int)(threadIdx.x / LW);
+    if (x >= f.nx || y >= f.ny) return;
+    const int64_t np = (int64_t)f.nx * f.ny;
+    const int64_t p = (int64_t)y * f.nx + x;
+    const T* ut = u + f.off;
+    const T* ut1 = ut + np;
+    const T* vf = v + 2 * f.pair_off;
+    const Quad<T> vx = ld4(vf + p), vy = ld4(vf + np + p);
+    const T* src = direction > 0 ? ut1 : ut;
+    const Quad<T> sub = ld4((direction > 0 ? ut : ut1) + p);
+    Quad<T> o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        o.v[j] = warp_sample<T, INTERP>(src, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - sub.v[j];
+    st4(r + f.pair_off + p, o);
+}
+
+template <class T, int INTERP, int LW>
+__global__ __launch_bounds__(256) void k_flow_fwd_cols4(const Tile* __restrict__ tiles,
+                                                        const FrameInfo* __restrict__ fr,
+                                                        const double* __restrict__ U, int64_t ldu,
+                                                        const T* __restrict__ v, const T* __restrict__ vr,
+                                                        T* __restrict__ out, int64_t ldo, int64_t oF, int64_t oR) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + 4 * (int)(threadIdx.x % LW);
+    const int y = tl.y0 + (int)(threadIdx.x / LW);
+    if (x >= f.nx || y >= f.ny) return;
+    const int64_t np = (int64_t)f.nx * f.ny;
+    const int64_t p = (int64_t)y * f.nx + x;
+    const double* ut = U + (int64_t)blockIdx.y * ldu + f.off;
+    const double* ut1 = ut + np;
+    T* o = out + (int64_t)blockIdx.y * ldo;
+    const Quad<double> a = ld4(ut + p), b = ld4(ut1 + p);
+    {
+        const T* vf = v + 2 * f.pair_off;
+        const Quad<T> vx = ld4(vf + p), vy = ld4(vf + np + p);
+        Quad<T> q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            q.v[j] = warp_sample<T, INTERP, double>(ut1, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)a.v[j];
+        st4(o + oF + f.pair_off + p, q);
+    }
+    if (vr) {
+        const T* vb = vr + 2 * f.pair_off;
+        const Quad<T> vx = ld4(vb + p), vy = ld4(vb + np + p);
+        Quad<T> q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            q.v[j] = warp_sample<T, INTERP, double>(ut, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)b.v[j];
+        st4(o + oR + f.pair_off + p, q);
+    }
+}
+
 // Cell of a source pixel: clipped floor coordinates and fractions (0 for INTERP 1).
 template <class T, int INTERP>
 __device__ __forceinline__ void source_cell(int sx, int sy, T vx, T vy, int nx, int ny, int& x0, int& y0, T& fx,
@@ -329,6 +394,20 @@ const TileShape kFlowShapes[] = {{64, 4, 0}, {32, 8, 0}, {128, 2, 0}, {16, 16, 0
 const int kFlowCandidates = sizeof(kFlowShapes) / sizeof(kFlowShapes[0]);
 const TileShape kFlowAdjShapes[] = {{64, 16, 0}, {32, 32, 0}, {64, 8, 0}, {32, 8, 0}};
 const int kFlowAdjCandidates = sizeof(kFlowAdjShapes) / sizeof(kFlowAdjShapes[0]);
+// vector-form candidates of the forward operator: lanes per tile row (4 pixels each) and
+// waves per workgroup
+struct Flow4Shape {
+    int lw, nw;
+    int tw() const { return 4 * lw; }
+    int th() const { return 64 * nw / lw; }
+};
+static const Flow4Shape kFlow4Shapes[] = {{64, 4}, {32, 4}, {64, 2}, {32, 2}};
+static_assert(sizeof(kFlow4Shapes) / sizeof(kFlow4Shapes[0]) == sizeof(kFlowShapes) / sizeof(kFlowShapes[0]),
+              "both forms offer the same number of tile candidates");
+
+TileShape flow_tile(const Geom& g, int choice) {
+    return g.vec4 ? TileShape{kFlow4Shapes[choice].tw(), kFlow4Shapes[choice].th(), 0} : kFlowShapes[choice];
+}
 
 template <class T, int INTERP>
 static auto flow_fwd_kernel(int choice) {
@@ -336,6 +415,10 @@ static auto flow_fwd_kernel(int choice) {
            : choice == 1 ? k_flow_fwd<T, INTERP, 32, 8>
            : choice == 2 ? k_flow_fwd<T, INTERP, 128, 2>
                          : k_flow_fwd<T, INTERP, 16, 16>;
+}
+template <class T, int INTERP>
+static auto flow_fwd4_kernel(int choice) {
+    return kFlow4Shapes[choice].lw == 64 ? k_flow_fwd4<T, INTERP, 64> : k_flow_fwd4<T, INTERP, 32>;
 }
 template <class T, int INTERP>
 static auto flow_adj_kernel(int choice) {
@@ -348,16 +431,24 @@ static auto flow_adj_kernel(int choice) {
 void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r,
                      int choice) {
     if (g.n_pairs == 0) return;
-    if (choice < 0) choice = g.choice("flow_fwd", dt);
+    if (choice < 0) choice = g.choice("flow_fwd", dt, 1);
     MMOF_CHECK(choice >= 0 && choice < kFlowCandidates, MMOF_ERR_INVALID, "flow tile candidate out of range");
-    const TileShape sh = kFlowShapes[choice];
-    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_fwd", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
-        auto k = interp == MMOF_INTERP_ROUND ? flow_fwd_kernel<T, 1>(choice) : flow_fwd_kernel<T, 0>(choice);
-        hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
-                           (const T*)u, (const T*)v, (T*)r, direction);
+        if (g.vec4 && aligned_to(4 * sizeof(T), {u, v, r})) {
+            const Flow4Shape sh = kFlow4Shapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
+            auto k = interp == MMOF_INTERP_ROUND ? flow_fwd4_kernel<T, 1>(choice) : flow_fwd4_kernel<T, 0>(choice);
+            hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(64 * sh.nw), 0, c.stream, tl.buf.as<Tile>(),
+                               g.dframes(), (const T*)u, (const T*)v, (T*)r, direction);
+        } else {
+            const TileShape sh = kFlowShapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
+            auto k = interp == MMOF_INTERP_ROUND ? flow_fwd_kernel<T, 1>(choice) : flow_fwd_kernel<T, 0>(choice);
+            hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
+                               (const T*)u, (const T*)v, (T*)r, direction);
+        }
         MMOF_LAUNCH_CHECK();
     });
 }
@@ -365,24 +456,40 @@ void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const v
 void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const double* U, int64_t ldu, int K, const void* v,
                           const void* vr, void* out, int64_t ldo, int64_t oF, int64_t oR) {
     if (g.n_pairs == 0 || K <= 0) return;
-    const int choice = g.choice("flow_fwd", dt);
-    const TileShape sh = kFlowShapes[choice];
-    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
+    const int choice = g.choice("flow_fwd", dt, 1);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_fwd_cols", (vr ? 2.0 : 1.0) * K * (4.0 * sizeof(T) + 16.0) * g.pair_px,
                       (vr ? 2.0 : 1.0) * K * 12.0 * g.pair_px);
-        auto pick = [&](auto interp_tag) {
-            constexpr int I = decltype(interp_tag)::value;
-            return choice == 0 ? k_flow_fwd_cols<T, I, 64, 4>
-                   : choice == 1 ? k_flow_fwd_cols<T, I, 32, 8>
-                   : choice == 2 ? k_flow_fwd_cols<T, I, 128, 2>
-                                 : k_flow_fwd_cols<T, I, 16, 16>;
-        };
-        auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
-                                             : pick(std::integral_constant<int, 0>{});
-        hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo, oF, oR);
+        const bool v4 = g.vec4 && ldu % 4 == 0 && ldo % 4 == 0 && oF % 4 == 0 && oR % 4 == 0 &&
+                        aligned_to(4 * sizeof(double), {U}) && aligned_to(4 * sizeof(T), {v, vr, out});
+        if (v4) {
+            const Flow4Shape sh = kFlow4Shapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
+            auto pick = [&](auto interp_tag) {
+                constexpr int I = decltype(interp_tag)::value;
+                return sh.lw == 64 ? k_flow_fwd_cols4<T, I, 64> : k_flow_fwd_cols4<T, I, 32>;
+            };
+            auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
+                                                 : pick(std::integral_constant<int, 0>{});
+            hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(64 * sh.nw), 0, c.stream,
+                               tl.buf.as<Tile>(), g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo, oF,
+                               oR);
+        } else {
+            const TileShape sh = kFlowShapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
+            auto pick = [&](auto interp_tag) {
+                constexpr int I = decltype(interp_tag)::value;
+                return choice == 0 ? k_flow_fwd_cols<T, I, 64, 4>
+                       : choice == 1 ? k_flow_fwd_cols<T, I, 32, 8>
+                       : choice == 2 ? k_flow_fwd_cols<T, I, 128, 2>
+                                     : k_flow_fwd_cols<T, I, 16, 16>;
+            };
+            auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
+                                                 : pick(std::integral_constant<int, 0>{});
+            hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                               g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo, oF, oR);
+        }
         MMOF_LAUNCH_CHECK();
     });
 }

@@ -88,8 +88,132 @@ __global__ __launch_bounds__(256) void k_grad_adj(const Tile* __restrict__ tiles
     }
 }
 
+// Vector form, for stacks whose frame widths are multiples of 4: each thread owns 4
+// consecutive pixels of RPT consecutive rows, so image and gy rows move as whole 16-byte
+// (FP32) or 2 x 16-byte (FP64) accesses and every wave keeps 4x more bytes in flight than
+// with one pixel per lane.  A row of the tile is LW lanes (4*LW pixels) wide; gx rows
+// (stride nx-1, not 4-aligned) move as single values.  The pixel right of a thread's four
+// (forward) or the gx value left of them (adjoint) comes from the neighbouring lane, or from
+// memory at the edge of a lane row.  Values and summation order equal those of the scalar
+// kernels above.
+template <class T, int LW, int RPT>
+__global__ __launch_bounds__(256) void k_grad_fwd4(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                   const T* __restrict__ u, const T* __restrict__ wx,
+                                                   const T* __restrict__ wy, T* __restrict__ gx, T* __restrict__ gy) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int lx = (int)(threadIdx.x % LW);
+    const int x = tl.x0 + 4 * lx;
+    const int y0 = tl.y0 + (int)(threadIdx.x / LW) * RPT;
+    const int nx = f.nx, ny = f.ny;
+    if (x >= nx || y0 >= ny) return;  // x < nx implies x + 3 < nx
+    const T* uf = u + f.off;
+    Quad<T> c = ld4(uf + (int64_t)y0 * nx + x);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int y = y0 + k;
+        if (y >= ny) break;
+        const int64_t p = (int64_t)y * nx + x;
+        // pixel x + 4: the next lane's first pixel (same row, live whenever x + 4 < nx)
+        T right = __shfl_down(c.v[0], 1);
+        if (lx == LW - 1 && x + 4 < nx) right = uf[p + 4];
+        const int64_t o = f.gx_off + (int64_t)y * (nx - 1) + x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j == 3 && x + 4 >= nx) break;
+            const T d = (j < 3 ? c.v[j + 1] : right) - c.v[j];
+            gx[o + j] = wx ? wx[o + j] * d : d;
+        }
+        Quad<T> below = zero4<T>();
+        if (y < ny - 1) {
+            below = ld4(uf + p + nx);
+            const int64_t og = f.gy_off + p;
+            Quad<T> d;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) d.v[j] = below.v[j] - c.v[j];
+            if (wy) {
+                const Quad<T> w = ld4(wy + og);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) d.v[j] = w.v[j] * d.v[j];
+            }
+            st4(gy + og, d);
+        }
+        c = below;
+    }
+}
+
+template <class T, int LW, int RPT>
+__global__ __launch_bounds__(256) void k_grad_adj4(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                   const T* __restrict__ gx, const T* __restrict__ gy,
+                                                   const T* __restrict__ wx, const T* __restrict__ wy,
+                                                   T* __restrict__ u, int accumulate) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int lx = (int)(threadIdx.x % LW);
+    const int x = tl.x0 + 4 * lx;
+    const int y0 = tl.y0 + (int)(threadIdx.x / LW) * RPT;
+    const int nx = f.nx, ny = f.ny;
+    if (x >= nx || y0 >= ny) return;
+    const int64_t ry = f.gy_off;
+    auto wgy = [&](int64_t o) {
+        Quad<T> q = ld4(gy + o);
+        if (wy) {
+            const Quad<T> w = ld4(wy + o);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q.v[j] = w.v[j] * q.v[j];
+        }
+        return q;
+    };
+    // weighted gy of the row above the first row
+    Quad<T> up = zero4<T>();
+    if (y0 > 0) up = wgy(ry + (int64_t)(y0 - 1) * nx + x);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int y = y0 + k;
+        if (y >= ny) break;
+        const int64_t rx = f.gx_off + (int64_t)y * (nx - 1) + x;  // gx at (x, y)
+        T g[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            g[j] = T(0);
+            if (j < 3 || x + 4 < nx) g[j] = wx ? wx[rx + j] * gx[rx + j] : gx[rx + j];
+        }
+        // gx at x - 1: the previous lane's last value (same row), or memory at a lane-row edge
+        T left = __shfl_up(g[3], 1);
+        if (lx == 0) left = x > 0 ? (wx ? wx[rx - 1] * gx[rx - 1] : gx[rx - 1]) : T(0);
+        Quad<T> here = zero4<T>();
+        if (y < ny - 1) here = wgy(ry + (int64_t)y * nx + x);
+        const int64_t p = f.off + (int64_t)y * nx + x;
+        Quad<T> out = accumulate ? ld4(u + p) : zero4<T>();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            T acc = T(0);
+            if (x + j > 0) acc += j == 0 ? left : g[j - 1];
+            if (x + j < nx - 1) acc -= g[j];
+            if (y > 0) acc += up.v[j];
+            if (y < ny - 1) acc -= here.v[j];
+            out.v[j] = accumulate ? out.v[j] + acc : acc;
+        }
+        st4(u + p, out);
+        up = here;
+    }
+}
+
 const TileShape kGradShapes[] = {{64, 16, 0}, {64, 8, 0}, {64, 4, 0}, {32, 32, 0}};
 const int kGradCandidates = sizeof(kGradShapes) / sizeof(kGradShapes[0]);
+// vector-form candidates: lanes per tile row, rows per thread, waves per workgroup
+struct Grad4Shape {
+    int lw, rpt, nw;
+    int tw() const { return 4 * lw; }
+    int th() const { return 64 * nw / lw * rpt; }
+};
+static const Grad4Shape kGrad4Shapes[] = {{64, 1, 4}, {64, 2, 4}, {32, 1, 2}, {32, 1, 4}};
+static_assert(sizeof(kGrad4Shapes) / sizeof(kGrad4Shapes[0]) == sizeof(kGradShapes) / sizeof(kGradShapes[0]),
+              "both forms offer the same number of tile candidates");
+
+TileShape grad_tile(const Geom& g, int choice) {
+    return g.vec4 ? TileShape{kGrad4Shapes[choice].tw(), kGrad4Shapes[choice].th(), 0} : kGradShapes[choice];
+}
 
 template <class T>
 static auto grad_fwd_kernel(int choice) {
@@ -105,18 +229,41 @@ static auto grad_adj_kernel(int choice) {
            : choice == 2 ? k_grad_adj<T, 64, 4>
                          : k_grad_adj<T, 32, 32>;
 }
+template <class T>
+static auto grad_fwd4_kernel(int choice) {
+    return choice == 0 ? k_grad_fwd4<T, 64, 1>
+           : choice == 1 ? k_grad_fwd4<T, 64, 2>
+                         : k_grad_fwd4<T, 32, 1>;  // candidates 2 and 3 differ in waves only
+}
+template <class T>
+static auto grad_adj4_kernel(int choice) {
+    return choice == 0 ? k_grad_adj4<T, 64, 1>
+           : choice == 1 ? k_grad_adj4<T, 64, 2>
+                         : k_grad_adj4<T, 32, 1>;
+}
 
 void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy,
                      int choice) {
     if (choice < 0) choice = g.choice("grad_fwd", dt, 2);
     MMOF_CHECK(choice >= 0 && choice < kGradCandidates, MMOF_ERR_INVALID, "grad tile candidate out of range");
-    const TileShape sh = kGradShapes[choice];
-    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "grad_fwd", 3.0 * sizeof(T) * g.n, 2.0 * g.n);
-        hipLaunchKernelGGL(grad_fwd_kernel<T>(choice), dim3((unsigned)tl.count), dim3(256), 0, c.stream,
-                           tl.buf.as<Tile>(), g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx, (T*)gy);
+        // u read, gx and gy written, weights read when given
+        const double bytes = sizeof(T) * ((double)g.n + (wx ? 2.0 : 1.0) * g.gx_len + (wy ? 2.0 : 1.0) * g.gy_len);
+        ScopedTime st(&c, "grad_fwd", bytes, (wx ? 2.0 : 1.0) * g.gx_len + (wy ? 2.0 : 1.0) * g.gy_len);
+        if (g.vec4 && aligned_to(4 * sizeof(T), {u, wy, gy})) {
+            const Grad4Shape sh = kGrad4Shapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), false);
+            hipLaunchKernelGGL(grad_fwd4_kernel<T>(choice), dim3((unsigned)tl.count), dim3(64 * sh.nw), 0, c.stream,
+                               tl.buf.as<Tile>(), g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx,
+                               (T*)gy);
+        } else {
+            const TileShape sh = kGradShapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
+            hipLaunchKernelGGL(grad_fwd_kernel<T>(choice), dim3((unsigned)tl.count), dim3(256), 0, c.stream,
+                               tl.buf.as<Tile>(), g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx,
+                               (T*)gy);
+        }
         MMOF_LAUNCH_CHECK();
     });
 }
@@ -125,14 +272,25 @@ void launch_grad_adj(Ctx& c, Geom& g, int dt, const void* gx, const void* gy, co
                      void* u, bool accumulate, int choice) {
     if (choice < 0) choice = g.choice("grad_adj", dt, 2);
     MMOF_CHECK(choice >= 0 && choice < kGradCandidates, MMOF_ERR_INVALID, "grad tile candidate out of range");
-    const TileShape sh = kGradShapes[choice];
-    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "grad_adj", 3.0 * sizeof(T) * g.n, 3.0 * g.n);
-        hipLaunchKernelGGL(grad_adj_kernel<T>(choice), dim3((unsigned)tl.count), dim3(256), 0, c.stream,
-                           tl.buf.as<Tile>(), g.dframes(), (const T*)gx, (const T*)gy, (const T*)wx, (const T*)wy,
-                           (T*)u, accumulate ? 1 : 0);
+        // gx and gy (and weights) read, u written (and read when accumulating)
+        const double bytes =
+            sizeof(T) * ((accumulate ? 2.0 : 1.0) * g.n + (wx ? 2.0 : 1.0) * g.gx_len + (wy ? 2.0 : 1.0) * g.gy_len);
+        ScopedTime st(&c, "grad_adj", bytes, 3.0 * g.n);
+        if (g.vec4 && aligned_to(4 * sizeof(T), {u, gy, wy})) {
+            const Grad4Shape sh = kGrad4Shapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), false);
+            hipLaunchKernelGGL(grad_adj4_kernel<T>(choice), dim3((unsigned)tl.count), dim3(64 * sh.nw), 0, c.stream,
+                               tl.buf.as<Tile>(), g.dframes(), (const T*)gx, (const T*)gy, (const T*)wx,
+                               (const T*)wy, (T*)u, accumulate ? 1 : 0);
+        } else {
+            const TileShape sh = kGradShapes[choice];
+            const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
+            hipLaunchKernelGGL(grad_adj_kernel<T>(choice), dim3((unsigned)tl.count), dim3(256), 0, c.stream,
+                               tl.buf.as<Tile>(), g.dframes(), (const T*)gx, (const T*)gy, (const T*)wx,
+                               (const T*)wy, (T*)u, accumulate ? 1 : 0);
+        }
         MMOF_LAUNCH_CHECK();
     });
 }

@@ -87,6 +87,90 @@ __global__ __launch_bounds__(512) void k_of_derivs_lds(const Tile* __restrict__ 
     Ip[2 * np + p] = It / (box * box);
 }
 
+// Vector form for stacks whose frame widths are multiples of 4 (and dr <= 4): a workgroup of
+// DV_LW x DV_TH threads owns a (4*DV_LW) x DV_TH tile; both frames are staged with a halo of
+// one 4-pixel vector left and right and DR rows above and below, moved as whole vectors (a
+// vector beyond a frame edge is the mirror image of the edge vector, reversed).  Each thread
+// forms 4 outputs from register copies of the 4 + 2*DR staged values of each row it needs;
+// per output the sums run in the order of k_of_derivs, so the values are identical.
+static constexpr int DV_LW = 32, DV_TH = 8;
+
+template <class T, int DR>
+__global__ __launch_bounds__(DV_LW * DV_TH) void k_of_derivs4(const Tile* __restrict__ tiles,
+                                                              const FrameInfo* __restrict__ fr,
+                                                              const T* __restrict__ u, T* __restrict__ I) {
+    constexpr int SW = 4 * DV_LW + 8, SH = DV_TH + 2 * DR;  // staged columns start 4 left of the tile
+    constexpr int NQ = SW / 4;                              // vectors per staged row
+    constexpr int W = 4 + 2 * DR;                           // values a thread needs per row
+    __shared__ Quad<T> sa[SH][NQ], sb[SH][NQ];
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int nx = f.nx, ny = f.ny;
+    const int64_t np = (int64_t)nx * ny;
+    const T* a = u + f.off;  // frame t
+    const T* b = a + np;     // frame t+1
+    for (int i = threadIdx.x; i < SH * NQ; i += DV_LW * DV_TH) {
+        const int ly = i / NQ, lq = i % NQ;
+        const int yy = tl.y0 - DR + ly, xs = tl.x0 - 4 + 4 * lq;  // first pixel of the vector
+        if (yy >= ny + DR || xs >= nx + 4) continue;               // beyond the frame's own halo
+        const int64_t row = (int64_t)mirror(yy, ny) * nx;
+        if (xs >= 0 && xs < nx) {
+            sa[ly][lq] = ld4(a + row + xs);
+            sb[ly][lq] = ld4(b + row + xs);
+        } else {
+            // xs = -4 mirrors the vector at 0, xs = nx the one at nx - 4, both reversed
+            const int ms = xs < 0 ? 0 : nx - 4;
+            const Quad<T> qa = ld4(a + row + ms), qb = ld4(b + row + ms);
+            sa[ly][lq] = Quad<T>{{qa.v[3], qa.v[2], qa.v[1], qa.v[0]}};
+            sb[ly][lq] = Quad<T>{{qb.v[3], qb.v[2], qb.v[1], qb.v[0]}};
+        }
+    }
+    __syncthreads();
+    const int lx = (int)(threadIdx.x % DV_LW), ty = (int)(threadIdx.x / DV_LW);
+    const int x = tl.x0 + 4 * lx, y = tl.y0 + ty;
+    if (x >= nx || y >= ny) return;
+    // staged values x - DR .. x + 3 + DR of a row (vector lx holds x - 4 .. x - 1)
+    auto row_vals = [&](const Quad<T> (*s)[NQ], int ly, T* r) {
+        const Quad<T> q0 = s[ly][lx], q1 = s[ly][lx + 1], q2 = s[ly][lx + 2];
+        const T all[12] = {q0.v[0], q0.v[1], q0.v[2], q0.v[3], q1.v[0], q1.v[1],
+                           q1.v[2], q1.v[3], q2.v[0], q2.v[1], q2.v[2], q2.v[3]};
+#pragma unroll
+        for (int c = 0; c < W; ++c) r[c] = all[4 - DR + c];
+    };
+    T Ix[4], Iy[4], It[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Ix[j] = Iy[j] = It[j] = T(0);
+    T ym[W], yp[W];  // rows y - DR and y + DR
+    row_vals(sa, ty, ym);
+    row_vals(sa, ty + 2 * DR, yp);
+#pragma unroll
+    for (int i = -DR; i <= DR; ++i) {
+        T ra[W], rb[W];
+        row_vals(sa, ty + DR + i, ra);
+        row_vals(sb, ty + DR + i, rb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Ix[j] += ra[j + 2 * DR] - ra[j];
+            Iy[j] += yp[j + DR + i] - ym[j + DR + i];
+#pragma unroll
+            for (int k = -DR; k <= DR; ++k) It[j] += rb[j + DR + k] - ra[j + DR + k];
+        }
+    }
+    const T box = T(2 * DR + 1);
+    const int64_t p = (int64_t)y * nx + x;
+    T* Ip = I + 3 * f.pair_off;
+    Quad<T> ox, oy, ot;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        ox.v[j] = Ix[j] / (box * T(2 * DR));
+        oy.v[j] = Iy[j] / (box * T(2 * DR));
+        ot.v[j] = It[j] / (box * box);
+    }
+    st4(Ip + p, ox);
+    st4(Ip + np + p, oy);
+    st4(Ip + 2 * np + p, ot);
+}
+
 // Exact 2x2 block-Jacobi sweeps for the p = q = 2 flow energy: per pixel,
 // sbar = mean of the in-image 4-neighbours, s = sbar - g (g.sbar + I_t) / (gamma d + |g|^2).
 // Up to HS_MAX block-Jacobi sweeps per launch (temporal blocking).  A workgroup owns an
@@ -235,7 +319,13 @@ void launch_of_derivs(Ctx& c, Geom& g, int dt, const void* u, void* I, int dr) {
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "of_derivs", 5.0 * sizeof(T) * g.pair_px, (4.0 * (2 * dr + 1) + 2.0 * (2 * dr + 1) * (2 * dr + 1)) * g.pair_px);
-        if (dr <= DTR_MAX) {
+        if (dr <= 4 && g.vec4 && aligned_to(4 * sizeof(T), {u, I})) {
+            const TileList& tl = g.tile_list(c.stream, 4 * DV_LW, DV_TH, true);
+            auto k = dr == 1 ? k_of_derivs4<T, 1> : dr == 2 ? k_of_derivs4<T, 2> : dr == 3 ? k_of_derivs4<T, 3>
+                                                                                        : k_of_derivs4<T, 4>;
+            hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(DV_LW * DV_TH), 0, c.stream, tl.buf.as<Tile>(),
+                               g.dframes(), (const T*)u, (T*)I);
+        } else if (dr <= DTR_MAX) {
             const TileList& tl = g.tile_list(c.stream, DTW, DTH, true);
             hipLaunchKernelGGL(k_of_derivs_lds<T>, dim3((unsigned)tl.count), dim3(512), 0, c.stream,
                                tl.buf.as<Tile>(), g.dframes(), (const T*)u, (T*)I, dr);

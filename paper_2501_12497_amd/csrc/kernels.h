@@ -9,6 +9,10 @@ namespace mmof {
 // choice (candidate 0 until the autotuner has run).
 extern const TileShape kBlurShapes[], kGradShapes[], kFlowShapes[], kFlowAdjShapes[];
 extern const int kBlurCandidates, kGradCandidates, kFlowCandidates, kFlowAdjCandidates;
+// Output tile of candidate `choice` of Psi / Psi^T and of L(v) on geometry g (the vector
+// forms, used when every frame width is a multiple of 4, have tiles of their own).
+TileShape grad_tile(const Geom& g, int choice);
+TileShape flow_tile(const Geom& g, int choice);
 
 // Psi and Psi^T (eq. L); weights optional.
 void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy,

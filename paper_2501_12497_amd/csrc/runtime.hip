@@ -58,6 +58,8 @@ static void build_geom(Geom& g, const mmof_stack* s, hipStream_t st) {
     }
     g.n = off;
     g.n_frames = (int64_t)g.frames.size();
+    g.vec4 = true;
+    for (int i = 0; i < g.n_seq; ++i) g.vec4 = g.vec4 && g.nx[i] % 4 == 0;
     g.pair_px = poff;
     g.gx_len = gx;
     g.gy_len = gy;

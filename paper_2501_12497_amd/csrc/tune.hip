@@ -8,6 +8,7 @@
 // which changes its sum by rounding only.
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "krylov.h"
@@ -37,6 +38,7 @@ static float time_launches(Ctx& c, F&& launch) {
 template <class F>
 static int pick(Ctx& c, Geom& g, const char* name, int dt, int n_cand, const TileShape* shapes, F&& launch,
                 std::string& report) {
+    // (shapes: the tile of each candidate, for the report)
     int best = 0;
     float best_ms = 0.f;
     for (int k = 0; k < n_cand; ++k) {
@@ -83,13 +85,16 @@ std::string autotune(Plan& P, int dt) {
         pick(c, g, "radon_fwd", dt, kRadonCandidates, groups,
              [&](int k) { launch_radon_fwd(c, P, dt, u, sino, k); }, rep);
     }
-    pick(c, g, "grad_fwd", dt, kGradCandidates, kGradShapes,
+    std::vector<TileShape> gsh, fsh;
+    for (int k = 0; k < kGradCandidates; ++k) gsh.push_back(grad_tile(g, k));
+    for (int k = 0; k < kFlowCandidates; ++k) fsh.push_back(flow_tile(g, k));
+    pick(c, g, "grad_fwd", dt, kGradCandidates, gsh.data(),
          [&](int k) { launch_grad_fwd(c, g, dt, u, nullptr, nullptr, gx, gy, k); }, rep);
-    pick(c, g, "grad_adj", dt, kGradCandidates, kGradShapes,
+    pick(c, g, "grad_adj", dt, kGradCandidates, gsh.data(),
          [&](int k) { launch_grad_adj(c, g, dt, gx, gy, nullptr, nullptr, o, false, k); }, rep);
     if (g.n_pairs > 0) {
         launch_flow_radius(c, g, dt, v, rad);
-        pick(c, g, "flow_fwd", dt, kFlowCandidates, kFlowShapes,
+        pick(c, g, "flow_fwd", dt, kFlowCandidates, fsh.data(),
              [&](int k) { launch_flow_fwd(c, g, dt, +1, MMOF_INTERP_BILINEAR, u, v, r, k); }, rep);
         pick(c, g, "flow_adj", dt, kFlowAdjCandidates, kFlowAdjShapes,
              [&](int k) { launch_flow_adj(c, g, dt, +1, MMOF_INTERP_BILINEAR, r, v, o, true, rad, k); }, rep);

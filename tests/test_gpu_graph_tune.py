@@ -15,18 +15,20 @@ from synth import noisy
 pytestmark = pytest.mark.gpu
 
 SIZES = [(3, 40, 70), (5, 33, 33), (2, 64, 20)]
+# widths that are multiples of 4: the stencil kernels take their vector forms
+SIZES4 = [(3, 40, 72), (5, 33, 36), (2, 64, 20)]
 
 
-def _ragged_blur_problem(B, torch, dtype):
+def _ragged_blur_problem(B, torch, dtype, sizes=SIZES):
     r = np.random.default_rng(31)
     us = []
-    for (nt, ny, nx) in SIZES:
+    for (nt, ny, nx) in sizes:
         yy, xx = np.mgrid[0:ny, 0:nx]
         cx, cy = nx * 0.4, ny * 0.5
         us.append(np.stack([(((xx - (cx + 1.5 * t)) ** 2 / 60.0 + (yy - cy) ** 2 / 30.0) <= 1.0).astype(float)
                             for t in range(nt)]))
     ut = np.concatenate([u.ravel() for u in us])
-    plan = B.plan_blur(B.Stack(SIZES), 9, 2.0)
+    plan = B.plan_blur(B.Stack(sizes), 9, 2.0)
     clean = B.apply_A(plan, torch.as_tensor(ut, device="cuda")).cpu().numpy()
     b = noisy(clean, r.standard_normal(clean.shape), 0.01)
     return plan, torch.as_tensor(b, device="cuda"), float(np.linalg.norm(b - clean)), \
@@ -40,10 +42,11 @@ def _solve(B, plan, b, delta, ut, op, use_graph, **extra):
 
 
 @pytest.mark.parametrize("op", ["f64", "f32"])
-def test_graph_replays_match_eager(op):
+@pytest.mark.parametrize("sizes", [SIZES, SIZES4], ids=["ragged", "vec4"])
+def test_graph_replays_match_eager(op, sizes):
     import torch
     from paper_2501_12497_amd import binding as B
-    plan, b, delta, ut = _ragged_blur_problem(B, torch, op)
+    plan, b, delta, ut = _ragged_blur_problem(B, torch, op, sizes)
     ref = _solve(B, plan, b, delta, ut, op, 0)
     for rep in range(3):
         got = _solve(B, plan, b, delta, ut, op, 1)
@@ -76,10 +79,11 @@ def test_graph_radon_solve_matches_eager():
         assert torch.equal(got.u, ref.u) and got.rre == ref.rre
 
 
-def test_every_tile_candidate_gives_the_same_solve():
+@pytest.mark.parametrize("sizes", [SIZES, SIZES4], ids=["ragged", "vec4"])
+def test_every_tile_candidate_gives_the_same_solve(sizes):
     import torch
     from paper_2501_12497_amd import binding as B
-    plan, b, delta, ut = _ragged_blur_problem(B, torch, "f64")
+    plan, b, delta, ut = _ragged_blur_problem(B, torch, "f64", sizes)
     ref = _solve(B, plan, b, delta, ut, "f64", 0)
     x = torch.as_tensor(np.random.default_rng(5).standard_normal(plan.n), device="cuda")
     ax0 = B.apply_A(plan, x)
@@ -94,11 +98,12 @@ def test_every_tile_candidate_gives_the_same_solve():
         plan.set_tile(k, 0, torch.float64)
 
 
-def test_autotune_report_and_errors():
+@pytest.mark.parametrize("sizes", [SIZES, SIZES4], ids=["ragged", "vec4"])
+def test_autotune_report_and_errors(sizes):
     import torch
     from paper_2501_12497_amd import binding as B
     from paper_2501_12497_amd._lib import MMOFError
-    plan, b, delta, ut = _ragged_blur_problem(B, torch, "f32")
+    plan, b, delta, ut = _ragged_blur_problem(B, torch, "f32", sizes)
     rep = plan.autotune(torch.float32)
     names = [item.split("=")[0] for item in rep.split()]
     assert names == ["blur", "grad_fwd", "grad_adj", "flow_fwd", "flow_adj"], rep

@@ -17,6 +17,11 @@ from synth import bins_for, nudge_off_kinks
 pytestmark = pytest.mark.gpu
 
 SIZES = [(3, 37, 75), (2, 20, 130), (4, 33, 33)]   # (n_t, ny, nx) per sequence
+# every width a multiple of 4: the stencil kernels take their vector forms (4 pixels per
+# lane); ragged heights and widths that end in partial tiles of every candidate, and a
+# frame one vector wide
+SIZES4 = [(3, 37, 76), (2, 21, 132), (4, 33, 36), (2, 9, 8), (2, 6, 4)]
+LAYOUTS = {"ragged": SIZES, "vec4": SIZES4}
 
 
 @pytest.fixture(scope="module")
@@ -107,37 +112,40 @@ def test_blur(B, which):
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
 @pytest.mark.parametrize("weighted", [False, True])
-def test_grad_forward_and_adjoint(B, which, weighted):
+@pytest.mark.parametrize("layout", ["ragged", "vec4"])
+def test_grad_forward_and_adjoint(B, which, weighted, layout):
     import torch
     dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    sizes = LAYOUTS[layout]
+    nseq = len(sizes)
     r = np.random.default_rng(14)
-    us = _rand_stack(15)
-    gxs = [r.standard_normal((s[0], s[1], s[2] - 1)) for s in SIZES]
-    gys = [r.standard_normal((s[0], s[1] - 1, s[2])) for s in SIZES]
+    us = _rand_stack(15, sizes)
+    gxs = [r.standard_normal((s[0], s[1], s[2] - 1)) for s in sizes]
+    gys = [r.standard_normal((s[0], s[1] - 1, s[2])) for s in sizes]
     wxs = [r.random(g.shape) for g in gxs] if weighted else None
     wys = [r.random(g.shape) for g in gys] if weighted else None
     if dt == torch.float32:
         us, gxs, gys = [list(map(roundtrip32, a)) for a in (us, gxs, gys)]
         if weighted:
             wxs, wys = list(map(roundtrip32, wxs)), list(map(roundtrip32, wys))
-    stack = B.Stack(SIZES)
+    stack = B.Stack(sizes)
     wx = dev(pack(wxs), dt) if weighted else None
     wy = dev(pack(wys), dt) if weighted else None
     gx, gy = B.apply_grad(stack, dev(pack(us), dt), wx=wx, wy=wy)
     ex = [regops.grad_fwd(u, *((a, b) if weighted else ())) for u, a, b in
-          zip(us, wxs or [None] * 3, wys or [None] * 3)]
+          zip(us, wxs or [None] * nseq, wys or [None] * nseq)]
     sx = pack([np.abs(u[:, :, 1:]) + np.abs(u[:, :, :-1]) for u in us])
     sy = pack([np.abs(u[:, 1:, :]) + np.abs(u[:, :-1, :]) for u in us])
     assert rel(host(gx), pack([e[0] for e in ex]), sx if not weighted else None) < tol
     assert rel(host(gy), pack([e[1] for e in ex]), sy if not weighted else None) < tol
     u = host(B.apply_grad(stack, gx=dev(pack(gxs), dt), gy=dev(pack(gys), dt), wx=wx, wy=wy, transpose=True))
     exp = pack([regops.grad_adj(a, b, *((c, d) if weighted else ())) for a, b, c, d in
-                zip(gxs, gys, wxs or [None] * 3, wys or [None] * 3)])
+                zip(gxs, gys, wxs or [None] * nseq, wys or [None] * nseq)])
     scale = []
     for i, (a, b) in enumerate(zip(gxs, gys)):
         a = np.abs(a) * (wxs[i] if weighted else 1.0)
         b = np.abs(b) * (wys[i] if weighted else 1.0)
-        sc = np.zeros(SIZES[i])
+        sc = np.zeros(sizes[i])
         sc[:, :, 1:] += a
         sc[:, :, :-1] += a
         sc[:, 1:, :] += b
@@ -185,16 +193,18 @@ def _abs_warp(u, v, direction, interp, adjoint=False, r=None):
 @pytest.mark.parametrize("direction", [1, -1])
 @pytest.mark.parametrize("interp", ["bilinear", "round"])
 @pytest.mark.parametrize("vmax", [3.5, 11.0])   # LDS-staged adjoint (radius <= 8) and the wide-window path
-def test_flow_operator(B, which, direction, interp, vmax):
+@pytest.mark.parametrize("layout", ["ragged", "vec4"])
+def test_flow_operator(B, which, direction, interp, vmax, layout):
     import torch
     from paper_2501_12497_amd import _lib
     dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
-    us = _rand_stack(16)
-    vs = _flows(17, vmax)
-    rs = [np.random.default_rng(18 + i).standard_normal((s[0] - 1, s[1], s[2])) for i, s in enumerate(SIZES)]
+    sizes = LAYOUTS[layout]
+    us = _rand_stack(16, sizes)
+    vs = _flows(17, vmax, sizes)
+    rs = [np.random.default_rng(18 + i).standard_normal((s[0] - 1, s[1], s[2])) for i, s in enumerate(sizes)]
     if dt == torch.float32:
         us, vs, rs = [list(map(roundtrip32, a)) for a in (us, vs, rs)]
-    stack = B.Stack(SIZES)
+    stack = B.Stack(sizes)
     ip = _lib.MMOF_INTERP_BILINEAR if interp == "bilinear" else _lib.MMOF_INTERP_ROUND
     du, dv, dr = dev(pack(us), dt), dev(pack(vs), dt), dev(pack(rs), dt)
     y = host(B.apply_flow_op(stack, _lib.MMOF_FLOW_FWD, direction, ip, du, dv))
@@ -202,7 +212,7 @@ def test_flow_operator(B, which, direction, interp, vmax):
     scale = pack([_abs_warp(u, v, direction, interp) for u, v in zip(us, vs)])
     assert rel(y, exp, scale) < tol
     ya = B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, direction, ip, None, dv, dr)
-    exp = pack([regops.flow_adj(r, v, s[0], direction, interp) for r, v, s in zip(rs, vs, SIZES)])
+    exp = pack([regops.flow_adj(r, v, s[0], direction, interp) for r, v, s in zip(rs, vs, sizes)])
     scale = pack([_abs_warp(None, v, direction, interp, True, r) for r, v in zip(rs, vs)])
     assert rel(host(ya), exp, scale) < tol
     # the adjoint is a deterministic gather: bitwise reproducible
@@ -233,29 +243,35 @@ def test_flow_dv(B, which, direction):
 
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
-@pytest.mark.parametrize("dr", [1, 2])
-def test_of_derivs(B, which, dr):
+@pytest.mark.parametrize("dr,layout", [(1, "ragged"), (2, "ragged"), (1, "vec4"), (2, "vec4"), (3, "vec4"),
+                                       (4, "vec4"), (5, "vec4")])
+def test_of_derivs(B, which, dr, layout):
     import torch
     dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
-    us = _rand_stack(22)
+    sizes = LAYOUTS[layout]
+    if layout == "vec4":   # radius below every frame side
+        sizes = [s for s in sizes if min(s[1], s[2]) > dr]
+    us = _rand_stack(22, sizes)
     if dt == torch.float32:
         us = [roundtrip32(u) for u in us]
-    I = host(B.of_derivs(B.Stack(SIZES), dev(pack(us), dt), dr))
+    I = host(B.of_derivs(B.Stack(sizes), dev(pack(us), dt), dr))
     exp = pack([optflow.of_derivs(u, dr) for u in us])
     scale = pack([optflow.of_derivs(np.abs(u), dr) * 0 + np.abs(u).max() for u in us])
     assert rel(I, exp, scale) < tol
 
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
-def test_flow_update_and_reverse(B, which):
+@pytest.mark.parametrize("layout", ["ragged", "vec4"])
+def test_flow_update_and_reverse(B, which, layout):
     import torch
     dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    sizes = LAYOUTS[layout]
     r = np.random.default_rng(23)
-    us = [np.cumsum(np.cumsum(r.standard_normal(s), axis=1), axis=2) * 0.05 for s in SIZES]   # smooth-ish images
-    vs0 = _flows(24, 0.5)
+    us = [np.cumsum(np.cumsum(r.standard_normal(s), axis=1), axis=2) * 0.05 for s in sizes]   # smooth-ish images
+    vs0 = _flows(24, 0.5, sizes)
     if dt == torch.float32:
         us, vs0 = [list(map(roundtrip32, a)) for a in (us, vs0)]
-    stack = B.Stack(SIZES)
+    stack = B.Stack(sizes)
     v = dev(pack(vs0), dt)
     vr = torch.empty_like(v)
     B.flow_update(stack, dev(pack(us), dt), v, alpha=0.3, n_sweeps=25, delta_r=1, v_rev=vr)

@@ -128,10 +128,10 @@ def test_solve_disk32_refined(B):
     assert early.iters <= 15 and early.rre[-1] <= tgt and early.status == 0
 
 
-def test_solve_blur_ragged_fp64(B):
+@pytest.mark.parametrize("sizes", [[(3, 24, 30), (4, 18, 18)], [(3, 24, 32), (4, 18, 20)]], ids=["ragged", "vec4"])
+def test_solve_blur_ragged_fp64(B, sizes):
     import torch
     r = np.random.default_rng(5)
-    sizes = [(3, 24, 30), (4, 18, 18)]
     us = []
     for (nt, ny, nx) in sizes:
         yy, xx = np.mgrid[0:ny, 0:nx]
