@@ -102,7 +102,9 @@ int mmof_plan_sizes(mmof_plan plan, int64_t* n, int64_t* m);
 /* Tile-shape autotuner of the plan's stencil kernels (blur for blur plans, the angle
  * grouping of the projector for Radon plans, Psi, Psi^T, L(v), L(v)^T): every candidate
  * is timed on the plan's stack in dtype dt (HIP events on the context's stream) and the
- * fastest is used by later launches of the plan (apply_A/At, solve_joint) in that dtype.
+ * fastest is used by later launches of the plan (apply_A/At, solve_joint) in that dtype,
+ * and by the stack-level operator calls on the plan's context for a stack of the same
+ * sizes (apply_grad, apply_flow_op).
  * The stencil candidates compute identical values; the projector's angle groups split the
  * rows of a ray differently, which changes its sums by rounding only.
  * report: host buffer of report_len bytes (or NULL) that receives a NUL-terminated line

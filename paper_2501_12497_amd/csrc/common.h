@@ -60,6 +60,16 @@ struct Tile {
     int32_t pad;
 };
 
+// A tile of one frame with what the flow adjoint needs of the frame and its neighbour,
+// so a workgroup finds everything in one load.
+struct alignas(16) AdjTile {
+    int64_t off;  // pixel offset of the frame
+    int64_t po;   // pixel offset (in pair arrays) of pair (t, t+1); -1 for the last frame
+    int64_t pp;   // pixel offset of pair (t-1, t); -1 for the first frame
+    int32_t nx, ny;
+    int32_t x0, y0;
+};
+
 // ----------------------------------------------------------------------------- host objects
 
 struct DeviceBuffer {
@@ -117,6 +127,7 @@ struct Geom {
     std::vector<int64_t> seq_off;        // pixel offset per sequence
     DeviceBuffer d_frames;               // FrameInfo[n_frames]
     std::map<uint64_t, std::unique_ptr<TileList>> tiles;  // (tw, th, pairs) -> list
+    std::map<uint64_t, std::unique_ptr<TileList>> adj_tiles;  // (tw, th) -> AdjTile list
     // Tile-shape candidate chosen by the autotuner per "kernel/dtype".  Untuned kernels use
     // candidate 0 (tiles of 1024 outputs) on frames of at least 512 x 512 pixels and
     // `small` (tiles of 256 outputs, more workgroups) on smaller frames.
@@ -129,6 +140,7 @@ struct Geom {
 
     bool same_as(const mmof_stack& s) const;
     const TileList& tile_list(hipStream_t st, int tw, int th, bool pairs);
+    const TileList& adj_tile_list(hipStream_t st, int tw, int th);
     const FrameInfo* dframes() const { return d_frames.as<FrameInfo>(); }
 };
 

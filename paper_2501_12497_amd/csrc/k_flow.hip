@@ -3,10 +3,10 @@
 //   direction -1:  r_t = W(v_t) u_t - u_{t+1}      (-M-bar'(s'))
 // W(v) pulls a bilinear (or nearest, ties to even) sample at p + v(p) with clipped
 // coordinates.  The adjoint scatters through the bilinear weights; here it is a
-// deterministic gather: every output pixel sums, in a fixed order, the sources whose
-// sample cell touches it.  Sources are staged in LDS per output tile together with the
-// range of their integer displacements, so a pixel only visits the (dmax-dmin+2)^2
-// sources that can reach it.
+// deterministic gather: every output pixel sums, in a fixed order (per corner of the sample
+// cell, sources in raster order), the sources whose sample cell has it as a corner.
+// Sources are staged in LDS per output tile and bucketed by cell, so a pixel only visits
+// the sources that reach it.
 #include <climits>
 #include <type_traits>
 
@@ -168,54 +168,39 @@ __device__ __forceinline__ void source_cell(int sx, int sy, T vx, T vy, int nx, 
     }
 }
 
-template <class T>
-__device__ __forceinline__ bool corner_weight(int c0, T f, int q, T& w) {
-    if (c0 == q) {
-        w = T(1) - f;
-        return true;
-    }
-    if (c0 + 1 == q) {
-        w = f;
-        return true;
-    }
-    return false;
-}
-
 // Adjoint over an ATX x ATY output tile per workgroup of 256 threads; each thread owns
-// RPT = ATX * ATY / 256 consecutive rows of one column.  The sources of the tile's
-// neighbourhood are staged in LDS with their sample cell packed into one word, and a
-// thread scans the window of sources that can reach any of its rows once, in raster order,
-// adding each match to the row it lands in (so every output sums its sources in raster
-// order, whatever the tile shape).
+// RPT = ATX * ATY / 256 consecutive rows of one column.  The sources within the radius of
+// the tile are staged in LDS (cell fractions and value) and bucketed by the cell they
+// sample: a counting sort over the (ATX+1) x (ATY+1) cells whose corners touch the tile
+// (LDS counters, a workgroup scan for the bucket starts, then raster order restored inside
+// each bucket).  An output is a corner of exactly four cells; it sums each of their buckets
+// in raster order and adds the four partial sums in a fixed corner order, so it visits only
+// the sources that reach it and its value does not depend on the tile shape (the
+// wide-window path below forms the same sums).
 template <class T, int INTERP, int ATX, int ATY>
-__global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
-                                                  const T* __restrict__ r, const T* __restrict__ v,
-                                                  T* __restrict__ u, int direction, int accumulate,
-                                                  const int32_t* __restrict__ d_radius) {
+__global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ tiles, const T* __restrict__ r,
+                                                  const T* __restrict__ v, T* __restrict__ u, int direction,
+                                                  int accumulate, const int32_t* __restrict__ d_radius) {
     constexpr int RPT = ATX * ATY / 256;
-    constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);
-    __shared__ unsigned s_cell[SMAX];  // x0 | y0 << 16 of the source's sample cell
-    __shared__ T s_fx[SMAX], s_fy[SMAX], s_val[SMAX];
-    __shared__ int s_d[4];  // dmin_x, dmax_x, dmin_y, dmax_y
+    constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);  // source window (raster rank < 2^16)
+    constexpr int CW = ATX + 1, NC = (ATX + 1) * (ATY + 1);     // cells touching the tile
+    static_assert(SMAX <= 65536, "source ranks are kept in 16 bits");
+    __shared__ T s_fx[SMAX], s_fy[SMAX], s_val[SMAX];           // cell fractions and value per source
+    __shared__ unsigned short s_list[SMAX];                     // sources bucketed by cell
+    __shared__ int s_off[NC + 1];                               // bucket starts
+    __shared__ int s_wsum[4];
 
-    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
-    const int64_t fi = tl.frame;
-    const FrameInfo f = fr[fi];
-    const int nx = f.nx, ny = f.ny;
+    const AdjTile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int R = *d_radius;  // (independent of the tile: both loads are in flight together)
+    const int nx = tl.nx, ny = tl.ny;
     const int64_t np = (int64_t)nx * ny;
     const int qx = tl.x0 + (int)(threadIdx.x % ATX);
     const int qy0 = tl.y0 + (int)(threadIdx.x / ATX) * RPT;
     const bool col_in = qx < nx;
 
     // direct terms and the pair whose warp gathers into this frame
-    int64_t dp = -1, gp = -1;  // pair offsets of the direct term and of the gathering pair
-    if (direction > 0) {
-        if (f.t + 1 < f.n_t) dp = f.pair_off;
-        if (f.t >= 1) gp = fr[fi - 1].pair_off;
-    } else {
-        if (f.t >= 1) dp = fr[fi - 1].pair_off;
-        if (f.t + 1 < f.n_t) gp = f.pair_off;
-    }
+    const int64_t dp = direction > 0 ? tl.po : tl.pp;  // pair offset of the direct term (-1: none)
+    const int64_t gp = direction > 0 ? tl.pp : tl.po;  // pair offset of the gathering pair (-1: none)
     T acc[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) acc[k] = T(0);
@@ -224,93 +209,159 @@ __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles
         const T* rg = r + gp;
         const T* vxg = v + 2 * gp;
         const T* vyg = vxg + np;
-        const int R = *d_radius;
         if (R <= RMAX) {
             const int sx0 = max(tl.x0 - R, 0), sx1 = min(tl.x0 + ATX - 1 + R, nx - 1);
             const int sy0 = max(tl.y0 - R, 0), sy1 = min(tl.y0 + ATY - 1 + R, ny - 1);
             const int sw = sx1 - sx0 + 1, sh = sy1 - sy0 + 1;
-            if (threadIdx.x == 0) {
-                s_d[0] = INT_MAX;
-                s_d[1] = INT_MIN;
-                s_d[2] = INT_MAX;
-                s_d[3] = INT_MIN;
-            }
-            // displacement range of the sources whose cell touches the tile: per-thread
-            // bounds, then one LDS atomic per wave
-            int dxn = INT_MAX, dxx = INT_MIN, dyn = INT_MAX, dyx = INT_MIN;
-            for (int i = threadIdx.x; i < sw * sh; i += 256) {
-                const int sy = sy0 + i / sw, sx = sx0 + i % sw;
-                const int64_t p = (int64_t)sy * nx + sx;
-                int x0, y0;
-                T fx, fy;
-                source_cell<T, INTERP>(sx, sy, vxg[p], vyg[p], nx, ny, x0, y0, fx, fy);
-                s_cell[i] = (unsigned)x0 | ((unsigned)y0 << 16);
-                s_fx[i] = fx;
-                s_fy[i] = fy;
-                s_val[i] = rg[p];
-                if (x0 >= tl.x0 - 1 && x0 <= tl.x0 + ATX - 1 && y0 >= tl.y0 - 1 && y0 <= tl.y0 + ATY - 1) {
-                    dxn = min(dxn, x0 - sx);
-                    dxx = max(dxx, x0 - sx);
-                    dyn = min(dyn, y0 - sy);
-                    dyx = max(dyx, y0 - sy);
+            for (int i = threadIdx.x; i <= NC; i += 256) s_off[i] = 0;
+            // Staging: a thread first loads all of its sources (independent loads, in flight
+            // together), then forms their cells.  Threads walk the window with the fixed row
+            // pitch SWM (constant divisions); the LDS copy is packed with pitch sw, so a
+            // source's LDS index is its raster rank in the window.
+            constexpr int SWM = ATX + 2 * RMAX;
+            constexpr int NI = (SMAX + 255) / 256;
+            T lvx[NI], lvy[NI], lr[NI];
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int i = (int)threadIdx.x + 256 * k;
+                const int ly = i / SWM, lx = i % SWM;
+                lvx[k] = lvy[k] = lr[k] = T(0);
+                if (ly < sh && lx < sw) {
+                    const int64_t p = (int64_t)(sy0 + ly) * nx + sx0 + lx;
+                    lvx[k] = vxg[p];
+                    lvy[k] = vyg[p];
+                    lr[k] = rg[p];
                 }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                dxn = min(dxn, __shfl_xor(dxn, o));
-                dxx = max(dxx, __shfl_xor(dxx, o));
-                dyn = min(dyn, __shfl_xor(dyn, o));
-                dyx = max(dyx, __shfl_xor(dyx, o));
-            }
-            __syncthreads();  // s_d initialised
-            if ((threadIdx.x & 63) == 0) {
-                atomicMin(&s_d[0], dxn);
-                atomicMax(&s_d[1], dxx);
-                atomicMin(&s_d[2], dyn);
-                atomicMax(&s_d[3], dyx);
-            }
-            __syncthreads();
-            if (col_in && qy0 < ny && s_d[0] <= s_d[1]) {
-                const int qy_last = min(qy0 + RPT - 1, ny - 1);
-                const int px_lo = max(qx - 1 - s_d[1], sx0), px_hi = min(qx - s_d[0], sx1);
-                const int py_lo = max(qy0 - 1 - s_d[3], sy0), py_hi = min(qy_last - s_d[2], sy1);
-                for (int py = py_lo; py <= py_hi; ++py) {
-                    const int row = (py - sy0) * sw - sx0;
-                    for (int px = px_lo; px <= px_hi; ++px) {
-                        const int i = row + px;
-                        const unsigned cell = s_cell[i];
-                        const int cx = (int)(cell & 0xffffu), cy = (int)(cell >> 16);
-                        if ((unsigned)(cx - (qx - 1)) > 1u) continue;
-                        const int ky = cy - qy0;  // row offset of the cell's upper corner
-                        if (ky < -1 || ky >= RPT) continue;
-                        const T wx = cx == qx ? T(1) - s_fx[i] : s_fx[i];
-                        const T fy = s_fy[i], val = s_val[i];
+            __syncthreads();  // counts cleared
+            // bucket the sources by the cell they sample, over the (ATX+1) x (ATY+1) cells
+            // whose corners touch the tile (cell (tl.x0-1, tl.y0-1) first)
+            int cell[NI], slot[NI];
 #pragma unroll
-                        for (int k = 0; k < RPT; ++k) {
-                            if (cy == qy0 + k) acc[k] += wx * (T(1) - fy) * val;
-                            else if (cy + 1 == qy0 + k) acc[k] += wx * fy * val;
-                        }
+            for (int k = 0; k < NI; ++k) {
+                const int i = (int)threadIdx.x + 256 * k;
+                const int ly = i / SWM, lx = i % SWM;
+                cell[k] = -1;
+                if (ly < sh && lx < sw) {
+                    const int sy = sy0 + ly, sx = sx0 + lx, j = ly * sw + lx;
+                    int x0, y0;
+                    T fx, fy;
+                    source_cell<T, INTERP>(sx, sy, lvx[k], lvy[k], nx, ny, x0, y0, fx, fy);
+                    s_fx[j] = fx;
+                    s_fy[j] = fy;
+                    s_val[j] = lr[k];
+                    const int cx = x0 - tl.x0 + 1, cy = y0 - tl.y0 + 1;
+                    if (cx >= 0 && cx <= ATX && cy >= 0 && cy <= ATY) {
+                        cell[k] = cy * CW + cx;
+                        slot[k] = atomicAdd(&s_off[cell[k] + 1], 1);  // arrival order: sorted below
                     }
                 }
             }
+            __syncthreads();
+            // bucket starts: inclusive scan of the counts in s_off[1..NC] (chunk per thread,
+            // then a scan of the chunk totals over the workgroup)
+            {
+                constexpr int CH = (NC + 255) / 256;
+                const int c0 = 1 + (int)threadIdx.x * CH;
+                int run = 0;
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+                    if (c0 + q <= NC) run += s_off[c0 + q];
+                int incl = run;  // inclusive scan over the wave
+                const int lane = (int)(threadIdx.x & 63);
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(incl, o);
+                    if (lane >= o) incl += t;
+                }
+                if (lane == 63) s_wsum[threadIdx.x >> 6] = incl;
+                __syncthreads();
+                int base = incl - run;
+                for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) base += s_wsum[w];
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+                    if (c0 + q <= NC) {
+                        base += s_off[c0 + q];
+                        s_off[c0 + q] = base;
+                    }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NI; ++k)
+                if (cell[k] >= 0) {
+                    const int i = (int)threadIdx.x + 256 * k;
+                    s_list[s_off[cell[k]] + slot[k]] = (unsigned short)((i / SWM) * sw + i % SWM);
+                }
+            __syncthreads();
+            // raster order inside every bucket (buckets hold a few sources)
+            for (int c = threadIdx.x; c < NC; c += 256) {
+                const int b = s_off[c], e = s_off[c + 1];
+                for (int a = b + 1; a < e; ++a) {
+                    const unsigned short key = s_list[a];
+                    int z = a - 1;
+                    while (z >= b && s_list[z] > key) {
+                        s_list[z + 1] = s_list[z];
+                        --z;
+                    }
+                    s_list[z + 1] = key;
+                }
+            }
+            __syncthreads();
+            if (col_in) {
+                const int lx = qx - tl.x0;
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const int qy = qy0 + k;
+                    if (qy >= ny) break;
+                    // the output is corner (1,1), (0,1), (1,0), (0,0) of the cells at
+                    // (qx-1, qy-1), (qx, qy-1), (qx-1, qy), (qx, qy): one partial sum per
+                    // corner, each over its bucket in raster order
+                    const int c00 = (qy - tl.y0) * CW + lx;
+                    T part[4];
+#pragma unroll
+                    for (int cr = 0; cr < 4; ++cr) {
+                        const int cc = c00 + (cr & 1) + (cr >> 1) * CW;
+                        const int e = s_off[cc + 1];
+                        T a = T(0);
+                        for (int t = s_off[cc]; t < e; ++t) {
+                            const int jj = s_list[t];
+                            const T fx = s_fx[jj], fy = s_fy[jj];
+                            const T wx = (cr & 1) ? T(1) - fx : fx;
+                            const T wy = (cr >> 1) ? T(1) - fy : fy;
+                            a += wx * wy * s_val[jj];
+                        }
+                        part[cr] = a;
+                    }
+                    acc[k] = ((part[0] + part[1]) + part[2]) + part[3];
+                }
+            }
         } else if (col_in) {
-            // Large displacements: scan the full window in global memory (same order).
+            // Large displacements: scan the full window in global memory, with the per-corner
+            // partial sums and their combination of the LDS path (same values).
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
                 const int qy = qy0 + k;
                 if (qy >= ny) break;
                 const int py_lo = max(qy - R, 0), py_hi = min(qy + R, ny - 1);
                 const int px_lo = max(qx - R, 0), px_hi = min(qx + R, nx - 1);
+                T part[4] = {T(0), T(0), T(0), T(0)};
                 for (int py = py_lo; py <= py_hi; ++py)
                     for (int px = px_lo; px <= px_hi; ++px) {
                         const int64_t p = (int64_t)py * nx + px;
                         int x0, y0;
                         T fx, fy;
                         source_cell<T, INTERP>(px, py, vxg[p], vyg[p], nx, ny, x0, y0, fx, fy);
-                        T wx, wy;
-                        if (!corner_weight(x0, fx, qx, wx)) continue;
-                        if (!corner_weight(y0, fy, qy, wy)) continue;
-                        acc[k] += wx * wy * rg[p];
+                        const int ex = qx - x0, ey = qy - y0;  // 1: the output is the cell's far corner
+                        if ((unsigned)ex > 1u || (unsigned)ey > 1u) continue;
+                        const T wx = ex ? fx : T(1) - fx;
+                        const T wy = ey ? fy : T(1) - fy;
+                        const T term = wx * wy * rg[p];
+                        const int cr = (1 - ex) + 2 * (1 - ey);
+                        if (cr == 0) part[0] += term;
+                        else if (cr == 1) part[1] += term;
+                        else if (cr == 2) part[2] += term;
+                        else part[3] += term;
                     }
+                acc[k] = ((part[0] + part[1]) + part[2]) + part[3];
             }
         }
     }
@@ -321,7 +372,7 @@ __global__ __launch_bounds__(256) void k_flow_adj(const Tile* __restrict__ tiles
         if (qy >= ny) break;
         const int64_t q = (int64_t)qy * nx + qx;
         const T direct = dp >= 0 ? -r[dp + q] : T(0);
-        T* uo = u + f.off + q;
+        T* uo = u + tl.off + q;
         const T val = acc[k] + direct;
         *uo = accumulate ? *uo + val : val;
     }
@@ -504,13 +555,13 @@ void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const v
     if (choice < 0) choice = g.choice("flow_adj", dt, 3);
     MMOF_CHECK(choice >= 0 && choice < kFlowAdjCandidates, MMOF_ERR_INVALID, "flow adjoint tile candidate out of range");
     const TileShape sh = kFlowAdjShapes[choice];
-    const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
+    const TileList& tl = g.adj_tile_list(c.stream, sh.tw, sh.th);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_adj", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
         auto k = interp == MMOF_INTERP_ROUND ? flow_adj_kernel<T, 1>(choice) : flow_adj_kernel<T, 0>(choice);
-        hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
-                           (const T*)r, (const T*)v, (T*)u, direction, accumulate ? 1 : 0, rad);
+        hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<AdjTile>(), (const T*)r,
+                           (const T*)v, (T*)u, direction, accumulate ? 1 : 0, rad);
         MMOF_LAUNCH_CHECK();
     });
 }

@@ -286,8 +286,8 @@ const int kRadonCandidates = 4;  // angle groups of 1, 2, 4, 8 per workgroup
 int radon_fwd_choice(Plan& p, int dt) {
     auto it = p.geom->tuned.find(std::string("radon_fwd") + (dt == MMOF_F32 ? "/f32" : "/f64"));
     if (it != p.geom->tuned.end()) return it->second;
-    // untuned: wide angle groups once a frame no longer fits the cache of one angle's pass
-    return p.geom->max_ny >= 512 ? 3 : 1;
+    // untuned: one angle per workgroup (more workgroups) on large frames, pairs on small ones
+    return p.geom->max_ny >= 512 ? 0 : 1;
 }
 
 void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b, int choice) {

@@ -93,6 +93,31 @@ const TileList& Geom::tile_list(hipStream_t st, int tw, int th, bool pairs) {
     return ref;
 }
 
+const TileList& Geom::adj_tile_list(hipStream_t st, int tw, int th) {
+    const uint64_t key = ((uint64_t)tw << 32) | (uint64_t)th;
+    auto it = adj_tiles.find(key);
+    if (it != adj_tiles.end()) return *it->second;
+    std::vector<AdjTile> host;
+    for (int64_t f = 0; f < n_frames; ++f) {
+        const FrameInfo& fi = frames[f];
+        const int64_t po = fi.t + 1 < fi.n_t ? fi.pair_off : -1;
+        const int64_t pp = fi.t >= 1 ? frames[f - 1].pair_off : -1;
+        for (int y0 = 0; y0 < fi.ny; y0 += th)
+            for (int x0 = 0; x0 < fi.nx; x0 += tw) host.push_back(AdjTile{fi.off, po, pp, fi.nx, fi.ny, x0, y0});
+    }
+    std::unique_ptr<TileList> tl(new TileList());
+    tl->count = (int64_t)host.size();
+    tl->buf.ensure(sizeof(AdjTile) * std::max<size_t>(host.size(), 1));
+    if (!host.empty()) {
+        MMOF_HIP(hipMemcpyAsync(tl->buf.ptr, host.data(), sizeof(AdjTile) * host.size(), hipMemcpyHostToDevice, st));
+        MMOF_HIP(hipStreamSynchronize(st));
+    }
+    MMOF_CHECK(tl->count < (int64_t)INT32_MAX, MMOF_ERR_SHAPE, "too many tiles");
+    auto& ref = *tl;
+    adj_tiles[key] = std::move(tl);
+    return ref;
+}
+
 std::unique_ptr<Geom> make_geom(const mmof_stack* s, hipStream_t st) {
     std::unique_ptr<Geom> g(new Geom());
     build_geom(*g, s, st);

@@ -56,6 +56,15 @@ static int pick(Ctx& c, Geom& g, const char* name, int dt, int n_cand, const Til
     return best;
 }
 
+// The stack-level operator calls of the context (Psi, L(v), ...) use the context's cached
+// geometry of the stack, not the plan's copy: the plan's choices are mirrored there.
+static void share_choices(Plan& P) {
+    Geom& pg = *P.geom;
+    const mmof_stack s{pg.n_seq, pg.n_t.data(), pg.ny.data(), pg.nx.data()};
+    Geom& g = P.ctx->geom(&s);  // (created if the context has not seen the stack yet)
+    if (&g != &pg) g.tuned = pg.tuned;
+}
+
 std::string autotune(Plan& P, int dt) {
     Ctx& c = *P.ctx;
     Geom& g = *P.geom;
@@ -100,6 +109,7 @@ std::string autotune(Plan& P, int dt) {
              [&](int k) { launch_flow_adj(c, g, dt, +1, MMOF_INTERP_BILINEAR, r, v, o, true, rad, k); }, rep);
     }
     MMOF_HIP(hipStreamSynchronize(c.stream));
+    share_choices(P);
     if (!rep.empty()) rep.pop_back();
     return rep;
 }
@@ -114,6 +124,7 @@ void set_tile(Plan& P, const std::string& kernel, int dt, int choice) {
     MMOF_CHECK(n > 0, MMOF_ERR_INVALID, "unknown tunable kernel '" + kernel + "'");
     MMOF_CHECK(choice >= 0 && choice < n, MMOF_ERR_INVALID, "tile candidate out of range for " + kernel);
     P.geom->tuned[kernel + (dt == MMOF_F32 ? "/f32" : "/f64")] = choice;
+    share_choices(P);
 }
 
 }  // namespace mmof
