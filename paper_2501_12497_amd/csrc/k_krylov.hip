@@ -30,6 +30,23 @@ __device__ __forceinline__ double block_sum(double v, double* s4) {
     return r;
 }
 
+// sum_j X[j][i] h[j] in column order; the loads go out in groups of 8 (all in flight
+// together) ahead of the sequential sum.
+template <class TX>
+__device__ __forceinline__ double dot_row(const TX* __restrict__ X, int64_t ld, int64_t i, int K,
+                                          const double* __restrict__ h) {
+    double acc = 0.0;
+    for (int j0 = 0; j0 < K; j0 += 8) {
+        double q[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) q[t] = j0 + t < K ? (double)X[(int64_t)(j0 + t) * ld + i] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (j0 + t < K) acc += q[t] * h[j0 + t];
+    }
+    return acc;
+}
+
 // FP64 MM weights w2 = 1/sqrt(nu^2 + eps^2) of the rows of Theta.
 template <class TX>
 __global__ void k_mm_weights_f64(int64_t n, const TX* __restrict__ nu, double eps2, double* __restrict__ w) {
@@ -84,17 +101,26 @@ __global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, const TX* __restr
             (s8[0][threadIdx.x] + s8[1][threadIdx.x]) + (s8[2][threadIdx.x] + s8[3][threadIdx.x]);
 }
 
-// Sums of the chunk partials in a fixed order (wave w takes columns w, w+4, ...; lane l sums
+// Sums of the chunk partials in a fixed order (one wave per column, 16 waves; lane l sums
 // chunks l, l+64, ...; then a fixed butterfly):
 //   G == null: out[j] = alpha * s_j (j < Kt)
 //   G != null: G[row][j] = G[j][row] = s_j for j < Kt - 1 and dj[0] = s_{Kt-1}.
-__global__ __launch_bounds__(KB) void k_mdot_final(int nb, int Kt, const double* __restrict__ part, double alpha,
-                                                   double* __restrict__ out, double* __restrict__ G, int ldg,
-                                                   int row, double* __restrict__ dj) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int j = w; j < Kt; j += 4) {
-        double a = 0.0;
-        for (int b = lane; b < nb; b += 64) a += part[(int64_t)b * Kt + j];
+__global__ __launch_bounds__(1024) void k_mdot_final(int nb, int Kt, const double* __restrict__ part, double alpha,
+                                                     double* __restrict__ out, double* __restrict__ G, int ldg,
+                                                     int row, double* __restrict__ dj) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = w; j < Kt; j += nw) {
+        // lane l sums chunks l, l+64, l+128, ... in four interleaved running sums (four
+        // loads in flight), combined in a fixed order
+        double a4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b0 = lane; b0 < nb; b0 += 256) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int b = b0 + 64 * u;
+                if (b < nb) a4[u] += part[(int64_t)b * Kt + j];
+            }
+        }
+        double a = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         a = wave_sum(a);
         if (lane == 0) {
             if (!G)
@@ -118,8 +144,7 @@ __global__ __launch_bounds__(KB) void k_gemv_cols(int64_t n, int K, const TX* __
     for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
-        double acc = 0.0;
-        for (int j = 0; j < K; ++j) acc += (double)X[(int64_t)j * ld + i] * sh[j];
+        const double acc = dot_row(X, ld, i, K, sh);
         out[i] = (beta == 0.0 ? 0.0 : beta * out[i]) + alpha * acc;
     }
 }
@@ -138,8 +163,7 @@ __global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* _
     __syncthreads();
     double e2 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
-        double acc = 0.0;
-        for (int j = 0; j < K; ++j) acc += (double)X[(int64_t)j * ld + i] * sh[j];
+        const double acc = dot_row(X, ld, i, K, sh);
         const double v = alpha * acc + (y ? beta * y[i] : 0.0);
         if (out_d) out_d[i] = v;
         if (out_t) out_t[i] = (TO)v;
@@ -153,10 +177,63 @@ __global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* _
     if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }
 
+// y = x - Q h and the chunk partials of Q^T y, reading Q once (y must not alias x).  The
+// four waves of a workgroup split the columns (wave w owns columns w*CPW .. w*CPW+CPW-1)
+// and walk the workgroup's row chunk 64 rows at a time: each wave forms its columns' part
+// of (Q h)_i for its lane's row and keeps its Q entries in registers; the four parts are
+// added through LDS in a fixed order, every wave forms the same y_i = x_i - (Q h)_i, and
+// the wave then accumulates its columns' products with y_i.  CPW >= ceil(K / 4).
+template <int CPW>
+__global__ __launch_bounds__(KB) void k_gemv_mdot(int64_t n, int K, const double* __restrict__ Q, int64_t ld,
+                                                  const double* __restrict__ h, const double* __restrict__ x,
+                                                  double* __restrict__ y, double* __restrict__ part) {
+    __shared__ double sp[2][4][64];  // per-row parts of Q h, double-buffered
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int jw = w * CPW;
+    double hw[CPW], acc[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        hw[c] = jw + c < K ? h[jw + c] : 0.0;
+        acc[c] = 0.0;
+    }
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = (n + nb - 1) / nb;
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    int buf = 0;
+    for (int64_t i0 = lo; i0 < hi; i0 += 64, buf ^= 1) {
+        const int64_t i = i0 + lane;
+        const bool in = i < hi;
+        double q[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) q[c] = (in && jw + c < K) ? Q[(int64_t)(jw + c) * ld + i] : 0.0;
+        const double xi = in ? x[i] : 0.0;
+        double sw = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) sw += q[c] * hw[c];
+        sp[buf][w][lane] = sw;
+        __syncthreads();
+        const double s = (sp[buf][0][lane] + sp[buf][1][lane]) + (sp[buf][2][lane] + sp[buf][3][lane]);
+        const double v = xi - s;
+        if (w == 0 && in) y[i] = v;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) acc[c] += q[c] * v;
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const double a = wave_sum(acc[c]);
+        if (lane == 0 && jw + c < K) part[(int64_t)blockIdx.x * K + jw + c] = a;
+    }
+}
+
 // out[0] = sum of nb partials in a fixed order (one wavefront)
 __global__ __launch_bounds__(64) void k_sum_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 64) a += part[b];
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 256) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (b0 + 64 * u < nb) a4[u] += part[b0 + 64 * u];
+    }
+    double a = (a4[0] + a4[1]) + (a4[2] + a4[3]);
     a = wave_sum(a);
     if (threadIdx.x == 0) out[0] = a;
 }
@@ -199,7 +276,7 @@ __global__ void k_axpy_conv(int64_t n, const TX* __restrict__ in, const double* 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 static constexpr int GRAM_WAVES = 8;       // waves per stage-1 workgroup
-static constexpr int GRAM_BLOCKS = 256;    // stage-1 workgroups (partials)
+static constexpr int GRAM_BLOCKS = 1024;   // most stage-1 workgroups (partials)
 static constexpr int GRAM_PAIRS = 10;      // upper blocks of a 4x4 block grid
 static constexpr int GRAM_SLAB = 64;       // partial entries per stage-2 workgroup
 
@@ -482,13 +559,30 @@ void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double
                            (const double*)nullptr, part);
         MMOF_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(KB), 0, c.stream, nb, K, part, alpha, out, (double*)nullptr, 0, 0,
+    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, K, part, alpha, out, (double*)nullptr, 0, 0,
                        (double*)nullptr);
     MMOF_LAUNCH_CHECK();
 }
 template void mdot<float, double>(Ctx&, int64_t, int, const float*, int64_t, const double*, double, double*);
 template void mdot<double, double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double, double*);
 template void mdot<float, float>(Ctx&, int64_t, int, const float*, int64_t, const float*, double, double*);
+
+void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const double* h, const double* x, double* y,
+               double* hout) {
+    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for a block inner product");
+    // row chunks of at least 256 rows, at most MAX_PART partials
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 256)));
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
+    {
+        ScopedTime st(&c, "gemv_mdot", (double)n * (8.0 * K + 16.0), 4.0 * n * K);
+        auto k = K <= 16 ? k_gemv_mdot<4> : K <= 32 ? k_gemv_mdot<8> : K <= 48 ? k_gemv_mdot<12> : k_gemv_mdot<16>;
+        hipLaunchKernelGGL(k, dim3(nb), dim3(KB), 0, c.stream, n, K, Q, ld, h, x, y, part);
+        MMOF_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, K, part, 1.0, hout, (double*)nullptr, 0, 0,
+                       (double*)nullptr);
+    MMOF_LAUNCH_CHECK();
+}
 
 template <class TX>
 void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e, double* G, int ldg, double* dj) {
@@ -499,7 +593,7 @@ void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e
     hipLaunchKernelGGL((k_mdot<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1, X,
                        ld, xj, e, part);
     MMOF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(KB), 0, c.stream, nb, j + 2, part, 1.0, (double*)nullptr, G, ldg,
+    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, j + 2, part, 1.0, (double*)nullptr, G, ldg,
                        j, dj);
     MMOF_LAUNCH_CHECK();
 }
@@ -596,9 +690,10 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
     const int Gb = (K + 15) / 16;
     const int np = Gb * (Gb + 1) / 2;
-    // enough 16-row steps per wave to amortise the partial, at most GRAM_BLOCKS partials
+    // about 32 16-row steps per wave (enough to amortise a partial and keep the prefetch
+    // pipeline full), at most GRAM_BLOCKS partials: 4 workgroups per CU on large inputs
     const int64_t steps = (n + 15) / 16;
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 8 * GRAM_WAVES)));
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 32 * GRAM_WAVES)));
     const bool vec = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
                      (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     double* part =

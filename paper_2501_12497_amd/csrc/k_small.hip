@@ -122,15 +122,34 @@ __device__ bool chol(SmallLds& s, int K, double lam, double* inv) {
     return true;
 }
 
+// The solves below walk the columns in groups of four with the next group's LDS entries
+// loaded ahead, so the LDS latency overlaps the broadcast chain.  The walk runs up to K
+// rounded up to 4 (at most the padded size of the factor): a step j >= K changes nothing,
+// since entry j of the right-hand side is zero and the rows it would update lie outside
+// [0, K).
+
 // y = L^{-1} b (one entry per lane)
 __device__ double fwd_solve(const SmallLds& s, int K, double inv, double b) {
     const int i = threadIdx.x;
+    const int row = min(i, KMAX_SMALL - 1);
+    const int K4 = (K + 3) & ~3;
     double y = i < K ? b : 0.0;
-    for (int j = 0; j < K; ++j) {
-        const double lij = s.L[min(i, KMAX_SMALL - 1)][j];
-        const double yj = bcast(y * inv, j);
-        const double upd = fma(-lij, yj, y);
-        y = (i == j) ? yj : ((i > j && i < K) ? upd : y);
+    double l[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) l[q] = s.L[row][q];
+    for (int j = 0; j < K4; j += 4) {
+        double nl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nl[q] = s.L[row][min(j + 4 + q, KMAX_SMALL)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = j + q;
+            const double yj = bcast(y * inv, jj);
+            const double upd = fma(-l[q], yj, y);
+            y = (i == jj) ? yj : ((i > jj && i < K) ? upd : y);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) l[q] = nl[q];
     }
     return i < K ? y : 0.0;
 }
@@ -138,24 +157,41 @@ __device__ double fwd_solve(const SmallLds& s, int K, double inv, double b) {
 // z = L^{-T} y
 __device__ double bwd_solve(const SmallLds& s, int K, double inv, double y) {
     const int i = threadIdx.x;
+    const int col = min(i, KMAX_SMALL - 1);
+    const int K4 = (K + 3) & ~3;
     double z = i < K ? y : 0.0;
-    for (int j = K - 1; j >= 0; --j) {
-        const double lji = s.L[j][min(i, KMAX_SMALL - 1)];
-        const double zj = bcast(z * inv, j);
-        const double upd = fma(-lji, zj, z);
-        z = (i == j) ? zj : (i < j ? upd : z);
+    double l[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) l[q] = s.L[K4 - 1 - q][col];
+    for (int j = K4 - 1; j >= 0; j -= 4) {
+        double nl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nl[q] = s.L[max(j - 4 - q, 0)][col];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = j - q;
+            const double zj = bcast(z * inv, jj);
+            const double upd = fma(-l[q], zj, z);
+            z = (i == jj) ? zj : ((i < jj && i < K) ? upd : z);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) l[q] = nl[q];
     }
     return i < K ? z : 0.0;
 }
 
-// (T z)_i for the lane's row, z distributed one entry per lane.
+// (T z)_i for the lane's row, z distributed one entry per lane (T is zero outside K x K).
 __device__ double matvec_T(const SmallLds& s, int K, double z) {
     const int i = threadIdx.x;
+    const int row = min(i, KMAX_SMALL - 1);
+    const int K4 = (K + 3) & ~3;
     double acc = 0.0;
-    for (int j = 0; j < K; ++j) {
-        const double tij = s.T[min(i, KMAX_SMALL - 1)][j];
-        const double zj = bcast(z, j);
-        acc += tij * zj;
+    for (int j = 0; j < K4; j += 4) {
+        double t[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[q] = s.T[row][j + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += t[q] * bcast(z, j + q);
     }
     return i < K ? acc : 0.0;
 }
@@ -190,14 +226,16 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
                                                     double* __restrict__ res, double* __restrict__ lam_out) {
     __shared__ SmallLds s;
     const int i = threadIdx.x;
-    // coalesced loads: each instruction moves one contiguous row of the 64-wide matrices
-    for (int r = 0; r < K; ++r) {
-        const double ga = GA[(int64_t)r * KMAX_SMALL + i];
-        const double gt = GT[(int64_t)r * KMAX_SMALL + i];
-        if (i < K) {
-            s.A[r][i] = ga;
-            s.T[r][i] = gt;
+    // coalesced loads: each instruction moves one contiguous row of the 64-wide matrices;
+    // entries outside K x K are zero
+    for (int r = 0; r < KMAX_SMALL; ++r) {
+        double ga = 0.0, gt = 0.0;
+        if (r < K) {
+            ga = GA[(int64_t)r * KMAX_SMALL + i];
+            gt = GT[(int64_t)r * KMAX_SMALL + i];
         }
+        s.A[r][i] = i < K ? ga : 0.0;
+        s.T[r][i] = i < K ? gt : 0.0;
     }
     const double d = i < K ? dvec[i] : 0.0;
     __syncthreads();

@@ -24,6 +24,11 @@ void gemv_cols(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* 
 template <class TX, class TO>
 void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, const double* y,
                 double beta, double* out_d, TO* out_t, const double* cv, double* sq);
+// The middle step of classical Gram-Schmidt with reorthogonalisation, in one pass over Q:
+// y = x - Q h and hout = Q^T y, FP64 (Q column-major [K][ld], K <= 64; y must not alias x;
+// hout may alias h).
+void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const double* h, const double* x, double* y,
+               double* hout);
 // s = sqrt(s2[0]) (written to s1 when not null); out_d = x / s and out_t = (TO)(x / s)
 // (a zero vector when s = 0).
 template <class TO>

@@ -246,11 +246,11 @@ struct Solver {
             norm_into(len, x, sq);
             return;
         }
-        for (int pass = 0; pass < 2; ++pass) {
-            mdot<double, double>(c, len, k, Q, len, x, 1.0, h);
-            gemv_fused<double, double>(c, len, k, Q, len, h, -1.0, x, 1.0, x, nullptr, nullptr,
-                                       pass == 1 ? sq : nullptr);
-        }
+        // h = Q^T x; y = x - Q h and h = Q^T y in one pass over Q; x = y - Q h with ||x||^2
+        double* y = static_cast<double*>(c.work("reorth_y", sizeof(double) * (size_t)std::max<int64_t>(len, 1)));
+        mdot<double, double>(c, len, k, Q, len, x, 1.0, h);
+        gemv_mdot(c, len, k, Q, len, h, x, y, h);
+        gemv_fused<double, double>(c, len, k, Q, len, h, -1.0, y, 1.0, x, nullptr, nullptr, sq);
     }
 
     // H v_j, the row/column j of G_H, d_j = (H v_j)^T b and Theta v_j; vin_n already holds
