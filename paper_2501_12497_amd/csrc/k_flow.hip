@@ -413,9 +413,14 @@ template <class T>
 __global__ __launch_bounds__(256) void k_flow_radius(const T* __restrict__ v, int64_t n, int32_t* __restrict__ out) {
     __shared__ T s4[4];
     T m = T(0);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const T a = fabs(v[i]);
-        m = (a != a) ? T(1e30) : fmax(m, a);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // four loads in flight per step
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
+        T a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = i0 + u * stride < n ? fabs(v[i0 + u * stride]) : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m = (a[u] != a[u]) ? T(1e30) : fmax(m, a[u]);
     }
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = m;
@@ -436,7 +441,9 @@ void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out) 
     if (n == 0) return;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        hipLaunchKernelGGL(k_flow_radius<T>, grid_for(n, 256, 4096), dim3(256), 0, c.stream, (const T*)v, n, d_out);
+        // one atomic per workgroup: few workgroups, so the atomics do not queue up
+        hipLaunchKernelGGL(k_flow_radius<T>, grid_for(n, 256 * 4, 2 * c.cu_count), dim3(256), 0, c.stream,
+                           (const T*)v, n, d_out);
         MMOF_LAUNCH_CHECK();
     });
 }

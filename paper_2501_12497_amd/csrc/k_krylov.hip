@@ -545,7 +545,12 @@ template void weight_mul<float>(Ctx&, int64_t, const double*, const float*, floa
 template void weight_mul<double>(Ctx&, int64_t, const double*, const double*, double*);
 
 
-int mdot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 1024))); }
+// row chunks of 1024 rows (four per thread), but at least 256 chunks (of no fewer than 256
+// rows) so that short vectors still spread over the chip; at most MAX_PART partials
+int mdot_blocks(int64_t n) {
+    const int64_t nb = std::max<int64_t>(cdiv(n, 1024), std::min<int64_t>(cdiv(n, 256), 256));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, nb));
+}
 
 template <class TX, class TY>
 void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double alpha, double* out) {
@@ -570,8 +575,7 @@ template void mdot<float, float>(Ctx&, int64_t, int, const float*, int64_t, cons
 void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const double* h, const double* x, double* y,
                double* hout) {
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for a block inner product");
-    // row chunks of at least 256 rows, at most MAX_PART partials
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 256)));
+    const int nb = mdot_blocks(n);
     double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
     {
         ScopedTime st(&c, "gemv_mdot", (double)n * (8.0 * K + 16.0), 4.0 * n * K);
