@@ -575,7 +575,8 @@ template void mdot<float, float>(Ctx&, int64_t, int, const float*, int64_t, cons
 void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const double* h, const double* x, double* y,
                double* hout) {
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for a block inner product");
-    const int nb = mdot_blocks(n);
+    // chunks of 256 rows (4 steps of the workgroup), at most MAX_PART partials
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 256)));
     double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
     {
         ScopedTime st(&c, "gemv_mdot", (double)n * (8.0 * K + 16.0), 4.0 * n * K);
@@ -694,8 +695,9 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
     const int Gb = (K + 15) / 16;
     const int np = Gb * (Gb + 1) / 2;
-    // about 32 16-row steps per wave (enough to amortise a partial and keep the prefetch
-    // pipeline full), at most GRAM_BLOCKS partials: 4 workgroups per CU on large inputs
+    // about 32 16-row steps per wave (enough to amortise a partial, whose stage-2 sum grows
+    // with the count, and keep the prefetch pipeline busy), at most GRAM_BLOCKS partials:
+    // 4 workgroups per CU on large inputs
     const int64_t steps = (n + 15) / 16;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 32 * GRAM_WAVES)));
     const bool vec = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
