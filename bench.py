@@ -194,6 +194,49 @@ def large_solve(B, torch, k_ref=30, k_cap=40):
     return out
 
 
+def ragged_blur(B, torch, reps=2):
+    """The batched deblurring workload (40 sequences of 64^2..256^2 x 8..32 frames, 9x9
+    Gaussian blur, 1% noise): FP32-operator solves with the launch sequences replayed from
+    HIP graphs and the autotuned tiles, the same solves launched eagerly, and the FP64
+    solve; wall time per solve (median of `reps` after a warm-up), inputs resident."""
+    from synth import cfg_blur_ragged
+    wl = cfg_blur_ragged()
+    sizes = [(s.n_t, s.ny, s.nx) for s in wl.seqs]
+    stack = B.Stack(sizes)
+    plan = B.plan_blur(stack, wl.params["ksize"], wl.params["sigma"])
+    u_true = torch.as_tensor(np.concatenate([s.u_true.ravel() for s in wl.seqs]), dtype=torch.float64,
+                             device="cuda")
+    clean = B.apply_A(plan, u_true)
+    g = torch.as_tensor(np.concatenate([s.noise_g.ravel() for s in wl.seqs]), dtype=torch.float64, device="cuda")
+    e = wl.noise_level * torch.linalg.vector_norm(clean) * g / torch.linalg.vector_norm(g)
+    b = (clean + e).contiguous()
+    delta = float(torch.linalg.vector_norm(e))
+    tiles = {str(dt): plan.autotune(dt) for dt in (torch.float32, torch.float64)}
+    log(f"ragged autotune: {tiles}")
+    p = wl.params
+    out = {"workload": f"blur_ragged40: {len(sizes)} sequences, {min(s[1] for s in sizes)}^2..{max(s[1] for s in sizes)}^2 "
+                       f"x {min(s[0] for s in sizes)}..{max(s[0] for s in sizes)} frames, 9x9 Gaussian blur, 1% noise",
+           "n_pixels": plan.n, "tiles": tiles}
+    for name, op, graph in (("f32_graph", "f32", 1), ("f32_eager", "f32", 0), ("f64_graph", "f64", 1)):
+        kw = dict(ell=p["ell"], k_max=p["k_max"], tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
+                  eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"], op_dtype=op, use_graph=graph)
+        r = B.solve_joint(plan, b, delta, u_true=u_true, **kw)   # warm-up (graphs captured)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = B.solve_joint(plan, b, delta, u_true=u_true, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        sec = float(np.median(ts))
+        mv = r.counts["A"] + r.counts["At"] + r.counts["L"]
+        out[name] = {"seconds": sec, "iters": r.iters, "rre": r.rre[-1], "matvecs": mv,
+                     "matvecs_per_s": mv / sec}
+        log(f"ragged {name}: {out[name]}")
+    del plan
+    return out
+
+
 def solve_params(wl, op, graph=True):
     p = wl.params
     return dict(ell=p["ell"], k_max=p["k_max"], tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
@@ -260,6 +303,7 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the operator table at 1024x1024x64")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tile shapes")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the batched-deblurring (40 sequences) solves")
     ap.add_argument("--no-large-solve", action="store_true",
                     help="skip the FP64 / FP32 / FP32+refined solves of the 1024x1024x64 workload")
     ap.add_argument("--graph", action="store_true",
@@ -368,6 +412,10 @@ def main():
         large = operators_large(B, torch)
         log(f"operators at 1024x1024x64: {large['kernels']}")
 
+    ragged = None
+    if not a.no_ragged:
+        ragged = ragged_blur(B, torch)
+
     big = None
     if not a.no_large_solve:
         big = large_solve(B, torch)
@@ -398,6 +446,8 @@ def main():
         "cpu_baseline": cpu,
         "operators_large": large,
     }
+    if ragged is not None:
+        out["ragged_blur"] = ragged
     if big is not None:
         out["time_to_solution_large"] = big
     print(json.dumps(out))

@@ -51,6 +51,69 @@ __global__ __launch_bounds__(256) void k_blur(const Tile* __restrict__ tiles, in
     }
 }
 
+// The same sums with the radius R compiled in (the 9-tap case): both passes are unrolled and
+// a thread forms 4 outputs from one register copy of the 4 + 2R inputs they share (a row
+// segment in the horizontal pass, a column segment in the vertical one), so a tap costs
+// one FMA and the LDS reads drop from 2R + 1 to (4 + 2R) / 4 per output.  Per output the
+// taps are added in the order of k_blur, so the values are identical.
+template <class T, int TW, int TH, bool PERS, int R>
+__global__ __launch_bounds__(256) void k_blur_r(const Tile* __restrict__ tiles, int64_t n_tiles,
+                                                const FrameInfo* __restrict__ fr, const double* __restrict__ k1d,
+                                                const T* __restrict__ in, T* __restrict__ out) {
+    constexpr int HW = TW + 2 * R, HH = TH + 2 * R;
+    static_assert(TW % 4 == 0 && TH % 4 == 0, "tiles split into 4-output segments");
+    __shared__ T s_in[HH][HW + 1];
+    __shared__ T s_h[HH][TW + 1];
+    T kk[2 * R + 1];
+#pragma unroll
+    for (int j = 0; j <= 2 * R; ++j) kk[j] = (T)k1d[j];
+    const int64_t step = PERS ? gridDim.x : n_tiles;
+    for (int64_t ti = PERS ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x); ti < n_tiles; ti += step) {
+        const Tile tl = tiles[ti];
+        const FrameInfo f = fr[tl.frame];
+        const int nx = f.nx, ny = f.ny;
+        const T* src = in + f.off;
+        __syncthreads();  // LDS of the previous tile is free
+        for (int i = threadIdx.x; i < HW * HH; i += 256) {
+            const int ly = i / HW, lx = i % HW;
+            const int y = tl.y0 - R + ly, x = tl.x0 - R + lx;
+            s_in[ly][lx] = (y >= 0 && y < ny && x >= 0 && x < nx) ? src[(int64_t)y * nx + x] : T(0);
+        }
+        __syncthreads();
+        // horizontal pass: row ly, outputs lx0 .. lx0 + 3
+        for (int i = threadIdx.x; i < (TW / 4) * HH; i += 256) {
+            const int ly = i / (TW / 4), lx0 = 4 * (i % (TW / 4));
+            T v[4 + 2 * R];
+#pragma unroll
+            for (int c = 0; c < 4 + 2 * R; ++c) v[c] = s_in[ly][lx0 + c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j <= 2 * R; ++j) acc += kk[j] * v[q + j];
+                s_h[ly][lx0 + q] = acc;
+            }
+        }
+        __syncthreads();
+        // vertical pass: column lx, outputs ly0 .. ly0 + 3
+        for (int i = threadIdx.x; i < TW * (TH / 4); i += 256) {
+            const int lx = i % TW, ly0 = 4 * (i / TW);
+            T v[4 + 2 * R];
+#pragma unroll
+            for (int c = 0; c < 4 + 2 * R; ++c) v[c] = s_h[ly0 + c][lx];
+            const int x = tl.x0 + lx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int y = tl.y0 + ly0 + q;
+                T acc = T(0);
+#pragma unroll
+                for (int k = 0; k <= 2 * R; ++k) acc += kk[k] * v[q + k];
+                if (y < ny && x < nx) out[f.off + (int64_t)y * nx + x] = acc;
+            }
+        }
+    }
+}
+
 const TileShape kBlurShapes[] = {{64, 16, 0}, {32, 32, 0}, {128, 8, 0}, {32, 16, 0}, {64, 16, 1}};
 const int kBlurCandidates = sizeof(kBlurShapes) / sizeof(kBlurShapes[0]);
 
@@ -64,14 +127,24 @@ void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out, int choice)
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "blur", 2.0 * sizeof(T) * g.n, 4.0 * p.ksize * g.n);
-        auto k = choice == 0 ? k_blur<T, 64, 16, false>
-                 : choice == 1 ? k_blur<T, 32, 32, false>
-                 : choice == 2 ? k_blur<T, 128, 8, false>
-                 : choice == 3 ? k_blur<T, 32, 16, false>
-                               : k_blur<T, 64, 16, true>;
         const int64_t grid = sh.persistent ? std::min<int64_t>(tl.count, (int64_t)c.cu_count * 4) : tl.count;
-        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, c.stream, tl.buf.as<Tile>(), tl.count,
-                           g.dframes(), p.d_k1.as<double>(), p.ksize / 2, (const T*)in, (T*)out);
+        if (p.ksize == 9) {
+            auto k = choice == 0 ? k_blur_r<T, 64, 16, false, 4>
+                     : choice == 1 ? k_blur_r<T, 32, 32, false, 4>
+                     : choice == 2 ? k_blur_r<T, 128, 8, false, 4>
+                     : choice == 3 ? k_blur_r<T, 32, 16, false, 4>
+                                   : k_blur_r<T, 64, 16, true, 4>;
+            hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, c.stream, tl.buf.as<Tile>(), tl.count,
+                               g.dframes(), p.d_k1.as<double>(), (const T*)in, (T*)out);
+        } else {
+            auto k = choice == 0 ? k_blur<T, 64, 16, false>
+                     : choice == 1 ? k_blur<T, 32, 32, false>
+                     : choice == 2 ? k_blur<T, 128, 8, false>
+                     : choice == 3 ? k_blur<T, 32, 16, false>
+                                   : k_blur<T, 64, 16, true>;
+            hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, c.stream, tl.buf.as<Tile>(), tl.count,
+                               g.dframes(), p.d_k1.as<double>(), p.ksize / 2, (const T*)in, (T*)out);
+        }
         MMOF_LAUNCH_CHECK();
     });
 }

@@ -275,7 +275,7 @@ __global__ void k_axpy_conv(int64_t n, const TX* __restrict__ in, const double* 
 // are combined in LDS in a fixed order); stage 2 sums the partials in a fixed order.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-static constexpr int GRAM_WAVES = 8;       // waves per stage-1 workgroup
+static constexpr int GRAM_WAVES = 16;      // most waves per stage-1 workgroup (8 for G = 4: registers)
 static constexpr int GRAM_BLOCKS = 1024;   // most stage-1 workgroups (partials)
 static constexpr int GRAM_PAIRS = 10;      // upper blocks of a 4x4 block grid
 static constexpr int GRAM_SLAB = 64;       // partial entries per stage-2 workgroup
@@ -307,12 +307,15 @@ __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restr
                     st.x[g][2] = v.z;
                     st.x[g][3] = v.w;
                 } else {
-                    const double2 v0 = *reinterpret_cast<const double2*>(src);
-                    const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
-                    st.x[g][0] = v0.x;
-                    st.x[g][1] = v0.y;
-                    st.x[g][2] = v1.x;
-                    st.x[g][3] = v1.y;
+                    struct alignas(16) D2 {
+                        double a, b;
+                    };
+                    const D2 v0 = *reinterpret_cast<const D2*>(src);
+                    const D2 v1 = *reinterpret_cast<const D2*>(src + 2);
+                    st.x[g][0] = v0.a;
+                    st.x[g][1] = v0.b;
+                    st.x[g][2] = v1.a;
+                    st.x[g][3] = v1.b;
                 }
             } else {
 #pragma unroll
@@ -345,20 +348,20 @@ __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restr
     }
 }
 
-template <class TX, int G, bool VEC>
-__global__ __launch_bounds__(64 * GRAM_WAVES) void k_wgram_part(int64_t n, int K, const TX* __restrict__ X,
+template <class TX, int G, bool VEC, int W>
+__global__ __launch_bounds__(64 * W) void k_wgram_part(int64_t n, int K, const TX* __restrict__ X,
                                                                 int64_t ld, const double* __restrict__ w,
                                                                 double* __restrict__ part) {
     constexpr int NP = G * (G + 1) / 2;
-    __shared__ double sred[GRAM_WAVES][256];
+    __shared__ double sred[W][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     dbl4 acc[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[p] = dbl4{0.0, 0.0, 0.0, 0.0};
     // contiguous 16-row steps per wave
     const int64_t steps = (n + 15) / 16;
-    const int64_t nw = (int64_t)gridDim.x * GRAM_WAVES;
-    const int64_t gw = (int64_t)blockIdx.x * GRAM_WAVES + wave;
+    const int64_t nw = (int64_t)gridDim.x * W;
+    const int64_t gw = (int64_t)blockIdx.x * W + wave;
     const int64_t s_lo = steps * gw / nw, s_hi = steps * (gw + 1) / nw;
     GramRows<TX, G> cur, nxt;
     if (s_lo < s_hi) gram_rows<TX, G, VEC>(cur, X, ld, w, n, K, 16 * s_lo, lane);
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(64 * GRAM_WAVES) void k_wgram_part(int64_t n, int K
         if (threadIdx.x < 256) {
             double sum = 0.0;
 #pragma unroll
-            for (int q = 0; q < GRAM_WAVES; ++q) sum += sred[q][threadIdx.x];
+            for (int q = 0; q < W; ++q) sum += sred[q][threadIdx.x];
             out[p * 256 + threadIdx.x] = sum;
         }
         __syncthreads();
@@ -676,18 +679,22 @@ template void mm_weights_f64<float>(Ctx&, int64_t, const float*, double, double*
 template void mm_weights_f64<double>(Ctx&, int64_t, const double*, double, double*);
 
 template <class TX, int G, bool VEC>
-static void wgram_launch(Ctx& c, int nb, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* part) {
-    hipLaunchKernelGGL((k_wgram_part<TX, G, VEC>), dim3(nb), dim3(64 * GRAM_WAVES), 0, c.stream, n, K, X, ld, w,
-                       part);
+static void wgram_launch(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* part, int& nb) {
+    // 16 waves per workgroup where the registers allow (4 per SIMD, to overlap the loads with
+    // the matrix-core work), about 16 16-row steps per wave, at most GRAM_BLOCKS partials
+    constexpr int W = (sizeof(TX) == 4 && G <= 3) ? 16 : 8;
+    const int64_t steps = (n + 15) / 16;
+    nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 16 * W)));
+    hipLaunchKernelGGL((k_wgram_part<TX, G, VEC, W>), dim3(nb), dim3(64 * W), 0, c.stream, n, K, X, ld, w, part);
 }
 
 template <class TX, int G>
-static void wgram_launch_g(Ctx& c, int nb, bool vec, int64_t n, int K, const TX* X, int64_t ld, const double* w,
+static void wgram_launch_g(Ctx& c, int& nb, bool vec, int64_t n, int K, const TX* X, int64_t ld, const double* w,
                            double* part) {
     if (vec)
-        wgram_launch<TX, G, true>(c, nb, n, K, X, ld, w, part);
+        wgram_launch<TX, G, true>(c, n, K, X, ld, w, part, nb);
     else
-        wgram_launch<TX, G, false>(c, nb, n, K, X, ld, w, part);
+        wgram_launch<TX, G, false>(c, n, K, X, ld, w, part, nb);
 }
 
 template <class TX>
@@ -695,11 +702,7 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
     MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
     const int Gb = (K + 15) / 16;
     const int np = Gb * (Gb + 1) / 2;
-    // about 32 16-row steps per wave (enough to amortise a partial, whose stage-2 sum grows
-    // with the count, and keep the prefetch pipeline busy), at most GRAM_BLOCKS partials:
-    // 4 workgroups per CU on large inputs
-    const int64_t steps = (n + 15) / 16;
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 32 * GRAM_WAVES)));
+    int nb = 1;  // stage-1 workgroups (partials), set by the launch
     const bool vec = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
                      (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     double* part =

@@ -93,18 +93,20 @@ def test_radon_adjoint_identity_fp64(B):
 
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
-def test_blur(B, which):
+@pytest.mark.parametrize("ksize,sigma", [(9, 2.0), (5, 1.0)])   # compiled-in 9-tap path and the general one
+def test_blur(B, which, ksize, sigma):
     import torch
     dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
     us = _rand_stack(13)
     if dt == torch.float32:
         us = [roundtrip32(u) for u in us]
-    plan = B.plan_blur(B.Stack(SIZES), 9, 2.0)
+    plan = B.plan_blur(B.Stack(SIZES), ksize, sigma)
     y = host(B.apply_A(plan, dev(pack(us), dt)))
-    exp = pack([forward.blur(u) for u in us])
-    assert rel(y, exp, pack([forward.blur(np.abs(u)) for u in us])) < tol
+    exp = pack([forward.blur(u, ksize, sigma) for u in us])
+    sc = pack([forward.blur(np.abs(u), ksize, sigma) for u in us])
+    assert rel(y, exp, sc) < tol
     y2 = host(B.apply_At(plan, dev(pack(us), dt)))
-    assert rel(y2, pack([forward.blur_adj(u) for u in us]), pack([forward.blur(np.abs(u)) for u in us])) < tol
+    assert rel(y2, pack([forward.blur_adj(u, ksize, sigma) for u in us]), sc) < tol
 
 
 # --------------------------------------------------------------------------- gradient
