@@ -191,6 +191,23 @@ def large_solve(B, torch, k_ref=30, k_cap=40):
         log(f"large {name}: {out[name]}")
     free, total = torch.cuda.mem_get_info()
     out["hbm_used_gb"] = round((total - free) / 1e9, 1)
+    # the FP64 Krylov kernels at this size: HIP-event time and algorithmic bytes of every
+    # launch of one kernel over one FP32 solve of k_ref iterations (one solve per kernel)
+    ctx = plan.ctx
+    kry = {}
+    prm["k_max"] = k_ref
+    for kname in ("wgram", "mdot", "gemv_mdot", "gemv"):
+        ctx.profile_kernel(kname)
+        B.solve_joint(plan, b, delta, u_true=u_true, op_dtype="f32", **prm)
+        torch.cuda.synchronize()
+        nl, ms, by, fl = ctx.kernel_timing()
+        ctx.profile_kernel(None)
+        if nl:
+            sec = ms * 1e-3
+            kry[kname] = {"launches": nl, "avg_us": round(ms * 1e3 / nl, 1), "GB/s": round(by / sec / 1e9, 1),
+                          "hbm_frac": round(by / sec / 1e9 / HBM_PEAK_GBS, 3), "TFLOP/s": round(fl / sec / 1e12, 2)}
+    out["krylov_kernels"] = kry
+    log(f"large krylov kernels: {kry}")
     return out
 
 

@@ -275,7 +275,7 @@ __global__ void k_axpy_conv(int64_t n, const TX* __restrict__ in, const double* 
 // are combined in LDS in a fixed order); stage 2 sums the partials in a fixed order.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-static constexpr int GRAM_WAVES = 16;      // most waves per stage-1 workgroup (8 for G = 4: registers)
+static constexpr int GRAM_WAVES = 16;      // most waves per stage-1 workgroup (8 for G >= 3: registers)
 static constexpr int GRAM_BLOCKS = 1024;   // most stage-1 workgroups (partials)
 static constexpr int GRAM_PAIRS = 10;      // upper blocks of a 4x4 block grid
 static constexpr int GRAM_SLAB = 64;       // partial entries per stage-2 workgroup
@@ -618,9 +618,15 @@ void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double*
     }
     const dim3 grid = grid_for(n, KB, 2048);
     double* part = sq ? static_cast<double*>(c.work("gemv_part", sizeof(double) * 2048)) : nullptr;
-    hipLaunchKernelGGL((k_gemv_fused<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta, out_d,
-                       out_t, cv, part);
-    MMOF_LAUNCH_CHECK();
+    {
+        // K columns and y (if any) read, the outputs written, cv read when given
+        const double bytes = (double)n * ((double)sizeof(TX) * K + (y ? 8.0 : 0.0) + (out_d ? 8.0 : 0.0) +
+                                          (out_t ? (double)sizeof(TO) : 0.0) + (cv ? 8.0 : 0.0));
+        ScopedTime st(&c, "gemv", bytes, 2.0 * n * K);
+        hipLaunchKernelGGL((k_gemv_fused<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta, out_d,
+                           out_t, cv, part);
+        MMOF_LAUNCH_CHECK();
+    }
     if (sq) {
         hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c.stream, (int)grid.x, (const double*)part, sq);
         MMOF_LAUNCH_CHECK();
@@ -682,7 +688,7 @@ template <class TX, int G, bool VEC>
 static void wgram_launch(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* part, int& nb) {
     // 16 waves per workgroup where the registers allow (4 per SIMD, to overlap the loads with
     // the matrix-core work), about 16 16-row steps per wave, at most GRAM_BLOCKS partials
-    constexpr int W = (sizeof(TX) == 4 && G <= 3) ? 16 : 8;
+    constexpr int W = (sizeof(TX) == 4 && G <= 2) ? 16 : 8;
     const int64_t steps = (n + 15) / 16;
     nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 16 * W)));
     hipLaunchKernelGGL((k_wgram_part<TX, G, VEC, W>), dim3(nb), dim3(64 * W), 0, c.stream, n, K, X, ld, w, part);
@@ -691,10 +697,13 @@ static void wgram_launch(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, cons
 template <class TX, int G>
 static void wgram_launch_g(Ctx& c, int& nb, bool vec, int64_t n, int K, const TX* X, int64_t ld, const double* w,
                            double* part) {
-    if (vec)
-        wgram_launch<TX, G, true>(c, n, K, X, ld, w, part, nb);
-    else
-        wgram_launch<TX, G, false>(c, n, K, X, ld, w, part, nb);
+    if constexpr (sizeof(TX) == 4) {
+        if (vec) {
+            wgram_launch<TX, G, true>(c, n, K, X, ld, w, part, nb);
+            return;
+        }
+    }
+    wgram_launch<TX, G, false>(c, n, K, X, ld, w, part, nb);
 }
 
 template <class TX>
@@ -703,7 +712,9 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
     const int Gb = (K + 15) / 16;
     const int np = Gb * (Gb + 1) / 2;
     int nb = 1;  // stage-1 workgroups (partials), set by the launch
-    const bool vec = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+    // (vector loads for FP32 columns; FP64 columns load a double per row, which keeps the
+    // row buffers in registers)
+    const bool vec = sizeof(TX) == 4 && (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
                      (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     double* part =
         static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * GRAM_PAIRS * 256));
