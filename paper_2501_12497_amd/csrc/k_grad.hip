@@ -91,11 +91,12 @@ __global__ __launch_bounds__(256) void k_grad_adj(const Tile* __restrict__ tiles
 // Vector form, for stacks whose frame widths are multiples of 4: each thread owns 4
 // consecutive pixels of RPT consecutive rows, so image and gy rows move as whole 16-byte
 // (FP32) or 2 x 16-byte (FP64) accesses and every wave keeps 4x more bytes in flight than
-// with one pixel per lane.  A row of the tile is LW lanes (4*LW pixels) wide; gx rows
-// (stride nx-1, not 4-aligned) move as single values.  The pixel right of a thread's four
-// (forward) or the gx value left of them (adjoint) comes from the neighbouring lane, or from
-// memory at the edge of a lane row.  Values and summation order equal those of the scalar
-// kernels above.
+// with one pixel per lane.  A row of the tile is LW lanes (4*LW pixels) wide.  gx rows
+// (stride nx-1) are not 4-aligned: the forward kernel realigns its gx values across lanes
+// and stores aligned vectors; the adjoint reads gx as single values.  The pixel right of a
+// thread's four (forward) or the gx value left of them (adjoint) comes from the neighbouring
+// lane, or from memory at the edge of a lane row.  Values and summation order equal those
+// of the scalar kernels above.
 template <class T, int LW, int RPT>
 __global__ __launch_bounds__(256) void k_grad_fwd4(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                    const T* __restrict__ u, const T* __restrict__ wx,
@@ -117,12 +118,41 @@ __global__ __launch_bounds__(256) void k_grad_fwd4(const Tile* __restrict__ tile
         // pixel x + 4: the next lane's first pixel (same row, live whenever x + 4 < nx)
         T right = __shfl_down(c.v[0], 1);
         if (lx == LW - 1 && x + 4 < nx) right = uf[p + 4];
-        const int64_t o = f.gx_off + (int64_t)y * (nx - 1) + x;
+        T d[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j == 3 && x + 4 >= nx) break;
-            const T d = (j < 3 ? c.v[j + 1] : right) - c.v[j];
-            gx[o + j] = wx ? wx[o + j] * d : d;
+        for (int j = 0; j < 4; ++j) d[j] = (j < 3 ? c.v[j + 1] : right) - c.v[j];
+        // The lane row's n_el gx values start at element B of gx (rows of nx - 1 values, so B
+        // is rarely 4-aligned): lane lx stores the aligned 4 values from element
+        // B + t0 + 4 lx on, taking the ones past its own from the next lane; the t0 values
+        // before the first aligned element and the short tail go out singly.
+        const int64_t B = f.gx_off + (int64_t)y * (nx - 1) + tl.x0;
+        const int n_el = min(4 * LW, nx - 1 - tl.x0);
+        const int t0 = (int)((4 - (B & 3)) & 3);
+        T sh[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sh[j] = __shfl_down(d[j], 1);
+        Quad<T> g;  // values of elements B + t0 + 4 lx + i
+        if (t0 == 0) g = Quad<T>{{d[0], d[1], d[2], d[3]}};
+        else if (t0 == 1) g = Quad<T>{{d[1], d[2], d[3], sh[0]}};
+        else if (t0 == 2) g = Quad<T>{{d[2], d[3], sh[0], sh[1]}};
+        else g = Quad<T>{{d[3], sh[0], sh[1], sh[2]}};
+        const int e0 = t0 + 4 * lx;  // first element of the lane's aligned group
+        if (e0 + 3 < n_el) {
+            if (wx) {
+                const Quad<T> w = ld4(wx + B + e0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) g.v[i] = w.v[i] * g.v[i];
+            }
+            st4(gx + B + e0, g);
+        } else if (e0 < n_el) {  // the tail (fewer than 4 values)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (e0 + i < n_el) gx[B + e0 + i] = wx ? wx[B + e0 + i] * g.v[i] : g.v[i];
+        }
+        if (lx == 0) {  // the head, before the first aligned element
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (i < t0 && i < n_el) gx[B + i] = wx ? wx[B + i] * d[i] : d[i];
         }
         Quad<T> below = zero4<T>();
         if (y < ny - 1) {
@@ -251,7 +281,7 @@ void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, con
         // u read, gx and gy written, weights read when given
         const double bytes = sizeof(T) * ((double)g.n + (wx ? 2.0 : 1.0) * g.gx_len + (wy ? 2.0 : 1.0) * g.gy_len);
         ScopedTime st(&c, "grad_fwd", bytes, (wx ? 2.0 : 1.0) * g.gx_len + (wy ? 2.0 : 1.0) * g.gy_len);
-        if (g.vec4 && aligned_to(4 * sizeof(T), {u, wy, gy})) {
+        if (g.vec4 && aligned_to(4 * sizeof(T), {u, wx, wy, gx, gy})) {
             const Grad4Shape sh = kGrad4Shapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), false);
             hipLaunchKernelGGL(grad_fwd4_kernel<T>(choice), dim3((unsigned)tl.count), dim3(64 * sh.nw), 0, c.stream,
