@@ -75,15 +75,26 @@ __device__ bool chol(SmallLds& s, int K, double lam, double* inv) {
     const int i = threadIdx.x;
     const int nbk = (K + 15) >> 4;
     const int KP = nbk << 4;
-    for (int c = 0; c < KP; ++c)
-        if (c <= i && i < KP) s.L[i][c] = (i < K && c < K) ? s.A[i][c] + lam * s.T[i][c] : (i == c ? 1.0 : 0.0);
+    // M = A + lam T with the identity on the padded diagonal (A and T are zero outside
+    // K x K); whole rows, without branches, so the LDS loads of 16 columns go out together
+    const double pad = i >= K ? 1.0 : 0.0;
+    for (int c0 = 0; c0 < KP; c0 += 16) {
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+            const int c = c0 + cc;
+            s.L[i][c] = fma(lam, s.T[i][c], s.A[i][c]) + (i == c ? pad : 0.0);
+        }
+    }
     __syncthreads();
     double my_inv = 0.0;
     for (int J = 0; J < nbk; ++J) {
         const int c0 = J << 4;
         double a[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) a[c] = (i >= c0 + c && i < KP) ? s.L[i][c0 + c] : 0.0;
+        for (int c = 0; c < 16; ++c) {
+            const double v = s.L[i][c0 + c];  // (every row is in the array: loads without branches)
+            a[c] = (i >= c0 + c && i < KP) ? v : 0.0;
+        }
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             const double piv = bcast(a[c], c0 + c);
@@ -95,9 +106,9 @@ __device__ bool chol(SmallLds& s, int K, double lam, double* inv) {
 #pragma unroll
             for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= l * bcast(l, c0 + c2);
         }
+        // (the entries above the diagonal become zero; nothing reads them)
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
-            if (i >= c0 + c && i < KP) s.L[i][c0 + c] = a[c];
+        for (int c = 0; c < 16; ++c) s.L[i][c0 + c] = a[c];
         __syncthreads();
         // trailing update of the lower blocks (I, J'), J < J' <= I
         const int lr = i & 15, lk = i >> 4;
