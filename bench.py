@@ -254,6 +254,50 @@ def ragged_blur(B, torch, reps=2):
     return out
 
 
+def autograd_step(B, torch, reps=10):
+    """The differentiation workload (256x256x16, Radon with 30 angles, a smooth flow of up to
+    3 px): one forward and backward pass of f(u, v) = <w1, H u> + <w2, Psi u> + <w3, L(v) u>
+    through the library's autograd functions (backward = the adjoint kernels and dL/dv), FP32
+    and FP64; wall time per pass, median of `reps` after a warm-up."""
+    from paper_2501_12497_amd import autograd as AG
+    from synth import cfg_autograd256
+    wl = cfg_autograd256()
+    s = wl.seqs[0]
+    n_t, n = s.n_t, s.ny
+    stack = B.Stack.single(n_t, n, n)
+    plan = B.plan_radon(stack, [s.angles.shape[1]], [s.n_bins], s.angles.ravel())
+    r = np.random.default_rng(wl.params["loss_seed"])
+    ws = [r.standard_normal(sh) for sh in ((n_t, s.angles.shape[1], s.n_bins), (n_t, n, n - 1), (n_t, n - 1, n),
+                                            (n_t - 1, n, n))]
+    out = {"workload": "autograd256: 256x256x16, 30 angles/frame, 363 bins, smooth flow |v| <= 3 px; "
+                       "loss <w1,Hu> + <w2,Psi u> + <w3,L(v)u>, gradients in u and v"}
+    for dt in (torch.float32, torch.float64):
+        wt = [torch.as_tensor(w.ravel(), dtype=dt, device="cuda") for w in ws]
+        u0 = torch.as_tensor(s.u_true.ravel(), dtype=dt, device="cuda")
+        v0 = torch.as_tensor(np.asarray(wl.params["flow"]).ravel(), dtype=dt, device="cuda")
+
+        def step():
+            u = u0.clone().requires_grad_(True)
+            v = v0.clone().requires_grad_(True)
+            b = AG.forward_op(u, plan)
+            gx, gy = AG.gradient_op(u, stack)
+            rr = AG.flow_op(u, v, stack, 1)
+            f = (wt[0] * b).sum() + (wt[1] * gx).sum() + (wt[2] * gy).sum() + (wt[3] * rr).sum()
+            f.backward()
+            return u.grad, v.grad
+        step()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out["f32" if dt == torch.float32 else "f64"] = {"ms_per_forward_backward": round(float(np.median(ts)) * 1e3, 3)}
+    log(f"autograd: {out}")
+    return out
+
+
 def solve_params(wl, op, graph=True):
     p = wl.params
     return dict(ell=p["ell"], k_max=p["k_max"], tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
@@ -321,6 +365,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the operator table at 1024x1024x64")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tile shapes")
     ap.add_argument("--no-ragged", action="store_true", help="skip the batched-deblurring (40 sequences) solves")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd forward/backward timing")
     ap.add_argument("--no-large-solve", action="store_true",
                     help="skip the FP64 / FP32 / FP32+refined solves of the 1024x1024x64 workload")
     ap.add_argument("--graph", action="store_true",
@@ -433,6 +478,10 @@ def main():
     if not a.no_ragged:
         ragged = ragged_blur(B, torch)
 
+    agrad = None
+    if not a.no_autograd:
+        agrad = autograd_step(B, torch)
+
     big = None
     if not a.no_large_solve:
         big = large_solve(B, torch)
@@ -465,6 +514,8 @@ def main():
     }
     if ragged is not None:
         out["ragged_blur"] = ragged
+    if agrad is not None:
+        out["autograd"] = agrad
     if big is not None:
         out["time_to_solution_large"] = big
     print(json.dumps(out))
