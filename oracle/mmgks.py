@@ -63,12 +63,13 @@ class StackOps:
     """H, Theta and the flow update over a batch of sequences stored one after another."""
 
     def __init__(self, seqs: List[SeqGeom], op: str, use_flow: bool = True, use_reverse: bool = True,
-                 interp: str = "bilinear"):
+                 interp: str = "bilinear", flow_scale: int = 1):
         self.seqs = seqs
         self.op = op
         self.use_flow = use_flow
         self.use_reverse = use_reverse
         self.interp = interp
+        self.flow_scale = flow_scale  # flow computed on frames reduced by this factor
         self.n = sum(s.n for s in seqs)
         self.m = sum(s.m for s in seqs)
         self._mats = {}
@@ -124,7 +125,7 @@ class StackOps:
     def update_flows(self, u, flows, alpha, n_sweeps, dr):
         out = []
         for us, (v, _) in zip(self.split_u(u), flows):
-            vn = optflow.flow_update(us, v, alpha, n_sweeps, dr)
+            vn = optflow.flow_update_scaled(us, v, alpha, n_sweeps, dr, self.flow_scale)
             vr = optflow.reverse_flow(vn) if self.use_reverse else np.zeros_like(vn)
             out.append((vn, vr))
         return out

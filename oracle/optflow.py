@@ -22,6 +22,14 @@ with D the first differences of regops (no boundary rows) is decreased by exact
   s_new(p) = sbar - g (g . sbar + I_t) / (gamma d_p + |g|^2),   g = (I_x, I_y).
 Horn-Schunck's alpha weights the smoothness term by alpha^2, so gamma = alpha^2.
 
+Flow on rescaled frames (Sec. 4.2, cost reduction; Sec. 5 downsamples by 2 or 4 before
+every flow computation and upscales the velocities).  The paper names no filters.
+Reading, for a factor f: frames are reduced by f x f block means (a block at the right or
+bottom edge averages its in-frame pixels only, so sizes become ceil(n / f)); the solver's
+current flow is reduced the same way and divided by f as the warm start; the sweeps run on
+the reduced pair; the result is sampled bilinearly at the reduced-grid position of every
+pixel centre, ((x + 1/2) / f - 1/2, clamped to the grid), and multiplied by f.
+
 Reverse flow (Remark on estimating the reverse optical flow): s'(r + s(r), t+1) =
 -s(r, t), with r + s(r) rounded half-to-even to a pixel.  The paper is silent on
 collisions and holes: all contributions to a pixel are averaged, pixels that
@@ -130,6 +138,51 @@ def flow_update(u: np.ndarray, v: np.ndarray, alpha: float, n_sweeps: int, dr: i
             s = hs_sweep(I[t], s, gamma)
         out[t] = s
     return out
+
+
+# ------------------------------------------------------------------ rescaled flow
+
+
+def box_down(u: np.ndarray, f: int) -> np.ndarray:
+    """f x f block means of the last two axes; edge blocks average their in-frame pixels."""
+    ny, nx = u.shape[-2:]
+    nys, nxs = -(-ny // f), -(-nx // f)
+    out = np.zeros(u.shape[:-2] + (nys, nxs))
+    for by in range(nys):
+        for bx in range(nxs):
+            blk = u[..., by * f:min(by * f + f, ny), bx * f:min(bx * f + f, nx)]
+            out[..., by, bx] = blk.sum(axis=(-2, -1)) / (blk.shape[-2] * blk.shape[-1])
+    return out
+
+
+def flow_up(vs: np.ndarray, f: int, ny: int, nx: int) -> np.ndarray:
+    """f times the bilinear sample of vs [..., nys, nxs] at ((x + 1/2)/f - 1/2, (y + 1/2)/f - 1/2),
+    positions clamped to the reduced grid -> [..., ny, nx]."""
+    nys, nxs = vs.shape[-2:]
+    out = np.zeros(vs.shape[:-2] + (ny, nx))
+    for y in range(ny):
+        Y = min(max((y + 0.5) / f - 0.5, 0.0), nys - 1.0)
+        y0 = min(int(np.floor(Y)), nys - 1)
+        y1 = min(y0 + 1, nys - 1)
+        fy = Y - y0
+        for x in range(nx):
+            X = min(max((x + 0.5) / f - 0.5, 0.0), nxs - 1.0)
+            x0 = min(int(np.floor(X)), nxs - 1)
+            x1 = min(x0 + 1, nxs - 1)
+            fx = X - x0
+            out[..., y, x] = f * ((1 - fy) * ((1 - fx) * vs[..., y0, x0] + fx * vs[..., y0, x1]) +
+                                  fy * ((1 - fx) * vs[..., y1, x0] + fx * vs[..., y1, x1]))
+    return out
+
+
+def flow_update_scaled(u: np.ndarray, v: np.ndarray, alpha: float, n_sweeps: int, dr: int = 1,
+                       f: int = 1) -> np.ndarray:
+    """flow_update on frames reduced by f (f = 1: flow_update itself)."""
+    if f == 1:
+        return flow_update(u, v, alpha, n_sweeps, dr)
+    ny, nx = u.shape[-2:]
+    vs = flow_update(box_down(u, f), box_down(v, f) / f, alpha, n_sweeps, dr)
+    return flow_up(vs, f, ny, nx)
 
 
 # ----------------------------------------------------------------------- reverse flow

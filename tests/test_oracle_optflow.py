@@ -7,6 +7,9 @@ Horn-Schunck sweeps: their fixed point solves the normal equations of the p = q 
 flow energy (eq. of_reg), checked against a sparse direct solve; a flat image (no
 gradient) reduces the sweep to neighbour averaging.
 Reverse flow: a uniform integer translation reverses exactly where pixels land.
+Rescaled flow: block means exact (edge blocks over in-frame pixels), bilinear upscaling
+reproduces constant and linear fields times f, f = 1 is the plain update, and a pattern
+translating by 2 px/frame gets a flow of about 2 px through frames reduced by 2.
 """
 import numpy as np
 import pytest
@@ -83,3 +86,55 @@ def test_reverse_flow_collisions_are_averaged():
     v[0, 0, 0] = [1.0, 0.0, 0.4, -2.0]   # pixels 0 and 1 both land on x = 1; 2 -> 2; 3 -> 1
     vr = optflow.reverse_flow(v)
     np.testing.assert_allclose(vr[0, 0, 0], [0.0, -(1.0 + 0.0 - 2.0) / 3.0, -0.4, 0.0])
+
+
+# --------------------------------------------------------------------------- rescaled flow
+
+
+def test_box_down_block_means_and_edges():
+    """Exact block means, and edge blocks over their in-frame pixels only (5 -> 3 at f = 2)."""
+    u = np.arange(25, dtype=float).reshape(5, 5)
+    d = optflow.box_down(u, 2)
+    assert d.shape == (3, 3)
+    assert d[0, 0] == (0 + 1 + 5 + 6) / 4
+    assert d[0, 2] == (4 + 9) / 2            # right edge: one column
+    assert d[2, 0] == (20 + 21) / 2          # bottom edge: one row
+    assert d[2, 2] == 24.0                   # corner: one pixel
+    # a linear ramp reduces to its values at the block centres when f divides the size
+    y, x = np.mgrid[0:8, 0:12]
+    ramp = 0.5 * x - 0.25 * y + 3.0
+    yc, xc = np.mgrid[0:2, 0:3]
+    np.testing.assert_allclose(optflow.box_down(ramp, 4), 0.5 * (4 * xc + 1.5) - 0.25 * (4 * yc + 1.5) + 3.0,
+                               rtol=0, atol=1e-13)
+
+
+def test_flow_up_constant_and_linear():
+    """Upscaling multiplies by f; bilinear sampling reproduces a field linear in the reduced
+    coordinates away from the clamped border."""
+    f, nys, nxs = 4, 5, 6
+    c = np.full((2, nys, nxs), 0.75)
+    np.testing.assert_allclose(optflow.flow_up(c, f, nys * f, nxs * f), 3.0, rtol=0, atol=1e-14)
+    Y, X = np.mgrid[0:nys, 0:nxs]
+    lin = np.stack([0.3 * X - 0.1 * Y, 0.05 * X + 0.2 * Y])
+    up = optflow.flow_up(lin, f, nys * f, nxs * f)
+    y, x = np.mgrid[0:nys * f, 0:nxs * f]
+    Xs, Ys = (x + 0.5) / f - 0.5, (y + 0.5) / f - 0.5
+    inside = (Xs >= 0) & (Xs <= nxs - 1) & (Ys >= 0) & (Ys <= nys - 1)
+    exp = f * np.stack([0.3 * Xs - 0.1 * Ys, 0.05 * Xs + 0.2 * Ys])
+    assert inside.sum() > 0.6 * inside.size
+    np.testing.assert_allclose(up[:, inside], exp[:, inside], rtol=0, atol=1e-13)
+
+
+def test_flow_update_scaled_reduces_to_plain_and_tracks_translation():
+    r = np.random.default_rng(3)
+    u = np.cumsum(np.cumsum(r.standard_normal((3, 24, 24)), axis=1), axis=2) * 0.05
+    v = r.uniform(-0.3, 0.3, size=(2, 2, 24, 24))
+    np.testing.assert_array_equal(optflow.flow_update_scaled(u, v, 0.2, 7, 1, 1), optflow.flow_update(u, v, 0.2, 7, 1))
+    # a smooth pattern translating by 2 px/frame: on frames reduced by 2 the flow is about
+    # 1 px, and the upscaled flow about 2 px in the interior
+    yy, xx = np.mgrid[0:32, 0:32]
+    frames = np.stack([np.sin(0.25 * (xx - 2 * t)) + np.cos(0.2 * yy) for t in range(3)])
+    out = optflow.flow_update_scaled(frames, np.zeros((2, 2, 32, 32)), 0.05, 400, 1, 2)
+    # (u_{t+1}(x + 2) = u_t(x): the flow is +2 px in x and 0 in y)
+    assert abs(np.median(out[:, 0, 8:24, 8:24]) - 2.0) < 0.3
+    assert abs(np.median(out[:, 1, 8:24, 8:24])) < 0.3
