@@ -43,6 +43,8 @@ COMPUTE = {
     "grad_adj": ("alu", 157.3),
     "hs_multi": ("alu", 157.3),
     "of_derivs": ("alu", 157.3),
+    "box_down": ("alu", 157.3),
+    "flow_up": ("alu", 157.3),
     "mdot": ("alu", 78.6),          # FP64 vector ALU
 }
 # The committed HBM-traffic summary of a kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) and
@@ -129,6 +131,9 @@ def operators_large(B, torch, reps=5):
         "flow_adj": lambda: B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, 1, 0, None, v, r),
         "of_derivs": lambda: B.of_derivs(stack, u, 1),
         "hs_multi": lambda: B.flow_update(stack, u, w, alpha=0.1, n_sweeps=8, delta_r=1),
+        # frames and flow reduced by 4 (both block means) and the flow upscaled, no sweeps
+        "box_down": lambda: B.flow_update_scaled(stack, u, w, alpha=0.1, n_sweeps=0, delta_r=1, scale=4),
+        "flow_up": lambda: B.flow_update_scaled(stack, u, w, alpha=0.1, n_sweeps=0, delta_r=1, scale=4),
     }
     table = {}
     for name, f in ops.items():
@@ -148,9 +153,24 @@ def operators_large(B, torch, reps=5):
         if name == "hs_multi":
             ent["sweeps_per_launch"] = 8
         table[name] = ent
+    # one whole flow update (derivatives, 200 warm-started sweeps, reverse flow) on the full
+    # frames and on frames reduced by 2, 4 and the automatic factor: HIP-event time
+    upd = {}
+    vr = torch.empty_like(v)
+    for sc in (1, 2, 4, _lib.MMOF_FLOW_SCALE_AUTO):
+        f = lambda: B.flow_update_scaled(stack, u, w, alpha=0.1, n_sweeps=200, delta_r=1, scale=sc, v_rev=vr)
+        f()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(3):
+            f()
+        ev1.record()
+        torch.cuda.synchronize()
+        upd["auto" if sc < 0 else str(sc)] = round(ev0.elapsed_time(ev1) / 3, 3)
     del plan
     return {"workload": "large1024x1024x64: 12 moving/rotating ellipses, 90 golden-angle-shifted angles/frame, "
-                        "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "tiles": tuned, "kernels": table}
+                        "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "tiles": tuned, "kernels": table,
+            "flow_update_200_sweeps_ms_by_scale": upd}
 
 
 def large_solve(B, torch, k_ref=30, k_cap=40):

@@ -54,6 +54,8 @@ typedef enum { MMOF_F32 = 0, MMOF_F64 = 1 } mmof_dtype;
 /* warp interpolation */
 #define MMOF_INTERP_BILINEAR 0
 #define MMOF_INTERP_ROUND 1
+/* flow scale picked from the frame sizes (mmof_flow_update_scaled) */
+#define MMOF_FLOW_SCALE_AUTO (-1)
 
 typedef struct mmof_ctx_s* mmof_ctx;
 typedef struct mmof_plan_s* mmof_plan;
@@ -172,6 +174,23 @@ int mmof_of_derivs(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const v
 int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u,
                      void* v, void* v_rev, double alpha, int32_t n_sweeps, int32_t delta_r);
 
+/* The same flow update computed on frames reduced by `scale` (Sec. 4.2 suggests cheaper
+ * flow estimates; Sec. 5 reports flows computed on downscaled frames).  With f = scale:
+ *   1. u_s = f x f block means of every frame of u, v_s = block means of v divided by f
+ *      (reduced sides ceil(n / f); a block at the right or bottom border averages its
+ *      in-frame pixels);
+ *   2. the derivatives and n_sweeps Horn-Schunck sweeps of mmof_flow_update on (u_s, v_s);
+ *   3. v(y, x) = f * bilinear sample of v_s at ((x + 1/2)/f - 1/2, (y + 1/2)/f - 1/2),
+ *      the position clamped to the reduced grid.
+ * scale = 1 (or 0) is mmof_flow_update.  scale = MMOF_FLOW_SCALE_AUTO picks the smallest
+ * power of two that brings every frame side below 50 pixels (Sec. 5 reduces the frames by 2
+ * or 4 to below 50 x 50), at most 64.  Arguments, layouts and ownership as there; errors:
+ * MMOF_ERR_INVALID unless 1 <= scale <= 64 and 1 <= delta_r < every reduced frame side.
+ * Workspaces of the reduced frames live in the context. */
+int mmof_flow_update_scaled(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u,
+                            void* v, void* v_rev, double alpha, int32_t n_sweeps, int32_t delta_r,
+                            int32_t scale);
+
 /* Reverse flow (Remark on estimating the reverse optical flow): v_rev at
  * rint(p + v(p)) = -v(p), contributions to one pixel averaged, pixels that receive
  * none set to 0, targets outside the frame dropped. */
@@ -202,6 +221,9 @@ typedef struct {
     int32_t use_graph;    /* 1: replay the fixed launch sequences of an iteration (the flow  */
                           /* update and the residual's operator applications) from HIP      */
                           /* graphs captured on their second use and kept in the context    */
+    int32_t flow_scale;   /* >= 2: the flow is computed on frames reduced by this factor    */
+                          /* and upscaled (mmof_flow_update_scaled); 0 or 1: full frames;    */
+                          /* MMOF_FLOW_SCALE_AUTO: the factor that setting picks            */
 } mmof_solve_params;
 
 typedef struct {

@@ -325,14 +325,21 @@ def of_derivs(stack: Stack, u: torch.Tensor, delta_r: int = 1, out: Optional[tor
 def flow_update(stack: Stack, u: torch.Tensor, v: torch.Tensor, alpha: float, n_sweeps: int, delta_r: int = 1,
                 v_rev: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
     """Horn-Schunck sweeps, in place on v; fills v_rev with the reverse flow when given."""
+    return flow_update_scaled(stack, u, v, alpha, n_sweeps, delta_r, 1, v_rev, ctx)
+
+
+def flow_update_scaled(stack: Stack, u: torch.Tensor, v: torch.Tensor, alpha: float, n_sweeps: int,
+                       delta_r: int = 1, scale: int = 1, v_rev: Optional[torch.Tensor] = None,
+                       ctx: Optional[Context] = None) -> torch.Tensor:
+    """flow_update computed on frames reduced by `scale` and upscaled (in place on v)."""
     ctx = ctx or context()
     _need(u, stack.n, "u")
     _need(v, 2 * stack.n_pair_px, "v")
     if v_rev is not None:
         _need(v_rev, 2 * stack.n_pair_px, "v_rev")
     ctx.bind()
-    check(ctx.lib.mmof_flow_update(ctx.h, stack.ref, _dt(u, v, v_rev), _ptr(u), _ptr(v), _ptr(v_rev), float(alpha),
-                                   int(n_sweeps), int(delta_r)))
+    check(ctx.lib.mmof_flow_update_scaled(ctx.h, stack.ref, _dt(u, v, v_rev), _ptr(u), _ptr(v), _ptr(v_rev),
+                                          float(alpha), int(n_sweeps), int(delta_r), int(scale)))
     return v
 
 

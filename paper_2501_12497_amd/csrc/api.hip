@@ -1,4 +1,5 @@
 // extern "C" entry points: argument checks, error translation, dispatch to launchers.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -307,8 +308,8 @@ int mmof_of_derivs(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const v
     });
 }
 
-int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
-                     double alpha, int32_t n_sweeps, int32_t delta_r) {
+int mmof_flow_update_scaled(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v,
+                            void* v_rev, double alpha, int32_t n_sweeps, int32_t delta_r, int32_t scale) {
     return guarded(ctx, [&] {
         need(ctx, "ctx");
         need_dt(dt);
@@ -317,19 +318,28 @@ int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const
         MMOF_CHECK(alpha > 0 && std::isfinite(alpha), MMOF_ERR_INVALID, "alpha must be > 0");
         MMOF_CHECK(n_sweeps >= 0, MMOF_ERR_INVALID, "n_sweeps must be >= 0");
         Geom& g = ctx->geom(stack);
-        for (int s = 0; s < g.n_seq; ++s)
-            MMOF_CHECK(delta_r >= 1 && delta_r < g.nx[s] && delta_r < g.ny[s], MMOF_ERR_INVALID,
-                       "delta_r must be in [1, frame size)");
+        scale = resolve_flow_scale(g, scale);
+        check_flow_frames(g, scale, delta_r);
         if (g.n_pairs == 0) return MMOF_OK;
         const size_t es = dt == MMOF_F32 ? 4 : 8;
-        void* I = ctx->work("fu_I", es * 3 * g.pair_px);
-        void* tmp = ctx->work("fu_tmp", es * 2 * g.pair_px);
-        launch_of_derivs(*ctx, g, dt, u, I, delta_r);
-        if (launch_hs_sweeps(*ctx, g, dt, I, v, tmp, alpha * alpha, n_sweeps))
-            MMOF_HIP(hipMemcpyAsync(v, tmp, es * 2 * g.pair_px, hipMemcpyDeviceToDevice, ctx->stream));
+        Geom* gs = scale > 1 ? &reduced_geom(*ctx, g, scale) : nullptr;
+        const Geom& gw = gs ? *gs : g;
+        FlowWork w;
+        w.I = ctx->work("fu_I", es * 3 * gw.pair_px);
+        w.tmp = ctx->work("fu_tmp", es * 2 * gw.pair_px);
+        if (gs) {
+            w.us = ctx->work("fu_us", es * gw.n);
+            w.vs = ctx->work("fu_vs", es * 2 * gw.pair_px);
+        }
+        flow_update_core(*ctx, g, gs, dt, u, v, scale, alpha * alpha, n_sweeps, delta_r, w);
         if (v_rev) launch_reverse_flow(*ctx, g, dt, v, v_rev, nullptr);
         return MMOF_OK;
     });
+}
+
+int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
+                     double alpha, int32_t n_sweeps, int32_t delta_r) {
+    return mmof_flow_update_scaled(ctx, stack, dt, u, v, v_rev, alpha, n_sweeps, delta_r, 1);
 }
 
 int mmof_reverse_flow(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* v, void* v_rev) {
@@ -366,6 +376,7 @@ void mmof_solve_defaults(mmof_solve_params* p) {
     p->rre_target = 0.0;
     p->u_true = nullptr;
     p->use_graph = 0;
+    p->flow_scale = 1;
 }
 
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p, void* u_inout,
@@ -377,10 +388,7 @@ int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_s
         need(u_inout, "u_inout");
         MMOF_CHECK(std::isfinite(noise_norm) && noise_norm >= 0, MMOF_ERR_INVALID, "noise_norm must be >= 0");
         MMOF_CHECK(p->interp == MMOF_INTERP_BILINEAR || p->interp == MMOF_INTERP_ROUND, MMOF_ERR_INVALID, "bad interp");
-        if (p->use_flow)
-            for (int s = 0; s < A->geom->n_seq; ++s)
-                MMOF_CHECK(p->delta_r >= 1 && p->delta_r < A->geom->nx[s] && p->delta_r < A->geom->ny[s],
-                           MMOF_ERR_INVALID, "delta_r must be in [1, frame size)");
+        if (p->use_flow) check_flow_frames(*A->geom, resolve_flow_scale(*A->geom, p->flow_scale), p->delta_r);
         int rc = solve_joint(*A, static_cast<const double*>(b), noise_norm, *p, static_cast<double*>(u_inout), v_out,
                              v_rev_out, rep);
         if (rep) rep->status = rc;

@@ -215,6 +215,9 @@ struct Plan {
     // choice their launches depend on; they die with the plan (and its tile lists)
     std::map<std::string, CachedGraph> graphs;
     std::map<std::string, int> graph_seen;
+    // geometries of the frames reduced for the flow (by factor), owned by the plan so that
+    // captured graphs keep valid tile lists
+    std::map<int, std::unique_ptr<Geom>> reduced;
     Plan() = default;
     Plan(const Plan&) = delete;
     Plan& operator=(const Plan&) = delete;

@@ -1,8 +1,11 @@
 // Optical-flow subproblem kernels: App. C image derivatives, Horn-Schunck block-Jacobi
 // sweeps for the p = q = 2 flow energy (eq. of_reg), the reverse-flow estimate of the
 // Remark in Sec. 3, and the MM weights of Sec. 4.1.1.
+#include <vector>
+
 #include "dev.h"
 #include "kernels.h"
+#include "krylov.h"
 
 namespace mmof {
 
@@ -358,6 +361,144 @@ int launch_hs_sweeps(Ctx& c, Geom& g, int dt, const void* I, void* v, void* tmp,
         }
     });
     return parity;
+}
+
+// Block means over f x f blocks of the frames (mode 0) or of the two flow components of the
+// pairs, divided by f (mode 1); a block at the right or bottom edge averages its in-frame
+// pixels.  One thread per reduced pixel over the reduced geometry's tiles.
+template <class T>
+__global__ __launch_bounds__(256) void k_box_down(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ frs,
+                                                  const FrameInfo* __restrict__ fr, const T* __restrict__ in,
+                                                  T* __restrict__ out, int f, int mode) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo s = frs[tl.frame], b = fr[tl.frame];  // the reduced frame and its full frame
+    const int xs = tl.x0 + (int)(threadIdx.x % OTW), ys = tl.y0 + (int)(threadIdx.x / OTW);
+    if (xs >= s.nx || ys >= s.ny) return;
+    const int x0 = xs * f, y0 = ys * f;
+    const int x1 = min(x0 + f, b.nx), y1 = min(y0 + f, b.ny);
+    const T inv = T(1) / T((x1 - x0) * (y1 - y0));
+    const int ncomp = mode == 0 ? 1 : 2;
+    const int64_t npb = (int64_t)b.nx * b.ny, nps = (int64_t)s.nx * s.ny;
+    for (int comp = 0; comp < ncomp; ++comp) {
+        const T* src = mode == 0 ? in + b.off : in + 2 * b.pair_off + comp * npb;
+        T acc = T(0);
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) acc += src[(int64_t)y * b.nx + x];
+        T m = acc * inv;
+        if (mode == 1) m = m / T(f);
+        T* dst = mode == 0 ? out + s.off : out + 2 * s.pair_off + comp * nps;
+        dst[(int64_t)ys * s.nx + xs] = m;
+    }
+}
+
+// v = f * bilinear sample of the reduced flow at ((x + 1/2)/f - 1/2, (y + 1/2)/f - 1/2),
+// positions clamped to the reduced grid; one thread per full-resolution pair pixel.
+template <class T>
+__global__ __launch_bounds__(256) void k_flow_up(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                 const FrameInfo* __restrict__ frs, const T* __restrict__ vs,
+                                                 T* __restrict__ v, int f) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo b = fr[tl.frame], s = frs[tl.frame];
+    const int x = tl.x0 + (int)(threadIdx.x % OTW), y = tl.y0 + (int)(threadIdx.x / OTW);
+    if (x >= b.nx || y >= b.ny) return;
+    const double X = fmin(fmax((x + 0.5) / f - 0.5, 0.0), (double)(s.nx - 1));
+    const double Y = fmin(fmax((y + 0.5) / f - 0.5, 0.0), (double)(s.ny - 1));
+    const int xa = min((int)floor(X), s.nx - 1), ya = min((int)floor(Y), s.ny - 1);
+    const int xb = min(xa + 1, s.nx - 1), yb = min(ya + 1, s.ny - 1);
+    const T fx = (T)(X - xa), fy = (T)(Y - ya);
+    const int64_t npb = (int64_t)b.nx * b.ny, nps = (int64_t)s.nx * s.ny;
+    for (int comp = 0; comp < 2; ++comp) {
+        const T* q = vs + 2 * s.pair_off + comp * nps;
+        const T a00 = q[(int64_t)ya * s.nx + xa], a01 = q[(int64_t)ya * s.nx + xb];
+        const T a10 = q[(int64_t)yb * s.nx + xa], a11 = q[(int64_t)yb * s.nx + xb];
+        v[2 * b.pair_off + comp * npb + (int64_t)y * b.nx + x] =
+            T(f) * ((T(1) - fy) * ((T(1) - fx) * a00 + fx * a01) + fy * ((T(1) - fx) * a10 + fx * a11));
+    }
+}
+
+// The stack with every frame side ceil(n / f), handed to `use`.
+template <class F>
+static decltype(auto) with_reduced_stack(const Geom& g, int f, F&& use) {
+    std::vector<int32_t> ny(g.ny), nx(g.nx);
+    for (auto& v : ny) v = (v + f - 1) / f;
+    for (auto& v : nx) v = (v + f - 1) / f;
+    const mmof_stack s{g.n_seq, g.n_t.data(), ny.data(), nx.data()};
+    return use(&s);
+}
+
+Geom& reduced_geom(Ctx& c, const Geom& g, int f) {
+    return with_reduced_stack(g, f, [&](const mmof_stack* s) -> Geom& { return c.geom(s); });
+}
+
+std::unique_ptr<Geom> make_reduced_geom(const Geom& g, int f, hipStream_t st) {
+    return with_reduced_stack(g, f, [&](const mmof_stack* s) { return make_geom(s, st); });
+}
+
+int resolve_flow_scale(const Geom& g, int f) {
+    if (f == 0) return 1;
+    if (f != MMOF_FLOW_SCALE_AUTO) return f;
+    const int side = std::max(g.max_ny, g.max_nx);
+    int s = 1;
+    while (s < 64 && (side + s - 1) / s >= 50) s *= 2;
+    return s;
+}
+
+void check_flow_frames(const Geom& g, int f, int dr) {
+    MMOF_CHECK(f >= 1 && f <= 64, MMOF_ERR_INVALID, "flow scale must be in [1, 64]");
+    for (int s = 0; s < g.n_seq; ++s) {
+        const int ny = (g.ny[s] + f - 1) / f, nx = (g.nx[s] + f - 1) / f;
+        MMOF_CHECK(dr >= 1 && dr < nx && dr < ny, MMOF_ERR_INVALID,
+                   f == 1 ? "delta_r must be in [1, frame size)" : "delta_r must be in [1, reduced frame size)");
+    }
+}
+
+void launch_box_down(Ctx& c, Geom& g, Geom& gs, int dt, int mode, int f, const void* in, void* out) {
+    if (mode == 1 && gs.n_pairs == 0) return;
+    const TileList& tl = gs.tile_list(c.stream, OTW, OTH, mode == 1);
+    if (tl.count == 0) return;
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        const double px = mode == 0 ? (double)g.n : 2.0 * g.pair_px, pxs = mode == 0 ? (double)gs.n : 2.0 * gs.pair_px;
+        ScopedTime st(&c, "box_down", sizeof(T) * (px + pxs), px);
+        hipLaunchKernelGGL(k_box_down<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                           gs.dframes(), g.dframes(), (const T*)in, (T*)out, f, mode);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+void launch_flow_up(Ctx& c, Geom& g, Geom& gs, int dt, int f, const void* vs, void* v) {
+    if (g.n_pairs == 0) return;
+    const TileList& tl = g.tile_list(c.stream, OTW, OTH, true);
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        ScopedTime st(&c, "flow_up", sizeof(T) * 2.0 * (g.pair_px + gs.pair_px), 2.0 * 8.0 * g.pair_px);
+        hipLaunchKernelGGL(k_flow_up<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
+                           g.dframes(), gs.dframes(), (const T*)vs, (T*)v, f);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+void flow_update_core(Ctx& c, Geom& g, Geom* gs, int dt, const void* u, void* v, int f, double gamma, int n_sweeps,
+                      int dr, const FlowWork& w) {
+    if (g.n_pairs == 0) return;
+    MMOF_CHECK(f == 1 || gs, MMOF_ERR_INVALID, "reduced geometry missing");
+    Geom& gw = f > 1 ? *gs : g;  // the frames the sweeps run on
+    const void* uw = u;
+    void* vw = v;
+    if (f > 1) {
+        launch_box_down(c, g, gw, dt, 0, f, u, w.us);
+        launch_box_down(c, g, gw, dt, 1, f, v, w.vs);
+        uw = w.us;
+        vw = w.vs;
+    }
+    launch_of_derivs(c, gw, dt, uw, w.I, dr);
+    if (launch_hs_sweeps(c, gw, dt, w.I, vw, w.tmp, gamma, n_sweeps)) {
+        dispatch(dt, [&](auto z) {
+            using T = decltype(z);
+            convert<T, T>(c, 2 * gw.pair_px, (const T*)w.tmp, (T*)vw);
+        });
+    }
+    if (f > 1) launch_flow_up(c, g, gw, dt, f, w.vs, v);
 }
 
 void launch_reverse_flow(Ctx& c, Geom& g, int dt, const void* v, void* vr, const int32_t* d_radius) {

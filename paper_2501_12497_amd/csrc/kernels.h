@@ -42,6 +42,29 @@ void launch_of_derivs(Ctx& c, Geom& g, int dt, const void* u, void* I, int dr);
 int launch_hs_sweeps(Ctx& c, Geom& g, int dt, const void* I, void* v, void* tmp, double gamma, int n_sweeps);
 void launch_reverse_flow(Ctx& c, Geom& g, int dt, const void* v, void* vr, const int32_t* d_radius);
 
+// Flow on frames reduced by a factor f (Sec. 4.2): the geometry of the stack with every frame
+// side ceil(n / f) (cached in the context, or owned), block means of the frames (mode 0) or of the
+// flow, divided by f (mode 1), and the reduced flow upscaled bilinearly and multiplied by f.
+Geom& reduced_geom(Ctx& c, const Geom& g, int f);
+std::unique_ptr<Geom> make_reduced_geom(const Geom& g, int f, hipStream_t st);  // an owned copy
+// The factor a requested scale stands for: 0 -> 1, MMOF_FLOW_SCALE_AUTO -> the smallest power
+// of two (at most 64) that brings every frame side below 50 pixels, others unchanged.
+int resolve_flow_scale(const Geom& g, int f);
+// Raises MMOF_ERR_INVALID unless 1 <= f <= 64 and 1 <= dr < every side of the reduced frames.
+void check_flow_frames(const Geom& g, int f, int dr);
+void launch_box_down(Ctx& c, Geom& g, Geom& gs, int dt, int mode, int f, const void* in, void* out);
+void launch_flow_up(Ctx& c, Geom& g, Geom& gs, int dt, int f, const void* vs, void* v);
+// Workspace of one flow update: I and tmp sized for the frames the sweeps run on (the reduced
+// ones when f > 1), us / vs for the reduced frames and flow (unused when f = 1).
+struct FlowWork {
+    void *I = nullptr, *tmp = nullptr, *us = nullptr, *vs = nullptr;
+};
+// Derivatives and n_sweeps HS sweeps warm-started from v (updated in place), on the frames
+// reduced by f (gs = reduced_geom(g, f); f = 1: on the frames themselves, gs unused);
+// graph-safe (no memcpy nodes).
+void flow_update_core(Ctx& c, Geom& g, Geom* gs, int dt, const void* u, void* v, int f, double gamma, int n_sweeps,
+                      int dr, const FlowWork& w);
+
 // Elementwise.
 void launch_mm_weights(Ctx& c, int dt, int64_t n, const void* nu, double eps, void* w2);
 

@@ -126,8 +126,15 @@ std::unique_ptr<Geom> make_geom(const mmof_stack* s, hipStream_t st) {
 
 Geom& Ctx::geom(const mmof_stack* s) {
     MMOF_CHECK(s != nullptr, MMOF_ERR_INVALID, "stack is NULL");
-    for (auto& g : geoms)
-        if (g->same_as(*s)) return *g;
+    // most recently used last, so that a call holding the geometry it looked up first can
+    // look up a second one without evicting the first
+    for (size_t i = 0; i < geoms.size(); ++i)
+        if (geoms[i]->same_as(*s)) {
+            std::unique_ptr<Geom> hit = std::move(geoms[i]);
+            geoms.erase(geoms.begin() + (std::ptrdiff_t)i);
+            geoms.push_back(std::move(hit));
+            return *geoms.back();
+        }
     std::unique_ptr<Geom> g(new Geom());
     build_geom(*g, s, stream);
     if (geoms.size() >= 16) geoms.erase(geoms.begin());

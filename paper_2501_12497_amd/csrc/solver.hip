@@ -10,6 +10,7 @@
 //
 // Theta = [Psi; M-bar(v); M-bar'(v')] is stored row block after row block:
 // [gx (all frames) | gy (all frames) | forward flow rows | reverse flow rows].
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -57,6 +58,10 @@ struct Solver {
     // workspace
     double *V, *U, *r, *tmp_n, *tmp_m, *GA, *GT, *dvec, *z, *h, *sc, *res, *scal;
     TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *yW, *flow_v, *flow_vr, *flow_tmp, *I;
+    // flow on reduced frames: their geometry (owned by the plan), frames and flow
+    int fscale = 1;
+    Geom* gs = nullptr;
+    TX *flow_us = nullptr, *flow_vs = nullptr;
     double* w2;  // FP64 MM weights of the rows of Theta
     int32_t *rad_v, *rad_vr;
     double* host;  // pinned report staging
@@ -73,6 +78,12 @@ struct Solver {
         oRR = oRF + (flow ? g.pair_px : 0);
         R = oRR + ((flow && p.use_reverse) ? g.pair_px : 0);
         Kcap = p.ell + p.k_max - 1;
+        fscale = resolve_flow_scale(g, p.flow_scale);
+        if (flow && fscale > 1) {
+            auto& r = P.reduced[fscale];
+            if (!r) r = make_reduced_geom(g, fscale, c.stream);
+            gs = r.get();
+        }
     }
 
     // FP64 buffers (the Krylov state) are shared by both operator precisions, so an FP32
@@ -119,8 +130,13 @@ struct Solver {
         w2 = ws<double>("w2", R);
         flow_v = wsx("flow_v", 2 * g.pair_px);
         flow_vr = wsx("flow_vr", 2 * g.pair_px);
-        flow_tmp = wsx("flow_tmp", 2 * g.pair_px);
-        I = wsx("I", 3 * g.pair_px);
+        const Geom& gw = gs ? *gs : g;  // frames the flow sweeps run on
+        flow_tmp = wsx("flow_tmp", 2 * gw.pair_px);
+        I = wsx("I", 3 * gw.pair_px);
+        if (gs) {
+            flow_us = wsx("flow_us", gs->n);
+            flow_vs = wsx("flow_vs", 2 * gs->pair_px);
+        }
         rad_v = ws<int32_t>("rad_v", 64);
         rad_vr = ws<int32_t>("rad_vr", 64);
     }
@@ -227,10 +243,12 @@ struct Solver {
     }
     std::string graph_key(const char* what) const {
         char buf[512];
-        std::snprintf(buf, sizeof buf, "%s|%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%lld|%lld", what, dt,
+        std::snprintf(buf, sizeof buf,
+                      "%s|%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%a|%lld|%lld", what, dt,
                       (void*)u_op, (void*)I, (void*)flow_v, (void*)flow_tmp, (void*)flow_vr, (void*)rad_v,
                       (void*)rad_vr, (void*)vin_m, (void*)out_n, (void*)out_n2, (void*)w2, (void*)r, (void*)scal,
-                      p.interp, p.use_reverse, p.n_sweeps, p.delta_r, p.alpha, (long long)n, (long long)R);
+                      (void*)flow_us, (void*)flow_vs, p.interp, p.use_reverse, p.n_sweeps, p.delta_r, fscale,
+                      p.alpha, (long long)n, (long long)R);
         std::string key(buf);
         for (const auto& t : g.tuned) key += "|" + t.first + "=" + std::to_string(t.second);  // tile lists used
         return key;
@@ -372,9 +390,12 @@ struct Solver {
             // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
             if (flow && k % p.tau == 0) {
                 replayable(graph_key("flow"), [&] {
-                    launch_of_derivs(c, g, dt, u_op, I, p.delta_r);
-                    if (launch_hs_sweeps(c, g, dt, I, flow_v, flow_tmp, gamma, p.n_sweeps))
-                        convert<TX, TX>(c, 2 * g.pair_px, flow_tmp, flow_v);
+                    FlowWork w;
+                    w.I = I;
+                    w.tmp = flow_tmp;
+                    w.us = flow_us;
+                    w.vs = flow_vs;
+                    flow_update_core(c, g, gs, dt, u_op, flow_v, fscale, gamma, p.n_sweeps, p.delta_r, w);
                     launch_flow_radius(c, g, dt, flow_v, rad_v);
                     if (p.use_reverse) {
                         launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);

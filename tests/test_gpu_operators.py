@@ -286,6 +286,69 @@ def test_flow_update_and_reverse(B, which, layout):
     assert rel(host(vr), exp_r) < tol
 
 
+@pytest.mark.parametrize("which", ["f64", "f32"])
+@pytest.mark.parametrize("layout", ["ragged", "vec4"])
+@pytest.mark.parametrize("scale", [2, 3])
+def test_flow_update_scaled(B, which, layout, scale):
+    """The flow computed on frames reduced by `scale` (block means, warm start v/scale, HS on
+    the reduced frames, bilinear upscaling times scale) against the oracle; frame sides not
+    divisible by the scale leave partial border blocks."""
+    import torch
+    dt = torch.float64 if which == "f64" else torch.float32
+    sizes = LAYOUTS[layout]
+    r = np.random.default_rng(27)
+    us = [np.cumsum(np.cumsum(r.standard_normal(s), axis=1), axis=2) * 0.05 for s in sizes]
+    vs0 = _flows(28, 1.0, sizes)
+    if dt == torch.float32:
+        us, vs0 = [list(map(roundtrip32, a)) for a in (us, vs0)]
+    stack = B.Stack(sizes)
+    v = dev(pack(vs0), dt)
+    vr = torch.empty_like(v)
+    B.flow_update_scaled(stack, dev(pack(us), dt), v, alpha=0.3, n_sweeps=25, delta_r=1, scale=scale, v_rev=vr)
+    exp = [optflow.flow_update_scaled(u, v0, 0.3, 25, 1, scale) for u, v0 in zip(us, vs0)]
+    got = host(v)
+    assert rel(got, pack(exp)) < (TOL64 if dt == torch.float64 else 1e-4)
+    gshapes = [e.shape for e in exp]
+    exp_r = pack([optflow.reverse_flow(x) for x in unpack(got, gshapes)])
+    assert rel(host(vr), exp_r) < (TOL64 if dt == torch.float64 else TOL32)
+
+
+def test_flow_update_scaled_edges(B):
+    """scale 1 is the plain update bit for bit; a scale that leaves a reduced side <= delta_r
+    is rejected before any launch; frames that reduce to 2 x 2 still work."""
+    import torch
+    from paper_2501_12497_amd._lib import MMOFError
+    sizes = [(3, 9, 8), (2, 4, 7)]
+    r = np.random.default_rng(29)
+    us = [r.standard_normal(sz) for sz in sizes]
+    vs0 = [r.uniform(-1, 1, (sz[0] - 1, 2, sz[1], sz[2])) for sz in sizes]
+    stack = B.Stack(sizes)
+    u = dev(pack(us), torch.float64)
+    a, b = dev(pack(vs0), torch.float64), dev(pack(vs0), torch.float64)
+    B.flow_update(stack, u, a, alpha=0.2, n_sweeps=9, delta_r=1)
+    B.flow_update_scaled(stack, u, b, alpha=0.2, n_sweeps=9, delta_r=1, scale=1)
+    assert torch.equal(a, b)
+    c = dev(pack(vs0), torch.float64)
+    B.flow_update_scaled(stack, u, c, alpha=0.2, n_sweeps=9, delta_r=1, scale=3)   # (4,4,3,3) -> (3,3), (2,3)
+    exp = pack([optflow.flow_update_scaled(x, v0, 0.2, 9, 1, 3) for x, v0 in zip(us, vs0)])
+    assert rel(host(c), exp) < TOL64
+    # automatic factor: the smallest power of two that brings the sides below 50
+    big = [(2, 100, 120), (2, 30, 44)]
+    ub = dev(pack([r.standard_normal(sz) for sz in big]), torch.float64)
+    vb = pack([r.uniform(-1, 1, (sz[0] - 1, 2, sz[1], sz[2])) for sz in big])
+    got = {}
+    for sc in (-1, 2, 4):
+        got[sc] = dev(vb, torch.float64)
+        B.flow_update_scaled(B.Stack(big), ub, got[sc], alpha=0.2, n_sweeps=5, delta_r=1, scale=sc)
+    assert torch.equal(got[-1], got[4]) and not torch.equal(got[-1], got[2])
+    before = c.clone()
+    for sc, dr in ((4, 1), (2, 2), (65, 1), (-2, 1)):   # (2,4,7)/4 -> 1 x 2;  /2 -> 2 x 4 with dr 2
+        with pytest.raises(MMOFError) as e:
+            B.flow_update_scaled(stack, u, c, alpha=0.2, n_sweeps=9, delta_r=dr, scale=sc)
+        assert e.value.code == -1
+    assert torch.equal(c, before)
+
+
 @pytest.mark.parametrize("n_sweeps", [0, 1, 8, 9, 40])
 def test_flow_update_sweep_counts_small_frames(B, n_sweeps):
     """Sweep counts around the per-launch block of sweeps, on frames smaller than one tile

@@ -151,6 +151,41 @@ def test_solve_blur_ragged_fp64(B, sizes):
     assert np.linalg.norm(res.u.cpu().numpy() - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
 
 
+@pytest.mark.parametrize("op", ["f64", "f32"])
+def test_solve_blur_flow_on_reduced_frames(B, op):
+    """flow_scale = 2: every flow update runs on frames reduced by 2 (odd sides, so the
+    border blocks are partial) and is upscaled; the oracle's StackOps does the same."""
+    import torch
+    sizes = [(3, 25, 30), (4, 18, 21)]
+    us = []
+    for (nt, ny, nx) in sizes:
+        yy, xx = np.mgrid[0:ny, 0:nx]
+        us.append(np.stack([(((xx - (8.0 + 1.5 * t)) ** 2 + (yy - ny / 2) ** 2) <= 16.0).astype(float)
+                            for t in range(nt)]))
+    geoms = [mmgks.SeqGeom(nt, ny, nx) for (nt, ny, nx) in sizes]
+    ops = mmgks.StackOps(geoms, "blur", flow_scale=2)
+    ut = np.concatenate([u.ravel() for u in us])
+    clean = ops.A(ut)
+    b = noisy(clean, np.random.default_rng(7).standard_normal(clean.shape), 0.01)
+    delta = float(np.linalg.norm(b - clean))
+    prm = dict(ell=5, k_max=8, tau=3, n_sweeps=30, alpha=0.2)
+    ref = mmgks.mmgks_of(ops, b, delta, mmgks.SolveParams(**prm), u_true=ut)
+    plan = B.plan_blur(B.Stack(sizes), 9, 2.0)
+    res = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta, u_true=torch.as_tensor(ut, device="cuda"),
+                        op_dtype=op, flow_scale=2, **prm)
+    assert res.iters == ref.iters
+    assert abs(res.rre[-1] - ref.rre[-1]) <= 1e-4
+    if op == "f64":
+        np.testing.assert_allclose(res.lambdas, ref.lambdas, rtol=1e-7)
+        assert np.linalg.norm(res.u.cpu().numpy() - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
+        v_or = np.concatenate([fl[0].ravel() for fl in ref.flows])
+        assert np.linalg.norm(res.v.cpu().numpy() - v_or) <= 1e-6 * max(np.linalg.norm(v_or), 1e-30)
+    # graph replay of the reduced-frame flow update gives the eager result bit for bit
+    again = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta, u_true=torch.as_tensor(ut, device="cuda"),
+                          op_dtype=op, flow_scale=2, use_graph=1, **prm)
+    assert torch.equal(again.u, res.u) and again.lambdas == res.lambdas
+
+
 def test_solve_rejects_bad_arguments(B):
     import torch
     from paper_2501_12497_amd._lib import MMOFError
@@ -165,4 +200,10 @@ def test_solve_rejects_bad_arguments(B):
     assert e.value.code == -1
     with pytest.raises(MMOFError) as e:
         B.solve_joint(plan, b, 0.1, op_dtype="f32", refine_iters=-1)
+    assert e.value.code == -1
+    with pytest.raises(MMOFError) as e:
+        B.solve_joint(plan, b, 0.1, flow_scale=65)
+    assert e.value.code == -1
+    with pytest.raises(MMOFError) as e:   # 20 x 20 frames reduced by 10 leave no room for delta_r = 2
+        B.solve_joint(plan, b, 0.1, flow_scale=10, delta_r=2)
     assert e.value.code == -1
