@@ -167,10 +167,22 @@ def operators_large(B, torch, reps=5):
         ev1.record()
         torch.cuda.synchronize()
         upd["auto" if sc < 0 else str(sc)] = round(ev0.elapsed_time(ev1) / 3, 3)
+    # Solve-OF (GKS with GCV: 10 Golub-Kahan steps, 20 projected solves, one workgroup per
+    # pair) on the frames reduced by the automatic factor (32 x 32), with the reverse flow
+    f = lambda: B.flow_solve_gks(stack, u, w, delta_r=1, ell=10, n_iter=20, scale=_lib.MMOF_FLOW_SCALE_AUTO,
+                                 v_rev=vr)
+    f()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(3):
+        f()
+    ev1.record()
+    torch.cuda.synchronize()
+    upd["solve_of_auto"] = round(ev0.elapsed_time(ev1) / 3, 3)
     del plan
     return {"workload": "large1024x1024x64: 12 moving/rotating ellipses, 90 golden-angle-shifted angles/frame, "
                         "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "tiles": tuned, "kernels": table,
-            "flow_update_200_sweeps_ms_by_scale": upd}
+            "flow_update_ms": upd}
 
 
 def large_solve(B, torch, k_ref=30, k_cap=40):

@@ -56,6 +56,9 @@ typedef enum { MMOF_F32 = 0, MMOF_F64 = 1 } mmof_dtype;
 #define MMOF_INTERP_ROUND 1
 /* flow scale picked from the frame sizes (mmof_flow_update_scaled) */
 #define MMOF_FLOW_SCALE_AUTO (-1)
+/* flow solvers of the joint solve */
+#define MMOF_FLOW_HS 0
+#define MMOF_FLOW_GKS 1
 
 typedef struct mmof_ctx_s* mmof_ctx;
 typedef struct mmof_plan_s* mmof_plan;
@@ -191,6 +194,34 @@ int mmof_flow_update_scaled(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt
                             void* v, void* v_rev, double alpha, int32_t n_sweeps, int32_t delta_r,
                             int32_t scale);
 
+/* Solve-OF (Alg. 2) with p = q = 2, the paper's own flow solver: for every pair, with the
+ * App. C derivatives (delta_r) and Y = [diag(I_x) diag(I_y)], b = -I_t, L = blockdiag(D, D)
+ * (D: the first differences of mmof_apply_grad), the flow minimising
+ *   ||Y s - b||^2 + lambda ||L s||^2          (eq. subproblem_motion_estimation_redefined)
+ * by GKS (MMGKS with unit weights): `ell` Golub-Kahan steps on Y from b (both bases
+ * re-orthogonalised), then `n_iter` projected solves; before each, lambda minimises the GCV
+ * functional (eq. gcv_functional) of the projected solution V z,
+ *   G(lambda) = ||Y V z - b||^2 / (m - trace(M^-1 (Y V)^T Y V))^2,
+ *   M = (Y V)^T Y V + lambda (L V)^T L V, m = pixels of the pair,
+ * over x = log10 lambda by a grid search (32 points over c + [-12, 12], c = log10(||Y V||_F^2 /
+ * ||L V||_F^2), then 5 refinements of 8 points over [x* - h, x* + h], h the previous spacing;
+ * in increasing x a point wins only when it lowers G by more than a relative 1e-9);
+ * fixed_lambda > 0 skips the search.  Between solves the
+ * basis grows by the residual Y^T(Y s - b) + lambda L^T L s orthogonalised twice against it;
+ * the solve stops early when that residual vanishes (<= 1e-14 ||Y^T b||); Y^T b = 0 gives
+ * s = 0.  v [pairs][2][ny][nx] receives the flow (its previous content is not used); v_rev,
+ * if not NULL, the reverse flow of v.  scale > 1 computes on frames reduced as in
+ * mmof_flow_update_scaled (no warm start is reduced).  lambdas, if not NULL, is a HOST array
+ * [pairs][n_iter] that receives every lambda (0 after an early stop); the call then waits for
+ * the stream.  Arithmetic in FP64 (the derivatives in dt).  Errors: MMOF_ERR_INVALID unless
+ * ell >= 1, n_iter >= 1, ell + n_iter - 1 <= 32, fixed_lambda >= 0, every frame (reduced) has
+ * more than ell and fewer than 2^30 pixels, and delta_r and scale are as for
+ * mmof_flow_update_scaled.  Workspace (context-owned): about (2 (ell + n_iter) + 5) doubles
+ * per pixel of the pairs. */
+int mmof_flow_solve_gks(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u,
+                        void* v, void* v_rev, int32_t delta_r, int32_t ell, int32_t n_iter,
+                        double fixed_lambda, int32_t scale, double* lambdas);
+
 /* Reverse flow (Remark on estimating the reverse optical flow): v_rev at
  * rint(p + v(p)) = -v(p), contributions to one pixel averaged, pixels that receive
  * none set to 0, targets outside the frame dropped. */
@@ -224,6 +255,11 @@ typedef struct {
     int32_t flow_scale;   /* >= 2: the flow is computed on frames reduced by this factor    */
                           /* and upscaled (mmof_flow_update_scaled); 0 or 1: full frames;    */
                           /* MMOF_FLOW_SCALE_AUTO: the factor that setting picks            */
+    int32_t flow_solver;  /* MMOF_FLOW_HS: n_sweeps Horn-Schunck sweeps warm-started from    */
+                          /* the last flow (gamma = alpha^2); MMOF_FLOW_GKS: Solve-OF        */
+                          /* (mmof_flow_solve_gks, lambda by GCV)                           */
+    int32_t of_ell;       /* Solve-OF: Golub-Kahan steps (10)                               */
+    int32_t of_iters;     /* Solve-OF: projected solves per flow computation (20)           */
 } mmof_solve_params;
 
 typedef struct {

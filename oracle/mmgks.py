@@ -63,13 +63,18 @@ class StackOps:
     """H, Theta and the flow update over a batch of sequences stored one after another."""
 
     def __init__(self, seqs: List[SeqGeom], op: str, use_flow: bool = True, use_reverse: bool = True,
-                 interp: str = "bilinear", flow_scale: int = 1):
+                 interp: str = "bilinear", flow_scale: int = 1, flow_solver: str = "hs", of_ell: int = 10,
+                 of_iters: int = 20):
         self.seqs = seqs
         self.op = op
         self.use_flow = use_flow
         self.use_reverse = use_reverse
         self.interp = interp
         self.flow_scale = flow_scale  # flow computed on frames reduced by this factor
+        # "hs": warm-started Horn-Schunck sweeps; "gks": Solve-OF (Alg. 2, GKS with GCV)
+        self.flow_solver = flow_solver
+        self.of_ell = of_ell
+        self.of_iters = of_iters
         self.n = sum(s.n for s in seqs)
         self.m = sum(s.m for s in seqs)
         self._mats = {}
@@ -123,9 +128,13 @@ class StackOps:
         return [(np.zeros((s.n_t - 1, 2, s.ny, s.nx)), np.zeros((s.n_t - 1, 2, s.ny, s.nx))) for s in self.seqs]
 
     def update_flows(self, u, flows, alpha, n_sweeps, dr):
+        from . import solve_of
         out = []
         for us, (v, _) in zip(self.split_u(u), flows):
-            vn = optflow.flow_update_scaled(us, v, alpha, n_sweeps, dr, self.flow_scale)
+            if self.flow_solver == "gks":
+                vn = solve_of.solve_of(us, dr, self.of_ell, self.of_iters, 0.0, self.flow_scale)
+            else:
+                vn = optflow.flow_update_scaled(us, v, alpha, n_sweeps, dr, self.flow_scale)
             vr = optflow.reverse_flow(vn) if self.use_reverse else np.zeros_like(vn)
             out.append((vn, vr))
         return out

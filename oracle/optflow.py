@@ -159,20 +159,19 @@ def flow_up(vs: np.ndarray, f: int, ny: int, nx: int) -> np.ndarray:
     """f times the bilinear sample of vs [..., nys, nxs] at ((x + 1/2)/f - 1/2, (y + 1/2)/f - 1/2),
     positions clamped to the reduced grid -> [..., ny, nx]."""
     nys, nxs = vs.shape[-2:]
-    out = np.zeros(vs.shape[:-2] + (ny, nx))
-    for y in range(ny):
-        Y = min(max((y + 0.5) / f - 0.5, 0.0), nys - 1.0)
-        y0 = min(int(np.floor(Y)), nys - 1)
-        y1 = min(y0 + 1, nys - 1)
-        fy = Y - y0
-        for x in range(nx):
-            X = min(max((x + 0.5) / f - 0.5, 0.0), nxs - 1.0)
-            x0 = min(int(np.floor(X)), nxs - 1)
-            x1 = min(x0 + 1, nxs - 1)
-            fx = X - x0
-            out[..., y, x] = f * ((1 - fy) * ((1 - fx) * vs[..., y0, x0] + fx * vs[..., y0, x1]) +
-                                  fy * ((1 - fx) * vs[..., y1, x0] + fx * vs[..., y1, x1]))
-    return out
+    Y = np.minimum(np.maximum((np.arange(ny) + 0.5) / f - 0.5, 0.0), nys - 1.0)
+    X = np.minimum(np.maximum((np.arange(nx) + 0.5) / f - 0.5, 0.0), nxs - 1.0)
+    y0 = np.minimum(np.floor(Y).astype(np.int64), nys - 1)
+    x0 = np.minimum(np.floor(X).astype(np.int64), nxs - 1)
+    y1 = np.minimum(y0 + 1, nys - 1)
+    x1 = np.minimum(x0 + 1, nxs - 1)
+    fy = (Y - y0)[:, None]          # per row
+    fx = X - x0                     # per column
+    a00 = vs[..., y0[:, None], x0[None, :]]
+    a01 = vs[..., y0[:, None], x1[None, :]]
+    a10 = vs[..., y1[:, None], x0[None, :]]
+    a11 = vs[..., y1[:, None], x1[None, :]]
+    return f * ((1 - fy) * ((1 - fx) * a00 + fx * a01) + fy * ((1 - fx) * a10 + fx * a11))
 
 
 def flow_update_scaled(u: np.ndarray, v: np.ndarray, alpha: float, n_sweeps: int, dr: int = 1,

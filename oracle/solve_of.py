@@ -29,8 +29,10 @@ Readings (the paper is silent or garbled):
     lambda is the minimiser over x = log10 lambda found by a grid search: 32 points evenly
     over c + [-12, 12], c = log10(||Y V||_F^2 / ||L V||_F^2), then 5 refinements, each with 8
     points evenly over [x* - h, x* + h] (h: the previous spacing) around the best point so
-    far; a point replaces the best only with a strictly smaller G, points are visited in
-    increasing x, a G that is not finite (or an M that is not positive definite) never wins.
+    far; points are visited in increasing x and a point replaces the best only when its G is
+    smaller by more than a relative TIE (values closer than that are ties and the earlier
+    point stays: G is nearly flat towards small lambda, and the choice must not depend on
+    rounding); a G that is not finite (or an M that is not positive definite) never wins.
   * Y^T b = 0 (no temporal change, or none where the frame has a gradient) gives s = 0.
   * The reverse flow is not solved for: the Remark on the reverse optical flow forms it
     from s (optflow.reverse_flow).
@@ -45,6 +47,7 @@ GRID0 = 32          # points of the first grid
 REFINE = 5          # refinement stages
 GRID_R = 8          # points per refinement stage
 SPAN = 12.0         # decades on either side of the centre
+TIE = 1e-9          # relative improvement of G that a later point needs to win
 
 
 def pair_ops(I: np.ndarray):
@@ -98,7 +101,7 @@ def gcv_lambda(YV: np.ndarray, LV: np.ndarray, b: np.ndarray) -> float:
             h = 2.0 * h / (GRID_R - 1)
         for x in xs:
             g = gcv_value(YV, LV, b, 10.0 ** x)[0]
-            if g < best_g:
+            if g < best_g * (1.0 - TIE):
                 best_g, best_x = g, x
     return 10.0 ** best_x
 

@@ -14,6 +14,7 @@ MMOF_F32, MMOF_F64 = 0, 1
 MMOF_FLOW_FWD, MMOF_FLOW_ADJ, MMOF_FLOW_DV = 0, 1, 2
 MMOF_INTERP_BILINEAR, MMOF_INTERP_ROUND = 0, 1
 MMOF_FLOW_SCALE_AUTO = -1
+MMOF_FLOW_HS, MMOF_FLOW_GKS = 0, 1
 STATUS = {0: "OK", -1: "MMOF_ERR_INVALID", -2: "MMOF_ERR_SHAPE", -3: "MMOF_ERR_DTYPE", -4: "MMOF_ERR_HIP",
           -5: "MMOF_ERR_OOM", -6: "MMOF_ERR_NONFINITE", 1: "MMOF_WARN_KMAX", 2: "MMOF_WARN_DP_CLAMPED",
           3: "MMOF_WARN_BREAKDOWN"}
@@ -30,7 +31,8 @@ class mmof_solve_params(C.Structure):
                 ("interp", C.c_int32), ("op_dtype", C.c_int32), ("refine_iters", C.c_int32),
                 ("eps", C.c_double), ("eta", C.c_double), ("alpha", C.c_double), ("fixed_lambda", C.c_double),
                 ("rre_target", C.c_double), ("u_true", C.c_void_p), ("use_graph", C.c_int32),
-                ("flow_scale", C.c_int32)]
+                ("flow_scale", C.c_int32), ("flow_solver", C.c_int32), ("of_ell", C.c_int32),
+                ("of_iters", C.c_int32)]
 
 
 class mmof_report(C.Structure):
@@ -64,6 +66,8 @@ _SIGS = {
     "mmof_flow_update": (_I, [_P, C.POINTER(mmof_stack), _I, _P, _P, _P, C.c_double, C.c_int32, C.c_int32]),
     "mmof_flow_update_scaled": (_I, [_P, C.POINTER(mmof_stack), _I, _P, _P, _P, C.c_double, C.c_int32, C.c_int32,
                                      C.c_int32]),
+    "mmof_flow_solve_gks": (_I, [_P, C.POINTER(mmof_stack), _I, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32,
+                                 C.c_double, C.c_int32, _P]),
     "mmof_reverse_flow": (_I, [_P, C.POINTER(mmof_stack), _I, _P, _P]),
     "mmof_solve_defaults": (None, [C.POINTER(mmof_solve_params)]),
     "mmof_solve_joint": (_I, [_P, _P, C.c_double, C.POINTER(mmof_solve_params), _P, _P, _P,

@@ -308,18 +308,18 @@ int mmof_of_derivs(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const v
     });
 }
 
-int mmof_flow_update_scaled(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v,
-                            void* v_rev, double alpha, int32_t n_sweeps, int32_t delta_r, int32_t scale) {
-    return guarded(ctx, [&] {
+// The flow calls: checks, workspaces in the context, flow_update_core, the reverse flow.
+static int flow_call(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
+                     int32_t delta_r, int32_t scale, const FlowMethod& fm, double* lambdas) {
+    {
         need(ctx, "ctx");
         need_dt(dt);
         need(u, "u");
         need(v, "v");
-        MMOF_CHECK(alpha > 0 && std::isfinite(alpha), MMOF_ERR_INVALID, "alpha must be > 0");
-        MMOF_CHECK(n_sweeps >= 0, MMOF_ERR_INVALID, "n_sweeps must be >= 0");
         Geom& g = ctx->geom(stack);
         scale = resolve_flow_scale(g, scale);
         check_flow_frames(g, scale, delta_r);
+        if (fm.solver == 1) check_gks_frames(g, scale, fm.ell, fm.n_iter);
         if (g.n_pairs == 0) return MMOF_OK;
         const size_t es = dt == MMOF_F32 ? 4 : 8;
         Geom* gs = scale > 1 ? &reduced_geom(*ctx, g, scale) : nullptr;
@@ -331,9 +331,42 @@ int mmof_flow_update_scaled(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt
             w.us = ctx->work("fu_us", es * gw.n);
             w.vs = ctx->work("fu_vs", es * 2 * gw.pair_px);
         }
-        flow_update_core(*ctx, g, gs, dt, u, v, scale, alpha * alpha, n_sweeps, delta_r, w);
+        if (fm.solver == 1) w.gks = gks_work(*ctx, gw, fm, "fu_gks_");
+        flow_update_core(*ctx, g, gs, dt, u, v, scale, delta_r, fm, w);
         if (v_rev) launch_reverse_flow(*ctx, g, dt, v, v_rev, nullptr);
+        if (lambdas && fm.solver == 1) {
+            MMOF_HIP(hipMemcpyAsync(lambdas, w.gks.lam, sizeof(double) * gw.n_pairs * fm.n_iter,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+            MMOF_HIP(hipStreamSynchronize(ctx->stream));
+        }
         return MMOF_OK;
+    }
+}
+
+int mmof_flow_update_scaled(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v,
+                            void* v_rev, double alpha, int32_t n_sweeps, int32_t delta_r, int32_t scale) {
+    return guarded(ctx, [&] {
+        MMOF_CHECK(alpha > 0 && std::isfinite(alpha), MMOF_ERR_INVALID, "alpha must be > 0");
+        MMOF_CHECK(n_sweeps >= 0, MMOF_ERR_INVALID, "n_sweeps must be >= 0");
+        FlowMethod fm;
+        fm.solver = 0;
+        fm.gamma = alpha * alpha;
+        fm.n_sweeps = n_sweeps;
+        return flow_call(ctx, stack, dt, u, v, v_rev, delta_r, scale, fm, nullptr);
+    });
+}
+
+int mmof_flow_solve_gks(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
+                        int32_t delta_r, int32_t ell, int32_t n_iter, double fixed_lambda, int32_t scale,
+                        double* lambdas) {
+    return guarded(ctx, [&] {
+        MMOF_CHECK(fixed_lambda >= 0 && std::isfinite(fixed_lambda), MMOF_ERR_INVALID, "fixed_lambda must be >= 0");
+        FlowMethod fm;
+        fm.solver = 1;
+        fm.ell = ell;
+        fm.n_iter = n_iter;
+        fm.fixed_lambda = fixed_lambda;
+        return flow_call(ctx, stack, dt, u, v, v_rev, delta_r, scale, fm, lambdas);
     });
 }
 
@@ -377,6 +410,9 @@ void mmof_solve_defaults(mmof_solve_params* p) {
     p->u_true = nullptr;
     p->use_graph = 0;
     p->flow_scale = 1;
+    p->flow_solver = MMOF_FLOW_HS;
+    p->of_ell = 10;
+    p->of_iters = 20;
 }
 
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p, void* u_inout,
@@ -388,7 +424,13 @@ int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_s
         need(u_inout, "u_inout");
         MMOF_CHECK(std::isfinite(noise_norm) && noise_norm >= 0, MMOF_ERR_INVALID, "noise_norm must be >= 0");
         MMOF_CHECK(p->interp == MMOF_INTERP_BILINEAR || p->interp == MMOF_INTERP_ROUND, MMOF_ERR_INVALID, "bad interp");
-        if (p->use_flow) check_flow_frames(*A->geom, resolve_flow_scale(*A->geom, p->flow_scale), p->delta_r);
+        if (p->use_flow) {
+            const int f = resolve_flow_scale(*A->geom, p->flow_scale);
+            check_flow_frames(*A->geom, f, p->delta_r);
+            MMOF_CHECK(p->flow_solver == MMOF_FLOW_HS || p->flow_solver == MMOF_FLOW_GKS, MMOF_ERR_INVALID,
+                       "bad flow_solver");
+            if (p->flow_solver == MMOF_FLOW_GKS) check_gks_frames(*A->geom, f, p->of_ell, p->of_iters);
+        }
         int rc = solve_joint(*A, static_cast<const double*>(b), noise_norm, *p, static_cast<double*>(u_inout), v_out,
                              v_rev_out, rep);
         if (rep) rep->status = rc;

@@ -478,21 +478,23 @@ void launch_flow_up(Ctx& c, Geom& g, Geom& gs, int dt, int f, const void* vs, vo
     });
 }
 
-void flow_update_core(Ctx& c, Geom& g, Geom* gs, int dt, const void* u, void* v, int f, double gamma, int n_sweeps,
-                      int dr, const FlowWork& w) {
+void flow_update_core(Ctx& c, Geom& g, Geom* gs, int dt, const void* u, void* v, int f, int dr, const FlowMethod& fm,
+                      const FlowWork& w) {
     if (g.n_pairs == 0) return;
     MMOF_CHECK(f == 1 || gs, MMOF_ERR_INVALID, "reduced geometry missing");
-    Geom& gw = f > 1 ? *gs : g;  // the frames the sweeps run on
+    Geom& gw = f > 1 ? *gs : g;  // the frames the flow is computed on
     const void* uw = u;
     void* vw = v;
     if (f > 1) {
         launch_box_down(c, g, gw, dt, 0, f, u, w.us);
-        launch_box_down(c, g, gw, dt, 1, f, v, w.vs);
+        if (fm.solver == 0) launch_box_down(c, g, gw, dt, 1, f, v, w.vs);  // the warm start
         uw = w.us;
         vw = w.vs;
     }
     launch_of_derivs(c, gw, dt, uw, w.I, dr);
-    if (launch_hs_sweeps(c, gw, dt, w.I, vw, w.tmp, gamma, n_sweeps)) {
+    if (fm.solver == 1)
+        launch_of_gks(c, gw, dt, w.I, vw, fm.ell, fm.n_iter, fm.fixed_lambda, w.gks);
+    else if (launch_hs_sweeps(c, gw, dt, w.I, vw, w.tmp, fm.gamma, fm.n_sweeps)) {
         dispatch(dt, [&](auto z) {
             using T = decltype(z);
             convert<T, T>(c, 2 * gw.pair_px, (const T*)w.tmp, (T*)vw);

@@ -54,16 +54,46 @@ int resolve_flow_scale(const Geom& g, int f);
 void check_flow_frames(const Geom& g, int f, int dr);
 void launch_box_down(Ctx& c, Geom& g, Geom& gs, int dt, int mode, int f, const void* in, void* out);
 void launch_flow_up(Ctx& c, Geom& g, Geom& gs, int dt, int f, const void* vs, void* v);
-// Workspace of one flow update: I and tmp sized for the frames the sweeps run on (the reduced
-// ones when f > 1), us / vs for the reduced frames and flow (unused when f = 1).
+// Solve-OF (Alg. 2, p = q = 2) per pair on geometry g: GKS with GCV (or a fixed lambda),
+// from the derivatives I into the flow v (dtype dt; v's previous content is not used).
+// Workspace (FP64): V (ell + n_iter - 1) * 2 * pair_px, U (ell + 1) * pair_px, S and R
+// 2 * pair_px each, lam n_pairs * n_iter (the lambda of every iteration, 0 past a breakdown).
+struct GksWork {
+    double *V = nullptr, *U = nullptr, *S = nullptr, *R = nullptr, *lam = nullptr;
+};
+int of_gks_capacity();  // largest ell + n_iter - 1
+void launch_of_gks(Ctx& c, Geom& g, int dt, const void* I, void* v, int ell, int n_iter, double fixed_lambda,
+                   const GksWork& w);
+
+// Raises MMOF_ERR_INVALID unless ell >= 1, n_iter >= 1, ell + n_iter - 1 <= of_gks_capacity(),
+// and every (reduced by f) frame has more than ell pixels and fewer than 2^30.
+void check_gks_frames(const Geom& g, int f, int ell, int n_iter);
+struct FlowMethod;
+// Solve-OF workspaces for geometry g (the frames the flow is computed on), named prefix + part
+// in the context.
+GksWork gks_work(Ctx& c, const Geom& g, const FlowMethod& fm, const std::string& prefix);
+
+// How a flow update computes the flow: Horn-Schunck sweeps warm-started from the current flow
+// (solver 0) or Solve-OF (solver 1).
+struct FlowMethod {
+    int solver = 0;
+    double gamma = 0.01;   // HS: alpha^2
+    int n_sweeps = 200;    // HS
+    int ell = 10, n_iter = 20;
+    double fixed_lambda = 0.0;  // Solve-OF: > 0 skips the GCV search
+};
+// Workspace of one flow update: I and tmp sized for the frames the flow is computed on (the
+// reduced ones when f > 1), us / vs for the reduced frames and flow (unused when f = 1), gks
+// for Solve-OF.
 struct FlowWork {
     void *I = nullptr, *tmp = nullptr, *us = nullptr, *vs = nullptr;
+    GksWork gks;
 };
-// Derivatives and n_sweeps HS sweeps warm-started from v (updated in place), on the frames
-// reduced by f (gs = reduced_geom(g, f); f = 1: on the frames themselves, gs unused);
-// graph-safe (no memcpy nodes).
-void flow_update_core(Ctx& c, Geom& g, Geom* gs, int dt, const void* u, void* v, int f, double gamma, int n_sweeps,
-                      int dr, const FlowWork& w);
+// Derivatives and the flow (method fm) into v (updated in place), on the frames reduced by f
+// (gs = reduced_geom(g, f); f = 1: on the frames themselves, gs unused); graph-safe (no memcpy
+// nodes).
+void flow_update_core(Ctx& c, Geom& g, Geom* gs, int dt, const void* u, void* v, int f, int dr, const FlowMethod& fm,
+                      const FlowWork& w);
 
 // Elementwise.
 void launch_mm_weights(Ctx& c, int dt, int64_t n, const void* nu, double eps, void* w2);

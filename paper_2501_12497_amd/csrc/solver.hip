@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "kernels.h"
@@ -62,6 +63,8 @@ struct Solver {
     int fscale = 1;
     Geom* gs = nullptr;
     TX *flow_us = nullptr, *flow_vs = nullptr;
+    FlowMethod fm;
+    GksWork gks;
     double* w2;  // FP64 MM weights of the rows of Theta
     int32_t *rad_v, *rad_vr;
     double* host;  // pinned report staging
@@ -79,6 +82,10 @@ struct Solver {
         R = oRR + ((flow && p.use_reverse) ? g.pair_px : 0);
         Kcap = p.ell + p.k_max - 1;
         fscale = resolve_flow_scale(g, p.flow_scale);
+        fm.solver = p.flow_solver;
+        fm.n_sweeps = p.n_sweeps;
+        fm.ell = p.of_ell;
+        fm.n_iter = p.of_iters;
         if (flow && fscale > 1) {
             auto& r = P.reduced[fscale];
             if (!r) r = make_reduced_geom(g, fscale, c.stream);
@@ -137,6 +144,7 @@ struct Solver {
             flow_us = wsx("flow_us", gs->n);
             flow_vs = wsx("flow_vs", 2 * gs->pair_px);
         }
+        if (flow && fm.solver == MMOF_FLOW_GKS) gks = gks_work(c, gw, fm, "solve_gks_");
         rad_v = ws<int32_t>("rad_v", 64);
         rad_vr = ws<int32_t>("rad_vr", 64);
     }
@@ -242,13 +250,17 @@ struct Solver {
         MMOF_HIP(hipGraphLaunch(cg.exec, c.stream));
     }
     std::string graph_key(const char* what) const {
-        char buf[512];
+        char buf[1024];
         std::snprintf(buf, sizeof buf,
                       "%s|%d|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%a|%lld|%lld", what, dt,
                       (void*)u_op, (void*)I, (void*)flow_v, (void*)flow_tmp, (void*)flow_vr, (void*)rad_v,
                       (void*)rad_vr, (void*)vin_m, (void*)out_n, (void*)out_n2, (void*)w2, (void*)r, (void*)scal,
                       (void*)flow_us, (void*)flow_vs, p.interp, p.use_reverse, p.n_sweeps, p.delta_r, fscale,
                       p.alpha, (long long)n, (long long)R);
+        if (fm.solver == MMOF_FLOW_GKS) {
+            std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), "|gks|%d|%d|%p|%p|%p|%p|%p", fm.ell,
+                          fm.n_iter, (void*)gks.V, (void*)gks.U, (void*)gks.S, (void*)gks.R, (void*)gks.lam);
+        }
         std::string key(buf);
         for (const auto& t : g.tuned) key += "|" + t.first + "=" + std::to_string(t.second);  // tile lists used
         return key;
@@ -395,7 +407,9 @@ struct Solver {
                     w.tmp = flow_tmp;
                     w.us = flow_us;
                     w.vs = flow_vs;
-                    flow_update_core(c, g, gs, dt, u_op, flow_v, fscale, gamma, p.n_sweeps, p.delta_r, w);
+                    w.gks = gks;
+                    fm.gamma = gamma;
+                    flow_update_core(c, g, gs, dt, u_op, flow_v, fscale, p.delta_r, fm, w);
                     launch_flow_radius(c, g, dt, flow_v, rad_v);
                     if (p.use_reverse) {
                         launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);

@@ -2,7 +2,8 @@
 
 * 1024x1024 x 64 frames, 12 moving/rotating ellipses, 90 angles per frame shifted by the
   golden angle, 1449 bins: H, H^T, Psi, Psi^T, L(v), L(v)^T (both directions), d/dv,
-  App. C derivatives and Horn-Schunck sweeps in FP32 on the whole stack; the oracle
+  App. C derivatives, Horn-Schunck sweeps, and the flow on frames reduced by 32 (sweeps and
+  Solve-OF) in FP32 on the whole stack; the oracle
   recomputes sampled frames/pairs in FP64 from the same FP32 inputs.  Adjoint
   identities at full size in FP64.
 * 128x128 x 16 (the benchmark workload, in its launch configuration): the first MM
@@ -136,6 +137,29 @@ def test_optical_flow_fullsize_sampled(big):
         assert rel(I[p], exp, np.abs(upair).max() * np.ones_like(exp)) < TOL32, p
         expv = optflow.flow_update(upair, np.zeros((1, 2, s.ny, s.nx)), 0.1, 10, 1)[0]
         assert rel(vh[p], expv) < 1e-4, p
+
+
+def test_reduced_frame_flows_fullsize_sampled(big):
+    """The flow on frames reduced by the automatic factor (32: 32 x 32 frames), by Horn-Schunck
+    sweeps and by Solve-OF (GKS with GCV, 10 + 20), FP32 on the whole stack; the oracle
+    recomputes sampled pairs in FP64 from the same FP32 frames."""
+    import torch
+    from oracle import solve_of
+    from paper_2501_12497_amd import _lib
+    B, s, u32 = big["B"], big["s"], big["u32"]
+    st = big["stack"]
+    auto = _lib.MMOF_FLOW_SCALE_AUTO
+    v = torch.zeros(2 * st.n_pair_px, dtype=torch.float32, device="cuda")
+    B.flow_update_scaled(st, big["u"], v, alpha=0.1, n_sweeps=50, delta_r=1, scale=auto)
+    vh = v.view(s.n_t - 1, 2, s.ny, s.nx).cpu().numpy()
+    B.flow_solve_gks(st, big["u"], v, delta_r=1, ell=10, n_iter=20, scale=auto)
+    vg = v.view(s.n_t - 1, 2, s.ny, s.nx).cpu().numpy()
+    for p in PAIRS[:2]:
+        upair = u32[p:p + 2].astype(np.float64)
+        exp = optflow.flow_update_scaled(upair, np.zeros((1, 2, s.ny, s.nx)), 0.1, 50, 1, 32)[0]
+        assert rel(vh[p], exp) < 1e-4, p
+        exp = solve_of.solve_of(upair, 1, 10, 20, 0.0, 32)[0]
+        assert rel(vg[p], exp) < 1e-4, p
 
 
 def _ellipse128():

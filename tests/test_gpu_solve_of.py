@@ -1,0 +1,160 @@
+"""GPU parity of Solve-OF (Alg. 2, p = q = 2: GKS with GCV) against the FP64 oracle, through
+the C ABI (mmof_flow_solve_gks), and of the joint solve that uses it for the flow.
+
+Bars: with a fixed lambda the FP64 flow matches to 1e-10 (only summation order differs);
+with the GCV search the chosen lambdas match to 1e-6 relative and the flows to 1e-8 (the
+search's points are the same on both sides and ties within a relative 1e-9 of G keep the
+earlier point, so rounding does not move the choice; G is evaluated from Gram matrices on the
+GPU and from the stacked least-squares form in the oracle); FP32 derivatives (FP64 solve):
+flows to 1e-4 (their G values differ by FP32 rounding, more than the tie width, so the
+lambdas are not compared).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import TOL32, dev, host, pack, rel, roundtrip32, unpack
+from oracle import optflow, solve_of
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(3, 14, 16), (2, 11, 9)]   # ragged; widths of both parities
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch  # noqa: F401
+    from paper_2501_12497_amd import binding
+    return binding
+
+
+def _frames(seed, sizes=SIZES, noise=0.02):
+    """Smooth moving patterns (sub-pixel shifts per frame) plus a little noise."""
+    r = np.random.default_rng(seed)
+    out = []
+    for i, (nt, ny, nx) in enumerate(sizes):
+        y, x = np.mgrid[0:ny, 0:nx].astype(float)
+        fr = [np.sin(0.45 * (x - 0.4 * t) + 0.3 * i) + np.cos(0.37 * (y + 0.3 * t)) + noise * r.standard_normal((ny, nx))
+              for t in range(nt)]
+        out.append(np.stack(fr))
+    return out
+
+
+def _run(B, us, dt, **kw):
+    import torch
+    stack = B.Stack([u.shape for u in us])
+    v = torch.zeros(2 * stack.n_pair_px, dtype=dt, device="cuda")
+    vr = torch.empty_like(v)
+    v, lam = B.flow_solve_gks(stack, dev(pack(us), dt), v, v_rev=vr, want_lambdas=True, **kw)
+    return host(v), host(vr), lam
+
+
+def _oracle(us, ell, n_iter, fixed_lambda=0.0, dr=1):
+    flows, lams = [], []
+    for u in us:
+        I = optflow.of_derivs(u, dr)
+        for t in range(I.shape[0]):
+            s, l = solve_of.solve_of_pair(I[t], ell, n_iter, fixed_lambda)
+            flows.append(s)
+            lams.append(l)
+    return flows, lams
+
+
+def test_fixed_lambda_fp64(B):
+    import torch
+    us = _frames(1)
+    got, _, lam = _run(B, us, torch.float64, ell=6, n_iter=8, fixed_lambda=0.05)
+    exp, _ = _oracle(us, 6, 8, 0.05)
+    assert rel(got, pack(exp)) < 1e-10
+    assert np.all(lam == 0.05)
+
+
+@pytest.mark.parametrize("ell,n_iter", [(10, 20), (4, 7), (1, 1)])
+def test_gcv_fp64(B, ell, n_iter):
+    import torch
+    us = _frames(2)
+    got, gotr, lam = _run(B, us, torch.float64, ell=ell, n_iter=n_iter)
+    exp, elams = _oracle(us, ell, n_iter)
+    np.testing.assert_allclose(lam, np.array(elams), rtol=1e-6)
+    assert rel(got, pack(exp)) < 1e-8
+    # reverse flow of the GPU's own flow
+    shapes = [(u.shape[0] - 1, 2) + u.shape[1:] for u in us]
+    flows = unpack(got, shapes)
+    assert rel(gotr, pack([optflow.reverse_flow(f) for f in flows])) < 1e-12
+
+
+def test_gcv_fp32_derivatives(B):
+    import torch
+    us = [roundtrip32(u) for u in _frames(3)]
+    got, _, lam = _run(B, us, torch.float32, ell=10, n_iter=20)
+    exp, elams = _oracle(us, 10, 20)
+    assert rel(got, pack(exp)) < 1e-4   # (the lambdas may move to another point where G is flat)
+
+
+def test_reduced_frames(B):
+    """scale = 2 on 40 x 44 / 30 x 27 frames: the solve runs on 20 x 22 / 15 x 14 frames."""
+    import torch
+    sizes = [(3, 40, 44), (2, 30, 27)]
+    us = _frames(4, sizes)
+    got, _, _ = _run(B, us, torch.float64, ell=8, n_iter=10, scale=2)
+    exp = pack([solve_of.solve_of(u, 1, 8, 10, 0.0, 2) for u in us])
+    assert rel(got, exp) < 1e-8
+
+
+def test_edges(B):
+    import torch
+    from paper_2501_12497_amd._lib import MMOFError
+    # no temporal change: zero flow, lambdas 0
+    u = _frames(5, [(3, 9, 11)], noise=0.0)[0]
+    still = [np.stack([u[0]] * 3)]
+    got, _, lam = _run(B, still, torch.float64, ell=5, n_iter=4)
+    assert not np.any(got) and not np.any(lam)
+    # a stack whose sequences have single frames and pairs side by side
+    us = [_frames(6, [(1, 8, 8)])[0], _frames(7, [(2, 10, 9)])[0]]
+    got, _, _ = _run(B, us, torch.float64, ell=5, n_iter=5)
+    exp, _ = _oracle([us[1]], 5, 5)
+    assert rel(got, pack(exp)) < 1e-8
+    # argument checks, before any launch
+    stack = B.Stack([(2, 6, 5)])
+    uu = dev(np.zeros(60), torch.float64)
+    v = torch.full((60,), 7.0, dtype=torch.float64, device="cuda")
+    for kw in (dict(ell=20, n_iter=14), dict(ell=0, n_iter=3), dict(ell=3, n_iter=0), dict(ell=30, n_iter=1),
+               dict(ell=3, n_iter=3, fixed_lambda=-1.0), dict(ell=3, n_iter=3, scale=3, delta_r=2)):
+        with pytest.raises(MMOFError) as e:
+            B.flow_solve_gks(stack, uu, v, **kw)
+        assert e.value.code == -1, kw
+    assert torch.all(v == 7.0)
+
+
+@pytest.mark.parametrize("op", ["f64", "f32"])
+def test_joint_solve_with_solve_of(B, op):
+    """The joint solve with the paper's flow solver on frames reduced by 2 (its Sec. 5
+    setting), FP64 against the oracle's run of the same configuration."""
+    import torch
+    from oracle import mmgks
+    from synth import noisy
+    sizes = [(3, 25, 30), (4, 18, 21)]
+    us = []
+    for (nt, ny, nx) in sizes:
+        yy, xx = np.mgrid[0:ny, 0:nx]
+        us.append(np.stack([(((xx - (8.0 + 1.5 * t)) ** 2 + (yy - ny / 2) ** 2) <= 16.0).astype(float)
+                            for t in range(nt)]))
+    geoms = [mmgks.SeqGeom(nt, ny, nx) for (nt, ny, nx) in sizes]
+    ops = mmgks.StackOps(geoms, "blur", flow_scale=2, flow_solver="gks", of_ell=6, of_iters=8)
+    ut = np.concatenate([u.ravel() for u in us])
+    clean = ops.A(ut)
+    b = noisy(clean, np.random.default_rng(8).standard_normal(clean.shape), 0.01)
+    delta = float(np.linalg.norm(b - clean))
+    prm = dict(ell=5, k_max=8, tau=3, alpha=0.2)
+    ref = mmgks.mmgks_of(ops, b, delta, mmgks.SolveParams(n_sweeps=0, **prm), u_true=ut)
+    plan = B.plan_blur(B.Stack(sizes), 9, 2.0)
+    kw = dict(op_dtype=op, flow_scale=2, flow_solver=1, of_ell=6, of_iters=8, **prm)
+    res = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta, u_true=torch.as_tensor(ut, device="cuda"),
+                        **kw)
+    assert res.iters == ref.iters
+    assert abs(res.rre[-1] - ref.rre[-1]) <= 1e-4
+    if op == "f64":
+        np.testing.assert_allclose(res.lambdas, ref.lambdas, rtol=1e-7)
+        assert np.linalg.norm(res.u.cpu().numpy() - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
+    again = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta, u_true=torch.as_tensor(ut, device="cuda"),
+                          use_graph=1, **kw)
+    assert torch.equal(again.u, res.u) and again.lambdas == res.lambdas
