@@ -50,7 +50,8 @@ struct FrameInfo {
     int64_t pair_off;  // pixel offset of pair (t, t+1) in pair arrays (valid if t < n_t-1)
     int32_t ny, nx;
     int32_t t, n_t;
-    int32_t seq, pad;
+    int32_t seq;
+    int32_t blk_off;   // pairs: offset of the frame's 16 x 16 blocks in per-block arrays
 };
 
 // A rectangular work tile of one frame (or one pair: frame = first frame of the pair).
@@ -118,6 +119,7 @@ struct Geom {
     int64_t n_frames = 0;
     int64_t n_pairs = 0;    // frame pairs
     int64_t pair_px = 0;    // pixels over all pairs
+    int64_t pair_blocks = 0;  // 16 x 16 blocks (partial ones included) over all pairs
     int64_t gx_len = 0, gy_len = 0;
     int32_t max_ny = 0, max_nx = 0;
     // every frame width is a multiple of 4, so frame, pair and row starts (and those of the

@@ -1,6 +1,7 @@
 // Optical-flow subproblem kernels: App. C image derivatives, Horn-Schunck block-Jacobi
 // sweeps for the p = q = 2 flow energy (eq. of_reg), the reverse-flow estimate of the
 // Remark in Sec. 3, and the MM weights of Sec. 4.1.1.
+#include <climits>
 #include <vector>
 
 #include "dev.h"
@@ -275,10 +276,70 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
 
 // Reverse flow: target q gathers, in raster order of the sources p, every p with
 // rint(p + v(p)) == q; the result is minus the mean of their velocities (0 if none).
+// Target boxes of the sources of the pairs: the smallest rectangle (x_min, x_max, y_min,
+// y_max) holding the pixels the flows round to, for every 16 x 16 block and for every row
+// strip of 16 pixels of a block (empty: x_min > x_max).  Block b's strips are entries
+// 16 b .. 16 b + 15 of `strips`.  64 x 64 tiles; wave w takes block row w of the tile, lane l
+// column l; 16-lane reductions per row.
+__device__ __forceinline__ void box_reduce16(int& x0, int& x1, int& y0, int& y1) {
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) {
+        x0 = min(x0, __shfl_xor(x0, o));
+        x1 = max(x1, __shfl_xor(x1, o));
+        y0 = min(y0, __shfl_xor(y0, o));
+        y1 = max(y1, __shfl_xor(y1, o));
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_rev_boxes(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
+                                                   const T* __restrict__ v, int4* __restrict__ boxes,
+                                                   int4* __restrict__ strips) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int lane = (int)threadIdx.x % 64, w = (int)threadIdx.x / 64;
+    const int nx = f.nx, ny = f.ny;
+    const int x = tl.x0 + lane, yb = tl.y0 + 16 * w;
+    const int64_t np = (int64_t)nx * ny;
+    const T* vx = v + 2 * f.pair_off;
+    const T* vy = vx + np;
+    const int64_t blk = f.blk_off + (int64_t)(yb / 16) * ((nx + 15) / 16) + x / 16;
+    const bool writer = lane % 16 == 0 && x < nx && yb < ny;
+    int bx0 = INT_MAX, bx1 = INT_MIN, by0 = INT_MAX, by1 = INT_MIN;
+    for (int r = 0; r < 16; ++r) {
+        const int y = yb + r;
+        int x0 = INT_MAX, x1 = INT_MIN, y0 = INT_MAX, y1 = INT_MIN;
+        if (x < nx && y < ny) {
+            const int64_t p = (int64_t)y * nx + x;
+            const T a = vx[p], b = vy[p];
+            if (fabs(a) < T(1048576) && fabs(b) < T(1048576)) {
+                x0 = x1 = rint_shift(x, a);
+                y0 = y1 = rint_shift(y, b);
+            }
+        }
+        box_reduce16(x0, x1, y0, y1);  // the same values on all 16 lanes
+        if (writer && y < ny) strips[16 * blk + r] = make_int4(x0, x1, y0, y1);
+        bx0 = min(bx0, x0);
+        bx1 = max(bx1, x1);
+        by0 = min(by0, y0);
+        by1 = max(by1, y1);
+    }
+    if (writer) boxes[blk] = make_int4(bx0, bx1, by0, by1);
+}
+
+// s'(rint(p + s(p))) = -s(p), averaged over collisions, 0 at holes: every target pixel q
+// gathers the sources within the flow radius R (d_radius) that round to it, in raster order
+// of the sources.  Source blocks whose target box does not hold q are skipped (a block is
+// tested once per block row; a bit mask keeps up to 64 block columns), and so are the row
+// strips of a candidate block whose boxes do not hold q, so large or uneven displacements do
+// not make every target scan its (2R + 1)^2 window: a smooth flow leaves a few candidate
+// blocks and strips per target whatever its size.
 template <class T>
 __global__ __launch_bounds__(256) void k_reverse_flow(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                       const T* __restrict__ v, T* __restrict__ vr,
-                                                      const int32_t* __restrict__ d_radius) {
+                                                      const int32_t* __restrict__ d_radius,
+                                                      const int4* __restrict__ boxes,
+                                                      const int4* __restrict__ strips) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
     const int qx = tl.x0 + (int)(threadIdx.x % OTW);
@@ -288,21 +349,42 @@ __global__ __launch_bounds__(256) void k_reverse_flow(const Tile* __restrict__ t
     const int64_t np = (int64_t)nx * ny;
     const T* vx = v + 2 * f.pair_off;
     const T* vy = vx + np;
+    const int4* bb = boxes + f.blk_off;
+    const int4* sb = strips + 16 * (int64_t)f.blk_off;
+    const int nbx = (nx + 15) / 16;
     const int R = *d_radius;
     T ax = T(0), ay = T(0);
     int cnt = 0;
     const int py_lo = max(qy - R, 0), py_hi = min(qy + R, ny - 1);
     const int px_lo = max(qx - R, 0), px_hi = min(qx + R, nx - 1);
-    for (int py = py_lo; py <= py_hi; ++py)
-        for (int px = px_lo; px <= px_hi; ++px) {
-            const int64_t p = (int64_t)py * nx + px;
-            const T a = vx[p], b = vy[p];
-            if (!(fabs(a) < T(1048576)) || !(fabs(b) < T(1048576))) continue;
-            if (rint_shift(px, a) != qx || rint_shift(py, b) != qy) continue;
-            ax -= a;
-            ay -= b;
-            ++cnt;
+    const int bx_lo = px_lo >> 4, bx_hi = px_hi >> 4;
+    const bool wide = bx_hi - bx_lo >= 64;  // columns past the mask are scanned without the test
+    for (int by = py_lo >> 4; by <= (py_hi >> 4); ++by) {
+        const int y0 = by * 16, y1 = y0 + 15;
+        uint64_t mask = 0;
+        for (int bx = bx_lo; bx <= bx_hi && bx - bx_lo < 64; ++bx) {
+            const int4 t = bb[by * nbx + bx];
+            if (qx >= t.x && qx <= t.y && qy >= t.z && qy <= t.w) mask |= 1ull << (bx - bx_lo);
         }
+        if (!mask && !wide) continue;
+        for (int py = max(py_lo, y0); py <= min(py_hi, y1); ++py)
+            for (int bx = bx_lo; bx <= bx_hi; ++bx) {
+                const int i = bx - bx_lo;
+                if (i < 64 && !((mask >> i) & 1ull)) continue;
+                const int4 t = sb[16 * ((int64_t)by * nbx + bx) + (py - y0)];
+                if (!(qx >= t.x && qx <= t.y && qy >= t.z && qy <= t.w)) continue;
+                const int xa = max(px_lo, bx * 16), xb = min(px_hi, bx * 16 + 15);
+                for (int px = xa; px <= xb; ++px) {
+                    const int64_t p = (int64_t)py * nx + px;
+                    const T a = vx[p], b = vy[p];
+                    if (!(fabs(a) < T(1048576)) || !(fabs(b) < T(1048576))) continue;
+                    if (rint_shift(px, a) != qx || rint_shift(py, b) != qy) continue;
+                    ax -= a;
+                    ay -= b;
+                    ++cnt;
+                }
+            }
+    }
     const int64_t q = (int64_t)qy * nx + qx;
     T* o = vr + 2 * f.pair_off;
     o[q] = cnt ? ax / T(cnt) : T(0);
@@ -510,12 +592,19 @@ void launch_reverse_flow(Ctx& c, Geom& g, int dt, const void* v, void* vr, const
         rad = static_cast<int32_t*>(c.work("rev_radius", 256));
         launch_flow_radius(c, g, dt, v, rad);
     }
+    const size_t nb = (size_t)std::max<int64_t>(g.pair_blocks, 1);
+    int4* boxes = static_cast<int4*>(c.work("rev_boxes", sizeof(int4) * 17 * nb));
+    int4* strips = boxes + nb;
+    const TileList& tb = g.tile_list(c.stream, 64, 64, true);
     const TileList& tl = g.tile_list(c.stream, OTW, OTH, true);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
+        hipLaunchKernelGGL(k_rev_boxes<T>, dim3((unsigned)tb.count), dim3(256), 0, c.stream, tb.buf.as<Tile>(),
+                           g.dframes(), (const T*)v, boxes, strips);
+        MMOF_LAUNCH_CHECK();
         ScopedTime st(&c, "reverse_flow");
         hipLaunchKernelGGL(k_reverse_flow<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), (const T*)v, (T*)vr, rad);
+                           g.dframes(), (const T*)v, (T*)vr, rad, boxes, strips);
         MMOF_LAUNCH_CHECK();
     });
 }

@@ -25,7 +25,7 @@ static void build_geom(Geom& g, const mmof_stack* s, hipStream_t st) {
     g.n_t.assign(s->n_t, s->n_t + s->n_seq);
     g.ny.assign(s->ny, s->ny + s->n_seq);
     g.nx.assign(s->nx, s->nx + s->n_seq);
-    int64_t off = 0, gx = 0, gy = 0, poff = 0;
+    int64_t off = 0, gx = 0, gy = 0, poff = 0, boff = 0;
     for (int i = 0; i < g.n_seq; ++i) {
         MMOF_CHECK(g.n_t[i] >= 1 && g.ny[i] >= 2 && g.nx[i] >= 2, MMOF_ERR_SHAPE,
                    "sequence " + std::to_string(i) + " needs n_t >= 1, ny >= 2, nx >= 2");
@@ -45,6 +45,7 @@ static void build_geom(Geom& g, const mmof_stack* s, hipStream_t st) {
             f.t = t;
             f.n_t = g.n_t[i];
             f.seq = i;
+            f.blk_off = (int32_t)boff;
             g.frames.push_back(f);
             int64_t np = (int64_t)g.ny[i] * g.nx[i];
             off += np;
@@ -52,6 +53,8 @@ static void build_geom(Geom& g, const mmof_stack* s, hipStream_t st) {
             gy += (int64_t)(g.ny[i] - 1) * g.nx[i];
             if (t + 1 < g.n_t[i]) {
                 poff += np;
+                boff += (int64_t)((g.ny[i] + 15) / 16) * ((g.nx[i] + 15) / 16);
+                MMOF_CHECK(boff < INT32_MAX, MMOF_ERR_SHAPE, "too many frame pairs");
                 g.n_pairs += 1;
             }
         }
@@ -61,6 +64,7 @@ static void build_geom(Geom& g, const mmof_stack* s, hipStream_t st) {
     g.vec4 = true;
     for (int i = 0; i < g.n_seq; ++i) g.vec4 = g.vec4 && g.nx[i] % 4 == 0;
     g.pair_px = poff;
+    g.pair_blocks = boff;
     g.gx_len = gx;
     g.gy_len = gy;
     g.d_frames.ensure(sizeof(FrameInfo) * g.frames.size());

@@ -364,6 +364,30 @@ def test_flow_update_sweep_counts_small_frames(B, n_sweeps):
     assert rel(host(v), exp) < TOL64
 
 
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_reverse_flow_with_outliers(B, which):
+    """Mostly small displacements plus a few of 35 px, and in a 1200-px-wide frame some of
+    1100 px (more than 64 block columns in the window): the block reach table must not drop
+    any source.  FP64 sums in the oracle's order (raster order of the sources): equal."""
+    import torch
+    dt = torch.float64 if which == "f64" else torch.float32
+    sizes = [(3, 40, 70), (2, 12, 1200)]
+    r = np.random.default_rng(31)
+    vs = []
+    for (nt, ny, nx), big in zip(sizes, (35.0, 1100.0)):
+        v = r.uniform(-2, 2, size=(nt - 1, 2, ny, nx))
+        for _ in range(6):
+            t, c, y, x = r.integers(nt - 1), r.integers(2), r.integers(ny), r.integers(nx)
+            v[t, c, y, x] = big * (1 if r.random() < 0.5 else -1) + r.uniform(-0.4, 0.4)
+        vs.append(roundtrip32(v) if dt == torch.float32 else v)
+    got = host(B.reverse_flow(B.Stack(sizes), dev(pack(vs), dt)))
+    exp = pack([optflow.reverse_flow(v) for v in vs])
+    if dt == torch.float64:
+        assert np.array_equal(got, exp)
+    else:
+        np.testing.assert_allclose(got, exp, rtol=1e-6, atol=1e-6)
+
+
 def test_reverse_flow_exact_on_half_integers(B):
     import torch
     sizes = [(2, 9, 11)]
