@@ -27,7 +27,7 @@ namespace mmof {
 
 namespace {
 
-constexpr int GK_THREADS = 256;
+constexpr int GK_THREADS = 512;
 constexpr int GK_WAVES = GK_THREADS / 64;
 constexpr int GK_KC = 32;         // basis capacity (ell + n_iter - 1)
 constexpr int GK_P = GK_KC + 1;   // padded LDS row stride of the factorization buffers
