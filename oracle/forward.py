@@ -12,10 +12,14 @@ model with unit pixels and unit detector bins:
 so (H^t u)_{theta,j} = sum_p a_{(theta,j),p} u_p and H^T uses the same entries.
 Bins outside [0, n_d) are not measured (their weights are dropped).
 
+Fan beam (flat detector): see fan_rays and fan_matrix (Joseph's method).
+
 Blur.  A 9x9 Gaussian (sigma = 2), normalised to unit sum, zero boundary,
 output the size of the input; it is symmetric, so H^T is the same sum.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -71,6 +75,76 @@ def radon_adj(b: np.ndarray, angles: np.ndarray, ny: int, nx: int) -> np.ndarray
         for k in range(n_theta):
             j, a = hat_weights(ny, nx, float(angles[t, k]), n_bins)
             out[t] += (a * b[t, k][j]).sum(axis=0)
+    return out.reshape(n_t, ny, nx)
+
+
+# ---------------------------------------------------------------------------- fan beam
+
+
+def fan_rays(theta: float, n_bins: int, dso: float, dsd: float, du: float):
+    """Source position and (unnormalised) directions of the rays of one angle.
+
+    Fan beam with a flat detector (Sec. 5 builds its operators on such a geometry and names
+    no projector model).  Reading, in the pixel frame of the parallel model: detector axis
+    a = (cos theta, sin theta), central ray e = (-sin theta, cos theta), point source at
+    S = -dso e, flat detector at distance dsd from the source with bins of width du centred at
+    u_j = (j - (n_d-1)/2) du; ray j runs from S along d_j = dsd e + u_j a.  (The trig values
+    come from the C library, math.cos / math.sin, like the library's table.)"""
+    c, s = math.cos(theta), math.sin(theta)
+    uj = (np.arange(n_bins) - (n_bins - 1) / 2.0) * du
+    dx = -dsd * s + uj * c
+    dy = dsd * c + uj * s
+    return (dso * s, -dso * c), dx, dy
+
+
+def fan_matrix(ny: int, nx: int, theta: float, n_bins: int, dso: float, dsd: float, du: float):
+    """Rows of H for one angle by Joseph's method (ray-driven linear interpolation): a ray
+    with |d_y| >= |d_x| is sampled on every pixel row at its crossing X_c(Y) = S_x + (Y - S_y)
+    d_x / d_y, each sample being the linear interpolation between the two pixels around X_c
+    (pixels outside the frame count as 0) and weighted by the path length per row |d| / |d_y|;
+    other rays likewise on the columns.  Returns a dense [n_bins, ny*nx] matrix."""
+    (sx, sy), dxs, dys = fan_rays(theta, n_bins, dso, dsd, du)
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    A = np.zeros((n_bins, ny * nx))
+    for j in range(n_bins):
+        dx, dy = dxs[j], dys[j]
+        step = np.hypot(dx, dy)
+        if abs(dy) >= abs(dx):
+            for y in range(ny):
+                xc = sx + ((y - cy) - sy) * dx / dy + cx
+                x0 = math.floor(xc)
+                f = xc - x0
+                for x, w in ((x0, 1.0 - f), (x0 + 1, f)):
+                    if 0 <= x < nx:
+                        A[j, y * nx + x] += w * step / abs(dy)
+        else:
+            for x in range(nx):
+                yc = sy + ((x - cx) - sx) * dy / dx + cy
+                y0 = math.floor(yc)
+                f = yc - y0
+                for y, w in ((y0, 1.0 - f), (y0 + 1, f)):
+                    if 0 <= y < ny:
+                        A[j, y * nx + x] += w * step / abs(dx)
+    return A
+
+
+def fan_fwd(u: np.ndarray, angles: np.ndarray, n_bins: int, dso: float, dsd: float, du: float) -> np.ndarray:
+    """b = H u (fan beam) for u [n_t, ny, nx], angles [n_t, n_theta] -> [n_t, n_theta, n_bins]."""
+    n_t, ny, nx = u.shape
+    out = np.zeros((n_t, angles.shape[1], n_bins))
+    for t in range(n_t):
+        for k in range(angles.shape[1]):
+            out[t, k] = fan_matrix(ny, nx, float(angles[t, k]), n_bins, dso, dsd, du) @ u[t].ravel()
+    return out
+
+
+def fan_adj(b: np.ndarray, angles: np.ndarray, ny: int, nx: int, dso: float, dsd: float, du: float) -> np.ndarray:
+    """u = H^T b (fan beam)."""
+    n_t, n_theta, n_bins = b.shape
+    out = np.zeros((n_t, ny * nx))
+    for t in range(n_t):
+        for k in range(n_theta):
+            out[t] += fan_matrix(ny, nx, float(angles[t, k]), n_bins, dso, dsd, du).T @ b[t, k]
     return out.reshape(n_t, ny, nx)
 
 

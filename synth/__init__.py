@@ -7,6 +7,7 @@ both the FP64 oracle and the HIP path receive the arrays it returns as inputs.
 from .workloads import (  # noqa: F401
     Sequence,
     Workload,
+    angle_schedule,
     angles_shifted,
     cfg_disk32,
     cfg_ellipse128,

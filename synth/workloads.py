@@ -71,6 +71,26 @@ class Workload:
         return int(sum(s.u_true.size for s in self.seqs))
 
 
+def angle_schedule(kind: str, n_t: int, n_views: int) -> np.ndarray:
+    """Projection angles [n_t, n_views] in radians for the paper's three schedules (Sec. 5,
+    Tests 1 and 2), n_views evenly spaced angles per frame over the frame's interval:
+      "fixed":   [0, 180) every frame;
+      "equal":   [180 (t-1) / n_t, 180 t / n_t), one of n_t equal sub-intervals per frame;
+      "shifted": [z (t-1) / n_t, z (t-1) / n_t + 180) with z = 180 / n_views.
+    """
+    t = np.arange(n_t)[:, None]
+    k = np.arange(n_views)[None, :]
+    if kind == "fixed":
+        deg = np.broadcast_to(180.0 * k / n_views, (n_t, n_views))
+    elif kind == "equal":
+        deg = 180.0 * t / n_t + (180.0 / n_t) * k / n_views
+    elif kind == "shifted":
+        deg = (180.0 / n_views) * t / n_t + 180.0 * k / n_views
+    else:
+        raise ValueError(kind)
+    return np.radians(np.array(deg, dtype=np.float64))
+
+
 def noisy(clean: np.ndarray, g: np.ndarray, level: float) -> np.ndarray:
     """b = clean + level*||clean||*g/||g||  (Gaussian noise at a relative level)."""
     clean = np.asarray(clean, dtype=np.float64)
