@@ -44,6 +44,8 @@ COMPUTE = {
     "hs_multi": ("alu", 157.3),
     "of_derivs": ("alu", 157.3),
     "box_down": ("alu", 157.3),
+    "fan_fwd": ("alu", 157.3),
+    "fan_adj": ("alu", 157.3),
     "flow_up": ("alu", 157.3),
     "mdot": ("alu", 78.6),          # FP64 vector ALU
 }
@@ -135,6 +137,12 @@ def operators_large(B, torch, reps=5):
         "box_down": lambda: B.flow_update_scaled(stack, u, w, alpha=0.1, n_sweeps=0, delta_r=1, scale=4),
         "flow_up": lambda: B.flow_update_scaled(stack, u, w, alpha=0.1, n_sweeps=0, delta_r=1, scale=4),
     }
+    # the same frames through a flat-detector fan beam (source 1500 px from the centre,
+    # detector 2500 px from the source, bins of 5/3 px: one pixel at the centre per bin)
+    fplan = B.plan_fan(stack, [s.angles.shape[1]], [s.n_bins], s.angles.ravel(), 1500.0, 2500.0, 2500.0 / 1500.0)
+    bf = B.apply_A(fplan, u)
+    ops["fan_fwd"] = lambda: B.apply_A(fplan, u, out=bf)
+    ops["fan_adj"] = lambda: B.apply_At(fplan, bf)
     table = {}
     for name, f in ops.items():
         f()
@@ -179,7 +187,7 @@ def operators_large(B, torch, reps=5):
     ev1.record()
     torch.cuda.synchronize()
     upd["solve_of_auto"] = round(ev0.elapsed_time(ev1) / 3, 3)
-    del plan
+    del plan, fplan
     return {"workload": "large1024x1024x64: 12 moving/rotating ellipses, 90 golden-angle-shifted angles/frame, "
                         "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "tiles": tuned, "kernels": table,
             "flow_update_ms": upd}

@@ -96,6 +96,22 @@ const char* mmof_version(void);
  * Sinograms are stored [frame][angle][bin], sequences packed. */
 int mmof_plan_radon(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles,
                     const int32_t* n_bins, const double* angles_rad, mmof_plan* out);
+
+/* Plan for a fan-beam projector with a flat detector (Sec. 5 builds its operators on a flat
+ * fan-beam geometry; it states no projector model or distances).  Angle theta: detector
+ * axis a = (cos theta, sin theta), central ray e = (-sin theta, cos theta), point source at
+ * -dso e from the frame centre, detector line at distance dsd from the source, n_bins bins
+ * of width du centred at u_j = (j - (n_bins-1)/2) du; ray j runs from the source along
+ * dsd e + u_j a (all lengths in pixel units).  Model: Joseph's method -- a ray with
+ * |d_y| >= |d_x| is sampled on every pixel row by linear interpolation between the two
+ * pixels around its crossing (pixels outside the frame count as 0), each sample weighted
+ * by its path length per row |d| / |d_y|; other rays on the columns.  mmof_apply_At is the
+ * exact transpose.  Sizes, angles and layouts as for mmof_plan_radon.  Errors:
+ * MMOF_ERR_INVALID unless du > 0, dsd > dso and dso exceeds half the diagonal of every frame
+ * by 2 (the source lies outside the frames). */
+int mmof_plan_fan(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles,
+                  const int32_t* n_bins, const double* angles_rad, double dso, double dsd,
+                  double du, mmof_plan* out);
 /* Plan for a per-frame Gaussian blur H^t: K(i,j) = exp(-(i^2+j^2)/(2 sigma^2)) / sum,
  * |i|,|j| <= ksize/2 (ksize odd, <= 15), zero boundary, output the size of the input.
  * K is symmetric so H^T applies the same sum. */

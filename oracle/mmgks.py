@@ -64,13 +64,14 @@ class StackOps:
 
     def __init__(self, seqs: List[SeqGeom], op: str, use_flow: bool = True, use_reverse: bool = True,
                  interp: str = "bilinear", flow_scale: int = 1, flow_solver: str = "hs", of_ell: int = 10,
-                 of_iters: int = 20):
+                 of_iters: int = 20, fan: tuple = None):
         self.seqs = seqs
         self.op = op
         self.use_flow = use_flow
         self.use_reverse = use_reverse
         self.interp = interp
         self.flow_scale = flow_scale  # flow computed on frames reduced by this factor
+        self.fan = fan                # op "fan": (dso, dsd, du) of the flat-detector fan beam
         # "hs": warm-started Horn-Schunck sweeps; "gks": Solve-OF (Alg. 2, GKS with GCV)
         self.flow_solver = flow_solver
         self.of_ell = of_ell
@@ -110,6 +111,8 @@ class StackOps:
         for s, us in zip(self.seqs, self.split_u(u)):
             if self.op == "radon":
                 parts.append(forward.radon_fwd(us, s.angles, s.n_bins).ravel())
+            elif self.op == "fan":
+                parts.append(forward.fan_fwd(us, s.angles, s.n_bins, *self.fan).ravel())
             else:
                 parts.append(forward.blur(us, s.ksize, s.sigma).ravel())
         return np.concatenate(parts)
@@ -119,6 +122,8 @@ class StackOps:
         for s, bs in zip(self.seqs, self.split_b(b)):
             if self.op == "radon":
                 parts.append(forward.radon_adj(bs, s.angles, s.ny, s.nx).ravel())
+            elif self.op == "fan":
+                parts.append(forward.fan_adj(bs, s.angles, s.ny, s.nx, *self.fan).ravel())
             else:
                 parts.append(forward.blur_adj(bs, s.ksize, s.sigma).ravel())
         return np.concatenate(parts)

@@ -54,6 +54,8 @@ _SIGS = {
     "mmof_set_stream": (_I, [_P, _P]),
     "mmof_plan_radon": (_I, [_P, C.POINTER(mmof_stack), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_double), C.POINTER(_P)]),
+    "mmof_plan_fan": (_I, [_P, C.POINTER(mmof_stack), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                           C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double, C.POINTER(_P)]),
     "mmof_plan_blur": (_I, [_P, C.POINTER(mmof_stack), C.c_int32, C.c_double, C.POINTER(_P)]),
     "mmof_plan_destroy": (_I, [_P]),
     "mmof_plan_sizes": (_I, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),

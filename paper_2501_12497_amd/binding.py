@@ -217,6 +217,23 @@ def plan_radon(stack: Stack, n_angles: Sequence[int], n_bins: Sequence[int], ang
     return Plan(h, ctx, stack, "radon")
 
 
+def plan_fan(stack: Stack, n_angles: Sequence[int], n_bins: Sequence[int], angles_rad: np.ndarray, dso: float,
+             dsd: float, du: float, ctx: Optional[Context] = None) -> Plan:
+    """Flat-detector fan-beam projector plan (Joseph's method); sizes and angles as plan_radon."""
+    ctx = ctx or context()
+    na = (C.c_int32 * len(n_angles))(*[int(v) for v in n_angles])
+    nb = (C.c_int32 * len(n_bins))(*[int(v) for v in n_bins])
+    ang = np.ascontiguousarray(np.asarray(angles_rad, dtype=np.float64).ravel())
+    want = sum(s[0] * a for s, a in zip(stack.sizes, n_angles))
+    if ang.size != want:
+        raise ValueError(f"angles_rad has {ang.size} entries, expected {want}")
+    h = C.c_void_p()
+    ctx.bind()
+    check(ctx.lib.mmof_plan_fan(ctx.h, stack.ref, na, nb, ang.ctypes.data_as(C.POINTER(C.c_double)), float(dso),
+                                float(dsd), float(du), C.byref(h)))
+    return Plan(h, ctx, stack, "fan")
+
+
 def plan_blur(stack: Stack, ksize: int = 9, sigma: float = 2.0, ctx: Optional[Context] = None) -> Plan:
     ctx = ctx or context()
     h = C.c_void_p()

@@ -88,8 +88,8 @@ int mmof_set_stream(mmof_ctx ctx, void* hip_stream) {
 
 // ------------------------------------------------------------------ plans
 
-int mmof_plan_radon(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles, const int32_t* n_bins,
-                    const double* angles_rad, mmof_plan* out) {
+static int plan_projector(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles, const int32_t* n_bins,
+                          const double* angles_rad, int kind, double dso, double dsd, double du, mmof_plan* out) {
     return guarded(ctx, [&] {
         need(ctx, "ctx");
         need(stack, "stack");
@@ -100,10 +100,20 @@ int mmof_plan_radon(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angl
         *out = nullptr;
         std::unique_ptr<mmof_plan_s> p(new mmof_plan_s());
         p->ctx = ctx;
-        p->kind = 0;
+        p->kind = kind;
         p->geom_own = make_geom(stack, ctx->stream);
         p->geom = p->geom_own.get();
         p->n = p->geom->n;
+        if (kind == 2) {
+            MMOF_CHECK(std::isfinite(dso) && std::isfinite(dsd) && std::isfinite(du) && du > 0 && dsd > dso,
+                       MMOF_ERR_INVALID, "fan beam needs du > 0 and dsd > dso");
+            for (int s = 0; s < stack->n_seq; ++s)
+                MMOF_CHECK(dso > 0.5 * std::hypot((double)stack->nx[s], (double)stack->ny[s]) + 2.0, MMOF_ERR_INVALID,
+                           "fan beam: the source must lie outside every frame (dso > half diagonal + 2)");
+            p->fan_dso = dso;
+            p->fan_dsd = dsd;
+            p->fan_du = du;
+        }
         int64_t n_trig = 0;
         for (int s = 0; s < stack->n_seq; ++s) {
             MMOF_CHECK(n_angles[s] >= 1 && n_bins[s] >= 1, MMOF_ERR_SHAPE, "n_angles and n_bins must be >= 1");
@@ -124,6 +134,16 @@ int mmof_plan_radon(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angl
         *out = p.release();
         return MMOF_OK;
     });
+}
+
+int mmof_plan_radon(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles, const int32_t* n_bins,
+                    const double* angles_rad, mmof_plan* out) {
+    return plan_projector(ctx, stack, n_angles, n_bins, angles_rad, 0, 0.0, 0.0, 0.0, out);
+}
+
+int mmof_plan_fan(mmof_ctx ctx, const mmof_stack* stack, const int32_t* n_angles, const int32_t* n_bins,
+                  const double* angles_rad, double dso, double dsd, double du, mmof_plan* out) {
+    return plan_projector(ctx, stack, n_angles, n_bins, angles_rad, 2, dso, dsd, du, out);
 }
 
 int mmof_plan_blur(mmof_ctx ctx, const mmof_stack* stack, int32_t ksize, double sigma, mmof_plan* out) {
@@ -206,6 +226,8 @@ int mmof_apply_A(mmof_plan plan, mmof_dtype dt, const void* u, void* b) {
         need(b, "b");
         if (plan->kind == 0)
             launch_radon_fwd(*plan->ctx, *plan, dt, u, b);
+        else if (plan->kind == 2)
+            launch_fan_fwd(*plan->ctx, *plan, dt, u, b);
         else
             launch_blur(*plan->ctx, *plan, dt, u, b);
         return MMOF_OK;
@@ -220,6 +242,8 @@ int mmof_apply_At(mmof_plan plan, mmof_dtype dt, const void* b, void* u) {
         need(b, "b");
         if (plan->kind == 0)
             launch_radon_adj(*plan->ctx, *plan, dt, b, u);
+        else if (plan->kind == 2)
+            launch_fan_adj(*plan->ctx, *plan, dt, b, u);
         else
             launch_blur(*plan->ctx, *plan, dt, b, u);
         return MMOF_OK;

@@ -195,7 +195,7 @@ struct Ctx {
 
 struct Plan {
     Ctx* ctx = nullptr;
-    int kind = 0;  // 0 radon, 1 blur
+    int kind = 0;  // 0 radon (parallel beam), 1 blur, 2 fan beam
     std::unique_ptr<Geom> geom_own;  // the plan's own copy of its stack geometry
     Geom* geom = nullptr;
     int64_t n = 0, m = 0;
@@ -209,6 +209,8 @@ struct Plan {
     DeviceBuffer d_tiles_a;         // pixel tiles of the back-projector
     DeviceBuffer d_tiles_b;         // 32x32 tiles of the frame transpose
     int64_t n_rays[4] = {0, 0, 0, 0}, n_tiles_a = 0, n_tiles_b = 0;
+    // fan beam: source-to-centre and source-to-detector distances, bin width (pixel units)
+    double fan_dso = 0.0, fan_dsd = 0.0, fan_du = 0.0;
     // blur
     int ksize = 9;
     double sigma = 2.0;

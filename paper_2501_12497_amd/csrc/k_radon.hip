@@ -281,6 +281,161 @@ void radon_plan_init(Ctx& c, Plan& p) {
     MMOF_HIP(hipStreamSynchronize(c.stream));
 }
 
+// ---------------------------------------------------------------- fan beam
+//
+// Flat-detector fan beam by Joseph's method.  Angle theta: detector axis a = (cos, sin),
+// central ray e = (-sin, cos), source S = -dso e, ray j along d_j = dsd e + u_j a with
+// u_j = (j - (n_d-1)/2) du.  A ray with |d_y| >= |d_x| is sampled on every pixel row at
+// X_c(Y) = S_x + (Y - S_y) d_x / d_y by linear interpolation between the two pixels around
+// it (out-of-frame pixels are 0), each sample weighted by the path length per row
+// |d| / |d_y|; other rays on the columns.  Forward: one lane per ray (four angles x 64 bins
+// per workgroup), column-stepping rays read the transposed frame so that the lanes stay on
+// neighbouring addresses.  Transpose: one lane per pixel; per angle, the rays that can
+// sample the pixel are those whose detector coordinate lies between the projections of its
+// row neighbours (X -+ 1, Y) or of its column neighbours (X, Y -+ 1); each candidate ray's
+// weight on the pixel is recomputed exactly as the forward computes it.
+
+struct FanGeo {
+    double dso, dsd, du;
+};
+
+// Source and direction of ray j (no contraction: the row / column choice is taken on values
+// rounded exactly like plain double arithmetic).
+__device__ __forceinline__ void fan_ray(double c, double s, int j, int nb, const FanGeo& g, double& sx, double& sy,
+                                        double& dx, double& dy) {
+#pragma clang fp contract(off)
+    const double uj = ((double)j - (nb - 1) / 2.0) * g.du;
+    dx = -g.dsd * s + uj * c;
+    dy = g.dsd * c + uj * s;
+    sx = g.dso * s;
+    sy = -g.dso * c;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fan_fwd(const RayTile* __restrict__ rays, const RadonFrame* __restrict__ rf,
+                                                 const double2* __restrict__ trig, const T* __restrict__ u,
+                                                 const T* __restrict__ ut, T* __restrict__ b, FanGeo geo) {
+    const RayTile rt = rays[xcd_remap(blockIdx.x, gridDim.x)];
+    const RadonFrame f = rf[rt.frame];
+    const int k = rt.angle + (int)threadIdx.x / 64, j = rt.bin0 + (int)threadIdx.x % 64;
+    if (k >= f.n_ang || j >= f.n_bins) return;
+    const double2 cs = trig[f.trig_off + k];
+    double sx, sy, dx, dy;
+    fan_ray(cs.x, cs.y, j, f.n_bins, geo, sx, sy, dx, dy);
+    const double cx = (f.nx - 1) / 2.0, cy = (f.ny - 1) / 2.0;
+    T acc = T(0);
+    double step;
+    if (fabs(dy) >= fabs(dx)) {
+        step = sqrt(dx * dx + dy * dy) / fabs(dy);
+        const T* img = u + f.u_off;
+        for (int y = 0; y < f.ny; ++y) {
+            const double xc = sx + (((double)y - cy) - sy) * dx / dy + cx;
+            const double x0d = floor(xc);
+            const T fr = (T)(xc - x0d);
+            if (x0d < -1.0 || x0d > (double)f.nx) continue;
+            const int x0 = (int)x0d;
+            const T* row = img + (int64_t)y * f.nx;
+            if (x0 >= 0 && x0 < f.nx) acc += (T(1) - fr) * row[x0];
+            if (x0 + 1 >= 0 && x0 + 1 < f.nx) acc += fr * row[x0 + 1];
+        }
+    } else {
+        step = sqrt(dx * dx + dy * dy) / fabs(dx);
+        const T* img = ut + f.u_off;  // [x][y]
+        for (int x = 0; x < f.nx; ++x) {
+            const double yc = sy + (((double)x - cx) - sx) * dy / dx + cy;
+            const double y0d = floor(yc);
+            const T fr = (T)(yc - y0d);
+            if (y0d < -1.0 || y0d > (double)f.ny) continue;
+            const int y0 = (int)y0d;
+            const T* col = img + (int64_t)x * f.ny;
+            if (y0 >= 0 && y0 < f.ny) acc += (T(1) - fr) * col[y0];
+            if (y0 + 1 >= 0 && y0 + 1 < f.ny) acc += fr * col[y0 + 1];
+        }
+    }
+    b[f.sino_off + (int64_t)k * f.n_bins + j] = acc * (T)step;
+}
+
+// Detector position (in bin units) of the ray from the source through the point (X, Y).
+__device__ __forceinline__ double fan_pos(double X, double Y, double c, double s, int nb, const FanGeo& g) {
+    const double t = X * c + Y * s, r = -X * s + Y * c;
+    return g.dsd * t / (g.dso + r) / g.du + (nb - 1) / 2.0;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fan_adj(const Tile* __restrict__ tiles, const RadonFrame* __restrict__ rf,
+                                                 const double2* __restrict__ trig, const T* __restrict__ b,
+                                                 T* __restrict__ u, FanGeo geo) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const RadonFrame f = rf[tl.frame];
+    const int x = tl.x0 + (int)threadIdx.x % RTW, y = tl.y0 + (int)threadIdx.x / RTW;
+    if (x >= f.nx || y >= f.ny) return;
+    const double cx = (f.nx - 1) / 2.0, cy = (f.ny - 1) / 2.0;
+    const double X = x - cx, Y = y - cy;
+    const int nb = f.n_bins;
+    T acc = T(0);
+    for (int k = 0; k < f.n_ang; ++k) {
+        const double2 cs = trig[f.trig_off + k];
+        const double p0 = fan_pos(X - 1.0, Y, cs.x, cs.y, nb, geo), p1 = fan_pos(X + 1.0, Y, cs.x, cs.y, nb, geo);
+        const double p2 = fan_pos(X, Y - 1.0, cs.x, cs.y, nb, geo), p3 = fan_pos(X, Y + 1.0, cs.x, cs.y, nb, geo);
+        const double lo = fmin(fmin(p0, p1), fmin(p2, p3)), hi = fmax(fmax(p0, p1), fmax(p2, p3));
+        // candidate bins, clamped to the detector before the conversion to int
+        const int jlo = (int)fmin(fmax(floor(lo) - 1.0, 0.0), (double)nb);
+        const int jhi = (int)fmax(fmin(ceil(hi) + 1.0, (double)(nb - 1)), -1.0);
+        const T* bk = b + f.sino_off + (int64_t)k * nb;
+        for (int j = jlo; j <= jhi; ++j) {
+            double sx, sy, dx, dy;
+            fan_ray(cs.x, cs.y, j, nb, geo, sx, sy, dx, dy);
+            T w = T(0);
+            double step;
+            if (fabs(dy) >= fabs(dx)) {
+                step = sqrt(dx * dx + dy * dy) / fabs(dy);
+                const double xc = sx + (((double)y - cy) - sy) * dx / dy + cx;
+                const double x0d = floor(xc);
+                const T fr = (T)(xc - x0d);
+                if (x0d == (double)x) w = T(1) - fr;
+                else if (x0d + 1.0 == (double)x) w = fr;
+            } else {
+                step = sqrt(dx * dx + dy * dy) / fabs(dx);
+                const double yc = sy + (((double)x - cx) - sx) * dy / dx + cy;
+                const double y0d = floor(yc);
+                const T fr = (T)(yc - y0d);
+                if (y0d == (double)y) w = T(1) - fr;
+                else if (y0d + 1.0 == (double)y) w = fr;
+            }
+            if (w != T(0)) acc += (w * (T)step) * bk[j];
+        }
+    }
+    u[f.u_off + (int64_t)y * f.nx + x] = acc;
+}
+
+void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
+    if (p.n_rays[2] == 0) return;
+    const FanGeo geo{p.fan_dso, p.fan_dsd, p.fan_du};
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        T* ut = static_cast<T*>(c.work("radon_transpose", sizeof(T) * p.n));
+        hipLaunchKernelGGL(k_transpose_frames<T>, dim3((unsigned)p.n_tiles_b), dim3(256), 0, c.stream,
+                           p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), (const T*)u, ut);
+        MMOF_LAUNCH_CHECK();
+        ScopedTime st(&c, "fan_fwd", (double)sizeof(T) * (p.n + p.m), 0.0);
+        hipLaunchKernelGGL(k_fan_fwd<T>, dim3((unsigned)p.n_rays[2]), dim3(256), 0, c.stream,
+                           p.d_rays[2].as<RayTile>(), p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(),
+                           (const T*)u, (const T*)ut, (T*)b, geo);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
+void launch_fan_adj(Ctx& c, Plan& p, int dt, const void* b, void* u) {
+    const FanGeo geo{p.fan_dso, p.fan_dsd, p.fan_du};
+    dispatch(dt, [&](auto z) {
+        using T = decltype(z);
+        ScopedTime st(&c, "fan_adj", (double)sizeof(T) * (p.n + p.m), 0.0);
+        hipLaunchKernelGGL(k_fan_adj<T>, dim3((unsigned)p.n_tiles_a), dim3(256), 0, c.stream, p.d_tiles_a.as<Tile>(),
+                           p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), (const T*)b, (T*)u, geo);
+        MMOF_LAUNCH_CHECK();
+    });
+}
+
 const int kRadonCandidates = 4;  // angle groups of 1, 2, 4, 8 per workgroup
 
 int radon_fwd_choice(Plan& p, int dt) {

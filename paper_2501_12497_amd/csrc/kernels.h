@@ -104,5 +104,10 @@ extern const int kRadonCandidates;
 void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b, int choice = -1);
 void launch_radon_adj(Ctx& c, Plan& p, int dt, const void* b, void* u);
 void launch_blur(Ctx& c, Plan& p, int dt, const void* in, void* out, int choice = -1);
+void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b);
+void launch_fan_adj(Ctx& c, Plan& p, int dt, const void* b, void* u);
+// Builds the frame table, trig table users and tile lists of a projector plan (radon or fan);
+// the trig table must already be in p.d_trig.
+void radon_plan_init(Ctx& c, Plan& p);
 
 }  // namespace mmof

@@ -153,6 +153,8 @@ struct Solver {
     void A(const TX* in, TX* out) {
         if (P.kind == 0)
             launch_radon_fwd(c, P, dt, in, out);
+        else if (P.kind == 2)
+            launch_fan_fwd(c, P, dt, in, out);
         else
             launch_blur(c, P, dt, in, out);
         if (rep) rep->n_A++;
@@ -160,6 +162,8 @@ struct Solver {
     void At(const TX* in, TX* out) {
         if (P.kind == 0)
             launch_radon_adj(c, P, dt, in, out);
+        else if (P.kind == 2)
+            launch_fan_adj(c, P, dt, in, out);
         else
             launch_blur(c, P, dt, in, out);
         if (rep) rep->n_At++;
