@@ -131,6 +131,7 @@ static int plan_projector(mmof_ctx ctx, const mmof_stack* stack, const int32_t* 
         MMOF_HIP(hipMemcpyAsync(p->d_trig.ptr, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice,
                                 ctx->stream));
         radon_plan_init(*ctx, *p);  // synchronizes the stream
+        if (kind == 2) fan_plan_init(*ctx, *p);
         *out = p.release();
         return MMOF_OK;
     });

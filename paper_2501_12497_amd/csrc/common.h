@@ -211,6 +211,7 @@ struct Plan {
     int64_t n_rays[4] = {0, 0, 0, 0}, n_tiles_a = 0, n_tiles_b = 0;
     // fan beam: source-to-centre and source-to-detector distances, bin width (pixel units)
     double fan_dso = 0.0, fan_dsd = 0.0, fan_du = 0.0;
+    DeviceBuffer d_fanrays;         // double4 per ray (sinogram layout): line and path length
     // blur
     int ksize = 9;
     double sigma = 2.0;

@@ -311,10 +311,14 @@ __device__ __forceinline__ void fan_ray(double c, double s, int j, int nb, const
     sy = -g.dso * c;
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_fan_fwd(const RayTile* __restrict__ rays, const RadonFrame* __restrict__ rf,
-                                                 const double2* __restrict__ trig, const T* __restrict__ u,
-                                                 const T* __restrict__ ut, T* __restrict__ b, FanGeo geo) {
+// Per-ray table, built once per plan in the sinogram layout: {A, B, step, dir} with the
+// sample position of the ray on row y (dir > 0: |d_y| >= |d_x|) x_c = A + B y, or on column
+// x (dir < 0) y_c = A + B x, in pixel-index coordinates, and the path length per step.  Both
+// the forward and the transpose evaluate positions as fma(B, index, A) from this table, so
+// their weights are the same numbers.
+__global__ __launch_bounds__(256) void k_fan_rays(const RayTile* __restrict__ rays, const RadonFrame* __restrict__ rf,
+                                                  const double2* __restrict__ trig, FanGeo geo,
+                                                  double4* __restrict__ table) {
     const RayTile rt = rays[xcd_remap(blockIdx.x, gridDim.x)];
     const RadonFrame f = rf[rt.frame];
     const int k = rt.angle + (int)threadIdx.x / 64, j = rt.bin0 + (int)threadIdx.x % 64;
@@ -323,94 +327,114 @@ __global__ __launch_bounds__(256) void k_fan_fwd(const RayTile* __restrict__ ray
     double sx, sy, dx, dy;
     fan_ray(cs.x, cs.y, j, f.n_bins, geo, sx, sy, dx, dy);
     const double cx = (f.nx - 1) / 2.0, cy = (f.ny - 1) / 2.0;
-    T acc = T(0);
-    double step;
+    double4 e;
     if (fabs(dy) >= fabs(dx)) {
-        step = sqrt(dx * dx + dy * dy) / fabs(dy);
-        const T* img = u + f.u_off;
-        for (int y = 0; y < f.ny; ++y) {
-            const double xc = sx + (((double)y - cy) - sy) * dx / dy + cx;
-            const double x0d = floor(xc);
-            const T fr = (T)(xc - x0d);
-            if (x0d < -1.0 || x0d > (double)f.nx) continue;
-            const int x0 = (int)x0d;
-            const T* row = img + (int64_t)y * f.nx;
-            if (x0 >= 0 && x0 < f.nx) acc += (T(1) - fr) * row[x0];
-            if (x0 + 1 >= 0 && x0 + 1 < f.nx) acc += fr * row[x0 + 1];
-        }
+        e.y = dx / dy;
+        e.x = sx + (-cy - sy) * e.y + cx;
+        e.z = sqrt(dx * dx + dy * dy) / fabs(dy);
+        e.w = 1.0;
     } else {
-        step = sqrt(dx * dx + dy * dy) / fabs(dx);
-        const T* img = ut + f.u_off;  // [x][y]
-        for (int x = 0; x < f.nx; ++x) {
-            const double yc = sy + (((double)x - cx) - sx) * dy / dx + cy;
-            const double y0d = floor(yc);
-            const T fr = (T)(yc - y0d);
-            if (y0d < -1.0 || y0d > (double)f.ny) continue;
-            const int y0 = (int)y0d;
-            const T* col = img + (int64_t)x * f.ny;
-            if (y0 >= 0 && y0 < f.ny) acc += (T(1) - fr) * col[y0];
-            if (y0 + 1 >= 0 && y0 + 1 < f.ny) acc += fr * col[y0 + 1];
-        }
+        e.y = dy / dx;
+        e.x = sy + (-cx - sx) * e.y + cy;
+        e.z = sqrt(dx * dx + dy * dy) / fabs(dx);
+        e.w = -1.0;
     }
-    b[f.sino_off + (int64_t)k * f.n_bins + j] = acc * (T)step;
-}
-
-// Detector position (in bin units) of the ray from the source through the point (X, Y).
-__device__ __forceinline__ double fan_pos(double X, double Y, double c, double s, int nb, const FanGeo& g) {
-    const double t = X * c + Y * s, r = -X * s + Y * c;
-    return g.dsd * t / (g.dso + r) / g.du + (nb - 1) / 2.0;
+    table[f.sino_off + (int64_t)k * f.n_bins + j] = e;
 }
 
 template <class T>
+__global__ __launch_bounds__(256) void k_fan_fwd(const RayTile* __restrict__ rays, const RadonFrame* __restrict__ rf,
+                                                 const double4* __restrict__ table, const T* __restrict__ u,
+                                                 const T* __restrict__ ut, T* __restrict__ b) {
+    const RayTile rt = rays[xcd_remap(blockIdx.x, gridDim.x)];
+    const RadonFrame f = rf[rt.frame];
+    const int k = rt.angle + (int)threadIdx.x / 64, j = rt.bin0 + (int)threadIdx.x % 64;
+    if (k >= f.n_ang || j >= f.n_bins) return;
+    const int64_t ri = f.sino_off + (int64_t)k * f.n_bins + j;
+    const double4 e = table[ri];
+    // rows: samples along x of row y; columns: along y of column x (transposed frame)
+    const bool rows = e.w > 0.0;
+    const int nsteps = rows ? f.ny : f.nx, nline = rows ? f.nx : f.ny;
+    const T* img = rows ? u + f.u_off : ut + f.u_off;
+    T acc = T(0);
+    for (int q = 0; q < nsteps; ++q) {
+        const double pc = fma(e.y, (double)q, e.x);
+        const double p0d = floor(pc);
+        if (p0d < -1.0 || p0d > (double)nline) continue;
+        const T fr = (T)(pc - p0d);
+        const int p0 = (int)p0d;
+        const T* line = img + (int64_t)q * nline;
+        if (p0 >= 0 && p0 < nline) acc += (T(1) - fr) * line[p0];
+        if (p0 + 1 >= 0 && p0 + 1 < nline) acc += fr * line[p0 + 1];
+    }
+    b[ri] = acc * (T)e.z;
+}
+
+// Detector position (in bin units) of the ray from the source through the point (X, Y); the
+// reciprocal of the depth from an FP32 estimate and one Newton step (relative error ~1e-14,
+// no FP64 division): it only bounds the candidate rays of a pixel (margin 0.05 bins).
+__device__ __forceinline__ double fan_pos_bound(double X, double Y, double c, double s, double dso, double g,
+                                                double off) {
+    const double t = X * c + Y * s, den = dso - X * s + Y * c;
+    double inv = (double)__frcp_rn((float)den);
+    inv = inv * (2.0 - den * inv);
+    inv = inv * (2.0 - den * inv);
+    return g * t * inv + off;
+}
+
+// Transpose: one lane per pixel; per angle the candidate bins lie between the projections
+// of the pixel's four neighbours.
+template <class T>
 __global__ __launch_bounds__(256) void k_fan_adj(const Tile* __restrict__ tiles, const RadonFrame* __restrict__ rf,
-                                                 const double2* __restrict__ trig, const T* __restrict__ b,
-                                                 T* __restrict__ u, FanGeo geo) {
+                                                 const double2* __restrict__ trig, const double4* __restrict__ table,
+                                                 const T* __restrict__ b, T* __restrict__ u, FanGeo geo) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const RadonFrame f = rf[tl.frame];
     const int x = tl.x0 + (int)threadIdx.x % RTW, y = tl.y0 + (int)threadIdx.x / RTW;
     if (x >= f.nx || y >= f.ny) return;
-    const double cx = (f.nx - 1) / 2.0, cy = (f.ny - 1) / 2.0;
-    const double X = x - cx, Y = y - cy;
+    const double X = x - (f.nx - 1) / 2.0, Y = y - (f.ny - 1) / 2.0;
     const int nb = f.n_bins;
+    const double gsc = geo.dsd / geo.du, off = (nb - 1) / 2.0;
     T acc = T(0);
     for (int k = 0; k < f.n_ang; ++k) {
         const double2 cs = trig[f.trig_off + k];
-        const double p0 = fan_pos(X - 1.0, Y, cs.x, cs.y, nb, geo), p1 = fan_pos(X + 1.0, Y, cs.x, cs.y, nb, geo);
-        const double p2 = fan_pos(X, Y - 1.0, cs.x, cs.y, nb, geo), p3 = fan_pos(X, Y + 1.0, cs.x, cs.y, nb, geo);
+        const double p0 = fan_pos_bound(X - 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
+        const double p1 = fan_pos_bound(X + 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
+        const double p2 = fan_pos_bound(X, Y - 1.0, cs.x, cs.y, geo.dso, gsc, off);
+        const double p3 = fan_pos_bound(X, Y + 1.0, cs.x, cs.y, geo.dso, gsc, off);
         const double lo = fmin(fmin(p0, p1), fmin(p2, p3)), hi = fmax(fmax(p0, p1), fmax(p2, p3));
         // candidate bins, clamped to the detector before the conversion to int
-        const int jlo = (int)fmin(fmax(floor(lo) - 1.0, 0.0), (double)nb);
-        const int jhi = (int)fmax(fmin(ceil(hi) + 1.0, (double)(nb - 1)), -1.0);
-        const T* bk = b + f.sino_off + (int64_t)k * nb;
+        const int jlo = (int)fmin(fmax(floor(lo - 0.05), 0.0), (double)nb);
+        const int jhi = (int)fmax(fmin(ceil(hi + 0.05), (double)(nb - 1)), -1.0);
+        const int64_t row = f.sino_off + (int64_t)k * nb;
         for (int j = jlo; j <= jhi; ++j) {
-            double sx, sy, dx, dy;
-            fan_ray(cs.x, cs.y, j, nb, geo, sx, sy, dx, dy);
+            const double4 e = table[row + j];
+            const bool rows = e.w > 0.0;
+            const double pc = fma(e.y, rows ? (double)y : (double)x, e.x);
+            const double p0d = floor(pc);
+            const T fr = (T)(pc - p0d);
+            const double own = rows ? (double)x : (double)y;
             T w = T(0);
-            double step;
-            if (fabs(dy) >= fabs(dx)) {
-                step = sqrt(dx * dx + dy * dy) / fabs(dy);
-                const double xc = sx + (((double)y - cy) - sy) * dx / dy + cx;
-                const double x0d = floor(xc);
-                const T fr = (T)(xc - x0d);
-                if (x0d == (double)x) w = T(1) - fr;
-                else if (x0d + 1.0 == (double)x) w = fr;
-            } else {
-                step = sqrt(dx * dx + dy * dy) / fabs(dx);
-                const double yc = sy + (((double)x - cx) - sx) * dy / dx + cy;
-                const double y0d = floor(yc);
-                const T fr = (T)(yc - y0d);
-                if (y0d == (double)y) w = T(1) - fr;
-                else if (y0d + 1.0 == (double)y) w = fr;
-            }
-            if (w != T(0)) acc += (w * (T)step) * bk[j];
+            if (p0d == own) w = T(1) - fr;
+            else if (p0d + 1.0 == own) w = fr;
+            if (w != T(0)) acc += (w * (T)e.z) * b[row + j];
         }
     }
     u[f.u_off + (int64_t)y * f.nx + x] = acc;
 }
 
-void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
+void fan_plan_init(Ctx& c, Plan& p) {
+    p.d_fanrays.ensure(sizeof(double4) * (size_t)std::max<int64_t>(p.m, 1));
     if (p.n_rays[2] == 0) return;
     const FanGeo geo{p.fan_dso, p.fan_dsd, p.fan_du};
+    hipLaunchKernelGGL(k_fan_rays, dim3((unsigned)p.n_rays[2]), dim3(256), 0, c.stream, p.d_rays[2].as<RayTile>(),
+                       p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), geo, p.d_fanrays.as<double4>());
+    MMOF_LAUNCH_CHECK();
+    MMOF_HIP(hipStreamSynchronize(c.stream));
+}
+
+void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
+    if (p.n_rays[2] == 0) return;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         T* ut = static_cast<T*>(c.work("radon_transpose", sizeof(T) * p.n));
@@ -419,8 +443,8 @@ void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
         MMOF_LAUNCH_CHECK();
         ScopedTime st(&c, "fan_fwd", (double)sizeof(T) * (p.n + p.m), 0.0);
         hipLaunchKernelGGL(k_fan_fwd<T>, dim3((unsigned)p.n_rays[2]), dim3(256), 0, c.stream,
-                           p.d_rays[2].as<RayTile>(), p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(),
-                           (const T*)u, (const T*)ut, (T*)b, geo);
+                           p.d_rays[2].as<RayTile>(), p.d_rinfo.as<RadonFrame>(), p.d_fanrays.as<double4>(),
+                           (const T*)u, (const T*)ut, (T*)b);
         MMOF_LAUNCH_CHECK();
     });
 }
@@ -431,7 +455,8 @@ void launch_fan_adj(Ctx& c, Plan& p, int dt, const void* b, void* u) {
         using T = decltype(z);
         ScopedTime st(&c, "fan_adj", (double)sizeof(T) * (p.n + p.m), 0.0);
         hipLaunchKernelGGL(k_fan_adj<T>, dim3((unsigned)p.n_tiles_a), dim3(256), 0, c.stream, p.d_tiles_a.as<Tile>(),
-                           p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), (const T*)b, (T*)u, geo);
+                           p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), p.d_fanrays.as<double4>(),
+                           (const T*)b, (T*)u, geo);
         MMOF_LAUNCH_CHECK();
     });
 }

@@ -109,5 +109,6 @@ void launch_fan_adj(Ctx& c, Plan& p, int dt, const void* b, void* u);
 // Builds the frame table, trig table users and tile lists of a projector plan (radon or fan);
 // the trig table must already be in p.d_trig.
 void radon_plan_init(Ctx& c, Plan& p);
+void fan_plan_init(Ctx& c, Plan& p);  // the per-ray table of a fan-beam plan (after radon_plan_init)
 
 }  // namespace mmof
