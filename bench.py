@@ -104,7 +104,7 @@ def gpu_data(wl, B, torch):
     return stack, plan, u_true, b, delta
 
 
-def operators_large(B, torch, reps=5):
+def operators_large(B, torch, reps=5, before_ops=None):
     """Per-kernel rates of the operators on the 1024x1024x64 workload (FP32; 90 angles per
     frame shifted by the golden angle, 1449 bins; a smooth flow of up to 3 px): HIP-event
     mean over `reps` launches, algorithmic bytes and flops as the library counts them."""
@@ -143,6 +143,8 @@ def operators_large(B, torch, reps=5):
     bf = B.apply_A(fplan, u)
     ops["fan_fwd"] = lambda: B.apply_A(fplan, u, out=bf)
     ops["fan_adj"] = lambda: B.apply_At(fplan, bf)
+    if before_ops is not None:
+        before_ops()
     table = {}
     for name, f in ops.items():
         f()
@@ -412,6 +414,9 @@ def main():
                     help="replay the fixed launch sequences of each iteration from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
+    ap.add_argument("--only", choices=["operators", "large-solve"],
+                    help="for profiler runs: only the operator table at 1024x1024x64 (after a 256 MiB copy), "
+                         "or only one FP32 solve of that workload (30 iterations, after the autotuner)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no multi-GPU path.",
@@ -423,6 +428,31 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.only == "operators":
+        def calibration_copy():
+            src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        # every operator: one warm-up launch, then 3 timed ones, right after the copy
+        print(json.dumps(operators_large(B, torch, reps=3, before_ops=calibration_copy)), flush=True)
+        return
+    if a.only == "large-solve":
+        from synth import cfg_large1024
+        wl = cfg_large1024()
+        stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
+        p = wl.params
+        for dt in (torch.float32, torch.float64):
+            log(f"large autotune {dt}: {plan.autotune(dt)}")
+        t0 = time.perf_counter()
+        r = B.solve_joint(plan, b, delta, u_true=u_true, op_dtype="f32", ell=p["ell"], k_max=30, tau=p["tau"],
+                          n_sweeps=p["n_sweeps"], alpha=p["alpha"], eps=p["eps"], eta=p["eta"],
+                          delta_r=p["delta_r"])
+        torch.cuda.synchronize()
+        print(json.dumps({"seconds": time.perf_counter() - t0, "iters": r.iters, "rre": r.rre[-1],
+                          "counts": r.counts}), flush=True)
+        return
     wl = make_workload()
     stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
     ctx = plan.ctx
