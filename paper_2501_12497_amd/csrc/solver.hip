@@ -44,6 +44,14 @@ struct PhaseOut {
     const void* flow_vr = nullptr;
 };
 
+// Destroys a HIP event when the scope ends.
+struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
 template <class TX>
 struct Solver {
     Ctx& c;
@@ -402,36 +410,49 @@ struct Solver {
         // report slots: scal[6] = ||u - u_true||^2, scal[7] = ||r||^2, scal[8..11] = lambda,
         // D^2, status, factorizations (written by the projected solve)
         double* res = scal + 8;
+        // Steps 2-5 of the next iteration (and the column append that precedes them) change
+        // only the solver's own buffers, so they are queued before the host waits for the
+        // report of the current iteration: the device keeps working while the host decides
+        // whether to stop (a stop discards them; the operator counts they added are taken
+        // back).  Not when the next iteration updates the flow (that changes the returned
+        // flows) and not while projected systems are being dumped.
+        const bool may_queue_ahead = std::getenv("MMOF_DUMP_PROJECTED") == nullptr;
+        EventGuard ev_rep;
+        MMOF_HIP(hipEventCreateWithFlags(&ev_rep.e, hipEventDisableTiming));
+        bool queued = false;  // steps 2-5 of this iteration are already queued
         for (int k = ph.k_begin; k < ph.k_end; ++k) {
-            // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
-            if (flow && k % p.tau == 0) {
-                replayable(graph_key("flow"), [&] {
-                    FlowWork w;
-                    w.I = I;
-                    w.tmp = flow_tmp;
-                    w.us = flow_us;
-                    w.vs = flow_vs;
-                    w.gks = gks;
-                    fm.gamma = gamma;
-                    flow_update_core(c, g, gs, dt, u_op, flow_v, fscale, p.delta_r, fm, w);
-                    launch_flow_radius(c, g, dt, flow_v, rad_v);
-                    if (p.use_reverse) {
-                        launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);
-                        launch_flow_radius(c, g, dt, flow_vr, rad_vr);
-                    }
-                });
-                launch_flow_fwd_cols(c, g, dt, p.interp, V, n, K, flow_v, p.use_reverse ? flow_vr : nullptr, TV, R,
-                                     oRF, oRR);
-                if (rep) rep->n_L += (int64_t)K * (p.use_reverse ? 2 : 1);
-                if (rep) rep->n_flow_updates++;
-                nu_fresh = false;
+            if (!queued) {
+                // 1. flow update on u^(k) and rebuild of the flow rows of Theta V
+                if (flow && k % p.tau == 0) {
+                    replayable(graph_key("flow"), [&] {
+                        FlowWork w;
+                        w.I = I;
+                        w.tmp = flow_tmp;
+                        w.us = flow_us;
+                        w.vs = flow_vs;
+                        w.gks = gks;
+                        fm.gamma = gamma;
+                        flow_update_core(c, g, gs, dt, u_op, flow_v, fscale, p.delta_r, fm, w);
+                        launch_flow_radius(c, g, dt, flow_v, rad_v);
+                        if (p.use_reverse) {
+                            launch_reverse_flow(c, g, dt, flow_v, flow_vr, rad_v);
+                            launch_flow_radius(c, g, dt, flow_vr, rad_vr);
+                        }
+                    });
+                    launch_flow_fwd_cols(c, g, dt, p.interp, V, n, K, flow_v, p.use_reverse ? flow_vr : nullptr, TV, R,
+                                         oRF, oRR);
+                    if (rep) rep->n_L += (int64_t)K * (p.use_reverse ? 2 : 1);
+                    if (rep) rep->n_flow_updates++;
+                    nu_fresh = false;
+                }
+                // 2. nu = Theta u^(k); FP64 weights; weighted Gram of Theta V
+                if (!nu_fresh) theta(u_op, nu);
+                mm_weights_f64<TX>(c, R, nu, p.eps, w2);
+                wgram<TX>(c, R, K, TV, R, w2, GT, KMAX_SMALL);
+                // 3-5. lambda (discrepancy principle) and z; lambda is kept in sc[2] as the next warm start
+                small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
             }
-            // 2. nu = Theta u^(k); FP64 weights; weighted Gram of Theta V
-            if (!nu_fresh) theta(u_op, nu);
-            mm_weights_f64<TX>(c, R, nu, p.eps, w2);
-            wgram<TX>(c, R, K, TV, R, w2, GT, KMAX_SMALL);
-            // 3-5. lambda (discrepancy principle) and z; lambda is kept in sc[2] as the next warm start
-            small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
+            queued = false;
             // 6. u^(k+1) = V z (FP64 and operator copies, and ||u - u_true||^2)
             gemv_fused<double, TX>(c, n, K, V, n, z, 1.0, nullptr, 0.0, u_io, u_op, p.u_true,
                                    p.u_true ? scal + 6 : nullptr);
@@ -456,7 +477,30 @@ struct Solver {
                 nu_fresh = true;
             }
             MMOF_HIP(hipMemcpyAsync(host, scal + 6, 6 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            MMOF_HIP(hipStreamSynchronize(c.stream));
+            MMOF_HIP(hipEventRecord(ev_rep.e, c.stream));
+            const bool ahead = may_queue_ahead && !last && k + 1 < ph.k_end && !(flow && (k + 1) % p.tau == 0) &&
+                               K + 1 <= Kcap;
+            mmof_report saved{};
+            if (rep) saved = *rep;
+            if (ahead) {
+                normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
+                add_column(K, true);
+                if (!nu_fresh) theta(u_op, nu);
+                mm_weights_f64<TX>(c, R, nu, p.eps, w2);
+                wgram<TX>(c, R, K + 1, TV, R, w2, GT, KMAX_SMALL);
+                small_solve(c, K + 1, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
+            }
+            // counts of work queued ahead, taken back if the iteration ends the solve
+            auto take_back = [&] {
+                if (ahead && rep) {
+                    rep->n_A = saved.n_A;
+                    rep->n_At = saved.n_At;
+                    rep->n_theta = saved.n_theta;
+                    rep->n_thetaT = saved.n_thetaT;
+                    rep->n_L = saved.n_L;
+                }
+            };
+            MMOF_HIP(hipEventSynchronize(ev_rep.e));
             const double rre2 = host[0], rnorm = std::sqrt(std::max(host[1], 0.0));
             const double lam = host[2], D2 = host[3];
             const int st = (int)host[4];
@@ -477,6 +521,7 @@ struct Solver {
             }
             if (rep) rep->n_cols = K;
             if (p.u_true && p.rre_target > 0 && rre <= p.rre_target) {
+                take_back();
                 stopped = true;
                 break;
             }
@@ -486,13 +531,17 @@ struct Solver {
             }
             // 9. breakdown or append r/||r||
             if (!(rnorm > 1e-14 * atb)) {
+                take_back();
                 status = MMOF_WARN_BREAKDOWN;
                 stopped = true;
                 break;
             }
-            normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
-            add_column(K, true);
+            if (!ahead) {
+                normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
+                add_column(K, true);
+            }
             ++K;
+            queued = ahead;
         }
         if (rep) {
             rep->iters = std::max(rep->iters, iters);
