@@ -307,8 +307,12 @@ __global__ __launch_bounds__(64) void k_small_solve(int K, const double* __restr
                 nmu = 0.5 * (lo + hi);
             }
             if (fabs(nmu - mu) <= 1e-11 * fmax(1.0, fabs(mu)) || hi - lo <= 1e-14 * fmax(1.0, fabs(mu))) {
-                mu = nmu;
-                e = evaluate(s, K, pow(10.0, mu), bb, d, false, nfac);
+                // converged to ~1e-11 in log10(lambda): keep the evaluation at mu (its z and
+                // D^2 differ from those at the root by the same relative amount) unless it failed
+                if (!e.ok) {
+                    mu = nmu;
+                    e = evaluate(s, K, pow(10.0, mu), bb, d, false, nfac);
+                }
                 break;
             }
             mu = nmu;
