@@ -60,6 +60,19 @@ __device__ __forceinline__ int round_clip(int x, T v, int n) {
     return r < 0 ? 0 : (r > n - 1 ? n - 1 : r);
 }
 
+// Two consecutive values loaded by one instruction from an address aligned to one element
+// (global memory accepts element-aligned multi-word loads).
+template <class T>
+struct Pair {
+    T a, b;
+};
+template <class T>
+__device__ __forceinline__ Pair<T> ld2(const T* p) {
+    typedef T V2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+    const V2 v = *reinterpret_cast<const V2*>(p);
+    return Pair<T>{v.x, v.y};
+}
+
 // Four consecutive values moved as one 16-byte (FP32) or two 16-byte (FP64) accesses; the
 // address must be aligned to 4 elements.
 template <class T>

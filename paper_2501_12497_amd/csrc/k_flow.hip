@@ -31,11 +31,16 @@ __device__ __forceinline__ T warp_sample(const S* __restrict__ src, int nx, int 
     bool cx, cy;
     clip_cell(x, vx, nx, x0, fx, cx);
     clip_cell(y, vy, ny, y0, fy, cy);
-    const int x1 = min(x0 + 1, nx - 1), y1 = min(y0 + 1, ny - 1);
+    const int y1 = min(y0 + 1, ny - 1);
     const S* r0 = src + (int64_t)y0 * nx;
     const S* r1 = src + (int64_t)y1 * nx;
-    return (T(1) - fx) * (T(1) - fy) * (T)r0[x0] + fx * (T(1) - fy) * (T)r0[x1] + (T(1) - fx) * fy * (T)r1[x0] +
-           fx * fy * (T)r1[x1];
+    // the two pixels of a row as one 2-element load at xa = min(x0, nx - 2) (nx >= 2); a cell
+    // clipped to the last column (x0 = nx - 1, fx = 0) takes its value from the second one
+    const int xa = min(x0, nx - 2);
+    const Pair<S> p0 = ld2(r0 + xa), p1 = ld2(r1 + xa);
+    const bool edge = xa != x0;
+    const T a0 = (T)(edge ? p0.b : p0.a), a1 = (T)p0.b, b0 = (T)(edge ? p1.b : p1.a), b1 = (T)p1.b;
+    return (T(1) - fx) * (T(1) - fy) * a0 + fx * (T(1) - fy) * a1 + (T(1) - fx) * fy * b0 + fx * fy * b1;
 }
 
 template <class T, int INTERP, int FTW, int FTH>
