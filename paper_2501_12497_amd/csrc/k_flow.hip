@@ -402,9 +402,12 @@ __global__ __launch_bounds__(256) void k_flow_dv(const Tile* __restrict__ tiles,
     bool cx, cy;
     clip_cell(x, vv[p], nx, x0, fx, cx);
     clip_cell(y, vv[np + p], ny, y0, fy, cy);
-    const int x1 = min(x0 + 1, nx - 1), y1 = min(y0 + 1, ny - 1);
-    const T s00 = src[(int64_t)y0 * nx + x0], s01 = src[(int64_t)y0 * nx + x1];
-    const T s10 = src[(int64_t)y1 * nx + x0], s11 = src[(int64_t)y1 * nx + x1];
+    const int y1 = min(y0 + 1, ny - 1);
+    // row pairs as in warp_sample (a cell clipped to the last column reads the second element)
+    const int xa = min(x0, nx - 2);
+    const Pair<T> p0 = ld2(src + (int64_t)y0 * nx + xa), p1 = ld2(src + (int64_t)y1 * nx + xa);
+    const bool edge = xa != x0;
+    const T s00 = edge ? p0.b : p0.a, s01 = p0.b, s10 = edge ? p1.b : p1.a, s11 = p1.b;
     const T ww = w[f.pair_off + p];
     T dx = (T(1) - fy) * (s01 - s00) + fy * (s11 - s10);
     T dy = (T(1) - fx) * (s10 - s00) + fx * (s11 - s01);

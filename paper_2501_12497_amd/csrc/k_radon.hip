@@ -81,7 +81,10 @@ __device__ __forceinline__ T hat_row_inner(const T* __restrict__ row, int ncol, 
     const T w0 = T(1) - aa * fr;
     const T w1 = T(1) - aa * (T(1) - fr);
     const T w2 = fmax(T(1) - aa * (T(1) + (lo ? fr : T(1) - fr)), T(0));
-    return w0 * row[xi] + w1 * row[xi + 1] + w2 * row[lo ? xi - 1 : xi + 2];
+    // the four pixels xi - 1 .. xi + 2 (all inside the row) as one 4-element load
+    typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+    const V4 q = *reinterpret_cast<const V4*>(row + xi - 1);
+    return w0 * q.y + w1 * q.z + w2 * (lo ? q.x : q.w);
 }
 
 // One workgroup of 8 waves per (frame, ANG consecutive angles, 64 bins): lane = bin, wave
@@ -364,8 +367,14 @@ __global__ __launch_bounds__(256) void k_fan_fwd(const RayTile* __restrict__ ray
         const T fr = (T)(pc - p0d);
         const int p0 = (int)p0d;
         const T* line = img + (int64_t)q * nline;
-        if (p0 >= 0 && p0 < nline) acc += (T(1) - fr) * line[p0];
-        if (p0 + 1 >= 0 && p0 + 1 < nline) acc += fr * line[p0 + 1];
+        if (p0 >= 0 && p0 + 1 < nline) {  // both pixels inside: one 2-element load
+            const Pair<T> pr = ld2(line + p0);
+            acc += (T(1) - fr) * pr.a;
+            acc += fr * pr.b;
+        } else {
+            if (p0 >= 0 && p0 < nline) acc += (T(1) - fr) * line[p0];
+            if (p0 + 1 >= 0 && p0 + 1 < nline) acc += fr * line[p0 + 1];
+        }
     }
     b[ri] = acc * (T)e.z;
 }
