@@ -47,6 +47,28 @@ __device__ __forceinline__ double dot_row(const TX* __restrict__ X, int64_t ld, 
     return acc;
 }
 
+// dot_row for the rows i and i + 1 at once (i even, ld even, X aligned to two elements):
+// one 2-element load per column; each row's sum in column order as in dot_row.
+template <class TX>
+__device__ __forceinline__ void dot_row2(const TX* __restrict__ X, int64_t ld, int64_t i, int K,
+                                         const double* __restrict__ h, double& a0, double& a1) {
+    typedef TX V2 __attribute__((ext_vector_type(2)));
+    a0 = 0.0;
+    a1 = 0.0;
+    for (int j0 = 0; j0 < K; j0 += 8) {
+        V2 q[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            q[t] = j0 + t < K ? *reinterpret_cast<const V2*>(X + (int64_t)(j0 + t) * ld + i) : V2{TX(0), TX(0)};
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (j0 + t < K) {
+                a0 += (double)q[t].x * h[j0 + t];
+                a1 += (double)q[t].y * h[j0 + t];
+            }
+    }
+}
+
 // FP64 MM weights w2 = 1/sqrt(nu^2 + eps^2) of the rows of Theta.
 template <class TX>
 __global__ void k_mm_weights_f64(int64_t n, const TX* __restrict__ nu, double eps2, double* __restrict__ w) {
@@ -87,6 +109,69 @@ __global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, const TX* __restr
         for (int q = 0; q < 8; ++q) {
             const int j = j0 + q;
             if (q < nj) acc[q] += (j < K ? (double)X[(int64_t)j * ld + i] : xe[i]) * yi;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s8[w][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < nj)
+        part[(int64_t)blockIdx.x * Kt + j0 + threadIdx.x] =
+            (s8[0][threadIdx.x] + s8[1][threadIdx.x]) + (s8[2][threadIdx.x] + s8[3][threadIdx.x]);
+}
+
+// k_mdot with two rows per lane (chunks of an even number of rows; 2-element loads of the
+// columns, of y and of xe); a chunk with an odd row count ends with one single row.
+template <class TX, class TY>
+__global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
+                                              const TY* __restrict__ y, const double* __restrict__ xe,
+                                              double* __restrict__ part) {
+    typedef TX VX __attribute__((ext_vector_type(2)));
+    typedef TY VY __attribute__((ext_vector_type(2)));
+    typedef double VD __attribute__((ext_vector_type(2)));
+    __shared__ double s8[4][8];
+    const int Kt = K + (xe ? 1 : 0);
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = 2 * ((n + 2 * nb - 1) / (2 * nb));
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j0 = blockIdx.y * 8;
+    const int nj = min(8, Kt - j0);
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int64_t i = lo + 2 * (int64_t)threadIdx.x; i < hi; i += 2 * KB) {
+        if (i + 1 < hi) {
+            const VY yv = *reinterpret_cast<const VY*>(y + i);
+            const double y0 = (double)yv.x, y1 = (double)yv.y;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + q;
+                if (q < nj) {
+                    double x0, x1;
+                    if (j < K) {
+                        const VX xv = *reinterpret_cast<const VX*>(X + (int64_t)j * ld + i);
+                        x0 = (double)xv.x;
+                        x1 = (double)xv.y;
+                    } else {
+                        const VD xv = *reinterpret_cast<const VD*>(xe + i);
+                        x0 = xv.x;
+                        x1 = xv.y;
+                    }
+                    acc[q] += x0 * y0;
+                    acc[q] += x1 * y1;
+                }
+            }
+        } else {
+            const double yi = (double)y[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + q;
+                if (q < nj) acc[q] += (j < K ? (double)X[(int64_t)j * ld + i] : xe[i]) * yi;
+            }
         }
     }
 #pragma unroll
@@ -170,6 +255,41 @@ __global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* _
         if (part) {
             const double e = cv ? v - cv[i] : v;
             e2 += e * e;
+        }
+    }
+    if (!part) return;
+    const double bs = block_sum(e2, s4);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// k_gemv_fused with two rows per lane (dot_row2); n odd leaves one single row.
+template <class TX, class TO>
+__global__ __launch_bounds__(KB) void k_gemv_fused2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
+                                                    const double* __restrict__ h, double alpha, const double* y,
+                                                    double beta, double* out_d, TO* __restrict__ out_t,
+                                                    const double* __restrict__ cv, double* __restrict__ part) {
+    __shared__ double sh[KMAX_SMALL];
+    __shared__ double s4[4];
+    for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
+    __syncthreads();
+    double e2 = 0.0;
+    auto finish = [&](int64_t i, double acc) {
+        const double v = alpha * acc + (y ? beta * y[i] : 0.0);
+        if (out_d) out_d[i] = v;
+        if (out_t) out_t[i] = (TO)v;
+        if (part) {
+            const double e = cv ? v - cv[i] : v;
+            e2 += e * e;
+        }
+    };
+    for (int64_t i = 2 * ((int64_t)blockIdx.x * KB + threadIdx.x); i < n; i += 2 * (int64_t)gridDim.x * KB) {
+        if (i + 1 < n) {
+            double a0, a1;
+            dot_row2(X, ld, i, K, sh, a0, a1);
+            finish(i, a0);
+            finish(i + 1, a1);
+        } else {
+            finish(i, dot_row(X, ld, i, K, sh));
         }
     }
     if (!part) return;
@@ -555,6 +675,14 @@ int mdot_blocks(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, nb));
 }
 
+// Two rows per lane (k_mdot2) when every column, y and xe allow 2-element loads.
+template <class TX, class TY>
+static bool mdot_pairs(const TX* X, int64_t ld, const TY* y, const double* xe) {
+    return ld % 2 == 0 && reinterpret_cast<uintptr_t>(X) % (2 * sizeof(TX)) == 0 &&
+           reinterpret_cast<uintptr_t>(y) % (2 * sizeof(TY)) == 0 &&
+           (!xe || reinterpret_cast<uintptr_t>(xe) % (2 * sizeof(double)) == 0);
+}
+
 template <class TX, class TY>
 void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double alpha, double* out) {
     if (K <= 0) return;
@@ -563,8 +691,12 @@ void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double
     double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
     {
         ScopedTime st(&c, "mdot", (double)n * ((double)sizeof(TX) * K + sizeof(TY)), 2.0 * n * K);
-        hipLaunchKernelGGL((k_mdot<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld, y,
-                           (const double*)nullptr, part);
+        if (mdot_pairs(X, ld, y, nullptr))
+            hipLaunchKernelGGL((k_mdot2<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld,
+                               y, (const double*)nullptr, part);
+        else
+            hipLaunchKernelGGL((k_mdot<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld,
+                               y, (const double*)nullptr, part);
         MMOF_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, K, part, alpha, out, (double*)nullptr, 0, 0,
@@ -598,8 +730,12 @@ void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e
     const int nb = mdot_blocks(n);
     double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
     const TX* xj = X + (int64_t)j * ld;
-    hipLaunchKernelGGL((k_mdot<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1, X,
-                       ld, xj, e, part);
+    if (mdot_pairs(X, ld, xj, e))
+        hipLaunchKernelGGL((k_mdot2<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1,
+                           X, ld, xj, e, part);
+    else
+        hipLaunchKernelGGL((k_mdot<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1,
+                           X, ld, xj, e, part);
     MMOF_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, j + 2, part, 1.0, (double*)nullptr, G, ldg,
                        j, dj);
@@ -616,15 +752,21 @@ void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double*
         if (sq) set_scalar(c, sq, 0.0);
         return;
     }
-    const dim3 grid = grid_for(n, KB, 2048);
+    // two rows per lane when the columns allow 2-element loads (the grid covers row pairs)
+    const bool pair = ld % 2 == 0 && reinterpret_cast<uintptr_t>(X) % (2 * sizeof(TX)) == 0;
+    const dim3 grid = grid_for(pair ? cdiv(n, 2) : n, KB, 2048);
     double* part = sq ? static_cast<double*>(c.work("gemv_part", sizeof(double) * 2048)) : nullptr;
     {
         // K columns and y (if any) read, the outputs written, cv read when given
         const double bytes = (double)n * ((double)sizeof(TX) * K + (y ? 8.0 : 0.0) + (out_d ? 8.0 : 0.0) +
                                           (out_t ? (double)sizeof(TO) : 0.0) + (cv ? 8.0 : 0.0));
         ScopedTime st(&c, "gemv", bytes, 2.0 * n * K);
-        hipLaunchKernelGGL((k_gemv_fused<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta, out_d,
-                           out_t, cv, part);
+        if (pair)
+            hipLaunchKernelGGL((k_gemv_fused2<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta,
+                               out_d, out_t, cv, part);
+        else
+            hipLaunchKernelGGL((k_gemv_fused<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta,
+                               out_d, out_t, cv, part);
         MMOF_LAUNCH_CHECK();
     }
     if (sq) {
