@@ -36,6 +36,14 @@ Readings (the paper is silent or garbled):
   * Y^T b = 0 (no temporal change, or none where the frame has a gradient) gives s = 0.
   * The reverse flow is not solved for: the Remark on the reverse optical flow forms it
     from s (optflow.reverse_flow).
+
+The p = q = 1 variant (mentioned for standalone flow problems) is MMGKS proper on
+||Y s - b||_1 + lambda ||L s||_1 smoothed with eps (phi_eps(x) = sqrt(x^2 + eps^2), as for the
+image problem): at iteration k the weights come from the current iterate s^(k) (s^(0) = 0),
+W_d = diag((e^2 + eps^2)^(-1/2)) on the data rows (e = Y s^(k) - b) and
+W_r = diag(((L s^(k))^2 + eps^2)^(-1/2)) on the rows of L; the projected problem, GCV and the
+residual use Y -> W_d^(1/2) Y, b -> W_d^(1/2) b, L -> W_r^(1/2) L (so G is the printed functional
+of the weighted problem); the rest as above.  Reading: eps = 1e-3, the image problem's value.
 """
 from __future__ import annotations
 
@@ -73,6 +81,17 @@ def pair_ops(I: np.ndarray):
     return Y, Yt, L, Lt
 
 
+EPS_L1 = 1e-3
+
+
+def l1_weights(I: np.ndarray, s: np.ndarray, eps: float = EPS_L1):
+    """W_d and W_r (as vectors) of the p = q = 1 majorant at the iterate s [2 n]."""
+    Y, _, L, _ = pair_ops(I)
+    e = Y(s) + I[2].ravel()                  # Y s - b with b = -I_t
+    g = L(s)
+    return 1.0 / np.sqrt(e * e + eps * eps), 1.0 / np.sqrt(g * g + eps * eps)
+
+
 def gcv_value(YV: np.ndarray, LV: np.ndarray, b: np.ndarray, lam: float):
     """G(lambda) of the projected solution and its z (inf when the problem is singular)."""
     m = b.size
@@ -107,9 +126,9 @@ def gcv_lambda(YV: np.ndarray, LV: np.ndarray, b: np.ndarray) -> float:
 
 
 def solve_of_pair(I: np.ndarray, ell: int = 10, n_iter: int = 20, fixed_lambda: float = 0.0,
-                  basis: list = None):
+                  basis: list = None, p: int = 2, eps: float = EPS_L1):
     """s [2, ny, nx] of one pair and the lambda of every iteration (`basis`, if given, receives
-    the final V)."""
+    the final V); p = 1: the p = q = 1 MM variant."""
     ny, nx = I.shape[1:]
     b = -I[2].ravel()
     Y, Yt, L, Lt = pair_ops(I)
@@ -118,17 +137,26 @@ def solve_of_pair(I: np.ndarray, ell: int = 10, n_iter: int = 20, fixed_lambda: 
         return np.zeros((2, ny, nx)), []
     V = mmgks.gkb(Y, Yt, b, ell)[0]
     lams = []
-    s = None
+    s = np.zeros(2 * ny * nx)
     for k in range(n_iter):
-        YV = np.stack([Y(V[:, j]) for j in range(V.shape[1])], axis=1)
+        if p == 1:
+            wd, wr = l1_weights(I, s, eps)
+        else:
+            wd, wr = np.ones(b.size), None
+        sd = np.sqrt(wd)
+        YV = np.stack([sd * Y(V[:, j]) for j in range(V.shape[1])], axis=1)
         LV = np.stack([L(V[:, j]) for j in range(V.shape[1])], axis=1)
-        lam = fixed_lambda if fixed_lambda > 0 else gcv_lambda(YV, LV, b)
+        if wr is not None:
+            LV = np.sqrt(wr)[:, None] * LV
+        bw = sd * b
+        lam = fixed_lambda if fixed_lambda > 0 else gcv_lambda(YV, LV, bw)
         lams.append(lam)
-        z = gcv_value(YV, LV, b, lam)[1]
+        z = gcv_value(YV, LV, bw, lam)[1]
         s = V @ z
         if k == n_iter - 1:
             break
-        r = Yt(YV @ z - b) + lam * Lt(LV @ z)
+        # r = Y^T W_d (Y s - b) + lambda L^T W_r L s  (W = I for p = 2)
+        r = Yt(wd * (Y(s) - b)) + lam * Lt((wr if wr is not None else 1.0) * L(s))
         r = mmgks.reorth(V, r)
         nr = np.linalg.norm(r)
         if nr <= 1e-14 * atb:
@@ -140,11 +168,11 @@ def solve_of_pair(I: np.ndarray, ell: int = 10, n_iter: int = 20, fixed_lambda: 
 
 
 def solve_of(u: np.ndarray, dr: int = 1, ell: int = 10, n_iter: int = 20, fixed_lambda: float = 0.0,
-             f: int = 1):
+             f: int = 1, p: int = 2):
     """Flows [n_pairs, 2, ny, nx] of a sequence u [n_t, ny, nx] (each pair on its own), on
     frames reduced by f (optflow's block means and upscaling) when f > 1."""
     ny, nx = u.shape[1:]
     uw = optflow.box_down(u, f) if f > 1 else u
     I = optflow.of_derivs(uw, dr)
-    out = np.stack([solve_of_pair(I[t], ell, n_iter, fixed_lambda)[0] for t in range(I.shape[0])])
+    out = np.stack([solve_of_pair(I[t], ell, n_iter, fixed_lambda, p=p)[0] for t in range(I.shape[0])])
     return optflow.flow_up(out, f, ny, nx) if f > 1 else out

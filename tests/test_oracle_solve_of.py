@@ -161,3 +161,55 @@ def test_no_change_and_translation():
     # the regulariser): the right direction and about half to all of the shift
     assert 0.2 < np.median(s[0][inner]) < 0.6
     assert abs(np.median(s[1][inner])) < 0.05
+
+
+# ------------------------------------------------------------------ p = q = 1 variant
+
+
+def _j_l1(I, s, lam, eps):
+    Y, _, L, _ = solve_of.pair_ops(I)
+    e = Y(s.ravel()) + I[2].ravel()
+    g = L(s.ravel())
+    return float(np.sqrt(e * e + eps * eps).sum() + lam * np.sqrt(g * g + eps * eps).sum())
+
+
+def test_l1_with_huge_eps_is_the_quadratic_solver():
+    """eps far above every residual makes both weights the same constant 1/eps: the weighted
+    problem is the p = q = 2 one scaled, with the same GCV choice and the same flow."""
+    I = optflow.of_derivs(np.stack([np.sin(0.5 * np.arange(11))[None, :] * np.ones((9, 1)),
+                                    np.sin(0.5 * (np.arange(11) - 0.3))[None, :] * np.ones((9, 1))]) +
+                          0.01 * np.random.default_rng(11).standard_normal((2, 9, 11)), 1)[0]
+    s2, l2 = solve_of.solve_of_pair(I, ell=5, n_iter=6)
+    s1, l1 = solve_of.solve_of_pair(I, ell=5, n_iter=6, p=1, eps=1e8)
+    assert np.linalg.norm(s1 - s2) <= 1e-8 * np.linalg.norm(s2)
+    np.testing.assert_allclose(l1, l2, rtol=1e-8)
+
+
+@pytest.mark.parametrize("lam", [0.05, 0.5])
+def test_l1_majorize_minimize_decreases_the_objective(lam):
+    """At a fixed lambda every MM iterate lowers the smoothed l1 objective (the iterate of
+    step k lies in the grown basis of step k + 1, and the quadratic majorant touches J there)."""
+    I = _pair(12, 5, 6)
+    eps = 1e-2
+    prev = None
+    for k in range(1, 12):
+        s, _ = solve_of.solve_of_pair(I, ell=4, n_iter=k, fixed_lambda=lam, p=1, eps=eps)
+        j = _j_l1(I, s, lam, eps)
+        if prev is not None:
+            assert j <= prev * (1 + 1e-12), k
+        prev = j
+
+
+def test_l1_converges_to_a_stationary_point():
+    """With a basis that grows to the whole space and a fixed lambda, the iterates approach
+    a zero of the gradient of the smoothed objective (dense matrices)."""
+    I = _pair(13, 3, 4)
+    Y, L = _dense_ops(I)
+    b = -I[2].ravel()
+    lam, eps = 0.2, 1e-1
+    s, _ = solve_of.solve_of_pair(I, ell=4, n_iter=32, fixed_lambda=lam, p=1, eps=eps)
+    x = s.ravel()
+    e, g = Y @ x - b, L @ x
+    grad = Y.T @ (e / np.sqrt(e * e + eps * eps)) + lam * L.T @ (g / np.sqrt(g * g + eps * eps))
+    g0 = Y.T @ (-b / np.sqrt(b * b + eps * eps))
+    assert np.linalg.norm(grad) <= 1e-3 * np.linalg.norm(g0)
