@@ -238,6 +238,23 @@ int mmof_flow_solve_gks(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, co
                         void* v, void* v_rev, int32_t delta_r, int32_t ell, int32_t n_iter,
                         double fixed_lambda, int32_t scale, double* lambdas);
 
+/* Solve-OF (Alg. 2) with a choice of norms: pq = 2 is mmof_flow_solve_gks; pq = 1 is the
+ * p = q = 1 variant, MMGKS on ||Y s - b||_1 + lambda ||L s||_1 smoothed with eps (each
+ * |x| -> sqrt(x^2 + eps^2), as for the image problem, eq. smoothed-l1 / Sec. 3.1): at
+ * projected solve k the weights come from the iterate s^(k) (s^(0) = 0),
+ *   W_d = diag((e^2 + eps^2)^(-1/2)), e = Y s^(k) - b   (data rows),
+ *   W_r = diag(((L s^(k))^2 + eps^2)^(-1/2))           (rows of L),
+ * and the projected problem, the GCV functional and the residual are those of the weighted
+ * problem (Y -> W_d^(1/2) Y, b -> W_d^(1/2) b, L -> W_r^(1/2) L; m stays the pixel count);
+ * the basis, start and stopping rule as for pq = 2 (the weighted Gram matrices are formed
+ * anew at every solve).  Arguments, output, lambdas and errors as for mmof_flow_solve_gks,
+ * plus MMOF_ERR_INVALID unless pq is 1 or 2 and, for pq = 1, eps > 0 (the paper's reading:
+ * 1e-3).  Workspace with pq = 1: 5 more doubles per pixel of the pairs. */
+int mmof_flow_solve_of(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u,
+                       void* v, void* v_rev, int32_t delta_r, int32_t ell, int32_t n_iter,
+                       double fixed_lambda, int32_t scale, int32_t pq, double eps,
+                       double* lambdas);
+
 /* Reverse flow (Remark on estimating the reverse optical flow): v_rev at
  * rint(p + v(p)) = -v(p), contributions to one pixel averaged, pixels that receive
  * none set to 0, targets outside the frame dropped. */

@@ -70,6 +70,8 @@ _SIGS = {
                                      C.c_int32]),
     "mmof_flow_solve_gks": (_I, [_P, C.POINTER(mmof_stack), _I, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32,
                                  C.c_double, C.c_int32, _P]),
+    "mmof_flow_solve_of": (_I, [_P, C.POINTER(mmof_stack), _I, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32,
+                                C.c_double, C.c_int32, C.c_int32, C.c_double, _P]),
     "mmof_reverse_flow": (_I, [_P, C.POINTER(mmof_stack), _I, _P, _P]),
     "mmof_solve_defaults": (None, [C.POINTER(mmof_solve_params)]),
     "mmof_solve_joint": (_I, [_P, _P, C.c_double, C.POINTER(mmof_solve_params), _P, _P, _P,

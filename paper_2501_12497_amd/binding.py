@@ -363,8 +363,9 @@ def flow_update_scaled(stack: Stack, u: torch.Tensor, v: torch.Tensor, alpha: fl
 def flow_solve_gks(stack: Stack, u: torch.Tensor, v: torch.Tensor, delta_r: int = 1, ell: int = 10,
                    n_iter: int = 20, fixed_lambda: float = 0.0, scale: int = 1,
                    v_rev: Optional[torch.Tensor] = None, want_lambdas: bool = False,
-                   ctx: Optional[Context] = None):
-    """Solve-OF (GKS with GCV) into v; returns v, or (v, lambdas [pairs, n_iter]) when asked."""
+                   pq: int = 2, eps: float = 1e-3, ctx: Optional[Context] = None):
+    """Solve-OF (lambda by GCV) into v: pq = 2 GKS on the quadratic flow problem, pq = 1 the
+    smoothed-l1 MM variant; returns v, or (v, lambdas [pairs, n_iter]) when asked."""
     ctx = ctx or context()
     _need(u, stack.n, "u")
     _need(v, 2 * stack.n_pair_px, "v")
@@ -373,9 +374,14 @@ def flow_solve_gks(stack: Stack, u: torch.Tensor, v: torch.Tensor, delta_r: int 
     n_pairs = sum(t - 1 for t, _, _ in stack.sizes)
     lam = np.zeros((max(n_pairs, 1), max(int(n_iter), 1))) if want_lambdas else None
     ctx.bind()
-    check(ctx.lib.mmof_flow_solve_gks(ctx.h, stack.ref, _dt(u, v, v_rev), _ptr(u), _ptr(v), _ptr(v_rev),
-                                      int(delta_r), int(ell), int(n_iter), float(fixed_lambda), int(scale),
-                                      None if lam is None else lam.ctypes.data_as(C.c_void_p)))
+    lp = None if lam is None else lam.ctypes.data_as(C.c_void_p)
+    if pq == 2:
+        check(ctx.lib.mmof_flow_solve_gks(ctx.h, stack.ref, _dt(u, v, v_rev), _ptr(u), _ptr(v), _ptr(v_rev),
+                                          int(delta_r), int(ell), int(n_iter), float(fixed_lambda), int(scale), lp))
+    else:
+        check(ctx.lib.mmof_flow_solve_of(ctx.h, stack.ref, _dt(u, v, v_rev), _ptr(u), _ptr(v), _ptr(v_rev),
+                                         int(delta_r), int(ell), int(n_iter), float(fixed_lambda), int(scale),
+                                         int(pq), float(eps), lp))
     return (v, lam[:n_pairs]) if want_lambdas else v
 
 

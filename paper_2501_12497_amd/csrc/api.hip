@@ -381,18 +381,29 @@ int mmof_flow_update_scaled(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt
     });
 }
 
-int mmof_flow_solve_gks(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
-                        int32_t delta_r, int32_t ell, int32_t n_iter, double fixed_lambda, int32_t scale,
-                        double* lambdas) {
+int mmof_flow_solve_of(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
+                       int32_t delta_r, int32_t ell, int32_t n_iter, double fixed_lambda, int32_t scale, int32_t pq,
+                       double eps, double* lambdas) {
     return guarded(ctx, [&] {
         MMOF_CHECK(fixed_lambda >= 0 && std::isfinite(fixed_lambda), MMOF_ERR_INVALID, "fixed_lambda must be >= 0");
+        MMOF_CHECK(pq == 1 || pq == 2, MMOF_ERR_INVALID, "pq must be 1 or 2");
+        MMOF_CHECK(pq == 2 || (eps > 0 && std::isfinite(eps)), MMOF_ERR_INVALID, "eps must be > 0");
         FlowMethod fm;
         fm.solver = 1;
         fm.ell = ell;
         fm.n_iter = n_iter;
         fm.fixed_lambda = fixed_lambda;
+        fm.of_p = pq;
+        fm.of_eps = eps;
         return flow_call(ctx, stack, dt, u, v, v_rev, delta_r, scale, fm, lambdas);
     });
+}
+
+int mmof_flow_solve_gks(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,
+                        int32_t delta_r, int32_t ell, int32_t n_iter, double fixed_lambda, int32_t scale,
+                        double* lambdas) {
+    return mmof_flow_solve_of(ctx, stack, dt, u, v, v_rev, delta_r, ell, n_iter, fixed_lambda, scale, 2, 0.0,
+                              lambdas);
 }
 
 int mmof_flow_update(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, const void* u, void* v, void* v_rev,

@@ -1,4 +1,4 @@
-// Solve-OF (Alg. 2) with p = q = 2: per frame pair, the flow s minimising
+// Solve-OF (Alg. 2), p = q = 2 and p = q = 1: per frame pair, the flow s minimising
 //   ||Y s + u_t||^2 + lambda ||L s||^2,  Y = [diag(I_x) diag(I_y)],  L = blockdiag(D, D)
 // (eq. subproblem_motion_estimation_redefined) by the generalized Krylov subspace method
 // (MMGKS with unit weights): ell Golub-Kahan steps on Y from b = -u_t, then n_iter projected
@@ -20,6 +20,12 @@
 // not depend on rounding where G is flat); a factorization that fails gives G = inf.  Every wave of the workgroup evaluates one point
 // at a time (Cholesky of M in LDS, lanes = rows; the K columns of G_Y and d solved together,
 // lanes = columns).
+//
+// The p = q = 1 variant (MMGKS on the smoothed l1 norms of the data rows and of the flow
+// differences): before every projected solve the weights of the current iterate are formed
+// per pixel (one data weight, four edge weights stored at an edge's left / upper pixel), the
+// weighted Gram matrices, d and b^T W_d b are built from scratch, and GCV, z and the residual
+// are those of the weighted problem.
 #include "dev.h"
 #include "kernels.h"
 
@@ -139,10 +145,11 @@ __device__ __forceinline__ PixVals pix_vals(const double* v, int n, int nx, int 
     return r;
 }
 
-// Row j of the Gram matrices (against columns 0..j) and d[j].
+// Row j of the Gram matrices (against columns 0..j) and d[j]; with W (the p = q = 1 variant)
+// every data row is weighted by W[p] and every difference by its edge weight W[n + 4p + e].
 template <class T>
 __device__ void gram_row(int j, const double* V, int n, int nx, int ny, const T* Ix, const T* Iy, const T* It,
-                         GksLds& s) {
+                         GksLds& s, const double* W) {
     const int64_t N = 2 * (int64_t)n;
     const double* vj = V + (int64_t)j * N;
     for (int i0 = 0; i0 <= j; i0 += GK_G) {
@@ -153,7 +160,15 @@ __device__ void gram_row(int j, const double* V, int n, int nx, int ny, const T*
             const int x = p % nx, y = p / nx;
             const bool hx = x + 1 < nx, hy = y + 1 < ny;
             const T ix = Ix[p], iy = Iy[p];
-            const PixVals J = pix_vals(vj, n, nx, p, hx, hy, ix, iy);
+            PixVals J = pix_vals(vj, n, nx, p, hx, hy, ix, iy);
+            if (W) {  // weighted copies of the new column's values
+                const double* we = W + n + 4 * (int64_t)p;
+                J.y *= W[p];
+                J.dxx *= we[0];
+                J.dxy *= we[1];
+                J.dyx *= we[2];
+                J.dyy *= we[3];
+            }
             if (i0 == 0) a[2 * GK_G] += J.y * -(double)It[p];
 #pragma unroll
             for (int c = 0; c < GK_G; ++c) {
@@ -289,7 +304,7 @@ __global__ __launch_bounds__(GK_THREADS) void k_of_gks(const Tile* __restrict__ 
                                                        double* __restrict__ Vw, double* __restrict__ Uw,
                                                        double* __restrict__ Sw, double* __restrict__ Rw,
                                                        double* __restrict__ lam_out, int ell, int n_iter, int kc,
-                                                       double fixed_lambda) {
+                                                       double fixed_lambda, double* __restrict__ Ww, double eps) {
     __shared__ GksLds s;
     const FrameInfo f = frames[pairs[blockIdx.x].frame];
     const int nx = f.nx, ny = f.ny, n = nx * ny;
@@ -302,6 +317,9 @@ __global__ __launch_bounds__(GK_THREADS) void k_of_gks(const Tile* __restrict__ 
     double* sv = Sw + 2 * f.pair_off;
     double* r = Rw + 2 * f.pair_off;
     double* lam = lam_out + (int64_t)blockIdx.x * n_iter;
+    // p = q = 1: weights of the current iterate, W[p] for the data row and W[n + 4p + e] for
+    // the differences (e: x of s_x, x of s_y, y of s_x, y of s_y) (null: p = q = 2)
+    double* W = Ww ? Ww + 5 * f.pair_off : nullptr;
     T* vo = vout + 2 * f.pair_off;
     const int tid = threadIdx.x;
     for (int k = tid; k < n_iter; k += GK_THREADS) lam[k] = 0.0;
@@ -361,15 +379,44 @@ __global__ __launch_bounds__(GK_THREADS) void k_of_gks(const Tile* __restrict__ 
 
     // generalized Krylov iterations
     int K = ell;
-    for (int j = 0; j < K; ++j) gram_row(j, V, n, nx, ny, Ix, Iy, It, s);
+    if (!W)
+        for (int j = 0; j < K; ++j) gram_row(j, V, n, nx, ny, Ix, Iy, It, s, (const double*)nullptr);
+    else
+        for (int64_t p = tid; p < N; p += GK_THREADS) sv[p] = 0.0;  // s^(0)
     const double m = (double)n;
+    double bbw = bb;  // b^T W_d b
     for (int k = 0; k < n_iter; ++k) {
+        if (W) {
+            // weights of the iterate s^(k), then the weighted Gram matrices from scratch
+            __syncthreads();
+            double a1w[1] = {0.0};
+            for (int p = tid; p < n; p += GK_THREADS) {
+                const int x = p % nx, y = p / nx;
+                const double sx = sv[p], sy = sv[n + p];
+                const double e = (double)Ix[p] * sx + (double)Iy[p] * sy + (double)It[p];
+                const double wd = 1.0 / sqrt(e * e + eps * eps);
+                W[p] = wd;
+                const double bt = (double)It[p];
+                a1w[0] += wd * bt * bt;
+                double* we = W + n + 4 * (int64_t)p;
+                const double gxx = x + 1 < nx ? sv[p + 1] - sx : 0.0, gxy = x + 1 < nx ? sv[n + p + 1] - sy : 0.0;
+                const double gyx = y + 1 < ny ? sv[p + nx] - sx : 0.0, gyy = y + 1 < ny ? sv[n + p + nx] - sy : 0.0;
+                we[0] = x + 1 < nx ? 1.0 / sqrt(gxx * gxx + eps * eps) : 0.0;
+                we[1] = x + 1 < nx ? 1.0 / sqrt(gxy * gxy + eps * eps) : 0.0;
+                we[2] = y + 1 < ny ? 1.0 / sqrt(gyx * gyx + eps * eps) : 0.0;
+                we[3] = y + 1 < ny ? 1.0 / sqrt(gyy * gyy + eps * eps) : 0.0;
+            }
+            wg_sum<1>(a1w, s);
+            bbw = a1w[0];
+            __syncthreads();
+            for (int j = 0; j < K; ++j) gram_row(j, V, n, nx, ny, Ix, Iy, It, s, (const double*)W);
+        }
         double lk = fixed_lambda;
         if (!(fixed_lambda > 0.0)) {
             // rho0 = ||Y V z0 - b||^2 from a pass over the pixels (< 0 when G_Y is singular)
             double st[1] = {0.0};
             if (tid < 64) {
-                const double g0 = gcv_eval(K, 0.0, bb, -1.0, m, s, s.z0);
+                const double g0 = gcv_eval(K, 0.0, bbw, -1.0, m, s, s.z0);
                 st[0] = tid == 0 ? g0 : 0.0;
             }
             wg_sum<1>(st, s);  // every thread learns whether z0 exists
@@ -383,15 +430,15 @@ __global__ __launch_bounds__(GK_THREADS) void k_of_gks(const Tile* __restrict__ 
                         acc += s.z0[j] * ((double)Ix[p] * vj[p] + (double)Iy[p] * vj[n + p]);
                     }
                     const double e = acc + (double)It[p];
-                    e2[0] += e * e;
+                    e2[0] += (W ? W[p] : 1.0) * e * e;
                 }
                 wg_sum<1>(e2, s);
                 rho0 = e2[0];
             }
-            lk = gcv_search(K, bb, rho0, m, s);
+            lk = gcv_search(K, bbw, rho0, m, s);
         }
         if (tid == 0) lam[k] = lk;
-        if (tid < 64) (void)gcv_eval(K, lk, bb, -1.0, m, s, s.z);
+        if (tid < 64) (void)gcv_eval(K, lk, bbw, -1.0, m, s, s.z);
         __syncthreads();
         for (int64_t p = tid; p < N; p += GK_THREADS) {
             double acc = 0.0;
@@ -400,28 +447,34 @@ __global__ __launch_bounds__(GK_THREADS) void k_of_gks(const Tile* __restrict__ 
         }
         if (k == n_iter - 1) break;
         __syncthreads();
-        // r = Y^T (Y s - b) + lambda L^T L s
+        // r = Y^T W_d (Y s - b) + lambda L^T W_r L s (W = I for p = q = 2)
         for (int p = tid; p < n; p += GK_THREADS) {
             const int x = p % nx, y = p / nx;
             const double sx = sv[p], sy = sv[n + p];
-            const double e = (double)Ix[p] * sx + (double)Iy[p] * sy + (double)It[p];
+            double e = (double)Ix[p] * sx + (double)Iy[p] * sy + (double)It[p];
             double lx = 0.0, ly = 0.0;
+            // L^T W_r L s: every edge (p, q) adds w_pq (s(p) - s(q)), its weight stored at the
+            // edge's left / upper end (all ones for p = q = 2)
+            const double* wp = W ? W + n + 4 * (int64_t)p : nullptr;
             if (x > 0) {
-                lx += sx - sv[p - 1];
-                ly += sy - sv[n + p - 1];
+                const double* wq = W ? W + n + 4 * (int64_t)(p - 1) : nullptr;
+                lx += (W ? wq[0] : 1.0) * (sx - sv[p - 1]);
+                ly += (W ? wq[1] : 1.0) * (sy - sv[n + p - 1]);
             }
             if (x + 1 < nx) {
-                lx += sx - sv[p + 1];
-                ly += sy - sv[n + p + 1];
+                lx += (W ? wp[0] : 1.0) * (sx - sv[p + 1]);
+                ly += (W ? wp[1] : 1.0) * (sy - sv[n + p + 1]);
             }
             if (y > 0) {
-                lx += sx - sv[p - nx];
-                ly += sy - sv[n + p - nx];
+                const double* wq = W ? W + n + 4 * (int64_t)(p - nx) : nullptr;
+                lx += (W ? wq[2] : 1.0) * (sx - sv[p - nx]);
+                ly += (W ? wq[3] : 1.0) * (sy - sv[n + p - nx]);
             }
             if (y + 1 < ny) {
-                lx += sx - sv[p + nx];
-                ly += sy - sv[n + p + nx];
+                lx += (W ? wp[2] : 1.0) * (sx - sv[p + nx]);
+                ly += (W ? wp[3] : 1.0) * (sy - sv[n + p + nx]);
             }
+            if (W) e *= W[p];
             r[p] = (double)Ix[p] * e + lk * lx;
             r[n + p] = (double)Iy[p] * e + lk * ly;
         }
@@ -433,7 +486,7 @@ __global__ __launch_bounds__(GK_THREADS) void k_of_gks(const Tile* __restrict__ 
         for (int64_t p = tid; p < N; p += GK_THREADS) vk[p] = r[p] / nr;
         __syncthreads();
         ++K;
-        gram_row(K - 1, V, n, nx, ny, Ix, Iy, It, s);
+        if (!W) gram_row(K - 1, V, n, nx, ny, Ix, Iy, It, s, (const double*)nullptr);
     }
     __syncthreads();
     for (int64_t p = tid; p < N; p += GK_THREADS) vo[p] = (T)sv[p];
@@ -463,11 +516,13 @@ GksWork gks_work(Ctx& c, const Geom& g, const FlowMethod& fm, const std::string&
     w.R = static_cast<double*>(c.work(prefix + "R", sizeof(double) * 2 * (size_t)P));
     w.lam = static_cast<double*>(
         c.work(prefix + "lam", sizeof(double) * (size_t)std::max<int64_t>(g.n_pairs, 1) * fm.n_iter));
+    if (fm.of_p == 1) w.W = static_cast<double*>(c.work(prefix + "W", sizeof(double) * 5 * (size_t)P));
     return w;
 }
 
 void launch_of_gks(Ctx& c, Geom& g, int dt, const void* I, void* v, int ell, int n_iter, double fixed_lambda,
-                   const GksWork& w) {
+                   const GksWork& w, bool l1, double eps) {
+    MMOF_CHECK(!l1 || (w.W && eps > 0 && std::isfinite(eps)), MMOF_ERR_INVALID, "p = q = 1 needs eps > 0");
     if (g.n_pairs == 0) return;
     const int kc = ell + n_iter - 1;
     MMOF_CHECK(ell >= 1 && n_iter >= 1 && kc <= GK_KC, MMOF_ERR_INVALID,
@@ -479,7 +534,8 @@ void launch_of_gks(Ctx& c, Geom& g, int dt, const void* I, void* v, int ell, int
         using T = decltype(z);
         ScopedTime st(&c, "of_gks", sizeof(T) * 5.0 * g.pair_px, 0.0);
         hipLaunchKernelGGL(k_of_gks<T>, dim3((unsigned)tl.count), dim3(GK_THREADS), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), (const T*)I, (T*)v, w.V, w.U, w.S, w.R, w.lam, ell, n_iter, kc, fixed_lambda);
+                           g.dframes(), (const T*)I, (T*)v, w.V, w.U, w.S, w.R, w.lam, ell, n_iter, kc, fixed_lambda,
+                           l1 ? w.W : nullptr, eps);
         MMOF_LAUNCH_CHECK();
     });
 }

@@ -575,7 +575,7 @@ void flow_update_core(Ctx& c, Geom& g, Geom* gs, int dt, const void* u, void* v,
     }
     launch_of_derivs(c, gw, dt, uw, w.I, dr);
     if (fm.solver == 1)
-        launch_of_gks(c, gw, dt, w.I, vw, fm.ell, fm.n_iter, fm.fixed_lambda, w.gks);
+        launch_of_gks(c, gw, dt, w.I, vw, fm.ell, fm.n_iter, fm.fixed_lambda, w.gks, fm.of_p == 1, fm.of_eps);
     else if (launch_hs_sweeps(c, gw, dt, w.I, vw, w.tmp, fm.gamma, fm.n_sweeps)) {
         dispatch(dt, [&](auto z) {
             using T = decltype(z);

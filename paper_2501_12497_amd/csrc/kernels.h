@@ -60,10 +60,13 @@ void launch_flow_up(Ctx& c, Geom& g, Geom& gs, int dt, int f, const void* vs, vo
 // 2 * pair_px each, lam n_pairs * n_iter (the lambda of every iteration, 0 past a breakdown).
 struct GksWork {
     double *V = nullptr, *U = nullptr, *S = nullptr, *R = nullptr, *lam = nullptr;
+    double* W = nullptr;  // p = q = 1: 5 * pair_px weights
 };
 int of_gks_capacity();  // largest ell + n_iter - 1
+// l1: the p = q = 1 variant (MM weights (x^2 + eps^2)^(-1/2) of the data rows and of the flow
+// differences, from the current iterate); needs w.W.
 void launch_of_gks(Ctx& c, Geom& g, int dt, const void* I, void* v, int ell, int n_iter, double fixed_lambda,
-                   const GksWork& w);
+                   const GksWork& w, bool l1 = false, double eps = 1e-3);
 
 // Raises MMOF_ERR_INVALID unless ell >= 1, n_iter >= 1, ell + n_iter - 1 <= of_gks_capacity(),
 // and every (reduced by f) frame has more than ell pixels and fewer than 2^30.
@@ -81,6 +84,8 @@ struct FlowMethod {
     int n_sweeps = 200;    // HS
     int ell = 10, n_iter = 20;
     double fixed_lambda = 0.0;  // Solve-OF: > 0 skips the GCV search
+    int of_p = 2;               // Solve-OF: 2 (p = q = 2) or 1 (the smoothed-l1 MM variant)
+    double of_eps = 1e-3;       // Solve-OF p = q = 1: smoothing of the l1 terms
 };
 // Workspace of one flow update: I and tmp sized for the frames the flow is computed on (the
 // reduced ones when f > 1), us / vs for the reduced frames and flow (unused when f = 1), gks

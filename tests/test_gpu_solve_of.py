@@ -1,5 +1,6 @@
-"""GPU parity of Solve-OF (Alg. 2, p = q = 2: GKS with GCV) against the FP64 oracle, through
-the C ABI (mmof_flow_solve_gks), and of the joint solve that uses it for the flow.
+"""GPU parity of Solve-OF (Alg. 2, p = q = 2: GKS with GCV; and the p = q = 1 MM variant)
+against the FP64 oracle, through the C ABI (mmof_flow_solve_gks, mmof_flow_solve_of), and of
+the joint solve that uses it for the flow.
 
 Bars: with a fixed lambda the FP64 flow matches to 1e-10 (only summation order differs);
 with the GCV search the chosen lambdas match to 1e-6 relative and the flows to 1e-8 (the
@@ -158,3 +159,77 @@ def test_joint_solve_with_solve_of(B, op):
     again = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta, u_true=torch.as_tensor(ut, device="cuda"),
                           use_graph=1, **kw)
     assert torch.equal(again.u, res.u) and again.lambdas == res.lambdas
+
+
+# ------------------------------------------------------------------ p = q = 1 variant
+#
+# Bars: the weights (e^2 + eps^2)^(-1/2) amplify rounding of the iterate by up to 1 / eps
+# (1e3 at eps = 1e-3) in relative terms, so the p = q = 1 flows are compared to 1e-8 with a
+# fixed lambda and to 1e-7 with the GCV search (lambdas to 1e-6, as for p = q = 2).
+
+
+def _oracle_l1(us, ell, n_iter, fixed_lambda=0.0, eps=solve_of.EPS_L1):
+    flows, lams = [], []
+    for u in us:
+        I = optflow.of_derivs(u, 1)
+        for t in range(I.shape[0]):
+            s, l = solve_of.solve_of_pair(I[t], ell, n_iter, fixed_lambda, p=1, eps=eps)
+            flows.append(s)
+            lams.append(l)
+    return flows, lams
+
+
+@pytest.mark.parametrize("lam,eps", [(0.05, 1e-3), (0.5, 1e-2)])
+def test_l1_fixed_lambda_fp64(B, lam, eps):
+    import torch
+    us = _frames(21)
+    got, _, lams = _run(B, us, torch.float64, ell=6, n_iter=9, fixed_lambda=lam, pq=1, eps=eps)
+    exp, _ = _oracle_l1(us, 6, 9, lam, eps)
+    assert rel(got, pack(exp)) < 1e-8
+    assert np.all(lams == lam)
+
+
+@pytest.mark.parametrize("ell,n_iter", [(10, 20), (3, 6), (1, 1)])
+def test_l1_gcv_fp64(B, ell, n_iter):
+    import torch
+    us = _frames(22)
+    got, gotr, lam = _run(B, us, torch.float64, ell=ell, n_iter=n_iter, pq=1)
+    exp, elams = _oracle_l1(us, ell, n_iter)
+    np.testing.assert_allclose(lam, np.array(elams), rtol=1e-6)
+    assert rel(got, pack(exp)) < 1e-7
+    shapes = [(u.shape[0] - 1, 2) + u.shape[1:] for u in us]
+    assert rel(gotr, pack([optflow.reverse_flow(f) for f in unpack(got, shapes)])) < 1e-12
+
+
+def test_l1_large_eps_is_the_quadratic_solve(B):
+    """eps far above every residual: both weights are the constant 1/eps, so the GPU's p = q = 1
+    run reproduces its own p = q = 2 run (same lambdas up to rounding, same flow)."""
+    import torch
+    us = _frames(23)
+    g2, _, l2 = _run(B, us, torch.float64, ell=5, n_iter=7)
+    g1, _, l1 = _run(B, us, torch.float64, ell=5, n_iter=7, pq=1, eps=1e8)
+    np.testing.assert_allclose(l1, l2, rtol=1e-7)
+    assert rel(g1, g2) < 1e-8
+
+
+def test_l1_reduced_frames_fp32(B):
+    """p = q = 1 on frames reduced by 2, FP32 derivatives (FP64 solve)."""
+    import torch
+    sizes = [(3, 36, 40), (2, 22, 27)]
+    us = [roundtrip32(u) for u in _frames(24, sizes)]
+    got, _, _ = _run(B, us, torch.float32, ell=6, n_iter=8, scale=2, pq=1)
+    exp = pack([solve_of.solve_of(u, 1, 6, 8, 0.0, 2, p=1) for u in us])
+    assert rel(got, exp) < 1e-4
+
+
+def test_l1_rejects(B):
+    import torch
+    from paper_2501_12497_amd._lib import MMOFError
+    stack = B.Stack([(2, 6, 5)])
+    uu = dev(np.zeros(60), torch.float64)
+    v = torch.full((60,), 7.0, dtype=torch.float64, device="cuda")
+    for kw in (dict(pq=3), dict(pq=0), dict(pq=1, eps=0.0), dict(pq=1, eps=-1.0), dict(pq=1, eps=float("inf"))):
+        with pytest.raises(MMOFError) as e:
+            B.flow_solve_gks(stack, uu, v, ell=3, n_iter=3, **kw)
+        assert e.value.code == -1, kw
+    assert torch.all(v == 7.0)
