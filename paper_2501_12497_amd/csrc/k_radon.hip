@@ -380,56 +380,146 @@ __global__ __launch_bounds__(256) void k_fan_fwd(const RayTile* __restrict__ ray
 }
 
 // Detector position (in bin units) of the ray from the source through the point (X, Y); the
-// reciprocal of the depth from an FP32 estimate and one Newton step (relative error ~1e-14,
-// no FP64 division): it only bounds the candidate rays of a pixel (margin 0.05 bins).
+// reciprocal of the depth from the hardware FP32 reciprocal and two Newton steps (relative
+// error near FP64 rounding, no FP64 division): it only bounds candidate rays (margin 0.05 bins).
 __device__ __forceinline__ double fan_pos_bound(double X, double Y, double c, double s, double dso, double g,
                                                 double off) {
     const double t = X * c + Y * s, den = dso - X * s + Y * c;
-    double inv = (double)__frcp_rn((float)den);
+    double inv = (double)__builtin_amdgcn_rcpf((float)den);
     inv = inv * (2.0 - den * inv);
     inv = inv * (2.0 - den * inv);
     return g * t * inv + off;
 }
 
-// Transpose: one lane per pixel; per angle the candidate bins lie between the projections
-// of the pixel's four neighbours.
+// Detector position in FP32 (bounds only; the caller's margin covers its rounding, the
+// hardware reciprocal's 1 ulp included).
+__device__ __forceinline__ float fan_pos_f32(float t, float den, float g, float off) {
+    return fmaf(g * t, __builtin_amdgcn_rcpf(den), off);
+}
+
+constexpr int FAC = 16;  // angles per staged chunk of the transpose
+constexpr int FAW = 64;  // staged bins per angle (wider tile windows read the table directly)
+
+// Transpose: one lane per pixel of a 16 x 16 tile.  Per chunk of FAC angles, the bins whose
+// rays can touch the tile (between the projections of the corners of the tile grown by one
+// pixel: the projection is monotone along every line that misses the source, so its extremes
+// over the box are at the corners) are staged in LDS: the line {A, B}, the path length signed
+// by the direction (> 0: rows) and the sinogram value.  Per angle a pixel's candidates lie
+// between the projections of its four neighbours, taken in FP32 with the caller's margin
+// (bins) when fp32_bounds, else in FP64; a window wider than FAW bins reads the table from
+// global memory instead.  Every candidate's weight is the forward's: fma(B, index, A) in FP64.
 template <class T>
 __global__ __launch_bounds__(256) void k_fan_adj(const Tile* __restrict__ tiles, const RadonFrame* __restrict__ rf,
                                                  const double2* __restrict__ trig, const double4* __restrict__ table,
-                                                 const T* __restrict__ b, T* __restrict__ u, FanGeo geo) {
+                                                 const T* __restrict__ b, T* __restrict__ u, FanGeo geo,
+                                                 float margin, int fp32_bounds) {
+    __shared__ double2 s_ab[FAC][FAW];
+    __shared__ T s_sb[FAC][FAW][2];  // {signed path length, sinogram value}
+    __shared__ int s_j0[FAC], s_cnt[FAC];
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const RadonFrame f = rf[tl.frame];
     const int x = tl.x0 + (int)threadIdx.x % RTW, y = tl.y0 + (int)threadIdx.x / RTW;
-    if (x >= f.nx || y >= f.ny) return;
-    const double X = x - (f.nx - 1) / 2.0, Y = y - (f.ny - 1) / 2.0;
+    const bool inside = x < f.nx && y < f.ny;
+    const double hx = (f.nx - 1) / 2.0, hy = (f.ny - 1) / 2.0;
+    const double X = x - hx, Y = y - hy, xd = x, yd = y;
     const int nb = f.n_bins;
     const double gsc = geo.dsd / geo.du, off = (nb - 1) / 2.0;
+    const float Xf = (float)X, Yf = (float)Y, gf = (float)gsc, offf = (float)off, dsof = (float)geo.dso;
+    // the tile grown by one pixel (clipped to the frame first)
+    const double Xa = tl.x0 - hx - 1.0, Xb = min(tl.x0 + RTW, f.nx) - hx, Ya = tl.y0 - hy - 1.0,
+                 Yb = min(tl.y0 + RTH, f.ny) - hy;
     T acc = T(0);
-    for (int k = 0; k < f.n_ang; ++k) {
-        const double2 cs = trig[f.trig_off + k];
-        const double p0 = fan_pos_bound(X - 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
-        const double p1 = fan_pos_bound(X + 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
-        const double p2 = fan_pos_bound(X, Y - 1.0, cs.x, cs.y, geo.dso, gsc, off);
-        const double p3 = fan_pos_bound(X, Y + 1.0, cs.x, cs.y, geo.dso, gsc, off);
-        const double lo = fmin(fmin(p0, p1), fmin(p2, p3)), hi = fmax(fmax(p0, p1), fmax(p2, p3));
-        // candidate bins, clamped to the detector before the conversion to int
-        const int jlo = (int)fmin(fmax(floor(lo - 0.05), 0.0), (double)nb);
-        const int jhi = (int)fmax(fmin(ceil(hi + 0.05), (double)(nb - 1)), -1.0);
-        const int64_t row = f.sino_off + (int64_t)k * nb;
-        for (int j = jlo; j <= jhi; ++j) {
-            const double4 e = table[row + j];
-            const bool rows = e.w > 0.0;
-            const double pc = fma(e.y, rows ? (double)y : (double)x, e.x);
-            const double p0d = floor(pc);
-            const T fr = (T)(pc - p0d);
-            const double own = rows ? (double)x : (double)y;
-            T w = T(0);
-            if (p0d == own) w = T(1) - fr;
-            else if (p0d + 1.0 == own) w = fr;
-            if (w != T(0)) acc += (w * (T)e.z) * b[row + j];
+    for (int k0 = 0; k0 < f.n_ang; k0 += FAC) {
+        const int nk = min(FAC, f.n_ang - k0);
+        __syncthreads();  // the previous chunk is no longer read
+        if (threadIdx.x < nk) {
+            const double2 cs = trig[f.trig_off + k0 + threadIdx.x];
+            const double q0 = fan_pos_bound(Xa, Ya, cs.x, cs.y, geo.dso, gsc, off);
+            const double q1 = fan_pos_bound(Xb, Ya, cs.x, cs.y, geo.dso, gsc, off);
+            const double q2 = fan_pos_bound(Xa, Yb, cs.x, cs.y, geo.dso, gsc, off);
+            const double q3 = fan_pos_bound(Xb, Yb, cs.x, cs.y, geo.dso, gsc, off);
+            const double lo = fmin(fmin(q0, q1), fmin(q2, q3)), hi = fmax(fmax(q0, q1), fmax(q2, q3));
+            const int j0 = (int)fmin(fmax(ceil(lo - 0.05), 0.0), (double)nb);
+            const int j1 = (int)fmax(fmin(floor(hi + 0.05), (double)(nb - 1)), -1.0);
+            const int cnt = max(j1 - j0 + 1, 0);
+            s_j0[threadIdx.x] = j0;
+            s_cnt[threadIdx.x] = cnt <= FAW ? cnt : -1;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nk * FAW; i += 256) {
+            const int kk = i / FAW, w = i % FAW;
+            if (w < s_cnt[kk]) {
+                const int64_t ri = f.sino_off + (int64_t)(k0 + kk) * nb + s_j0[kk] + w;
+                const double4 e = table[ri];
+                s_ab[kk][w] = make_double2(e.x, e.y);
+                s_sb[kk][w][0] = e.w > 0.0 ? (T)e.z : -(T)e.z;
+                s_sb[kk][w][1] = b[ri];
+            }
+        }
+        __syncthreads();
+        if (!inside) continue;
+        for (int kk = 0; kk < nk; ++kk) {
+            const int cnt = s_cnt[kk];
+            if (cnt == 0) continue;
+            const int k = k0 + kk;
+            const double2 cs = trig[f.trig_off + k];
+            double lo, hi;
+            if (fp32_bounds) {
+                const float c = (float)cs.x, sn = (float)cs.y;
+                const float t0 = fmaf(Xf, c, Yf * sn), d0 = dsof - Xf * sn + Yf * c;
+                const float p0 = fan_pos_f32(t0 - c, d0 + sn, gf, offf), p1 = fan_pos_f32(t0 + c, d0 - sn, gf, offf);
+                const float p2 = fan_pos_f32(t0 - sn, d0 - c, gf, offf), p3 = fan_pos_f32(t0 + sn, d0 + c, gf, offf);
+                lo = (double)fminf(fminf(p0, p1), fminf(p2, p3)) - (double)margin;
+                hi = (double)fmaxf(fmaxf(p0, p1), fmaxf(p2, p3)) + (double)margin;
+            } else {
+                const double p0 = fan_pos_bound(X - 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
+                const double p1 = fan_pos_bound(X + 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
+                const double p2 = fan_pos_bound(X, Y - 1.0, cs.x, cs.y, geo.dso, gsc, off);
+                const double p3 = fan_pos_bound(X, Y + 1.0, cs.x, cs.y, geo.dso, gsc, off);
+                lo = fmin(fmin(p0, p1), fmin(p2, p3)) - 0.05;
+                hi = fmax(fmax(p0, p1), fmax(p2, p3)) + 0.05;
+            }
+            // candidate bins: ray j lies at detector position j, and it can weigh on the
+            // pixel only strictly between the neighbours' projections (clamped to the
+            // detector, and to the staged window, before the conversion to int)
+            int jlo = (int)fmin(fmax(ceil(lo), 0.0), (double)nb);
+            int jhi = (int)fmax(fmin(floor(hi), (double)(nb - 1)), -1.0);
+            if (cnt > 0) {
+                const int j0 = s_j0[kk];
+                jlo = max(jlo, j0);
+                jhi = min(jhi, j0 + cnt - 1);
+                for (int j = jlo; j <= jhi; ++j) {
+                    const double2 ab = s_ab[kk][j - j0];
+                    const T sp = s_sb[kk][j - j0][0], bv = s_sb[kk][j - j0][1];
+                    const bool rows = sp > T(0);
+                    const double pc = fma(ab.y, rows ? yd : xd, ab.x);
+                    const double p0d = floor(pc);
+                    const T fr = (T)(pc - p0d);
+                    // the pixel is the sample's left (dl = 0) or right (dl = 1) neighbour, or
+                    // untouched (exact: small integers)
+                    const double dl = (rows ? xd : yd) - p0d;
+                    const T w = dl == 0.0 ? T(1) - fr : (dl == 1.0 ? fr : T(0));
+                    const T term = (w * (rows ? sp : -sp)) * bv;
+                    acc = w != T(0) ? acc + term : acc;
+                }
+            } else {
+                const int64_t row = f.sino_off + (int64_t)k * nb;
+                for (int j = jlo; j <= jhi; ++j) {
+                    const double4 e = table[row + j];
+                    const bool rows = e.w > 0.0;
+                    const double pc = fma(e.y, rows ? (double)y : (double)x, e.x);
+                    const double p0d = floor(pc);
+                    const T fr = (T)(pc - p0d);
+                    const double own = rows ? (double)x : (double)y;
+                    T w = T(0);
+                    if (p0d == own) w = T(1) - fr;
+                    else if (p0d + 1.0 == own) w = fr;
+                    if (w != T(0)) acc += (w * (T)e.z) * b[row + j];
+                }
+            }
         }
     }
-    u[f.u_off + (int64_t)y * f.nx + x] = acc;
+    if (inside) u[f.u_off + (int64_t)y * f.nx + x] = acc;
 }
 
 void fan_plan_init(Ctx& c, Plan& p) {
@@ -458,14 +548,38 @@ void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
     });
 }
 
+// Margin (bins) that covers the rounding of the FP32 candidate bounds: with every point at
+// most R from the centre, |t| <= R and den >= dso - R; each of t and den is off by at most a few
+// FP32 ulps of dso + R, and the position g t / den + off by the propagated relative errors; a
+// factor 4 on top, plus the FP64 path's 0.05.  Geometries where this exceeds 0.5 bins take the
+// FP64 bounds.
+static float fan_bound_margin(const Plan& p, bool& fp32) {
+    const Geom& g = *p.geom;
+    double R = 0.0;
+    int nbmax = 1;
+    for (int s = 0; s < g.n_seq; ++s) {
+        R = std::max(R, 0.5 * std::hypot((double)g.nx[s], (double)g.ny[s]) + 1.5);
+        nbmax = std::max(nbmax, p.n_bins[s]);
+    }
+    const double dmin = p.fan_dso - R, gsc = p.fan_dsd / p.fan_du, u = std::ldexp(1.0, -24);
+    const double ea = 16.0 * u * (p.fan_dso + R + 2.0);  // absolute error of t and den
+    const double pos = gsc * R / dmin;                   // |g t / den|
+    const double err = gsc * ea / dmin + pos * (ea / dmin + 8.0 * u) + 4.0 * u * (pos + 0.5 * nbmax);
+    const double m = 0.05 + 4.0 * err;
+    fp32 = dmin > 0.0 && m <= 0.5;
+    return (float)m;
+}
+
 void launch_fan_adj(Ctx& c, Plan& p, int dt, const void* b, void* u) {
     const FanGeo geo{p.fan_dso, p.fan_dsd, p.fan_du};
+    bool fp32 = false;
+    const float margin = fan_bound_margin(p, fp32);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "fan_adj", (double)sizeof(T) * (p.n + p.m), 0.0);
         hipLaunchKernelGGL(k_fan_adj<T>, dim3((unsigned)p.n_tiles_a), dim3(256), 0, c.stream, p.d_tiles_a.as<Tile>(),
                            p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), p.d_fanrays.as<double4>(),
-                           (const T*)b, (T*)u, geo);
+                           (const T*)b, (T*)u, geo, margin, fp32 ? 1 : 0);
         MMOF_LAUNCH_CHECK();
     });
 }
