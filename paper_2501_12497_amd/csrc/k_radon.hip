@@ -406,13 +406,13 @@ constexpr int FAW = 64;  // staged bins per angle (wider tile windows read the t
 // over the box are at the corners) are staged in LDS: the line {A, B}, the path length signed
 // by the direction (> 0: rows) and the sinogram value.  Per angle a pixel's candidates lie
 // between the projections of its four neighbours, taken in FP32 with the caller's margin
-// (bins) when fp32_bounds, else in FP64; a window wider than FAW bins reads the table from
+// (bins) when FP32_BOUNDS, else in FP64; a window wider than FAW bins reads the table from
 // global memory instead.  Every candidate's weight is the forward's: fma(B, index, A) in FP64.
-template <class T>
+template <class T, bool FP32_BOUNDS>
 __global__ __launch_bounds__(256) void k_fan_adj(const Tile* __restrict__ tiles, const RadonFrame* __restrict__ rf,
                                                  const double2* __restrict__ trig, const double4* __restrict__ table,
                                                  const T* __restrict__ b, T* __restrict__ u, FanGeo geo,
-                                                 float margin, int fp32_bounds) {
+                                                 float margin) {
     __shared__ double2 s_ab[FAC][FAW];
     __shared__ T s_sb[FAC][FAW][2];  // {signed path length, sinogram value}
     __shared__ int s_j0[FAC], s_cnt[FAC];
@@ -463,27 +463,29 @@ __global__ __launch_bounds__(256) void k_fan_adj(const Tile* __restrict__ tiles,
             if (cnt == 0) continue;
             const int k = k0 + kk;
             const double2 cs = trig[f.trig_off + k];
-            double lo, hi;
-            if (fp32_bounds) {
+            // candidate bins: ray j lies at detector position j, and it can weigh on the
+            // pixel only strictly between the neighbours' projections (clamped to the
+            // detector, and to the staged window, before the conversion to int)
+            int jlo, jhi;
+            if (FP32_BOUNDS) {
                 const float c = (float)cs.x, sn = (float)cs.y;
                 const float t0 = fmaf(Xf, c, Yf * sn), d0 = dsof - Xf * sn + Yf * c;
                 const float p0 = fan_pos_f32(t0 - c, d0 + sn, gf, offf), p1 = fan_pos_f32(t0 + c, d0 - sn, gf, offf);
                 const float p2 = fan_pos_f32(t0 - sn, d0 - c, gf, offf), p3 = fan_pos_f32(t0 + sn, d0 + c, gf, offf);
-                lo = (double)fminf(fminf(p0, p1), fminf(p2, p3)) - (double)margin;
-                hi = (double)fmaxf(fmaxf(p0, p1), fmaxf(p2, p3)) + (double)margin;
+                const float lo = fminf(fminf(p0, p1), fminf(p2, p3)) - margin;
+                const float hi = fmaxf(fmaxf(p0, p1), fmaxf(p2, p3)) + margin;
+                jlo = (int)fminf(fmaxf(ceilf(lo), 0.0f), (float)nb);
+                jhi = (int)fmaxf(fminf(floorf(hi), (float)(nb - 1)), -1.0f);
             } else {
                 const double p0 = fan_pos_bound(X - 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
                 const double p1 = fan_pos_bound(X + 1.0, Y, cs.x, cs.y, geo.dso, gsc, off);
                 const double p2 = fan_pos_bound(X, Y - 1.0, cs.x, cs.y, geo.dso, gsc, off);
                 const double p3 = fan_pos_bound(X, Y + 1.0, cs.x, cs.y, geo.dso, gsc, off);
-                lo = fmin(fmin(p0, p1), fmin(p2, p3)) - 0.05;
-                hi = fmax(fmax(p0, p1), fmax(p2, p3)) + 0.05;
+                const double lo = fmin(fmin(p0, p1), fmin(p2, p3)) - 0.05;
+                const double hi = fmax(fmax(p0, p1), fmax(p2, p3)) + 0.05;
+                jlo = (int)fmin(fmax(ceil(lo), 0.0), (double)nb);
+                jhi = (int)fmax(fmin(floor(hi), (double)(nb - 1)), -1.0);
             }
-            // candidate bins: ray j lies at detector position j, and it can weigh on the
-            // pixel only strictly between the neighbours' projections (clamped to the
-            // detector, and to the staged window, before the conversion to int)
-            int jlo = (int)fmin(fmax(ceil(lo), 0.0), (double)nb);
-            int jhi = (int)fmax(fmin(floor(hi), (double)(nb - 1)), -1.0);
             if (cnt > 0) {
                 const int j0 = s_j0[kk];
                 jlo = max(jlo, j0);
@@ -577,9 +579,10 @@ void launch_fan_adj(Ctx& c, Plan& p, int dt, const void* b, void* u) {
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "fan_adj", (double)sizeof(T) * (p.n + p.m), 0.0);
-        hipLaunchKernelGGL(k_fan_adj<T>, dim3((unsigned)p.n_tiles_a), dim3(256), 0, c.stream, p.d_tiles_a.as<Tile>(),
+        auto kern = fp32 ? k_fan_adj<T, true> : k_fan_adj<T, false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)p.n_tiles_a), dim3(256), 0, c.stream, p.d_tiles_a.as<Tile>(),
                            p.d_rinfo.as<RadonFrame>(), p.d_trig.as<double2>(), p.d_fanrays.as<double4>(),
-                           (const T*)b, (T*)u, geo, margin, fp32 ? 1 : 0);
+                           (const T*)b, (T*)u, geo, margin);
         MMOF_LAUNCH_CHECK();
     });
 }

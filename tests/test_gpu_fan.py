@@ -122,3 +122,32 @@ def test_joint_solve_on_fan_beam(B):
     assert res.iters == ref.iters
     np.testing.assert_allclose(res.lambdas, ref.lambdas, rtol=1e-7)
     assert np.linalg.norm(res.u.cpu().numpy() - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_fan_source_close_to_the_frame(B, which):
+    """A source 0.2 px beyond the bound the plan accepts and a fine detector: the transpose's
+    FP32 candidate bounds would need a margin above half a bin, so it takes the FP64 bounds,
+    and a tile's rays span more bins than are staged, so it reads the ray table directly."""
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    sizes = [(2, 24, 20)]
+    geo = dict(dso=0.5 * math.hypot(24, 20) + 2.2, dsd=30.0, du=0.2)
+    nv, nb = 6, 81
+    angs = _angles("equal", sizes, nv)
+    r = np.random.default_rng(17)
+    bs = [r.standard_normal((2, nv, nb))]
+    us = [r.standard_normal(sizes[0])]
+    if dt == torch.float32:
+        bs = [roundtrip32(b) for b in bs]
+        us = [roundtrip32(u) for u in us]
+    plan = B.plan_fan(B.Stack(sizes), [nv], [nb], angs[0].ravel(), **geo)
+    got = host(B.apply_At(plan, dev(pack(bs), dt)))
+    exp = forward.fan_adj(bs[0], angs[0], 24, 20, **geo).ravel()
+    sc = forward.fan_adj(np.abs(bs[0]), angs[0], 24, 20, **geo).ravel()
+    assert np.abs(exp).max() > 0
+    assert rel(got, exp, sc) < tol
+    got = host(B.apply_A(plan, dev(pack(us), dt)))
+    exp = forward.fan_fwd(us[0], angs[0], nb, **geo).ravel()
+    sc = forward.fan_fwd(np.abs(us[0]), angs[0], nb, **geo).ravel()
+    assert rel(got, exp, sc) < tol
