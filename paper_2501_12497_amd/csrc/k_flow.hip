@@ -175,13 +175,16 @@ __device__ __forceinline__ void source_cell(int sx, int sy, T vx, T vy, int nx, 
 
 // Adjoint over an ATX x ATY output tile per workgroup of 256 threads; each thread owns
 // RPT = ATX * ATY / 256 consecutive rows of one column.  The sources within the radius of
-// the tile are staged in LDS (cell fractions and value) and bucketed by the cell they
-// sample: a counting sort over the (ATX+1) x (ATY+1) cells whose corners touch the tile
-// (LDS counters, a workgroup scan for the bucket starts, then raster order restored inside
-// each bucket).  An output is a corner of exactly four cells; it sums each of their buckets
-// in raster order and adds the four partial sums in a fixed corner order, so it visits only
-// the sources that reach it and its value does not depend on the tile shape (the
-// wide-window path below forms the same sums).
+// the tile are loaded together and dropped into the (ATX+1) x (ATY+1) cells whose corners
+// touch the tile: each cell has ADJ_SLOTS slots in LDS (cell fractions, value and the
+// source's raster rank in the window), taken in arrival order through an LDS counter.  An
+// output is a corner of exactly four cells; for each it sums the cell's sources in raster
+// order (the few slots ordered by rank in registers) and adds the four partial sums in a
+// fixed corner order, so its value does not depend on the tile shape or on the arrival
+// order.  A tile where some cell receives more sources than it has slots (a strongly
+// converging flow) forms the same sums by the wide-window path below.
+constexpr int ADJ_SLOTS = 4;
+
 template <class T, int INTERP, int ATX, int ATY>
 __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ tiles, const T* __restrict__ r,
                                                   const T* __restrict__ v, T* __restrict__ u, int direction,
@@ -190,10 +193,10 @@ __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ ti
     constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);  // source window (raster rank < 2^16)
     constexpr int CW = ATX + 1, NC = (ATX + 1) * (ATY + 1);     // cells touching the tile
     static_assert(SMAX <= 65536, "source ranks are kept in 16 bits");
-    __shared__ T s_fx[SMAX], s_fy[SMAX], s_val[SMAX];           // cell fractions and value per source
-    __shared__ unsigned short s_list[SMAX];                     // sources bucketed by cell
-    __shared__ int s_off[NC + 1];                               // bucket starts
-    __shared__ int s_wsum[4];
+    __shared__ T s_fx[NC * ADJ_SLOTS], s_fy[NC * ADJ_SLOTS], s_val[NC * ADJ_SLOTS];
+    __shared__ unsigned short s_rank[NC * ADJ_SLOTS];
+    __shared__ int s_cnt[NC];
+    __shared__ int s_over;
 
     const AdjTile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const int R = *d_radius;  // (independent of the tile: both loads are in flight together)
@@ -206,32 +209,46 @@ __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ ti
     // direct terms and the pair whose warp gathers into this frame
     const int64_t dp = direction > 0 ? tl.po : tl.pp;  // pair offset of the direct term (-1: none)
     const int64_t gp = direction > 0 ? tl.pp : tl.po;  // pair offset of the gathering pair (-1: none)
-    T acc[RPT];
+    T acc[RPT], direct[RPT], old[RPT];
+    // the direct terms and old outputs are loaded first, with the sources (their latency
+    // then overlaps the staging instead of following it)
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) acc[k] = T(0);
+    for (int k = 0; k < RPT; ++k) {
+        acc[k] = direct[k] = old[k] = T(0);
+        const int qy = qy0 + k;
+        if (col_in && qy < ny) {
+            const int64_t q = (int64_t)qy * nx + qx;
+            if (dp >= 0) direct[k] = -r[dp + q];
+            if (accumulate) old[k] = u[tl.off + q];
+        }
+    }
 
     if (gp >= 0) {
         const T* rg = r + gp;
         const T* vxg = v + 2 * gp;
         const T* vyg = vxg + np;
-        if (R <= RMAX) {
+        bool wide = R > RMAX;
+        if (!wide) {
             const int sx0 = max(tl.x0 - R, 0), sx1 = min(tl.x0 + ATX - 1 + R, nx - 1);
             const int sy0 = max(tl.y0 - R, 0), sy1 = min(tl.y0 + ATY - 1 + R, ny - 1);
             const int sw = sx1 - sx0 + 1, sh = sy1 - sy0 + 1;
-            for (int i = threadIdx.x; i <= NC; i += 256) s_off[i] = 0;
+            for (int i = threadIdx.x; i < NC; i += 256) s_cnt[i] = 0;
+            if (threadIdx.x == 0) s_over = 0;
             // Staging: a thread first loads all of its sources (independent loads, in flight
-            // together), then forms their cells.  Threads walk the window with the fixed row
-            // pitch SWM (constant divisions); the LDS copy is packed with pitch sw, so a
-            // source's LDS index is its raster rank in the window.
-            constexpr int SWM = ATX + 2 * RMAX;
+            // together), then forms their cells.  Source i of the window (its raster index,
+            // pitch sw, which is also its rank) is taken by thread i mod 256; the row is
+            // i / sw from an FP32 product (exact: i < 2^16 and the quotient's fraction is
+            // at least 1/(2 sw) away from an integer).
             constexpr int NI = (SMAX + 255) / 256;
+            const int nsrc = sw * sh;
+            const float inv_sw = 1.0f / (float)sw;
             T lvx[NI], lvy[NI], lr[NI];
 #pragma unroll
             for (int k = 0; k < NI; ++k) {
                 const int i = (int)threadIdx.x + 256 * k;
-                const int ly = i / SWM, lx = i % SWM;
                 lvx[k] = lvy[k] = lr[k] = T(0);
-                if (ly < sh && lx < sw) {
+                if (i < nsrc) {
+                    const int ly = (int)(((float)i + 0.5f) * inv_sw), lx = i - ly * sw;
                     const int64_t p = (int64_t)(sy0 + ly) * nx + sx0 + lx;
                     lvx[k] = vxg[p];
                     lvy[k] = vyg[p];
@@ -239,79 +256,33 @@ __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ ti
                 }
             }
             __syncthreads();  // counts cleared
-            // bucket the sources by the cell they sample, over the (ATX+1) x (ATY+1) cells
-            // whose corners touch the tile (cell (tl.x0-1, tl.y0-1) first)
-            int cell[NI], slot[NI];
 #pragma unroll
             for (int k = 0; k < NI; ++k) {
                 const int i = (int)threadIdx.x + 256 * k;
-                const int ly = i / SWM, lx = i % SWM;
-                cell[k] = -1;
-                if (ly < sh && lx < sw) {
-                    const int sy = sy0 + ly, sx = sx0 + lx, j = ly * sw + lx;
+                if (i < nsrc) {
+                    const int ly = (int)(((float)i + 0.5f) * inv_sw), lx = i - ly * sw;
                     int x0, y0;
                     T fx, fy;
-                    source_cell<T, INTERP>(sx, sy, lvx[k], lvy[k], nx, ny, x0, y0, fx, fy);
-                    s_fx[j] = fx;
-                    s_fy[j] = fy;
-                    s_val[j] = lr[k];
+                    source_cell<T, INTERP>(sx0 + lx, sy0 + ly, lvx[k], lvy[k], nx, ny, x0, y0, fx, fy);
                     const int cx = x0 - tl.x0 + 1, cy = y0 - tl.y0 + 1;
                     if (cx >= 0 && cx <= ATX && cy >= 0 && cy <= ATY) {
-                        cell[k] = cy * CW + cx;
-                        slot[k] = atomicAdd(&s_off[cell[k] + 1], 1);  // arrival order: sorted below
+                        const int cell = cy * CW + cx;
+                        const int slot = atomicAdd(&s_cnt[cell], 1);
+                        if (slot < ADJ_SLOTS) {
+                            const int e = cell * ADJ_SLOTS + slot;
+                            s_fx[e] = fx;
+                            s_fy[e] = fy;
+                            s_val[e] = lr[k];
+                            s_rank[e] = (unsigned short)i;
+                        } else {
+                            s_over = 1;
+                        }
                     }
                 }
             }
             __syncthreads();
-            // bucket starts: inclusive scan of the counts in s_off[1..NC] (chunk per thread,
-            // then a scan of the chunk totals over the workgroup)
-            {
-                constexpr int CH = (NC + 255) / 256;
-                const int c0 = 1 + (int)threadIdx.x * CH;
-                int run = 0;
-#pragma unroll
-                for (int q = 0; q < CH; ++q)
-                    if (c0 + q <= NC) run += s_off[c0 + q];
-                int incl = run;  // inclusive scan over the wave
-                const int lane = (int)(threadIdx.x & 63);
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int t = __shfl_up(incl, o);
-                    if (lane >= o) incl += t;
-                }
-                if (lane == 63) s_wsum[threadIdx.x >> 6] = incl;
-                __syncthreads();
-                int base = incl - run;
-                for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) base += s_wsum[w];
-#pragma unroll
-                for (int q = 0; q < CH; ++q)
-                    if (c0 + q <= NC) {
-                        base += s_off[c0 + q];
-                        s_off[c0 + q] = base;
-                    }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < NI; ++k)
-                if (cell[k] >= 0) {
-                    const int i = (int)threadIdx.x + 256 * k;
-                    s_list[s_off[cell[k]] + slot[k]] = (unsigned short)((i / SWM) * sw + i % SWM);
-                }
-            __syncthreads();
-            // raster order inside every bucket (buckets hold a few sources)
-            for (int c = threadIdx.x; c < NC; c += 256) {
-                const int b = s_off[c], e = s_off[c + 1];
-                for (int a = b + 1; a < e; ++a) {
-                    const unsigned short key = s_list[a];
-                    int z = a - 1;
-                    while (z >= b && s_list[z] > key) {
-                        s_list[z + 1] = s_list[z];
-                        --z;
-                    }
-                    s_list[z + 1] = key;
-                }
-            }
-            __syncthreads();
-            if (col_in) {
+            wide = s_over != 0;  // (the same value on every thread)
+            if (!wide && col_in) {
                 const int lx = qx - tl.x0;
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
@@ -319,35 +290,55 @@ __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ ti
                     if (qy >= ny) break;
                     // the output is corner (1,1), (0,1), (1,0), (0,0) of the cells at
                     // (qx-1, qy-1), (qx, qy-1), (qx-1, qy), (qx, qy): one partial sum per
-                    // corner, each over its bucket in raster order
+                    // corner, each over its cell's sources in raster order
                     const int c00 = (qy - tl.y0) * CW + lx;
                     T part[4];
 #pragma unroll
                     for (int cr = 0; cr < 4; ++cr) {
                         const int cc = c00 + (cr & 1) + (cr >> 1) * CW;
-                        const int e = s_off[cc + 1];
+                        const int n = s_cnt[cc];
+                        const int e0 = cc * ADJ_SLOTS;
                         T a = T(0);
-                        for (int t = s_off[cc]; t < e; ++t) {
-                            const int jj = s_list[t];
-                            const T fx = s_fx[jj], fy = s_fy[jj];
+                        if (n == 1) {  // the common case: one source
+                            const T fx = s_fx[e0], fy = s_fy[e0];
                             const T wx = (cr & 1) ? T(1) - fx : fx;
                             const T wy = (cr >> 1) ? T(1) - fy : fy;
-                            a += wx * wy * s_val[jj];
+                            a += wx * wy * s_val[e0];
+                        } else if (n > 1) {
+                            unsigned key[ADJ_SLOTS];
+#pragma unroll
+                            for (int q = 0; q < ADJ_SLOTS; ++q) key[q] = q < n ? s_rank[e0 + q] : 0xFFFFFu;
+                            // visit the slots by increasing rank (selection over at most 4 keys)
+                            for (int t = 0; t < n; ++t) {
+                                int best = 0;
+#pragma unroll
+                                for (int q = 1; q < ADJ_SLOTS; ++q)
+                                    if (key[q] < key[best]) best = q;
+                                key[best] = 0xFFFFFu;
+                                const int e = e0 + best;
+                                const T fx = s_fx[e], fy = s_fy[e];
+                                const T wx = (cr & 1) ? T(1) - fx : fx;
+                                const T wy = (cr >> 1) ? T(1) - fy : fy;
+                                a += wx * wy * s_val[e];
+                            }
                         }
                         part[cr] = a;
                     }
                     acc[k] = ((part[0] + part[1]) + part[2]) + part[3];
                 }
             }
-        } else if (col_in) {
-            // Large displacements: scan the full window in global memory, with the per-corner
-            // partial sums and their combination of the LDS path (same values).
+        }
+        if (wide && col_in) {
+            // Large displacements or crowded cells: scan the full window in global memory,
+            // with the per-corner partial sums and their combination of the LDS path (same
+            // values).
+            const int Rw = max(R, 1);
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
                 const int qy = qy0 + k;
                 if (qy >= ny) break;
-                const int py_lo = max(qy - R, 0), py_hi = min(qy + R, ny - 1);
-                const int px_lo = max(qx - R, 0), px_hi = min(qx + R, nx - 1);
+                const int py_lo = max(qy - Rw, 0), py_hi = min(qy + Rw, ny - 1);
+                const int px_lo = max(qx - Rw, 0), px_hi = min(qx + Rw, nx - 1);
                 T part[4] = {T(0), T(0), T(0), T(0)};
                 for (int py = py_lo; py <= py_hi; ++py)
                     for (int px = px_lo; px <= px_hi; ++px) {
@@ -375,11 +366,8 @@ __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ ti
     for (int k = 0; k < RPT; ++k) {
         const int qy = qy0 + k;
         if (qy >= ny) break;
-        const int64_t q = (int64_t)qy * nx + qx;
-        const T direct = dp >= 0 ? -r[dp + q] : T(0);
-        T* uo = u + tl.off + q;
-        const T val = acc[k] + direct;
-        *uo = accumulate ? *uo + val : val;
+        const T val = acc[k] + direct[k];
+        u[tl.off + (int64_t)qy * nx + qx] = accumulate ? old[k] + val : val;
     }
 }
 
@@ -458,7 +446,7 @@ void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out) 
 
 const TileShape kFlowShapes[] = {{64, 4, 0}, {32, 8, 0}, {128, 2, 0}, {16, 16, 0}};
 const int kFlowCandidates = sizeof(kFlowShapes) / sizeof(kFlowShapes[0]);
-const TileShape kFlowAdjShapes[] = {{64, 16, 0}, {32, 32, 0}, {64, 8, 0}, {32, 8, 0}};
+const TileShape kFlowAdjShapes[] = {{16, 16, 0}, {32, 16, 0}, {64, 8, 0}, {32, 8, 0}};
 const int kFlowAdjCandidates = sizeof(kFlowAdjShapes) / sizeof(kFlowAdjShapes[0]);
 // vector-form candidates of the forward operator: lanes per tile row (4 pixels each) and
 // waves per workgroup
@@ -488,8 +476,8 @@ static auto flow_fwd4_kernel(int choice) {
 }
 template <class T, int INTERP>
 static auto flow_adj_kernel(int choice) {
-    return choice == 0 ? k_flow_adj<T, INTERP, 64, 16>
-           : choice == 1 ? k_flow_adj<T, INTERP, 32, 32>
+    return choice == 0 ? k_flow_adj<T, INTERP, 16, 16>
+           : choice == 1 ? k_flow_adj<T, INTERP, 32, 16>
            : choice == 2 ? k_flow_adj<T, INTERP, 64, 8>
                          : k_flow_adj<T, INTERP, 32, 8>;
 }
