@@ -179,16 +179,18 @@ def operators_large(B, torch, reps=5, before_ops=None):
         upd["auto" if sc < 0 else str(sc)] = round(ev0.elapsed_time(ev1) / 3, 3)
     # Solve-OF (GKS with GCV: 10 Golub-Kahan steps, 20 projected solves, one workgroup per
     # pair) on the frames reduced by the automatic factor (32 x 32), with the reverse flow
-    f = lambda: B.flow_solve_gks(stack, u, w, delta_r=1, ell=10, n_iter=20, scale=_lib.MMOF_FLOW_SCALE_AUTO,
-                                 v_rev=vr)
-    f()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(3):
+    # and its p = q = 1 variant (smoothed-l1 weights, Gram matrices rebuilt per solve)
+    for key, pq in (("solve_of_auto", 2), ("solve_of_l1_auto", 1)):
+        f = lambda: B.flow_solve_gks(stack, u, w, delta_r=1, ell=10, n_iter=20, scale=_lib.MMOF_FLOW_SCALE_AUTO,
+                                     v_rev=vr, pq=pq)
         f()
-    ev1.record()
-    torch.cuda.synchronize()
-    upd["solve_of_auto"] = round(ev0.elapsed_time(ev1) / 3, 3)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(3):
+            f()
+        ev1.record()
+        torch.cuda.synchronize()
+        upd[key] = round(ev0.elapsed_time(ev1) / 3, 3)
     del plan, fplan
     return {"workload": "large1024x1024x64: 12 moving/rotating ellipses, 90 golden-angle-shifted angles/frame, "
                         "1449 bins, smooth flow |v| <= 3 px", "dtype": "f32", "tiles": tuned, "kernels": table,
