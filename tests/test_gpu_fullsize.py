@@ -3,7 +3,7 @@
 * 1024x1024 x 64 frames, 12 moving/rotating ellipses, 90 angles per frame shifted by the
   golden angle, 1449 bins: H, H^T, Psi, Psi^T, L(v), L(v)^T (both directions), d/dv,
   App. C derivatives, Horn-Schunck sweeps, and the flow on frames reduced by 32 (sweeps and
-  Solve-OF) in FP32 on the whole stack; the oracle
+  Solve-OF, p = q = 2 and 1) in FP32 on the whole stack; the oracle
   recomputes sampled frames/pairs in FP64 from the same FP32 inputs.  Adjoint
   identities at full size in FP64.
 * 128x128 x 16 (the benchmark workload, in its launch configuration): the first MM
@@ -159,6 +159,24 @@ def test_reduced_frame_flows_fullsize_sampled(big):
         exp = optflow.flow_update_scaled(upair, np.zeros((1, 2, s.ny, s.nx)), 0.1, 50, 1, 32)[0]
         assert rel(vh[p], exp) < 1e-4, p
         exp = solve_of.solve_of(upair, 1, 10, 20, 0.0, 32)[0]
+        assert rel(vg[p], exp) < 1e-4, p
+
+
+def test_reduced_frame_solve_of_l1_fullsize_sampled(big):
+    """The p = q = 1 variant of Solve-OF (smoothed-l1 weights, eps = 1e-3) on frames reduced by
+    the automatic factor, FP32 derivatives on the whole stack (the benchmark's configuration);
+    the oracle recomputes sampled pairs in FP64 from the same FP32 frames."""
+    import torch
+    from oracle import solve_of
+    from paper_2501_12497_amd import _lib
+    B, s, u32 = big["B"], big["s"], big["u32"]
+    st = big["stack"]
+    v = torch.zeros(2 * st.n_pair_px, dtype=torch.float32, device="cuda")
+    B.flow_solve_gks(st, big["u"], v, delta_r=1, ell=10, n_iter=20, scale=_lib.MMOF_FLOW_SCALE_AUTO, pq=1)
+    vg = v.view(s.n_t - 1, 2, s.ny, s.nx).cpu().numpy()
+    for p in PAIRS[:2]:
+        upair = u32[p:p + 2].astype(np.float64)
+        exp = solve_of.solve_of(upair, 1, 10, 20, 0.0, 32, p=1)[0]
         assert rel(vg[p], exp) < 1e-4, p
 
 
