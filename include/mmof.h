@@ -239,9 +239,10 @@ int mmof_flow_solve_gks(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, co
                         double fixed_lambda, int32_t scale, double* lambdas);
 
 /* Solve-OF (Alg. 2) with a choice of norms: pq = 2 is mmof_flow_solve_gks; pq = 1 is the
- * p = q = 1 variant, MMGKS on ||Y s - b||_1 + lambda ||L s||_1 smoothed with eps (each
- * |x| -> sqrt(x^2 + eps^2), as for the image problem, eq. smoothed-l1 / Sec. 3.1): at
- * projected solve k the weights come from the iterate s^(k) (s^(0) = 0),
+ * p = q = 1 variant of eq. of_reg_full, MMGKS on ||Y s - b||_1 + lambda ||L s||_1 with each
+ * |x| smoothed to sqrt(x^2 + eps^2) and majorized by the weights 1 / phi_eps of the current
+ * iterate as for the image problem (eq. QuadraticMajorantQ): at projected solve k the
+ * weights come from the iterate s^(k) (s^(0) = 0),
  *   W_d = diag((e^2 + eps^2)^(-1/2)), e = Y s^(k) - b   (data rows),
  *   W_r = diag(((L s^(k))^2 + eps^2)^(-1/2))           (rows of L),
  * and the projected problem, the GCV functional and the residual are those of the weighted

@@ -37,9 +37,10 @@ Readings (the paper is silent or garbled):
   * The reverse flow is not solved for: the Remark on the reverse optical flow forms it
     from s (optflow.reverse_flow).
 
-The p = q = 1 variant (mentioned for standalone flow problems) is MMGKS proper on
-||Y s - b||_1 + lambda ||L s||_1 smoothed with eps (phi_eps(x) = sqrt(x^2 + eps^2), as for the
-image problem): at iteration k the weights come from the current iterate s^(k) (s^(0) = 0),
+The p = q = 1 variant (eq. of_reg_full with p = q = 1; the paper mentions it for flow problems
+on their own) is MMGKS proper on ||Y s - b||_1 + lambda ||L s||_1 smoothed with eps
+(phi_eps(x) = sqrt(x^2 + eps^2), majorized with the weights 1 / phi_eps as for the image
+problem, eq. QuadraticMajorantQ): at iteration k the weights come from the current iterate s^(k) (s^(0) = 0),
 W_d = diag((e^2 + eps^2)^(-1/2)) on the data rows (e = Y s^(k) - b) and
 W_r = diag(((L s^(k))^2 + eps^2)^(-1/2)) on the rows of L; the projected problem, GCV and the
 residual use Y -> W_d^(1/2) Y, b -> W_d^(1/2) b, L -> W_r^(1/2) L (so G is the printed functional
