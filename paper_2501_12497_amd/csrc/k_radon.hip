@@ -48,12 +48,12 @@ __global__ __launch_bounds__(256) void k_transpose_frames(const Tile* __restrict
     }
 }
 
-// Sum over the (at most three) pixels of one row with non-zero hat weight for a ray whose
-// centre crosses the row at xs: weights 1 - |a| |x - xs| with |a| >= 1/sqrt(2), so the
+// Sum over the (at most three) pixels of one row (the row starting at offset roff of the
+// frame img) with non-zero hat weight for a ray whose centre crosses the row at xs: weights 1 - |a| |x - xs| with |a| >= 1/sqrt(2), so the
 // pixels are floor(xs) - 1 .. floor(xs) + 1 when the fraction is below 1/2, else
 // floor(xs) .. floor(xs) + 2.
 template <class T>
-__device__ __forceinline__ T hat_row(const T* __restrict__ row, int ncol, double xs, T aa) {
+__device__ __forceinline__ T hat_row(const T* __restrict__ img, int roff, int ncol, double xs, T aa) {
     const double fl = floor(xs);
     const int xi = (int)fl;
     const T fr = (T)(xs - fl);
@@ -63,7 +63,7 @@ __device__ __forceinline__ T hat_row(const T* __restrict__ row, int ncol, double
     for (int k = 0; k < 3; ++k) {
         const int x = xi + k0 + k;
         const T w = T(1) - aa * fabs(T(k0 + k) - fr);
-        if (x >= 0 && x < ncol && w > T(0)) acc += w * row[x];
+        if (x >= 0 && x < ncol && w > T(0)) acc += w * img[(uint32_t)(roff + x)];
     }
     return acc;
 }
@@ -72,7 +72,7 @@ __device__ __forceinline__ T hat_row(const T* __restrict__ row, int ncol, double
 // pixels floor(xs) and floor(xs) + 1 with weights 1 - |a| f and 1 - |a| (1 - f), and the
 // outer neighbour on the nearer side with weight max(0, 1 - |a| (1 + min(f, 1 - f))).
 template <class T>
-__device__ __forceinline__ T hat_row_inner(const T* __restrict__ row, int ncol, double xs, T aa) {
+__device__ __forceinline__ T hat_row_inner(const T* __restrict__ img, int roff, int ncol, double xs, T aa) {
     // xs >= 1: truncation is the floor; the clamp keeps every access inside the row even if
     // rounding puts xs a hair outside the interior (the weights then still match xs)
     const int xi = min(max((int)xs, 1), ncol - 3);
@@ -83,7 +83,7 @@ __device__ __forceinline__ T hat_row_inner(const T* __restrict__ row, int ncol, 
     const T w2 = fmax(T(1) - aa * (T(1) + (lo ? fr : T(1) - fr)), T(0));
     // the four pixels xi - 1 .. xi + 2 (all inside the row) as one 4-element load
     typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
-    const V4 q = *reinterpret_cast<const V4*>(row + xi - 1);
+    const V4 q = *reinterpret_cast<const V4*>(img + (uint32_t)(roff + xi - 1));
     return w0 * q.y + w1 * q.z + w2 * (lo ? q.x : q.w);
 }
 
@@ -147,23 +147,23 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
         }
         if (in_hi < in_lo || ncol < 4) in_hi = in_lo = r_lo;  // no interior (also for rows shorter than 4)
         int r = r_lo;
-        for (; r < min(in_lo, r_hi); ++r) acc += hat_row(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+        for (; r < min(in_lo, r_hi); ++r) acc += hat_row(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
         for (; r < in_hi - 3; r += 4) {
-            const T a0 = hat_row_inner(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
-            const T a1 = hat_row_inner(img + (int64_t)(r + 1) * ncol, ncol, fma((double)(r + 1), step, xs0), aa);
-            const T a2 = hat_row_inner(img + (int64_t)(r + 2) * ncol, ncol, fma((double)(r + 2), step, xs0), aa);
-            const T a3 = hat_row_inner(img + (int64_t)(r + 3) * ncol, ncol, fma((double)(r + 3), step, xs0), aa);
+            const T a0 = hat_row_inner(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
+            const T a1 = hat_row_inner(img, (r + 1) * ncol, ncol, fma((double)(r + 1), step, xs0), aa);
+            const T a2 = hat_row_inner(img, (r + 2) * ncol, ncol, fma((double)(r + 2), step, xs0), aa);
+            const T a3 = hat_row_inner(img, (r + 3) * ncol, ncol, fma((double)(r + 3), step, xs0), aa);
             acc += (a0 + a1) + (a2 + a3);
         }
-        for (; r < in_hi; ++r) acc += hat_row_inner(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+        for (; r < in_hi; ++r) acc += hat_row_inner(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
         for (; r < r_hi - 3; r += 4) {
-            const T a0 = hat_row(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
-            const T a1 = hat_row(img + (int64_t)(r + 1) * ncol, ncol, fma((double)(r + 1), step, xs0), aa);
-            const T a2 = hat_row(img + (int64_t)(r + 2) * ncol, ncol, fma((double)(r + 2), step, xs0), aa);
-            const T a3 = hat_row(img + (int64_t)(r + 3) * ncol, ncol, fma((double)(r + 3), step, xs0), aa);
+            const T a0 = hat_row(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
+            const T a1 = hat_row(img, (r + 1) * ncol, ncol, fma((double)(r + 1), step, xs0), aa);
+            const T a2 = hat_row(img, (r + 2) * ncol, ncol, fma((double)(r + 2), step, xs0), aa);
+            const T a3 = hat_row(img, (r + 3) * ncol, ncol, fma((double)(r + 3), step, xs0), aa);
             acc += (a0 + a1) + (a2 + a3);
         }
-        for (; r < r_hi; ++r) acc += hat_row(img + (int64_t)r * ncol, ncol, fma((double)r, step, xs0), aa);
+        for (; r < r_hi; ++r) acc += hat_row(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
     }
     part[wave][lane] = acc;
     __syncthreads();
@@ -242,6 +242,8 @@ void radon_plan_init(Ctx& c, Plan& p) {
     int64_t sino = 0, trig = 0;
     for (int64_t fi = 0; fi < g.n_frames; ++fi) {
         const FrameInfo& fr = g.frames[fi];
+        // the projectors address pixels by 32-bit offsets within a frame
+        MMOF_CHECK((int64_t)fr.ny * fr.nx < ((int64_t)1 << 31), MMOF_ERR_SHAPE, "frames must have fewer than 2^31 pixels");
         RadonFrame r{};
         r.u_off = fr.off;
         r.sino_off = sino;
