@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ ti
                             s_val[e] = lr[k];
                             s_rank[e] = (unsigned short)i;
                         } else {
-                            s_over = 1;
+                            atomicOr(&s_over, 1);
                         }
                     }
                 }
