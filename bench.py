@@ -1,19 +1,23 @@
 """Benchmark of the MMGKS-OF hot path on one MI355X.
 
-Workload: 128x128 pixels x 16 frames, three ellipses translating with integer
-velocities in [-2, 2] px/frame, 30 parallel-beam angles per frame rotated 6 deg per
-frame, 181 detector bins, 2% Gaussian noise (synthetic, seeded).  One step is one
-complete joint solve (MMGKS-OF, Alg. 1): Golub-Kahan start (ell = 10), 30 outer
-MM iterations, Horn-Schunck flow update (200 sweeps) every 10 iterations, with FP32
-operator applications and the FP64 generalized-Krylov projection, Gram matrices,
-projected solve and discrepancy principle.  Inputs are resident on the GPU before
-the timed region starts.
+Workload (headline): 1024x1024 pixels x 64 frames, 12 ellipses moving with real
+velocities in [-2, 2] px/frame and rotating up to 3 deg/frame, 90 parallel-beam angles
+per frame shifted by the golden angle from frame to frame, 1449 detector bins, 2%
+Gaussian noise (synthetic, seeded).  One step is one complete joint solve (MMGKS-OF,
+Alg. 1): Golub-Kahan start (ell = 10), 30 outer MM iterations, Horn-Schunck flow update
+(100 sweeps) every 10 iterations, with FP32 operator applications and the FP64
+generalized-Krylov projection, Gram matrices, projected solve and discrepancy principle.
+Inputs are resident on the GPU before the timed region starts.  `value` counts the
+applications of H, H^T and L(v) (each flow direction of L or L^T once) per second of
+whole-solve wall time.
 
 Printed JSON fields beyond the driver's contract:
-  roofline         the dominant kernel's algorithmic bytes / its mean launch time
-                   (HIP events on the library's stream over the timed region)
-  time_to_solution FP32-operator vs FP64-operator solve to the same RRE target
-  cpu_baseline     the FP64 oracle on the host cores, on a bounded sample
+  roofline         the dominant kernel of the solve (largest summed HIP-event time):
+                   its algorithmic bytes (or flops) / its mean launch time over the timed
+                   region, against the HBM or compute peak its arithmetic intensity selects
+  kernel_share     summed HIP-event time per solve of the candidate kernels
+  time_to_solution FP64-operator, FP32-operator and FP32 + FP64-refined solves to one RRE
+  cpu_baseline     the FP64 oracle's operators on the host, on a bounded sample, extrapolated
 """
 from __future__ import annotations
 
@@ -48,6 +52,8 @@ COMPUTE = {
     "fan_adj": ("alu", 157.3),
     "flow_up": ("alu", 157.3),
     "mdot": ("alu", 78.6),          # FP64 vector ALU
+    "gemv": ("alu", 78.6),
+    "gemv_mdot": ("alu", 78.6),
 }
 # The committed HBM-traffic summary of a kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) and
 # the source file it was measured on: traffic is reported only while that source is unchanged.
@@ -80,15 +86,13 @@ def measured_traffic(kernel):
 
 # FP32+FP64-refined solves: the last outer iterations run with FP64 operators
 REFINE_ITERS = 10
+# candidate kernels for the roofline line: the projector pair, the weighted Gram and the
+# passes over the Krylov basis (every other kernel of the solve is far smaller)
+CANDIDATES = ("wgram", "radon_fwd", "radon_adj", "gemv", "mdot", "gemv_mdot", "flow_adj", "hs_multi")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def make_workload():
-    from synth import cfg_ellipse128
-    return cfg_ellipse128()
 
 
 def gpu_data(wl, B, torch):
@@ -197,64 +201,6 @@ def operators_large(B, torch, reps=5, before_ops=None):
             "flow_update_ms": upd}
 
 
-def large_solve(B, torch, k_ref=30, k_cap=40):
-    """Time to solution on the 1024x1024x64 workload: the target is the RRE of the
-    FP64-operator solve after k_ref iterations (x 1.01); FP64, FP32 and FP32 + FP64-refined
-    solves run to it (at most k_cap iterations), timed by the wall clock of solve_joint with
-    the inputs resident.  (k_cap bounds the Krylov basis: 49 columns of V, H V and Theta V
-    in both precisions take about 200 GB of HBM.)"""
-    from synth import cfg_large1024
-    wl = cfg_large1024()
-    stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
-    p = wl.params
-    prm = dict(ell=p["ell"], k_max=k_ref, tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
-               eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"])
-    for dt in (torch.float32, torch.float64):
-        log(f"large autotune {dt}: {plan.autotune(dt)}")
-    out = {"workload": "large1024x1024x64", "n_pixels": plan.n, "n_data": plan.m, "params": dict(prm),
-           "k_cap": k_cap}
-    t0 = time.perf_counter()
-    ref = B.solve_joint(plan, b, delta, u_true=u_true, op_dtype="f64", **prm)
-    torch.cuda.synchronize()
-    out["f64_reference"] = {"seconds": time.perf_counter() - t0, "iters": ref.iters, "rre": ref.rre[-1]}
-    log(f"large f64 reference: {out['f64_reference']}")
-    target = ref.rre[-1] * 1.01
-    out["rre_target"] = target
-    prm["k_max"] = k_cap
-    for name, kw in (("f64", dict(op_dtype="f64")), ("f32", dict(op_dtype="f32")),
-                     ("f32+refine", dict(op_dtype="f32", refine_iters=REFINE_ITERS))):
-        # untimed one-iteration solve of the same configuration: the workspaces (tens of GB
-        # at this size) are allocated outside the timed run
-        B.solve_joint(plan, b, delta, u_true=u_true, rre_target=1.0, **dict(prm, **kw))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = B.solve_joint(plan, b, delta, u_true=u_true, rre_target=target, **dict(prm, **kw))
-        torch.cuda.synchronize()
-        out[name] = {"seconds": time.perf_counter() - t0, "iters": r.iters, "rre": r.rre[-1],
-                     "reached": bool(r.rre[-1] <= target)}
-        log(f"large {name}: {out[name]}")
-    free, total = torch.cuda.mem_get_info()
-    out["hbm_used_gb"] = round((total - free) / 1e9, 1)
-    # the FP64 Krylov kernels at this size: HIP-event time and algorithmic bytes of every
-    # launch of one kernel over one FP32 solve of k_ref iterations (one solve per kernel)
-    ctx = plan.ctx
-    kry = {}
-    prm["k_max"] = k_ref
-    for kname in ("wgram", "mdot", "gemv_mdot", "gemv"):
-        ctx.profile_kernel(kname)
-        B.solve_joint(plan, b, delta, u_true=u_true, op_dtype="f32", **prm)
-        torch.cuda.synchronize()
-        nl, ms, by, fl = ctx.kernel_timing()
-        ctx.profile_kernel(None)
-        if nl:
-            sec = ms * 1e-3
-            kry[kname] = {"launches": nl, "avg_us": round(ms * 1e3 / nl, 1), "GB/s": round(by / sec / 1e9, 1),
-                          "hbm_frac": round(by / sec / 1e9 / HBM_PEAK_GBS, 3), "TFLOP/s": round(fl / sec / 1e12, 2)}
-    out["krylov_kernels"] = kry
-    log(f"large krylov kernels: {kry}")
-    return out
-
-
 def ragged_blur(B, torch, reps=2):
     """The batched deblurring workload (40 sequences of 64^2..256^2 x 8..32 frames, 9x9
     Gaussian blur, 1% noise): FP32-operator solves with the launch sequences replayed from
@@ -342,60 +288,126 @@ def autograd_step(B, torch, reps=10):
     return out
 
 
-def solve_params(wl, op, graph=True):
-    p = wl.params
-    return dict(ell=p["ell"], k_max=p["k_max"], tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
-                eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"], op_dtype=op, use_graph=1 if graph else 0)
+def solve_kw(p, k_max, op, graph=False, **extra):
+    kw = dict(ell=p["ell"], k_max=k_max, tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"], eps=p["eps"],
+              eta=p["eta"], delta_r=p["delta_r"], op_dtype=op, use_graph=1 if graph else 0)
+    kw.update(extra)
+    return kw
 
 
-def cpu_baseline(wl, k_iters: int = 3):
-    """The FP64 oracle's solve on the same workload, stopped after k_iters outer iterations
-    (one flow update included); matvecs counted by wrapping the oracle's operators."""
-    from oracle import mmgks
-    from synth import noisy
+def roofline_of(name, n_launch, k_ms, k_bytes, k_flops):
+    """Roofline object of a kernel from its HIP-event time and algorithmic work."""
+    if not (n_launch and k_ms > 0 and name in COMPUTE):
+        return None
+    unit, peak_tf = COMPUTE[name]
+    sec = k_ms * 1e-3
+    intensity = k_flops / max(k_bytes, 1.0)
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    common = {"kernel": name, "launches": n_launch, "avg_launch_us": round(k_ms * 1e3 / n_launch, 3),
+              "bytes_per_launch": round(k_bytes / n_launch), "flops_per_launch": round(k_flops / n_launch),
+              "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(ridge, 2)}
+    traffic = measured_traffic(name)
+    if intensity < ridge:
+        ach = k_bytes / sec / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, **common}
+    ach = k_flops / sec / 1e12
+    return {"bound": unit, "achieved": round(ach, 2), "peak": peak_tf, "unit": "TFLOP/s",
+            "frac": round(ach / peak_tf, 4), "traffic": traffic, **common}
 
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
+
+def kernel_shares(ctx, step, names):
+    """Summed HIP-event time (ms) of each named kernel over one call of step()."""
+    out = {}
+    for name in names:
+        ctx.profile_kernel(name)
+        step()
+        n, ms, _, _ = ctx.kernel_timing()
+        ctx.profile_kernel(None)
+        if n:
+            out[name] = {"launches": n, "ms": round(ms, 3)}
+    return out
+
+
+def tts(B, torch, plan, b, delta, u_true, p, k_ref, k_cap, reps=1, graph=False):
+    """Time to solution at a fixed relative error: the target is the RRE of the FP64-operator
+    solve after k_ref iterations (x 1.01); FP64, FP32 and FP32 + FP64-refined solves run to
+    it (at most k_cap iterations), timed by the wall clock of solve_joint (median of reps,
+    after an untimed run that also allocates the workspaces).  The refined solve runs its
+    last REFINE_ITERS iterations with FP64 operators and is given k_max = (iterations the
+    FP32 solve needed) + 1, so that its FP64 phase starts REFINE_ITERS - 1 iterations before
+    the FP32 solve reached the target; it is an error if no FP64 iteration ran."""
+    ref = B.solve_joint(plan, b, delta, u_true=u_true, **solve_kw(p, k_ref, "f64", graph))
+    target = ref.rre[-1] * 1.01
+    out = {"k_ref": k_ref, "k_cap": k_cap, "rre_target": target}
+
+    def run(kw):
+        B.solve_joint(plan, b, delta, u_true=u_true, **kw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = B.solve_joint(plan, b, delta, u_true=u_true, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return r, float(np.median(ts))
+
+    for name, op in (("f64", "f64"), ("f32", "f32")):
+        r, sec = run(solve_kw(p, k_cap, op, graph, rre_target=target))
+        out[name] = {"seconds": sec, "iters": r.iters, "rre": r.rre[-1], "reached": bool(r.rre[-1] <= target)}
+        log(f"tts {name}: {out[name]}")
+    k_max = out["f32"]["iters"] + 1
+    r, sec = run(solve_kw(p, k_max, "f32", graph, rre_target=target, refine_iters=REFINE_ITERS))
+    k_sw = max(0, k_max - REFINE_ITERS)
+    n64 = max(0, r.iters - k_sw)
+    out["f32+refine"] = {"seconds": sec, "iters": r.iters, "rre": r.rre[-1], "reached": bool(r.rre[-1] <= target),
+                         "k_max": k_max, "refine_iters": REFINE_ITERS, "fp32_iters": min(r.iters, k_sw),
+                         "fp64_iters": n64, "rre_vs_f64": r.rre[-1] - out["f64"]["rre"]}
+    log(f"tts f32+refine: {out['f32+refine']}")
+    if n64 == 0:
+        raise RuntimeError("the FP32 + FP64-refined solve ran no FP64 iteration")
+    return out
+
+
+def cpu_baseline_large(wl, counts, n_angles_sample=45):
+    """The FP64 oracle's operators on a bounded sample of the 1024x1024x64 workload, scaled
+    to the whole stack and to the operator mix of one GPU solve: H and H^T on frame 0 with
+    its first n_angles_sample angles (the projector is a sum over angles and frames, so its
+    time is linear in both), L(v) and L(v)^T in one direction on the pair (0, 1) (linear in
+    pairs).  Rate = applications in one GPU solve / the oracle's extrapolated time for them.
+    Only operator time is counted (none of the solve's Krylov or flow work), so the rate
+    favours the CPU."""
+    from oracle import forward, regops
+    from synth import smooth_flow_coarse
     s = wl.seqs[0]
-    g = mmgks.SeqGeom(s.n_t, s.ny, s.nx, s.angles, s.n_bins)
-    ops = mmgks.StackOps([g], "radon")
-    clean = ops.A(s.u_true.ravel())
-    b = noisy(clean, s.noise_g, wl.noise_level)
-    delta = float(np.linalg.norm(b - clean))
-    cnt = dict(A=0, At=0, L=0)
-    fA, fAt, fT, fTT = ops.A, ops.At, ops.theta, ops.thetaT
-
-    def A(x):
-        cnt["A"] += 1
-        return fA(x)
-
-    def At(x):
-        cnt["At"] += 1
-        return fAt(x)
-
-    def T(x, f):
-        cnt["L"] += 2
-        return fT(x, f)
-
-    def TT(x, f):
-        cnt["L"] += 2
-        return fTT(x, f)
-
-    ops.A, ops.At, ops.theta, ops.thetaT = A, At, T, TT
-    p = wl.params
-    prm = mmgks.SolveParams(ell=p["ell"], k_max=k_iters, tau=p["tau"], n_sweeps=p["n_sweeps"], alpha=p["alpha"],
-                            eps=p["eps"], eta=p["eta"], delta_r=p["delta_r"])
+    n_t, ny, nx = s.n_t, s.ny, s.nx
+    na = s.angles.shape[1]
+    u = s.u_true
+    ang = s.angles[:1, :n_angles_sample]
+    v = smooth_flow_coarse(1, nx, seed=11, coarse=16, vmax=3.0)
     t0 = time.perf_counter()
-    mmgks.mmgks_of(ops, b, delta, prm, u_true=s.u_true.ravel())
-    dt = time.perf_counter() - t0
-    n = cnt["A"] + cnt["At"] + cnt["L"]
-    return {"value": n / dt, "unit": "matvecs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"FP64 oracle MMGKS-OF on the same 128x128x16 data, {k_iters} outer iterations "
-                      f"(1 flow update of {p['n_sweeps']} sweeps), {n} A/At/L(v) applications in {dt:.1f} s; "
-                      f"sparse products single-threaded, dense QR/solves on {threads} BLAS threads"}
+    bb = forward.radon_fwd(u[:1], ang, s.n_bins)
+    t1 = time.perf_counter()
+    forward.radon_adj(bb, ang, ny, nx)
+    t2 = time.perf_counter()
+    rr = regops.flow_fwd(u[:2], v, 1)
+    t3 = time.perf_counter()
+    regops.flow_adj(rr, v, 2, 1)
+    t4 = time.perf_counter()
+    scale_a = n_t * na / n_angles_sample
+    t_A, t_At = (t1 - t0) * scale_a, (t2 - t1) * scale_a
+    t_L, t_Lt = (t3 - t2) * (n_t - 1), (t4 - t3) * (n_t - 1)
+    # L counts the forward and the adjoint applications together; take their mean per use
+    t_solve = counts["A"] * t_A + counts["At"] * t_At + counts["L"] * 0.5 * (t_L + t_Lt)
+    n_mv = counts["A"] + counts["At"] + counts["L"]
+    return {"value": n_mv / t_solve, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle (NumPy, one thread) on the 1024x1024x64 workload: H and H^T on frame 0 with "
+                      f"{n_angles_sample} of its {na} angles ({t1 - t0:.1f} s, {t2 - t1:.1f} s), L(v) and L(v)^T "
+                      f"on frames 0-1 ({t3 - t2:.2f} s, {t4 - t3:.2f} s), extrapolated linearly to {n_t} frames, "
+                      f"{na} angles and {n_t - 1} pairs (per stack application: H {t_A:.0f} s, H^T {t_At:.0f} s, "
+                      f"L {t_L:.1f} s, L^T {t_Lt:.1f} s) and weighted by one GPU solve's {counts['A']} H, "
+                      f"{counts['At']} H^T and {counts['L']} L/L^T applications; operator time only",
+            "seconds_per_stack_application": {"A": t_A, "At": t_At, "L": t_L, "Lt": t_Lt}}
 
 
 def main():
@@ -403,22 +415,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--profile-kernel", default="wgram")
+    ap.add_argument("--k-max", type=int, default=30, help="outer MM iterations of the headline solve")
+    ap.add_argument("--profile-kernel", default=None,
+                    help="roofline kernel (default: the largest summed time among the candidates)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution legs")
+    ap.add_argument("--no-small", action="store_true", help="skip the 128x128x16 solves")
     ap.add_argument("--no-large", action="store_true", help="skip the operator table at 1024x1024x64")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tile shapes")
     ap.add_argument("--no-ragged", action="store_true", help="skip the batched-deblurring (40 sequences) solves")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd forward/backward timing")
-    ap.add_argument("--no-large-solve", action="store_true",
-                    help="skip the FP64 / FP32 / FP32+refined solves of the 1024x1024x64 workload")
     ap.add_argument("--graph", action="store_true",
                     help="replay the fixed launch sequences of each iteration from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference dispatch for HBM counters)")
-    ap.add_argument("--only", choices=["operators", "large-solve"],
+    ap.add_argument("--only", choices=["operators", "headline"],
                     help="for profiler runs: only the operator table at 1024x1024x64 (after a 256 MiB copy), "
-                         "or only one FP32 solve of that workload (30 iterations, after the autotuner)")
+                         "or only the headline solves (no other leg)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no multi-GPU path.",
@@ -430,54 +443,50 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    def calibration_copy():
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+
     if a.only == "operators":
-        def calibration_copy():
-            src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-            dst = torch.empty_like(src)
-            dst.copy_(src)
-            torch.cuda.synchronize()
-            log("copy calibration: 268435456 bytes read, 268435456 bytes written")
         # every operator: one warm-up launch, then 3 timed ones, right after the copy
         print(json.dumps(operators_large(B, torch, reps=3, before_ops=calibration_copy)), flush=True)
         return
-    if a.only == "large-solve":
-        from synth import cfg_large1024
-        wl = cfg_large1024()
-        stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
-        p = wl.params
-        for dt in (torch.float32, torch.float64):
-            log(f"large autotune {dt}: {plan.autotune(dt)}")
-        t0 = time.perf_counter()
-        r = B.solve_joint(plan, b, delta, u_true=u_true, op_dtype="f32", ell=p["ell"], k_max=30, tau=p["tau"],
-                          n_sweeps=p["n_sweeps"], alpha=p["alpha"], eps=p["eps"], eta=p["eta"],
-                          delta_r=p["delta_r"])
-        torch.cuda.synchronize()
-        print(json.dumps({"seconds": time.perf_counter() - t0, "iters": r.iters, "rre": r.rre[-1],
-                          "counts": r.counts}), flush=True)
-        return
-    wl = make_workload()
+    if a.only == "headline":
+        a.no_tts = a.no_small = a.no_large = a.no_ragged = a.no_autograd = a.no_cpu_baseline = True
+
+    from synth import cfg_large1024
+    wl = cfg_large1024()
     stack, plan, u_true, b, delta = gpu_data(wl, B, torch)
     ctx = plan.ctx
-    prm = solve_params(wl, "f32", graph=a.graph)
+    p = wl.params
+    prm = solve_kw(p, a.k_max, "f32", a.graph)
     log(f"workload {wl.name}: n={plan.n} m={plan.m} params={prm}")
     if not a.no_autotune:  # tile shapes of this plan's stencil kernels, once, before any timing
         for dt in (torch.float32, torch.float64):
             log(f"autotune {dt}: {plan.autotune(dt)}")
 
     def step():
-        return B.solve_joint(plan, b, delta, u_true=u_true, **prm)
+        r = B.solve_joint(plan, b, delta, u_true=u_true, **prm)
+        return r
 
     if a.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
-        del src, dst
+        calibration_copy()
     for i in range(a.warmup):
         r = step()
+        torch.cuda.synchronize()
         log(f"warmup {i}: iters={r.iters} rre={r.rre[-1]:.5f}")
-    ctx.profile_kernel(a.profile_kernel)
+    # the dominant kernel: summed HIP-event time per solve of each candidate (untimed solves)
+    shares = None
+    prof = a.profile_kernel
+    if prof is None:
+        shares = kernel_shares(ctx, step, CANDIDATES)
+        prof = max(shares, key=lambda k: shares[k]["ms"])
+        log(f"kernel shares per solve: {shares}; roofline kernel: {prof}")
+    ctx.profile_kernel(prof)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = []
@@ -492,54 +501,50 @@ def main():
     mv = r.counts["A"] + r.counts["At"] + r.counts["L"]
     value = mv * a.steps / (t1 - t0)
     log(f"timed {a.steps} solves: {ms_step:.2f} ms/solve, {mv} matvecs/solve, rre={r.rre[-1]:.5f}, "
-        f"{a.profile_kernel}: {n_launch} launches {k_ms:.2f} ms")
+        f"{prof}: {n_launch} launches {k_ms:.2f} ms")
+    roof = roofline_of(prof, n_launch, k_ms, k_bytes, k_flops)
 
-    # roofline of the profiled kernel: its algorithmic work over its launches in the timed
-    # region (HIP events on the library's stream), against the bound its arithmetic
-    # intensity selects
-    roof = None
-    if n_launch and k_ms > 0 and a.profile_kernel in COMPUTE:
-        unit, peak_tf = COMPUTE[a.profile_kernel]
-        sec = k_ms * 1e-3
-        intensity = k_flops / max(k_bytes, 1.0)
-        ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
-        traffic = measured_traffic(a.profile_kernel)
-        common = {"kernel": a.profile_kernel, "launches": n_launch, "avg_launch_us": round(k_ms * 1e3 / n_launch, 3),
-                  "bytes_per_launch": round(k_bytes / n_launch), "flops_per_launch": round(k_flops / n_launch),
-                  "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(ridge, 2),
-                  "traffic": traffic}
-        if intensity < ridge:
-            ach = k_bytes / sec / 1e9
-            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), **common}
-        else:
-            ach = k_flops / sec / 1e12
-            roof = {"bound": unit, "achieved": round(ach, 2), "peak": peak_tf, "unit": "TFLOP/s",
-                    "frac": round(ach / peak_tf, 4), **common}
-
-    # time to solution at a fixed relative error: FP32 operators vs FP64 operators
-    tts = None
+    big_tts = None
     if not a.no_tts:
-        ref = B.solve_joint(plan, b, delta, u_true=u_true, **solve_params(wl, "f64", graph=a.graph))
-        target = ref.rre[-1] * 1.001
-        tts = {"rre_target": target, "k_max": prm["k_max"] + 15}
-        for op in ("f64", "f32", "f32+refine"):
-            kw = solve_params(wl, op.split("+")[0], graph=a.graph)
-            kw["k_max"] = prm["k_max"] + 15
-            kw["rre_target"] = target
-            if op.endswith("refine"):
-                kw["refine_iters"] = REFINE_ITERS
-            B.solve_joint(plan, b, delta, u_true=u_true, **kw)
+        big_tts = tts(B, torch, plan, b, delta, u_true, p, k_ref=30, k_cap=40, graph=a.graph)
+        free, total = torch.cuda.mem_get_info()
+        big_tts["hbm_used_gb"] = round((total - free) / 1e9, 1)
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline_large(wl, r.counts)
+        log(f"cpu baseline: {cpu}")
+    del plan
+    torch.cuda.empty_cache()
+
+    small = None
+    if not a.no_small:
+        from synth import cfg_ellipse128
+        ws = cfg_ellipse128()
+        _, splan, su, sb, sdelta = gpu_data(ws, B, torch)
+        if not a.no_autotune:
+            for dt in (torch.float32, torch.float64):
+                splan.autotune(dt)
+        sp = ws.params
+        skw = solve_kw(sp, sp["k_max"], "f32", a.graph)
+        B.solve_joint(splan, sb, sdelta, u_true=su, **skw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            t_0 = time.perf_counter()
+            sr = B.solve_joint(splan, sb, sdelta, u_true=su, **skw)
             torch.cuda.synchronize()
-            ts = []
-            for _ in range(3):
-                t0 = time.perf_counter()
-                rr = B.solve_joint(plan, b, delta, u_true=u_true, **kw)
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t0)
-            tts[op] = {"seconds": float(np.median(ts)), "iters": rr.iters, "rre": rr.rre[-1],
-                       "reached": bool(rr.rre[-1] <= target)}
-        log(f"time to solution: {tts}")
+            ts.append(time.perf_counter() - t_0)
+        sec = float(np.median(ts))
+        smv = sr.counts["A"] + sr.counts["At"] + sr.counts["L"]
+        small = {"workload": "ellipse128x128x16: 3 translating ellipses, 30 angles/frame (+6 deg/frame), 181 bins, "
+                             "2% noise; ell=10, 30 MM iterations, flow every 10 (200 HS sweeps)",
+                 "seconds_per_solve": sec, "matvecs_per_solve": smv, "matvecs_per_s": smv / sec, "rre": sr.rre[-1]}
+        if not a.no_tts:
+            small["time_to_solution"] = tts(B, torch, splan, sb, sdelta, su, sp, k_ref=sp["k_max"],
+                                            k_cap=sp["k_max"] + 15, reps=3, graph=a.graph)
+        log(f"small: {small}")
+        del splan
 
     large = None
     if not a.no_large:
@@ -554,15 +559,6 @@ def main():
     if not a.no_autograd:
         agrad = autograd_step(B, torch)
 
-    big = None
-    if not a.no_large_solve:
-        big = large_solve(B, torch)
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(wl)
-        log(f"cpu baseline: {cpu}")
-
     out = {
         "metric": "A+At+L(v) matvecs/s in the MMGKS-OF joint solve (FP32 operators, FP64 Krylov)",
         "value": round(value, 1),
@@ -576,20 +572,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 operators + f64 krylov",
         "data": "synthetic",
-        "config": {"workload": "ellipse128x128x16: 3 translating ellipses, 30 angles/frame (+6 deg/frame), "
-                               "181 bins, 2% noise; solve ell=10, 30 MM iterations, flow every 10 (200 HS sweeps)",
-                   "n_pixels": plan.n, "n_data": plan.m, "matvecs_per_step": mv, "rre": r.rre[-1]},
+        "config": {"workload": "large1024x1024x64: 12 ellipses moving (real velocities in [-2,2] px/frame) and "
+                               "rotating (up to 3 deg/frame), 90 parallel-beam angles/frame shifted by the golden "
+                               f"angle, 1449 bins, 2% noise; solve ell=10, {a.k_max} MM iterations, flow every "
+                               f"{p['tau']} ({p['n_sweeps']} HS sweeps)",
+                   "n_pixels": stack.n, "n_data": int(b.numel()), "matvecs_per_step": mv, "rre": r.rre[-1],
+                   "iters": r.iters},
         "roofline": roof,
-        "time_to_solution": tts,
+        "kernel_share": shares,
+        "time_to_solution": big_tts,
         "cpu_baseline": cpu,
+        "small_ellipse128": small,
         "operators_large": large,
     }
     if ragged is not None:
         out["ragged_blur"] = ragged
     if agrad is not None:
         out["autograd"] = agrad
-    if big is not None:
-        out["time_to_solution_large"] = big
     print(json.dumps(out))
 
 

@@ -314,7 +314,15 @@ typedef struct {
  * re-estimated every tau iterations.  b: device FP64 [m]; noise_norm: ||e|| for the
  * discrepancy principle; u_inout: device FP64 [n] (initial estimate in, solution out);
  * v_out, v_rev_out: device flows of dtype op_dtype (either may be NULL); rep may be NULL.
- * Krylov vectors, Gram matrices, the projected solve and lambda are FP64 on the GPU. */
+ * Krylov vectors, Gram matrices, the projected solve and lambda are FP64 on the GPU.
+ * A batch of several sequences is ONE problem: one objective over the packed stack, one
+ * Krylov basis and one lambda (the discrepancy principle of Sec. 4.1.3 applied to the
+ * stacked data), so noise_norm is the norm of the noise of the whole stack,
+ * sqrt(sum_s ||e_s||^2).  Independent problems with a lambda each are independent calls
+ * (one plan per sequence; several contexts on several streams run them concurrently).
+ * Errors: MMOF_ERR_NONFINITE when b or u_inout holds NaN or Inf (checked on the device
+ * before the first iteration); MMOF_ERR_SHAPE when ell + k_max - 1 exceeds the Krylov
+ * capacity. */
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p,
                      void* u_inout, void* v_out, void* v_rev_out, mmof_report* rep);
 /* Fill p with the defaults (ell 10, k_max 20, tau 1, 200 sweeps, delta_r 1, flow on,

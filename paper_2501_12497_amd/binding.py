@@ -465,15 +465,24 @@ def solve_joint(plan: Plan, b: torch.Tensor, noise_norm: float, u0: Optional[tor
                 u_true: Optional[torch.Tensor] = None, **params) -> SolveResult:
     """MMGKS-OF solve; b, u0, u_true are FP64 GPU tensors; params as in mmof_solve_params."""
     p = solve_params(**params)
-    _need(b, plan.m, "b")
+    # the library reads b and u_inout as FP64 device arrays of m and n values: every dtype
+    # and device is checked before a pointer is handed over
     if b.dtype != torch.float64:
-        raise TypeError("b must be float64")
+        raise TypeError(f"b must be float64 (got {b.dtype})")
+    if u0 is not None:
+        if u0.dtype != torch.float64:
+            raise TypeError(f"u0 must be float64 (got {u0.dtype})")
+        if u0.device != b.device:
+            raise ValueError(f"u0 is on {u0.device}, b on {b.device}")
+    if u_true is not None and u_true.dtype != torch.float64:
+        raise TypeError(f"u_true must be float64 (got {u_true.dtype})")
+    _need(b, plan.m, "b")
     u = torch.zeros(plan.n, dtype=torch.float64, device=b.device) if u0 is None else u0.clone()
     _need(u, plan.n, "u0")
     if u_true is not None:
         _need(u_true, plan.n, "u_true")
-        if u_true.dtype != torch.float64:
-            raise TypeError("u_true must be float64")
+        if u_true.device != b.device:
+            raise ValueError(f"u_true is on {u_true.device}, b on {b.device}")
         p.u_true = u_true.data_ptr()
     opdt = torch.float32 if p.op_dtype == _lib.MMOF_F32 else torch.float64
     P = plan.stack.n_pair_px

@@ -348,8 +348,14 @@ struct Solver {
         mdot<TX, TX>(c, n, 1, out_n, n, out_n, 1.0, scal + 4);
         // RRE denominator
         if (p.u_true) norm_into(n, p.u_true, scal + 5);
-        MMOF_HIP(hipMemcpyAsync(host, scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        // squared norms of the inputs (scal[6], scal[7] are free until the first report): a NaN
+        // or an infinity anywhere in b or u_inout makes its norm non-finite
+        copy_scalar(c, scal + 6, sc);
+        norm_into(n, u_io, scal + 7);
+        MMOF_HIP(hipMemcpyAsync(host, scal + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
         MMOF_HIP(hipStreamSynchronize(c.stream));
+        MMOF_CHECK(std::isfinite(host[2]), MMOF_ERR_NONFINITE, "b holds NaN or Inf (or its norm overflows)");
+        MMOF_CHECK(std::isfinite(host[3]), MMOF_ERR_NONFINITE, "u_inout holds NaN or Inf (or its norm overflows)");
         const double atb = std::sqrt(host[0]);
         const double utn = p.u_true ? std::sqrt(host[1]) : 0.0;
 

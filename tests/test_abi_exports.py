@@ -44,3 +44,21 @@ def test_version_without_gpu():
     from paper_2501_12497_amd import _lib
     lib = _lib.load()
     assert lib.mmof_version().decode().startswith("mmof-gfx950")
+
+
+def test_solve_joint_rejects_wrong_u0_dtype_before_any_launch():
+    """u_inout is read and written as n FP64 values: a float32 u0 must be refused in the
+    binding (it would be an out-of-bounds device write), before any GPU work."""
+    import torch
+    from paper_2501_12497_amd import binding as B
+
+    class _Plan:
+        n, m = 16, 8
+
+    b = torch.zeros(8, dtype=torch.float64)
+    with pytest.raises(TypeError, match="u0 must be float64"):
+        B.solve_joint(_Plan(), b, 0.1, u0=torch.zeros(16, dtype=torch.float32))
+    with pytest.raises(TypeError, match="b must be float64"):
+        B.solve_joint(_Plan(), b.float(), 0.1)
+    with pytest.raises(TypeError, match="u_true must be float64"):
+        B.solve_joint(_Plan(), b, 0.1, u_true=torch.zeros(16, dtype=torch.float32))

@@ -14,7 +14,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import TOL32, rel
+from gpu_helpers import TOL32, assert_close
 from oracle import forward, mmgks, optflow, regops
 from synth import cfg_ellipse128, cfg_large1024, noisy, smooth_flow_coarse
 
@@ -48,7 +48,7 @@ def test_radon_fullsize_sampled(big):
             th = float(s.angles[t, k])
             exp = forward.radon_project_angle(ut, th, s.n_bins)
             sc = forward.radon_project_angle(np.abs(ut), th, s.n_bins)
-            assert rel(b[t, k], exp, sc) < TOL32, (t, k)
+            assert_close(b[t, k], exp, TOL32, sc, msg=(t, k))
     # transpose on sampled frames, from a random FP32 sinogram
     r = np.random.default_rng(1)
     bs = r.standard_normal(b.shape).astype(np.float32)
@@ -56,7 +56,7 @@ def test_radon_fullsize_sampled(big):
     for t in FRAMES[:2]:
         exp = forward.radon_adj(bs[t:t + 1].astype(np.float64), s.angles[t:t + 1], s.ny, s.nx)[0]
         sc = forward.radon_adj(np.abs(bs[t:t + 1]).astype(np.float64), s.angles[t:t + 1], s.ny, s.nx)[0]
-        assert rel(ua[t], exp, sc) < TOL32, t
+        assert_close(ua[t], exp, TOL32, sc, msg=t)
 
 
 def test_adjoint_identities_fullsize_fp64(big):
@@ -109,9 +109,9 @@ def test_flow_fullsize_sampled(big, direction):
         exp = regops.flow_fwd(upair, vp, direction)[0]
         src, sub = (upair[1], upair[0]) if direction > 0 else (upair[0], upair[1])
         sc = (abs(regops.motion_matrix(vp[0])) @ np.abs(src).ravel()).reshape(src.shape) + np.abs(sub)
-        assert rel(r[p], exp, sc) < TOL32, p
+        assert_close(r[p], exp, TOL32, sc, msg=p)
         exp_g = regops.flow_dv(upair, vp, w[p:p + 1].astype(np.float64), direction)[0]
-        assert rel(gv[p], exp_g, 2 * np.abs(w[p]) * np.abs(upair).max()) < TOL32, p
+        assert_close(gv[p], exp_g, TOL32, 2 * np.abs(w[p]) * np.abs(upair).max(), msg=p)
     # adjoint: frame t receives the warp adjoint of one pair and minus the other pair's residual
     for t in (1, 40, 62):
         if direction > 0:
@@ -120,7 +120,7 @@ def test_flow_fullsize_sampled(big, direction):
         else:
             back = regops.flow_adj(w[t:t + 1].astype(np.float64), v32[t:t + 1].astype(np.float64), 2, -1)[0]
             exp = back - w[t - 1].astype(np.float64)
-        assert rel(ua[t], exp, np.abs(back) + 2 * np.abs(w[t]).max()) < TOL32, t
+        assert_close(ua[t], exp, TOL32, np.abs(back) + 2 * np.abs(w[t]).max(), msg=t)
 
 
 def test_optical_flow_fullsize_sampled(big):
@@ -134,9 +134,9 @@ def test_optical_flow_fullsize_sampled(big):
     for p in PAIRS[:2]:
         upair = u32[p:p + 2].astype(np.float64)
         exp = optflow.of_derivs(upair, 1)[0]
-        assert rel(I[p], exp, np.abs(upair).max() * np.ones_like(exp)) < TOL32, p
+        assert_close(I[p], exp, TOL32, np.abs(upair).max() * np.ones_like(exp), msg=p)
         expv = optflow.flow_update(upair, np.zeros((1, 2, s.ny, s.nx)), 0.1, 10, 1)[0]
-        assert rel(vh[p], expv) < 1e-4, p
+        assert_close(vh[p], expv, 1e-4, msg=p)
 
 
 def test_reduced_frame_flows_fullsize_sampled(big):
@@ -157,9 +157,9 @@ def test_reduced_frame_flows_fullsize_sampled(big):
     for p in PAIRS[:2]:
         upair = u32[p:p + 2].astype(np.float64)
         exp = optflow.flow_update_scaled(upair, np.zeros((1, 2, s.ny, s.nx)), 0.1, 50, 1, 32)[0]
-        assert rel(vh[p], exp) < 1e-4, p
+        assert_close(vh[p], exp, 1e-4, msg=p)
         exp = solve_of.solve_of(upair, 1, 10, 20, 0.0, 32)[0]
-        assert rel(vg[p], exp) < 1e-4, p
+        assert_close(vg[p], exp, 1e-4, msg=p)
 
 
 def test_reduced_frame_solve_of_l1_fullsize_sampled(big):
@@ -177,7 +177,7 @@ def test_reduced_frame_solve_of_l1_fullsize_sampled(big):
     for p in PAIRS[:2]:
         upair = u32[p:p + 2].astype(np.float64)
         exp = solve_of.solve_of(upair, 1, 10, 20, 0.0, 32, p=1)[0]
-        assert rel(vg[p], exp) < 1e-4, p
+        assert_close(vg[p], exp, 1e-4, msg=p)
 
 
 def _ellipse128():
@@ -207,7 +207,7 @@ def test_solve_ellipse128_first_iterations_fp64():
     for k in range(res.iters):
         assert abs(res.rre[k] - ref.rre[k]) <= 1e-8, (k, res.rre[k], ref.rre[k])
     np.testing.assert_allclose(res.lambdas, ref.lambdas, rtol=1e-6)
-    assert np.linalg.norm(res.u.cpu().numpy() - ref.u) <= 1e-6 * np.linalg.norm(ref.u)
+    assert_close(res.u.cpu().numpy(), ref.u, 1e-6)
 
 
 def _golden_solve():

@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import TOL32, TOL64, dev, host, pack, rel, roundtrip32, unpack
+from gpu_helpers import TOL32, TOL64, assert_close, dev, host, pack, roundtrip32, unpack
 from oracle import forward, optflow, regops
 from synth import bins_for, nudge_off_kinks
 
@@ -66,14 +66,14 @@ def test_radon_forward_and_adjoint(B, which):
     b = host(B.apply_A(plan, dev(pack(us), dt)))
     exp = [forward.radon_fwd(u, a, nb) for u, a, nb in zip(us, angs, nbins)]
     scale = pack([forward.radon_fwd(np.abs(u), a, nb) for u, a, nb in zip(us, angs, nbins)])
-    assert rel(b, pack(exp), scale) < tol
+    assert_close(b, pack(exp), tol, scale)
     bs = [r.standard_normal(e.shape) for e in exp]
     if dt == torch.float32:
         bs = [roundtrip32(x) for x in bs]
     u = host(B.apply_At(plan, dev(pack(bs), dt)))
     expu = [forward.radon_adj(x, a, s[1], s[2]) for x, a, s in zip(bs, angs, SIZES)]
     scale = pack([forward.radon_adj(np.abs(x), a, s[1], s[2]) for x, a, s in zip(bs, angs, SIZES)])
-    assert rel(u, pack(expu), scale) < tol
+    assert_close(u, pack(expu), tol, scale)
 
 
 def test_radon_adjoint_identity_fp64(B):
@@ -104,9 +104,9 @@ def test_blur(B, which, ksize, sigma):
     y = host(B.apply_A(plan, dev(pack(us), dt)))
     exp = pack([forward.blur(u, ksize, sigma) for u in us])
     sc = pack([forward.blur(np.abs(u), ksize, sigma) for u in us])
-    assert rel(y, exp, sc) < tol
+    assert_close(y, exp, tol, sc)
     y2 = host(B.apply_At(plan, dev(pack(us), dt)))
-    assert rel(y2, pack([forward.blur_adj(u, ksize, sigma) for u in us]), sc) < tol
+    assert_close(y2, pack([forward.blur_adj(u, ksize, sigma) for u in us]), tol, sc)
 
 
 # --------------------------------------------------------------------------- gradient
@@ -136,10 +136,11 @@ def test_grad_forward_and_adjoint(B, which, weighted, layout):
     gx, gy = B.apply_grad(stack, dev(pack(us), dt), wx=wx, wy=wy)
     ex = [regops.grad_fwd(u, *((a, b) if weighted else ())) for u, a, b in
           zip(us, wxs or [None] * nseq, wys or [None] * nseq)]
-    sx = pack([np.abs(u[:, :, 1:]) + np.abs(u[:, :, :-1]) for u in us])
-    sy = pack([np.abs(u[:, 1:, :]) + np.abs(u[:, :-1, :]) for u in us])
-    assert rel(host(gx), pack([e[0] for e in ex]), sx if not weighted else None) < tol
-    assert rel(host(gy), pack([e[1] for e in ex]), sy if not weighted else None) < tol
+    # per-element forward-error scales |w| (|u_right| + |u_left|)
+    sx = pack([(wxs[i] if weighted else 1.0) * (np.abs(u[:, :, 1:]) + np.abs(u[:, :, :-1])) for i, u in enumerate(us)])
+    sy = pack([(wys[i] if weighted else 1.0) * (np.abs(u[:, 1:, :]) + np.abs(u[:, :-1, :])) for i, u in enumerate(us)])
+    assert_close(host(gx), pack([e[0] for e in ex]), tol, sx)
+    assert_close(host(gy), pack([e[1] for e in ex]), tol, sy)
     u = host(B.apply_grad(stack, gx=dev(pack(gxs), dt), gy=dev(pack(gys), dt), wx=wx, wy=wy, transpose=True))
     exp = pack([regops.grad_adj(a, b, *((c, d) if weighted else ())) for a, b, c, d in
                 zip(gxs, gys, wxs or [None] * nseq, wys or [None] * nseq)])
@@ -154,7 +155,7 @@ def test_grad_forward_and_adjoint(B, which, weighted, layout):
         sc[:, :-1, :] += b
         scale.append(sc)
     scale = pack(scale)
-    assert rel(u, exp, scale) < tol
+    assert_close(u, exp, tol, scale)
 
 
 # --------------------------------------------------------------------------- flow operator
@@ -212,11 +213,11 @@ def test_flow_operator(B, which, direction, interp, vmax, layout):
     y = host(B.apply_flow_op(stack, _lib.MMOF_FLOW_FWD, direction, ip, du, dv))
     exp = pack([regops.flow_fwd(u, v, direction, interp) for u, v in zip(us, vs)])
     scale = pack([_abs_warp(u, v, direction, interp) for u, v in zip(us, vs)])
-    assert rel(y, exp, scale) < tol
+    assert_close(y, exp, tol, scale)
     ya = B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, direction, ip, None, dv, dr)
     exp = pack([regops.flow_adj(r, v, s[0], direction, interp) for r, v, s in zip(rs, vs, sizes)])
     scale = pack([_abs_warp(None, v, direction, interp, True, r) for r, v in zip(rs, vs)])
-    assert rel(host(ya), exp, scale) < tol
+    assert_close(host(ya), exp, tol, scale)
     # the adjoint is a deterministic gather: bitwise reproducible
     ya2 = B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, direction, ip, None, dv, dr)
     assert torch.equal(ya, ya2)
@@ -238,7 +239,7 @@ def test_flow_dv(B, which, direction):
                              dev(pack(us), dt), dev(pack(vs), dt), dev(pack(ws), dt)))
     exp = pack([regops.flow_dv(u, v, w, direction) for u, v, w in zip(us, vs, ws)])
     scale = pack([2 * np.abs(w)[:, None] * np.abs(u).max() * np.ones((1, 2, 1, 1)) for u, w in zip(us, ws)])
-    assert rel(g, exp, scale) < tol
+    assert_close(g, exp, tol, scale)
 
 
 # --------------------------------------------------------------------------- optical flow pieces
@@ -259,7 +260,7 @@ def test_of_derivs(B, which, dr, layout):
     I = host(B.of_derivs(B.Stack(sizes), dev(pack(us), dt), dr))
     exp = pack([optflow.of_derivs(u, dr) for u in us])
     scale = pack([optflow.of_derivs(np.abs(u), dr) * 0 + np.abs(u).max() for u in us])
-    assert rel(I, exp, scale) < tol
+    assert_close(I, exp, tol, scale)
 
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
@@ -279,11 +280,11 @@ def test_flow_update_and_reverse(B, which, layout):
     B.flow_update(stack, dev(pack(us), dt), v, alpha=0.3, n_sweeps=25, delta_r=1, v_rev=vr)
     exp = [optflow.flow_update(u, v0, 0.3, 25, 1) for u, v0 in zip(us, vs0)]
     got = host(v)
-    assert rel(got, pack(exp)) < (TOL64 if dt == torch.float64 else 1e-4)
+    assert_close(got, pack(exp), TOL64 if dt == torch.float64 else 1e-4)
     # reverse flow of the GPU's own flow (rounding decisions must see identical inputs)
     gshapes = [e.shape for e in exp]
     exp_r = pack([optflow.reverse_flow(x) for x in unpack(got, gshapes)])
-    assert rel(host(vr), exp_r) < tol
+    assert_close(host(vr), exp_r, tol)
 
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
@@ -307,10 +308,10 @@ def test_flow_update_scaled(B, which, layout, scale):
     B.flow_update_scaled(stack, dev(pack(us), dt), v, alpha=0.3, n_sweeps=25, delta_r=1, scale=scale, v_rev=vr)
     exp = [optflow.flow_update_scaled(u, v0, 0.3, 25, 1, scale) for u, v0 in zip(us, vs0)]
     got = host(v)
-    assert rel(got, pack(exp)) < (TOL64 if dt == torch.float64 else 1e-4)
+    assert_close(got, pack(exp), TOL64 if dt == torch.float64 else 1e-4)
     gshapes = [e.shape for e in exp]
     exp_r = pack([optflow.reverse_flow(x) for x in unpack(got, gshapes)])
-    assert rel(host(vr), exp_r) < (TOL64 if dt == torch.float64 else TOL32)
+    assert_close(host(vr), exp_r, TOL64 if dt == torch.float64 else TOL32)
 
 
 def test_flow_update_scaled_edges(B):
@@ -331,7 +332,7 @@ def test_flow_update_scaled_edges(B):
     c = dev(pack(vs0), torch.float64)
     B.flow_update_scaled(stack, u, c, alpha=0.2, n_sweeps=9, delta_r=1, scale=3)   # (4,4,3,3) -> (3,3), (2,3)
     exp = pack([optflow.flow_update_scaled(x, v0, 0.2, 9, 1, 3) for x, v0 in zip(us, vs0)])
-    assert rel(host(c), exp) < TOL64
+    assert_close(host(c), exp, TOL64, elementwise=True)
     # automatic factor: the smallest power of two that brings the sides below 50
     big = [(2, 100, 120), (2, 30, 44)]
     ub = dev(pack([r.standard_normal(sz) for sz in big]), torch.float64)
@@ -361,7 +362,7 @@ def test_flow_update_sweep_counts_small_frames(B, n_sweeps):
     v = dev(pack(vs0), torch.float64)
     B.flow_update(B.Stack(sizes), dev(pack(us), torch.float64), v, alpha=0.2, n_sweeps=n_sweeps, delta_r=1)
     exp = pack([optflow.flow_update(u, v0, 0.2, n_sweeps, 1) for u, v0 in zip(us, vs0)])
-    assert rel(host(v), exp) < TOL64
+    assert_close(host(v), exp, TOL64, elementwise=True)
 
 
 @pytest.mark.parametrize("which", ["f64", "f32"])
@@ -410,4 +411,4 @@ def test_mm_weights(B, which):
     if dt == torch.float32:
         nu = roundtrip32(nu)
     w = host(B.mm_weights(dev(nu, dt), 1e-3))
-    assert rel(w, mmgks.mm_weights_sq(nu, 1e-3)) < tol
+    assert_close(w, mmgks.mm_weights_sq(nu, 1e-3), tol)

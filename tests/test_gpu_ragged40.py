@@ -12,7 +12,7 @@
 import numpy as np
 import pytest
 
-from gpu_helpers import TOL32, rel
+from gpu_helpers import TOL32, assert_close
 from oracle import forward, regops
 from synth import cfg_blur_ragged, smooth_flow_coarse
 
@@ -51,7 +51,7 @@ def test_blur_psi_flow_ragged40_sampled(rag):
             ut = u32[i][t:t + 1].astype(np.float64)
             exp = forward.blur(ut)[0]
             sc = forward.blur(np.abs(ut))[0]
-            assert rel(hb[i][t], exp, sc) < TOL32, (i, t)
+            assert_close(hb[i][t], exp, TOL32, sc, msg=(i, t))
     # Psi
     gx, gy = B.apply_grad(rag["stack"], rag["u"])
     gxs = _split(gx.cpu().numpy(), [(nt, ny, nx - 1) for nt, ny, nx in sizes])
@@ -59,8 +59,8 @@ def test_blur_psi_flow_ragged40_sampled(rag):
     for i, (nt, ny, nx) in enumerate(sizes):
         ut = u32[i][[0, nt - 1]].astype(np.float64)
         ex, ey = regops.grad_fwd(ut)
-        assert rel(gxs[i][[0, nt - 1]], ex, np.abs(ut[:, :, 1:]) + np.abs(ut[:, :, :-1])) < TOL32, i
-        assert rel(gys[i][[0, nt - 1]], ey, np.abs(ut[:, 1:, :]) + np.abs(ut[:, :-1, :])) < TOL32, i
+        assert_close(gxs[i][[0, nt - 1]], ex, TOL32, np.abs(ut[:, :, 1:]) + np.abs(ut[:, :, :-1]), msg=i)
+        assert_close(gys[i][[0, nt - 1]], ey, TOL32, np.abs(ut[:, 1:, :]) + np.abs(ut[:, :-1, :]), msg=i)
     # L(v), forward direction, with a smooth flow of up to 2 px per sequence
     from paper_2501_12497_amd import _lib
     vs = [smooth_flow_coarse(nt - 1, nx, seed=40 + i, coarse=8, vmax=2.0).astype(np.float32)
@@ -75,7 +75,7 @@ def test_blur_psi_flow_ragged40_sampled(rag):
             exp = regops.flow_fwd(ut, vp, 1)[0]
             M = abs(regops.motion_matrix(vp[0]))
             sc = (M @ np.abs(ut[1]).ravel()).reshape(ny, nx) + np.abs(ut[0])
-            assert rel(rs[i][p], exp, sc) < TOL32, (i, p)
+            assert_close(rs[i][p], exp, TOL32, sc, msg=(i, p))
 
 
 def test_solve_ragged40_graph_matches_eager(rag):

@@ -13,7 +13,7 @@ lambdas are not compared).
 import numpy as np
 import pytest
 
-from gpu_helpers import TOL32, dev, host, pack, rel, roundtrip32, unpack
+from gpu_helpers import TOL32, assert_close, dev, host, pack, roundtrip32, unpack
 from oracle import optflow, solve_of
 
 pytestmark = pytest.mark.gpu
@@ -65,7 +65,7 @@ def test_fixed_lambda_fp64(B):
     us = _frames(1)
     got, _, lam = _run(B, us, torch.float64, ell=6, n_iter=8, fixed_lambda=0.05)
     exp, _ = _oracle(us, 6, 8, 0.05)
-    assert rel(got, pack(exp)) < 1e-10
+    assert_close(got, pack(exp), 1e-10)
     assert np.all(lam == 0.05)
 
 
@@ -76,11 +76,11 @@ def test_gcv_fp64(B, ell, n_iter):
     got, gotr, lam = _run(B, us, torch.float64, ell=ell, n_iter=n_iter)
     exp, elams = _oracle(us, ell, n_iter)
     np.testing.assert_allclose(lam, np.array(elams), rtol=1e-6)
-    assert rel(got, pack(exp)) < 1e-8
+    assert_close(got, pack(exp), 1e-8)
     # reverse flow of the GPU's own flow
     shapes = [(u.shape[0] - 1, 2) + u.shape[1:] for u in us]
     flows = unpack(got, shapes)
-    assert rel(gotr, pack([optflow.reverse_flow(f) for f in flows])) < 1e-12
+    assert_close(gotr, pack([optflow.reverse_flow(f) for f in flows]), 1e-12)
 
 
 def test_gcv_fp32_derivatives(B):
@@ -88,7 +88,7 @@ def test_gcv_fp32_derivatives(B):
     us = [roundtrip32(u) for u in _frames(3)]
     got, _, lam = _run(B, us, torch.float32, ell=10, n_iter=20)
     exp, elams = _oracle(us, 10, 20)
-    assert rel(got, pack(exp)) < 1e-4   # (the lambdas may move to another point where G is flat)
+    assert_close(got, pack(exp), 1e-4)   # (the lambdas may move to another point where G is flat)
 
 
 def test_reduced_frames(B):
@@ -98,7 +98,7 @@ def test_reduced_frames(B):
     us = _frames(4, sizes)
     got, _, _ = _run(B, us, torch.float64, ell=8, n_iter=10, scale=2)
     exp = pack([solve_of.solve_of(u, 1, 8, 10, 0.0, 2) for u in us])
-    assert rel(got, exp) < 1e-8
+    assert_close(got, exp, 1e-8)
 
 
 def test_edges(B):
@@ -113,7 +113,7 @@ def test_edges(B):
     us = [_frames(6, [(1, 8, 8)])[0], _frames(7, [(2, 10, 9)])[0]]
     got, _, _ = _run(B, us, torch.float64, ell=5, n_iter=5)
     exp, _ = _oracle([us[1]], 5, 5)
-    assert rel(got, pack(exp)) < 1e-8
+    assert_close(got, pack(exp), 1e-8)
     # argument checks, before any launch
     stack = B.Stack([(2, 6, 5)])
     uu = dev(np.zeros(60), torch.float64)
@@ -155,7 +155,7 @@ def test_joint_solve_with_solve_of(B, op):
     assert abs(res.rre[-1] - ref.rre[-1]) <= 1e-4
     if op == "f64":
         np.testing.assert_allclose(res.lambdas, ref.lambdas, rtol=1e-7)
-        assert np.linalg.norm(res.u.cpu().numpy() - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
+        assert_close(res.u.cpu().numpy(), ref.u, 1e-7)
     again = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta, u_true=torch.as_tensor(ut, device="cuda"),
                           use_graph=1, **kw)
     assert torch.equal(again.u, res.u) and again.lambdas == res.lambdas
@@ -185,7 +185,7 @@ def test_l1_fixed_lambda_fp64(B, lam, eps):
     us = _frames(21)
     got, _, lams = _run(B, us, torch.float64, ell=6, n_iter=9, fixed_lambda=lam, pq=1, eps=eps)
     exp, _ = _oracle_l1(us, 6, 9, lam, eps)
-    assert rel(got, pack(exp)) < 1e-8
+    assert_close(got, pack(exp), 1e-8)
     assert np.all(lams == lam)
 
 
@@ -196,9 +196,9 @@ def test_l1_gcv_fp64(B, ell, n_iter):
     got, gotr, lam = _run(B, us, torch.float64, ell=ell, n_iter=n_iter, pq=1)
     exp, elams = _oracle_l1(us, ell, n_iter)
     np.testing.assert_allclose(lam, np.array(elams), rtol=1e-6)
-    assert rel(got, pack(exp)) < 1e-7
+    assert_close(got, pack(exp), 1e-7)
     shapes = [(u.shape[0] - 1, 2) + u.shape[1:] for u in us]
-    assert rel(gotr, pack([optflow.reverse_flow(f) for f in unpack(got, shapes)])) < 1e-12
+    assert_close(gotr, pack([optflow.reverse_flow(f) for f in unpack(got, shapes)]), 1e-12)
 
 
 def test_l1_large_eps_is_the_quadratic_solve(B):
@@ -209,7 +209,7 @@ def test_l1_large_eps_is_the_quadratic_solve(B):
     g2, _, l2 = _run(B, us, torch.float64, ell=5, n_iter=7)
     g1, _, l1 = _run(B, us, torch.float64, ell=5, n_iter=7, pq=1, eps=1e8)
     np.testing.assert_allclose(l1, l2, rtol=1e-7)
-    assert rel(g1, g2) < 1e-8
+    assert_close(g1, g2, 1e-8)
 
 
 def test_l1_reduced_frames_fp32(B):
@@ -219,7 +219,7 @@ def test_l1_reduced_frames_fp32(B):
     us = [roundtrip32(u) for u in _frames(24, sizes)]
     got, _, _ = _run(B, us, torch.float32, ell=6, n_iter=8, scale=2, pq=1)
     exp = pack([solve_of.solve_of(u, 1, 6, 8, 0.0, 2, p=1) for u in us])
-    assert rel(got, exp) < 1e-4
+    assert_close(got, exp, 1e-4)
 
 
 def test_l1_rejects(B):

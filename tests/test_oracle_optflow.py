@@ -2,7 +2,8 @@
 
 App. C derivatives: exact on space-time ramps away from borders; constants give 0;
 the mirrored border of a ramp gives half the slope (closed form of the half-sample
-symmetric extension).
+symmetric extension); an impulse gives the closed-form averaging windows of every
+derivative (inside and on the mirrored border).
 Horn-Schunck sweeps: their fixed point solves the normal equations of the p = q = 2
 flow energy (eq. of_reg), checked against a sparse direct solve; a flat image (no
 gradient) reduces the sweep to neighbour averaging.
@@ -40,6 +41,56 @@ def test_derivs_mirrored_border():
     np.testing.assert_allclose(I[0, 0][:, 0], 0.4, atol=1e-14)
     np.testing.assert_allclose(I[0, 0][:, -1], 0.4, atol=1e-14)
     np.testing.assert_allclose(I[0, 0][:, 1:-1], 0.8, atol=1e-14)
+
+
+@pytest.mark.parametrize("dr", [1, 2])
+def test_derivs_impulse_closed_form(dr):
+    """App. C box averaging pinned by an impulse: frame 0 holds a unit impulse at (y0, x0)
+    well inside, frame 1 is zero.  The x-derivative is a column difference of half-width dr
+    averaged over 2dr+1 rows, so it is +1/((2dr+1) 2dr) on column x0-dr and -1/((2dr+1) 2dr)
+    on column x0+dr over rows y0-dr..y0+dr, zero elsewhere (I_y likewise with rows and columns
+    exchanged), and the time difference averaged over the (2dr+1)^2 box is -1/(2dr+1)^2 on
+    the box around the impulse.  A wrong averaging window, a missing box mean on I_t or a
+    wrong half-width changes one of these entries."""
+    ny, nx, y0, x0 = 13, 15, 6, 7
+    u = np.zeros((2, ny, nx))
+    u[0, y0, x0] = 1.0
+    I = optflow.of_derivs(u, dr)[0]
+    box = 2 * dr + 1
+    c = 1.0 / (box * 2 * dr)
+    ex = np.zeros((ny, nx))
+    ey = np.zeros((ny, nx))
+    et = np.zeros((ny, nx))
+    rows = slice(y0 - dr, y0 + dr + 1)
+    cols = slice(x0 - dr, x0 + dr + 1)
+    ex[rows, x0 - dr] = c
+    ex[rows, x0 + dr] = -c
+    ey[y0 - dr, cols] = c
+    ey[y0 + dr, cols] = -c
+    et[rows, cols] = -1.0 / box ** 2
+    np.testing.assert_allclose(I[0], ex, atol=1e-15)
+    np.testing.assert_allclose(I[1], ey, atol=1e-15)
+    np.testing.assert_allclose(I[2], et, atol=1e-15)
+
+
+def test_derivs_impulse_on_the_border_is_mirrored():
+    """The half-sample-symmetric mirror (index -1 reads index 0): an impulse in column 0 is
+    also seen by the x-difference of column 0 through its mirrored left neighbour, so both
+    columns 0 and 1 carry -1/6 (dr = 1) on the rows around the impulse, and the box mean of
+    the time difference counts the impulse twice at column 0 (2 of the 9 box samples of a
+    pixel in column 0 read it, one through the mirror) and once at column 1."""
+    ny, nx, y0 = 9, 8, 4
+    u = np.zeros((2, ny, nx))
+    u[0, y0, 0] = 1.0
+    I = optflow.of_derivs(u, 1)[0]
+    ex = np.zeros((ny, nx))
+    ex[y0 - 1:y0 + 2, 0] = -1.0 / 6.0
+    ex[y0 - 1:y0 + 2, 1] = -1.0 / 6.0
+    np.testing.assert_allclose(I[0], ex, atol=1e-15)
+    et = np.zeros((ny, nx))
+    et[y0 - 1:y0 + 2, 0] = -2.0 / 9.0
+    et[y0 - 1:y0 + 2, 1] = -1.0 / 9.0
+    np.testing.assert_allclose(I[2], et, atol=1e-15)
 
 
 def test_hs_fixed_point_is_direct_solution():
