@@ -369,12 +369,12 @@ def tts(B, torch, plan, b, delta, u_true, p, k_ref, k_cap, reps=1, graph=False):
     return out
 
 
-def cpu_baseline_large(wl, counts, n_angles_sample=45):
+def cpu_baseline_large(wl, counts, n_frames_sample=2):
     """The FP64 oracle's operators on a bounded sample of the 1024x1024x64 workload, scaled
-    to the whole stack and to the operator mix of one GPU solve: H and H^T on frame 0 with
-    its first n_angles_sample angles (the projector is a sum over angles and frames, so its
-    time is linear in both), L(v) and L(v)^T in one direction on the pair (0, 1) (linear in
-    pairs).  Rate = applications in one GPU solve / the oracle's extrapolated time for them.
+    to the whole stack and to the operator mix of one GPU solve: H and H^T on the first
+    n_frames_sample frames with all their angles (the projector is a sum over frames, so its
+    time is linear in them), L(v) and L(v)^T in one direction on the pairs of those frames
+    (linear in pairs).  Rate = applications in one GPU solve / the oracle's extrapolated time for them.
     Only operator time is counted (none of the solve's Krylov or flow work), so the rate
     favours the CPU."""
     from oracle import forward, regops
@@ -383,28 +383,28 @@ def cpu_baseline_large(wl, counts, n_angles_sample=45):
     n_t, ny, nx = s.n_t, s.ny, s.nx
     na = s.angles.shape[1]
     u = s.u_true
-    ang = s.angles[:1, :n_angles_sample]
-    v = smooth_flow_coarse(1, nx, seed=11, coarse=16, vmax=3.0)
+    f = n_frames_sample
+    ang = s.angles[:f]
+    v = smooth_flow_coarse(f - 1, nx, seed=11, coarse=16, vmax=3.0)
     t0 = time.perf_counter()
-    bb = forward.radon_fwd(u[:1], ang, s.n_bins)
+    bb = forward.radon_fwd(u[:f], ang, s.n_bins)
     t1 = time.perf_counter()
     forward.radon_adj(bb, ang, ny, nx)
     t2 = time.perf_counter()
-    rr = regops.flow_fwd(u[:2], v, 1)
+    rr = regops.flow_fwd(u[:f], v, 1)
     t3 = time.perf_counter()
-    regops.flow_adj(rr, v, 2, 1)
+    regops.flow_adj(rr, v, f, 1)
     t4 = time.perf_counter()
-    scale_a = n_t * na / n_angles_sample
-    t_A, t_At = (t1 - t0) * scale_a, (t2 - t1) * scale_a
-    t_L, t_Lt = (t3 - t2) * (n_t - 1), (t4 - t3) * (n_t - 1)
+    t_A, t_At = (t1 - t0) * n_t / f, (t2 - t1) * n_t / f
+    t_L, t_Lt = (t3 - t2) * (n_t - 1) / (f - 1), (t4 - t3) * (n_t - 1) / (f - 1)
     # L counts the forward and the adjoint applications together; take their mean per use
     t_solve = counts["A"] * t_A + counts["At"] * t_At + counts["L"] * 0.5 * (t_L + t_Lt)
     n_mv = counts["A"] + counts["At"] + counts["L"]
     return {"value": n_mv / t_solve, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle (NumPy, one thread) on the 1024x1024x64 workload: H and H^T on frame 0 with "
-                      f"{n_angles_sample} of its {na} angles ({t1 - t0:.1f} s, {t2 - t1:.1f} s), L(v) and L(v)^T "
-                      f"on frames 0-1 ({t3 - t2:.2f} s, {t4 - t3:.2f} s), extrapolated linearly to {n_t} frames, "
-                      f"{na} angles and {n_t - 1} pairs (per stack application: H {t_A:.0f} s, H^T {t_At:.0f} s, "
+            "sample": f"FP64 oracle (NumPy, one thread) on the 1024x1024x64 workload: H and H^T on frames 0-{f - 1} "
+                      f"with all {na} angles ({t1 - t0:.1f} s, {t2 - t1:.1f} s), L(v) and L(v)^T on their "
+                      f"{f - 1} pair(s) ({t3 - t2:.2f} s, {t4 - t3:.2f} s), extrapolated linearly to {n_t} frames "
+                      f"and {n_t - 1} pairs (per stack application: H {t_A:.0f} s, H^T {t_At:.0f} s, "
                       f"L {t_L:.1f} s, L^T {t_Lt:.1f} s) and weighted by one GPU solve's {counts['A']} H, "
                       f"{counts['At']} H^T and {counts['L']} L/L^T applications; operator time only",
             "seconds_per_stack_application": {"A": t_A, "At": t_At, "L": t_L, "Lt": t_Lt}}

@@ -50,7 +50,7 @@ def roundtrip32(x):
 FLOOR = 1e-2
 
 
-def assert_close(got, exp, tol, scale=None, elementwise=None, msg=None):
+def assert_close(got, exp, tol, scale=None, elementwise=None, msg=None, tol_inf=None):
     """Parity of `got` against `exp` at relative level `tol`, three ways:
       norm-wise     ||d||_2 / ||s||_2 < tol
       max-norm      ||d||_inf / ||s||_inf < tol
@@ -60,7 +60,9 @@ def assert_close(got, exp, tol, scale=None, elementwise=None, msg=None):
     (a per-element bound of the rounding error) unless elementwise=False, and for scale-less
     comparisons only when elementwise=True.  A seam or border of a few elements with an
     error far above rounding fails the max-norm or element-wise bar even when the 2-norm over
-    millions of elements does not see it."""
+    millions of elements does not see it.  tol_inf (default tol) is the max-norm bar; solution-
+    level comparisons of iterative FP32 pipelines set it apart from the norm-wise bar.
+    Returns (norm-wise, max-norm) ratios."""
     a = np.asarray(got, dtype=np.float64).ravel()
     b = np.asarray(exp, dtype=np.float64).ravel()
     if scale is None:
@@ -76,7 +78,8 @@ def assert_close(got, exp, tol, scale=None, elementwise=None, msg=None):
     assert r2 < tol, f"norm-wise {r2:.3e} >= {tol:.1e}{tag}"
     ninf = float(s.max()) if s.size else 0.0
     rinf = float(d.max() if d.size else 0.0) / (ninf if ninf > 0 else 1.0)
-    assert rinf < tol, f"max-norm {rinf:.3e} >= {tol:.1e}{tag}"
+    ti = tol if tol_inf is None else tol_inf
+    assert rinf < ti, f"max-norm {rinf:.3e} >= {ti:.1e}{tag}"
     if elementwise is None:
         elementwise = scale is not None
     if elementwise and s.size:
@@ -87,3 +90,4 @@ def assert_close(got, exp, tol, scale=None, elementwise=None, msg=None):
             i = int(np.argmax(d / bound))
             raise AssertionError(f"element-wise: {int(bad.sum())} of {s.size} elements above the bar, worst index "
                                  f"{i}: |d| = {d[i]:.3e}, scale = {s[i]:.3e}, rms scale = {rms:.3e}{tag}")
+    return r2, rinf
