@@ -339,6 +339,19 @@ void mmof_solve_defaults(mmof_solve_params* p);
 int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
                        const void* nu, double eps, double* G, int32_t ldg);
 
+/* mmof_weighted_gram for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same G, with the weights
+ * formed inside the kernel from nu and the per-workgroup partial sums held in a fixed
+ * library-owned device array of 5 MiB per GPU (kept until the process ends; looked up once per
+ * device when a context is created).  No hipMalloc, hipFree or allocating library call is made.
+ * Arguments, layouts and limits as for mmof_weighted_gram (1 <= K <= 64); the K x K entries
+ * of G are written (entries K..ldg-1 of a row are not touched).  Every call on one GPU uses the
+ * same array, which keeps the last call's partials: calls that overlap in time on one device
+ * (from several streams or host threads) race on it and must be serialized by the caller.
+ * The result equals mmof_weighted_gram's up to the order of the FP64 partial sums. */
+int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X,
+                               int64_t ld, const void* nu, double eps, double* G, int32_t ldg);
+
 /* Projected solve of MMGKS (eq. minKryov2) with the discrepancy principle (Sec. 4.1.3):
  * (G_H + lambda G_T) z = d, lambda such that ||b||^2 - d^T z - lambda z^T G_T z = target.
  * GA, GT: device FP64 K x K (leading dimension 64); d: device FP64 [K];

@@ -77,6 +77,8 @@ _SIGS = {
     "mmof_solve_joint": (_I, [_P, _P, C.c_double, C.POINTER(mmof_solve_params), _P, _P, _P,
                               C.POINTER(mmof_report)]),
     "mmof_weighted_gram": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_int32]),
+    "mmof_weighted_gram_noalloc": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P,
+                                        C.c_int32]),
     "mmof_projected_solve": (_I, [_P, C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
     "mmof_profile_kernel": (_I, [_P, C.c_char_p]),
     "mmof_autotune": (_I, [_P, C.c_int32, C.c_char_p, C.c_int32]),

@@ -64,6 +64,7 @@ int mmof_create(mmof_ctx* out, void* hip_stream) {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
             c->cu_count = cus;
         c->stream = static_cast<hipStream_t>(hip_stream);
+        noalloc_init(c->device);  // this device's address of the allocation-free Gram's scratch
         *out = c.release();
         return MMOF_OK;
     });
@@ -497,6 +498,23 @@ int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const 
             wgram<float>(*ctx, n, K, (const float*)X, ld, w, G, ldg);
         else
             wgram<double>(*ctx, n, K, (const double*)X, ld, w, G, ldg);
+        return MMOF_OK;
+    });
+}
+
+int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
+                               const void* nu, double eps, double* G, int32_t ldg) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(X, "X");
+        need(G, "G");
+        MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX_SMALL && ld >= n && ldg >= K, MMOF_ERR_SHAPE, "bad Gram sizes");
+        MMOF_CHECK(!nu || (eps > 0 && std::isfinite(eps)), MMOF_ERR_INVALID, "eps must be > 0");
+        if (dt == MMOF_F32)
+            wgram_noalloc<float>(*ctx, n, K, (const float*)X, ld, (const float*)nu, eps, G, ldg);
+        else
+            wgram_noalloc<double>(*ctx, n, K, (const double*)X, ld, (const double*)nu, eps, G, ldg);
         return MMOF_OK;
     });
 }

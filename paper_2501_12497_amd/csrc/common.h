@@ -239,8 +239,9 @@ struct ScopedTime {
     hipEvent_t ev = nullptr;
     // bytes / flops: the launch's algorithmic work (each input read once, each output written
     // once; the arithmetic the method needs), accumulated while the kernel is being timed
+    // (c == nullptr: never timed)
     ScopedTime(Ctx* c_, const char* n, double bytes = 0.0, double flops = 0.0) : c(c_), name(n) {
-        if (c->timing(name)) {
+        if (c && c->timing(name)) {
             c->time_begin(name, &ev);
             c->timer.bytes += bytes;
             c->timer.flops += flops;

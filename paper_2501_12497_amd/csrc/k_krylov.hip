@@ -5,6 +5,8 @@
 // Column blocks are stored column-major ([K][ld], each column contiguous) in the
 // operator precision TX (float or double); all accumulation is in double.  Every
 // reduction is two-stage with a fixed order, so results are bitwise reproducible.
+#include <mutex>
+
 #include "dev.h"
 #include "krylov.h"
 
@@ -406,12 +408,27 @@ struct GramRows {
     double w[4];
 };
 
+// Weight of one row: read from w (NU = false), or formed from nu as 1/sqrt(nu^2 + eps^2) with
+// the arithmetic of k_mm_weights_f64 (NU = true; wv then points to nu in TX).
+template <class TX, bool NU>
+__device__ __forceinline__ double row_weight(const void* __restrict__ wv, int64_t r, double eps2) {
+    if constexpr (NU) {
+        const double a = (double)static_cast<const TX*>(wv)[r];
+        return 1.0 / sqrt(a * a + eps2);
+    } else {
+        return static_cast<const double*>(wv)[r];
+    }
+}
+
 // Rows r0 + 4q + k (k < 4) of column blocks g < G for this lane; rows at or beyond n and
 // columns at or beyond K read as zero.  VEC: the four rows are loaded with vector loads
-// (requires ld % 4 == 0, 16-byte aligned X and rows r0 + 4q + 3 < n).
-template <class TX, int G, bool VEC>
+// (requires ld % 4 == 0, 16-byte aligned X and rows r0 + 4q + 3 < n).  The row weights come
+// from w (NU = false; null: 1) or from nu (NU = true, see row_weight).
+template <class TX, int G, bool VEC, bool NU = false>
 __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restrict__ X, int64_t ld,
-                                          const double* __restrict__ w, int64_t n, int K, int64_t r0, int lane) {
+                                          const void* __restrict__ wv, int64_t n, int K, int64_t r0, int lane,
+                                          double eps2 = 0.0) {
+    const double* __restrict__ w = static_cast<const double*>(wv);
     const int c = lane & 15;
     const int64_t rb = r0 + 4 * (lane >> 4);
     if (VEC && rb + 3 < n) {
@@ -442,7 +459,10 @@ __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restr
                 for (int k = 0; k < 4; ++k) st.x[g][k] = TX(0);
             }
         }
-        if (w) {
+        if constexpr (NU) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) st.w[k] = row_weight<TX, true>(wv, rb + k, eps2);
+        } else if (w) {
             const double2 w0 = *reinterpret_cast<const double2*>(w + rb);
             const double2 w1 = *reinterpret_cast<const double2*>(w + rb + 2);
             st.w[0] = w0.x;
@@ -459,7 +479,10 @@ __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restr
     for (int k = 0; k < 4; ++k) {
         const int64_t r = rb + k;
         const bool in = r < n;
-        st.w[k] = in ? (w ? w[r] : 1.0) : 0.0;
+        if constexpr (NU)
+            st.w[k] = in ? row_weight<TX, true>(wv, r, eps2) : 0.0;
+        else
+            st.w[k] = in ? (w ? w[r] : 1.0) : 0.0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int col = 16 * g + c;
@@ -468,10 +491,10 @@ __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restr
     }
 }
 
-template <class TX, int G, bool VEC, int W>
+template <class TX, int G, bool VEC, int W, bool NU = false>
 __global__ __launch_bounds__(64 * W) void k_wgram_part(int64_t n, int K, const TX* __restrict__ X,
-                                                                int64_t ld, const double* __restrict__ w,
-                                                                double* __restrict__ part) {
+                                                                int64_t ld, const void* __restrict__ w,
+                                                                double eps2, double* __restrict__ part) {
     constexpr int NP = G * (G + 1) / 2;
     __shared__ double sred[W][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -484,9 +507,9 @@ __global__ __launch_bounds__(64 * W) void k_wgram_part(int64_t n, int K, const T
     const int64_t gw = (int64_t)blockIdx.x * W + wave;
     const int64_t s_lo = steps * gw / nw, s_hi = steps * (gw + 1) / nw;
     GramRows<TX, G> cur, nxt;
-    if (s_lo < s_hi) gram_rows<TX, G, VEC>(cur, X, ld, w, n, K, 16 * s_lo, lane);
+    if (s_lo < s_hi) gram_rows<TX, G, VEC, NU>(cur, X, ld, w, n, K, 16 * s_lo, lane, eps2);
     for (int64_t st = s_lo; st < s_hi; ++st) {
-        if (st + 1 < s_hi) gram_rows<TX, G, VEC>(nxt, X, ld, w, n, K, 16 * (st + 1), lane);
+        if (st + 1 < s_hi) gram_rows<TX, G, VEC, NU>(nxt, X, ld, w, n, K, 16 * (st + 1), lane, eps2);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             double a[G], bw[G];
@@ -826,47 +849,49 @@ void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w) {
 template void mm_weights_f64<float>(Ctx&, int64_t, const float*, double, double*);
 template void mm_weights_f64<double>(Ctx&, int64_t, const double*, double, double*);
 
-template <class TX, int G, bool VEC>
-static void wgram_launch(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* part, int& nb) {
+template <class TX, int G, bool VEC, bool NU>
+static void wgram_launch(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const void* w, double eps2,
+                         double* part, int max_blocks, int& nb) {
     // 16 waves per workgroup where the registers allow (4 per SIMD, to overlap the loads with
-    // the matrix-core work), about 16 16-row steps per wave, at most GRAM_BLOCKS partials
+    // the matrix-core work), about 16 16-row steps per wave, at most max_blocks partials
     constexpr int W = (sizeof(TX) == 4 && G <= 2) ? 16 : 8;
     const int64_t steps = (n + 15) / 16;
-    nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 16 * W)));
-    hipLaunchKernelGGL((k_wgram_part<TX, G, VEC, W>), dim3(nb), dim3(64 * W), 0, c.stream, n, K, X, ld, w, part);
+    nb = (int)std::max<int64_t>(1, std::min<int64_t>(max_blocks, cdiv(steps, 16 * W)));
+    hipLaunchKernelGGL((k_wgram_part<TX, G, VEC, W, NU>), dim3(nb), dim3(64 * W), 0, c.stream, n, K, X, ld, w, eps2,
+                       part);
 }
 
-template <class TX, int G>
-static void wgram_launch_g(Ctx& c, int& nb, bool vec, int64_t n, int K, const TX* X, int64_t ld, const double* w,
-                           double* part) {
+template <class TX, int G, bool NU>
+static void wgram_launch_g(Ctx& c, int& nb, bool vec, int64_t n, int K, const TX* X, int64_t ld, const void* w,
+                           double eps2, double* part, int max_blocks) {
     if constexpr (sizeof(TX) == 4) {
         if (vec) {
-            wgram_launch<TX, G, true>(c, n, K, X, ld, w, part, nb);
+            wgram_launch<TX, G, true, NU>(c, n, K, X, ld, w, eps2, part, max_blocks, nb);
             return;
         }
     }
-    wgram_launch<TX, G, false>(c, n, K, X, ld, w, part, nb);
+    wgram_launch<TX, G, false, NU>(c, n, K, X, ld, w, eps2, part, max_blocks, nb);
 }
 
-template <class TX>
-void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg) {
-    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+// Stage 1 for 1..4 column blocks, then the fixed-order stage 2 into G.
+template <class TX, bool NU>
+static void wgram_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const void* w, double eps2, double* G,
+                         int ldg, double* part, int max_blocks, bool timed) {
     const int Gb = (K + 15) / 16;
     const int np = Gb * (Gb + 1) / 2;
     int nb = 1;  // stage-1 workgroups (partials), set by the launch
     // (vector loads for FP32 columns; FP64 columns load a double per row, which keeps the
-    // row buffers in registers)
+    // row buffers in registers; the vector path also reads w with 16-byte loads)
     const bool vec = sizeof(TX) == 4 && (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
-                     (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
-    double* part =
-        static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * GRAM_PAIRS * 256));
+                     (NU || !w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     {
-        ScopedTime st(&c, "wgram", (double)n * ((double)sizeof(TX) * K + 8.0), (double)n * K * (K + 1));
+        ScopedTime st(timed ? &c : nullptr, "wgram", (double)n * ((double)sizeof(TX) * K + 8.0),
+                      (double)n * K * (K + 1));
         switch (Gb) {
-            case 1: wgram_launch_g<TX, 1>(c, nb, vec, n, K, X, ld, w, part); break;
-            case 2: wgram_launch_g<TX, 2>(c, nb, vec, n, K, X, ld, w, part); break;
-            case 3: wgram_launch_g<TX, 3>(c, nb, vec, n, K, X, ld, w, part); break;
-            default: wgram_launch_g<TX, 4>(c, nb, vec, n, K, X, ld, w, part); break;
+            case 1: wgram_launch_g<TX, 1, NU>(c, nb, vec, n, K, X, ld, w, eps2, part, max_blocks); break;
+            case 2: wgram_launch_g<TX, 2, NU>(c, nb, vec, n, K, X, ld, w, eps2, part, max_blocks); break;
+            case 3: wgram_launch_g<TX, 3, NU>(c, nb, vec, n, K, X, ld, w, eps2, part, max_blocks); break;
+            default: wgram_launch_g<TX, 4, NU>(c, nb, vec, n, K, X, ld, w, eps2, part, max_blocks); break;
         }
         MMOF_LAUNCH_CHECK();
     }
@@ -874,8 +899,64 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
                        nb, K, Gb, part, G, ldg);
     MMOF_LAUNCH_CHECK();
 }
+
+template <class TX>
+void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg) {
+    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    double* part =
+        static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * GRAM_PAIRS * 256));
+    wgram_stages<TX, false>(c, n, K, X, ld, w, 0.0, G, ldg, part, GRAM_BLOCKS, true);
+}
 template void wgram<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int);
 template void wgram<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double*, int);
+
+// ------------------------------------------------------------------------ allocation-free Gram
+//
+// The Gram of a column block for callers that cannot allocate device memory: the stage-1
+// partials live in this file-scope array, one copy per GPU (its address on each device is
+// looked up once, at context creation, with hipGetSymbolAddress; the host-side name of the
+// array is never passed to a kernel), and the MM weights are formed inside the kernel from nu
+// instead of in an n-entry buffer.  Every call on one GPU uses the same array: calls that
+// overlap in time on one device (several streams, several host threads) race on it.
+static constexpr int NOALLOC_BLOCKS = 256;   // at most 256 stage-1 workgroups
+static constexpr size_t NOALLOC_DOUBLES = (size_t)NOALLOC_BLOCKS * GRAM_PAIRS * 256;   // 5 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+static constexpr int NOALLOC_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+void noalloc_init(int device) {
+    MMOF_CHECK(device >= 0 && device < NOALLOC_MAX_DEV, MMOF_ERR_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    int cur = -1;
+    MMOF_HIP(hipGetDevice(&cur));
+    MMOF_CHECK(cur == device, MMOF_ERR_INVALID, "scratch lookup needs the device current");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    MMOF_CHECK(e == hipSuccess && ptr, MMOF_ERR_HIP,
+               std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+}
+
+size_t noalloc_scratch_bytes() { return sizeof(double) * NOALLOC_DOUBLES; }
+
+template <class TX>
+void wgram_noalloc(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TX* nu, double eps, double* G,
+                   int ldg) {
+    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    MMOF_CHECK(c.device >= 0 && c.device < NOALLOC_MAX_DEV && g_scratch_ptr[c.device], MMOF_ERR_INVALID,
+               "the context was created without the scratch lookup");
+    double* part = g_scratch_ptr[c.device];
+    if (nu)
+        wgram_stages<TX, true>(c, n, K, X, ld, nu, eps * eps, G, ldg, part, NOALLOC_BLOCKS, false);
+    else
+        wgram_stages<TX, false>(c, n, K, X, ld, nullptr, 0.0, G, ldg, part, NOALLOC_BLOCKS, false);
+}
+template void wgram_noalloc<float>(Ctx&, int64_t, int, const float*, int64_t, const float*, double, double*, int);
+template void wgram_noalloc<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double, double*,
+                                    int);
 
 template <class TI, class TO>
 void convert(Ctx& c, int64_t n, const TI* in, TO* out) {

@@ -42,6 +42,13 @@ void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w);
 // G (K x K, leading dim ldg) = X^T diag(w) X   (w == null: unweighted), FP64 on the matrix cores
 template <class TX>
 void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg);
+// The same Gram without device allocation: weights formed in the kernel from nu (null: 1),
+// partials in a file-scope device array (noalloc_scratch_bytes() of it) whose address on the
+// device was looked up by noalloc_init(device) with that device current.
+void noalloc_init(int device);
+size_t noalloc_scratch_bytes();
+template <class TX>
+void wgram_noalloc(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TX* nu, double eps, double* G, int ldg);
 template <class TI, class TO>
 void convert(Ctx& c, int64_t n, const TI* in, TO* out);
 void normalize(Ctx& c, int64_t n, const double* x, const double* nrm, double thr, double* out);
