@@ -266,7 +266,7 @@ int mmof_reverse_flow(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, cons
 
 typedef struct {
     int32_t ell;          /* Golub-Kahan start dimension (paper: 10)                     */
-    int32_t k_max;        /* outer MM iterations (ell + k_max - 1 <= 64)                 */
+    int32_t k_max;        /* outer MM iterations (ell + k_max - 1 <= 256)                */
     int32_t tau;          /* flow update when k % tau == 0                               */
     int32_t n_sweeps;     /* Horn-Schunck sweeps per flow update                          */
     int32_t delta_r;      /* derivative box radius                                        */
@@ -335,7 +335,9 @@ void mmof_solve_defaults(mmof_solve_params* p);
  * P Theta V, eq. QR):  G = X^T diag(w2) X with w2 = 1/sqrt(nu^2 + eps^2) (nu NULL: w2 = 1).
  * X: device, K columns of length n in dtype dt, column j at X + j*ld; nu: device, n entries
  * of dtype dt or NULL.  G: device FP64, K x K row-major with leading dimension ldg.
- * 1 <= K <= 64.  Accumulation is FP64 on the matrix cores. */
+ * 1 <= K <= 256 (the paper runs up to 200 iterations from ell = 10 start vectors, Sec. 5).
+ * Accumulation is FP64 on the matrix cores; every entry is the sum over all n rows in a
+ * fixed order (run to run reproducible), and G is exactly symmetric. */
 int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
                        const void* nu, double eps, double* G, int32_t ldg);
 
@@ -354,7 +356,8 @@ int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K
 
 /* Projected solve of MMGKS (eq. minKryov2) with the discrepancy principle (Sec. 4.1.3):
  * (G_H + lambda G_T) z = d, lambda such that ||b||^2 - d^T z - lambda z^T G_T z = target.
- * GA, GT: device FP64 K x K (leading dimension 64); d: device FP64 [K];
+ * 1 <= K <= 256.  GA, GT: device FP64 K x K (leading dimension 256, symmetric; only the first
+ * K rows and columns are read); d: device FP64 [K];
  * sc: device FP64 {||b||^2, target = (eta delta)^2, previous lambda or 0};
  * fixed_lambda > 0 skips the root search.  Writes z (device FP64 [K]) and
  * res (device FP64 [4]) = {lambda, discrepancy^2, status 0 root / 2 clamped / 4 failure,

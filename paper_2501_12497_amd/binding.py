@@ -20,6 +20,8 @@ from . import _lib
 from ._lib import check
 
 _DT = {torch.float32: _lib.MMOF_F32, torch.float64: _lib.MMOF_F64}
+# largest Krylov basis of a solve and leading dimension of the projected matrices
+KRYLOV_MAX = 256
 
 # Library objects still alive at interpreter exit are released while the HIP runtime is
 # still up (plans before contexts); later finalizers then do nothing.
@@ -418,7 +420,9 @@ def projected_solve(GA: torch.Tensor, GT: torch.Tensor, d: torch.Tensor, bnorm2:
     """(G_H + lambda G_T) z = d with lambda from the discrepancy principle; returns (z, lambda, D^2, status)."""
     ctx = ctx or context()
     K = d.numel()
-    pad = lambda M: torch.nn.functional.pad(M.to(torch.float64), (0, 64 - K, 0, 64 - K)).contiguous()
+    if not 1 <= K <= KRYLOV_MAX:
+        raise ValueError(f"K must be in [1, {KRYLOV_MAX}] (got {K})")
+    pad = lambda M: torch.nn.functional.pad(M.to(torch.float64), (0, KRYLOV_MAX - K, 0, KRYLOV_MAX - K)).contiguous()
     A64, T64 = pad(GA), pad(GT)
     sc = torch.tensor([bnorm2, target, prev_lambda], dtype=torch.float64, device=d.device)
     z = torch.empty(K, dtype=torch.float64, device=d.device)

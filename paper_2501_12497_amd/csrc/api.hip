@@ -484,7 +484,7 @@ int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const 
         need_dt(dt);
         need(X, "X");
         need(G, "G");
-        MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX_SMALL && ld >= n && ldg >= K, MMOF_ERR_SHAPE, "bad Gram sizes");
+        MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX && ld >= n && ldg >= K, MMOF_ERR_SHAPE, "bad Gram sizes");
         MMOF_CHECK(!nu || eps > 0, MMOF_ERR_INVALID, "eps must be > 0");
         double* w = nullptr;
         if (nu) {

@@ -227,7 +227,7 @@ template <class TX>
 __global__ __launch_bounds__(KB) void k_gemv_cols(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                                   const double* __restrict__ h, double alpha, double beta,
                                                   double* __restrict__ out) {
-    __shared__ double sh[KMAX_SMALL];
+    __shared__ double sh[KMAX];
     for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* _
                                                    const double* __restrict__ h, double alpha, const double* y,
                                                    double beta, double* out_d, TO* __restrict__ out_t,
                                                    const double* __restrict__ cv, double* __restrict__ part) {
-    __shared__ double sh[KMAX_SMALL];
+    __shared__ double sh[KMAX];
     __shared__ double s4[4];
     for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
     __syncthreads();
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(KB) void k_gemv_fused2(int64_t n, int K, const TX* 
                                                     const double* __restrict__ h, double alpha, const double* y,
                                                     double beta, double* out_d, TO* __restrict__ out_t,
                                                     const double* __restrict__ cv, double* __restrict__ part) {
-    __shared__ double sh[KMAX_SMALL];
+    __shared__ double sh[KMAX];
     __shared__ double s4[4];
     for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
     __syncthreads();
@@ -578,6 +578,97 @@ __global__ __launch_bounds__(1024) void k_wgram_final(int nb, int K, int G, cons
     }
 }
 
+// Off-diagonal tile of a Gram with more than 64 columns: G[I][J] for the column blocks
+// I = i0 .. i0 + GI - 1 of XI and J = j0 .. j0 + GJ - 1 of XJ (XI, XJ point at the first
+// column of each tile; KI, KJ columns are valid), every block pair (gi, gj) on the matrix
+// cores as in k_wgram_part; part[b][gi * GJ + gj][256] receives workgroup b's sums.
+static constexpr int GRAM_RECT = 4;   // column blocks per side of an off-diagonal tile
+
+template <class TX, int GI, int GJ, bool VEC, int W>
+__global__ __launch_bounds__(64 * W) void k_wgram_rect(int64_t n, int KI, int KJ, const TX* __restrict__ XI,
+                                                       const TX* __restrict__ XJ, int64_t ld,
+                                                       const double* __restrict__ w, double* __restrict__ part) {
+    constexpr int NP = GI * GJ;
+    __shared__ double sred[W][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    dbl4 acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int64_t steps = (n + 15) / 16;
+    const int64_t nw = (int64_t)gridDim.x * W;
+    const int64_t gw = (int64_t)blockIdx.x * W + wave;
+    const int64_t s_lo = steps * gw / nw, s_hi = steps * (gw + 1) / nw;
+    GramRows<TX, GI> ci, ni;
+    GramRows<TX, GJ> cj, nj;
+    if (s_lo < s_hi) {
+        gram_rows<TX, GI, VEC>(ci, XI, ld, nullptr, n, KI, 16 * s_lo, lane);
+        gram_rows<TX, GJ, VEC>(cj, XJ, ld, w, n, KJ, 16 * s_lo, lane);
+    }
+    for (int64_t st = s_lo; st < s_hi; ++st) {
+        if (st + 1 < s_hi) {
+            gram_rows<TX, GI, VEC>(ni, XI, ld, nullptr, n, KI, 16 * (st + 1), lane);
+            gram_rows<TX, GJ, VEC>(nj, XJ, ld, w, n, KJ, 16 * (st + 1), lane);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double a[GI], bw[GJ];
+#pragma unroll
+            for (int g = 0; g < GI; ++g) a[g] = (double)ci.x[g][k];
+#pragma unroll
+            for (int g = 0; g < GJ; ++g) bw[g] = (double)cj.x[g][k] * cj.w[k];
+#pragma unroll
+            for (int gi = 0; gi < GI; ++gi)
+#pragma unroll
+                for (int gj = 0; gj < GJ; ++gj)
+                    acc[gi * GJ + gj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[gi], bw[gj], acc[gi * GJ + gj], 0, 0, 0);
+        }
+        ci = ni;
+        cj = nj;
+    }
+    double* out = part + (int64_t)blockIdx.x * (NP * 256);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sred[wave][v * 64 + lane] = acc[p][v];
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) sum += sred[q][threadIdx.x];
+            out[p * 256 + threadIdx.x] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// Stage 2 of an off-diagonal tile: entry e = (pair gi * GJ + gj, register slot) summed over the
+// partials in a fixed order; G[i][j] and G[j][i] (i in the I tile, j in the J tile) written.
+__global__ __launch_bounds__(1024) void k_wgram_final_rect(int nb, int GJ, int np, int KI, int KJ, int i0, int j0,
+                                                           const double* __restrict__ part, double* __restrict__ Gm,
+                                                           int ldg) {
+    __shared__ double s[16][GRAM_SLAB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = blockIdx.x * GRAM_SLAB + lane;
+    double acc = 0.0;
+    if (e < np * 256)
+        for (int b = wave; b < nb; b += 16) acc += part[(int64_t)b * (np * 256) + e];
+    s[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0 || e >= np * 256) return;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sum += s[q][lane];
+    const int p = e >> 8, slot = e & 255, v = slot >> 6, l = slot & 63;
+    const int gi = p / GJ, gj = p % GJ;
+    const int ri = 16 * gi + (l >> 4) + 4 * v, cj = 16 * gj + (l & 15);
+    if (ri < KI && cj < KJ) {
+        const int i = i0 + ri, j = j0 + cj;
+        Gm[(int64_t)i * ldg + j] = sum;
+        Gm[(int64_t)j * ldg + i] = sum;
+    }
+}
+
+
 // Scale x by 1/s[0] when s[0] > thr, else leave a zero column; s holds ||x||.
 __global__ void k_normalize(int64_t n, const double* __restrict__ x, const double* __restrict__ nrm, double thr,
                             double* __restrict__ out) {
@@ -710,8 +801,8 @@ template <class TX, class TY>
 void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double alpha, double* out) {
     if (K <= 0) return;
     const int nb = mdot_blocks(n);
-    MMOF_CHECK(K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for a block inner product");
-    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
+    MMOF_CHECK(K <= KMAX, MMOF_ERR_SHAPE, "too many columns for a block inner product");
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX + 1)));
     {
         ScopedTime st(&c, "mdot", (double)n * ((double)sizeof(TX) * K + sizeof(TY)), 2.0 * n * K);
         if (mdot_pairs(X, ld, y, nullptr))
@@ -732,10 +823,10 @@ template void mdot<float, float>(Ctx&, int64_t, int, const float*, int64_t, cons
 
 void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const double* h, const double* x, double* y,
                double* hout) {
-    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for a block inner product");
+    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many columns for the fused CGS pass");
     // chunks of 256 rows (4 steps of the workgroup), at most MAX_PART partials
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, cdiv(n, 256)));
-    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX + 1)));
     {
         ScopedTime st(&c, "gemv_mdot", (double)n * (8.0 * K + 16.0), 4.0 * n * K);
         auto k = K <= 16 ? k_gemv_mdot<4> : K <= 32 ? k_gemv_mdot<8> : K <= 48 ? k_gemv_mdot<12> : k_gemv_mdot<16>;
@@ -749,9 +840,9 @@ void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const doub
 
 template <class TX>
 void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e, double* G, int ldg, double* dj) {
-    MMOF_CHECK(j >= 0 && j < KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    MMOF_CHECK(j >= 0 && j < KMAX, MMOF_ERR_SHAPE, "too many Krylov columns");
     const int nb = mdot_blocks(n);
-    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX_SMALL + 1)));
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX + 1)));
     const TX* xj = X + (int64_t)j * ld;
     if (mdot_pairs(X, ld, xj, e))
         hipLaunchKernelGGL((k_mdot2<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1,
@@ -770,7 +861,7 @@ template void gram_row<double>(Ctx&, int64_t, int, const double*, int64_t, const
 template <class TX, class TO>
 void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, const double* y,
                 double beta, double* out_d, TO* out_t, const double* cv, double* sq) {
-    MMOF_CHECK(K >= 0 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    MMOF_CHECK(K >= 0 && K <= KMAX, MMOF_ERR_SHAPE, "too many Krylov columns");
     if (n == 0) {
         if (sq) set_scalar(c, sq, 0.0);
         return;
@@ -825,7 +916,7 @@ template void axpy_conv<double>(Ctx&, int64_t, const double*, const double*, con
 template <class TX>
 void gemv_cols(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, double beta,
                double* out) {
-    MMOF_CHECK(K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
+    MMOF_CHECK(K <= KMAX, MMOF_ERR_SHAPE, "too many Krylov columns");
     if (K <= 0) {
         if (beta != 1.0) {
             hipLaunchKernelGGL(k_axpby, grid_for(n, KB, 8192), dim3(KB), 0, c.stream, n, beta, (const double*)out,
@@ -902,10 +993,46 @@ static void wgram_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, cons
 
 template <class TX>
 void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg) {
-    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns");
-    double* part =
-        static_cast<double*>(c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * GRAM_PAIRS * 256));
-    wgram_stages<TX, false>(c, n, K, X, ld, w, 0.0, G, ldg, part, GRAM_BLOCKS, true);
+    MMOF_CHECK(K >= 1 && K <= KMAX, MMOF_ERR_SHAPE, "too many Krylov columns");
+    constexpr int RP = GRAM_RECT * GRAM_RECT;
+    double* part = static_cast<double*>(
+        c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * std::max(GRAM_PAIRS, RP) * 256));
+    if (K <= 64) {
+        wgram_stages<TX, false>(c, n, K, X, ld, w, 0.0, G, ldg, part, GRAM_BLOCKS, true);
+        return;
+    }
+    // more than 64 columns: tiles of 64 x 64 entries -- the diagonal tiles by the kernel above,
+    // the tiles above them by k_wgram_rect, one partial buffer reused tile after tile (stream order)
+    const int nsb = (K + 63) / 64;
+    const bool vec = sizeof(TX) == 4 && (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                     (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
+    for (int a = 0; a < nsb; ++a) {
+        const int Ka = std::min(64, K - 64 * a);
+        wgram_stages<TX, false>(c, n, Ka, X + (int64_t)64 * a * ld, ld, w, 0.0, G + (int64_t)64 * a * ldg + 64 * a,
+                                ldg, part, GRAM_BLOCKS, true);
+        for (int b2 = a + 1; b2 < nsb; ++b2) {
+            const int Kb = std::min(64, K - 64 * b2);
+            constexpr int W = sizeof(TX) == 4 ? 8 : 4;   // (FP64 rows need twice the registers)
+            const int64_t steps = (n + 15) / 16;
+            const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_BLOCKS, cdiv(steps, 16 * W)));
+            const TX* XI = X + (int64_t)64 * a * ld;
+            const TX* XJ = X + (int64_t)64 * b2 * ld;
+            {
+                ScopedTime st(&c, "wgram", (double)n * ((double)sizeof(TX) * (Ka + Kb) + 8.0),
+                              2.0 * (double)n * Ka * Kb);
+                if (vec)
+                    hipLaunchKernelGGL((k_wgram_rect<TX, GRAM_RECT, GRAM_RECT, sizeof(TX) == 4, W>), dim3(nb),
+                                       dim3(64 * W), 0, c.stream, n, Ka, Kb, XI, XJ, ld, w, part);
+                else
+                    hipLaunchKernelGGL((k_wgram_rect<TX, GRAM_RECT, GRAM_RECT, false, W>), dim3(nb), dim3(64 * W),
+                                       0, c.stream, n, Ka, Kb, XI, XJ, ld, w, part);
+                MMOF_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_wgram_final_rect, dim3((unsigned)cdiv((int64_t)RP * 256, GRAM_SLAB)), dim3(1024), 0,
+                               c.stream, nb, GRAM_RECT, RP, Ka, Kb, 64 * a, 64 * b2, (const double*)part, G, ldg);
+            MMOF_LAUNCH_CHECK();
+        }
+    }
 }
 template void wgram<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int);
 template void wgram<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double*, int);

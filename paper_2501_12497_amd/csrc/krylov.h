@@ -5,7 +5,10 @@
 
 namespace mmof {
 
-static constexpr int KMAX_SMALL = 64;  // largest Krylov basis handled by the small solve
+static constexpr int KMAX = 256;        // largest Krylov basis (columns of V)
+static constexpr int KLD = 256;         // leading dimension of the projected matrices G_H, G_T
+static constexpr int KMAX_SMALL = 64;   // largest basis of the one-wave projected solve (and of
+                                        // the allocation-free Gram)
 
 // out[j] = alpha * X_j^T y for j < K (X column-major [K][ld]); one launch.
 template <class TX, class TY>
@@ -71,7 +74,8 @@ void put_rowcol(Ctx& c, double* G, int ldg, int j, const double* h);
 template <class TX>
 void weight_mul(Ctx& c, int64_t n, const double* w, const TX* x, TX* y);
 
-// Small projected solve (one wavefront).  Inputs on the device: GA, GT (K x K, ld KMAX_SMALL),
+// Small projected solve (one wavefront for K <= 64, four above).  Inputs on the device: GA, GT
+// (K x K, leading dimension KLD),
 // d (K), and the scalars bb = ||b||^2 and target = (eta*delta)^2 in sc[0..1].
 // Writes z (K), and res[0] = lambda, res[1] = discrepancy^2, res[2] = status (0 root, 2 clamped,
 // 4 factorization failure), res[3] = factorizations done.  fixed_lambda > 0 skips the

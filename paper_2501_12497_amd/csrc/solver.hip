@@ -120,7 +120,7 @@ struct Solver {
         U = ws<double>("U", (int64_t)(p.ell + 1) * m);
         r = ws<double>("r", n);
         tmp_m = ws<double>("tmp_m", m);
-        h = ws<double>("h", KMAX_SMALL);
+        h = ws<double>("h", KMAX);
         sc = ws<double>("sc", 8);
         scal = ws<double>("scal", 24);
         vin_n = wsx("vin_n", n);
@@ -130,10 +130,10 @@ struct Solver {
         fill_zero<double>(c, 24, scal);
         if (!full) return;
         tmp_n = ws<double>("tmp_n", n);
-        GA = ws<double>("GA", KMAX_SMALL * KMAX_SMALL);
-        GT = ws<double>("GT", KMAX_SMALL * KMAX_SMALL);
-        dvec = ws<double>("dvec", KMAX_SMALL);
-        z = ws<double>("z", KMAX_SMALL);
+        GA = ws<double>("GA", KLD * KLD);
+        GT = ws<double>("GT", KLD * KLD);
+        dvec = ws<double>("dvec", KMAX);
+        z = ws<double>("z", KMAX);
         res = ws<double>("res", 8);
         AV = wsx("AV", (int64_t)Kcap * m);
         TV = wsx("TV", (int64_t)Kcap * R);
@@ -291,7 +291,13 @@ struct Solver {
         // h = Q^T x; y = x - Q h and h = Q^T y in one pass over Q; x = y - Q h with ||x||^2
         double* y = static_cast<double*>(c.work("reorth_y", sizeof(double) * (size_t)std::max<int64_t>(len, 1)));
         mdot<double, double>(c, len, k, Q, len, x, 1.0, h);
-        gemv_mdot(c, len, k, Q, len, h, x, y, h);
+        if (k <= KMAX_SMALL) {
+            gemv_mdot(c, len, k, Q, len, h, x, y, h);
+        } else {
+            // (beyond the fused pass's register budget: the two steps as separate passes)
+            gemv_fused<double, double>(c, len, k, Q, len, h, -1.0, x, 1.0, y, nullptr, nullptr, nullptr);
+            mdot<double, double>(c, len, k, Q, len, y, 1.0, h);
+        }
         gemv_fused<double, double>(c, len, k, Q, len, h, -1.0, y, 1.0, x, nullptr, nullptr, sq);
     }
 
@@ -301,7 +307,7 @@ struct Solver {
         if (!have_vin) convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
         TX* avj = AV + (int64_t)j * m;
         A(vin_n, avj);
-        gram_row<TX>(c, m, j, AV, m, b, GA, KMAX_SMALL, dvec + j);
+        gram_row<TX>(c, m, j, AV, m, b, GA, KLD, dvec + j);
         theta(vin_n, TV + (int64_t)j * R);
     }
 
@@ -312,15 +318,12 @@ struct Solver {
     void dump_projected(int K) {
         const char* path = std::getenv("MMOF_DUMP_PROJECTED");
         if (!path) return;
-        std::vector<double> buf(2 * KMAX_SMALL * KMAX_SMALL + KMAX_SMALL + 8);
+        std::vector<double> buf(2 * KLD * KLD + KMAX + 8);
         (void)hipStreamSynchronize(c.stream);
-        (void)hipMemcpy(buf.data(), GA, sizeof(double) * KMAX_SMALL * KMAX_SMALL, hipMemcpyDeviceToHost);
-        (void)hipMemcpy(buf.data() + KMAX_SMALL * KMAX_SMALL, GT, sizeof(double) * KMAX_SMALL * KMAX_SMALL,
-                        hipMemcpyDeviceToHost);
-        (void)hipMemcpy(buf.data() + 2 * KMAX_SMALL * KMAX_SMALL, dvec, sizeof(double) * KMAX_SMALL,
-                        hipMemcpyDeviceToHost);
-        (void)hipMemcpy(buf.data() + 2 * KMAX_SMALL * KMAX_SMALL + KMAX_SMALL, sc, sizeof(double) * 3,
-                        hipMemcpyDeviceToHost);
+        (void)hipMemcpy(buf.data(), GA, sizeof(double) * KLD * KLD, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(buf.data() + KLD * KLD, GT, sizeof(double) * KLD * KLD, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(buf.data() + 2 * KLD * KLD, dvec, sizeof(double) * KMAX, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(buf.data() + 2 * KLD * KLD + KMAX, sc, sizeof(double) * 3, hipMemcpyDeviceToHost);
         if (FILE* f = std::fopen(path, "wb")) {
             const double kk = K;
             std::fwrite(&kk, sizeof(double), 1, f);
@@ -331,8 +334,8 @@ struct Solver {
 
     PhaseOut run(const double* b_, double delta, double* u_io, void* v_out, void* vr_out, const Phase& ph) {
         b = b_;
-        MMOF_CHECK(Kcap >= 1 && Kcap <= KMAX_SMALL, MMOF_ERR_SHAPE,
-                   "ell + k_max - 1 must be in [1, " + std::to_string(KMAX_SMALL) + "]");
+        MMOF_CHECK(Kcap >= 1 && Kcap <= KMAX, MMOF_ERR_SHAPE,
+                   "ell + k_max - 1 must be in [1, " + std::to_string(KMAX) + "]");
         MMOF_CHECK(p.ell >= 1 && p.k_max >= 1 && p.tau >= 1, MMOF_ERR_INVALID, "ell, k_max, tau must be >= 1");
         MMOF_CHECK(!flow || p.n_sweeps >= 0, MMOF_ERR_INVALID, "n_sweeps must be >= 0");
         MMOF_CHECK(p.eps > 0 && p.alpha > 0 && p.eta > 0, MMOF_ERR_INVALID, "eps, alpha, eta must be > 0");
@@ -454,7 +457,7 @@ struct Solver {
                 // 2. nu = Theta u^(k); FP64 weights; weighted Gram of Theta V
                 if (!nu_fresh) theta(u_op, nu);
                 mm_weights_f64<TX>(c, R, nu, p.eps, w2);
-                wgram<TX>(c, R, K, TV, R, w2, GT, KMAX_SMALL);
+                wgram<TX>(c, R, K, TV, R, w2, GT, KLD);
                 // 3-5. lambda (discrepancy principle) and z; lambda is kept in sc[2] as the next warm start
                 small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
             }
@@ -493,7 +496,7 @@ struct Solver {
                 add_column(K, true);
                 if (!nu_fresh) theta(u_op, nu);
                 mm_weights_f64<TX>(c, R, nu, p.eps, w2);
-                wgram<TX>(c, R, K + 1, TV, R, w2, GT, KMAX_SMALL);
+                wgram<TX>(c, R, K + 1, TV, R, w2, GT, KLD);
                 small_solve(c, K + 1, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
             }
             // counts of work queued ahead, taken back if the iteration ends the solve

@@ -10,6 +10,7 @@ from .workloads import (  # noqa: F401
     angle_schedule,
     angles_shifted,
     cfg_disk32,
+    cfg_krylov210,
     cfg_ellipse128,
     cfg_blur_ragged,
     cfg_autograd256,

@@ -235,6 +235,23 @@ def cfg_disk32() -> Workload:
                          delta_r=1, op_dtype="f64"))
 
 
+def cfg_krylov210() -> Workload:
+    """20x20 x 3 frames; disk of radius sqrt(20) (value 1 on 0) translating +1 px/frame in x;
+    8 angles over [0,pi) offset 5 deg/frame, 29 bins; noise 2% (seed 3).  Solved with the
+    paper's iteration budget (Sec. 5): ell = 10 start vectors and 201 MM iterations, so the
+    last projected problem has 210 columns, flow every 20 iterations."""
+    n, n_t = 20, 3
+    x, y = _pixel_grid(n, n)
+    u = np.stack([(((x - (6.0 + t)) ** 2 + (y - 10.0) ** 2) <= 20.0).astype(np.float64) for t in range(n_t)])
+    ang = angles_shifted(n_t, 8, math.radians(5.0))
+    nb = bins_for(n)
+    g = np.random.default_rng(3).standard_normal((n_t, 8, nb))
+    seq = Sequence(u_true=u, angles=ang, n_bins=nb, noise_g=g, velocity=np.array([[1.0, 0.0]]))
+    return Workload("krylov210x20x20x3", "radon", [seq], 0.02,
+                    dict(alpha=0.2, k_max=201, tau=20, ell=10, n_sweeps=20, eps=1e-3, eta=1.01,
+                         delta_r=1, op_dtype="f64"))
+
+
 def cfg_ellipse128(seed: int = 2) -> Workload:
     """128x128 x 16; 3 ellipses (semi-axes 8-30 px, values U[0.3,1]) translating with
     integer velocities in [-2,2]; 30 angles/frame rotated 6 deg/frame; 181 bins; 2% noise."""

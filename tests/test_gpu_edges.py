@@ -4,7 +4,8 @@
   a moving sequence;
 * noise-free data (delta = 0): the discrepancy equation has no root above the lower end of
   the lambda bracket, which is taken with the clamped status;
-* the largest Krylov basis the projected solve holds (ell + k_max - 1 = 64);
+* the largest basis of the one-wave projected solve (ell + k_max - 1 = 64), and the paper's
+  iteration budget (210 columns: the multi-wave solve and the tiled Gram);
 * stacks the library must refuse (no sequences, a frame side above 65535, a single
   pixel row) and flow operators on a stack without frame pairs.
 """
@@ -87,6 +88,37 @@ def test_largest_krylov_basis():
     assert res.n_cols == ref.n_cols == 64
     assert abs(res.rre[-1] - ref.rre[-1]) <= 1e-6
     np.testing.assert_allclose(res.lambdas, ref.lambdas, rtol=1e-5)
+
+
+def test_paper_iteration_budget_210_columns():
+    """The paper's iteration budget (Sec. 5: ell = 10, up to 200 MM iterations, flow every 20):
+    201 iterations, so the last projected problems have up to 210 columns -- the Gram tiles
+    beyond 64 columns, the four-wave projected solve and the two-pass CGS2 all run.  Against the
+    oracle's stored run (tests/golden/krylov210.json, written by make_krylov210.py from the
+    oracle alone): the lambda of every iteration, the RRE trajectory and the final u."""
+    import json
+    import os
+    import torch
+    from paper_2501_12497_amd import binding as B
+    from synth import cfg_krylov210, noisy
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "krylov210.json")))
+    wl = cfg_krylov210()
+    s = wl.seqs[0]
+    g = mmgks.SeqGeom(s.n_t, s.ny, s.nx, s.angles, s.n_bins)
+    clean = mmgks.StackOps([g], "radon").A(s.u_true.ravel())
+    b = noisy(clean, s.noise_g, wl.noise_level)
+    delta = float(np.linalg.norm(b - clean))
+    plan = _gpu_plan(B, [g], [s.angles])
+    prm = dict(G["params"])
+    print("krylov210: solve ell 10, 201 iterations", flush=True)
+    res = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta,
+                        u_true=torch.as_tensor(s.u_true.ravel(), device="cuda"), op_dtype="f64", **prm)
+    assert res.iters == G["iters"] == 201
+    assert res.n_cols == G["n_cols"] == 210
+    assert res.dp_status == G["dp_status"]
+    np.testing.assert_allclose(res.lambdas, G["lambdas"], rtol=1e-6)
+    np.testing.assert_allclose(res.rre, G["rre"], rtol=0, atol=1e-7)
+    assert_close(res.u.cpu().numpy(), np.asarray(G["u"]), 1e-6)
 
 
 def test_refused_stacks():

@@ -1,7 +1,9 @@
 """GPU parity of the projected-problem steps of MMGKS (FP64 Krylov side) at every basis size.
 
-* weighted Gram X^T diag(w2) X on the matrix cores vs numpy, K = 1..64 (all block-grid shapes);
-* projected solve + discrepancy principle vs the oracle's bisection on the same Grams.
+* weighted Gram X^T diag(w2) X on the matrix cores vs numpy, K = 1..256 (all block-grid shapes,
+  the 64-column tiles beyond 64 and a ragged last tile);
+* projected solve + discrepancy principle vs the oracle's bisection on the same Grams, on the
+  one-wave path (K <= 64) and the multi-wave path (up to 256).
 """
 import numpy as np
 import pytest
@@ -18,13 +20,13 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("K", [1, 5, 16, 17, 31, 33, 40, 48, 63, 64])
+@pytest.mark.parametrize("K", [1, 5, 16, 17, 31, 33, 40, 48, 63, 64, 65, 97, 130, 210, 256])
 @pytest.mark.parametrize("which", ["f64", "f32"])
 def test_weighted_gram(B, K, which):
     import torch
     dt = torch.float64 if which == "f64" else torch.float32
     r = np.random.default_rng(K)
-    n = 50000 + 37 * K
+    n = (50000 if K <= 64 else 20000) + 37 * K
     X = r.standard_normal((K, n))
     nu = r.standard_normal(n) * np.logspace(-4, 0, n)
     if dt == torch.float32:
@@ -39,7 +41,7 @@ def test_weighted_gram(B, K, which):
     assert np.abs(G1 - X @ X.T).max() <= 1e-12 * np.abs(X @ X.T).max()
 
 
-@pytest.mark.parametrize("K", [3, 20, 39, 64])
+@pytest.mark.parametrize("K", [3, 20, 39, 64, 65, 100, 131, 210, 256])
 def test_projected_solve_matches_oracle_dp(B, K):
     import torch
     r = np.random.default_rng(100 + K)
@@ -69,3 +71,15 @@ def test_projected_solve_matches_oracle_dp(B, K):
     assert st == 2
     z, lam, D2, st = B.projected_solve(dev(GA), dev(GT), dev(d), bb, (10 * hi_d) ** 2)
     assert st == 2
+
+
+def test_weighted_gram_is_symmetric_and_rejects_more_than_256_columns(B):
+    import torch
+    from paper_2501_12497_amd._lib import MMOFError
+    r = np.random.default_rng(5)
+    X = torch.as_tensor(r.standard_normal((150, 3001)), device="cuda")
+    G = B.weighted_gram(X, torch.as_tensor(r.standard_normal(3001), device="cuda")).cpu().numpy()
+    assert np.array_equal(G, G.T)
+    with pytest.raises(MMOFError) as e:
+        B.weighted_gram(torch.zeros((257, 10), dtype=torch.float64, device="cuda"))
+    assert e.value.code == -2

@@ -194,7 +194,7 @@ def test_solve_rejects_bad_arguments(B):
     plan = B.plan_radon(B.Stack.single(g.n_t, g.ny, g.nx), [ang.shape[1]], [nb], ang.ravel())
     b = torch.zeros(plan.m, dtype=torch.float64, device="cuda")
     with pytest.raises(MMOFError) as e:
-        B.solve_joint(plan, b, 0.1, ell=10, k_max=60)   # basis larger than the small solve holds
+        B.solve_joint(plan, b, 0.1, ell=10, k_max=248)   # basis of 257 columns: above the capacity
     assert e.value.code == -2
     with pytest.raises(MMOFError) as e:
         B.solve_joint(plan, b, 0.1, eps=-1.0)
