@@ -354,6 +354,23 @@ int mmof_weighted_gram(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const 
 int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X,
                                int64_t ld, const void* nu, double eps, double* G, int32_t ldg);
 
+/* The passes over the Krylov basis of a GKS step (Alg. 1), exported so they can be checked on
+ * their own at full length.  X, Q: device, K columns of length n, column j at X + j*ld
+ * (1 <= K <= 256, ld >= n; 64-bit offsets, so K*ld may exceed 2^31); accumulation in FP64.
+ *   mmof_block_dot:     out[j] = X_j^T y (X in dt, y device FP64 [n], out device FP64 [K]);
+ *                       each inner product summed over row chunks in a fixed order.
+ *   mmof_block_combine: out = alpha X z + beta y (z device FP64 [K]; y device FP64 [n] or
+ *                       NULL, may alias out; out device FP64 [n]) -- u = V z and the CGS updates.
+ *   mmof_cgs2:          x <- x - Q (Q^T x), twice (classical Gram-Schmidt with one
+ *                       reorthogonalisation, the residual step of Alg. 1), Q FP64, x device FP64
+ *                       [n] in/out; sq device FP64 [1] receives ||x||^2 afterwards.  The
+ *                       context holds two workspace vectors (n and 256 doubles). */
+int mmof_block_dot(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
+                   const double* y, double* out);
+int mmof_block_combine(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
+                       const double* z, double alpha, const double* y, double beta, double* out);
+int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq);
+
 /* Projected solve of MMGKS (eq. minKryov2) with the discrepancy principle (Sec. 4.1.3):
  * (G_H + lambda G_T) z = d, lambda such that ||b||^2 - d^T z - lambda z^T G_T z = target.
  * 1 <= K <= 256.  GA, GT: device FP64 K x K (leading dimension 256, symmetric; only the first

@@ -79,6 +79,9 @@ _SIGS = {
     "mmof_weighted_gram": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_int32]),
     "mmof_weighted_gram_noalloc": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P,
                                         C.c_int32]),
+    "mmof_block_dot": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P]),
+    "mmof_block_combine": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_double, _P]),
+    "mmof_cgs2": (_I, [_P, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P]),
     "mmof_projected_solve": (_I, [_P, C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
     "mmof_profile_kernel": (_I, [_P, C.c_char_p]),
     "mmof_autotune": (_I, [_P, C.c_int32, C.c_char_p, C.c_int32]),

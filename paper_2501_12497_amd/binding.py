@@ -415,6 +415,52 @@ def weighted_gram(X: torch.Tensor, nu: Optional[torch.Tensor] = None, eps: float
     return G
 
 
+def block_dot(X: torch.Tensor, y: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
+    """out[j] = X_j^T y for X of shape [K, n] (float32 or float64) and an FP64 y of n entries."""
+    ctx = ctx or context()
+    K, n = X.shape
+    _need(X, K * n, "X")
+    _need(y, n, "y")
+    if y.dtype != torch.float64:
+        raise TypeError("y must be float64")
+    out = torch.empty(K, dtype=torch.float64, device=X.device)
+    ctx.bind()
+    check(ctx.lib.mmof_block_dot(ctx.h, _dt(X), n, K, _ptr(X), n, _ptr(y), _ptr(out)))
+    return out
+
+
+def block_combine(X: torch.Tensor, z: torch.Tensor, alpha: float = 1.0, y: Optional[torch.Tensor] = None,
+                  beta: float = 0.0, ctx: Optional[Context] = None) -> torch.Tensor:
+    """alpha X^T z + beta y (X of shape [K, n], z FP64 of K entries, y FP64 of n entries or None)."""
+    ctx = ctx or context()
+    K, n = X.shape
+    _need(X, K * n, "X")
+    _need(z, K, "z")
+    if z.dtype != torch.float64 or (y is not None and y.dtype != torch.float64):
+        raise TypeError("z and y must be float64")
+    if y is not None:
+        _need(y, n, "y")
+    out = torch.empty(n, dtype=torch.float64, device=X.device)
+    ctx.bind()
+    check(ctx.lib.mmof_block_combine(ctx.h, _dt(X), n, K, _ptr(X), n, _ptr(z), float(alpha), _ptr(y), float(beta),
+                                     _ptr(out)))
+    return out
+
+
+def cgs2(Q: torch.Tensor, x: torch.Tensor, ctx: Optional[Context] = None) -> float:
+    """x <- x - Q^T (Q x), twice, in place (Q FP64 of shape [K, n]); returns ||x||^2."""
+    ctx = ctx or context()
+    K, n = Q.shape
+    _need(Q, K * n, "Q")
+    _need(x, n, "x")
+    if Q.dtype != torch.float64 or x.dtype != torch.float64:
+        raise TypeError("Q and x must be float64")
+    sq = torch.empty(1, dtype=torch.float64, device=x.device)
+    ctx.bind()
+    check(ctx.lib.mmof_cgs2(ctx.h, n, K, _ptr(Q), n, _ptr(x), _ptr(sq)))
+    return float(sq.item())
+
+
 def projected_solve(GA: torch.Tensor, GT: torch.Tensor, d: torch.Tensor, bnorm2: float, target: float,
                     prev_lambda: float = 0.0, fixed_lambda: float = 0.0, ctx: Optional[Context] = None):
     """(G_H + lambda G_T) z = d with lambda from the discrepancy principle; returns (z, lambda, D^2, status)."""

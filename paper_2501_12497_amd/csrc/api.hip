@@ -519,6 +519,63 @@ int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K
     });
 }
 
+int mmof_block_dot(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld, const double* y,
+                   double* out) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(X, "X");
+        need(y, "y");
+        need(out, "out");
+        MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX && ld >= n, MMOF_ERR_SHAPE, "bad block sizes");
+        if (dt == MMOF_F32)
+            mdot<float, double>(*ctx, n, K, (const float*)X, ld, y, 1.0, out);
+        else
+            mdot<double, double>(*ctx, n, K, (const double*)X, ld, y, 1.0, out);
+        return MMOF_OK;
+    });
+}
+
+int mmof_block_combine(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
+                       const double* z, double alpha, const double* y, double beta, double* out) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(X, "X");
+        need(z, "z");
+        need(out, "out");
+        MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX && ld >= n, MMOF_ERR_SHAPE, "bad block sizes");
+        if (dt == MMOF_F32)
+            gemv_fused<float, float>(*ctx, n, K, (const float*)X, ld, z, alpha, y, beta, out, nullptr, nullptr,
+                                     nullptr);
+        else
+            gemv_fused<double, double>(*ctx, n, K, (const double*)X, ld, z, alpha, y, beta, out, nullptr, nullptr,
+                                       nullptr);
+        return MMOF_OK;
+    });
+}
+
+int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need(Q, "Q");
+        need(x, "x");
+        need(sq, "sq");
+        MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX && ld >= n, MMOF_ERR_SHAPE, "bad block sizes");
+        double* h = static_cast<double*>(ctx->work("cgs2_h", sizeof(double) * KMAX));
+        double* y = static_cast<double*>(ctx->work("cgs2_y", sizeof(double) * (size_t)n));
+        mdot<double, double>(*ctx, n, K, Q, ld, x, 1.0, h);
+        if (K <= KMAX_SMALL) {
+            gemv_mdot(*ctx, n, K, Q, ld, h, x, y, h);
+        } else {
+            gemv_fused<double, double>(*ctx, n, K, Q, ld, h, -1.0, x, 1.0, y, nullptr, nullptr, nullptr);
+            mdot<double, double>(*ctx, n, K, Q, ld, y, 1.0, h);
+        }
+        gemv_fused<double, double>(*ctx, n, K, Q, ld, h, -1.0, y, 1.0, x, nullptr, nullptr, sq);
+        return MMOF_OK;
+    });
+}
+
 int mmof_projected_solve(mmof_ctx ctx, int32_t K, const double* GA, const double* GT, const double* d,
                          const double* sc, double fixed_lambda, double* z, double* res) {
     return guarded(ctx, [&] {

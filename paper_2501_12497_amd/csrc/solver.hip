@@ -580,10 +580,52 @@ struct Solver {
     }
 };
 
+// The Krylov basis (V in FP64; H V and Theta V in each operator precision the solve uses) is
+// the bulk of a solve's memory: refuse before anything is allocated when it cannot fit, and
+// name the largest basis that would (at 1024 x 1024 x 64 a column takes 0.54 GB of V, 1.1 GB
+// of FP32 Theta V and 2.1 GB of FP64 Theta V).
+static void check_solve_capacity(Ctx& c, const Plan& P, const mmof_solve_params& p) {
+    const Geom& g = *P.geom;
+    const bool flow = p.use_flow != 0;
+    const size_t n = (size_t)P.n, m = (size_t)P.m;
+    const size_t R = (size_t)(g.gx_len + g.gy_len + (flow ? g.pair_px : 0) + ((flow && p.use_reverse) ? g.pair_px : 0));
+    const size_t K = (size_t)std::max(1, p.ell + p.k_max - 1);
+    const bool f64 = p.op_dtype == MMOF_F64 || p.refine_iters > 0;
+    const bool f32 = p.op_dtype == MMOF_F32 && p.refine_iters < p.k_max;
+    size_t per_col = sizeof(double) * n;
+    size_t grow = c.work_growth("solve_V", sizeof(double) * K * n);
+    if (f64) {
+        per_col += sizeof(double) * (m + R);
+        grow += c.work_growth("solve_d_AV", sizeof(double) * K * m) + c.work_growth("solve_d_TV", sizeof(double) * K * R);
+    }
+    if (f32) {
+        per_col += sizeof(float) * (m + R);
+        grow += c.work_growth("solve_f_AV", sizeof(float) * K * m) + c.work_growth("solve_f_TV", sizeof(float) * K * R);
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return;  // no estimate: the allocations report any failure themselves
+    }
+    // room for the per-iteration vectors (a few times n and R in FP64) and the flow buffers
+    const size_t reserve = sizeof(double) * 8 * (n + R) + ((size_t)1 << 30);
+    if (grow + reserve <= free_b) return;
+    const size_t avail = free_b > reserve ? free_b - reserve : 0;
+    char msg[512];
+    std::snprintf(msg, sizeof msg,
+                  "the Krylov basis of %zu columns needs %.1f GB more device memory (%.2f GB per column); %.1f GB "
+                  "are free, so at most about %zu columns (ell + k_max - 1) fit",
+                  K, grow / 1e9, per_col / 1e9, free_b / 1e9, avail / std::max<size_t>(per_col, 1));
+    throw Error(MMOF_ERR_OOM, msg);
+}
+
 int solve_joint(Plan& P, const double* b, double delta, const mmof_solve_params& p, double* u_io, void* v_out,
                 void* vr_out, mmof_report* rep) {
     MMOF_CHECK(p.op_dtype == MMOF_F32 || p.op_dtype == MMOF_F64, MMOF_ERR_DTYPE, "op_dtype must be F32 or F64");
     MMOF_CHECK(p.refine_iters >= 0, MMOF_ERR_INVALID, "refine_iters must be >= 0");
+    MMOF_CHECK(p.ell >= 1 && p.k_max >= 1 && p.ell + p.k_max - 1 <= KMAX, MMOF_ERR_SHAPE,
+               "ell + k_max - 1 must be in [1, " + std::to_string(KMAX) + "]");
+    check_solve_capacity(*P.ctx, P, p);
     if (rep) {
         rep->n_A = rep->n_At = rep->n_theta = rep->n_thetaT = rep->n_flow_updates = rep->n_L = 0;
         rep->n_factorizations = 0;

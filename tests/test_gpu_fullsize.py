@@ -247,3 +247,20 @@ def test_solve_ellipse128_full(mode):
     else:
         assert abs(res.rre[-1] - G["rre"][-1]) <= 1e-4
         np.testing.assert_allclose(res.rre, G["rre"], rtol=0, atol=1e-6)
+
+
+def test_basis_beyond_device_memory_is_refused_up_front(big):
+    """At 1024 x 1024 x 64 a Krylov column takes 0.54 GB of V and 1.1 GB of FP32 Theta V, so a
+    256-column basis (418 GB) cannot fit in 288 GB: the solve refuses with MMOF_ERR_OOM (-5)
+    before it allocates anything, and the message names how many columns would fit."""
+    import torch
+    from paper_2501_12497_amd._lib import MMOFError
+    B, plan = big["B"], big["plan"]
+    b = torch.zeros(plan.m, dtype=torch.float64, device="cuda")
+    free0, _ = torch.cuda.mem_get_info()
+    with pytest.raises(MMOFError) as e:
+        B.solve_joint(plan, b, 1.0, ell=10, k_max=247, op_dtype="f32")
+    assert e.value.code == -5
+    assert "columns (ell + k_max - 1) fit" in str(e.value)
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (1 << 30)   # nothing of the basis was allocated
