@@ -3,6 +3,24 @@
 Image subproblem (eq. rec_problem_s_fixed_joint): min ||H u - b||^2 + lambda ||Theta u||_1
 with Theta = [Psi; M-bar(s); M-bar'(s')] (l1 on every row of Theta).
 
+Regulariser variants (Sec. 5, table of methods, and the remark on its notation; `reg`):
+  "psi"    M / M-OF:    Theta = [Psi], l1 on every row (the default above);
+  "aniso"  D1 AnisoTV:  Theta = [Psi; L_t], l1 on every row (the vertical, horizontal and
+                        temporal first differences of the tensor U);
+  "iso"    D2 IsoTV:    Theta = [Psi; L_t]; the two spatial differences of a pixel (its
+                        horizontal one unless it is in the last column, its vertical one
+                        unless it is in the last row) form one group measured by its l2
+                        norm, the temporal differences are l1;
+  "gs"     D3 GS:       Theta = [Psi]; L_s U (every spatial difference of every frame) as a
+                        matrix with one row per difference location and one column per
+                        frame, measured by the l2,1 norm: each location's differences over
+                        all frames of its sequence form one group;
+each with the motion rows [M-bar(s); M-bar'(s')] appended for the -OF variant (use_flow).
+A group g enters the smoothed objective as sqrt(||(Theta u)_g||^2 + eps^2) (an l1 row is a
+group of one), and its MM weight is P^2 = 1 / sqrt(||(Theta u^(k))_g||^2 + eps^2) on every row
+of the group: by concavity of sqrt in ||.||^2, the same quadratic tangent majorant as for the
+l1 rows (eq. QuadraticMajorantQ) with these weights.
+
 Per outer iteration k (Alg. 1):
   1. every tau iterations (k mod tau == 0) update the flow on u^(k) and the reverse
      flow from it (Sec. 4.1.4 strategies), which changes Theta;
@@ -64,7 +82,11 @@ class StackOps:
 
     def __init__(self, seqs: List[SeqGeom], op: str, use_flow: bool = True, use_reverse: bool = True,
                  interp: str = "bilinear", flow_scale: int = 1, flow_solver: str = "hs", of_ell: int = 10,
-                 of_iters: int = 20, fan: tuple = None):
+                 of_iters: int = 20, fan: tuple = None, reg: str = "psi"):
+        assert reg in ("psi", "aniso", "iso", "gs"), reg
+        self.reg = reg
+        self.tdiff = reg in ("aniso", "iso")   # Theta holds the temporal differences L_t
+        self._groups = None
         self.seqs = seqs
         self.op = op
         self.use_flow = use_flow
@@ -150,6 +172,8 @@ class StackOps:
         for i, (s, us, (v, vr)) in enumerate(zip(self.seqs, self.split_u(u), flows)):
             gx, gy = regops.grad_fwd(us)
             parts += [gx.ravel(), gy.ravel()]
+            if self.tdiff:
+                parts.append(regops.tdiff_fwd(us).ravel())
             if self.use_flow and s.n_t > 1:
                 parts.append(self._flow_mat(i, v, s.n_t, 1) @ us.ravel())
                 if self.use_reverse:
@@ -165,6 +189,10 @@ class StackOps:
             gy = y[o:o + nt * (ny - 1) * nx].reshape(nt, ny - 1, nx)
             o += gy.size
             us = regops.grad_adj(gx, gy)
+            if self.tdiff:
+                npx = (nt - 1) * ny * nx
+                us = us + regops.tdiff_adj(y[o:o + npx].reshape(nt - 1, ny, nx))
+                o += npx
             if self.use_flow and nt > 1:
                 npx = (nt - 1) * ny * nx
                 rf = y[o:o + npx].reshape(nt - 1, ny, nx)
@@ -176,6 +204,59 @@ class StackOps:
                     us = us + (self._flow_mat(i, vr, nt, -1).T @ rr.ravel()).reshape(nt, ny, nx)
             parts.append(us.ravel())
         return np.concatenate(parts)
+
+
+    # -- groups of the regulariser and the MM weights
+    def group_ids(self) -> np.ndarray:
+        """The group of every row of Theta, in the row order of theta(): rows of one group
+        share one smoothed l2 norm in the regulariser; an l1 row is a group of its own."""
+        if self._groups is not None:
+            return self._groups
+        ids, nxt = [], 0
+
+        def fresh(k):
+            nonlocal nxt
+            out = np.arange(nxt, nxt + k)
+            nxt += k
+            return out
+
+        for s in self.seqs:
+            nt, ny, nx = s.n_t, s.ny, s.nx
+            t, y, x = np.meshgrid(np.arange(nt), np.arange(ny), np.arange(nx), indexing="ij")
+            if self.reg == "iso":
+                # one group per pixel: its horizontal and its vertical difference
+                pix = fresh(nt * ny * nx).reshape(nt, ny, nx)
+                ids += [pix[:, :, :-1].ravel(), pix[:, :-1, :].ravel()]
+            elif self.reg == "gs":
+                # one group per difference location, over all frames of the sequence
+                locx = fresh(ny * (nx - 1)).reshape(ny, nx - 1)
+                locy = fresh((ny - 1) * nx).reshape(ny - 1, nx)
+                ids += [np.broadcast_to(locx, (nt, ny, nx - 1)).ravel(),
+                        np.broadcast_to(locy, (nt, ny - 1, nx)).ravel()]
+            else:
+                ids += [fresh(nt * ny * (nx - 1)), fresh(nt * (ny - 1) * nx)]
+            if self.tdiff:
+                ids.append(fresh((nt - 1) * ny * nx))
+            if self.use_flow and nt > 1:
+                ids.append(fresh((nt - 1) * ny * nx))
+                if self.use_reverse:
+                    ids.append(fresh((nt - 1) * ny * nx))
+        self._groups = np.concatenate(ids).astype(np.int64)
+        return self._groups
+
+    def group_sq_norms(self, nu: np.ndarray) -> np.ndarray:
+        """||nu_g||^2 of every group."""
+        ids = self.group_ids()
+        return np.bincount(ids, weights=nu * nu, minlength=int(ids.max()) + 1)
+
+    def weights(self, nu: np.ndarray, eps: float) -> np.ndarray:
+        """Diagonal of P_eps^2 for the rows of Theta: 1 / sqrt(||nu_g||^2 + eps^2) of each
+        row's group (for l1 rows the weights of mm_weights_sq)."""
+        return 1.0 / np.sqrt(self.group_sq_norms(nu)[self.group_ids()] + eps * eps)
+
+    def j_eps(self, Au_minus_b: np.ndarray, nu: np.ndarray, lam: float, eps: float) -> float:
+        """||Hu - b||^2 + 2 lambda sum_g sqrt(||nu_g||^2 + eps^2) (j_eps with groups)."""
+        return float(Au_minus_b @ Au_minus_b + 2.0 * lam * np.sqrt(self.group_sq_norms(nu) + eps * eps).sum())
 
 
 # ------------------------------------------------------------------------ pieces
@@ -312,7 +393,7 @@ def mmgks_of(ops: StackOps, b: np.ndarray, delta: float, p: SolveParams, u0=None
         if ops.use_flow and k % p.tau == 0:
             flows = ops.update_flows(u, flows, p.alpha, p.n_sweeps, p.delta_r)
         nu = ops.theta(u, flows)
-        w2 = mm_weights_sq(nu, p.eps)
+        w2 = ops.weights(nu, p.eps)
         TV = np.stack([ops.theta(V[:, j], flows) for j in range(V.shape[1])], axis=1)
         PTV = np.sqrt(w2)[:, None] * TV
         QA, RA = np.linalg.qr(AV)
@@ -331,7 +412,7 @@ def mmgks_of(ops: StackOps, b: np.ndarray, delta: float, p: SolveParams, u0=None
         res.last_w2 = w2
         res.n_cols = V.shape[1]
         res.resid.append(float(np.linalg.norm(Avz - b)))
-        res.jeps.append(j_eps(Avz - b, TV @ z, lam, p.eps))
+        res.jeps.append(ops.j_eps(Avz - b, TV @ z, lam, p.eps))
         if u_true is not None:
             res.rre.append(rre(u, u_true))
         res.iters = k + 1

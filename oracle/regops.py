@@ -19,6 +19,11 @@ M-bar(s) has block rows [.. I, -M(s(t)) ..] and M-bar'(s') block rows
 -M-bar' for the reverse direction), so that its rows read
 W(v)u(t+1) - u(t) ~ u_t + v . grad u; the sign does not change any norm.
 
+Temporal difference (Sec. 5, the spatio-temporal regularisers of the method family: the
+mode-3 product U x_3 L_t with L_t the first-difference matrix in time): for every frame pair,
+(L_t u)_t = u(t+1) - u(t), stored [n_pairs, ny, nx] like a flow residual (it is the flow
+operator with a zero flow).
+
 Flow arrays are [n_pairs, 2, ny, nx] with component 0 = x, 1 = y.  The reverse
 flow s'(t+1) is stored at pair index t (the earlier frame of the pair).
 """
@@ -197,3 +202,20 @@ def flow_dv(u: np.ndarray, v: np.ndarray, w: np.ndarray, direction: int = 1, int
         out[t, 0] = w[t] * dx
         out[t, 1] = w[t] * dy
     return out
+
+
+# ----------------------------------------------------------------------------- L_t
+
+
+def tdiff_fwd(u: np.ndarray) -> np.ndarray:
+    """U x_3 L_t: r[t] = u[t+1] - u[t] for t < n_t - 1 ([n_t - 1, ny, nx])."""
+    return u[1:] - u[:-1]
+
+
+def tdiff_adj(r: np.ndarray) -> np.ndarray:
+    """(U x_3 L_t)^T: u[t] = r[t-1] (t >= 1) - r[t] (t <= n_t - 2), [n_t, ny, nx]."""
+    n_pairs = r.shape[0]
+    u = np.zeros((n_pairs + 1,) + r.shape[1:])
+    u[1:] += r
+    u[:-1] -= r
+    return u
