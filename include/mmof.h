@@ -59,6 +59,12 @@ typedef enum { MMOF_F32 = 0, MMOF_F64 = 1 } mmof_dtype;
 /* flow solvers of the joint solve */
 #define MMOF_FLOW_HS 0
 #define MMOF_FLOW_GKS 1
+/* regularisers of the joint solve (Sec. 5, table of methods); each with the motion rows when
+ * use_flow is set (the -OF variants) */
+#define MMOF_REG_PSI 0     /* M:  Theta = [Psi], l1 on every row                             */
+#define MMOF_REG_ANISO 1   /* D1 AnisoTV: Theta = [Psi; L_t], l1 on every row                 */
+#define MMOF_REG_ISO 2     /* D2 IsoTV: [Psi; L_t], a pixel's two spatial differences grouped */
+#define MMOF_REG_GS 3      /* D3 GS: [Psi], each difference location grouped over the frames  */
 
 typedef struct mmof_ctx_s* mmof_ctx;
 typedef struct mmof_plan_s* mmof_plan;
@@ -171,6 +177,24 @@ int mmof_apply_grad(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int tr
 int mmof_apply_flow_op(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int mode,
                        int direction, int interp, const void* u, const void* v,
                        const void* in, void* out);
+
+/* Temporal first difference L_t of the spatio-temporal regularisers (Sec. 5, table of methods:
+ * the mode-3 product U x_3 L_t):
+ *   transpose = 0: out (r, [pairs][ny][nx]) <- u(t+1) - u(t) for every pair of every sequence;
+ *   transpose = 1: out (u, [frames][ny][nx]) <- L_t^T in, i.e. in(t-1) - in(t) with the terms
+ *                  of missing pairs left out (overwrites out). */
+int mmof_apply_tdiff(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int transpose, const void* in,
+                     void* out);
+
+/* MM weights of the rows of Theta for regulariser reg (MMOF_REG_*; eq. QuadraticMajorantQ with
+ * groups): nu (dtype dt, n_rows entries) is Theta u in the joint solve's row order, starting with
+ * the gx rows ([frames][ny][nx-1]) and the gy rows ([frames][ny-1][nx]) of the stack; w2 (device
+ * FP64, n_rows) receives 1 / sqrt(||nu_g||^2 + eps^2) for every row, g its group: a row of its
+ * own for MMOF_REG_PSI and MMOF_REG_ANISO and for every row after the gy rows; for MMOF_REG_ISO a
+ * pixel's horizontal and vertical difference; for MMOF_REG_GS a difference location's entries in
+ * all frames of its sequence.  MMOF_ERR_SHAPE unless n_rows >= the gx and gy rows of the stack. */
+int mmof_reg_weights(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int reg, int64_t n_rows,
+                     const void* nu, double eps, double* w2);
 
 /* MM weights of Sec. 4.1.1: w2 = diag(P_eps^2) = 1 / sqrt(nu^2 + eps^2), n entries. */
 int mmof_mm_weights(mmof_ctx ctx, mmof_dtype dt, int64_t n, const void* nu, double eps, void* w2);
@@ -294,6 +318,7 @@ typedef struct {
                           /* (mmof_flow_solve_gks, lambda by GCV)                           */
     int32_t of_ell;       /* Solve-OF: Golub-Kahan steps (10)                               */
     int32_t of_iters;     /* Solve-OF: projected solves per flow computation (20)           */
+    int32_t reg;          /* MMOF_REG_*: the spatial(-temporal) part of Theta (M by default)  */
 } mmof_solve_params;
 
 typedef struct {
@@ -311,7 +336,10 @@ typedef struct {
 } mmof_report;
 
 /* MMGKS-OF (Alg. 1) for min ||H u - b||^2 + lambda ||Theta u||_1 with the flow
- * re-estimated every tau iterations.  b: device FP64 [m]; noise_norm: ||e|| for the
+ * re-estimated every tau iterations; p->reg selects the regulariser variant of the method
+ * family (Sec. 5: M, D1 AnisoTV, D2 IsoTV, D3 GS; Theta's rows [gx | gy | L_t | forward flow |
+ * reverse flow] as present), its groups entering the smoothed norm and the MM weights as in
+ * mmof_reg_weights.  b: device FP64 [m]; noise_norm: ||e|| for the
  * discrepancy principle; u_inout: device FP64 [n] (initial estimate in, solution out);
  * v_out, v_rev_out: device flows of dtype op_dtype (either may be NULL); rep may be NULL.
  * Krylov vectors, Gram matrices, the projected solve and lambda are FP64 on the GPU.

@@ -25,6 +25,10 @@ class mmof_stack(C.Structure):
                 ("nx", C.POINTER(C.c_int32))]
 
 
+MMOF_REG_PSI, MMOF_REG_ANISO, MMOF_REG_ISO, MMOF_REG_GS = 0, 1, 2, 3
+REGS = {"psi": MMOF_REG_PSI, "aniso": MMOF_REG_ANISO, "iso": MMOF_REG_ISO, "gs": MMOF_REG_GS}
+
+
 class mmof_solve_params(C.Structure):
     _fields_ = [("ell", C.c_int32), ("k_max", C.c_int32), ("tau", C.c_int32), ("n_sweeps", C.c_int32),
                 ("delta_r", C.c_int32), ("use_flow", C.c_int32), ("use_reverse", C.c_int32),
@@ -32,7 +36,7 @@ class mmof_solve_params(C.Structure):
                 ("eps", C.c_double), ("eta", C.c_double), ("alpha", C.c_double), ("fixed_lambda", C.c_double),
                 ("rre_target", C.c_double), ("u_true", C.c_void_p), ("use_graph", C.c_int32),
                 ("flow_scale", C.c_int32), ("flow_solver", C.c_int32), ("of_ell", C.c_int32),
-                ("of_iters", C.c_int32)]
+                ("of_iters", C.c_int32), ("reg", C.c_int32)]
 
 
 class mmof_report(C.Structure):
@@ -79,6 +83,8 @@ _SIGS = {
     "mmof_weighted_gram": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_int32]),
     "mmof_weighted_gram_noalloc": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P,
                                         C.c_int32]),
+    "mmof_apply_tdiff": (_I, [_P, C.POINTER(mmof_stack), _I, _I, _P, _P]),
+    "mmof_reg_weights": (_I, [_P, C.POINTER(mmof_stack), _I, _I, C.c_int64, _P, C.c_double, _P]),
     "mmof_block_dot": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P]),
     "mmof_block_combine": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_double, _P]),
     "mmof_cgs2": (_I, [_P, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P]),

@@ -415,6 +415,30 @@ def weighted_gram(X: torch.Tensor, nu: Optional[torch.Tensor] = None, eps: float
     return G
 
 
+def apply_tdiff(stack: Stack, x: torch.Tensor, transpose: bool = False, out: Optional[torch.Tensor] = None,
+                ctx: Optional[Context] = None) -> torch.Tensor:
+    """L_t x (x: n pixels -> pair pixels) or L_t^T x (pair pixels -> n pixels)."""
+    ctx = ctx or context()
+    n_in, n_out = (stack.n_pair_px, stack.n) if transpose else (stack.n, stack.n_pair_px)
+    _need(x, n_in, "x")
+    out = torch.empty(n_out, dtype=x.dtype, device=x.device) if out is None else out
+    _need(out, n_out, "out")
+    ctx.bind()
+    check(ctx.lib.mmof_apply_tdiff(ctx.h, stack.ref, _dt(x, out), 1 if transpose else 0, _ptr(x), _ptr(out)))
+    return out
+
+
+def reg_weights(stack: Stack, reg, nu: torch.Tensor, eps: float = 1e-3, ctx: Optional[Context] = None) -> torch.Tensor:
+    """FP64 MM weights of the rows of Theta u (nu) for a regulariser ("psi", "aniso", "iso", "gs")."""
+    ctx = ctx or context()
+    code = _lib.REGS[reg] if isinstance(reg, str) else int(reg)
+    _need(nu, nu.numel(), "nu")
+    w2 = torch.empty(nu.numel(), dtype=torch.float64, device=nu.device)
+    ctx.bind()
+    check(ctx.lib.mmof_reg_weights(ctx.h, stack.ref, _dt(nu), code, nu.numel(), _ptr(nu), float(eps), _ptr(w2)))
+    return w2
+
+
 def block_dot(X: torch.Tensor, y: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
     """out[j] = X_j^T y for X of shape [K, n] (float32 or float64) and an FP64 y of n entries."""
     ctx = ctx or context()
@@ -490,6 +514,8 @@ def solve_params(**kw) -> _lib.mmof_solve_params:
     for k, val in kw.items():
         if k == "op_dtype" and isinstance(val, str):
             val = {"f32": _lib.MMOF_F32, "f64": _lib.MMOF_F64}[val]
+        if k == "reg" and isinstance(val, str):
+            val = _lib.REGS[val]
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, val)

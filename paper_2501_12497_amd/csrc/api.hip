@@ -450,6 +450,7 @@ void mmof_solve_defaults(mmof_solve_params* p) {
     p->flow_solver = MMOF_FLOW_HS;
     p->of_ell = 10;
     p->of_iters = 20;
+    p->reg = MMOF_REG_PSI;
 }
 
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p, void* u_inout,
@@ -461,6 +462,7 @@ int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_s
         need(u_inout, "u_inout");
         MMOF_CHECK(std::isfinite(noise_norm) && noise_norm >= 0, MMOF_ERR_INVALID, "noise_norm must be >= 0");
         MMOF_CHECK(p->interp == MMOF_INTERP_BILINEAR || p->interp == MMOF_INTERP_ROUND, MMOF_ERR_INVALID, "bad interp");
+        MMOF_CHECK(p->reg >= MMOF_REG_PSI && p->reg <= MMOF_REG_GS, MMOF_ERR_INVALID, "bad regulariser");
         if (p->use_flow) {
             const int f = resolve_flow_scale(*A->geom, p->flow_scale);
             check_flow_frames(*A->geom, f, p->delta_r);
@@ -515,6 +517,39 @@ int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K
             wgram_noalloc<float>(*ctx, n, K, (const float*)X, ld, (const float*)nu, eps, G, ldg);
         else
             wgram_noalloc<double>(*ctx, n, K, (const double*)X, ld, (const double*)nu, eps, G, ldg);
+        return MMOF_OK;
+    });
+}
+
+int mmof_apply_tdiff(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int transpose, const void* in,
+                     void* out) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(in, "in");
+        need(out, "out");
+        Geom& g = ctx->geom(stack);
+        launch_tdiff(*ctx, g, dt, transpose != 0, in, out, false);
+        return MMOF_OK;
+    });
+}
+
+int mmof_reg_weights(mmof_ctx ctx, const mmof_stack* stack, mmof_dtype dt, int reg, int64_t n_rows, const void* nu,
+                     double eps, double* w2) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need_dt(dt);
+        need(nu, "nu");
+        need(w2, "w2");
+        MMOF_CHECK(reg >= MMOF_REG_PSI && reg <= MMOF_REG_GS, MMOF_ERR_INVALID, "bad regulariser");
+        MMOF_CHECK(eps > 0 && std::isfinite(eps), MMOF_ERR_INVALID, "eps must be > 0");
+        Geom& g = ctx->geom(stack);
+        MMOF_CHECK(n_rows >= g.gx_len + g.gy_len, MMOF_ERR_SHAPE, "n_rows is below the gradient rows of the stack");
+        if (dt == MMOF_F32)
+            mm_weights_f64<float>(*ctx, n_rows, (const float*)nu, eps, w2);
+        else
+            mm_weights_f64<double>(*ctx, n_rows, (const double*)nu, eps, w2);
+        if (reg == MMOF_REG_ISO || reg == MMOF_REG_GS) launch_group_weights(*ctx, g, dt, reg, nu, eps, w2);
         return MMOF_OK;
     });
 }

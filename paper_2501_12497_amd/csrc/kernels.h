@@ -35,6 +35,15 @@ void launch_flow_dv(Ctx& c, Geom& g, int dt, int direction, int interp, const vo
 // Device int *d_out = floor(max |v|) + 1 over all pairs (saturating at 1<<20, NaN -> saturate).
 void launch_flow_radius(Ctx& c, Geom& g, int dt, const void* v, int32_t* d_out);
 
+// Temporal first difference L_t of the spatio-temporal regularisers: forward r = u(t+1) - u(t)
+// per pair ([pairs][ny][nx]); transpose (accumulating into u or overwriting it).
+void launch_tdiff(Ctx& c, Geom& g, int dt, bool transpose, const void* in, void* out, bool accumulate);
+// MM weights of the grouped rows of Theta (reg MMOF_REG_ISO: per pixel over its horizontal
+// and vertical difference; MMOF_REG_GS: per difference location over the frames of its
+// sequence): nu holds Theta u from its start (gx rows, then gy rows), w2 (FP64) likewise;
+// only the gx and gy rows of w2 are written.
+void launch_group_weights(Ctx& c, Geom& g, int dt, int reg, const void* nu, double eps, double* w2);
+
 // App. C derivatives, Horn-Schunck sweeps, reverse flow.
 void launch_of_derivs(Ctx& c, Geom& g, int dt, const void* u, void* I, int dr);
 // n_sweeps Horn-Schunck sweeps starting from v, several per launch, ping-ponging between

@@ -8,8 +8,10 @@
 // the Gram matrices, the projected solve and lambda are FP64.  H V and Theta V are kept
 // in TX (they are operator outputs) and are accumulated in FP64.
 //
-// Theta = [Psi; M-bar(v); M-bar'(v')] is stored row block after row block:
-// [gx (all frames) | gy (all frames) | forward flow rows | reverse flow rows].
+// Theta = [Psi; L_t; M-bar(v); M-bar'(v')] (the blocks the regulariser and the flow use) is
+// stored row block after row block:
+// [gx (all frames) | gy (all frames) | temporal differences | forward flow rows | reverse flow rows].
+// The MM weights are per row (l1) or per group of rows (IsoTV, GS: Sec. 5, table of methods).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -59,9 +61,10 @@ struct Solver {
     Geom& g;
     const mmof_solve_params& p;
     int dt;
-    int64_t n, m, R, oGX, oGY, oRF, oRR;
+    int64_t n, m, R, oGX, oGY, oTD, oRF, oRR;
     int Kcap;
     bool flow;
+    bool tdiff;  // Theta holds the temporal differences L_t (AnisoTV, IsoTV)
     mmof_report* rep;
 
     // workspace
@@ -83,9 +86,11 @@ struct Solver {
         n = P.n;
         m = P.m;
         flow = p.use_flow != 0;
+        tdiff = p.reg == MMOF_REG_ANISO || p.reg == MMOF_REG_ISO;
         oGX = 0;
         oGY = g.gx_len;
-        oRF = g.gx_len + g.gy_len;
+        oTD = g.gx_len + g.gy_len;
+        oRF = oTD + (tdiff ? g.pair_px : 0);
         oRR = oRF + (flow ? g.pair_px : 0);
         R = oRR + ((flow && p.use_reverse) ? g.pair_px : 0);
         Kcap = p.ell + p.k_max - 1;
@@ -184,17 +189,25 @@ struct Solver {
     }
     void theta(const TX* in, TX* out) {
         launch_grad_fwd(c, g, dt, in, nullptr, nullptr, out + oGX, out + oGY);
+        if (tdiff) launch_tdiff(c, g, dt, false, in, out + oTD, false);
         theta_flow(in, out);
         if (rep) rep->n_theta++;
     }
     void thetaT(const TX* in, TX* out) {
         launch_grad_adj(c, g, dt, in + oGX, in + oGY, nullptr, nullptr, out, false);
+        if (tdiff) launch_tdiff(c, g, dt, true, in + oTD, out, true);
         if (flow) {
             launch_flow_adj(c, g, dt, +1, p.interp, in + oRF, flow_v, out, true, rad_v);
             if (p.use_reverse) launch_flow_adj(c, g, dt, -1, p.interp, in + oRR, flow_vr, out, true, rad_vr);
             if (rep) rep->n_L += p.use_reverse ? 2 : 1;
         }
         if (rep) rep->n_thetaT++;
+    }
+
+    // FP64 MM weights of the rows of Theta u: per row, then per group for IsoTV and GS
+    void weights(const TX* nu_, double* w) {
+        mm_weights_f64<TX>(c, R, nu_, p.eps, w);
+        if (p.reg == MMOF_REG_ISO || p.reg == MMOF_REG_GS) launch_group_weights(c, g, dt, p.reg, nu_, p.eps, w);
     }
 
     // ---------------------------------------------------------------- graphs
@@ -269,6 +282,7 @@ struct Solver {
                       (void*)rad_vr, (void*)vin_m, (void*)out_n, (void*)out_n2, (void*)w2, (void*)r, (void*)scal,
                       (void*)flow_us, (void*)flow_vs, p.interp, p.use_reverse, p.n_sweeps, p.delta_r, fscale,
                       p.alpha, (long long)n, (long long)R);
+        std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), "|reg%d", p.reg);
         if (fm.solver == MMOF_FLOW_GKS) {
             std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), "|gks|%d|%d|%p|%p|%p|%p|%p", fm.ell,
                           fm.n_iter, (void*)gks.V, (void*)gks.U, (void*)gks.S, (void*)gks.R, (void*)gks.lam);
@@ -456,7 +470,7 @@ struct Solver {
                 }
                 // 2. nu = Theta u^(k); FP64 weights; weighted Gram of Theta V
                 if (!nu_fresh) theta(u_op, nu);
-                mm_weights_f64<TX>(c, R, nu, p.eps, w2);
+                weights(nu, w2);
                 wgram<TX>(c, R, K, TV, R, w2, GT, KLD);
                 // 3-5. lambda (discrepancy principle) and z; lambda is kept in sc[2] as the next warm start
                 small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
@@ -495,7 +509,7 @@ struct Solver {
                 normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
                 add_column(K, true);
                 if (!nu_fresh) theta(u_op, nu);
-                mm_weights_f64<TX>(c, R, nu, p.eps, w2);
+                weights(nu, w2);
                 wgram<TX>(c, R, K + 1, TV, R, w2, GT, KLD);
                 small_solve(c, K + 1, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
             }
@@ -588,7 +602,9 @@ static void check_solve_capacity(Ctx& c, const Plan& P, const mmof_solve_params&
     const Geom& g = *P.geom;
     const bool flow = p.use_flow != 0;
     const size_t n = (size_t)P.n, m = (size_t)P.m;
-    const size_t R = (size_t)(g.gx_len + g.gy_len + (flow ? g.pair_px : 0) + ((flow && p.use_reverse) ? g.pair_px : 0));
+    const bool tdiff = p.reg == MMOF_REG_ANISO || p.reg == MMOF_REG_ISO;
+    const size_t R = (size_t)(g.gx_len + g.gy_len + (tdiff ? g.pair_px : 0) + (flow ? g.pair_px : 0) +
+                              ((flow && p.use_reverse) ? g.pair_px : 0));
     const size_t K = (size_t)std::max(1, p.ell + p.k_max - 1);
     const bool f64 = p.op_dtype == MMOF_F64 || p.refine_iters > 0;
     const bool f32 = p.op_dtype == MMOF_F32 && p.refine_iters < p.k_max;
