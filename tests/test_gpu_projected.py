@@ -20,7 +20,10 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("K", [1, 5, 16, 17, 31, 33, 40, 48, 63, 64, 65, 97, 130, 210, 256])
+# 17, 20, 24, 33, 36, 39, 40, 52, 56: full blocks plus a tail of at most 8 columns (vector-ALU
+# tail path); 31, 47, 63: tails of more than 8 (padded block)
+@pytest.mark.parametrize("K", [1, 5, 16, 17, 20, 24, 31, 33, 36, 39, 40, 47, 48, 52, 56, 63, 64, 65, 97, 130, 210,
+                               256])
 @pytest.mark.parametrize("which", ["f64", "f32"])
 def test_weighted_gram(B, K, which):
     import torch
