@@ -43,6 +43,48 @@ __device__ __forceinline__ T warp_sample(const S* __restrict__ src, int nx, int 
     return (T(1) - fx) * (T(1) - fy) * a0 + fx * (T(1) - fy) * a1 + (T(1) - fx) * fy * b0 + fx * fy * b1;
 }
 
+// A sample position prepared once and used for many source images of the same frame
+// geometry: the offsets of the two pixel pairs read (or of the nearest pixel for INTERP 1),
+// the edge flag and the fractions, as warp_sample forms them.
+template <class T>
+struct SampleCell {
+    int o0, o1;    // row * nx + xa of the rows y0 and y1 (INTERP 1: the pixel's offset in o0)
+    T fx, fy;
+    bool edge;
+};
+
+template <class T, int INTERP>
+__device__ __forceinline__ SampleCell<T> sample_cell(int nx, int ny, int x, int y, T vx, T vy) {
+    SampleCell<T> c;
+    if (INTERP == 1) {
+        c.o0 = round_clip(y, vy, ny) * nx + round_clip(x, vx, nx);
+        c.o1 = c.o0;
+        c.fx = c.fy = T(0);
+        c.edge = false;
+        return c;
+    }
+    int x0, y0;
+    bool cx, cy;
+    clip_cell(x, vx, nx, x0, c.fx, cx);
+    clip_cell(y, vy, ny, y0, c.fy, cy);
+    const int y1 = min(y0 + 1, ny - 1);
+    const int xa = min(x0, nx - 2);
+    c.o0 = y0 * nx + xa;
+    c.o1 = y1 * nx + xa;
+    c.edge = xa != x0;
+    return c;
+}
+
+// warp_sample(src, ...) for a prepared cell (the same arithmetic, so the same value).
+template <class T, int INTERP, class S>
+__device__ __forceinline__ T sample_at(const S* __restrict__ src, const SampleCell<T>& c) {
+    if (INTERP == 1) return (T)src[c.o0];
+    const Pair<S> p0 = ld2(src + c.o0), p1 = ld2(src + c.o1);
+    const T a0 = (T)(c.edge ? p0.b : p0.a), a1 = (T)p0.b, b0 = (T)(c.edge ? p1.b : p1.a), b1 = (T)p1.b;
+    const T fx = c.fx, fy = c.fy;
+    return (T(1) - fx) * (T(1) - fy) * a0 + fx * (T(1) - fy) * a1 + (T(1) - fx) * fy * b0 + fx * fy * b1;
+}
+
 template <class T, int INTERP, int FTW, int FTH>
 __global__ __launch_bounds__(256) void k_flow_fwd(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ u, const T* __restrict__ v,
@@ -154,6 +196,55 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols4(const Tile* __restrict__
         for (int j = 0; j < 4; ++j)
             q.v[j] = warp_sample<T, INTERP, double>(ut, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)b.v[j];
         st4(o + oR + f.pair_off + p, q);
+    }
+}
+
+// k_flow_fwd_cols4 with the sample cells of a lane's four pixels (both directions) formed
+// once from the flows and reused for JC consecutive columns (grid.y = column groups): the
+// flows are read once per JC columns instead of once per column.
+template <class T, int INTERP, int LW, int JC>
+__global__ __launch_bounds__(256) void k_flow_fwd_colsJ(const Tile* __restrict__ tiles,
+                                                        const FrameInfo* __restrict__ fr,
+                                                        const double* __restrict__ U, int64_t ldu, int K,
+                                                        const T* __restrict__ v, const T* __restrict__ vr,
+                                                        T* __restrict__ out, int64_t ldo, int64_t oF, int64_t oR) {
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const FrameInfo f = fr[tl.frame];
+    const int x = tl.x0 + 4 * (int)(threadIdx.x % LW);
+    const int y = tl.y0 + (int)(threadIdx.x / LW);
+    if (x >= f.nx || y >= f.ny) return;
+    const int64_t np = (int64_t)f.nx * f.ny;
+    const int64_t p = (int64_t)y * f.nx + x;
+    SampleCell<T> cf[4], cr[4];
+    {
+        const T* vf = v + 2 * f.pair_off;
+        const Quad<T> vx = ld4(vf + p), vy = ld4(vf + np + p);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cf[j] = sample_cell<T, INTERP>(f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]);
+    }
+    if (vr) {
+        const T* vb = vr + 2 * f.pair_off;
+        const Quad<T> vx = ld4(vb + p), vy = ld4(vb + np + p);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cr[j] = sample_cell<T, INTERP>(f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]);
+    }
+    const int c0 = blockIdx.y * JC;
+    for (int jj = 0; jj < JC; ++jj) {
+        const int col = c0 + jj;
+        if (col >= K) break;
+        const double* ut = U + (int64_t)col * ldu + f.off;
+        const double* ut1 = ut + np;
+        T* o = out + (int64_t)col * ldo;
+        const Quad<double> a = ld4(ut + p), b = ld4(ut1 + p);
+        Quad<T> q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, double>(ut1, cf[j]) - (T)a.v[j];
+        st4(o + oF + f.pair_off + p, q);
+        if (vr) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, double>(ut, cr[j]) - (T)b.v[j];
+            st4(o + oR + f.pair_off + p, q);
+        }
     }
 }
 
@@ -520,15 +611,29 @@ void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const double* U, 
         if (v4) {
             const Flow4Shape sh = kFlow4Shapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
-            auto pick = [&](auto interp_tag) {
-                constexpr int I = decltype(interp_tag)::value;
-                return sh.lw == 64 ? k_flow_fwd_cols4<T, I, 64> : k_flow_fwd_cols4<T, I, 32>;
-            };
-            auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
-                                                 : pick(std::integral_constant<int, 0>{});
-            hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(64 * sh.nw), 0, c.stream,
-                               tl.buf.as<Tile>(), g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo, oF,
-                               oR);
+            if ((int64_t)g.max_ny * g.max_nx < ((int64_t)1 << 31)) {
+                // (prepared cells hold 32-bit offsets within a frame)
+                constexpr int JC = 8;   // columns per thread
+                auto pick = [&](auto interp_tag) {
+                    constexpr int I = decltype(interp_tag)::value;
+                    return sh.lw == 64 ? k_flow_fwd_colsJ<T, I, 64, JC> : k_flow_fwd_colsJ<T, I, 32, JC>;
+                };
+                auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
+                                                     : pick(std::integral_constant<int, 0>{});
+                hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)cdiv(K, JC)), dim3(64 * sh.nw), 0,
+                                   c.stream, tl.buf.as<Tile>(), g.dframes(), U, ldu, K, (const T*)v, (const T*)vr,
+                                   (T*)out, ldo, oF, oR);
+            } else {
+                auto pick = [&](auto interp_tag) {
+                    constexpr int I = decltype(interp_tag)::value;
+                    return sh.lw == 64 ? k_flow_fwd_cols4<T, I, 64> : k_flow_fwd_cols4<T, I, 32>;
+                };
+                auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
+                                                     : pick(std::integral_constant<int, 0>{});
+                hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(64 * sh.nw), 0, c.stream,
+                                   tl.buf.as<Tile>(), g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo,
+                                   oF, oR);
+            }
         } else {
             const TileShape sh = kFlowShapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);

@@ -264,7 +264,10 @@ __global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* _
     if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }
 
-// k_gemv_fused with two rows per lane (dot_row2); n odd leaves one single row.
+// k_gemv_fused with two rows per lane (dot_row2); n odd leaves one single row.  Each
+// workgroup walks one contiguous chunk of rows (a multiple of 2 KB rows), so that each column
+// is read as long sequential runs (measured 5.0 TB/s at 67M rows x 32..39 FP64 columns against
+// 4.5-4.7 TB/s for a grid-strided walk).
 template <class TX, class TO>
 __global__ __launch_bounds__(KB) void k_gemv_fused2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                                     const double* __restrict__ h, double alpha, const double* y,
@@ -284,8 +287,11 @@ __global__ __launch_bounds__(KB) void k_gemv_fused2(int64_t n, int K, const TX* 
             e2 += e * e;
         }
     };
-    for (int64_t i = 2 * ((int64_t)blockIdx.x * KB + threadIdx.x); i < n; i += 2 * (int64_t)gridDim.x * KB) {
-        if (i + 1 < n) {
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = 2 * KB * ((n + 2 * KB * nb - 1) / (2 * KB * nb));
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    for (int64_t i = lo + 2 * (int64_t)threadIdx.x; i < hi; i += 2 * KB) {
+        if (i + 1 < hi) {
             double a0, a1;
             dot_row2(X, ld, i, K, sh, a0, a1);
             finish(i, a0);
@@ -868,7 +874,9 @@ void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double*
     }
     // two rows per lane when the columns allow 2-element loads (the grid covers row pairs)
     const bool pair = ld % 2 == 0 && reinterpret_cast<uintptr_t>(X) % (2 * sizeof(TX)) == 0;
-    const dim3 grid = grid_for(pair ? cdiv(n, 2) : n, KB, 2048);
+    // pairs: up to 1024 workgroups of contiguous row chunks; otherwise a grid-strided walk
+    const dim3 grid = pair ? dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 2 * KB))))
+                           : grid_for(n, KB, 2048);
     double* part = sq ? static_cast<double*>(c.work("gemv_part", sizeof(double) * 2048)) : nullptr;
     {
         // K columns and y (if any) read, the outputs written, cv read when given

@@ -33,6 +33,8 @@ struct Phase {
     bool final = true;             // the last phase: no subspace growth after its last iteration
     int K_in = 0;                  // 0: start with Golub-Kahan
     bool start_only = false;       // build the Golub-Kahan basis V and return
+    int start_av = 0;              // columns j < start_av of H V come from the Golub-Kahan start's
+                                   // FP64 products (kept in the shared FP64 workspace)
     const void* v_in = nullptr;    // flows of the previous phase (NULL: zero flows)
     const void* vr_in = nullptr;
     int in_dt = MMOF_F32;
@@ -69,6 +71,7 @@ struct Solver {
 
     // workspace
     double *V, *U, *r, *tmp_n, *tmp_m, *GA, *GT, *dvec, *z, *h, *sc, *res, *scal;
+    double* AVs;  // H v_j of the Golub-Kahan start (FP64, columns 0 .. ell-2)
     TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *yW, *flow_v, *flow_vr, *flow_tmp, *I;
     // flow on reduced frames: their geometry (owned by the plan), frames and flow
     int fscale = 1;
@@ -123,6 +126,7 @@ struct Solver {
     void alloc(bool full) {
         V = ws<double>("V", (int64_t)Kcap * n);
         U = ws<double>("U", (int64_t)(p.ell + 1) * m);
+        AVs = ws<double>("AVs", (int64_t)std::max(1, p.ell - 1) * m);
         r = ws<double>("r", n);
         tmp_m = ws<double>("tmp_m", m);
         h = ws<double>("h", KMAX);
@@ -316,11 +320,15 @@ struct Solver {
     }
 
     // H v_j, the row/column j of G_H, d_j = (H v_j)^T b and Theta v_j; vin_n already holds
-    // v_j in TX when have_vin
-    void add_column(int j, bool have_vin) {
+    // v_j in TX when have_vin.  For j < start_av, H v_j is the Golub-Kahan start's FP64 product
+    // (rounded to TX) instead of a new application of H.
+    void add_column(int j, bool have_vin, int start_av = 0) {
         if (!have_vin) convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
         TX* avj = AV + (int64_t)j * m;
-        A(vin_n, avj);
+        if (j < start_av)
+            convert<double, TX>(c, m, AVs + (int64_t)j * m, avj);
+        else
+            A(vin_n, avj);
         gram_row<TX>(c, m, j, AV, m, b, GA, KLD, dvec + j);
         theta(vin_n, TV + (int64_t)j * R);
     }
@@ -388,8 +396,9 @@ struct Solver {
             norm_into(n, r, scal);
             normalize2<TX>(c, n, r, scal, scal + 1, V, vin_n);
             for (int i = 1; i < p.ell; ++i) {
-                // w = H v_{i-1} - alpha u_{i-1}
+                // w = H v_{i-1} - alpha u_{i-1}; H v_{i-1} is kept as column i-1 of H V
                 A(vin_n, vin_m);
+                convert<TX, double>(c, m, vin_m, AVs + (int64_t)(i - 1) * m);
                 axpy_conv<TX>(c, m, vin_m, U + (int64_t)(i - 1) * m, scal + 1, -1.0, tmp_m);
                 reorth(m, U, i, tmp_m, scal + 2);
                 normalize2<TX>(c, m, tmp_m, scal + 2, scal + 3, U + (int64_t)i * m, vin_m);
@@ -424,7 +433,8 @@ struct Solver {
             launch_flow_radius(c, g, dt, flow_v, rad_v);
             launch_flow_radius(c, g, dt, flow_vr, rad_vr);
         }
-        for (int j = 0; j < K; ++j) add_column(j, false);
+        const int start_av = ph.K_in == 0 ? p.ell - 1 : ph.start_av;
+        for (int j = 0; j < K; ++j) add_column(j, false, start_av);
         int status = 0;
         int iters = 0;
         const double gamma = p.alpha * p.alpha;
@@ -668,6 +678,7 @@ int solve_joint(Plan& P, const double* b, double delta, const mmof_solve_params&
     }
     Phase p1 = ph;
     p1.K_in = p.ell;
+    p1.start_av = p.ell - 1;
     p1.k_end = k_sw;
     p1.final = p.refine_iters == 0;
     Solver<float> s1(*P.ctx, P, p, rep);
@@ -677,6 +688,7 @@ int solve_joint(Plan& P, const double* b, double delta, const mmof_solve_params&
     Phase p2 = ph;
     p2.k_begin = k_sw;
     p2.K_in = o1.K;
+    p2.start_av = p.ell - 1;
     p2.v_in = o1.flow_v;
     p2.vr_in = o1.flow_vr;
     p2.in_dt = MMOF_F32;
