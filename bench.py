@@ -58,7 +58,7 @@ COMPUTE = {
 # The committed HBM-traffic summary of a kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) and
 # the source file it was measured on: traffic is reported only while that source is unchanged.
 TRAFFIC = {
-    "wgram": ("profiles/wgram_ellipse128_traffic.txt", "paper_2501_12497_amd/csrc/k_krylov.hip"),
+    "wgram": ("profiles/wgram_large1024_traffic.txt", "paper_2501_12497_amd/csrc/k_krylov.hip"),
 }
 
 

@@ -187,11 +187,12 @@ struct Ctx {
         if (!p) p.reset(new DeviceBuffer());
         return p->ensure(bytes);
     }
-    // Bytes that work(name, bytes) would newly allocate (0 when the buffer is large enough).
+    // Device memory that work(name, bytes) would take beyond what the buffer holds now (a
+    // growing buffer is freed before the larger one is allocated, so only the difference is new).
     size_t work_growth(const std::string& name, size_t bytes) const {
         auto it = ws.find(name);
         const size_t have = (it != ws.end() && it->second) ? it->second->bytes : 0;
-        return bytes > have ? bytes : 0;
+        return bytes > have ? bytes - have : 0;
     }
     // Event-timing hooks around launches of a named kernel.
     bool timing(const char* kname) const { return !capturing && !timer.name.empty() && timer.name == kname; }

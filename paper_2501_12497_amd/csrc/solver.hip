@@ -620,21 +620,26 @@ static void check_solve_capacity(Ctx& c, const Plan& P, const mmof_solve_params&
     const bool f32 = p.op_dtype == MMOF_F32 && p.refine_iters < p.k_max;
     size_t per_col = sizeof(double) * n;
     size_t grow = c.work_growth("solve_V", sizeof(double) * K * n);
-    if (f64) {
-        per_col += sizeof(double) * (m + R);
-        grow += c.work_growth("solve_d_AV", sizeof(double) * K * m) + c.work_growth("solve_d_TV", sizeof(double) * K * R);
-    }
-    if (f32) {
-        per_col += sizeof(float) * (m + R);
-        grow += c.work_growth("solve_f_AV", sizeof(float) * K * m) + c.work_growth("solve_f_TV", sizeof(float) * K * R);
-    }
+    // the vectors of one iteration: FP64 ones shared by both precisions, the others per precision
+    size_t vecs = 0;
+    for (const char* nm : {"solve_r", "solve_tmp_n", "reorth_y"}) vecs += c.work_growth(nm, sizeof(double) * n);
+    vecs += c.work_growth("solve_w2", sizeof(double) * R) + c.work_growth("solve_AVs", sizeof(double) * p.ell * m);
+    auto per_precision = [&](const char* tag, size_t es) {
+        const std::string t(tag);
+        per_col += es * (m + R);
+        grow += c.work_growth(t + "AV", es * K * m) + c.work_growth(t + "TV", es * K * R);
+        for (const char* nm : {"u_op", "out_n", "out_n2", "vin_n"}) vecs += c.work_growth(t + nm, es * n);
+        for (const char* nm : {"nu", "yR", "yW"}) vecs += c.work_growth(t + nm, es * R);
+    };
+    if (f64) per_precision("solve_d_", sizeof(double));
+    if (f32) per_precision("solve_f_", sizeof(float));
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
         (void)hipGetLastError();
         return;  // no estimate: the allocations report any failure themselves
     }
-    // room for the per-iteration vectors (a few times n and R in FP64) and the flow buffers
-    const size_t reserve = sizeof(double) * 8 * (n + R) + ((size_t)1 << 30);
+    // room for those vectors, the flow buffers and smaller workspaces
+    const size_t reserve = vecs + sizeof(double) * 2 * (size_t)g.pair_px * 4 + ((size_t)1 << 30);
     if (grow + reserve <= free_b) return;
     const size_t avail = free_b > reserve ? free_b - reserve : 0;
     char msg[512];
