@@ -4,6 +4,7 @@
 * Sampled parity: H (blur), Psi and L(v) in FP32 on the whole stack in one launch each; the
   oracle recomputes the first and last frame (or pair) of every sequence in FP64 from the
   same FP32 inputs.
+* A ragged subset of five sequences solved against the oracle's stored run (FP64 and FP32).
 * The solve in its benchmark configuration (FP32 operators, FP64 Krylov, autotuned tiles)
   with the launch sequences replayed from HIP graphs gives bit for bit the eagerly launched
   solve, and its error decreases.  (The oracle's full solve at this size would take hours;
@@ -96,3 +97,38 @@ def test_solve_ragged40_graph_matches_eager(rag):
         assert got.rre == ref.rre and got.lambdas == ref.lambdas, rep
     assert ref.iters == 6 and all(np.isfinite(ref.rre))
     assert ref.rre[-1] < ref.rre[0]
+
+
+@pytest.mark.parametrize("op", ["f64", "f32"])
+def test_ragged_subset_solve_against_oracle(op):
+    """The five smallest sequences of the 40 (80^2 x 8 .. 115^2 x 12, 410,305 pixels) as one
+    ragged batch, 13 iterations with one flow update on a nonzero image, against the oracle's
+    stored run (tests/golden/ragged5.json, written by make_ragged5.py): FP64 operators give the
+    oracle's lambda of every iteration and its RRE trajectory; FP32 operators its final RRE to
+    1e-4 (the solve bar)."""
+    import json
+    import os
+    import sys
+    import torch
+    from paper_2501_12497_amd import binding as B
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    sys.path.insert(0, here)
+    try:
+        from make_ragged5 import subset
+    finally:
+        sys.path.remove(here)
+    G = json.load(open(os.path.join(here, "ragged5.json")))
+    wl, pick, seqs, ops, ut, b, delta = subset()
+    assert pick == G["pick"]
+    stack = B.Stack([(s.n_t, s.ny, s.nx) for s in seqs])
+    plan = B.plan_blur(stack, 9, 2.0)
+    print(f"ragged subset solve {op}", flush=True)
+    res = B.solve_joint(plan, torch.as_tensor(b, device="cuda"), delta, u_true=torch.as_tensor(ut, device="cuda"),
+                        op_dtype=op, **G["params"])
+    assert res.iters == G["iters"]
+    if op == "f64":
+        assert res.dp_status == G["dp_status"]
+        np.testing.assert_allclose(res.lambdas, G["lambdas"], rtol=1e-6)
+        np.testing.assert_allclose(res.rre, G["rre"], rtol=0, atol=1e-8)
+    else:
+        assert abs(res.rre[-1] - G["rre"][-1]) <= 1e-4, (res.rre[-1], G["rre"][-1])
