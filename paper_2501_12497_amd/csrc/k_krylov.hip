@@ -389,7 +389,9 @@ __global__ void k_axpy_conv(int64_t n, const TX* __restrict__ in, const double* 
         out[i] = (double)in[i] + a * q[i];
 }
 
-// Weighted Gram G = X^T diag(w) X (K <= 64; w = 1 when null) on the FP64 matrix cores.
+// Weighted Gram G = X^T diag(w) X (w = 1 when null) on the FP64 matrix cores: up to 40
+// columns on the 4x4x4 form below (k_wgram_quad), 41..64 columns and the diagonal tiles of
+// wider bases on the 16x16x4 form (k_wgram_part), the tiles above them by k_wgram_rect.
 // v_mfma_f64_16x16x4f64 multiplies a 16x4 block A by a 4x16 block B: lane l supplies
 // A[l%16][l/16] and B[l/16][l%16], and the 16x16 result sits in four doubles per lane,
 // D[l/16 + 4v][l%16].  Here A[i][k] = X[row_k][16gi + i] and B[k][j] = w[row_k] X[row_k][16gj + j]
@@ -578,6 +580,233 @@ __global__ __launch_bounds__(1024) void k_wgram_final(int nb, int K, int G, cons
     const int i = 16 * gi + (l >> 4) + 4 * v, j = 16 * gj + (l & 15);
     // a diagonal block holds both (i, j) and (j, i), which round differently: the upper one
     // is written to both triangles, so G is exactly symmetric and every entry has one writer
+    if (i <= j && j < K) {
+        Gm[(int64_t)i * ldg + j] = sum;
+        Gm[(int64_t)j * ldg + i] = sum;
+    }
+}
+
+// Weighted Gram on the 4x4x4 FP64 MFMA (K <= 4 * GRAM_QUADS).  v_mfma_f64_4x4x4f64 holds four
+// independent products of a 4x4 block A by a 4x4 block B: in block b, lane l = 16k + 4b + i
+// supplies A[i][k] and lane 16k + 4b + j supplies B[k][j], and the result D[i][j] of block b
+// sits in lane 16i + 4b + j.  The four blocks take four different row groups of one 4x4 tile
+// of G: with x_r the row r of X, a tile (qa, qb) of column quads qa <= qb gets
+// A[i][k] = x_r[4qa + i] and B[k][j] = w_r x_r[4qb + j] for the row r of (block, k), so each
+// instruction adds 16 rows to one 4x4 tile and every tile costs 16 multiply-adds per row:
+// ceil(K/4)(ceil(K/4)+1)/2 tiles instead of the 16-column blocks' padding (at K = 39, 880
+// instead of 1536 per row).
+//
+// A lane owns row slot s = l/4 and column i = l%4 of each quad: it reads the 16 bytes of rows
+// r0 + RPL s .. r0 + RPL s + RPL - 1 (RPL = 4 floats or 2 doubles) of column 4q + i, so a load
+// instruction covers 256 contiguous bytes of each of four columns, and a wave step covers
+// 16 RPL rows; the step's t-th instructions take row r0 + RPL s + t of every slot.  The next
+// step's loads are issued before the current step's MFMAs.  At the end the four row groups of
+// a result are summed across lanes (l, l^4, l^8, l^12), the waves of a workgroup in LDS in a
+// fixed order, and stage 2 sums the workgroups' partials in a fixed order.
+static constexpr int GRAM_QUADS = 10;   // most column quads of the 4x4x4 form (K <= 40)
+
+template <class TX, int NQ>
+struct QuadRows {
+    static constexpr int RPL = 16 / (int)sizeof(TX);
+    TX x[NQ][RPL];    // [column quad][row t]
+    double w[RPL];
+};
+
+// Row weights of the quad kernels: none (1), read from an FP64 buffer, or formed from nu.
+enum QuadWeight { QW_ONE = 0, QW_BUF = 1, QW_NU = 2 };
+
+// This lane's rows rb .. rb + RPL - 1 (rb = r0 + RPL (lane/4)), all below n, of columns
+// 4q + lane%4, with 16-byte loads and no branches (requires ld % RPL == 0, 16-byte aligned X
+// and, for QW_BUF, w).  Columns at or beyond K exist only in the last quad; they read column
+// K - 1 instead.  A result D[i][j] involves only column i of the A operand and column j of
+// the B operand, so those copies reach only entries with i or j at or beyond K, which stage 2
+// never writes.
+template <class TX, int NQ, int WK>
+__device__ __forceinline__ void quad_load_full(QuadRows<TX, NQ>& st, const TX* __restrict__ X, int64_t ld,
+                                               const void* __restrict__ wv, int K, int64_t rb, int ci,
+                                               double eps2) {
+    constexpr int RPL = QuadRows<TX, NQ>::RPL;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int col = 4 * q + ci;
+        const int cl = (q == NQ - 1) ? min(col, K - 1) : col;   // (only the last quad can pass K)
+        const TX* src = X + (int64_t)cl * ld + rb;
+        if constexpr (sizeof(TX) == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(src);
+            st.x[q][0] = v.x;
+            st.x[q][1] = v.y;
+            st.x[q][2] = v.z;
+            st.x[q][3] = v.w;
+        } else {
+            const double2 v = *reinterpret_cast<const double2*>(src);
+            st.x[q][0] = v.x;
+            st.x[q][1] = v.y;
+        }
+    }
+    if constexpr (WK == QW_BUF) {
+        const double* __restrict__ w = static_cast<const double*>(wv);
+#pragma unroll
+        for (int t = 0; t < RPL; t += 2) {
+            const double2 v = *reinterpret_cast<const double2*>(w + rb + t);
+            st.w[t] = v.x;
+            st.w[t + 1] = v.y;
+        }
+    } else if constexpr (WK == QW_NU) {
+        const TX* __restrict__ nu = static_cast<const TX*>(wv);
+        if constexpr (sizeof(TX) == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(nu + rb);
+            const double a[4] = {(double)v.x, (double)v.y, (double)v.z, (double)v.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) st.w[t] = 1.0 / sqrt(a[t] * a[t] + eps2);
+        } else {
+            const double2 v = *reinterpret_cast<const double2*>(nu + rb);
+            st.w[0] = 1.0 / sqrt(v.x * v.x + eps2);
+            st.w[1] = 1.0 / sqrt(v.y * v.y + eps2);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) st.w[t] = 1.0;
+    }
+}
+
+// The same rows with one guarded load per element: rows at or beyond n and columns at or beyond
+// K read as zero (the ragged last step, and any step of unaligned columns).
+template <class TX, int NQ, int WK>
+__device__ __forceinline__ void quad_load_guarded(QuadRows<TX, NQ>& st, const TX* __restrict__ X, int64_t ld,
+                                                  const void* __restrict__ wv, int64_t n, int K, int64_t rb, int ci,
+                                                  double eps2) {
+    constexpr int RPL = QuadRows<TX, NQ>::RPL;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+        const int64_t r = rb + t;
+        const bool in = r < n;
+        if constexpr (WK == QW_NU)
+            st.w[t] = in ? row_weight<TX, true>(wv, r, eps2) : 0.0;
+        else if constexpr (WK == QW_BUF)
+            st.w[t] = in ? static_cast<const double*>(wv)[r] : 0.0;
+        else
+            st.w[t] = in ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int col = 4 * q + ci;
+            st.x[q][t] = (in && col < K) ? X[(int64_t)col * ld + r] : TX(0);
+        }
+    }
+}
+
+// The MFMAs of one step: every tile (qa <= qb) and row t of the lanes' slots.
+template <class TX, int NQ>
+__device__ __forceinline__ void quad_mfma(const QuadRows<TX, NQ>& st, double* acc) {
+#pragma unroll
+    for (int t = 0; t < QuadRows<TX, NQ>::RPL; ++t) {
+        double a[NQ], bw[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            a[q] = (double)st.x[q][t];
+            bw[q] = a[q] * st.w[t];
+        }
+        int p = 0;
+#pragma unroll
+        for (int qa = 0; qa < NQ; ++qa)
+#pragma unroll
+            for (int qb = qa; qb < NQ; ++qb, ++p)
+                acc[p] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[qa], bw[qb], acc[p], 0, 0, 0);
+    }
+}
+
+template <class TX, int NQ, bool VEC, int W, int WK>
+__global__ __launch_bounds__(64 * W) void k_wgram_quad(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
+                                                       const void* __restrict__ w, double eps2,
+                                                       double* __restrict__ part) {
+    constexpr int RPL = QuadRows<TX, NQ>::RPL;
+    constexpr int STEP = 16 * RPL;
+    constexpr int NT = NQ * (NQ + 1) / 2;
+    __shared__ double sred[W][NT * 16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ci = lane & 3;
+    const int64_t slot = RPL * (lane >> 2);
+    double acc[NT];
+#pragma unroll
+    for (int p = 0; p < NT; ++p) acc[p] = 0.0;
+    // contiguous steps per wave; steps below n / STEP hold no row at or beyond n
+    const int64_t steps = (n + STEP - 1) / STEP;
+    const int64_t nw = (int64_t)gridDim.x * W;
+    const int64_t gw = (int64_t)blockIdx.x * W + wave;
+    const int64_t s_lo = steps * gw / nw, s_hi = steps * (gw + 1) / nw;
+    int64_t st = s_lo;
+    QuadRows<TX, NQ> A, B;
+    if constexpr (VEC) {
+        const int64_t f_hi = std::min<int64_t>(s_hi, n / STEP);
+        if (st < f_hi) {
+            // two buffers in turn: the next step's loads are in flight during this step's MFMAs
+            quad_load_full<TX, NQ, WK>(A, X, ld, w, K, STEP * st + slot, ci, eps2);
+            // (the scheduling barriers keep each buffer's conversions after the other buffer's
+            // MFMAs, so no wait for the loads in flight is placed inside them)
+            for (; st + 2 <= f_hi; st += 2) {
+                quad_load_full<TX, NQ, WK>(B, X, ld, w, K, STEP * (st + 1) + slot, ci, eps2);
+                __builtin_amdgcn_sched_barrier(0);
+                quad_mfma<TX, NQ>(A, acc);
+                __builtin_amdgcn_sched_barrier(0);
+                const int64_t s2 = std::min<int64_t>(st + 2, f_hi - 1);   // (a repeat load at the end)
+                quad_load_full<TX, NQ, WK>(A, X, ld, w, K, STEP * s2 + slot, ci, eps2);
+                __builtin_amdgcn_sched_barrier(0);
+                quad_mfma<TX, NQ>(B, acc);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (st < f_hi) {
+                quad_mfma<TX, NQ>(A, acc);
+                ++st;
+            }
+        }
+    }
+    for (; st < s_hi; ++st) {
+        quad_load_guarded<TX, NQ, WK>(A, X, ld, w, n, K, STEP * st + slot, ci, eps2);
+        quad_mfma<TX, NQ>(A, acc);
+    }
+    // the four row groups of each result, then the waves in order
+#pragma unroll
+    for (int p = 0; p < NT; ++p) {
+        double v = acc[p];
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if ((lane & 12) == 0) sred[wave][p * 16 + (lane >> 4) * 4 + (lane & 3)] = v;
+    }
+    __syncthreads();
+    double* out = part + (int64_t)blockIdx.x * (NT * 16);
+    for (int e = threadIdx.x; e < NT * 16; e += 64 * W) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) sum += sred[q][e];
+        out[e] = sum;
+    }
+}
+
+// Stage 2 of the 4x4x4 form: entry e = 16 p + 4 i + j of tile p (quads qa <= qb in row-major
+// order) summed over the partials in a fixed order; G[4qa + i][4qb + j] written to both
+// triangles when 4qa + i <= 4qb + j < K (the upper entry of a diagonal tile serves both).
+__global__ __launch_bounds__(1024) void k_wgram_final_quad(int nb, int K, int NQ, const double* __restrict__ part,
+                                                           double* __restrict__ Gm, int ldg) {
+    __shared__ double s[16][GRAM_SLAB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ne = NQ * (NQ + 1) / 2 * 16;
+    const int e = blockIdx.x * GRAM_SLAB + lane;
+    double acc = 0.0;
+    if (e < ne)
+        for (int b = wave; b < nb; b += 16) acc += part[(int64_t)b * ne + e];
+    s[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0 || e >= ne) return;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sum += s[q][lane];
+    const int p = e >> 4;
+    int qa = 0, base = 0;
+    while (p >= base + (NQ - qa)) {
+        base += NQ - qa;
+        ++qa;
+    }
+    const int qb = qa + (p - base);
+    const int i = 4 * qa + ((e >> 2) & 3), j = 4 * qb + (e & 3);
     if (i <= j && j < K) {
         Gm[(int64_t)i * ldg + j] = sum;
         Gm[(int64_t)j * ldg + i] = sum;
@@ -972,10 +1201,73 @@ static void wgram_launch_g(Ctx& c, int& nb, bool vec, int64_t n, int K, const TX
     wgram_launch<TX, G, false, NU>(c, n, K, X, ld, w, eps2, part, max_blocks, nb);
 }
 
+template <class TX, int NQ, bool NU>
+static void wgram_quad_launch(Ctx& c, bool vec, int64_t n, int K, const TX* X, int64_t ld, const void* w,
+                              double eps2, double* part, int max_blocks, int& nb) {
+    // four waves per workgroup (the largest forms hold one wave per SIMD: 294 registers at
+    // 10 FP32 quads), at least 16 steps per wave, at most max_blocks partials
+    constexpr int W = 4;
+    constexpr int STEP = 16 * QuadRows<TX, NQ>::RPL;
+    const int64_t steps = (n + STEP - 1) / STEP;
+    nb = (int)std::max<int64_t>(1, std::min<int64_t>(max_blocks, cdiv(steps, 16 * W)));
+    constexpr int WN = NU ? QW_NU : QW_BUF;
+    if (vec) {
+        if (NU || w)
+            hipLaunchKernelGGL((k_wgram_quad<TX, NQ, true, W, WN>), dim3(nb), dim3(64 * W), 0, c.stream, n, K, X, ld,
+                               w, eps2, part);
+        else
+            hipLaunchKernelGGL((k_wgram_quad<TX, NQ, true, W, QW_ONE>), dim3(nb), dim3(64 * W), 0, c.stream, n, K, X,
+                               ld, w, eps2, part);
+    } else {
+        if (NU || w)
+            hipLaunchKernelGGL((k_wgram_quad<TX, NQ, false, W, WN>), dim3(nb), dim3(64 * W), 0, c.stream, n, K, X,
+                               ld, w, eps2, part);
+        else
+            hipLaunchKernelGGL((k_wgram_quad<TX, NQ, false, W, QW_ONE>), dim3(nb), dim3(64 * W), 0, c.stream, n, K,
+                               X, ld, w, eps2, part);
+    }
+}
+
+// K <= 4 GRAM_QUADS: stage 1 on the 4x4x4 form, then its fixed-order stage 2 into G.
+template <class TX, bool NU>
+static void wgram_quad_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const void* w, double eps2,
+                              double* G, int ldg, double* part, int max_blocks, bool timed) {
+    constexpr int RPL = QuadRows<TX, 1>::RPL;
+    const int NQ = (K + 3) / 4;
+    const bool vec = (ld % RPL == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                     (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
+    int nb = 1;
+    {
+        ScopedTime st(timed ? &c : nullptr, "wgram", (double)n * ((double)sizeof(TX) * K + 8.0),
+                      (double)n * K * (K + 1));
+        switch (NQ) {
+            case 1: wgram_quad_launch<TX, 1, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 2: wgram_quad_launch<TX, 2, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 3: wgram_quad_launch<TX, 3, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 4: wgram_quad_launch<TX, 4, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 5: wgram_quad_launch<TX, 5, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 6: wgram_quad_launch<TX, 6, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 7: wgram_quad_launch<TX, 7, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 8: wgram_quad_launch<TX, 8, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            case 9: wgram_quad_launch<TX, 9, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+            default: wgram_quad_launch<TX, GRAM_QUADS, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
+        }
+        MMOF_LAUNCH_CHECK();
+    }
+    const int ne = NQ * (NQ + 1) / 2 * 16;
+    hipLaunchKernelGGL(k_wgram_final_quad, dim3((unsigned)cdiv((int64_t)ne, GRAM_SLAB)), dim3(1024), 0, c.stream, nb,
+                       K, NQ, part, G, ldg);
+    MMOF_LAUNCH_CHECK();
+}
+
 // Stage 1 for 1..4 column blocks, then the fixed-order stage 2 into G.
 template <class TX, bool NU>
 static void wgram_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const void* w, double eps2, double* G,
                          int ldg, double* part, int max_blocks, bool timed) {
+    if (K <= 4 * GRAM_QUADS) {
+        wgram_quad_stages<TX, NU>(c, n, K, X, ld, w, eps2, G, ldg, part, max_blocks, timed);
+        return;
+    }
     const int Gb = (K + 15) / 16;
     const int np = Gb * (Gb + 1) / 2;
     int nb = 1;  // stage-1 workgroups (partials), set by the launch

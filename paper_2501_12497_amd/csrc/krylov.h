@@ -43,6 +43,7 @@ void axpy_conv(Ctx& c, int64_t n, const TX* in, const double* q, const double* s
 template <class TX>
 void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w);
 // G (K x K, leading dim ldg) = X^T diag(w) X   (w == null: unweighted), FP64 on the matrix cores
+// (v_mfma_f64_4x4x4f64 in 4-column quads for K <= 40, 16-column blocks above)
 template <class TX>
 void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg);
 // The same Gram without device allocation: weights formed in the kernel from nu (null: 1),
