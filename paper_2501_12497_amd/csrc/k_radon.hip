@@ -87,11 +87,50 @@ __device__ __forceinline__ T hat_row_inner(const T* __restrict__ img, int roff, 
     return w0 * q.y + w1 * q.z + w2 * (lo ? q.x : q.w);
 }
 
+// Interior rows of an FP32 image in groups of RG: the ray centre of the group's first row in
+// FP64, split into its floor and an FP32 fraction fb; row k of the group at t = fb + k step
+// in FP32 (error below 1e-6 px for |step| <= 1, k < 8), pixel floor(t) + floor(xs) through a
+// floor-convert and weight fraction fract(t).  The four pixels xi - 1 .. xi + 2 come in one
+// 16-byte load (a 32-bit byte offset from the frame base, so the frame must hold fewer than
+// 2^30 pixels) and their weights max(0, 1 - |a| |x - xs|) are single FMAs whose results lie in
+// [0, 1], so the clamp of the outer two is the FMA's output clamp.  The caller guarantees
+// 1 + INTERIOR_MARGIN <= xs < ncol - 2 - INTERIOR_MARGIN on every row it passes, so the FP32
+// position never leaves the row.
+static constexpr int RG = 8;
+static constexpr double INTERIOR_MARGIN = 1e-3;
+
+__device__ __forceinline__ float hat_rows_f32(const float* __restrict__ img, int r, int ncol, double xs0,
+                                              double step, float aa) {
+    const double xb = fma((double)r, step, xs0);
+    const double flb = floor(xb);
+    const float fb = (float)(xb - flb);
+    const float stepf = (float)step;
+    const float c1 = 1.f - aa, c2 = 1.f - 2.f * aa;
+    const uint32_t rowb = (uint32_t)(r * ncol + (int)flb - 1) * 4u;
+    const uint32_t ncolb = (uint32_t)ncol * 4u;
+    const char* __restrict__ base = reinterpret_cast<const char*>(img);
+    typedef float F4 __attribute__((ext_vector_type(4), aligned(4)));
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int k = 0; k < RG; ++k) {
+        const float t = fmaf((float)k, stepf, fb);
+        int xr;
+        asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(xr) : "v"(t));
+        const float fr = __builtin_amdgcn_fractf(t);
+        const F4 q = *reinterpret_cast<const F4*>(base + (rowb + (uint32_t)k * ncolb + ((uint32_t)xr << 2)));
+        s0 = fmaf(__builtin_amdgcn_fmed3f(fmaf(-aa, fr, c1), 0.f, 1.f), q.x, s0);
+        s1 = fmaf(fmaf(-aa, fr, 1.f), q.y, s1);
+        s0 = fmaf(fmaf(aa, fr, c1), q.z, s0);
+        s1 = fmaf(__builtin_amdgcn_fmed3f(fmaf(aa, fr, c2), 0.f, 1.f), q.w, s1);
+    }
+    return s0 + s1;
+}
+
 // One workgroup of 8 waves per (frame, ANG consecutive angles, 64 bins): lane = bin, wave
 // w takes angle w / (8/ANG) and the (w % (8/ANG))-th block of rows, walking four rows per
-// step so that their loads are in flight together.  The waves of one workgroup read
-// overlapping spans of the same rows, so a wider angle group reuses the image through the
-// cache; partial sums are added in a fixed order.
+// step (FP32 images: eight, see hat_rows_f32) so that their loads are in flight together.
+// The waves of one workgroup read overlapping spans of the same rows, so a wider angle group
+// reuses the image through the cache; partial sums are added in a fixed order.
 template <class T, int ANG>
 __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ rays, const RadonFrame* __restrict__ rf,
                                                    const double2* __restrict__ trig, const T* __restrict__ u,
@@ -100,9 +139,13 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
     __shared__ T part[8][64];
     const RayTile rt = rays[xcd_remap(blockIdx.x, gridDim.x)];
     const RadonFrame f = rf[rt.frame];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // (uniform: angle, image in SGPRs)
     const int ang = rt.angle + wave / RSL, sl = wave % RSL;
     const int j = rt.bin0 + lane;
+    // FP32 interior rows by hat_rows_f32 (32-bit byte offsets within the frame)
+    const bool f32rows = sizeof(T) == 4 && (int64_t)f.ny * f.nx < ((int64_t)1 << 30);
+    const double margin = f32rows ? INTERIOR_MARGIN : 0.0;
     T acc = T(0);
     if (ang < f.n_ang && j < f.n_bins) {
         const double2 cs = trig[f.trig_off + ang];
@@ -138,16 +181,20 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
             const double t_lo = fmin(ra, rb), t_hi = fmax(ra, rb);
             r_lo = max(r_lo, clamp_row(floor(t_lo) - 1.0));
             r_hi = min(r_hi, clamp_row(ceil(t_hi) + 2.0));
-            const double ia = row_of(1.0), ib = row_of((double)ncol - 2.0);
+            const double ia = row_of(1.0 + margin), ib = row_of((double)ncol - 2.0 - margin);
             in_lo = max(r_lo, clamp_row(ceil(fmin(ia, ib)) + 1.0));
             in_hi = min(r_hi, clamp_row(floor(fmax(ia, ib)) - 1.0));
-        } else if (xs0 >= 1.0 && xs0 < (double)ncol - 2.0) {
+        } else if (xs0 >= 1.0 + margin && xs0 < (double)ncol - 2.0 - margin) {
             in_lo = r_lo;
             in_hi = r_hi;
         }
         if (in_hi < in_lo || ncol < 4) in_hi = in_lo = r_lo;  // no interior (also for rows shorter than 4)
         int r = r_lo;
         for (; r < min(in_lo, r_hi); ++r) acc += hat_row(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
+        if constexpr (sizeof(T) == 4) {
+            if (f32rows)
+                for (; r < in_hi - (RG - 1); r += RG) acc += hat_rows_f32(img, r, ncol, xs0, step, aa);
+        }
         for (; r < in_hi - 3; r += 4) {
             const T a0 = hat_row_inner(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
             const T a1 = hat_row_inner(img, (r + 1) * ncol, ncol, fma((double)(r + 1), step, xs0), aa);
