@@ -71,12 +71,26 @@ __device__ __forceinline__ void dot_row2(const TX* __restrict__ X, int64_t ld, i
     }
 }
 
+// The MM weight 1/sqrt(nu^2 + eps^2) (eps > 0) in FP64, the one formula of every weight path
+// (the buffer, the Gram and the residual with weights formed from nu): the hardware reciprocal
+// square root (relative error below 2^-22) refined by two Newton steps r <- r (3 - x r^2) / 2,
+// each of which squares the relative error, so the result is within a few ulp of the rounded
+// value; a sum too large for the refinement takes the division.
+__device__ __forceinline__ double mm_weight(double a, double eps2) {
+    const double x = fma(a, a, eps2);
+    if (!(x < 1.0e300)) return 1.0 / sqrt(x);
+    const double h = 0.5 * x;
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(-h * r, r, 1.5);
+    r = r * fma(-h * r, r, 1.5);
+    return r;
+}
+
 // FP64 MM weights w2 = 1/sqrt(nu^2 + eps^2) of the rows of Theta.
 template <class TX>
 __global__ void k_mm_weights_f64(int64_t n, const TX* __restrict__ nu, double eps2, double* __restrict__ w) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double a = (double)nu[i];
-        w[i] = 1.0 / sqrt(a * a + eps2);
+        w[i] = mm_weight((double)nu[i], eps2);
     }
 }
 
@@ -416,13 +430,12 @@ struct GramRows {
     double w[4];
 };
 
-// Weight of one row: read from w (NU = false), or formed from nu as 1/sqrt(nu^2 + eps^2) with
-// the arithmetic of k_mm_weights_f64 (NU = true; wv then points to nu in TX).
+// Weight of one row: read from w (NU = false), or formed from nu by mm_weight, the weights of
+// k_mm_weights_f64 (NU = true; wv then points to nu in TX).
 template <class TX, bool NU>
 __device__ __forceinline__ double row_weight(const void* __restrict__ wv, int64_t r, double eps2) {
     if constexpr (NU) {
-        const double a = (double)static_cast<const TX*>(wv)[r];
-        return 1.0 / sqrt(a * a + eps2);
+        return mm_weight((double)static_cast<const TX*>(wv)[r], eps2);
     } else {
         return static_cast<const double*>(wv)[r];
     }
@@ -652,16 +665,18 @@ __device__ __forceinline__ void quad_load_full(QuadRows<TX, NQ>& st, const TX* _
             st.w[t + 1] = v.y;
         }
     } else if constexpr (WK == QW_NU) {
+        // (nu itself: the weights are formed in quad_mfma, after the loads have arrived)
         const TX* __restrict__ nu = static_cast<const TX*>(wv);
         if constexpr (sizeof(TX) == 4) {
             const float4 v = *reinterpret_cast<const float4*>(nu + rb);
-            const double a[4] = {(double)v.x, (double)v.y, (double)v.z, (double)v.w};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) st.w[t] = 1.0 / sqrt(a[t] * a[t] + eps2);
+            st.w[0] = v.x;
+            st.w[1] = v.y;
+            st.w[2] = v.z;
+            st.w[3] = v.w;
         } else {
             const double2 v = *reinterpret_cast<const double2*>(nu + rb);
-            st.w[0] = 1.0 / sqrt(v.x * v.x + eps2);
-            st.w[1] = 1.0 / sqrt(v.y * v.y + eps2);
+            st.w[0] = v.x;
+            st.w[1] = v.y;
         }
     } else {
 #pragma unroll
@@ -681,7 +696,7 @@ __device__ __forceinline__ void quad_load_guarded(QuadRows<TX, NQ>& st, const TX
         const int64_t r = rb + t;
         const bool in = r < n;
         if constexpr (WK == QW_NU)
-            st.w[t] = in ? row_weight<TX, true>(wv, r, eps2) : 0.0;
+            st.w[t] = in ? (double)static_cast<const TX*>(wv)[r] : 0.0;   // (nu; zero rows stay zero below)
         else if constexpr (WK == QW_BUF)
             st.w[t] = in ? static_cast<const double*>(wv)[r] : 0.0;
         else
@@ -694,16 +709,19 @@ __device__ __forceinline__ void quad_load_guarded(QuadRows<TX, NQ>& st, const TX
     }
 }
 
-// The MFMAs of one step: every tile (qa <= qb) and row t of the lanes' slots.
-template <class TX, int NQ>
-__device__ __forceinline__ void quad_mfma(const QuadRows<TX, NQ>& st, double* acc) {
+// The MFMAs of one step: every tile (qa <= qb) and row t of the lanes' slots.  QW_NU: st.w holds
+// nu, and the row weight 1/sqrt(nu^2 + eps^2) is formed here (a row beyond n has x = 0).
+template <class TX, int NQ, int WK>
+__device__ __forceinline__ void quad_mfma(const QuadRows<TX, NQ>& st, double* acc, double eps2) {
 #pragma unroll
     for (int t = 0; t < QuadRows<TX, NQ>::RPL; ++t) {
+        double wt = st.w[t];
+        if constexpr (WK == QW_NU) wt = mm_weight(wt, eps2);
         double a[NQ], bw[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             a[q] = (double)st.x[q][t];
-            bw[q] = a[q] * st.w[t];
+            bw[q] = a[q] * wt;
         }
         int p = 0;
 #pragma unroll
@@ -745,23 +763,23 @@ __global__ __launch_bounds__(64 * W) void k_wgram_quad(int64_t n, int K, const T
             for (; st + 2 <= f_hi; st += 2) {
                 quad_load_full<TX, NQ, WK>(B, X, ld, w, K, STEP * (st + 1) + slot, ci, eps2);
                 __builtin_amdgcn_sched_barrier(0);
-                quad_mfma<TX, NQ>(A, acc);
+                quad_mfma<TX, NQ, WK>(A, acc, eps2);
                 __builtin_amdgcn_sched_barrier(0);
                 const int64_t s2 = std::min<int64_t>(st + 2, f_hi - 1);   // (a repeat load at the end)
                 quad_load_full<TX, NQ, WK>(A, X, ld, w, K, STEP * s2 + slot, ci, eps2);
                 __builtin_amdgcn_sched_barrier(0);
-                quad_mfma<TX, NQ>(B, acc);
+                quad_mfma<TX, NQ, WK>(B, acc, eps2);
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (st < f_hi) {
-                quad_mfma<TX, NQ>(A, acc);
+                quad_mfma<TX, NQ, WK>(A, acc, eps2);
                 ++st;
             }
         }
     }
     for (; st < s_hi; ++st) {
         quad_load_guarded<TX, NQ, WK>(A, X, ld, w, n, K, STEP * st + slot, ci, eps2);
-        quad_mfma<TX, NQ>(A, acc);
+        quad_mfma<TX, NQ, WK>(A, acc, eps2);
     }
     // the four row groups of each result, then the waves in order
 #pragma unroll
@@ -977,6 +995,15 @@ __global__ void k_weight_mul(int64_t n, const double* __restrict__ w, const TX* 
         y[i] = (TX)((double)x[i] * w[i]);
 }
 
+// y = x w with w = mm_weight(nu) formed here (the weights of k_mm_weights_f64).
+template <class TX>
+__global__ void k_weight_mul_nu(int64_t n, const TX* __restrict__ nu, double eps2, const TX* __restrict__ x,
+                                TX* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        y[i] = (TX)((double)x[i] * mm_weight((double)nu[i], eps2));
+    }
+}
+
 // ------------------------------------------------------------------------ host launchers
 
 template <class T>
@@ -1015,6 +1042,14 @@ void weight_mul(Ctx& c, int64_t n, const double* w, const TX* x, TX* y) {
 }
 template void weight_mul<float>(Ctx&, int64_t, const double*, const float*, float*);
 template void weight_mul<double>(Ctx&, int64_t, const double*, const double*, double*);
+
+template <class TX>
+void weight_mul_nu(Ctx& c, int64_t n, const TX* nu, double eps, const TX* x, TX* y) {
+    hipLaunchKernelGGL(k_weight_mul_nu<TX>, grid_for(n, KB, 8192), dim3(KB), 0, c.stream, n, nu, eps * eps, x, y);
+    MMOF_LAUNCH_CHECK();
+}
+template void weight_mul_nu<float>(Ctx&, int64_t, const float*, double, const float*, float*);
+template void weight_mul_nu<double>(Ctx&, int64_t, const double*, double, const double*, double*);
 
 
 // row chunks of 1024 rows (four per thread), but at least 256 chunks (of no fewer than 256
@@ -1238,7 +1273,9 @@ static void wgram_quad_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld,
                      (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     int nb = 1;
     {
-        ScopedTime st(timed ? &c : nullptr, "wgram", (double)n * ((double)sizeof(TX) * K + 8.0),
+        // K columns and the row weights (8 bytes from w, the size of TX from nu, none when null)
+        const double wb = NU ? (double)sizeof(TX) : (w ? 8.0 : 0.0);
+        ScopedTime st(timed ? &c : nullptr, "wgram", (double)n * ((double)sizeof(TX) * K + wb),
                       (double)n * K * (K + 1));
         switch (NQ) {
             case 1: wgram_quad_launch<TX, 1, NU>(c, vec, n, K, X, ld, w, eps2, part, max_blocks, nb); break;
@@ -1276,7 +1313,8 @@ static void wgram_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, cons
     const bool vec = sizeof(TX) == 4 && (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
                      (NU || !w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     {
-        ScopedTime st(timed ? &c : nullptr, "wgram", (double)n * ((double)sizeof(TX) * K + 8.0),
+        const double wb = NU ? (double)sizeof(TX) : (w ? 8.0 : 0.0);
+        ScopedTime st(timed ? &c : nullptr, "wgram", (double)n * ((double)sizeof(TX) * K + wb),
                       (double)n * K * (K + 1));
         switch (Gb) {
             case 1: wgram_launch_g<TX, 1, NU>(c, nb, vec, n, K, X, ld, w, eps2, part, max_blocks); break;
@@ -1336,6 +1374,17 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
 }
 template void wgram<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int);
 template void wgram<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double*, int);
+
+template <class TX>
+void wgram_nu(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TX* nu, double eps, double* G, int ldg) {
+    MMOF_CHECK(K >= 1 && K <= KMAX_SMALL, MMOF_ERR_SHAPE, "too many Krylov columns for weights formed from nu");
+    constexpr int RP = GRAM_RECT * GRAM_RECT;
+    double* part = static_cast<double*>(
+        c.work("wgram_part", sizeof(double) * (size_t)GRAM_BLOCKS * std::max(GRAM_PAIRS, RP) * 256));
+    wgram_stages<TX, true>(c, n, K, X, ld, nu, eps * eps, G, ldg, part, GRAM_BLOCKS, true);
+}
+template void wgram_nu<float>(Ctx&, int64_t, int, const float*, int64_t, const float*, double, double*, int);
+template void wgram_nu<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double, double*, int);
 
 // ------------------------------------------------------------------------ allocation-free Gram
 //

@@ -46,6 +46,10 @@ void mm_weights_f64(Ctx& c, int64_t n, const TX* nu, double eps, double* w);
 // (v_mfma_f64_4x4x4f64 in 4-column quads for K <= 40, 16-column blocks above)
 template <class TX>
 void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, double* G, int ldg);
+// The same Gram with the weights formed in the kernel from nu, 1/sqrt(nu^2 + eps^2) with the
+// arithmetic of mm_weights_f64 (K <= KMAX_SMALL): no weight buffer is written or read.
+template <class TX>
+void wgram_nu(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TX* nu, double eps, double* G, int ldg);
 // The same Gram without device allocation: weights formed in the kernel from nu (null: 1),
 // partials in a file-scope device array (noalloc_scratch_bytes() of it) whose address on the
 // device was looked up by noalloc_init(device) with that device current.
@@ -74,6 +78,9 @@ void put_rowcol(Ctx& c, double* G, int ldg, int j, const double* h);
 // y = w * x
 template <class TX>
 void weight_mul(Ctx& c, int64_t n, const double* w, const TX* x, TX* y);
+// y = w * x with w = 1/sqrt(nu^2 + eps^2) formed from nu (the arithmetic of mm_weights_f64)
+template <class TX>
+void weight_mul_nu(Ctx& c, int64_t n, const TX* nu, double eps, const TX* x, TX* y);
 
 // Small projected solve (one wavefront for K <= 64, four above).  Inputs on the device: GA, GT
 // (K x K, leading dimension KLD),

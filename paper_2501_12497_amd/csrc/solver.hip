@@ -208,10 +208,27 @@ struct Solver {
         if (rep) rep->n_thetaT++;
     }
 
-    // FP64 MM weights of the rows of Theta u: per row, then per group for IsoTV and GS
-    void weights(const TX* nu_, double* w) {
+    // FP64 MM weights of the rows of Theta u: per row, then per group for IsoTV and GS.  Per-row
+    // weights of a Gram with at most KMAX_SMALL columns are not stored: wsrc = nu_, and the
+    // Gram and the residual form each weight 1/sqrt(nu^2 + eps^2) from it (the buffer would
+    // cost a pass of 12 bytes per row and 4 more bytes per row in each of its two readers).
+    const TX* wsrc = nullptr;
+    void weights(const TX* nu_, double* w, int Kg) {
+        const bool grouped = p.reg == MMOF_REG_ISO || p.reg == MMOF_REG_GS;
+        if (!grouped && Kg <= KMAX_SMALL) {
+            wsrc = nu_;
+            return;
+        }
+        wsrc = nullptr;
         mm_weights_f64<TX>(c, R, nu_, p.eps, w);
-        if (p.reg == MMOF_REG_ISO || p.reg == MMOF_REG_GS) launch_group_weights(c, g, dt, p.reg, nu_, p.eps, w);
+        if (grouped) launch_group_weights(c, g, dt, p.reg, nu_, p.eps, w);
+    }
+    // G_T = (P Theta V)^T (P Theta V) for the first Kg columns, with the weights of weights()
+    void gram_theta(int Kg, const TX* TV_, const double* w, double* GT_) {
+        if (wsrc)
+            wgram_nu<TX>(c, R, Kg, TV_, R, wsrc, p.eps, GT_, KLD);
+        else
+            wgram<TX>(c, R, Kg, TV_, R, w, GT_, KLD);
     }
 
     // ---------------------------------------------------------------- graphs
@@ -480,8 +497,8 @@ struct Solver {
                 }
                 // 2. nu = Theta u^(k); FP64 weights; weighted Gram of Theta V
                 if (!nu_fresh) theta(u_op, nu);
-                weights(nu, w2);
-                wgram<TX>(c, R, K, TV, R, w2, GT, KLD);
+                weights(nu, w2, K);
+                gram_theta(K, TV, w2, GT);
                 // 3-5. lambda (discrepancy principle) and z; lambda is kept in sc[2] as the next warm start
                 small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
             }
@@ -495,11 +512,15 @@ struct Solver {
                 gemv_fused<TX, TX>(c, m, K, AV, m, z, 1.0, b, -1.0, nullptr, vin_m, nullptr, nullptr);
                 std::string key = graph_key("residual");
                 key += "|" + std::to_string(reinterpret_cast<uintptr_t>(yR)) + "|" +
-                       std::to_string(reinterpret_cast<uintptr_t>(yW));
+                       std::to_string(reinterpret_cast<uintptr_t>(yW)) + "|" +
+                       std::to_string(reinterpret_cast<uintptr_t>(wsrc));
                 replayable(key, [&] {
                     At(vin_m, out_n);
                     theta(u_op, yR);
-                    weight_mul<TX>(c, R, w2, yR, yW);
+                    if (wsrc)
+                        weight_mul_nu<TX>(c, R, wsrc, p.eps, yR, yW);
+                    else
+                        weight_mul<TX>(c, R, w2, yR, yW);
                     thetaT(yW, out_n2);
                     residual_combine<TX>(c, n, out_n, out_n2, res, r);
                 });
@@ -519,8 +540,8 @@ struct Solver {
                 normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
                 add_column(K, true);
                 if (!nu_fresh) theta(u_op, nu);
-                weights(nu, w2);
-                wgram<TX>(c, R, K + 1, TV, R, w2, GT, KLD);
+                weights(nu, w2, K + 1);
+                gram_theta(K + 1, TV, w2, GT);
                 small_solve(c, K + 1, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
             }
             // counts of work queued ahead, taken back if the iteration ends the solve

@@ -101,6 +101,22 @@ def test_reg_weights_match_oracle(B, reg, which):
     assert_close(w, w_exp, 1e-13, elementwise=True)
 
 
+@pytest.mark.parametrize("eps", [1e-3, 0.05, 10.0])
+def test_mm_weight_precision(B, eps):
+    """The FP64 weight 1/sqrt(nu^2 + eps^2) of every weight path (hardware reciprocal square root
+    and two Newton steps) against the correctly rounded division and square root of numpy, over
+    |nu| from 1e-12 to 1e12: within 1e-15 relative (a few ulp), element by element."""
+    import torch
+    r = np.random.default_rng(43)
+    nrow = sum(sum(k for _, k in _blocks(nt, ny, nx, "aniso", nt > 1)) for nt, ny, nx in SIZES)
+    nu = r.choice([-1.0, 1.0], size=nrow) * 10.0 ** r.uniform(-12, 12, size=nrow)
+    nu[:4] = [0.0, eps, -eps, 1e-300]
+    w = B.reg_weights(B.Stack(SIZES), "aniso", dev(nu, torch.float64), eps).cpu().numpy()
+    w_exp = 1.0 / np.sqrt(nu * nu + eps * eps)
+    rel = np.abs(w - w_exp) / w_exp
+    assert rel.max() <= 1e-15, (rel.max(), nu[np.argmax(rel)])
+
+
 def _disk_seq(nt, n, x0, r2=10.0):
     yy, xx = np.mgrid[0:n, 0:n]
     return np.stack([(((xx - (x0 + t)) ** 2 + (yy - n / 2) ** 2) <= r2).astype(float) for t in range(nt)])
