@@ -225,8 +225,17 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
 // Transpose: one workgroup per 16 x 16 pixel tile.  For each angle the tile projects onto
 // fewer than AW consecutive bins; those sinogram windows are staged in LDS, AC angles at a
 // time (zeros outside the detector), and every pixel then gathers its two hat weights per
-// angle from LDS.
+// angle from LDS.  FP32: per (tile, angle) the detector coordinate of the tile centre in FP64,
+// split into its floor J and an FP32 fraction; a pixel at (dx, dy) from the centre
+// (|dx|, |dy| <= 7.5) is at J + t, t = frac + dx cos + dy sin in FP32 (error below 3e-6 bins),
+// and its two weights come from floor(t) and fract(t); the window has one bin of margin on
+// each side, so a floor one off at an integer stays inside it (and gives the same weights).
 static constexpr int AW = 32, AC = 32;
+
+struct AdjAngle {
+    float frac, c, s;
+    uint32_t base;   // LDS byte offset of bin J in the angle's window (from the window array)
+};
 
 template <class T>
 __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tiles, const RadonFrame* __restrict__ rf,
@@ -248,14 +257,26 @@ __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tile
     const double Y0 = tl.y0 - hy, Y1 = min(tl.y0 + RTH, f.ny) - 1 - hy;
     const T* sino = b + f.sino_off;
     T acc = T(0);
+    // FP32 path: offsets of this pixel from the tile centre, and the per-angle bases
+    __shared__ AdjAngle aa[AC];
+    const double XC = tl.x0 + 0.5 * (RTW - 1) - hx, YC = tl.y0 + 0.5 * (RTH - 1) - hy;
+    const float dxc = (float)(threadIdx.x % RTW) - 0.5f * (RTW - 1);
+    const float dyc = (float)(threadIdx.x / RTW) - 0.5f * (RTH - 1);
     for (int k0 = 0; k0 < f.n_ang; k0 += AC) {
         const int nk = min(AC, f.n_ang - k0);
         __syncthreads();  // the previous chunk's windows are no longer read
         if (threadIdx.x < nk) {
             const double2 cs = trig[f.trig_off + k0 + threadIdx.x];
             const double pmin = cd + fmin(X0 * cs.x, X1 * cs.x) + fmin(Y0 * cs.y, Y1 * cs.y);
-            jlo[threadIdx.x] = (int)floor(pmin) - 1;
+            const int lo = (int)floor(pmin) - 1;
+            jlo[threadIdx.x] = lo;
             scs[threadIdx.x] = cs;
+            if constexpr (sizeof(T) == 4) {
+                const double pc = fma(XC, cs.x, fma(YC, cs.y, cd));
+                const double J = floor(pc);
+                aa[threadIdx.x] = AdjAngle{(float)(pc - J), (float)cs.x, (float)cs.y,
+                                           (uint32_t)((int)threadIdx.x * AW + (int)J - lo) * 4u};
+            }
         }
         __syncthreads();
         for (int i = threadIdx.x; i < nk * AW; i += 256) {
@@ -264,6 +285,33 @@ __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tile
             win[kk][w] = (j >= 0 && j < f.n_bins) ? sino[(int64_t)(k0 + kk) * f.n_bins + j] : T(0);
         }
         __syncthreads();
+        if constexpr (sizeof(T) == 4) {
+            if (inside) {
+                const char* wb = reinterpret_cast<const char*>(&win[0][0]);
+                float acc1 = 0.f, acc2 = 0.f;
+                auto one = [&](int kk) {
+                    const AdjAngle g = aa[kk];
+                    const float t = fmaf(dxc, g.c, fmaf(dyc, g.s, g.frac));
+                    int w0;
+                    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(w0) : "v"(t));
+                    const float fr = __builtin_amdgcn_fractf(t);
+                    const float* q = reinterpret_cast<const float*>(wb + (g.base + ((uint32_t)w0 << 2)));
+                    const float a = q[0], bq = q[1];
+                    acc1 += a;
+                    acc2 = fmaf(fr, bq - a, acc2);
+                };
+                int kk = 0;
+                for (; kk + 4 <= nk; kk += 4) {
+                    one(kk);
+                    one(kk + 1);
+                    one(kk + 2);
+                    one(kk + 3);
+                }
+                for (; kk < nk; ++kk) one(kk);
+                acc += acc1 + acc2;
+            }
+            continue;
+        }
         if (inside) {
 #pragma unroll 4
             for (int kk = 0; kk < nk; ++kk) {
