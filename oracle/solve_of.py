@@ -127,9 +127,10 @@ def gcv_lambda(YV: np.ndarray, LV: np.ndarray, b: np.ndarray) -> float:
 
 
 def solve_of_pair(I: np.ndarray, ell: int = 10, n_iter: int = 20, fixed_lambda: float = 0.0,
-                  basis: list = None, p: int = 2, eps: float = EPS_L1):
+                  basis: list = None, p: int = 2, eps: float = EPS_L1, trace: list = None):
     """s [2, ny, nx] of one pair and the lambda of every iteration (`basis`, if given, receives
-    the final V); p = 1: the p = q = 1 MM variant."""
+    the final V; `trace`, if given, the projected problem (Y V, L V, b) of every iteration, the
+    arguments of gcv_value); p = 1: the p = q = 1 MM variant."""
     ny, nx = I.shape[1:]
     b = -I[2].ravel()
     Y, Yt, L, Lt = pair_ops(I)
@@ -150,6 +151,8 @@ def solve_of_pair(I: np.ndarray, ell: int = 10, n_iter: int = 20, fixed_lambda: 
         if wr is not None:
             LV = np.sqrt(wr)[:, None] * LV
         bw = sd * b
+        if trace is not None:
+            trace.append((YV, LV, bw))
         lam = fixed_lambda if fixed_lambda > 0 else gcv_lambda(YV, LV, bw)
         lams.append(lam)
         z = gcv_value(YV, LV, bw, lam)[1]

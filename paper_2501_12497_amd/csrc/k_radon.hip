@@ -226,10 +226,11 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
 // fewer than AW consecutive bins; those sinogram windows are staged in LDS, AC angles at a
 // time (zeros outside the detector), and every pixel then gathers its two hat weights per
 // angle from LDS.  FP32: per (tile, angle) the detector coordinate of the tile centre in FP64,
-// split into its floor J and an FP32 fraction; a pixel at (dx, dy) from the centre
-// (|dx|, |dy| <= 7.5) is at J + t, t = frac + dx cos + dy sin in FP32 (error below 3e-6 bins),
-// and its two weights come from floor(t) and fract(t); the window has one bin of margin on
-// each side, so a floor one off at an integer stays inside it (and gives the same weights).
+// split into its floor J and an FP32 fraction; a pixel at (dx, dy) from the centre (|dx|, |dy|
+// <= 7.5) is at J + t, t = frac + dx cos + dy sin in FP32 (error below 3e-6 bins), and its two
+// weights come from floor(t) and fract(t); the window has one bin of margin on each side, so a
+// floor one off at an integer stays inside it (and gives the same weights).  FP64: each
+// pixel's position in FP64 from its own coordinates (the tile-centre form measured slower).
 static constexpr int AW = 32, AC = 32;
 
 struct AdjAngle {

@@ -69,12 +69,40 @@ def test_fixed_lambda_fp64(B):
     assert np.all(lam == 0.05)
 
 
+def _gcv_choices_valid(lam, us, ell, n_iter, rel, dr=1):
+    """Each pair's lambdas against the oracle's: equal to 1e-6, or, at the first iteration where
+    they differ, a choice no worse than the oracle's on the oracle's own GCV functional of that
+    iteration, G(lambda_gpu) <= (1 + rel) G(lambda_oracle) (several lambdas can be equally good
+    where G is flat); the iterations after a different choice have another basis and are not
+    compared.  Returns the number of pairs whose lambdas all agree."""
+    lam = np.asarray(lam)
+    agree, p = 0, 0
+    for u in us:
+        I = optflow.of_derivs(u, dr)
+        for t in range(I.shape[0]):
+            trace = []
+            _, el = solve_of.solve_of_pair(I[t], ell, n_iter, 0.0, trace=trace)
+            for k, (lg, lo) in enumerate(zip(lam[p], el)):
+                if abs(lg - lo) <= 1e-6 * abs(lo):
+                    continue
+                YV, LV, bw = trace[k]
+                gg, go = solve_of.gcv_value(YV, LV, bw, lg)[0], solve_of.gcv_value(YV, LV, bw, lo)[0]
+                assert gg <= (1.0 + rel) * go, (p, k, lg, lo, gg, go)
+                break
+            else:
+                agree += 1
+            p += 1
+    return agree
+
+
 @pytest.mark.parametrize("ell,n_iter", [(10, 20), (4, 7), (1, 1)])
 def test_gcv_fp64(B, ell, n_iter):
     import torch
     us = _frames(2)
     got, gotr, lam = _run(B, us, torch.float64, ell=ell, n_iter=n_iter)
     exp, elams = _oracle(us, ell, n_iter)
+    # every choice valid; on these frames also the same choices and flows as the oracle's
+    assert _gcv_choices_valid(lam, us, ell, n_iter, 1e-9) == len(elams)
     np.testing.assert_allclose(lam, np.array(elams), rtol=1e-6)
     assert_close(got, pack(exp), 1e-8)
     # reverse flow of the GPU's own flow
@@ -88,7 +116,10 @@ def test_gcv_fp32_derivatives(B):
     us = [roundtrip32(u) for u in _frames(3)]
     got, _, lam = _run(B, us, torch.float32, ell=10, n_iter=20)
     exp, elams = _oracle(us, 10, 20)
-    assert_close(got, pack(exp), 1e-4)   # (the lambdas may move to another point where G is flat)
+    assert_close(got, pack(exp), 1e-4)
+    # the lambdas may move to another point where G is flat: such a choice must still be as
+    # good on the oracle's functional, to the FP32 derivatives' accuracy
+    _gcv_choices_valid(lam, us, 10, 20, 1e-5)
 
 
 def test_reduced_frames(B):

@@ -213,3 +213,19 @@ def test_l1_converges_to_a_stationary_point():
     grad = Y.T @ (e / np.sqrt(e * e + eps * eps)) + lam * L.T @ (g / np.sqrt(g * g + eps * eps))
     g0 = Y.T @ (-b / np.sqrt(b * b + eps * eps))
     assert np.linalg.norm(grad) <= 1e-3 * np.linalg.norm(g0)
+
+
+def test_trace_holds_each_iterations_problem_and_a_worse_lambda_is_detected():
+    """The per-iteration projected problems (the `trace` hook) reproduce the chosen lambdas,
+    and moving a chosen lambda by two decades raises G by far more than the 1e-9 a GPU choice
+    is allowed (so that validity check can fail)."""
+    I = _pair(11, 6, 7)
+    trace = []
+    _, lams = solve_of.solve_of_pair(I, 3, 4, 0.0, trace=trace)
+    assert len(trace) == len(lams) == 4
+    for (YV, LV, bw), lam in zip(trace, lams):
+        assert YV.shape[1] == LV.shape[1]
+        assert solve_of.gcv_lambda(YV, LV, bw) == lam
+        g0 = solve_of.gcv_value(YV, LV, bw, lam)[0]
+        for f in (1e-2, 1e2):
+            assert solve_of.gcv_value(YV, LV, bw, lam * f)[0] > (1.0 + 1e-9) * g0
