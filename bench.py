@@ -59,6 +59,7 @@ COMPUTE = {
 # the source file it was measured on: traffic is reported only while that source is unchanged.
 TRAFFIC = {
     "wgram": ("profiles/wgram_large1024_traffic.txt", "paper_2501_12497_amd/csrc/k_krylov.hip"),
+    "gemv": ("profiles/gemv_large1024_traffic.txt", "paper_2501_12497_amd/csrc/k_krylov.hip"),
 }
 
 
