@@ -10,7 +10,7 @@
 
 namespace mmof {
 const char* last_error_cstr();
-void radon_plan_init(Ctx& c, Plan& p);
+void radon_plan_init(Ctx& c, Plan& p, const double* cs);  // cs: the host copy of the trig table
 }  // namespace mmof
 
 using namespace mmof;
@@ -131,7 +131,7 @@ static int plan_projector(mmof_ctx ctx, const mmof_stack* stack, const int32_t* 
         p->d_trig.ensure(sizeof(double) * cs.size());
         MMOF_HIP(hipMemcpyAsync(p->d_trig.ptr, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice,
                                 ctx->stream));
-        radon_plan_init(*ctx, *p);  // synchronizes the stream
+        radon_plan_init(*ctx, *p, cs.data());  // synchronizes the stream
         if (kind == 2) fan_plan_init(*ctx, *p);
         *out = p.release();
         return MMOF_OK;

@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tile
 
 // ----------------------------------------------------------------------------- host side
 
-void radon_plan_init(Ctx& c, Plan& p) {
+void radon_plan_init(Ctx& c, Plan& p, const double* cs) {
     Geom& g = *p.geom;
     std::vector<RadonFrame> rfs;
     std::vector<RayTile> rays[4];  // angle groups of 1, 2, 4, 8
@@ -350,10 +350,17 @@ void radon_plan_init(Ctx& c, Plan& p) {
         r.nx = fr.nx;
         rfs.push_back(r);
         p.sino_off.push_back(sino);
+        // a frame's angle groups that walk the rows of u, then those that walk the rows of its
+        // transpose (a group is placed by its first angle): consecutive tiles, which run together
+        // on one XCD (xcd_remap), then read one image, not both
         for (int gi = 0; gi < 4; ++gi) {
             const int ag = 1 << gi;
-            for (int k = 0; k < r.n_ang; k += ag)
-                for (int j0 = 0; j0 < r.n_bins; j0 += 64) rays[gi].push_back(RayTile{(int32_t)fi, k, j0, 0});
+            for (int pass = 0; pass < 2; ++pass)
+                for (int k = 0; k < r.n_ang; k += ag) {
+                    const double c0 = cs[2 * (trig + k)], s0 = cs[2 * (trig + k) + 1];
+                    if ((std::fabs(s0) > std::fabs(c0)) != (pass == 1)) continue;
+                    for (int j0 = 0; j0 < r.n_bins; j0 += 64) rays[gi].push_back(RayTile{(int32_t)fi, k, j0, 0});
+                }
         }
         for (int y0 = 0; y0 < fr.ny; y0 += RTH)
             for (int x0 = 0; x0 < fr.nx; x0 += RTW) px.push_back(Tile{(int32_t)fi, y0, x0, 0});

@@ -122,7 +122,7 @@ void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b);
 void launch_fan_adj(Ctx& c, Plan& p, int dt, const void* b, void* u);
 // Builds the frame table, trig table users and tile lists of a projector plan (radon or fan);
 // the trig table must already be in p.d_trig.
-void radon_plan_init(Ctx& c, Plan& p);
+void radon_plan_init(Ctx& c, Plan& p, const double* cs);  // cs: the host copy of the trig table
 void fan_plan_init(Ctx& c, Plan& p);  // the per-ray table of a fan-beam plan (after radon_plan_init)
 
 }  // namespace mmof
