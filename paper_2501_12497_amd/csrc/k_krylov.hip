@@ -49,12 +49,12 @@ __device__ __forceinline__ double dot_row(const TX* __restrict__ X, int64_t ld, 
     return acc;
 }
 
-// dot_row for the rows i and i + 1 at once (i even, ld even, X aligned to two elements):
-// one 2-element load per column; each row's sum in column order as in dot_row.
+// dot_row for the rows i and i + 1 at once: one 2-element load per column (element-aligned,
+// which global loads accept, so any ld qualifies); each row's sum in column order as in dot_row.
 template <class TX>
 __device__ __forceinline__ void dot_row2(const TX* __restrict__ X, int64_t ld, int64_t i, int K,
                                          const double* __restrict__ h, double& a0, double& a1) {
-    typedef TX V2 __attribute__((ext_vector_type(2)));
+    typedef TX V2 __attribute__((ext_vector_type(2), aligned(sizeof(TX))));
     a0 = 0.0;
     a1 = 0.0;
     for (int j0 = 0; j0 < K; j0 += 8) {
@@ -145,9 +145,10 @@ template <class TX, class TY>
 __global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                               const TY* __restrict__ y, const double* __restrict__ xe,
                                               double* __restrict__ part) {
-    typedef TX VX __attribute__((ext_vector_type(2)));
-    typedef TY VY __attribute__((ext_vector_type(2)));
-    typedef double VD __attribute__((ext_vector_type(2)));
+    // (element-aligned: global multi-word loads accept it, so any ld and any column qualify)
+    typedef TX VX __attribute__((ext_vector_type(2), aligned(sizeof(TX))));
+    typedef TY VY __attribute__((ext_vector_type(2), aligned(sizeof(TY))));
+    typedef double VD __attribute__((ext_vector_type(2), aligned(sizeof(double))));
     __shared__ double s8[4][8];
     const int Kt = K + (xe ? 1 : 0);
     const int64_t nb = gridDim.x;
@@ -442,8 +443,8 @@ __device__ __forceinline__ double row_weight(const void* __restrict__ wv, int64_
 }
 
 // Rows r0 + 4q + k (k < 4) of column blocks g < G for this lane; rows at or beyond n and
-// columns at or beyond K read as zero.  VEC: the four rows are loaded with vector loads
-// (requires ld % 4 == 0, 16-byte aligned X and rows r0 + 4q + 3 < n).  The row weights come
+// columns at or beyond K read as zero.  VEC: the four rows are loaded with one vector load
+// (element-aligned X suffices; rows r0 + 4q + 3 < n).  The row weights come
 // from w (NU = false; null: 1) or from nu (NU = true, see row_weight).
 template <class TX, int G, bool VEC, bool NU = false>
 __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restrict__ X, int64_t ld,
@@ -459,7 +460,8 @@ __device__ __forceinline__ void gram_rows(GramRows<TX, G>& st, const TX* __restr
             if (col < K) {
                 const TX* src = X + (int64_t)col * ld + rb;
                 if constexpr (sizeof(TX) == 4) {
-                    const float4 v = *reinterpret_cast<const float4*>(src);
+                    typedef float F4e __attribute__((ext_vector_type(4), aligned(4)));
+                    const F4e v = *reinterpret_cast<const F4e*>(src);
                     st.x[g][0] = v.x;
                     st.x[g][1] = v.y;
                     st.x[g][2] = v.z;
@@ -629,8 +631,9 @@ struct QuadRows {
 enum QuadWeight { QW_ONE = 0, QW_BUF = 1, QW_NU = 2 };
 
 // This lane's rows rb .. rb + RPL - 1 (rb = r0 + RPL (lane/4)), all below n, of columns
-// 4q + lane%4, with 16-byte loads and no branches (requires ld % RPL == 0, 16-byte aligned X
-// and, for QW_BUF, w).  Columns at or beyond K exist only in the last quad; they read column
+// 4q + lane%4, with 16-byte loads and no branches (X needs only element alignment: global
+// multi-word loads accept it, so columns of any leading dimension qualify; w and nu, read at
+// rows rb that are multiples of RPL, must be 16-byte aligned).  Columns at or beyond K exist only in the last quad; they read column
 // K - 1 instead.  A result D[i][j] involves only column i of the A operand and column j of
 // the B operand, so those copies reach only entries with i or j at or beyond K, which stage 2
 // never writes.
@@ -644,17 +647,10 @@ __device__ __forceinline__ void quad_load_full(QuadRows<TX, NQ>& st, const TX* _
         const int col = 4 * q + ci;
         const int cl = (q == NQ - 1) ? min(col, K - 1) : col;   // (only the last quad can pass K)
         const TX* src = X + (int64_t)cl * ld + rb;
-        if constexpr (sizeof(TX) == 4) {
-            const float4 v = *reinterpret_cast<const float4*>(src);
-            st.x[q][0] = v.x;
-            st.x[q][1] = v.y;
-            st.x[q][2] = v.z;
-            st.x[q][3] = v.w;
-        } else {
-            const double2 v = *reinterpret_cast<const double2*>(src);
-            st.x[q][0] = v.x;
-            st.x[q][1] = v.y;
-        }
+        typedef TX VR __attribute__((ext_vector_type(RPL), aligned(sizeof(TX))));
+        const VR v = *reinterpret_cast<const VR*>(src);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) st.x[q][t] = v[t];
     }
     if constexpr (WK == QW_BUF) {
         const double* __restrict__ w = static_cast<const double*>(wv);
@@ -1059,12 +1055,13 @@ int mdot_blocks(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, nb));
 }
 
-// Two rows per lane (k_mdot2) when every column, y and xe allow 2-element loads.
+// Two rows per lane (k_mdot2) when every column, y and xe are element-aligned (2-element
+// loads need no more).
 template <class TX, class TY>
 static bool mdot_pairs(const TX* X, int64_t ld, const TY* y, const double* xe) {
-    return ld % 2 == 0 && reinterpret_cast<uintptr_t>(X) % (2 * sizeof(TX)) == 0 &&
-           reinterpret_cast<uintptr_t>(y) % (2 * sizeof(TY)) == 0 &&
-           (!xe || reinterpret_cast<uintptr_t>(xe) % (2 * sizeof(double)) == 0);
+    (void)ld;
+    return reinterpret_cast<uintptr_t>(X) % sizeof(TX) == 0 && reinterpret_cast<uintptr_t>(y) % sizeof(TY) == 0 &&
+           (!xe || reinterpret_cast<uintptr_t>(xe) % sizeof(double) == 0);
 }
 
 template <class TX, class TY>
@@ -1137,7 +1134,7 @@ void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double*
         return;
     }
     // two rows per lane when the columns allow 2-element loads (the grid covers row pairs)
-    const bool pair = ld % 2 == 0 && reinterpret_cast<uintptr_t>(X) % (2 * sizeof(TX)) == 0;
+    const bool pair = reinterpret_cast<uintptr_t>(X) % sizeof(TX) == 0;
     // pairs: up to 1024 workgroups of contiguous row chunks; otherwise a grid-strided walk
     const dim3 grid = pair ? dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 2 * KB))))
                            : grid_for(n, KB, 2048);
@@ -1269,7 +1266,8 @@ static void wgram_quad_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld,
                               double* G, int ldg, double* part, int max_blocks, bool timed) {
     constexpr int RPL = QuadRows<TX, 1>::RPL;
     const int NQ = (K + 3) / 4;
-    const bool vec = (ld % RPL == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+    (void)RPL;
+    const bool vec = (reinterpret_cast<uintptr_t>(X) % sizeof(TX) == 0) &&
                      (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     int nb = 1;
     {
@@ -1310,7 +1308,7 @@ static void wgram_stages(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, cons
     int nb = 1;  // stage-1 workgroups (partials), set by the launch
     // (vector loads for FP32 columns; FP64 columns load a double per row, which keeps the
     // row buffers in registers; the vector path also reads w with 16-byte loads)
-    const bool vec = sizeof(TX) == 4 && (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+    const bool vec = sizeof(TX) == 4 && (reinterpret_cast<uintptr_t>(X) % 4 == 0) &&
                      (NU || !w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     {
         const double wb = NU ? (double)sizeof(TX) : (w ? 8.0 : 0.0);
@@ -1342,7 +1340,7 @@ void wgram(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* w, d
     // more than 64 columns: tiles of 64 x 64 entries -- the diagonal tiles by the kernel above,
     // the tiles above them by k_wgram_rect, one partial buffer reused tile after tile (stream order)
     const int nsb = (K + 63) / 64;
-    const bool vec = sizeof(TX) == 4 && (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+    const bool vec = sizeof(TX) == 4 && (reinterpret_cast<uintptr_t>(X) % 4 == 0) &&
                      (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
     for (int a = 0; a < nsb; ++a) {
         const int Ka = std::min(64, K - 64 * a);
