@@ -3,7 +3,9 @@
 * weighted Gram X^T diag(w2) X on the matrix cores vs numpy, K = 1..256 (all block-grid shapes,
   the 64-column tiles beyond 64 and a ragged last tile);
 * projected solve + discrepancy principle vs the oracle's bisection on the same Grams, on the
-  one-wave path (K <= 64) and the multi-wave path (up to 256).
+  one-wave path (K <= 64) and the multi-wave path (up to 256);
+* the Gram, inner products and column combinations on bases whose columns are only
+  element-aligned (odd leading dimension, base one element past a 16-byte boundary).
 """
 import numpy as np
 import pytest
@@ -86,3 +88,36 @@ def test_weighted_gram_is_symmetric_and_rejects_more_than_256_columns(B):
     with pytest.raises(MMOFError) as e:
         B.weighted_gram(torch.zeros((257, 10), dtype=torch.float64, device="cuda"))
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("which", ["f64", "f32"])
+@pytest.mark.parametrize("K", [7, 39, 70])
+def test_unaligned_bases(B, which, K):
+    """The Gram, the inner products and the column combinations on a basis that starts one
+    element past a 16-byte boundary and has an odd leading dimension: every column then starts
+    at an address that is only element-aligned, which their vector loads must accept."""
+    import torch
+    dt = torch.float64 if which == "f64" else torch.float32
+    r = np.random.default_rng(7 * K)
+    n = 40001 + 2 * K
+    X = r.standard_normal((K, n))
+    nu = r.standard_normal(n) * np.logspace(-3, 0, n)
+    if dt == torch.float32:
+        X = X.astype(np.float32).astype(np.float64)
+        nu = nu.astype(np.float32).astype(np.float64)
+    buf = torch.zeros(K * n + 1, dtype=dt, device="cuda")
+    buf[1:] = torch.as_tensor(X.ravel(), dtype=dt, device="cuda")
+    Xd = buf[1:].view(K, n)
+    assert Xd.data_ptr() % 16 != 0
+    w = mmgks.mm_weights_sq(nu, 1e-3)
+    G = B.weighted_gram(Xd, torch.as_tensor(nu, dtype=dt, device="cuda"), 1e-3).cpu().numpy()
+    exp = X @ (w[:, None] * X.T)
+    assert np.abs(G - exp).max() <= 1e-12 * np.abs(exp).max()
+    y = r.standard_normal(n)
+    d = B.block_dot(Xd, torch.as_tensor(y, device="cuda")).cpu().numpy()
+    ed = X @ y
+    assert np.abs(d - ed).max() <= 1e-12 * np.abs(X).sum(axis=1).max() * np.abs(y).max()
+    z = r.standard_normal(K)
+    u = B.block_combine(Xd, torch.as_tensor(z, device="cuda")).cpu().numpy()
+    eu = z @ X
+    assert np.abs(u - eu).max() <= 1e-12 * (np.abs(z) @ np.abs(X)).max()
