@@ -87,6 +87,37 @@ template <class T>
 __device__ __forceinline__ void st4(T* p, const Quad<T>& q) {
     *reinterpret_cast<Quad<T>*>(p) = q;
 }
+// The same four values from an address aligned to one element (global multi-word accesses
+// accept it), and the first nv of them (nv < 4: the rest read as zero / are not written).
+template <class T>
+__device__ __forceinline__ Quad<T> ld4u(const T* p) {
+    typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+    const V4 v = *reinterpret_cast<const V4*>(p);
+    return Quad<T>{{v.x, v.y, v.z, v.w}};
+}
+template <class T>
+__device__ __forceinline__ void st4u(T* p, const Quad<T>& q) {
+    typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+    *reinterpret_cast<V4*>(p) = V4{q.v[0], q.v[1], q.v[2], q.v[3]};
+}
+template <class T>
+__device__ __forceinline__ Quad<T> ld4n(const T* p, int nv) {
+    if (nv >= 4) return ld4u(p);
+    Quad<T> q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q.v[j] = j < nv ? p[j] : T(0);
+    return q;
+}
+template <class T>
+__device__ __forceinline__ void st4n(T* p, const Quad<T>& q, int nv) {
+    if (nv >= 4) {
+        st4u(p, q);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j < nv) p[j] = q.v[j];
+}
 template <class T>
 __device__ __forceinline__ Quad<T> zero4() {
     return Quad<T>{{T(0), T(0), T(0), T(0)}};

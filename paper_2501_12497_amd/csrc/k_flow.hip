@@ -134,10 +134,12 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols(const Tile* __restrict__ 
     }
 }
 
-// Vector forms of the two kernels above, for stacks whose frame widths are multiples of 4:
-// each thread owns 4 consecutive pixels of one row of a (4*LW)-pixel-wide tile, so flows,
-// the subtracted frame and the output move as 4-element vectors (16 bytes per FP32 access);
-// the bilinear samples stay single loads.  Values equal those of the scalar kernels.
+// Vector forms of the two kernels above: each thread owns 4 consecutive pixels of one row of
+// a (4*LW)-pixel-wide tile, so flows, the subtracted frame and the output move as 4-element
+// vectors (16 bytes per FP32 access, from element-aligned addresses: frames of any width and
+// offset); a row whose width is not a multiple of 4 ends with a thread of 1..3 pixels, whose
+// accesses go element by element.  The bilinear samples stay single loads.  Values equal those
+// of the scalar kernels.
 template <class T, int INTERP, int LW>
 __global__ __launch_bounds__(256) void k_flow_fwd4(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                    const T* __restrict__ u, const T* __restrict__ v,
@@ -151,15 +153,16 @@ __global__ __launch_bounds__(256) void k_flow_fwd4(const Tile* __restrict__ tile
     const int64_t p = (int64_t)y * f.nx + x;
     const T* ut = u + f.off;
     const T* ut1 = ut + np;
+    const int nv = min(4, f.nx - x);   // (fewer than 4 at the end of a row whose width is not a multiple of 4)
     const T* vf = v + 2 * f.pair_off;
-    const Quad<T> vx = ld4(vf + p), vy = ld4(vf + np + p);
+    const Quad<T> vx = ld4n(vf + p, nv), vy = ld4n(vf + np + p, nv);
     const T* src = direction > 0 ? ut1 : ut;
-    const Quad<T> sub = ld4((direction > 0 ? ut : ut1) + p);
+    const Quad<T> sub = ld4n((direction > 0 ? ut : ut1) + p, nv);
     Quad<T> o;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
         o.v[j] = warp_sample<T, INTERP>(src, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - sub.v[j];
-    st4(r + f.pair_off + p, o);
+    st4n(r + f.pair_off + p, o, nv);
 }
 
 template <class T, int INTERP, int LW>
@@ -178,24 +181,25 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols4(const Tile* __restrict__
     const double* ut = U + (int64_t)blockIdx.y * ldu + f.off;
     const double* ut1 = ut + np;
     T* o = out + (int64_t)blockIdx.y * ldo;
-    const Quad<double> a = ld4(ut + p), b = ld4(ut1 + p);
+    const int nv = min(4, f.nx - x);
+    const Quad<double> a = ld4n(ut + p, nv), b = ld4n(ut1 + p, nv);
     {
         const T* vf = v + 2 * f.pair_off;
-        const Quad<T> vx = ld4(vf + p), vy = ld4(vf + np + p);
+        const Quad<T> vx = ld4n(vf + p, nv), vy = ld4n(vf + np + p, nv);
         Quad<T> q;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             q.v[j] = warp_sample<T, INTERP, double>(ut1, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)a.v[j];
-        st4(o + oF + f.pair_off + p, q);
+        st4n(o + oF + f.pair_off + p, q, nv);
     }
     if (vr) {
         const T* vb = vr + 2 * f.pair_off;
-        const Quad<T> vx = ld4(vb + p), vy = ld4(vb + np + p);
+        const Quad<T> vx = ld4n(vb + p, nv), vy = ld4n(vb + np + p, nv);
         Quad<T> q;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             q.v[j] = warp_sample<T, INTERP, double>(ut, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)b.v[j];
-        st4(o + oR + f.pair_off + p, q);
+        st4n(o + oR + f.pair_off + p, q, nv);
     }
 }
 
@@ -215,16 +219,17 @@ __global__ __launch_bounds__(256) void k_flow_fwd_colsJ(const Tile* __restrict__
     if (x >= f.nx || y >= f.ny) return;
     const int64_t np = (int64_t)f.nx * f.ny;
     const int64_t p = (int64_t)y * f.nx + x;
+    const int nv = min(4, f.nx - x);
     SampleCell<T> cf[4], cr[4];
     {
         const T* vf = v + 2 * f.pair_off;
-        const Quad<T> vx = ld4(vf + p), vy = ld4(vf + np + p);
+        const Quad<T> vx = ld4n(vf + p, nv), vy = ld4n(vf + np + p, nv);
 #pragma unroll
         for (int j = 0; j < 4; ++j) cf[j] = sample_cell<T, INTERP>(f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]);
     }
     if (vr) {
         const T* vb = vr + 2 * f.pair_off;
-        const Quad<T> vx = ld4(vb + p), vy = ld4(vb + np + p);
+        const Quad<T> vx = ld4n(vb + p, nv), vy = ld4n(vb + np + p, nv);
 #pragma unroll
         for (int j = 0; j < 4; ++j) cr[j] = sample_cell<T, INTERP>(f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]);
     }
@@ -235,15 +240,15 @@ __global__ __launch_bounds__(256) void k_flow_fwd_colsJ(const Tile* __restrict__
         const double* ut = U + (int64_t)col * ldu + f.off;
         const double* ut1 = ut + np;
         T* o = out + (int64_t)col * ldo;
-        const Quad<double> a = ld4(ut + p), b = ld4(ut1 + p);
+        const Quad<double> a = ld4n(ut + p, nv), b = ld4n(ut1 + p, nv);
         Quad<T> q;
 #pragma unroll
         for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, double>(ut1, cf[j]) - (T)a.v[j];
-        st4(o + oF + f.pair_off + p, q);
+        st4n(o + oF + f.pair_off + p, q, nv);
         if (vr) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, double>(ut, cr[j]) - (T)b.v[j];
-            st4(o + oR + f.pair_off + p, q);
+            st4n(o + oR + f.pair_off + p, q, nv);
         }
     }
 }
@@ -551,7 +556,8 @@ static_assert(sizeof(kFlow4Shapes) / sizeof(kFlow4Shapes[0]) == sizeof(kFlowShap
               "both forms offer the same number of tile candidates");
 
 TileShape flow_tile(const Geom& g, int choice) {
-    return g.vec4 ? TileShape{kFlow4Shapes[choice].tw(), kFlow4Shapes[choice].th(), 0} : kFlowShapes[choice];
+    (void)g;   // (the forward runs in its 4-pixel form for every frame width)
+    return TileShape{kFlow4Shapes[choice].tw(), kFlow4Shapes[choice].th(), 0};
 }
 
 template <class T, int INTERP>
@@ -581,7 +587,7 @@ void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const v
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_fwd", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
-        if (g.vec4 && aligned_to(4 * sizeof(T), {u, v, r})) {
+        if (aligned_to(sizeof(T), {u, v, r})) {
             const Flow4Shape sh = kFlow4Shapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
             auto k = interp == MMOF_INTERP_ROUND ? flow_fwd4_kernel<T, 1>(choice) : flow_fwd4_kernel<T, 0>(choice);
@@ -606,8 +612,7 @@ void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const double* U, 
         using T = decltype(z);
         ScopedTime st(&c, "flow_fwd_cols", (vr ? 2.0 : 1.0) * K * (4.0 * sizeof(T) + 16.0) * g.pair_px,
                       (vr ? 2.0 : 1.0) * K * 12.0 * g.pair_px);
-        const bool v4 = g.vec4 && ldu % 4 == 0 && ldo % 4 == 0 && oF % 4 == 0 && oR % 4 == 0 &&
-                        aligned_to(4 * sizeof(double), {U}) && aligned_to(4 * sizeof(T), {v, vr, out});
+        const bool v4 = aligned_to(sizeof(double), {U}) && aligned_to(sizeof(T), {v, vr, out});
         if (v4) {
             const Flow4Shape sh = kFlow4Shapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
