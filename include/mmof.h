@@ -65,6 +65,11 @@ typedef enum { MMOF_F32 = 0, MMOF_F64 = 1 } mmof_dtype;
 #define MMOF_REG_ANISO 1   /* D1 AnisoTV: Theta = [Psi; L_t], l1 on every row                 */
 #define MMOF_REG_ISO 2     /* D2 IsoTV: [Psi; L_t], a pixel's two spatial differences grouped */
 #define MMOF_REG_GS 3      /* D3 GS: [Psi], each difference location grouped over the frames  */
+/* reorthogonalisation of the new Krylov vector against the basis (Sec. 4.1: the vector is
+ * orthogonal to the basis in exact arithmetic, and is reorthogonalised in floating point) */
+#define MMOF_REORTH_AUTO 0   /* one classical Gram-Schmidt pass, a second one only when the   */
+                             /* first keeps less than 1/sqrt(2) of the norm (Kahan's test)   */
+#define MMOF_REORTH_TWICE 1  /* always two passes                                            */
 
 typedef struct mmof_ctx_s* mmof_ctx;
 typedef struct mmof_plan_s* mmof_plan;
@@ -319,6 +324,8 @@ typedef struct {
     int32_t of_ell;       /* Solve-OF: Golub-Kahan steps (10)                               */
     int32_t of_iters;     /* Solve-OF: projected solves per flow computation (20)           */
     int32_t reg;          /* MMOF_REG_*: the spatial(-temporal) part of Theta (M by default)  */
+    int32_t reorth;       /* MMOF_REORTH_*: passes of the reorthogonalisation of each new     */
+                          /* basis vector (Golub-Kahan start and MM iterations)               */
 } mmof_solve_params;
 
 typedef struct {
@@ -354,7 +361,7 @@ typedef struct {
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p,
                      void* u_inout, void* v_out, void* v_rev_out, mmof_report* rep);
 /* Fill p with the defaults (ell 10, k_max 20, tau 1, 200 sweeps, delta_r 1, flow on,
- * reverse on, bilinear, F64 operators, eps 1e-3, eta 1.01, alpha 0.1). */
+ * reverse on, bilinear, F64 operators, eps 1e-3, eta 1.01, alpha 0.1, MMOF_REORTH_AUTO). */
 void mmof_solve_defaults(mmof_solve_params* p);
 
 /* ------------------------------------------------------------------ projected-problem steps */
@@ -392,12 +399,20 @@ int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K
  *   mmof_cgs2:          x <- x - Q (Q^T x), twice (classical Gram-Schmidt with one
  *                       reorthogonalisation, the residual step of Alg. 1), Q FP64, x device FP64
  *                       [n] in/out; sq device FP64 [1] receives ||x||^2 afterwards.  The
- *                       context holds two workspace vectors (n and 256 doubles). */
+ *                       context holds two workspace vectors (n and 256 doubles).
+ *   mmof_reorth:        the same with a choice of passes (MMOF_REORTH_*): MMOF_REORTH_TWICE
+ *                       is mmof_cgs2; MMOF_REORTH_AUTO makes one pass and a second one only
+ *                       when the first kept less than 1/sqrt(2) of ||x|| (the test is taken on
+ *                       the device; the second pass's launches then return at once).  The
+ *                       joint solve reorthogonalises its new basis vectors this way
+ *                       (mmof_solve_params.reorth).  MMOF_ERR_INVALID for another mode. */
 int mmof_block_dot(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
                    const double* y, double* out);
 int mmof_block_combine(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
                        const double* z, double alpha, const double* y, double beta, double* out);
 int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq);
+int mmof_reorth(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq,
+                int32_t mode);
 
 /* Projected solve of MMGKS (eq. minKryov2) with the discrepancy principle (Sec. 4.1.3):
  * (G_H + lambda G_T) z = d, lambda such that ||b||^2 - d^T z - lambda z^T G_T z = target.

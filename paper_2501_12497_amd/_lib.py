@@ -27,6 +27,8 @@ class mmof_stack(C.Structure):
 
 MMOF_REG_PSI, MMOF_REG_ANISO, MMOF_REG_ISO, MMOF_REG_GS = 0, 1, 2, 3
 REGS = {"psi": MMOF_REG_PSI, "aniso": MMOF_REG_ANISO, "iso": MMOF_REG_ISO, "gs": MMOF_REG_GS}
+MMOF_REORTH_AUTO, MMOF_REORTH_TWICE = 0, 1
+REORTHS = {"auto": MMOF_REORTH_AUTO, "twice": MMOF_REORTH_TWICE}
 
 
 class mmof_solve_params(C.Structure):
@@ -36,7 +38,7 @@ class mmof_solve_params(C.Structure):
                 ("eps", C.c_double), ("eta", C.c_double), ("alpha", C.c_double), ("fixed_lambda", C.c_double),
                 ("rre_target", C.c_double), ("u_true", C.c_void_p), ("use_graph", C.c_int32),
                 ("flow_scale", C.c_int32), ("flow_solver", C.c_int32), ("of_ell", C.c_int32),
-                ("of_iters", C.c_int32), ("reg", C.c_int32)]
+                ("of_iters", C.c_int32), ("reg", C.c_int32), ("reorth", C.c_int32)]
 
 
 class mmof_report(C.Structure):
@@ -88,6 +90,7 @@ _SIGS = {
     "mmof_block_dot": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P]),
     "mmof_block_combine": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_double, _P]),
     "mmof_cgs2": (_I, [_P, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P]),
+    "mmof_reorth": (_I, [_P, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P, C.c_int32]),
     "mmof_projected_solve": (_I, [_P, C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
     "mmof_profile_kernel": (_I, [_P, C.c_char_p]),
     "mmof_autotune": (_I, [_P, C.c_int32, C.c_char_p, C.c_int32]),

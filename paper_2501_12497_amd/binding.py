@@ -473,6 +473,14 @@ def block_combine(X: torch.Tensor, z: torch.Tensor, alpha: float = 1.0, y: Optio
 
 def cgs2(Q: torch.Tensor, x: torch.Tensor, ctx: Optional[Context] = None) -> float:
     """x <- x - Q^T (Q x), twice, in place (Q FP64 of shape [K, n]); returns ||x||^2."""
+    return reorth(Q, x, "twice", ctx)
+
+
+def reorth(Q: torch.Tensor, x: torch.Tensor, mode="auto", ctx: Optional[Context] = None) -> float:
+    """x <- x - Q^T (Q x) in place (Q FP64 of shape [K, n]), a second time always ("twice") or
+    only when the first pass kept less than 1/sqrt(2) of ||x|| ("auto"); returns ||x||^2."""
+    if isinstance(mode, str):
+        mode = _lib.REORTHS[mode]
     ctx = ctx or context()
     K, n = Q.shape
     _need(Q, K * n, "Q")
@@ -481,7 +489,7 @@ def cgs2(Q: torch.Tensor, x: torch.Tensor, ctx: Optional[Context] = None) -> flo
         raise TypeError("Q and x must be float64")
     sq = torch.empty(1, dtype=torch.float64, device=x.device)
     ctx.bind()
-    check(ctx.lib.mmof_cgs2(ctx.h, n, K, _ptr(Q), n, _ptr(x), _ptr(sq)))
+    check(ctx.lib.mmof_reorth(ctx.h, n, K, _ptr(Q), n, _ptr(x), _ptr(sq), int(mode)))
     return float(sq.item())
 
 
@@ -516,6 +524,8 @@ def solve_params(**kw) -> _lib.mmof_solve_params:
             val = {"f32": _lib.MMOF_F32, "f64": _lib.MMOF_F64}[val]
         if k == "reg" and isinstance(val, str):
             val = _lib.REGS[val]
+        if k == "reorth" and isinstance(val, str):
+            val = _lib.REORTHS[val]
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, val)

@@ -451,6 +451,7 @@ void mmof_solve_defaults(mmof_solve_params* p) {
     p->of_ell = 10;
     p->of_iters = 20;
     p->reg = MMOF_REG_PSI;
+    p->reorth = MMOF_REORTH_AUTO;
 }
 
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p, void* u_inout,
@@ -463,6 +464,8 @@ int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_s
         MMOF_CHECK(std::isfinite(noise_norm) && noise_norm >= 0, MMOF_ERR_INVALID, "noise_norm must be >= 0");
         MMOF_CHECK(p->interp == MMOF_INTERP_BILINEAR || p->interp == MMOF_INTERP_ROUND, MMOF_ERR_INVALID, "bad interp");
         MMOF_CHECK(p->reg >= MMOF_REG_PSI && p->reg <= MMOF_REG_GS, MMOF_ERR_INVALID, "bad regulariser");
+        MMOF_CHECK(p->reorth == MMOF_REORTH_AUTO || p->reorth == MMOF_REORTH_TWICE, MMOF_ERR_INVALID,
+                   "bad reorth");
         if (p->use_flow) {
             const int f = resolve_flow_scale(*A->geom, p->flow_scale);
             check_flow_frames(*A->geom, f, p->delta_r);
@@ -590,14 +593,20 @@ int mmof_block_combine(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const 
     });
 }
 
-int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq) {
+int mmof_reorth(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq,
+                int32_t mode) {
     return guarded(ctx, [&] {
         need(ctx, "ctx");
         need(Q, "Q");
         need(x, "x");
         need(sq, "sq");
         MMOF_CHECK(n >= 1 && K >= 1 && K <= KMAX && ld >= n, MMOF_ERR_SHAPE, "bad block sizes");
-        double* h = static_cast<double*>(ctx->work("cgs2_h", sizeof(double) * KMAX));
+        MMOF_CHECK(mode == MMOF_REORTH_AUTO || mode == MMOF_REORTH_TWICE, MMOF_ERR_INVALID, "bad reorth mode");
+        double* h = static_cast<double*>(ctx->work("cgs2_h", sizeof(double) * (KMAX + 1)));
+        if (mode == MMOF_REORTH_AUTO) {
+            cgs_once(*ctx, n, K, Q, ld, x, sq, h);
+            return MMOF_OK;
+        }
         double* y = static_cast<double*>(ctx->work("cgs2_y", sizeof(double) * (size_t)n));
         mdot<double, double>(*ctx, n, K, Q, ld, x, 1.0, h);
         if (K <= KMAX_SMALL) {
@@ -609,6 +618,10 @@ int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, d
         gemv_fused<double, double>(*ctx, n, K, Q, ld, h, -1.0, y, 1.0, x, nullptr, nullptr, sq);
         return MMOF_OK;
     });
+}
+
+int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq) {
+    return mmof_reorth(ctx, n, K, Q, ld, x, sq, MMOF_REORTH_TWICE);
 }
 
 int mmof_projected_solve(mmof_ctx ctx, int32_t K, const double* GA, const double* GT, const double* d,

@@ -104,10 +104,13 @@ __global__ void k_convert(int64_t n, const TI* __restrict__ in, TO* __restrict__
 // Grid: x = row chunks, y = groups of 8 columns; part[b][j] receives chunk b's sum for
 // column j.  (A single-launch completion by the last workgroup would need a device-scope
 // release per workgroup, which writes back the XCD's L2; a second small launch is cheaper.)
+// skip (may be null): when *skip is non-zero the launch does nothing (this and the other
+// kernels of a conditional pass read the decision on the device).
 template <class TX, class TY>
 __global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                              const TY* __restrict__ y, const double* __restrict__ xe,
-                                             double* __restrict__ part) {
+                                             double* __restrict__ part, const int* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ double s8[4][8];
     const int Kt = K + (xe ? 1 : 0);
     const int64_t nb = gridDim.x;
@@ -144,7 +147,8 @@ __global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, const TX* __restr
 template <class TX, class TY>
 __global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                               const TY* __restrict__ y, const double* __restrict__ xe,
-                                              double* __restrict__ part) {
+                                              double* __restrict__ part, const int* __restrict__ skip) {
+    if (skip && *skip) return;
     // (element-aligned: global multi-word loads accept it, so any ld and any column qualify)
     typedef TX VX __attribute__((ext_vector_type(2), aligned(sizeof(TX))));
     typedef TY VY __attribute__((ext_vector_type(2), aligned(sizeof(TY))));
@@ -209,7 +213,8 @@ __global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __rest
 //   G != null: G[row][j] = G[j][row] = s_j for j < Kt - 1 and dj[0] = s_{Kt-1}.
 __global__ __launch_bounds__(1024) void k_mdot_final(int nb, int Kt, const double* __restrict__ part, double alpha,
                                                      double* __restrict__ out, double* __restrict__ G, int ldg,
-                                                     int row, double* __restrict__ dj) {
+                                                     int row, double* __restrict__ dj, const int* __restrict__ skip) {
+    if (skip && *skip) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int j = w; j < Kt; j += nw) {
         // lane l sums chunks l, l+64, l+128, ... in four interleaved running sums (four
@@ -258,7 +263,9 @@ template <class TX, class TO>
 __global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                                    const double* __restrict__ h, double alpha, const double* y,
                                                    double beta, double* out_d, TO* __restrict__ out_t,
-                                                   const double* __restrict__ cv, double* __restrict__ part) {
+                                                   const double* __restrict__ cv, double* __restrict__ part,
+                                                   const int* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ double sh[KMAX];
     __shared__ double s4[4];
     for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
@@ -287,7 +294,9 @@ template <class TX, class TO>
 __global__ __launch_bounds__(KB) void k_gemv_fused2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                                     const double* __restrict__ h, double alpha, const double* y,
                                                     double beta, double* out_d, TO* __restrict__ out_t,
-                                                    const double* __restrict__ cv, double* __restrict__ part) {
+                                                    const double* __restrict__ cv, double* __restrict__ part,
+                                                    const int* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ double sh[KMAX];
     __shared__ double s4[4];
     for (int j = threadIdx.x; j < K; j += KB) sh[j] = h[j];
@@ -369,7 +378,9 @@ __global__ __launch_bounds__(KB) void k_gemv_mdot(int64_t n, int K, const double
 }
 
 // out[0] = sum of nb partials in a fixed order (one wavefront)
-__global__ __launch_bounds__(64) void k_sum_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+__global__ __launch_bounds__(64) void k_sum_final(int nb, const double* __restrict__ part, double* __restrict__ out,
+                                                 const int* __restrict__ skip) {
+    if (skip && *skip) return;
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b0 = threadIdx.x; b0 < nb; b0 += 256) {
 #pragma unroll
@@ -1074,14 +1085,14 @@ void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double
         ScopedTime st(&c, "mdot", (double)n * ((double)sizeof(TX) * K + sizeof(TY)), 2.0 * n * K);
         if (mdot_pairs(X, ld, y, nullptr))
             hipLaunchKernelGGL((k_mdot2<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld,
-                               y, (const double*)nullptr, part);
+                               y, (const double*)nullptr, part, (const int*)nullptr);
         else
             hipLaunchKernelGGL((k_mdot<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld,
-                               y, (const double*)nullptr, part);
+                               y, (const double*)nullptr, part, (const int*)nullptr);
         MMOF_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, K, part, alpha, out, (double*)nullptr, 0, 0,
-                       (double*)nullptr);
+                       (double*)nullptr, (const int*)nullptr);
     MMOF_LAUNCH_CHECK();
 }
 template void mdot<float, double>(Ctx&, int64_t, int, const float*, int64_t, const double*, double, double*);
@@ -1101,7 +1112,7 @@ void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const doub
         MMOF_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, K, part, 1.0, hout, (double*)nullptr, 0, 0,
-                       (double*)nullptr);
+                       (double*)nullptr, (const int*)nullptr);
     MMOF_LAUNCH_CHECK();
 }
 
@@ -1113,24 +1124,27 @@ void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e
     const TX* xj = X + (int64_t)j * ld;
     if (mdot_pairs(X, ld, xj, e))
         hipLaunchKernelGGL((k_mdot2<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1,
-                           X, ld, xj, e, part);
+                           X, ld, xj, e, part, (const int*)nullptr);
     else
         hipLaunchKernelGGL((k_mdot<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1,
-                           X, ld, xj, e, part);
+                           X, ld, xj, e, part, (const int*)nullptr);
     MMOF_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, j + 2, part, 1.0, (double*)nullptr, G, ldg,
-                       j, dj);
+                       j, dj, (const int*)nullptr);
     MMOF_LAUNCH_CHECK();
 }
 template void gram_row<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int, double*);
 template void gram_row<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double*, int, double*);
 
+// gemv_fused; with skip, every launch returns at once when *skip is non-zero on the device
+// (timed under the name tname)
 template <class TX, class TO>
-void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, const double* y,
-                double beta, double* out_d, TO* out_t, const double* cv, double* sq) {
+static void gemv_fused_impl(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha,
+                            const double* y, double beta, double* out_d, TO* out_t, const double* cv, double* sq,
+                            const int* skip, const char* tname) {
     MMOF_CHECK(K >= 0 && K <= KMAX, MMOF_ERR_SHAPE, "too many Krylov columns");
     if (n == 0) {
-        if (sq) set_scalar(c, sq, 0.0);
+        if (sq && !skip) set_scalar(c, sq, 0.0);
         return;
     }
     // two rows per lane when the columns allow 2-element loads (the grid covers row pairs)
@@ -1143,19 +1157,26 @@ void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double*
         // K columns and y (if any) read, the outputs written, cv read when given
         const double bytes = (double)n * ((double)sizeof(TX) * K + (y ? 8.0 : 0.0) + (out_d ? 8.0 : 0.0) +
                                           (out_t ? (double)sizeof(TO) : 0.0) + (cv ? 8.0 : 0.0));
-        ScopedTime st(&c, "gemv", bytes, 2.0 * n * K);
+        // (a conditional launch may do nothing: no work is credited to it)
+        ScopedTime st(&c, tname, skip ? 0.0 : bytes, skip ? 0.0 : 2.0 * n * K);
         if (pair)
             hipLaunchKernelGGL((k_gemv_fused2<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta,
-                               out_d, out_t, cv, part);
+                               out_d, out_t, cv, part, skip);
         else
             hipLaunchKernelGGL((k_gemv_fused<TX, TO>), grid, dim3(KB), 0, c.stream, n, K, X, ld, h, alpha, y, beta,
-                               out_d, out_t, cv, part);
+                               out_d, out_t, cv, part, skip);
         MMOF_LAUNCH_CHECK();
     }
     if (sq) {
-        hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c.stream, (int)grid.x, (const double*)part, sq);
+        hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c.stream, (int)grid.x, (const double*)part, sq, skip);
         MMOF_LAUNCH_CHECK();
     }
+}
+
+template <class TX, class TO>
+void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double* h, double alpha, const double* y,
+                double beta, double* out_d, TO* out_t, const double* cv, double* sq) {
+    gemv_fused_impl<TX, TO>(c, n, K, X, ld, h, alpha, y, beta, out_d, out_t, cv, sq, nullptr, "gemv");
 }
 template void gemv_fused<double, float>(Ctx&, int64_t, int, const double*, int64_t, const double*, double,
                                         const double*, double, double*, float*, const double*, double*);
@@ -1163,6 +1184,46 @@ template void gemv_fused<double, double>(Ctx&, int64_t, int, const double*, int6
                                          const double*, double, double*, double*, const double*, double*);
 template void gemv_fused<float, float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double,
                                        const double*, double, double*, float*, const double*, double*);
+
+// Second-pass test of cgs_once: flag[0] = 1 (skip the second pass) when the first pass kept at
+// least 1/sqrt(2) of the norm, ||x'||^2 >= ||x||^2 / 2.
+__global__ void k_cgs_keep(const double* __restrict__ xx, const double* __restrict__ sq, int* __restrict__ flag) {
+    flag[0] = (sq[0] >= 0.5 * xx[0]) ? 1 : 0;
+}
+
+void cgs_once(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, double* x, double* sq, double* h) {
+    MMOF_CHECK(K >= 1 && K <= KMAX, MMOF_ERR_SHAPE, "too many Krylov columns");
+    const int nb = mdot_blocks(n);
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX + 1)));
+    int* flag = static_cast<int*>(c.work("cgs_flag", sizeof(int)));
+    // h[0..K-1] = Q^T x and h[K] = ||x||^2 (x as the extra column), one pass over Q and x
+    auto dots = [&](const double* xe, const int* skip, const char* tname) {
+        const int Kt = K + (xe ? 1 : 0);
+        {
+            ScopedTime st(&c, tname, skip ? 0.0 : (double)n * (8.0 * K + 8.0), skip ? 0.0 : 2.0 * n * Kt);
+            if (mdot_pairs(Q, ld, x, xe))
+                hipLaunchKernelGGL((k_mdot2<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
+                                   n, K, Q, ld, (const double*)x, xe, part, skip);
+            else
+                hipLaunchKernelGGL((k_mdot<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
+                                   n, K, Q, ld, (const double*)x, xe, part, skip);
+            MMOF_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, Kt, part, 1.0, h, (double*)nullptr, 0,
+                           0, (double*)nullptr, skip);
+        MMOF_LAUNCH_CHECK();
+    };
+    dots(x, nullptr, "mdot");
+    // x <- x - Q h in place (each row read before it is written), ||x||^2 into sq
+    gemv_fused_impl<double, double>(c, n, K, Q, ld, h, -1.0, x, 1.0, x, (double*)nullptr, nullptr, sq, nullptr,
+                                    "gemv");
+    hipLaunchKernelGGL(k_cgs_keep, dim3(1), dim3(1), 0, c.stream, (const double*)(h + K), (const double*)sq, flag);
+    MMOF_LAUNCH_CHECK();
+    // the second pass, carried out only where the test asks for it
+    dots(nullptr, flag, "cgs_second");
+    gemv_fused_impl<double, double>(c, n, K, Q, ld, h, -1.0, x, 1.0, x, (double*)nullptr, nullptr, sq, flag,
+                                    "cgs_second");
+}
 
 template <class TO>
 void normalize2(Ctx& c, int64_t n, const double* x, const double* s2, double* s1, double* out_d, TO* out_t) {

@@ -32,6 +32,13 @@ void gemv_fused(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const double*
 // hout may alias h).
 void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const double* h, const double* x, double* y,
                double* hout);
+// Classical Gram-Schmidt of x against the K orthonormal FP64 columns of Q (column-major
+// [K][ld]), x <- x - Q (Q^T x), followed by a second such pass only when the first kept less
+// than 1/sqrt(2) of ||x|| (Kahan's test: otherwise one pass already leaves x orthogonal to Q
+// to working precision).  The test runs on the device: the second pass's launches return at
+// once when it is not needed, so nothing waits for the host.  sq[0] = ||x||^2 afterwards;
+// h: device scratch of K + 1 doubles.
+void cgs_once(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, double* x, double* sq, double* h);
 // s = sqrt(s2[0]) (written to s1 when not null); out_d = x / s and out_t = (TO)(x / s)
 // (a zero vector when s = 0).
 template <class TO>

@@ -129,7 +129,7 @@ struct Solver {
         AVs = ws<double>("AVs", (int64_t)std::max(1, p.ell - 1) * m);
         r = ws<double>("r", n);
         tmp_m = ws<double>("tmp_m", m);
-        h = ws<double>("h", KMAX);
+        h = ws<double>("h", KMAX + 1);
         sc = ws<double>("sc", 8);
         scal = ws<double>("scal", 24);
         vin_n = wsx("vin_n", n);
@@ -317,10 +317,16 @@ struct Solver {
     void norm_into(int64_t len, const double* x, double* out) {  // out = ||x||^2
         mdot<double, double>(c, len, 1, x, len, x, 1.0, out);
     }
-    // x <- x - Q (Q^T x), twice (Q has k columns of length len); sq[0] = ||x||^2 afterwards
+    // x <- x - Q (Q^T x) (Q has k columns of length len), once more when the first pass
+    // removed most of x (MMOF_REORTH_AUTO) or always (MMOF_REORTH_TWICE); sq[0] = ||x||^2
+    // afterwards
     void reorth(int64_t len, const double* Q, int k, double* x, double* sq) {
         if (k <= 0) {
             norm_into(len, x, sq);
+            return;
+        }
+        if (p.reorth == MMOF_REORTH_AUTO) {
+            cgs_once(c, len, k, Q, len, x, sq, h);
             return;
         }
         // h = Q^T x; y = x - Q h and h = Q^T y in one pass over Q; x = y - Q h with ||x||^2
@@ -643,7 +649,8 @@ static void check_solve_capacity(Ctx& c, const Plan& P, const mmof_solve_params&
     size_t grow = c.work_growth("solve_V", sizeof(double) * K * n);
     // the vectors of one iteration: FP64 ones shared by both precisions, the others per precision
     size_t vecs = 0;
-    for (const char* nm : {"solve_r", "solve_tmp_n", "reorth_y"}) vecs += c.work_growth(nm, sizeof(double) * n);
+    for (const char* nm : {"solve_r", "solve_tmp_n"}) vecs += c.work_growth(nm, sizeof(double) * n);
+    if (p.reorth == MMOF_REORTH_TWICE) vecs += c.work_growth("reorth_y", sizeof(double) * n);
     vecs += c.work_growth("solve_w2", sizeof(double) * R) + c.work_growth("solve_AVs", sizeof(double) * p.ell * m);
     auto per_precision = [&](const char* tag, size_t es) {
         const std::string t(tag);
