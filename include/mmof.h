@@ -70,6 +70,11 @@ typedef enum { MMOF_F32 = 0, MMOF_F64 = 1 } mmof_dtype;
 #define MMOF_REORTH_AUTO 0   /* one classical Gram-Schmidt pass, a second one only when the   */
                              /* first keeps less than 1/sqrt(2) of the norm (Kahan's test)   */
 #define MMOF_REORTH_TWICE 1  /* always two passes                                            */
+#define MMOF_REORTH_IMPLICIT 2  /* joint solve: each new direction is stored as computed and     */
+                                /* its components along the basis are carried in a triangular    */
+                                /* factor T of the basis (V = Vs T), from the one pass Vs^T r     */
+                                /* that the inner products need anyway; an explicit pass where r  */
+                                /* keeps less than 1/sqrt(2) of its norm; the start as AUTO       */
 
 typedef struct mmof_ctx_s* mmof_ctx;
 typedef struct mmof_plan_s* mmof_plan;
@@ -324,8 +329,8 @@ typedef struct {
     int32_t of_ell;       /* Solve-OF: Golub-Kahan steps (10)                               */
     int32_t of_iters;     /* Solve-OF: projected solves per flow computation (20)           */
     int32_t reg;          /* MMOF_REG_*: the spatial(-temporal) part of Theta (M by default)  */
-    int32_t reorth;       /* MMOF_REORTH_*: passes of the reorthogonalisation of each new     */
-                          /* basis vector (Golub-Kahan start and MM iterations)               */
+    int32_t reorth;       /* MMOF_REORTH_*: reorthogonalisation of each new basis vector      */
+                          /* (Golub-Kahan start and MM iterations)                            */
 } mmof_solve_params;
 
 typedef struct {
@@ -361,7 +366,7 @@ typedef struct {
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p,
                      void* u_inout, void* v_out, void* v_rev_out, mmof_report* rep);
 /* Fill p with the defaults (ell 10, k_max 20, tau 1, 200 sweeps, delta_r 1, flow on,
- * reverse on, bilinear, F64 operators, eps 1e-3, eta 1.01, alpha 0.1, MMOF_REORTH_AUTO). */
+ * reverse on, bilinear, F64 operators, eps 1e-3, eta 1.01, alpha 0.1, MMOF_REORTH_IMPLICIT). */
 void mmof_solve_defaults(mmof_solve_params* p);
 
 /* ------------------------------------------------------------------ projected-problem steps */
@@ -405,7 +410,8 @@ int mmof_weighted_gram_noalloc(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K
  *                       when the first kept less than 1/sqrt(2) of ||x|| (the test is taken on
  *                       the device; the second pass's launches then return at once).  The
  *                       joint solve reorthogonalises its new basis vectors this way
- *                       (mmof_solve_params.reorth).  MMOF_ERR_INVALID for another mode. */
+ *                       (mmof_solve_params.reorth).  MMOF_ERR_INVALID for another mode
+ *                       (MMOF_REORTH_IMPLICIT is a property of the solve's basis). */
 int mmof_block_dot(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
                    const double* y, double* out);
 int mmof_block_combine(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const void* X, int64_t ld,
@@ -413,6 +419,17 @@ int mmof_block_combine(mmof_ctx ctx, mmof_dtype dt, int64_t n, int32_t K, const 
 int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq);
 int mmof_reorth(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq,
                 int32_t mode);
+/* One step of the implicit basis of the joint solve (MMOF_REORTH_IMPLICIT): the orthonormal
+ * basis is V = Vs T with Vs the K stored columns (device FP64, column-major [K][ld]) and T unit
+ * upper triangular (device FP64 [256][256], column-major: T[j * 256 + i] = T(i, j), column j =
+ * the coefficients of v_j in Vs; rows below the diagonal are not read).  With g = V^T r and
+ * rho^2 = ||r||^2 - ||g||^2: writes sq[0] = rho^2 and column K of T, e_K - T g / rho, so that
+ * the new basis vector is v_K = r / rho - V g / rho when r / rho is stored as column K of Vs.
+ * When r keeps less than 1/sqrt(2) of its norm outside span(V), r (device FP64 [n], in/out)
+ * is first replaced by r - V g (one explicit pass; r is otherwise left as it is).  Reads Vs
+ * once (twice on the explicit path).  1 <= K <= 255. */
+int mmof_basis_extend(mmof_ctx ctx, int64_t n, int32_t K, const double* Vs, int64_t ld, double* r, double* T,
+                      double* sq);
 
 /* Projected solve of MMGKS (eq. minKryov2) with the discrepancy principle (Sec. 4.1.3):
  * (G_H + lambda G_T) z = d, lambda such that ||b||^2 - d^T z - lambda z^T G_T z = target.

@@ -27,8 +27,8 @@ class mmof_stack(C.Structure):
 
 MMOF_REG_PSI, MMOF_REG_ANISO, MMOF_REG_ISO, MMOF_REG_GS = 0, 1, 2, 3
 REGS = {"psi": MMOF_REG_PSI, "aniso": MMOF_REG_ANISO, "iso": MMOF_REG_ISO, "gs": MMOF_REG_GS}
-MMOF_REORTH_AUTO, MMOF_REORTH_TWICE = 0, 1
-REORTHS = {"auto": MMOF_REORTH_AUTO, "twice": MMOF_REORTH_TWICE}
+MMOF_REORTH_AUTO, MMOF_REORTH_TWICE, MMOF_REORTH_IMPLICIT = 0, 1, 2
+REORTHS = {"auto": MMOF_REORTH_AUTO, "twice": MMOF_REORTH_TWICE, "implicit": MMOF_REORTH_IMPLICIT}
 
 
 class mmof_solve_params(C.Structure):
@@ -91,6 +91,7 @@ _SIGS = {
     "mmof_block_combine": (_I, [_P, _I, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_double, _P, C.c_double, _P]),
     "mmof_cgs2": (_I, [_P, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P]),
     "mmof_reorth": (_I, [_P, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P, C.c_int32]),
+    "mmof_basis_extend": (_I, [_P, C.c_int64, C.c_int32, _P, C.c_int64, _P, _P, _P]),
     "mmof_projected_solve": (_I, [_P, C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
     "mmof_profile_kernel": (_I, [_P, C.c_char_p]),
     "mmof_autotune": (_I, [_P, C.c_int32, C.c_char_p, C.c_int32]),

@@ -493,6 +493,24 @@ def reorth(Q: torch.Tensor, x: torch.Tensor, mode="auto", ctx: Optional[Context]
     return float(sq.item())
 
 
+def basis_extend(Vs: torch.Tensor, r: torch.Tensor, T: torch.Tensor, ctx: Optional[Context] = None) -> float:
+    """One step of the implicit basis V = Vs T: Vs FP64 [K, n] (row k = stored column k), T FP64
+    [256, 256] with T[j, i] = T(i, j) (row j = the coefficients of v_j in Vs).  Writes row K of T
+    (e_K - T g / rho, g = V^T r) and returns rho^2 = ||r||^2 - ||g||^2; r is replaced by r - V g
+    when it keeps less than 1/sqrt(2) of its norm outside the basis."""
+    ctx = ctx or context()
+    K, n = Vs.shape
+    _need(Vs, K * n, "Vs")
+    _need(r, n, "r")
+    _need(T, KRYLOV_MAX * KRYLOV_MAX, "T")
+    if Vs.dtype != torch.float64 or r.dtype != torch.float64 or T.dtype != torch.float64:
+        raise TypeError("Vs, r and T must be float64")
+    sq = torch.empty(1, dtype=torch.float64, device=r.device)
+    ctx.bind()
+    check(ctx.lib.mmof_basis_extend(ctx.h, n, K, _ptr(Vs), n, _ptr(r), _ptr(T), _ptr(sq)))
+    return float(sq.item())
+
+
 def projected_solve(GA: torch.Tensor, GT: torch.Tensor, d: torch.Tensor, bnorm2: float, target: float,
                     prev_lambda: float = 0.0, fixed_lambda: float = 0.0, ctx: Optional[Context] = None):
     """(G_H + lambda G_T) z = d with lambda from the discrepancy principle; returns (z, lambda, D^2, status)."""

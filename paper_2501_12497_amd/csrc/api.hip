@@ -451,7 +451,7 @@ void mmof_solve_defaults(mmof_solve_params* p) {
     p->of_ell = 10;
     p->of_iters = 20;
     p->reg = MMOF_REG_PSI;
-    p->reorth = MMOF_REORTH_AUTO;
+    p->reorth = MMOF_REORTH_IMPLICIT;
 }
 
 int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_solve_params* p, void* u_inout,
@@ -464,8 +464,9 @@ int mmof_solve_joint(mmof_plan A, const void* b, double noise_norm, const mmof_s
         MMOF_CHECK(std::isfinite(noise_norm) && noise_norm >= 0, MMOF_ERR_INVALID, "noise_norm must be >= 0");
         MMOF_CHECK(p->interp == MMOF_INTERP_BILINEAR || p->interp == MMOF_INTERP_ROUND, MMOF_ERR_INVALID, "bad interp");
         MMOF_CHECK(p->reg >= MMOF_REG_PSI && p->reg <= MMOF_REG_GS, MMOF_ERR_INVALID, "bad regulariser");
-        MMOF_CHECK(p->reorth == MMOF_REORTH_AUTO || p->reorth == MMOF_REORTH_TWICE, MMOF_ERR_INVALID,
-                   "bad reorth");
+        MMOF_CHECK(p->reorth == MMOF_REORTH_AUTO || p->reorth == MMOF_REORTH_TWICE ||
+                       p->reorth == MMOF_REORTH_IMPLICIT,
+                   MMOF_ERR_INVALID, "bad reorth");
         if (p->use_flow) {
             const int f = resolve_flow_scale(*A->geom, p->flow_scale);
             check_flow_frames(*A->geom, f, p->delta_r);
@@ -622,6 +623,21 @@ int mmof_reorth(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld,
 
 int mmof_cgs2(mmof_ctx ctx, int64_t n, int32_t K, const double* Q, int64_t ld, double* x, double* sq) {
     return mmof_reorth(ctx, n, K, Q, ld, x, sq, MMOF_REORTH_TWICE);
+}
+
+int mmof_basis_extend(mmof_ctx ctx, int64_t n, int32_t K, const double* Vs, int64_t ld, double* r, double* T,
+                      double* sq) {
+    return guarded(ctx, [&] {
+        need(ctx, "ctx");
+        need(Vs, "Vs");
+        need(r, "r");
+        need(T, "T");
+        need(sq, "sq");
+        MMOF_CHECK(n >= 1 && K >= 1 && K < KMAX && ld >= n, MMOF_ERR_SHAPE, "bad block sizes");
+        double* h = static_cast<double*>(ctx->work("cgs2_h", sizeof(double) * (KMAX + 1)));
+        basis_extend(*ctx, n, K, Vs, ld, r, T, h, sq);
+        return MMOF_OK;
+    });
 }
 
 int mmof_projected_solve(mmof_ctx ctx, int32_t K, const double* GA, const double* GT, const double* d,

@@ -1225,6 +1225,192 @@ void cgs_once(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, double* x, 
                                     "cgs_second");
 }
 
+// ---------------------------------------------------------------- implicit basis
+// The true basis is V = Vs T with Vs the stored columns and T unit upper triangular
+// (column-major, leading dimension KLD: T(i, j) = T[j * KLD + i], column j = the coefficients
+// of v_j in Vs).  One workgroup of KB threads; K <= KMAX.
+
+// g = T^T h (g_i = sum_{k <= i} T(k, i) h_k), into LDS, and its squared norm (thread 0).
+__device__ double basis_coeffs(int K, const double* __restrict__ T, const double* __restrict__ h, double* g,
+                               double* s4) {
+    double e2 = 0.0;
+    for (int i = threadIdx.x; i < K; i += KB) {
+        const double* ti = T + (int64_t)i * KLD;
+        double a = 0.0;
+        for (int k = 0; k < i; ++k) a = fma(ti[k], h[k], a);
+        a += h[i];  // T(i, i) = 1
+        g[i] = a;
+        e2 = fma(a, a, e2);
+    }
+    return block_sum(e2, s4);  // (also orders the writes of g before any later read)
+}
+
+// keep[0] = 1 when ||r||^2 - ||g||^2 >= ||r||^2 / 2 (r keeps at least 1/sqrt(2) of its norm
+// outside the basis: no explicit pass); otherwise keep[0] = 0 and hc = T g, the coefficients
+// in Vs of the part of r along the basis.
+__global__ __launch_bounds__(KB) void k_basis_check(int K, const double* __restrict__ T,
+                                                    const double* __restrict__ h, const double* __restrict__ rr2,
+                                                    double* __restrict__ hc, int* __restrict__ keep) {
+    __shared__ double g[KMAX];
+    __shared__ double s4[4];
+    __shared__ int need;
+    const double G2 = basis_coeffs(K, T, h, g, s4);
+    if (threadIdx.x == 0) {
+        need = !(rr2[0] - G2 >= 0.5 * rr2[0]);
+        keep[0] = need ? 0 : 1;
+    }
+    __syncthreads();
+    if (!need) return;
+    for (int k = threadIdx.x; k < K; k += KB) {
+        double a = g[k];  // T(k, k) = 1
+        for (int i = k + 1; i < K; ++i) a = fma(T[(int64_t)i * KLD + k], g[i], a);
+        hc[k] = a;
+    }
+}
+
+// Appends column K of T for a new stored column vs_K = r / rho: g = T^T h with h = Vs^T r,
+// rho^2 = ||r||^2 - ||g||^2 (written to sq[0]), T(:, K) = e_K - T g / rho, so that
+// v_K = vs_K - V g / rho = (r - V V^T r) / rho.
+__global__ __launch_bounds__(KB) void k_basis_append(int K, double* __restrict__ T, const double* __restrict__ h,
+                                                     const double* __restrict__ rr2, double* __restrict__ sq) {
+    __shared__ double g[KMAX];
+    __shared__ double s4[4];
+    __shared__ double inv;
+    const double G2 = basis_coeffs(K, T, h, g, s4);
+    if (threadIdx.x == 0) {
+        const double rho2 = fmax(rr2[0] - G2, 0.0);
+        sq[0] = rho2;
+        inv = rho2 > 0.0 ? 1.0 / sqrt(rho2) : 0.0;
+    }
+    __syncthreads();
+    double* tK = T + (int64_t)K * KLD;
+    for (int k = threadIdx.x; k <= K; k += KB) {
+        if (k == K) {
+            tK[k] = 1.0;
+            continue;
+        }
+        double a = g[k];
+        for (int i = k + 1; i < K; ++i) a = fma(T[(int64_t)i * KLD + k], g[i], a);
+        tK[k] = -a * inv;
+    }
+}
+
+// W(a, j) = sum_{b <= j} Gs(a, b) T(b, j) for a, j < K (one thread per entry).
+__global__ __launch_bounds__(KB) void k_basis_right(int K, const double* __restrict__ Gs, int ldg,
+                                                    const double* __restrict__ T, double* __restrict__ W) {
+    const int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x;
+    if (e >= (int64_t)K * K) return;
+    const int a = (int)(e % K), j = (int)(e / K);
+    const double* tj = T + (int64_t)j * KLD;
+    double s = Gs[(int64_t)a * ldg + j];  // T(j, j) = 1
+    for (int b = 0; b < j; ++b) s = fma(Gs[(int64_t)a * ldg + b], tj[b], s);
+    W[(int64_t)j * KLD + a] = s;
+}
+
+// G(i, j) = G(j, i) = sum_{a <= i} T(a, i) W(a, j) for i <= j < K, and (d != null)
+// d_i = sum_{a <= i} T(a, i) ds_a.
+__global__ __launch_bounds__(KB) void k_basis_left(int K, const double* __restrict__ T, const double* __restrict__ W,
+                                                   double* __restrict__ G, int ldg, const double* __restrict__ ds,
+                                                   double* __restrict__ d) {
+    const int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x;
+    if (e < (int64_t)K * K) {
+        const int i = (int)(e % K), j = (int)(e / K);
+        if (i <= j) {
+            const double* ti = T + (int64_t)i * KLD;
+            const double* wj = W + (int64_t)j * KLD;
+            double s = wj[i];
+            for (int a = 0; a < i; ++a) s = fma(ti[a], wj[a], s);
+            G[(int64_t)i * ldg + j] = s;
+            G[(int64_t)j * ldg + i] = s;
+        }
+    }
+    if (d && blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < K; i += KB) {
+            const double* ti = T + (int64_t)i * KLD;
+            double s = ds[i];
+            for (int a = 0; a < i; ++a) s = fma(ti[a], ds[a], s);
+            d[i] = s;
+        }
+    }
+}
+
+// zt = T z (zt_k = sum_{i >= k} T(k, i) z_i).
+__global__ __launch_bounds__(KB) void k_basis_coef(int K, const double* __restrict__ T, const double* __restrict__ z,
+                                                   double* __restrict__ zt) {
+    for (int k = threadIdx.x; k < K; k += KB) {
+        double a = z[k];
+        for (int i = k + 1; i < K; ++i) a = fma(T[(int64_t)i * KLD + k], z[i], a);
+        zt[k] = a;
+    }
+}
+
+__global__ void k_basis_eye(int K0, double* __restrict__ T) {
+    // columns 0 .. K0-1 of the identity (the rest of T is written as columns are appended)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)K0 * KLD;
+         e += (int64_t)gridDim.x * blockDim.x)
+        T[e] = (e % KLD) == (e / KLD) ? 1.0 : 0.0;
+}
+
+void basis_identity(Ctx& c, int K0, double* T) {
+    if (K0 <= 0) return;
+    hipLaunchKernelGGL(k_basis_eye, grid_for((int64_t)K0 * KLD, KB, 1024), dim3(KB), 0, c.stream, K0, T);
+    MMOF_LAUNCH_CHECK();
+}
+
+void basis_extend(Ctx& c, int64_t n, int K, const double* Vs, int64_t ld, double* r, double* T, double* h,
+                  double* sq) {
+    MMOF_CHECK(K >= 1 && K < KMAX, MMOF_ERR_SHAPE, "too many Krylov columns");
+    const int nb = mdot_blocks(n);
+    double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX + 1)));
+    int* keep = static_cast<int*>(c.work("cgs_flag", sizeof(int)));
+    double* hc = static_cast<double*>(c.work("basis_hc", sizeof(double) * KMAX));
+    auto dots = [&](const double* xe, const int* skip, const char* tname) {
+        const int Kt = K + (xe ? 1 : 0);
+        {
+            ScopedTime st(&c, tname, skip ? 0.0 : (double)n * (8.0 * K + 8.0), skip ? 0.0 : 2.0 * n * Kt);
+            if (mdot_pairs(Vs, ld, r, xe))
+                hipLaunchKernelGGL((k_mdot2<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
+                                   n, K, Vs, ld, (const double*)r, xe, part, skip);
+            else
+                hipLaunchKernelGGL((k_mdot<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
+                                   n, K, Vs, ld, (const double*)r, xe, part, skip);
+            MMOF_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, Kt, part, 1.0, h, (double*)nullptr, 0,
+                           0, (double*)nullptr, skip);
+        MMOF_LAUNCH_CHECK();
+    };
+    // h = Vs^T r and h[K] = ||r||^2 in one pass
+    dots(r, nullptr, "mdot");
+    hipLaunchKernelGGL(k_basis_check, dim3(1), dim3(KB), 0, c.stream, K, (const double*)T, (const double*)h,
+                       (const double*)(h + K), hc, keep);
+    MMOF_LAUNCH_CHECK();
+    // where r lies mostly in the basis: r <- r - V V^T r explicitly (||r||^2 into h[K]) and
+    // h = Vs^T r again; these launches return at once otherwise
+    gemv_fused_impl<double, double>(c, n, K, Vs, ld, hc, -1.0, r, 1.0, r, (double*)nullptr, nullptr, h + K, keep,
+                                    "cgs_second");
+    dots(nullptr, keep, "cgs_second");
+    hipLaunchKernelGGL(k_basis_append, dim3(1), dim3(KB), 0, c.stream, K, T, (const double*)h,
+                       (const double*)(h + K), sq);
+    MMOF_LAUNCH_CHECK();
+}
+
+void basis_gram(Ctx& c, int K, const double* T, const double* Gs, const double* ds, double* G, double* d) {
+    if (K <= 0) return;
+    double* W = static_cast<double*>(c.work("basis_W", sizeof(double) * KLD * KLD));
+    const unsigned nb = (unsigned)cdiv((int64_t)K * K, KB);
+    hipLaunchKernelGGL(k_basis_right, dim3(nb), dim3(KB), 0, c.stream, K, Gs, KLD, T, W);
+    MMOF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_basis_left, dim3(nb), dim3(KB), 0, c.stream, K, T, (const double*)W, G, KLD, ds, d);
+    MMOF_LAUNCH_CHECK();
+}
+
+void basis_coef(Ctx& c, int K, const double* T, const double* z, double* zt) {
+    if (K <= 0) return;
+    hipLaunchKernelGGL(k_basis_coef, dim3(1), dim3(KB), 0, c.stream, K, T, z, zt);
+    MMOF_LAUNCH_CHECK();
+}
+
 template <class TO>
 void normalize2(Ctx& c, int64_t n, const double* x, const double* s2, double* s1, double* out_d, TO* out_t) {
     if (n == 0) return;

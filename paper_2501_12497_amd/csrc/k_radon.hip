@@ -87,43 +87,47 @@ __device__ __forceinline__ T hat_row_inner(const T* __restrict__ img, int roff, 
     return w0 * q.y + w1 * q.z + w2 * (lo ? q.x : q.w);
 }
 
-// Interior rows of an FP32 image in groups of RG: the ray centre of the group's first row in
-// FP64, split into its floor and an FP32 fraction fb; row k of the group at t = fb + k step
-// in FP32 (error below 1e-6 px for |step| <= 1, k < 8), pixel floor(t) + floor(xs) through a
-// floor-convert and weight fraction fract(t).  The four pixels xi - 1 .. xi + 2 come in one
-// 16-byte load (a 32-bit byte offset from the frame base, so the frame must hold fewer than
-// 2^30 pixels) and their weights max(0, 1 - |a| |x - xs|) are single FMAs whose results lie in
-// [0, 1], so the clamp of the outer two is the FMA's output clamp.  The caller guarantees
-// 1 + INTERIOR_MARGIN <= xs < ncol - 2 - INTERIOR_MARGIN on every row it passes, so the FP32
-// position never leaves the row.
+// Interior rows of an FP32 image in groups of G, three taps centred on the nearest pixel: with
+// n = round(xs) and d = xs - n in [-1/2, 1/2], the pixels n - 1, n, n + 1 have the weights
+// max(0, 1 - |a| (1 + d)), 1 - |a| |d| and max(0, 1 - |a| (1 - d)), and no other pixel is
+// within 1/|a| <= sqrt(2) of xs; the products are added to three running sums s0..s2 (one per
+// tap).  The group's first row: xs + 1/2 (xs0h: xs0 + 1/2) in FP64, split into its floor
+// and an FP32 fraction fb; row k at t = fb + k step in FP32 (error below 1e-6 px for
+// |step| <= 1, k < 8), n = floor(t) + that floor through a floor-convert, f = fract(t) = d + 1/2.
+// The three pixels come in one 12-byte load at a 32-bit byte offset (so the frame must hold
+// fewer than 2^30 pixels) from a per-row base that is the same for the whole wave; the outer
+// weights (1 - |a|/2) - |a| f and (1 - 3|a|/2) + |a| f are single FMAs clamped to [0, 1] by the
+// FMA's output clamp.  The caller guarantees 1/2 + INTERIOR_MARGIN <= xs < ncol - 3/2 -
+// INTERIOR_MARGIN on every row it passes, so the FP32 position never leaves the row.
 static constexpr int RG = 8;
 static constexpr double INTERIOR_MARGIN = 1e-3;
 
-__device__ __forceinline__ float hat_rows_f32(const float* __restrict__ img, int r, int ncol, double xs0,
-                                              double step, float aa) {
-    const double xb = fma((double)r, step, xs0);
+template <int G>
+__device__ __forceinline__ void hat_rows3_f32(const char* __restrict__ base, int r, int ncol, double xs0h,
+                                              double step, float aa, float& s0, float& s1, float& s2) {
+    const double xb = fma((double)r, step, xs0h);
     const double flb = floor(xb);
     const float fb = (float)(xb - flb);
     const float stepf = (float)step;
-    const float c1 = 1.f - aa, c2 = 1.f - 2.f * aa;
-    const uint32_t rowb = (uint32_t)(r * ncol + (int)flb - 1) * 4u;
+    const float cm = 1.f - 0.5f * aa, cp = 1.f - 1.5f * aa;
+    // the group's byte offset, formed once (kept opaque so that each row adds only its own
+    // pixel offset to it)
+    uint32_t rowb;
+    asm("v_mov_b32 %0, %1" : "=v"(rowb) : "v"((uint32_t)(r * ncol + (int)flb - 1) * 4u));
     const uint32_t ncolb = (uint32_t)ncol * 4u;
-    const char* __restrict__ base = reinterpret_cast<const char*>(img);
-    typedef float F4 __attribute__((ext_vector_type(4), aligned(4)));
-    float s0 = 0.f, s1 = 0.f;
+    typedef float F3 __attribute__((ext_vector_type(3), aligned(4)));
 #pragma unroll
-    for (int k = 0; k < RG; ++k) {
+    for (int k = 0; k < G; ++k) {
         const float t = fmaf((float)k, stepf, fb);
         int xr;
         asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(xr) : "v"(t));
-        const float fr = __builtin_amdgcn_fractf(t);
-        const F4 q = *reinterpret_cast<const F4*>(base + (rowb + (uint32_t)k * ncolb + ((uint32_t)xr << 2)));
-        s0 = fmaf(__builtin_amdgcn_fmed3f(fmaf(-aa, fr, c1), 0.f, 1.f), q.x, s0);
-        s1 = fmaf(fmaf(-aa, fr, 1.f), q.y, s1);
-        s0 = fmaf(fmaf(aa, fr, c1), q.z, s0);
-        s1 = fmaf(__builtin_amdgcn_fmed3f(fmaf(aa, fr, c2), 0.f, 1.f), q.w, s1);
+        const float f = __builtin_amdgcn_fractf(t);
+        const char* __restrict__ rowk = base + (size_t)k * ncolb;
+        const F3 q = *reinterpret_cast<const F3*>(rowk + (rowb + ((uint32_t)xr << 2)));
+        s0 = fmaf(__builtin_amdgcn_fmed3f(fmaf(-aa, f, cm), 0.f, 1.f), q.x, s0);
+        s1 = fmaf(fmaf(-aa, fabsf(f - 0.5f), 1.f), q.y, s1);
+        s2 = fmaf(__builtin_amdgcn_fmed3f(fmaf(aa, f, cp), 0.f, 1.f), q.z, s2);
     }
-    return s0 + s1;
 }
 
 // One workgroup of 8 waves per (frame, ANG consecutive angles, 64 bins): lane = bin, wave
@@ -143,9 +147,11 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // (uniform: angle, image in SGPRs)
     const int ang = rt.angle + wave / RSL, sl = wave % RSL;
     const int j = rt.bin0 + lane;
-    // FP32 interior rows by hat_rows_f32 (32-bit byte offsets within the frame)
-    const bool f32rows = sizeof(T) == 4 && (int64_t)f.ny * f.nx < ((int64_t)1 << 30);
-    const double margin = f32rows ? INTERIOR_MARGIN : 0.0;
+    // FP32 interior rows by hat_rows3_f32 (32-bit byte offsets within the frame); FP64 rows by
+    // hat_row_inner (a three-tap FP64 form with one 16-byte and one 8-byte load per row measured
+    // slower: the row's two load instructions bound either form)
+    const bool rows3 = sizeof(T) == 4 && (int64_t)f.ny * f.nx < ((int64_t)1 << 30);
+    const double margin = rows3 ? INTERIOR_MARGIN : 0.0;
     T acc = T(0);
     if (ang < f.n_ang && j < f.n_bins) {
         const double2 cs = trig[f.trig_off + ang];
@@ -170,6 +176,9 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
         // the rows where every candidate is inside (xs in [1, ncol - 2)), from xs linear in r
         auto row_of = [&](double x) { return (x - xs0) * inv_step; };
         int in_lo = r_lo, in_hi = r_lo;  // [in_lo, in_hi): interior rows
+        // the interior of the three-tap rows, or of hat_row_inner
+        const double x_in_lo = rows3 ? 0.5 + margin : 1.0;
+        const double x_in_hi = rows3 ? (double)ncol - 1.5 - margin : (double)ncol - 2.0;
         // (bounds are clamped to [0, nrow] in double before the conversion, so near-axis
         // angles, whose tiny slope puts the crossings far away, give in-range integers)
         const double dn = (double)nrow;
@@ -181,10 +190,10 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
             const double t_lo = fmin(ra, rb), t_hi = fmax(ra, rb);
             r_lo = max(r_lo, clamp_row(floor(t_lo) - 1.0));
             r_hi = min(r_hi, clamp_row(ceil(t_hi) + 2.0));
-            const double ia = row_of(1.0 + margin), ib = row_of((double)ncol - 2.0 - margin);
+            const double ia = row_of(x_in_lo), ib = row_of(x_in_hi);
             in_lo = max(r_lo, clamp_row(ceil(fmin(ia, ib)) + 1.0));
             in_hi = min(r_hi, clamp_row(floor(fmax(ia, ib)) - 1.0));
-        } else if (xs0 >= 1.0 + margin && xs0 < (double)ncol - 2.0 - margin) {
+        } else if (xs0 >= x_in_lo && xs0 < x_in_hi) {
             in_lo = r_lo;
             in_hi = r_hi;
         }
@@ -192,8 +201,14 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
         int r = r_lo;
         for (; r < min(in_lo, r_hi); ++r) acc += hat_row(img, r * ncol, ncol, fma((double)r, step, xs0), aa);
         if constexpr (sizeof(T) == 4) {
-            if (f32rows)
-                for (; r < in_hi - (RG - 1); r += RG) acc += hat_rows_f32(img, r, ncol, xs0, step, aa);
+            if (rows3) {
+                const char* __restrict__ base = reinterpret_cast<const char*>(img);
+                const double xs0h = xs0 + 0.5;
+                float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+                for (; r < in_hi - (RG - 1); r += RG) hat_rows3_f32<RG>(base, r, ncol, xs0h, step, aa, s0, s1, s2);
+                for (; r < in_hi; ++r) hat_rows3_f32<1>(base, r, ncol, xs0h, step, aa, s0, s1, s2);
+                acc += (s0 + s2) + s1;
+            }
         }
         for (; r < in_hi - 3; r += 4) {
             const T a0 = hat_row_inner(img, r * ncol, ncol, fma((double)r, step, xs0), aa);

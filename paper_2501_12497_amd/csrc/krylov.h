@@ -39,6 +39,23 @@ void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const doub
 // once when it is not needed, so nothing waits for the host.  sq[0] = ||x||^2 afterwards;
 // h: device scratch of K + 1 doubles.
 void cgs_once(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, double* x, double* sq, double* h);
+// Implicit basis: the orthonormal basis is V = Vs T, Vs the stored FP64 columns and T unit upper
+// triangular (device, column-major, leading dimension KLD; column j holds the coefficients of
+// v_j in Vs).  basis_identity: T's first K0 columns = those of the identity.
+void basis_identity(Ctx& c, int K0, double* T);
+// Extends the basis by the direction of r: h = Vs^T r and ||r||^2 in one pass over Vs (h:
+// device scratch of K + 1 doubles), g = T^T h = V^T r, rho^2 = ||r||^2 - ||g||^2 into sq[0],
+// and column K of T = e_K - T g / rho, so that v_K = r / rho - V g / rho; the caller then
+// stores r / rho as column K of Vs.  When r keeps less than 1/sqrt(2) of its norm outside the
+// basis, r <- r - V g explicitly and h is formed again first (decided on the device; the
+// launches of that pass return at once otherwise).  K < KMAX.
+void basis_extend(Ctx& c, int64_t n, int K, const double* Vs, int64_t ld, double* r, double* T, double* h,
+                  double* sq);
+// G = T^T Gs T (K x K, leading dimension KLD, written symmetric) and, when ds is not null,
+// d = T^T ds.
+void basis_gram(Ctx& c, int K, const double* T, const double* Gs, const double* ds, double* G, double* d);
+// zt = T z: the coefficients in Vs of V z.
+void basis_coef(Ctx& c, int K, const double* T, const double* z, double* zt);
 // s = sqrt(s2[0]) (written to s1 when not null); out_d = x / s and out_t = (TO)(x / s)
 // (a zero vector when s = 0).
 template <class TO>

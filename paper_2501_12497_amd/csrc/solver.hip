@@ -72,6 +72,12 @@ struct Solver {
     // workspace
     double *V, *U, *r, *tmp_n, *tmp_m, *GA, *GT, *dvec, *z, *h, *sc, *res, *scal;
     double* AVs;  // H v_j of the Golub-Kahan start (FP64, columns 0 .. ell-2)
+    // implicit basis (MMOF_REORTH_IMPLICIT): V = Vs T with the stored columns Vs (the buffer V)
+    // and T unit upper triangular; G_H, d and G_T are formed for Vs (GAs, ds, GTs) and mapped
+    // to V (GA, dvec, GT) before each projected solve, and u = V z = Vs (T z) (zt = T z).
+    // Otherwise Vs = V, T = I: GAs, ds, GTs and zt alias GA, dvec, GT and z.
+    bool implicit = false;
+    double *Tb = nullptr, *GAs = nullptr, *GTs = nullptr, *ds = nullptr, *zt = nullptr;
     TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *yW, *flow_v, *flow_vr, *flow_tmp, *I;
     // flow on reduced frames: their geometry (owned by the plan), frames and flow
     int fscale = 1;
@@ -102,6 +108,7 @@ struct Solver {
         fm.n_sweeps = p.n_sweeps;
         fm.ell = p.of_ell;
         fm.n_iter = p.of_iters;
+        implicit = p.reorth == MMOF_REORTH_IMPLICIT;
         if (flow && fscale > 1) {
             auto& r = P.reduced[fscale];
             if (!r) r = make_reduced_geom(g, fscale, c.stream);
@@ -144,6 +151,18 @@ struct Solver {
         dvec = ws<double>("dvec", KMAX);
         z = ws<double>("z", KMAX);
         res = ws<double>("res", 8);
+        if (implicit) {
+            Tb = ws<double>("T", (int64_t)KLD * KLD);
+            GAs = ws<double>("GAs", KLD * KLD);
+            GTs = ws<double>("GTs", KLD * KLD);
+            ds = ws<double>("ds", KMAX);
+            zt = ws<double>("zt", KMAX);
+        } else {
+            GAs = GA;
+            GTs = GT;
+            ds = dvec;
+            zt = z;
+        }
         AV = wsx("AV", (int64_t)Kcap * m);
         TV = wsx("TV", (int64_t)Kcap * R);
         u_op = wsx("u_op", n);
@@ -325,7 +344,7 @@ struct Solver {
             norm_into(len, x, sq);
             return;
         }
-        if (p.reorth == MMOF_REORTH_AUTO) {
+        if (p.reorth != MMOF_REORTH_TWICE) {
             cgs_once(c, len, k, Q, len, x, sq, h);
             return;
         }
@@ -352,8 +371,27 @@ struct Solver {
             convert<double, TX>(c, m, AVs + (int64_t)j * m, avj);
         else
             A(vin_n, avj);
-        gram_row<TX>(c, m, j, AV, m, b, GA, KLD, dvec + j);
+        gram_row<TX>(c, m, j, AV, m, b, GAs, KLD, ds + j);
         theta(vin_n, TV + (int64_t)j * R);
+    }
+
+    // The Gram matrices and d of the true basis from those of the stored columns, the
+    // projected solve, and the coefficients of u = V z in the stored columns.
+    void projected(int Kg) {
+        if (implicit) {
+            basis_gram(c, Kg, Tb, GAs, ds, GA, dvec);
+            basis_gram(c, Kg, Tb, GTs, nullptr, GT, nullptr);
+        }
+        small_solve(c, Kg, GA, GT, dvec, sc, p.fixed_lambda, z, scal + 8, sc + 2);
+        if (implicit) basis_coef(c, Kg, Tb, z, zt);
+    }
+    // The new direction r against the basis of K columns: ||r'||^2 into sq; r' / ||r'|| becomes
+    // column K of V (explicit passes) or of Vs (implicit basis: r' = r, T gets column K).
+    void extend(int K, double* sq) {
+        if (implicit)
+            basis_extend(c, n, K, V, n, r, Tb, h, sq);
+        else
+            reorth(n, V, K, r, sq);
     }
 
     const double* b = nullptr;
@@ -457,6 +495,8 @@ struct Solver {
             launch_flow_radius(c, g, dt, flow_vr, rad_vr);
         }
         const int start_av = ph.K_in == 0 ? p.ell - 1 : ph.start_av;
+        // the start's columns are orthonormal as stored (a later phase keeps the T it gets)
+        if (implicit && ph.k_begin == 0) basis_identity(c, K, Tb);
         for (int j = 0; j < K; ++j) add_column(j, false, start_av);
         int status = 0;
         int iters = 0;
@@ -504,18 +544,18 @@ struct Solver {
                 // 2. nu = Theta u^(k); FP64 weights; weighted Gram of Theta V
                 if (!nu_fresh) theta(u_op, nu);
                 weights(nu, w2, K);
-                gram_theta(K, TV, w2, GT);
+                gram_theta(K, TV, w2, GTs);
                 // 3-5. lambda (discrepancy principle) and z; lambda is kept in sc[2] as the next warm start
-                small_solve(c, K, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
+                projected(K);
             }
             queued = false;
             // 6. u^(k+1) = V z (FP64 and operator copies, and ||u - u_true||^2)
-            gemv_fused<double, TX>(c, n, K, V, n, z, 1.0, nullptr, 0.0, u_io, u_op, p.u_true,
+            gemv_fused<double, TX>(c, n, K, V, n, zt, 1.0, nullptr, 0.0, u_io, u_op, p.u_true,
                                    p.u_true ? scal + 6 : nullptr);
             const bool last = ph.final && (k == ph.k_end - 1);
             if (!last) {
                 // 7. r = H^T (H V z - b) + lambda Theta^T P^2 Theta V z
-                gemv_fused<TX, TX>(c, m, K, AV, m, z, 1.0, b, -1.0, nullptr, vin_m, nullptr, nullptr);
+                gemv_fused<TX, TX>(c, m, K, AV, m, zt, 1.0, b, -1.0, nullptr, vin_m, nullptr, nullptr);
                 std::string key = graph_key("residual");
                 key += "|" + std::to_string(reinterpret_cast<uintptr_t>(yR)) + "|" +
                        std::to_string(reinterpret_cast<uintptr_t>(yW)) + "|" +
@@ -530,8 +570,8 @@ struct Solver {
                     thetaT(yW, out_n2);
                     residual_combine<TX>(c, n, out_n, out_n2, res, r);
                 });
-                // 8. CGS2 against V, ||r||^2
-                reorth(n, V, K, r, scal + 7);
+                // 8. r against the basis, ||r'||^2
+                extend(K, scal + 7);
                 // Theta u^(k+1) is the next iteration's nu unless the flow changes first
                 std::swap(nu, yR);
                 nu_fresh = true;
@@ -547,8 +587,8 @@ struct Solver {
                 add_column(K, true);
                 if (!nu_fresh) theta(u_op, nu);
                 weights(nu, w2, K + 1);
-                gram_theta(K + 1, TV, w2, GT);
-                small_solve(c, K + 1, GA, GT, dvec, sc, p.fixed_lambda, z, res, sc + 2);
+                gram_theta(K + 1, TV, w2, GTs);
+                projected(K + 1);
             }
             // counts of work queued ahead, taken back if the iteration ends the solve
             auto take_back = [&] {

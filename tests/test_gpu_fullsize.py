@@ -222,13 +222,15 @@ def _golden_solve():
         return json.load(f)
 
 
-@pytest.mark.parametrize("mode", ["f64", "f64/twice", "f32+refine", "f32"])
+@pytest.mark.parametrize("mode", ["f64", "f64/auto", "f64/twice", "f32+refine", "f32"])
 def test_solve_ellipse128_full(mode):
     """The whole 30-iteration solve of the benchmark workload against the oracle's stored run.
 
-    FP64 operators follow the oracle iteration by iteration, with the second Gram-Schmidt pass
-    taken only where Kahan's test asks for it (the default) or always ("/twice", as the
-    oracle does): the basis is orthonormal to working precision either way.  With FP32 operators in the MM
+    FP64 operators follow the oracle iteration by iteration with each of the solve's ways to
+    orthogonalise a new direction: the implicit basis V = Vs T (the default), one explicit
+    Gram-Schmidt pass and a second one where Kahan's test asks for it ("/auto"), or two
+    always ("/twice", as the oracle does); the basis is orthonormal to working precision in
+    every case.  With FP32 operators in the MM
     iterations (the Golub-Kahan start uses FP64 operators) the final RRE is within 1e-4 of
     the oracle's (the solve bar), with or without FP64 operators in the last 10 iterations;
     every iterate's RRE is also held to 1e-6 (about 2e-8 is typical), which a start built
@@ -240,8 +242,8 @@ def test_solve_ellipse128_full(mode):
     kw = dict(op_dtype=mode.split("+")[0].split("/")[0])
     if mode.endswith("refine"):
         kw["refine_iters"] = 10
-    if mode.endswith("twice"):
-        kw["reorth"] = "twice"
+    if "/" in mode:
+        kw["reorth"] = mode.split("/")[1]
     res = E["B"].solve_joint(E["plan"], E["bt"], E["delta"], u_true=E["ut"], **prm, **kw)
     assert res.iters == G["iters"]
     print(mode, "final rre", res.rre[-1], "oracle", G["rre"][-1])

@@ -182,3 +182,76 @@ def test_reorth_rejects_bad_mode(B):
     with pytest.raises(MMOFError) as e:
         B.reorth(Q, x, 7)
     assert e.value.code == -1
+
+
+def _implicit_basis(r, n, K, spread):
+    """An orthonormal V (n x K) and a unit upper-triangular T with off-diagonal entries of size
+    `spread`; the stored columns Vs = V T^-1, so that V = Vs T."""
+    Q, _ = np.linalg.qr(r.standard_normal((n, K)))
+    T = np.eye(K) + np.triu(r.standard_normal((K, K)) * spread, 1)
+    Vs = Q @ np.linalg.inv(T)
+    return Q, T, Vs
+
+
+def _device_T(T):
+    import torch
+    K = T.shape[0]
+    Tt = np.zeros((256, 256))
+    Tt[:K, :K] = T.T          # row j of the buffer = column j of T
+    return torch.as_tensor(Tt, device="cuda")
+
+
+@pytest.mark.parametrize("K", [1, 10, 39, 100, 255])
+def test_basis_extend_implicit_step(B, K):
+    """A direction with most of its norm outside span(V): one pass over Vs gives g = V^T r,
+    rho^2 = ||r||^2 - ||g||^2 and the new column of T, e_K - T g / rho; r is left as it is, and
+    the new basis vector r / rho - V g / rho is a unit vector orthogonal to V (numpy, FP64)."""
+    import torch
+    r = np.random.default_rng(900 + K)
+    n = 20000 + 7 * K
+    Q, T, Vs = _implicit_basis(r, n, K, 1e-3)
+    x0 = r.standard_normal(n) + Q @ r.standard_normal(K)
+    x = torch.as_tensor(x0, device="cuda")
+    Td = _device_T(T)
+    rho2 = B.basis_extend(torch.as_tensor(np.ascontiguousarray(Vs.T), device="cuda"), x, Td)
+    np.testing.assert_array_equal(x.cpu().numpy(), x0)
+    g = Q.T @ x0
+    exp2 = x0 @ x0 - g @ g
+    assert abs(rho2 - exp2) <= 1e-12 * exp2
+    col = Td.cpu().numpy()[K, :K + 1]
+    exp_col = -(T @ g) / np.sqrt(exp2)
+    assert np.abs(col[:K] - exp_col).max() <= 1e-12 * (np.abs(T) @ np.abs(g)).max() / np.sqrt(exp2) + 1e-15
+    assert col[K] == 1.0
+    vK = x0 / np.sqrt(rho2) + Vs @ col[:K]
+    assert abs(np.linalg.norm(vK) - 1.0) <= 1e-12
+    assert np.abs(Q.T @ vK).max() <= 1e-12
+    np.testing.assert_array_equal(Td.cpu().numpy()[:K, :K], T.T)   # the earlier columns untouched
+
+
+@pytest.mark.parametrize("K", [1, 10, 39, 100])
+def test_basis_extend_explicit_pass_when_needed(B, K):
+    """A direction within 1e-9 of span(V): the device test takes the explicit pass r <- r - V g
+    first (r changes), then the implicit step on what is left; the new basis vector is still a
+    unit vector orthogonal to V to working precision relative to it."""
+    import torch
+    r = np.random.default_rng(950 + K)
+    n = 20000 + 7 * K
+    Q, T, Vs = _implicit_basis(r, n, K, 1e-3)
+    w = r.standard_normal(n)
+    w -= Q @ (Q.T @ w)
+    w -= Q @ (Q.T @ w)
+    w /= np.linalg.norm(w)
+    c = r.standard_normal(K)
+    x0 = Q @ c + 1e-9 * np.linalg.norm(c) * w
+    x = torch.as_tensor(x0, device="cuda")
+    Td = _device_T(T)
+    rho2 = B.basis_extend(torch.as_tensor(np.ascontiguousarray(Vs.T), device="cuda"), x, Td)
+    x1 = x.cpu().numpy()
+    assert np.linalg.norm(x1) <= 1e-6 * np.linalg.norm(x0)        # the explicit pass ran
+    rem = 1e-9 * np.linalg.norm(c)
+    assert abs(np.sqrt(rho2) - rem) <= 1e-5 * rem
+    col = Td.cpu().numpy()[K, :K + 1]
+    vK = x1 / np.sqrt(rho2) + Vs @ col[:K]
+    assert abs(np.linalg.norm(vK) - 1.0) <= 1e-9
+    assert np.abs(Q.T @ vK).max() <= 1e-12
+    assert np.abs(vK - w).max() <= 1e-5 * np.abs(w).max()
