@@ -26,7 +26,7 @@ struct RayTile {
     int32_t frame, angle, bin0, pad;
 };
 
-static constexpr int RTW = 16, RTH = 16;  // pixel tiles of the transpose (backprojection)
+static constexpr int RTW = 16, RTH = 16;  // pixel tiles of the fan-beam transpose
 
 // Per-frame transpose uT[f][x][y] = u[f][y][x] through a 32x33 LDS tile.
 template <class T>
@@ -237,16 +237,21 @@ __global__ __launch_bounds__(512) void k_radon_fwd(const RayTile* __restrict__ r
     }
 }
 
-// Transpose: one workgroup per 16 x 16 pixel tile.  For each angle the tile projects onto
-// fewer than AW consecutive bins; those sinogram windows are staged in LDS, AC angles at a
-// time (zeros outside the detector), and every pixel then gathers its two hat weights per
-// angle from LDS.  FP32: per (tile, angle) the detector coordinate of the tile centre in FP64,
-// split into its floor J and an FP32 fraction; a pixel at (dx, dy) from the centre (|dx|, |dy|
-// <= 7.5) is at J + t, t = frac + dx cos + dy sin in FP32 (error below 3e-6 bins), and its two
-// weights come from floor(t) and fract(t); the window has one bin of margin on each side, so a
-// floor one off at an integer stays inside it (and gives the same weights).  FP64: each
-// pixel's position in FP64 from its own coordinates (the tile-centre form measured slower).
-static constexpr int AW = 32, AC = 32;
+// Transpose: one workgroup per ATW x ATH = 32 x 16 pixel tile, each lane two pixels 16 apart in
+// a row (x and x + 16).  For each angle the tile projects onto fewer than AW - 2 consecutive
+// bins (its extent sqrt(31^2 + 15^2) < 35 bins); those sinogram windows are staged in LDS, AC
+// angles at a time, as pairs (b_j, b_{j+1} - b_j) with zeros outside the detector, and a pixel
+// then gathers b_j0 + f (b_j0+1 - b_j0) per angle with one LDS load.  FP32: per (tile, angle)
+// the detector coordinate of the tile centre in FP64, split into its floor J and an FP32
+// fraction; the lane's first pixel at (dx, dy) from the centre (|dx| <= 15.5, |dy| <= 7.5) is at
+// J + t, t = frac + dx cos + dy sin in FP32, the second at t + 16 cos (error below 5e-6 bins),
+// and the weights come from floor(t) and fract(t); the window has one bin of margin on each
+// side, so a floor one off at an integer stays inside it (and gives the same value).  FP64:
+// each lane's first position in FP64 from its own coordinates, the second 16 cos further.
+// The windows cover the whole tile, also where it overhangs the frame, so every lane's
+// gathers stay inside them; pixels outside the frame are not written.
+static constexpr int ATW = 32, ATH = 16;  // pixel tiles of the transpose (parallel beam)
+static constexpr int AW = 48, AC = 32;
 
 struct AdjAngle {
     float frac, c, s;
@@ -257,27 +262,27 @@ template <class T>
 __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tiles, const RadonFrame* __restrict__ rf,
                                                    const double2* __restrict__ trig, const T* __restrict__ b,
                                                    T* __restrict__ u) {
-    __shared__ T win[AC][AW];
+    typedef T P2 __attribute__((ext_vector_type(2)));  // {b_j, b_{j+1} - b_j}
+    __shared__ P2 win[AC][AW];
     __shared__ int jlo[AC];
     __shared__ double2 scs[AC];
+    __shared__ AdjAngle aa[AC];
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const RadonFrame f = rf[tl.frame];
-    const int x = tl.x0 + (int)(threadIdx.x % RTW);
-    const int y = tl.y0 + (int)(threadIdx.x / RTW);
-    const bool inside = x < f.nx && y < f.ny;
+    const int lx = (int)(threadIdx.x % 16), ly = (int)(threadIdx.x / 16);
+    const int x = tl.x0 + lx, y = tl.y0 + ly;  // the lane's pixels: (x, y) and (x + 16, y)
+    const bool in0 = x < f.nx && y < f.ny, in1 = x + 16 < f.nx && y < f.ny;
     const double hx = 0.5 * (f.nx - 1), hy = 0.5 * (f.ny - 1);
     const double X = x - hx, Y = y - hy;
     const double cd = 0.5 * (f.n_bins - 1);
-    // tile corners (clipped to the frame) for the window bounds
-    const double X0 = tl.x0 - hx, X1 = min(tl.x0 + RTW, f.nx) - 1 - hx;
-    const double Y0 = tl.y0 - hy, Y1 = min(tl.y0 + RTH, f.ny) - 1 - hy;
+    // corners of the whole tile for the window bounds
+    const double X0 = tl.x0 - hx, X1 = tl.x0 + ATW - 1 - hx;
+    const double Y0 = tl.y0 - hy, Y1 = tl.y0 + ATH - 1 - hy;
     const T* sino = b + f.sino_off;
-    T acc = T(0);
-    // FP32 path: offsets of this pixel from the tile centre, and the per-angle bases
-    __shared__ AdjAngle aa[AC];
-    const double XC = tl.x0 + 0.5 * (RTW - 1) - hx, YC = tl.y0 + 0.5 * (RTH - 1) - hy;
-    const float dxc = (float)(threadIdx.x % RTW) - 0.5f * (RTW - 1);
-    const float dyc = (float)(threadIdx.x / RTW) - 0.5f * (RTH - 1);
+    T acc0 = T(0), acc1 = T(0);
+    const double XC = tl.x0 + 0.5 * (ATW - 1) - hx, YC = tl.y0 + 0.5 * (ATH - 1) - hy;
+    const float dxc = (float)lx - 0.5f * (ATW - 1);
+    const float dyc = (float)ly - 0.5f * (ATH - 1);
     for (int k0 = 0; k0 < f.n_ang; k0 += AC) {
         const int nk = min(AC, f.n_ang - k0);
         __syncthreads();  // the previous chunk's windows are no longer read
@@ -291,56 +296,64 @@ __global__ __launch_bounds__(256) void k_radon_adj(const Tile* __restrict__ tile
                 const double pc = fma(XC, cs.x, fma(YC, cs.y, cd));
                 const double J = floor(pc);
                 aa[threadIdx.x] = AdjAngle{(float)(pc - J), (float)cs.x, (float)cs.y,
-                                           (uint32_t)((int)threadIdx.x * AW + (int)J - lo) * 4u};
+                                           (uint32_t)((int)threadIdx.x * AW + (int)J - lo) * (uint32_t)sizeof(P2)};
             }
         }
         __syncthreads();
         for (int i = threadIdx.x; i < nk * AW; i += 256) {
             const int kk = i / AW, w = i % AW;
             const int j = jlo[kk] + w;
-            win[kk][w] = (j >= 0 && j < f.n_bins) ? sino[(int64_t)(k0 + kk) * f.n_bins + j] : T(0);
+            const T* row = sino + (int64_t)(k0 + kk) * f.n_bins;
+            const T v0 = (j >= 0 && j < f.n_bins) ? row[j] : T(0);
+            const T v1 = (j + 1 >= 0 && j + 1 < f.n_bins) ? row[j + 1] : T(0);
+            win[kk][w] = P2{v0, v1 - v0};
         }
         __syncthreads();
+        if (!in0) continue;
         if constexpr (sizeof(T) == 4) {
-            if (inside) {
-                const char* wb = reinterpret_cast<const char*>(&win[0][0]);
-                float acc1 = 0.f, acc2 = 0.f;
-                auto one = [&](int kk) {
-                    const AdjAngle g = aa[kk];
-                    const float t = fmaf(dxc, g.c, fmaf(dyc, g.s, g.frac));
-                    int w0;
-                    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(w0) : "v"(t));
-                    const float fr = __builtin_amdgcn_fractf(t);
-                    const float* q = reinterpret_cast<const float*>(wb + (g.base + ((uint32_t)w0 << 2)));
-                    const float a = q[0], bq = q[1];
-                    acc1 += a;
-                    acc2 = fmaf(fr, bq - a, acc2);
-                };
-                int kk = 0;
-                for (; kk + 4 <= nk; kk += 4) {
-                    one(kk);
-                    one(kk + 1);
-                    one(kk + 2);
-                    one(kk + 3);
-                }
-                for (; kk < nk; ++kk) one(kk);
-                acc += acc1 + acc2;
+            const char* wb = reinterpret_cast<const char*>(&win[0][0]);
+            float a0 = 0.f, d0 = 0.f, a1 = 0.f, d1 = 0.f;
+            auto one = [&](int kk) {
+                const AdjAngle g = aa[kk];
+                const float t0 = fmaf(dxc, g.c, fmaf(dyc, g.s, g.frac));
+                const float t1 = fmaf(16.f, g.c, t0);
+                int w0, w1;
+                asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(w0) : "v"(t0));
+                asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(w1) : "v"(t1));
+                const float f0 = __builtin_amdgcn_fractf(t0), f1 = __builtin_amdgcn_fractf(t1);
+                const P2 q0 = *reinterpret_cast<const P2*>(wb + (g.base + ((uint32_t)w0 << 3)));
+                const P2 q1 = *reinterpret_cast<const P2*>(wb + (g.base + ((uint32_t)w1 << 3)));
+                a0 += q0.x;
+                d0 = fmaf(f0, q0.y, d0);
+                a1 += q1.x;
+                d1 = fmaf(f1, q1.y, d1);
+            };
+            int kk = 0;
+            for (; kk + 4 <= nk; kk += 4) {
+                one(kk);
+                one(kk + 1);
+                one(kk + 2);
+                one(kk + 3);
             }
-            continue;
-        }
-        if (inside) {
+            for (; kk < nk; ++kk) one(kk);
+            acc0 += a0 + d0;
+            acc1 += a1 + d1;
+        } else {
 #pragma unroll 4
             for (int kk = 0; kk < nk; ++kk) {
                 const double2 cs = scs[kk];
-                const double pos = fma(X, cs.x, fma(Y, cs.y, cd));
-                const double fl = floor(pos);
-                const int w0 = (int)fl - jlo[kk];
-                const T fr = (T)(pos - fl);
-                acc += (T(1) - fr) * win[kk][w0] + fr * win[kk][w0 + 1];
+                const double p0 = fma(X, cs.x, fma(Y, cs.y, cd));
+                const double p1 = fma(16.0, cs.x, p0);
+                const double fl0 = floor(p0), fl1 = floor(p1);
+                const P2 q0 = win[kk][(int)fl0 - jlo[kk]];
+                const P2 q1 = win[kk][(int)fl1 - jlo[kk]];
+                acc0 += q0.x + (T)(p0 - fl0) * q0.y;
+                acc1 += q1.x + (T)(p1 - fl1) * q1.y;
             }
         }
     }
-    if (inside) u[f.u_off + (int64_t)y * f.nx + x] = acc;
+    if (in0) u[f.u_off + (int64_t)y * f.nx + x] = acc0;
+    if (in1) u[f.u_off + (int64_t)y * f.nx + x + 16] = acc1;
 }
 
 // ----------------------------------------------------------------------------- host side
@@ -377,8 +390,10 @@ void radon_plan_init(Ctx& c, Plan& p, const double* cs) {
                     for (int j0 = 0; j0 < r.n_bins; j0 += 64) rays[gi].push_back(RayTile{(int32_t)fi, k, j0, 0});
                 }
         }
-        for (int y0 = 0; y0 < fr.ny; y0 += RTH)
-            for (int x0 = 0; x0 < fr.nx; x0 += RTW) px.push_back(Tile{(int32_t)fi, y0, x0, 0});
+        // pixel tiles of the transpose: 32 x 16 for the parallel beam, 16 x 16 for the fan beam
+        const int tw = p.kind == 2 ? RTW : ATW, th = p.kind == 2 ? RTH : ATH;
+        for (int y0 = 0; y0 < fr.ny; y0 += th)
+            for (int x0 = 0; x0 < fr.nx; x0 += tw) px.push_back(Tile{(int32_t)fi, y0, x0, 0});
         for (int y0 = 0; y0 < fr.ny; y0 += 32)
             for (int x0 = 0; x0 < fr.nx; x0 += 32) tr.push_back(Tile{(int32_t)fi, y0, x0, 0});
         sino += (int64_t)r.n_ang * r.n_bins;
