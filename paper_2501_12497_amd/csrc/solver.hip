@@ -75,9 +75,11 @@ struct Solver {
     // implicit basis (MMOF_REORTH_IMPLICIT): V = Vs T with the stored columns Vs (the buffer V)
     // and T unit upper triangular; G_H, d and G_T are formed for Vs (GAs, ds, GTs) and mapped
     // to V (GA, dvec, GT) before each projected solve, and u = V z = Vs (T z) (zt = T z).
-    // Otherwise Vs = V, T = I: GAs, ds, GTs and zt alias GA, dvec, GT and z.
+    // Otherwise Vs = V, T = I: GAs, ds and GTs alias GA, dvec and GT, and zt is a copy of z.
+    // zt_prev keeps the previous projected solve's coefficients (the iterate a stop returns
+    // when the next solve was already queued).
     bool implicit = false;
-    double *Tb = nullptr, *GAs = nullptr, *GTs = nullptr, *ds = nullptr, *zt = nullptr;
+    double *Tb = nullptr, *GAs = nullptr, *GTs = nullptr, *ds = nullptr, *zt = nullptr, *zt_prev = nullptr;
     TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *yW, *flow_v, *flow_vr, *flow_tmp, *I;
     // flow on reduced frames: their geometry (owned by the plan), frames and flow
     int fscale = 1;
@@ -151,17 +153,17 @@ struct Solver {
         dvec = ws<double>("dvec", KMAX);
         z = ws<double>("z", KMAX);
         res = ws<double>("res", 8);
+        zt = ws<double>("zt", KMAX);
+        zt_prev = ws<double>("zt_prev", KMAX);
         if (implicit) {
             Tb = ws<double>("T", (int64_t)KLD * KLD);
             GAs = ws<double>("GAs", KLD * KLD);
             GTs = ws<double>("GTs", KLD * KLD);
             ds = ws<double>("ds", KMAX);
-            zt = ws<double>("zt", KMAX);
         } else {
             GAs = GA;
             GTs = GT;
             ds = dvec;
-            zt = z;
         }
         AV = wsx("AV", (int64_t)Kcap * m);
         TV = wsx("TV", (int64_t)Kcap * R);
@@ -383,7 +385,11 @@ struct Solver {
             basis_gram(c, Kg, Tb, GTs, nullptr, GT, nullptr);
         }
         small_solve(c, Kg, GA, GT, dvec, sc, p.fixed_lambda, z, scal + 8, sc + 2);
-        if (implicit) basis_coef(c, Kg, Tb, z, zt);
+        std::swap(zt, zt_prev);
+        if (implicit)
+            basis_coef(c, Kg, Tb, z, zt);
+        else
+            MMOF_HIP(hipMemcpyAsync(zt, z, sizeof(double) * (size_t)Kg, hipMemcpyDeviceToDevice, c.stream));
     }
     // The new direction r against the basis of K columns: ||r'||^2 into sq; r' / ||r'|| becomes
     // column K of V (explicit passes) or of Vs (implicit basis: r' = r, T gets column K).
@@ -549,8 +555,10 @@ struct Solver {
                 projected(K);
             }
             queued = false;
-            // 6. u^(k+1) = V z (FP64 and operator copies, and ||u - u_true||^2)
-            gemv_fused<double, TX>(c, n, K, V, n, zt, 1.0, nullptr, 0.0, u_io, u_op, p.u_true,
+            // 6. u^(k+1) = V z (the operator copy, ||u - u_true||^2, and the FP64 copy on the phase's
+            // last iteration; an earlier stop forms the FP64 copy afterwards)
+            const bool write_u = k == ph.k_end - 1;
+            gemv_fused<double, TX>(c, n, K, V, n, zt, 1.0, nullptr, 0.0, write_u ? u_io : nullptr, u_op, p.u_true,
                                    p.u_true ? scal + 6 : nullptr);
             const bool last = ph.final && (k == ph.k_end - 1);
             if (!last) {
@@ -582,6 +590,8 @@ struct Solver {
                                K + 1 <= Kcap;
             mmof_report saved{};
             if (rep) saved = *rep;
+            // the coefficients of u^(k+1), whatever is queued next
+            const double* zt_k = zt;
             if (ahead) {
                 normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
                 add_column(K, true);
@@ -620,8 +630,15 @@ struct Solver {
                 if (rep->dp_status) rep->dp_status[k] = st;
             }
             if (rep) rep->n_cols = K;
+            // u^(k+1) in FP64 when the phase stops before its last iteration
+            auto finish_u = [&] {
+                if (!write_u)
+                    gemv_fused<double, TX>(c, n, K, V, n, zt_k, 1.0, nullptr, 0.0, u_io, (TX*)nullptr, nullptr,
+                                           nullptr);
+            };
             if (p.u_true && p.rre_target > 0 && rre <= p.rre_target) {
                 take_back();
+                finish_u();
                 stopped = true;
                 break;
             }
@@ -632,6 +649,7 @@ struct Solver {
             // 9. breakdown or append r/||r||
             if (!(rnorm > 1e-14 * atb)) {
                 take_back();
+                finish_u();
                 status = MMOF_WARN_BREAKDOWN;
                 stopped = true;
                 break;

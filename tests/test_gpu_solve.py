@@ -127,6 +127,9 @@ def test_solve_disk32_refined(B):
     tgt = res.rre[4]
     early = B.solve_joint(plan, bt, delta, u_true=ut, op_dtype="f32", refine_iters=5, rre_target=tgt, **prm)
     assert early.iters <= 15 and early.rre[-1] <= tgt and early.status == 0
+    # the returned solution is the iterate whose RRE stopped the solve (formed after the stop)
+    rre_u = float(torch.linalg.vector_norm(early.u - ut) / torch.linalg.vector_norm(ut))
+    assert abs(rre_u - early.rre[-1]) <= 1e-9 * early.rre[-1], (rre_u, early.rre[-1])
 
 
 @pytest.mark.parametrize("sizes", [[(3, 24, 30), (4, 18, 18)], [(3, 24, 32), (4, 18, 20)]], ids=["ragged", "vec4"])
