@@ -50,8 +50,9 @@ def _angles(r, n_t, n_th):
     return a
 
 
+@pytest.mark.parametrize("cand", [0, 1, 2, 3])   # angle groups of 1, 2, 4, 8 per workgroup
 @pytest.mark.parametrize("which", ["f64", "f32"])
-def test_radon_forward_and_adjoint(B, which):
+def test_radon_forward_and_adjoint(B, which, cand):
     import torch
     dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
     r = np.random.default_rng(10)
@@ -61,6 +62,7 @@ def test_radon_forward_and_adjoint(B, which):
     angs = [_angles(r, s[0], k) for s, k in zip(SIZES, n_th)]
     stack = B.Stack(SIZES)
     plan = B.plan_radon(stack, n_th, nbins, np.concatenate([a.ravel() for a in angs]))
+    plan.set_tile("radon_fwd", cand, dt)
     if dt == torch.float32:
         us = [roundtrip32(u) for u in us]
     b = host(B.apply_A(plan, dev(pack(us), dt)))
@@ -74,6 +76,31 @@ def test_radon_forward_and_adjoint(B, which):
     expu = [forward.radon_adj(x, a, s[1], s[2]) for x, a, s in zip(bs, angs, SIZES)]
     scale = pack([forward.radon_adj(np.abs(x), a, s[1], s[2]) for x, a, s in zip(bs, angs, SIZES)])
     assert_close(u, pack(expu), tol, scale)
+
+
+@pytest.mark.parametrize("cand", [0, 3])
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_radon_forward_wide_frames(B, which, cand):
+    """Non-square frames of several hundred pixels (two 300 x 700 frames and a 620 x 90 one),
+    angles that include 0, 45, 90 and 135 degrees and a detector wider than the frames'
+    diagonal, with one and with eight angles per workgroup, against the oracle element by
+    element."""
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    r = np.random.default_rng(14)
+    sizes = [(2, 300, 700), (1, 620, 90)]
+    us = [r.uniform(0.0, 1.0, (nt, ny, nx)) for nt, ny, nx in sizes]
+    base = np.array([0.0, 0.25, 0.5, 0.75]) * math.pi
+    angs = [np.stack([np.concatenate([base, r.uniform(0, math.pi, 5)]) for _ in range(s[0])]) for s in sizes]
+    nbins = [bins_for(700) + 40, bins_for(620)]
+    plan = B.plan_radon(B.Stack(sizes), [9, 9], nbins, np.concatenate([a.ravel() for a in angs]))
+    plan.set_tile("radon_fwd", cand, dt)
+    if dt == torch.float32:
+        us = [roundtrip32(u) for u in us]
+    b = host(B.apply_A(plan, dev(pack(us), dt)))
+    exp = pack([forward.radon_fwd(u, a, nb) for u, a, nb in zip(us, angs, nbins)])
+    scale = pack([forward.radon_fwd(np.abs(u), a, nb) for u, a, nb in zip(us, angs, nbins)])
+    assert_close(b, exp, tol, scale)
 
 
 def test_radon_adjoint_identity_fp64(B):
