@@ -448,10 +448,13 @@ int launch_hs_sweeps(Ctx& c, Geom& g, int dt, const void* I, void* v, void* tmp,
 // Block means over f x f blocks of the frames (mode 0) or of the two flow components of the
 // pairs, divided by f (mode 1); a block at the right or bottom edge averages its in-frame
 // pixels.  One thread per reduced pixel over the reduced geometry's tiles.
-template <class T>
+template <class T, int F>
 __global__ __launch_bounds__(256) void k_box_down(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ frs,
                                                   const FrameInfo* __restrict__ fr, const T* __restrict__ in,
-                                                  T* __restrict__ out, int f, int mode) {
+                                                  T* __restrict__ out, int f_arg, int mode) {
+    // F > 0: the factor is F, and a block of full width is read row by row with one F-element
+    // load (the same sums in the same order as the element loads of F = 0)
+    const int f = F > 0 ? F : f_arg;
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo s = frs[tl.frame], b = fr[tl.frame];  // the reduced frame and its full frame
     const int xs = tl.x0 + (int)(threadIdx.x % OTW), ys = tl.y0 + (int)(threadIdx.x / OTW);
@@ -461,11 +464,30 @@ __global__ __launch_bounds__(256) void k_box_down(const Tile* __restrict__ tiles
     const T inv = T(1) / T((x1 - x0) * (y1 - y0));
     const int ncomp = mode == 0 ? 1 : 2;
     const int64_t npb = (int64_t)b.nx * b.ny, nps = (int64_t)s.nx * s.ny;
+    constexpr int FV = F > 0 ? F : 1;
+    typedef T VF __attribute__((ext_vector_type(FV), aligned(sizeof(T))));
     for (int comp = 0; comp < ncomp; ++comp) {
         const T* src = mode == 0 ? in + b.off : in + 2 * b.pair_off + comp * npb;
         T acc = T(0);
-        for (int y = y0; y < y1; ++y)
-            for (int x = x0; x < x1; ++x) acc += src[(int64_t)y * b.nx + x];
+        if (F > 0 && x1 - x0 == F && y1 - y0 == F) {
+            // a whole block: every row's load in flight before the sum
+            VF q[FV];
+#pragma unroll
+            for (int r = 0; r < FV; ++r) q[r] = *reinterpret_cast<const VF*>(src + (int64_t)(y0 + r) * b.nx + x0);
+#pragma unroll
+            for (int r = 0; r < FV; ++r)
+#pragma unroll
+                for (int e = 0; e < FV; ++e) acc += q[r][e];
+        } else if (F > 0 && x1 - x0 == F) {
+            for (int y = y0; y < y1; ++y) {
+                const VF q = *reinterpret_cast<const VF*>(src + (int64_t)y * b.nx + x0);
+#pragma unroll
+                for (int e = 0; e < FV; ++e) acc += q[e];
+            }
+        } else {
+            for (int y = y0; y < y1; ++y)
+                for (int x = x0; x < x1; ++x) acc += src[(int64_t)y * b.nx + x];
+        }
         T m = acc * inv;
         if (mode == 1) m = m / T(f);
         T* dst = mode == 0 ? out + s.off : out + 2 * s.pair_off + comp * nps;
@@ -474,27 +496,69 @@ __global__ __launch_bounds__(256) void k_box_down(const Tile* __restrict__ tiles
 }
 
 // v = f * bilinear sample of the reduced flow at ((x + 1/2)/f - 1/2, (y + 1/2)/f - 1/2),
-// positions clamped to the reduced grid; one thread per full-resolution pair pixel.
+// positions clamped to the reduced grid.  A lane takes four consecutive pixels of a row
+// (tiles of UTW x UTH pixels): for f >= 2 their samples fall within four consecutive columns
+// of the reduced flow, which it reads with one 4-element load per reduced row and component
+// (from column c0 = min(first column, reduced width - 4), reduced widths of at least 4) and
+// stores its four outputs of a component together.
+static constexpr int UTW = 256, UTH = 4;
+
 template <class T>
 __global__ __launch_bounds__(256) void k_flow_up(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                  const FrameInfo* __restrict__ frs, const T* __restrict__ vs,
                                                  T* __restrict__ v, int f) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo b = fr[tl.frame], s = frs[tl.frame];
-    const int x = tl.x0 + (int)(threadIdx.x % OTW), y = tl.y0 + (int)(threadIdx.x / OTW);
-    if (x >= b.nx || y >= b.ny) return;
-    const double X = fmin(fmax((x + 0.5) / f - 0.5, 0.0), (double)(s.nx - 1));
-    const double Y = fmin(fmax((y + 0.5) / f - 0.5, 0.0), (double)(s.ny - 1));
-    const int xa = min((int)floor(X), s.nx - 1), ya = min((int)floor(Y), s.ny - 1);
-    const int xb = min(xa + 1, s.nx - 1), yb = min(ya + 1, s.ny - 1);
-    const T fx = (T)(X - xa), fy = (T)(Y - ya);
+    const int xq = tl.x0 + 4 * (int)(threadIdx.x % (UTW / 4)), y = tl.y0 + (int)(threadIdx.x / (UTW / 4));
+    if (xq >= b.nx || y >= b.ny) return;
+    const int npx = min(4, b.nx - xq);
+    // (x + 1/2) / f as (x + 1/2) (1/f): exact for the power-of-two factors, within an ulp
+    // otherwise
+    const double invf = 1.0 / f;
+    const double Y = fmin(fmax(fma(y + 0.5, invf, -0.5), 0.0), (double)(s.ny - 1));
+    const int ya = min((int)floor(Y), s.ny - 1), yb = min(ya + 1, s.ny - 1);
+    const T fy = (T)(Y - ya);
+    int xa[4], xb[4];
+    T fx[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double X = fmin(fmax(fma(xq + i + 0.5, invf, -0.5), 0.0), (double)(s.nx - 1));
+        xa[i] = min((int)floor(X), s.nx - 1);
+        xb[i] = min(xa[i] + 1, s.nx - 1);
+        fx[i] = (T)(X - xa[i]);
+    }
     const int64_t npb = (int64_t)b.nx * b.ny, nps = (int64_t)s.nx * s.ny;
+    const bool vec = f >= 2 && s.nx >= 4;
+    const int c0 = min(xa[0], s.nx - 4);
+    typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
     for (int comp = 0; comp < 2; ++comp) {
         const T* q = vs + 2 * s.pair_off + comp * nps;
-        const T a00 = q[(int64_t)ya * s.nx + xa], a01 = q[(int64_t)ya * s.nx + xb];
-        const T a10 = q[(int64_t)yb * s.nx + xa], a11 = q[(int64_t)yb * s.nx + xb];
-        v[2 * b.pair_off + comp * npb + (int64_t)y * b.nx + x] =
-            T(f) * ((T(1) - fy) * ((T(1) - fx) * a00 + fx * a01) + fy * ((T(1) - fx) * a10 + fx * a11));
+        T o[4];
+        if (vec) {
+            const V4 ra = *reinterpret_cast<const V4*>(q + (int64_t)ya * s.nx + c0);
+            const V4 rb = *reinterpret_cast<const V4*>(q + (int64_t)yb * s.nx + c0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ia = xa[i] - c0, ib = xb[i] - c0;  // in [0, 3]
+                const T a00 = ra[ia], a01 = ra[ib], a10 = rb[ia], a11 = rb[ib];
+                o[i] = T(f) * ((T(1) - fy) * ((T(1) - fx[i]) * a00 + fx[i] * a01) +
+                               fy * ((T(1) - fx[i]) * a10 + fx[i] * a11));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const T a00 = q[(int64_t)ya * s.nx + xa[i]], a01 = q[(int64_t)ya * s.nx + xb[i]];
+                const T a10 = q[(int64_t)yb * s.nx + xa[i]], a11 = q[(int64_t)yb * s.nx + xb[i]];
+                o[i] = T(f) * ((T(1) - fy) * ((T(1) - fx[i]) * a00 + fx[i] * a01) +
+                               fy * ((T(1) - fx[i]) * a10 + fx[i] * a11));
+            }
+        }
+        T* dst = v + 2 * b.pair_off + comp * npb + (int64_t)y * b.nx + xq;
+        if (npx == 4) {
+            *reinterpret_cast<V4*>(dst) = V4{o[0], o[1], o[2], o[3]};
+        } else {
+            for (int i = 0; i < npx; ++i) dst[i] = o[i];
+        }
     }
 }
 
@@ -542,15 +606,16 @@ void launch_box_down(Ctx& c, Geom& g, Geom& gs, int dt, int mode, int f, const v
         using T = decltype(z);
         const double px = mode == 0 ? (double)g.n : 2.0 * g.pair_px, pxs = mode == 0 ? (double)gs.n : 2.0 * gs.pair_px;
         ScopedTime st(&c, "box_down", sizeof(T) * (px + pxs), px);
-        hipLaunchKernelGGL(k_box_down<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           gs.dframes(), g.dframes(), (const T*)in, (T*)out, f, mode);
+        auto k = f == 2 ? k_box_down<T, 2> : f == 4 ? k_box_down<T, 4> : f == 8 ? k_box_down<T, 8> : k_box_down<T, 0>;
+        hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), gs.dframes(),
+                           g.dframes(), (const T*)in, (T*)out, f, mode);
         MMOF_LAUNCH_CHECK();
     });
 }
 
 void launch_flow_up(Ctx& c, Geom& g, Geom& gs, int dt, int f, const void* vs, void* v) {
     if (g.n_pairs == 0) return;
-    const TileList& tl = g.tile_list(c.stream, OTW, OTH, true);
+    const TileList& tl = g.tile_list(c.stream, UTW, UTH, true);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_up", sizeof(T) * 2.0 * (g.pair_px + gs.pair_px), 2.0 * 8.0 * g.pair_px);

@@ -341,6 +341,27 @@ def test_flow_update_scaled(B, which, layout, scale):
     assert_close(host(vr), exp_r, TOL64 if dt == torch.float64 else TOL32)
 
 
+@pytest.mark.parametrize("which", ["f64", "f32"])
+@pytest.mark.parametrize("scale", [4, 8])
+def test_flow_update_scaled_wide_blocks(B, which, scale):
+    """Reduction factors 4 and 8 (block rows read as one vector of the block width) on frames
+    whose sides leave partial border blocks, and reduced frames narrower than four columns
+    (the upscaling's element-load path) next to wider ones, against the oracle."""
+    import torch
+    dt = torch.float64 if which == "f64" else torch.float32
+    sizes = [(3, 37, 75), (2, 40, 130), (2, 64, 64), (2, 28, 20)]
+    r = np.random.default_rng(29)
+    us = [np.cumsum(np.cumsum(r.standard_normal(s), axis=1), axis=2) * 0.05 for s in sizes]
+    vs0 = _flows(30, 1.0, sizes)
+    if dt == torch.float32:
+        us, vs0 = [list(map(roundtrip32, a)) for a in (us, vs0)]
+    stack = B.Stack(sizes)
+    v = dev(pack(vs0), dt)
+    B.flow_update_scaled(stack, dev(pack(us), dt), v, alpha=0.3, n_sweeps=25, delta_r=1, scale=scale)
+    exp = [optflow.flow_update_scaled(u, v0, 0.3, 25, 1, scale) for u, v0 in zip(us, vs0)]
+    assert_close(host(v), pack(exp), TOL64 if dt == torch.float64 else 1e-4)
+
+
 def test_flow_update_scaled_edges(B):
     """scale 1 is the plain update bit for bit; a scale that leaves a reduced side <= delta_r
     is rejected before any launch; frames that reduce to 2 x 2 still work."""
