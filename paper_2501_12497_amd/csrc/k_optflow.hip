@@ -497,67 +497,109 @@ __global__ __launch_bounds__(256) void k_box_down(const Tile* __restrict__ tiles
 
 // v = f * bilinear sample of the reduced flow at ((x + 1/2)/f - 1/2, (y + 1/2)/f - 1/2),
 // positions clamped to the reduced grid.  A lane takes four consecutive pixels of a row
-// (tiles of UTW x UTH pixels): for f >= 2 their samples fall within four consecutive columns
-// of the reduced flow, which it reads with one 4-element load per reduced row and component
-// (from column c0 = min(first column, reduced width - 4), reduced widths of at least 4) and
-// stores its four outputs of a component together.
-static constexpr int UTW = 256, UTH = 4;
+// on each of the UTH rows of a UTW x UTH tile (the workgroup's 256 lanes span its width; few,
+// long-lived workgroups): for f >= 2 their samples fall within four consecutive columns of the
+// reduced flow, which it reads with one 4-element load per reduced row and component (from
+// column c0 = min(first column, reduced width - 4), reduced widths of at least 4) and stores
+// its four outputs of a component together.  Its x positions and weights serve every row.
+// F = 2, 4, 8 (the factor known at compile time): on a lane whose four samples are unclamped
+// and whose window lies inside the reduced row the columns each pixel reads are the same for
+// every such lane (F = 4: c0, c0, c0+1, c0+1 and the next ones), so no per-pixel selection is
+// needed; other lanes take the general path, which gives the same values.
+static constexpr int UTW = 1024, UTH = 8;
 
-template <class T>
+template <int F>
+__device__ __forceinline__ void up_cols(int i, int& ia, int& ib) {
+    // columns (from the lane's first column) of pixel i's two samples on an interior lane
+    if (F == 2) {
+        ia = (i + 1) >> 1;  // 0, 1, 1, 2
+    } else if (F == 4) {
+        ia = i >> 1;        // 0, 0, 1, 1
+    } else {
+        ia = 0;             // F = 8: one cell for all four
+    }
+    ib = ia + 1;
+}
+
+template <class T, int F>
 __global__ __launch_bounds__(256) void k_flow_up(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                  const FrameInfo* __restrict__ frs, const T* __restrict__ vs,
-                                                 T* __restrict__ v, int f) {
+                                                 T* __restrict__ v, int f_arg) {
+    const int f = F > 0 ? F : f_arg;
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo b = fr[tl.frame], s = frs[tl.frame];
-    const int xq = tl.x0 + 4 * (int)(threadIdx.x % (UTW / 4)), y = tl.y0 + (int)(threadIdx.x / (UTW / 4));
-    if (xq >= b.nx || y >= b.ny) return;
+    const int xq = tl.x0 + 4 * (int)threadIdx.x;  // UTW = 4 x 256: one row of the tile per pass
+    if (xq >= b.nx) return;
     const int npx = min(4, b.nx - xq);
-    // (x + 1/2) / f as (x + 1/2) (1/f): exact for the power-of-two factors, within an ulp
-    // otherwise
+    const int64_t npb = (int64_t)b.nx * b.ny, nps = (int64_t)s.nx * s.ny;
+    typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+    // the lane's columns: positions, cells and weights in x are the same on every row
     const double invf = 1.0 / f;
-    const double Y = fmin(fmax(fma(y + 0.5, invf, -0.5), 0.0), (double)(s.ny - 1));
-    const int ya = min((int)floor(Y), s.ny - 1), yb = min(ya + 1, s.ny - 1);
-    const T fy = (T)(Y - ya);
     int xa[4], xb[4];
     T fx[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+        // (x + 1/2) / f as (x + 1/2) (1/f): exact for the power-of-two factors, within an ulp
+        // otherwise
         const double X = fmin(fmax(fma(xq + i + 0.5, invf, -0.5), 0.0), (double)(s.nx - 1));
         xa[i] = min((int)floor(X), s.nx - 1);
         xb[i] = min(xa[i] + 1, s.nx - 1);
         fx[i] = (T)(X - xa[i]);
     }
-    const int64_t npb = (int64_t)b.nx * b.ny, nps = (int64_t)s.nx * s.ny;
     const bool vec = f >= 2 && s.nx >= 4;
     const int c0 = min(xa[0], s.nx - 4);
-    typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
-    for (int comp = 0; comp < 2; ++comp) {
-        const T* q = vs + 2 * s.pair_off + comp * nps;
-        T o[4];
-        if (vec) {
-            const V4 ra = *reinterpret_cast<const V4*>(q + (int64_t)ya * s.nx + c0);
-            const V4 rb = *reinterpret_cast<const V4*>(q + (int64_t)yb * s.nx + c0);
+    // F > 0: on a lane whose samples are unclamped and whose window lies inside the reduced
+    // row, pixel i reads columns c0 + up_cols (the same values as the general path)
+    bool fixed = false;
+    if constexpr (F > 0) {
+        constexpr float iF = 1.0f / F;
+        const float X0 = fmaf((float)xq + 0.5f, iF, -0.5f);
+        fixed = npx == 4 && X0 >= 0.0f && X0 + 3.0f * iF <= (float)(s.nx - 1) && xa[0] + 3 <= s.nx - 1;
+    }
+    for (int r = 0; r < UTH; ++r) {
+        const int y = tl.y0 + r;
+        if (y >= b.ny) break;
+        const double Y = fmin(fmax(fma(y + 0.5, invf, -0.5), 0.0), (double)(s.ny - 1));
+        const int ya = min((int)floor(Y), s.ny - 1), yb = min(ya + 1, s.ny - 1);
+        const T fy = (T)(Y - ya);
+        for (int comp = 0; comp < 2; ++comp) {
+            const T* q = vs + 2 * s.pair_off + comp * nps;
+            T o[4];
+            if (fixed) {
+                const V4 ra = *reinterpret_cast<const V4*>(q + (int64_t)ya * s.nx + xa[0]);
+                const V4 rb = *reinterpret_cast<const V4*>(q + (int64_t)yb * s.nx + xa[0]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ia = xa[i] - c0, ib = xb[i] - c0;  // in [0, 3]
-                const T a00 = ra[ia], a01 = ra[ib], a10 = rb[ia], a11 = rb[ib];
-                o[i] = T(f) * ((T(1) - fy) * ((T(1) - fx[i]) * a00 + fx[i] * a01) +
-                               fy * ((T(1) - fx[i]) * a10 + fx[i] * a11));
-            }
-        } else {
+                for (int i = 0; i < 4; ++i) {
+                    int ia = 0, ib = 1;
+                    if constexpr (F > 0) up_cols<F>(i, ia, ib);
+                    o[i] = T(f) * ((T(1) - fy) * ((T(1) - fx[i]) * ra[ia] + fx[i] * ra[ib]) +
+                                   fy * ((T(1) - fx[i]) * rb[ia] + fx[i] * rb[ib]));
+                }
+            } else if (vec) {
+                const V4 ra = *reinterpret_cast<const V4*>(q + (int64_t)ya * s.nx + c0);
+                const V4 rb = *reinterpret_cast<const V4*>(q + (int64_t)yb * s.nx + c0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const T a00 = q[(int64_t)ya * s.nx + xa[i]], a01 = q[(int64_t)ya * s.nx + xb[i]];
-                const T a10 = q[(int64_t)yb * s.nx + xa[i]], a11 = q[(int64_t)yb * s.nx + xb[i]];
-                o[i] = T(f) * ((T(1) - fy) * ((T(1) - fx[i]) * a00 + fx[i] * a01) +
-                               fy * ((T(1) - fx[i]) * a10 + fx[i] * a11));
+                for (int i = 0; i < 4; ++i) {
+                    const int ia = xa[i] - c0, ib = xb[i] - c0;  // in [0, 3]
+                    const T a00 = ra[ia], a01 = ra[ib], a10 = rb[ia], a11 = rb[ib];
+                    o[i] = T(f) * ((T(1) - fy) * ((T(1) - fx[i]) * a00 + fx[i] * a01) +
+                                   fy * ((T(1) - fx[i]) * a10 + fx[i] * a11));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const T a00 = q[(int64_t)ya * s.nx + xa[i]], a01 = q[(int64_t)ya * s.nx + xb[i]];
+                    const T a10 = q[(int64_t)yb * s.nx + xa[i]], a11 = q[(int64_t)yb * s.nx + xb[i]];
+                    o[i] = T(f) * ((T(1) - fy) * ((T(1) - fx[i]) * a00 + fx[i] * a01) +
+                                   fy * ((T(1) - fx[i]) * a10 + fx[i] * a11));
+                }
             }
-        }
-        T* dst = v + 2 * b.pair_off + comp * npb + (int64_t)y * b.nx + xq;
-        if (npx == 4) {
-            *reinterpret_cast<V4*>(dst) = V4{o[0], o[1], o[2], o[3]};
-        } else {
-            for (int i = 0; i < npx; ++i) dst[i] = o[i];
+            T* dst = v + 2 * b.pair_off + comp * npb + (int64_t)y * b.nx + xq;
+            if (npx == 4) {
+                *reinterpret_cast<V4*>(dst) = V4{o[0], o[1], o[2], o[3]};
+            } else {
+                for (int i = 0; i < npx; ++i) dst[i] = o[i];
+            }
         }
     }
 }
@@ -619,8 +661,9 @@ void launch_flow_up(Ctx& c, Geom& g, Geom& gs, int dt, int f, const void* vs, vo
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         ScopedTime st(&c, "flow_up", sizeof(T) * 2.0 * (g.pair_px + gs.pair_px), 2.0 * 8.0 * g.pair_px);
-        hipLaunchKernelGGL(k_flow_up<T>, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                           g.dframes(), gs.dframes(), (const T*)vs, (T*)v, f);
+        auto k = f == 2 ? k_flow_up<T, 2> : f == 4 ? k_flow_up<T, 4> : f == 8 ? k_flow_up<T, 8> : k_flow_up<T, 0>;
+        hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
+                           gs.dframes(), (const T*)vs, (T*)v, f);
         MMOF_LAUNCH_CHECK();
     });
 }
