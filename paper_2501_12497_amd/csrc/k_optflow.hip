@@ -189,13 +189,16 @@ static constexpr int HRW = HTW + 2 * HS_MAX, HRH = HTH + 2 * HS_MAX;  // 80 x 32
 static constexpr int HS_THREADS = 640;
 static constexpr int HPT = HRW * HRH / HS_THREADS;                   // pixels per thread (4)
 static_assert(HRW * HRH == HS_THREADS * HPT, "halo region must split evenly over the workgroup");
+// LDS per buffer and component: the region, then a zero that neighbours outside the image read
+// (so every pixel reads its four neighbours unconditionally), padded to 64 elements
+static constexpr int HZERO = HRW * HRH, HCS = (HRW * HRH + 64) / 64 * 64;
 
 template <class T>
 __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict__ tiles,
                                                          const FrameInfo* __restrict__ fr, const T* __restrict__ I,
                                                          const T* __restrict__ vin, T* __restrict__ vout, T gamma,
                                                          int nsw) {
-    __shared__ T sv[2][2][HRH * HRW];  // [buffer][component][pixel]
+    __shared__ T sv[2][2][HCS];  // [buffer][component][pixel]
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
     const int nx = f.nx, ny = f.ny;
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
     const T* sx = vin + 2 * f.pair_off;
     const T* Ip = I + 3 * f.pair_off;
     T gx[HPT], gy[HPT], gt[HPT], rden[HPT], rd[HPT];
-    int nbr[HPT][4];  // LDS index of the y-1, y+1, x-1, x+1 neighbours, -1 outside the image
+    int nbr[HPT][4];  // LDS index of the y-1, y+1, x-1, x+1 neighbours, HZERO outside the image
     bool live[HPT];
 #pragma unroll
     for (int r = 0; r < HPT; ++r) {
@@ -217,10 +220,10 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
         gx[r] = gy[r] = gt[r] = T(0);
         rden[r] = rd[r] = T(0);
         // neighbours outside the loaded region read the pixel itself (stale halo only)
-        nbr[r][0] = (in && y > 0) ? (ry > 0 ? idx - HRW : idx) : -1;
-        nbr[r][1] = (in && y < ny - 1) ? (ry < HRH - 1 ? idx + HRW : idx) : -1;
-        nbr[r][2] = (in && x > 0) ? (rx > 0 ? idx - 1 : idx) : -1;
-        nbr[r][3] = (in && x < nx - 1) ? (rx < HRW - 1 ? idx + 1 : idx) : -1;
+        nbr[r][0] = (in && y > 0) ? (ry > 0 ? idx - HRW : idx) : HZERO;
+        nbr[r][1] = (in && y < ny - 1) ? (ry < HRH - 1 ? idx + HRW : idx) : HZERO;
+        nbr[r][2] = (in && x > 0) ? (rx > 0 ? idx - 1 : idx) : HZERO;
+        nbr[r][3] = (in && x < nx - 1) ? (rx < HRW - 1 ? idx + 1 : idx) : HZERO;
         if (in) {
             const int64_t p = (int64_t)y * nx + x;
             a = sx[p];
@@ -228,30 +231,38 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
             gx[r] = Ip[p];
             gy[r] = Ip[np + p];
             gt[r] = Ip[2 * np + p];
-            const int d = (nbr[r][0] >= 0) + (nbr[r][1] >= 0) + (nbr[r][2] >= 0) + (nbr[r][3] >= 0);
+            const int d = (nbr[r][0] != HZERO) + (nbr[r][1] != HZERO) + (nbr[r][2] != HZERO) + (nbr[r][3] != HZERO);
             rd[r] = T(1) / T(d);
             rden[r] = T(1) / (gamma * T(d) + gx[r] * gx[r] + gy[r] * gy[r]);
         }
         sv[0][0][idx] = a;
         sv[0][1][idx] = b;
     }
+    if (threadIdx.x < 4) sv[threadIdx.x >> 1][threadIdx.x & 1][HZERO] = T(0);
     __syncthreads();
     int cur = 0;
     for (int q = 0; q < nsw; ++q) {
         const T* cx = sv[cur][0];
         const T* cy = sv[cur][1];
+        // (a pixel outside the image reads four zeros and has zero weights: it stays 0, so it
+        // needs no branch); every neighbour of the thread's pixels is read before the first
+        // update is written, so all the reads are in flight together
+        T nbx[HPT][4], nby[HPT][4];
+#pragma unroll
+        for (int r = 0; r < HPT; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                nbx[r][e] = cx[nbr[r][e]];
+                nby[r][e] = cy[nbr[r][e]];
+            }
 #pragma unroll
         for (int r = 0; r < HPT; ++r) {
-            if (!live[r]) continue;
             const int idx = threadIdx.x + HS_THREADS * r;
             T ax = T(0), ay = T(0);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {  // neighbour order: y-1, y+1, x-1, x+1
-                const int j = nbr[r][e];
-                if (j >= 0) {
-                    ax += cx[j];
-                    ay += cy[j];
-                }
+            for (int e = 0; e < 4; ++e) {  // neighbour order: y-1, y+1, x-1, x+1 (a missing one adds 0)
+                ax += nbx[r][e];
+                ay += nby[r][e];
             }
             ax *= rd[r];
             ay *= rd[r];
