@@ -199,6 +199,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
                                                          const T* __restrict__ vin, T* __restrict__ vout, T gamma,
                                                          int nsw) {
     __shared__ T sv[2][2][HCS];  // [buffer][component][pixel]
+    static_assert(HRH == HPT * (HS_THREADS / HRW) && HS_THREADS % HRW == 0, "strips must tile the halo region");
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
     const int nx = f.nx, ny = f.ny;
@@ -206,37 +207,47 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
     const int ox = tl.x0 - HS_MAX, oy = tl.y0 - HS_MAX;  // image coordinates of the region origin
     const T* sx = vin + 2 * f.pair_off;
     const T* Ip = I + 3 * f.pair_off;
-    T gx[HPT], gy[HPT], gt[HPT], rden[HPT], rd[HPT];
-    int nbr[HPT][4];  // LDS index of the y-1, y+1, x-1, x+1 neighbours, HZERO outside the image
+    // a thread owns a strip of HPT consecutive rows of one column of the region: the vertical
+    // neighbours inside the strip come from its registers (the previous sweep's values), the
+    // others from LDS
+    const int rx = (int)threadIdx.x % HRW, ry0 = HPT * ((int)threadIdx.x / HRW);
+    const int x = ox + rx;
+    T av[HPT], bv[HPT], gx[HPT], gy[HPT], gt[HPT], rden[HPT], rd[HPT];
+    bool up_in[HPT], dn_in[HPT];  // pixel r's y-1 (y+1) neighbour exists (strip pixels r-1, r+1)
+    int lx[HPT][2];                 // LDS index of the x-1, x+1 neighbours, HZERO outside the image
+    int l_up = HZERO, l_dn = HZERO;  // LDS index of the y-1 neighbour of pixel 0, y+1 of pixel HPT-1
     bool live[HPT];
 #pragma unroll
     for (int r = 0; r < HPT; ++r) {
-        const int idx = threadIdx.x + HS_THREADS * r;
-        const int ry = idx / HRW, rx = idx % HRW;
-        const int x = ox + rx, y = oy + ry;
+        const int ry = ry0 + r, idx = ry * HRW + rx;
+        const int y = oy + ry;
         const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
         live[r] = in;
-        T a = T(0), b = T(0);
+        av[r] = bv[r] = T(0);
         gx[r] = gy[r] = gt[r] = T(0);
         rden[r] = rd[r] = T(0);
         // neighbours outside the loaded region read the pixel itself (stale halo only)
-        nbr[r][0] = (in && y > 0) ? (ry > 0 ? idx - HRW : idx) : HZERO;
-        nbr[r][1] = (in && y < ny - 1) ? (ry < HRH - 1 ? idx + HRW : idx) : HZERO;
-        nbr[r][2] = (in && x > 0) ? (rx > 0 ? idx - 1 : idx) : HZERO;
-        nbr[r][3] = (in && x < nx - 1) ? (rx < HRW - 1 ? idx + 1 : idx) : HZERO;
+        const bool has_u = in && y > 0, has_d = in && y < ny - 1;
+        const bool has_l = in && x > 0, has_r = in && x < nx - 1;
+        up_in[r] = has_u;
+        dn_in[r] = has_d;
+        if (r == 0) l_up = has_u ? (ry > 0 ? idx - HRW : idx) : HZERO;
+        if (r == HPT - 1) l_dn = has_d ? (ry < HRH - 1 ? idx + HRW : idx) : HZERO;
+        lx[r][0] = has_l ? (rx > 0 ? idx - 1 : idx) : HZERO;
+        lx[r][1] = has_r ? (rx < HRW - 1 ? idx + 1 : idx) : HZERO;
         if (in) {
             const int64_t p = (int64_t)y * nx + x;
-            a = sx[p];
-            b = sx[np + p];
+            av[r] = sx[p];
+            bv[r] = sx[np + p];
             gx[r] = Ip[p];
             gy[r] = Ip[np + p];
             gt[r] = Ip[2 * np + p];
-            const int d = (nbr[r][0] != HZERO) + (nbr[r][1] != HZERO) + (nbr[r][2] != HZERO) + (nbr[r][3] != HZERO);
+            const int d = (int)has_u + (int)has_d + (int)has_l + (int)has_r;
             rd[r] = T(1) / T(d);
             rden[r] = T(1) / (gamma * T(d) + gx[r] * gx[r] + gy[r] * gy[r]);
         }
-        sv[0][0][idx] = a;
-        sv[0][1][idx] = b;
+        sv[0][0][idx] = av[r];
+        sv[0][1][idx] = bv[r];
     }
     if (threadIdx.x < 4) sv[threadIdx.x >> 1][threadIdx.x & 1][HZERO] = T(0);
     __syncthreads();
@@ -244,31 +255,43 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
     for (int q = 0; q < nsw; ++q) {
         const T* cx = sv[cur][0];
         const T* cy = sv[cur][1];
-        // (a pixel outside the image reads four zeros and has zero weights: it stays 0, so it
-        // needs no branch); every neighbour of the thread's pixels is read before the first
-        // update is written, so all the reads are in flight together
-        T nbx[HPT][4], nby[HPT][4];
+        // the LDS neighbours first (all in flight together); a pixel outside the image reads
+        // zeros and has zero weights, so it stays 0 without a branch
+        T la[HPT][2], lb[HPT][2];
 #pragma unroll
         for (int r = 0; r < HPT; ++r)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                nbx[r][e] = cx[nbr[r][e]];
-                nby[r][e] = cy[nbr[r][e]];
+            for (int e = 0; e < 2; ++e) {
+                la[r][e] = cx[lx[r][e]];
+                lb[r][e] = cy[lx[r][e]];
             }
+        const T ua = cx[l_up], ub = cy[l_up], da = cx[l_dn], db = cy[l_dn];
+        T na[HPT], nb[HPT];
 #pragma unroll
         for (int r = 0; r < HPT; ++r) {
-            const int idx = threadIdx.x + HS_THREADS * r;
+            // neighbour order: y-1, y+1, x-1, x+1 (a missing one adds 0)
             T ax = T(0), ay = T(0);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {  // neighbour order: y-1, y+1, x-1, x+1 (a missing one adds 0)
-                ax += nbx[r][e];
-                ay += nby[r][e];
-            }
+            ax += r == 0 ? ua : (up_in[r] ? av[r - 1] : T(0));
+            ay += r == 0 ? ub : (up_in[r] ? bv[r - 1] : T(0));
+            ax += r == HPT - 1 ? da : (dn_in[r] ? av[r + 1] : T(0));
+            ay += r == HPT - 1 ? db : (dn_in[r] ? bv[r + 1] : T(0));
+            ax += la[r][0];
+            ay += lb[r][0];
+            ax += la[r][1];
+            ay += lb[r][1];
             ax *= rd[r];
             ay *= rd[r];
             const T k = (gx[r] * ax + gy[r] * ay + gt[r]) * rden[r];
-            sv[cur ^ 1][0][idx] = ax - gx[r] * k;
-            sv[cur ^ 1][1][idx] = ay - gy[r] * k;
+            na[r] = ax - gx[r] * k;
+            nb[r] = ay - gy[r] * k;
+        }
+#pragma unroll
+        for (int r = 0; r < HPT; ++r) {
+            const int idx = (ry0 + r) * HRW + rx;
+            av[r] = na[r];
+            bv[r] = nb[r];
+            sv[cur ^ 1][0][idx] = na[r];
+            sv[cur ^ 1][1][idx] = nb[r];
         }
         cur ^= 1;
         __syncthreads();
@@ -276,12 +299,11 @@ __global__ __launch_bounds__(HS_THREADS) void k_hs_multi(const Tile* __restrict_
     T* o = vout + 2 * f.pair_off;
 #pragma unroll
     for (int r = 0; r < HPT; ++r) {
-        const int idx = threadIdx.x + HS_THREADS * r;
-        const int ry = idx / HRW, rx = idx % HRW;
+        const int ry = ry0 + r;
         if (rx < HS_MAX || rx >= HS_MAX + HTW || ry < HS_MAX || ry >= HS_MAX + HTH || !live[r]) continue;
-        const int64_t p = (int64_t)(oy + ry) * nx + (ox + rx);
-        o[p] = sv[cur][0][idx];
-        o[np + p] = sv[cur][1][idx];
+        const int64_t p = (int64_t)(oy + ry) * nx + x;
+        o[p] = av[r];
+        o[np + p] = bv[r];
     }
 }
 
