@@ -95,7 +95,7 @@ def test_autograd_matches_oracle_adjoints(setup, which):
     f_or = (w1 * forward.radon_fwd(u_np, s.angles, s.n_bins)).sum() + \
         sum((a * b).sum() for a, b in zip((w2x, w2y), regops.grad_fwd(u_np))) + \
         (w3 * regops.flow_fwd(u_np, v_np, 1)).sum()
-    assert abs(float(f) - f_or) <= (1e-4 if dt == torch.float32 else 1e-11) * abs(f_or)
+    assert abs(float(f.detach()) - f_or) <= (1e-4 if dt == torch.float32 else 1e-11) * abs(f_or)
 
 
 def test_autograd_central_differences_fp64(setup):
