@@ -13,7 +13,8 @@
 namespace mmof {
 
 static constexpr int KB = 256;          // threads per block for the streaming kernels
-static constexpr int MAX_PART = 1024;   // max partial blocks of a reduction
+static constexpr int MAX_PART = 8192;   // max row chunks of a block inner product
+static constexpr int MAX_GEMV_PART = 32768;   // max workgroups of a column combination
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -51,6 +52,8 @@ __device__ __forceinline__ double dot_row(const TX* __restrict__ X, int64_t ld, 
 
 // dot_row for the rows i and i + 1 at once: one 2-element load per column (element-aligned,
 // which global loads accept, so any ld qualifies); each row's sum in column order as in dot_row.
+// The columns are streamed once, so their loads are marked nontemporal (measured at 67M rows
+// x 11..39 FP64 columns: 5.6-5.7 TB/s against 5.0-5.3 TB/s with ordinary loads).
 template <class TX>
 __device__ __forceinline__ void dot_row2(const TX* __restrict__ X, int64_t ld, int64_t i, int K,
                                          const double* __restrict__ h, double& a0, double& a1) {
@@ -61,7 +64,8 @@ __device__ __forceinline__ void dot_row2(const TX* __restrict__ X, int64_t ld, i
         V2 q[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t)
-            q[t] = j0 + t < K ? *reinterpret_cast<const V2*>(X + (int64_t)(j0 + t) * ld + i) : V2{TX(0), TX(0)};
+            q[t] = j0 + t < K ? __builtin_nontemporal_load(reinterpret_cast<const V2*>(X + (int64_t)(j0 + t) * ld + i))
+                              : V2{TX(0), TX(0)};
 #pragma unroll
         for (int t = 0; t < 8; ++t)
             if (j0 + t < K) {
@@ -100,24 +104,38 @@ __global__ void k_convert(int64_t n, const TI* __restrict__ in, TO* __restrict__
         out[i] = (TO)in[i];
 }
 
-// Inner products of K columns (and of one extra FP64 column xe, when given) with y.
-// Grid: x = row chunks, y = groups of 8 columns; part[b][j] receives chunk b's sum for
-// column j.  (A single-launch completion by the last workgroup would need a device-scope
-// release per workgroup, which writes back the XCD's L2; a second small launch is cheaper.)
+// Row chunk bx and column group gy (8 columns) of a block inner-product workgroup.  The grid is
+// one-dimensional, 8 * ceil(nb / 8) * ng workgroups (nb row chunks, ng column groups).  The
+// dispatcher deals workgroups to the eight XCDs in turn (workgroup L runs on XCD L % 8), and
+// the ng groups of one row chunk take consecutive slots of one XCD, so they run close together
+// and read y through that XCD's L2 once from HBM.  False for the padding of the last round.
+__device__ __forceinline__ bool mdot_tile(int nb, int ng, int& bx, int& gy) {
+    const int L = (int)blockIdx.x, x = L & 7, s = L >> 3;
+    bx = (s / ng) * 8 + x;
+    gy = s % ng;
+    return bx < nb;
+}
+
+// Inner products of K columns (and of one extra FP64 column xe, when given) with y, over nb
+// row chunks (grid: mdot_tile); part[j * nb + b] receives chunk b's sum for column j.  (A
+// single-launch completion by the last workgroup would need a device-scope release per
+// workgroup, which writes back the XCD's L2; a second small launch is cheaper.)
 // skip (may be null): when *skip is non-zero the launch does nothing (this and the other
 // kernels of a conditional pass read the decision on the device).
 template <class TX, class TY>
-__global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
+__global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, int nbc, const TX* __restrict__ X, int64_t ld,
                                              const TY* __restrict__ y, const double* __restrict__ xe,
                                              double* __restrict__ part, const int* __restrict__ skip) {
     if (skip && *skip) return;
     __shared__ double s8[4][8];
     const int Kt = K + (xe ? 1 : 0);
-    const int64_t nb = gridDim.x;
+    int bx, gy;
+    if (!mdot_tile(nbc, (Kt + 7) / 8, bx, gy)) return;
+    const int64_t nb = nbc;
     const int64_t chunk = (n + nb - 1) / nb;
-    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    const int64_t lo = bx * chunk, hi = min(n, lo + chunk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int j0 = blockIdx.y * 8;
+    const int j0 = gy * 8;
     const int nj = min(8, Kt - j0);
     double acc[8];
 #pragma unroll
@@ -138,14 +156,18 @@ __global__ __launch_bounds__(KB) void k_mdot(int64_t n, int K, const TX* __restr
     }
     __syncthreads();
     if (threadIdx.x < nj)
-        part[(int64_t)blockIdx.x * Kt + j0 + threadIdx.x] =
+        part[(int64_t)(j0 + threadIdx.x) * nb + bx] =
             (s8[0][threadIdx.x] + s8[1][threadIdx.x]) + (s8[2][threadIdx.x] + s8[3][threadIdx.x]);
 }
 
 // k_mdot with two rows per lane (chunks of an even number of rows; 2-element loads of the
-// columns, of y and of xe); a chunk with an odd row count ends with one single row.
+// columns, of y and of xe); a chunk with an odd row count ends with one single row.  The K
+// columns are streamed once and their loads are marked nontemporal, so that they do not
+// evict y, which the other column groups of the chunk read from L2 (measured at 67M rows x
+// 11..39 FP64 columns: 6.5-7.1 TB/s, against 5.3-5.7 TB/s with a two-dimensional grid and
+// ordinary loads).
 template <class TX, class TY>
-__global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
+__global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, int nbc, const TX* __restrict__ X, int64_t ld,
                                               const TY* __restrict__ y, const double* __restrict__ xe,
                                               double* __restrict__ part, const int* __restrict__ skip) {
     if (skip && *skip) return;
@@ -155,11 +177,13 @@ __global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __rest
     typedef double VD __attribute__((ext_vector_type(2), aligned(sizeof(double))));
     __shared__ double s8[4][8];
     const int Kt = K + (xe ? 1 : 0);
-    const int64_t nb = gridDim.x;
+    int bx, gy;
+    if (!mdot_tile(nbc, (Kt + 7) / 8, bx, gy)) return;
+    const int64_t nb = nbc;
     const int64_t chunk = 2 * ((n + 2 * nb - 1) / (2 * nb));
-    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    const int64_t lo = bx * chunk, hi = min(n, lo + chunk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int j0 = blockIdx.y * 8;
+    const int j0 = gy * 8;
     const int nj = min(8, Kt - j0);
     double acc[8];
 #pragma unroll
@@ -174,7 +198,7 @@ __global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __rest
                 if (q < nj) {
                     double x0, x1;
                     if (j < K) {
-                        const VX xv = *reinterpret_cast<const VX*>(X + (int64_t)j * ld + i);
+                        const VX xv = __builtin_nontemporal_load(reinterpret_cast<const VX*>(X + (int64_t)j * ld + i));
                         x0 = (double)xv.x;
                         x1 = (double)xv.y;
                     } else {
@@ -203,41 +227,40 @@ __global__ __launch_bounds__(KB) void k_mdot2(int64_t n, int K, const TX* __rest
     }
     __syncthreads();
     if (threadIdx.x < nj)
-        part[(int64_t)blockIdx.x * Kt + j0 + threadIdx.x] =
+        part[(int64_t)(j0 + threadIdx.x) * nb + bx] =
             (s8[0][threadIdx.x] + s8[1][threadIdx.x]) + (s8[2][threadIdx.x] + s8[3][threadIdx.x]);
 }
 
-// Sums of the chunk partials in a fixed order (one wave per column, 16 waves; lane l sums
-// chunks l, l+64, ...; then a fixed butterfly):
+// Sums of the chunk partials part[j * nb + b] in a fixed order, one workgroup of 256 threads per
+// column j (grid Kt): thread t sums chunks t, t + 256, ... in eight interleaved running sums
+// (the eight loads of a step in flight together) combined in a fixed order, then the
+// workgroup's fixed-order sum:
 //   G == null: out[j] = alpha * s_j (j < Kt)
 //   G != null: G[row][j] = G[j][row] = s_j for j < Kt - 1 and dj[0] = s_{Kt-1}.
-__global__ __launch_bounds__(1024) void k_mdot_final(int nb, int Kt, const double* __restrict__ part, double alpha,
-                                                     double* __restrict__ out, double* __restrict__ G, int ldg,
-                                                     int row, double* __restrict__ dj, const int* __restrict__ skip) {
+__global__ __launch_bounds__(KB) void k_mdot_final(int nb, int Kt, const double* __restrict__ part, double alpha,
+                                                   double* __restrict__ out, double* __restrict__ G, int ldg,
+                                                   int row, double* __restrict__ dj, const int* __restrict__ skip) {
     if (skip && *skip) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int j = w; j < Kt; j += nw) {
-        // lane l sums chunks l, l+64, l+128, ... in four interleaved running sums (four
-        // loads in flight), combined in a fixed order
-        double a4[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b0 = lane; b0 < nb; b0 += 256) {
+    __shared__ double s4[4];
+    const int j = blockIdx.x;
+    const double* __restrict__ pj = part + (int64_t)j * nb;
+    double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 8 * KB) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int b = b0 + 64 * u;
-                if (b < nb) a4[u] += part[(int64_t)b * Kt + j];
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + KB * u;
+            if (b < nb) a8[u] += pj[b];
         }
-        double a = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-        a = wave_sum(a);
-        if (lane == 0) {
-            if (!G)
-                out[j] = alpha * a;
-            else if (j < Kt - 1) {
-                G[(int64_t)row * ldg + j] = a;
-                G[(int64_t)j * ldg + row] = a;
-            } else {
-                dj[0] = a;
-            }
+    }
+    const double a = block_sum(((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7])), s4);
+    if (threadIdx.x == 0) {
+        if (!G)
+            out[j] = alpha * a;
+        else if (j < Kt - 1) {
+            G[(int64_t)row * ldg + j] = a;
+            G[(int64_t)j * ldg + row] = a;
+        } else {
+            dj[0] = a;
         }
     }
 }
@@ -288,8 +311,8 @@ __global__ __launch_bounds__(KB) void k_gemv_fused(int64_t n, int K, const TX* _
 
 // k_gemv_fused with two rows per lane (dot_row2); n odd leaves one single row.  Each
 // workgroup walks one contiguous chunk of rows (a multiple of 2 KB rows), so that each column
-// is read as long sequential runs (measured 5.0 TB/s at 67M rows x 32..39 FP64 columns against
-// 4.5-4.7 TB/s for a grid-strided walk).
+// is read as sequential runs (a grid-strided walk measured 10% slower); many short chunks
+// (2048 rows) beat few long ones (5.7 against 5.5 TB/s with 8192-row chunks at 67M rows).
 template <class TX, class TO>
 __global__ __launch_bounds__(KB) void k_gemv_fused2(int64_t n, int K, const TX* __restrict__ X, int64_t ld,
                                                     const double* __restrict__ h, double alpha, const double* y,
@@ -373,23 +396,32 @@ __global__ __launch_bounds__(KB) void k_gemv_mdot(int64_t n, int K, const double
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
         const double a = wave_sum(acc[c]);
-        if (lane == 0 && jw + c < K) part[(int64_t)blockIdx.x * K + jw + c] = a;
+        if (lane == 0 && jw + c < K) part[(int64_t)(jw + c) * gridDim.x + blockIdx.x] = a;
     }
 }
 
-// out[0] = sum of nb partials in a fixed order (one wavefront)
-__global__ __launch_bounds__(64) void k_sum_final(int nb, const double* __restrict__ part, double* __restrict__ out,
-                                                 const int* __restrict__ skip) {
+// out[0] = sum of nb partials in a fixed order: thread t of 1024 sums t, t + 1024, ... in eight
+// interleaved running sums (the eight loads of a step in flight together) combined in a fixed
+// order, then the waves' sums in wave order.
+__global__ __launch_bounds__(1024) void k_sum_final(int nb, const double* __restrict__ part, double* __restrict__ out,
+                                                   const int* __restrict__ skip) {
     if (skip && *skip) return;
-    double a4[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b0 = threadIdx.x; b0 < nb; b0 += 256) {
+    __shared__ double s16[16];
+    double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 8 * 1024) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (b0 + 64 * u < nb) a4[u] += part[b0 + 64 * u];
+        for (int u = 0; u < 8; ++u)
+            if (b0 + 1024 * u < nb) a8[u] += part[b0 + 1024 * u];
     }
-    double a = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    double a = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     a = wave_sum(a);
-    if (threadIdx.x == 0) out[0] = a;
+    if ((threadIdx.x & 63) == 0) s16[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += s16[w];
+        out[0] = t;
+    }
 }
 
 // s = sqrt(s2[0]); out_d = x / s, out_t = (TO)(x / s) (zero when s = 0); s1[0] = s.
@@ -1059,13 +1091,6 @@ template void weight_mul_nu<float>(Ctx&, int64_t, const float*, double, const fl
 template void weight_mul_nu<double>(Ctx&, int64_t, const double*, double, const double*, double*);
 
 
-// row chunks of 1024 rows (four per thread), but at least 256 chunks (of no fewer than 256
-// rows) so that short vectors still spread over the chip; at most MAX_PART partials
-int mdot_blocks(int64_t n) {
-    const int64_t nb = std::max<int64_t>(cdiv(n, 1024), std::min<int64_t>(cdiv(n, 256), 256));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, nb));
-}
-
 // Two rows per lane (k_mdot2) when every column, y and xe are element-aligned (2-element
 // loads need no more).
 template <class TX, class TY>
@@ -1075,6 +1100,36 @@ static bool mdot_pairs(const TX* X, int64_t ld, const TY* y, const double* xe) {
            (!xe || reinterpret_cast<uintptr_t>(xe) % sizeof(double) == 0);
 }
 
+// row chunks of 8192 rows (32 per thread), but at least 256 chunks (of no fewer than 256
+// rows) so that short vectors still spread over the chip; at most MAX_PART chunks
+int mdot_blocks(int64_t n) {
+    const int64_t nb = std::max<int64_t>(cdiv(n, 8192), std::min<int64_t>(cdiv(n, 256), 256));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(MAX_PART, nb));
+}
+
+// The block inner products of K columns of X (and of the FP64 column xe, when given) with y
+// over nb row chunks, into part (column-major, [Kt][nb]); then their fixed-order sums
+// (k_mdot_final: out, or a Gram row and column with dj).
+template <class TX, class TY>
+static void launch_mdot(Ctx& c, int nb, int64_t n, int K, const TX* X, int64_t ld, const TY* y, const double* xe,
+                        double* part, const int* skip) {
+    const int Kt = K + (xe ? 1 : 0);
+    const dim3 grid((unsigned)(8 * cdiv(nb, 8) * cdiv(Kt, 8)));
+    if (mdot_pairs(X, ld, y, xe))
+        hipLaunchKernelGGL((k_mdot2<TX, TY>), grid, dim3(KB), 0, c.stream, n, K, nb, X, ld, y, xe, part, skip);
+    else
+        hipLaunchKernelGGL((k_mdot<TX, TY>), grid, dim3(KB), 0, c.stream, n, K, nb, X, ld, y, xe, part, skip);
+    MMOF_LAUNCH_CHECK();
+}
+
+static void mdot_final(Ctx& c, int nb, int Kt, const double* part, double alpha, double* out, double* G, int ldg,
+                       int row, double* dj, const int* skip) {
+    hipLaunchKernelGGL(k_mdot_final, dim3((unsigned)Kt), dim3(KB), 0, c.stream, nb, Kt, part, alpha, out, G, ldg,
+                       row, dj, skip);
+    MMOF_LAUNCH_CHECK();
+}
+
+
 template <class TX, class TY>
 void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double alpha, double* out) {
     if (K <= 0) return;
@@ -1083,17 +1138,9 @@ void mdot(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, const TY* y, double
     double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX + 1)));
     {
         ScopedTime st(&c, "mdot", (double)n * ((double)sizeof(TX) * K + sizeof(TY)), 2.0 * n * K);
-        if (mdot_pairs(X, ld, y, nullptr))
-            hipLaunchKernelGGL((k_mdot2<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld,
-                               y, (const double*)nullptr, part, (const int*)nullptr);
-        else
-            hipLaunchKernelGGL((k_mdot<TX, TY>), dim3(nb, (unsigned)cdiv(K, 8)), dim3(KB), 0, c.stream, n, K, X, ld,
-                               y, (const double*)nullptr, part, (const int*)nullptr);
-        MMOF_LAUNCH_CHECK();
+        launch_mdot<TX, TY>(c, nb, n, K, X, ld, y, nullptr, part, nullptr);
     }
-    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, K, part, alpha, out, (double*)nullptr, 0, 0,
-                       (double*)nullptr, (const int*)nullptr);
-    MMOF_LAUNCH_CHECK();
+    mdot_final(c, nb, K, part, alpha, out, nullptr, 0, 0, nullptr, nullptr);
 }
 template void mdot<float, double>(Ctx&, int64_t, int, const float*, int64_t, const double*, double, double*);
 template void mdot<double, double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double, double*);
@@ -1111,9 +1158,7 @@ void gemv_mdot(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, const doub
         hipLaunchKernelGGL(k, dim3(nb), dim3(KB), 0, c.stream, n, K, Q, ld, h, x, y, part);
         MMOF_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, K, part, 1.0, hout, (double*)nullptr, 0, 0,
-                       (double*)nullptr, (const int*)nullptr);
-    MMOF_LAUNCH_CHECK();
+    mdot_final(c, nb, K, part, 1.0, hout, nullptr, 0, 0, nullptr, nullptr);
 }
 
 template <class TX>
@@ -1122,16 +1167,8 @@ void gram_row(Ctx& c, int64_t n, int j, const TX* X, int64_t ld, const double* e
     const int nb = mdot_blocks(n);
     double* part = static_cast<double*>(c.work("mdot_part", sizeof(double) * (size_t)MAX_PART * (KMAX + 1)));
     const TX* xj = X + (int64_t)j * ld;
-    if (mdot_pairs(X, ld, xj, e))
-        hipLaunchKernelGGL((k_mdot2<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1,
-                           X, ld, xj, e, part, (const int*)nullptr);
-    else
-        hipLaunchKernelGGL((k_mdot<TX, TX>), dim3(nb, (unsigned)cdiv(j + 2, 8)), dim3(KB), 0, c.stream, n, j + 1,
-                           X, ld, xj, e, part, (const int*)nullptr);
-    MMOF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, j + 2, part, 1.0, (double*)nullptr, G, ldg,
-                       j, dj, (const int*)nullptr);
-    MMOF_LAUNCH_CHECK();
+    launch_mdot<TX, TX>(c, nb, n, j + 1, X, ld, xj, e, part, nullptr);
+    mdot_final(c, nb, j + 2, part, 1.0, nullptr, G, ldg, j, dj, nullptr);
 }
 template void gram_row<float>(Ctx&, int64_t, int, const float*, int64_t, const double*, double*, int, double*);
 template void gram_row<double>(Ctx&, int64_t, int, const double*, int64_t, const double*, double*, int, double*);
@@ -1149,10 +1186,13 @@ static void gemv_fused_impl(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, c
     }
     // two rows per lane when the columns allow 2-element loads (the grid covers row pairs)
     const bool pair = reinterpret_cast<uintptr_t>(X) % sizeof(TX) == 0;
-    // pairs: up to 1024 workgroups of contiguous row chunks; otherwise a grid-strided walk
-    const dim3 grid = pair ? dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 2 * KB))))
+    // pairs: contiguous row chunks of 2048 rows (at least 1024 chunks of no fewer than 2 KB
+    // rows, so that short vectors still spread over the chip; at most MAX_GEMV_PART); otherwise
+    // a grid-strided walk
+    const int64_t nbp = std::max<int64_t>(cdiv(n, 2048), std::min<int64_t>(cdiv(n, 2 * KB), 1024));
+    const dim3 grid = pair ? dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(MAX_GEMV_PART, nbp)))
                            : grid_for(n, KB, 2048);
-    double* part = sq ? static_cast<double*>(c.work("gemv_part", sizeof(double) * 2048)) : nullptr;
+    double* part = sq ? static_cast<double*>(c.work("gemv_part", sizeof(double) * MAX_GEMV_PART)) : nullptr;
     {
         // K columns and y (if any) read, the outputs written, cv read when given
         const double bytes = (double)n * ((double)sizeof(TX) * K + (y ? 8.0 : 0.0) + (out_d ? 8.0 : 0.0) +
@@ -1168,7 +1208,7 @@ static void gemv_fused_impl(Ctx& c, int64_t n, int K, const TX* X, int64_t ld, c
         MMOF_LAUNCH_CHECK();
     }
     if (sq) {
-        hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c.stream, (int)grid.x, (const double*)part, sq, skip);
+        hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(1024), 0, c.stream, (int)grid.x, (const double*)part, sq, skip);
         MMOF_LAUNCH_CHECK();
     }
 }
@@ -1201,17 +1241,9 @@ void cgs_once(Ctx& c, int64_t n, int K, const double* Q, int64_t ld, double* x, 
         const int Kt = K + (xe ? 1 : 0);
         {
             ScopedTime st(&c, tname, skip ? 0.0 : (double)n * (8.0 * K + 8.0), skip ? 0.0 : 2.0 * n * Kt);
-            if (mdot_pairs(Q, ld, x, xe))
-                hipLaunchKernelGGL((k_mdot2<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
-                                   n, K, Q, ld, (const double*)x, xe, part, skip);
-            else
-                hipLaunchKernelGGL((k_mdot<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
-                                   n, K, Q, ld, (const double*)x, xe, part, skip);
-            MMOF_LAUNCH_CHECK();
+            launch_mdot<double, double>(c, nb, n, K, Q, ld, (const double*)x, xe, part, skip);
         }
-        hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, Kt, part, 1.0, h, (double*)nullptr, 0,
-                           0, (double*)nullptr, skip);
-        MMOF_LAUNCH_CHECK();
+        mdot_final(c, nb, Kt, part, 1.0, h, nullptr, 0, 0, nullptr, skip);
     };
     dots(x, nullptr, "mdot");
     // x <- x - Q h in place (each row read before it is written), ||x||^2 into sq
@@ -1368,17 +1400,9 @@ void basis_extend(Ctx& c, int64_t n, int K, const double* Vs, int64_t ld, double
         const int Kt = K + (xe ? 1 : 0);
         {
             ScopedTime st(&c, tname, skip ? 0.0 : (double)n * (8.0 * K + 8.0), skip ? 0.0 : 2.0 * n * Kt);
-            if (mdot_pairs(Vs, ld, r, xe))
-                hipLaunchKernelGGL((k_mdot2<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
-                                   n, K, Vs, ld, (const double*)r, xe, part, skip);
-            else
-                hipLaunchKernelGGL((k_mdot<double, double>), dim3(nb, (unsigned)cdiv(Kt, 8)), dim3(KB), 0, c.stream,
-                                   n, K, Vs, ld, (const double*)r, xe, part, skip);
-            MMOF_LAUNCH_CHECK();
+            launch_mdot<double, double>(c, nb, n, K, Vs, ld, (const double*)r, xe, part, skip);
         }
-        hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(1024), 0, c.stream, nb, Kt, part, 1.0, h, (double*)nullptr, 0,
-                           0, (double*)nullptr, skip);
-        MMOF_LAUNCH_CHECK();
+        mdot_final(c, nb, Kt, part, 1.0, h, nullptr, 0, 0, nullptr, skip);
     };
     // h = Vs^T r and h[K] = ||r||^2 in one pass
     dots(r, nullptr, "mdot");
