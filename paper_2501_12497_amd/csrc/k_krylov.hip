@@ -691,7 +691,7 @@ __device__ __forceinline__ void quad_load_full(QuadRows<TX, NQ>& st, const TX* _
         const int cl = (q == NQ - 1) ? min(col, K - 1) : col;   // (only the last quad can pass K)
         const TX* src = X + (int64_t)cl * ld + rb;
         typedef TX VR __attribute__((ext_vector_type(RPL), aligned(sizeof(TX))));
-        const VR v = *reinterpret_cast<const VR*>(src);
+        const VR v = __builtin_nontemporal_load(reinterpret_cast<const VR*>(src));
 #pragma unroll
         for (int t = 0; t < RPL; ++t) st.x[q][t] = v[t];
     }
@@ -707,7 +707,8 @@ __device__ __forceinline__ void quad_load_full(QuadRows<TX, NQ>& st, const TX* _
         // (nu itself: the weights are formed in quad_mfma, after the loads have arrived)
         const TX* __restrict__ nu = static_cast<const TX*>(wv);
         if constexpr (sizeof(TX) == 4) {
-            const float4 v = *reinterpret_cast<const float4*>(nu + rb);
+            typedef float F4 __attribute__((ext_vector_type(4), aligned(16)));
+            const F4 v = __builtin_nontemporal_load(reinterpret_cast<const F4*>(nu + rb));
             st.w[0] = v.x;
             st.w[1] = v.y;
             st.w[2] = v.z;
