@@ -89,6 +89,8 @@ def measured_traffic(kernel):
 REFINE_ITERS = 10
 # candidate kernels for the roofline line: the projector pair, the weighted Gram and the
 # passes over the Krylov basis (every other kernel of the solve is far smaller)
+# the library runs up to 6 Horn-Schunck sweeps per launch (one launch is timed)
+HS_SWEEPS_PER_LAUNCH = 6
 CANDIDATES = ("wgram", "radon_fwd", "radon_adj", "gemv", "mdot", "gemv_mdot", "flow_adj", "hs_multi")
 
 
@@ -137,7 +139,7 @@ def operators_large(B, torch, reps=5, before_ops=None):
         "flow_fwd": lambda: B.apply_flow_op(stack, _lib.MMOF_FLOW_FWD, 1, 0, u, v),
         "flow_adj": lambda: B.apply_flow_op(stack, _lib.MMOF_FLOW_ADJ, 1, 0, None, v, r),
         "of_derivs": lambda: B.of_derivs(stack, u, 1),
-        "hs_multi": lambda: B.flow_update(stack, u, w, alpha=0.1, n_sweeps=8, delta_r=1),
+        "hs_multi": lambda: B.flow_update(stack, u, w, alpha=0.1, n_sweeps=HS_SWEEPS_PER_LAUNCH, delta_r=1),
         # frames and flow reduced by 4 (both block means) and the flow upscaled, no sweeps
         "box_down": lambda: B.flow_update_scaled(stack, u, w, alpha=0.1, n_sweeps=0, delta_r=1, scale=4),
         "flow_up": lambda: B.flow_update_scaled(stack, u, w, alpha=0.1, n_sweeps=0, delta_r=1, scale=4),
@@ -166,7 +168,7 @@ def operators_large(B, torch, reps=5, before_ops=None):
         ent = {"us": round(ms * 1e3 / n, 1), "GB/s": round(by / sec / 1e9, 1), "hbm_frac": round(by / sec / 1e9 / HBM_PEAK_GBS, 3),
                "TFLOP/s": round(fl / sec / 1e12, 2), "compute_frac": round(fl / sec / 1e12 / peak, 3)}
         if name == "hs_multi":
-            ent["sweeps_per_launch"] = 8
+            ent["sweeps_per_launch"] = HS_SWEEPS_PER_LAUNCH
         table[name] = ent
     # one whole flow update (derivatives, 200 warm-started sweeps, reverse flow) on the full
     # frames and on frames reduced by 2, 4 and the automatic factor: HIP-event time
