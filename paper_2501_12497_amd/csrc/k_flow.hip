@@ -106,13 +106,13 @@ __global__ __launch_bounds__(256) void k_flow_fwd(const Tile* __restrict__ tiles
 }
 
 // Forward and (when vr is not null) reverse flow rows of Theta for K columns at once:
-// column j of U (FP64, leading dimension ldu) is rounded to T and mapped to
+// column j of U (S: FP64, or already T; leading dimension ldu) is rounded to T and mapped to
 // out[j*ldo + oF + pair pixel] (forward) and out[j*ldo + oR + pair pixel] (reverse).  The
 // values equal those of k_flow_fwd applied to the rounded column.
-template <class T, int INTERP, int FTW, int FTH>
+template <class T, class S, int INTERP, int FTW, int FTH>
 __global__ __launch_bounds__(256) void k_flow_fwd_cols(const Tile* __restrict__ tiles,
                                                        const FrameInfo* __restrict__ fr,
-                                                       const double* __restrict__ U, int64_t ldu,
+                                                       const S* __restrict__ U, int64_t ldu,
                                                        const T* __restrict__ v, const T* __restrict__ vr,
                                                        T* __restrict__ out, int64_t ldo, int64_t oF, int64_t oR) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -122,15 +122,14 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols(const Tile* __restrict__ 
     if (x >= f.nx || y >= f.ny) return;
     const int64_t np = (int64_t)f.nx * f.ny;
     const int64_t p = (int64_t)y * f.nx + x;
-    const double* ut = U + (int64_t)blockIdx.y * ldu + f.off;
-    const double* ut1 = ut + np;
+    const S* ut = U + (int64_t)blockIdx.y * ldu + f.off;
+    const S* ut1 = ut + np;
     T* o = out + (int64_t)blockIdx.y * ldo;
     const T* vf = v + 2 * f.pair_off;
-    o[oF + f.pair_off + p] = warp_sample<T, INTERP, double>(ut1, f.nx, f.ny, x, y, vf[p], vf[np + p]) - (T)ut[p];
+    o[oF + f.pair_off + p] = warp_sample<T, INTERP, S>(ut1, f.nx, f.ny, x, y, vf[p], vf[np + p]) - (T)ut[p];
     if (vr) {
         const T* vb = vr + 2 * f.pair_off;
-        o[oR + f.pair_off + p] =
-            warp_sample<T, INTERP, double>(ut, f.nx, f.ny, x, y, vb[p], vb[np + p]) - (T)ut1[p];
+        o[oR + f.pair_off + p] = warp_sample<T, INTERP, S>(ut, f.nx, f.ny, x, y, vb[p], vb[np + p]) - (T)ut1[p];
     }
 }
 
@@ -165,10 +164,10 @@ __global__ __launch_bounds__(256) void k_flow_fwd4(const Tile* __restrict__ tile
     st4n(r + f.pair_off + p, o, nv);
 }
 
-template <class T, int INTERP, int LW>
+template <class T, class S, int INTERP, int LW>
 __global__ __launch_bounds__(256) void k_flow_fwd_cols4(const Tile* __restrict__ tiles,
                                                         const FrameInfo* __restrict__ fr,
-                                                        const double* __restrict__ U, int64_t ldu,
+                                                        const S* __restrict__ U, int64_t ldu,
                                                         const T* __restrict__ v, const T* __restrict__ vr,
                                                         T* __restrict__ out, int64_t ldo, int64_t oF, int64_t oR) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -178,18 +177,18 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols4(const Tile* __restrict__
     if (x >= f.nx || y >= f.ny) return;
     const int64_t np = (int64_t)f.nx * f.ny;
     const int64_t p = (int64_t)y * f.nx + x;
-    const double* ut = U + (int64_t)blockIdx.y * ldu + f.off;
-    const double* ut1 = ut + np;
+    const S* ut = U + (int64_t)blockIdx.y * ldu + f.off;
+    const S* ut1 = ut + np;
     T* o = out + (int64_t)blockIdx.y * ldo;
     const int nv = min(4, f.nx - x);
-    const Quad<double> a = ld4n(ut + p, nv), b = ld4n(ut1 + p, nv);
+    const Quad<S> a = ld4n(ut + p, nv), b = ld4n(ut1 + p, nv);
     {
         const T* vf = v + 2 * f.pair_off;
         const Quad<T> vx = ld4n(vf + p, nv), vy = ld4n(vf + np + p, nv);
         Quad<T> q;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            q.v[j] = warp_sample<T, INTERP, double>(ut1, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)a.v[j];
+            q.v[j] = warp_sample<T, INTERP, S>(ut1, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)a.v[j];
         st4n(o + oF + f.pair_off + p, q, nv);
     }
     if (vr) {
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols4(const Tile* __restrict__
         Quad<T> q;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            q.v[j] = warp_sample<T, INTERP, double>(ut, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)b.v[j];
+            q.v[j] = warp_sample<T, INTERP, S>(ut, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - (T)b.v[j];
         st4n(o + oR + f.pair_off + p, q, nv);
     }
 }
@@ -206,10 +205,10 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols4(const Tile* __restrict__
 // k_flow_fwd_cols4 with the sample cells of a lane's four pixels (both directions) formed
 // once from the flows and reused for JC consecutive columns (grid.y = column groups): the
 // flows are read once per JC columns instead of once per column.
-template <class T, int INTERP, int LW, int JC>
+template <class T, class S, int INTERP, int LW, int JC>
 __global__ __launch_bounds__(256) void k_flow_fwd_colsJ(const Tile* __restrict__ tiles,
                                                         const FrameInfo* __restrict__ fr,
-                                                        const double* __restrict__ U, int64_t ldu, int K,
+                                                        const S* __restrict__ U, int64_t ldu, int K,
                                                         const T* __restrict__ v, const T* __restrict__ vr,
                                                         T* __restrict__ out, int64_t ldo, int64_t oF, int64_t oR) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -237,17 +236,17 @@ __global__ __launch_bounds__(256) void k_flow_fwd_colsJ(const Tile* __restrict__
     for (int jj = 0; jj < JC; ++jj) {
         const int col = c0 + jj;
         if (col >= K) break;
-        const double* ut = U + (int64_t)col * ldu + f.off;
-        const double* ut1 = ut + np;
+        const S* ut = U + (int64_t)col * ldu + f.off;
+        const S* ut1 = ut + np;
         T* o = out + (int64_t)col * ldo;
-        const Quad<double> a = ld4n(ut + p, nv), b = ld4n(ut1 + p, nv);
+        const Quad<S> a = ld4n(ut + p, nv), b = ld4n(ut1 + p, nv);
         Quad<T> q;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, double>(ut1, cf[j]) - (T)a.v[j];
+        for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, S>(ut1, cf[j]) - (T)a.v[j];
         st4n(o + oF + f.pair_off + p, q, nv);
         if (vr) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, double>(ut, cr[j]) - (T)b.v[j];
+            for (int j = 0; j < 4; ++j) q.v[j] = sample_at<T, INTERP, S>(ut, cr[j]) - (T)b.v[j];
             st4n(o + oR + f.pair_off + p, q, nv);
         }
     }
@@ -604,57 +603,66 @@ void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const v
     });
 }
 
-void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const double* U, int64_t ldu, int K, const void* v,
-                          const void* vr, void* out, int64_t ldo, int64_t oF, int64_t oR) {
+void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const void* Uv, bool u_op, int64_t ldu, int K,
+                          const void* v, const void* vr, void* out, int64_t ldo, int64_t oF, int64_t oR) {
     if (g.n_pairs == 0 || K <= 0) return;
     const int choice = g.choice("flow_fwd", dt, 1);
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "flow_fwd_cols", (vr ? 2.0 : 1.0) * K * (4.0 * sizeof(T) + 16.0) * g.pair_px,
-                      (vr ? 2.0 : 1.0) * K * 12.0 * g.pair_px);
-        const bool v4 = aligned_to(sizeof(double), {U}) && aligned_to(sizeof(T), {v, vr, out});
-        if (v4) {
-            const Flow4Shape sh = kFlow4Shapes[choice];
-            const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
-            if ((int64_t)g.max_ny * g.max_nx < ((int64_t)1 << 31)) {
-                // (prepared cells hold 32-bit offsets within a frame)
-                constexpr int JC = 8;   // columns per thread
-                auto pick = [&](auto interp_tag) {
-                    constexpr int I = decltype(interp_tag)::value;
-                    return sh.lw == 64 ? k_flow_fwd_colsJ<T, I, 64, JC> : k_flow_fwd_colsJ<T, I, 32, JC>;
-                };
-                auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
-                                                     : pick(std::integral_constant<int, 0>{});
-                hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)cdiv(K, JC)), dim3(64 * sh.nw), 0,
-                                   c.stream, tl.buf.as<Tile>(), g.dframes(), U, ldu, K, (const T*)v, (const T*)vr,
-                                   (T*)out, ldo, oF, oR);
+        auto run = [&](auto s_tag) {
+            using S = decltype(s_tag);
+            const S* U = static_cast<const S*>(Uv);
+            ScopedTime st(&c, "flow_fwd_cols", (vr ? 2.0 : 1.0) * K * (4.0 * sizeof(T) + 2.0 * sizeof(S)) * g.pair_px,
+                          (vr ? 2.0 : 1.0) * K * 12.0 * g.pair_px);
+            const bool v4 = aligned_to(sizeof(S), {U}) && aligned_to(sizeof(T), {v, vr, out});
+            if (v4) {
+                const Flow4Shape sh = kFlow4Shapes[choice];
+                const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
+                if ((int64_t)g.max_ny * g.max_nx < ((int64_t)1 << 31)) {
+                    // (prepared cells hold 32-bit offsets within a frame)
+                    constexpr int JC = 8;   // columns per thread
+                    auto pick = [&](auto interp_tag) {
+                        constexpr int I = decltype(interp_tag)::value;
+                        return sh.lw == 64 ? k_flow_fwd_colsJ<T, S, I, 64, JC> : k_flow_fwd_colsJ<T, S, I, 32, JC>;
+                    };
+                    auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
+                                                         : pick(std::integral_constant<int, 0>{});
+                    hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)cdiv(K, JC)), dim3(64 * sh.nw), 0,
+                                       c.stream, tl.buf.as<Tile>(), g.dframes(), U, ldu, K, (const T*)v, (const T*)vr,
+                                       (T*)out, ldo, oF, oR);
+                } else {
+                    auto pick = [&](auto interp_tag) {
+                        constexpr int I = decltype(interp_tag)::value;
+                        return sh.lw == 64 ? k_flow_fwd_cols4<T, S, I, 64> : k_flow_fwd_cols4<T, S, I, 32>;
+                    };
+                    auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
+                                                         : pick(std::integral_constant<int, 0>{});
+                    hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(64 * sh.nw), 0, c.stream,
+                                       tl.buf.as<Tile>(), g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out,
+                                       ldo, oF, oR);
+                }
             } else {
+                const TileShape sh = kFlowShapes[choice];
+                const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
                 auto pick = [&](auto interp_tag) {
                     constexpr int I = decltype(interp_tag)::value;
-                    return sh.lw == 64 ? k_flow_fwd_cols4<T, I, 64> : k_flow_fwd_cols4<T, I, 32>;
+                    return choice == 0 ? k_flow_fwd_cols<T, S, I, 64, 4>
+                           : choice == 1 ? k_flow_fwd_cols<T, S, I, 32, 8>
+                           : choice == 2 ? k_flow_fwd_cols<T, S, I, 128, 2>
+                                         : k_flow_fwd_cols<T, S, I, 16, 16>;
                 };
                 auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
                                                      : pick(std::integral_constant<int, 0>{});
-                hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(64 * sh.nw), 0, c.stream,
+                hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(256), 0, c.stream,
                                    tl.buf.as<Tile>(), g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo,
                                    oF, oR);
             }
-        } else {
-            const TileShape sh = kFlowShapes[choice];
-            const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
-            auto pick = [&](auto interp_tag) {
-                constexpr int I = decltype(interp_tag)::value;
-                return choice == 0 ? k_flow_fwd_cols<T, I, 64, 4>
-                       : choice == 1 ? k_flow_fwd_cols<T, I, 32, 8>
-                       : choice == 2 ? k_flow_fwd_cols<T, I, 128, 2>
-                                     : k_flow_fwd_cols<T, I, 16, 16>;
-            };
-            auto k = interp == MMOF_INTERP_ROUND ? pick(std::integral_constant<int, 1>{})
-                                                 : pick(std::integral_constant<int, 0>{});
-            hipLaunchKernelGGL(k, dim3((unsigned)tl.count, (unsigned)K), dim3(256), 0, c.stream, tl.buf.as<Tile>(),
-                               g.dframes(), U, ldu, (const T*)v, (const T*)vr, (T*)out, ldo, oF, oR);
-        }
-        MMOF_LAUNCH_CHECK();
+            MMOF_LAUNCH_CHECK();
+        };
+        if (u_op)
+            run(T{});
+        else
+            run(double{});
     });
 }
 

@@ -26,10 +26,11 @@ void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const v
 void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const void* r, const void* v, void* u,
                      bool accumulate, const int32_t* d_radius /* device int: floor(max|v|)+1, or null */,
                      int choice = -1);
-// Forward (v) and, when vr is not null, reverse (vr) flow rows of Theta for K FP64 columns U
-// (leading dimension ldu) in one launch: out[j*ldo + oF ...] and out[j*ldo + oR ...], dtype dt.
-void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const double* U, int64_t ldu, int K, const void* v,
-                          const void* vr, void* out, int64_t ldo, int64_t oF, int64_t oR);
+// Forward (v) and, when vr is not null, reverse (vr) flow rows of Theta for K columns U (FP64,
+// or in the operator precision of dt when u_op; leading dimension ldu) in one launch:
+// out[j*ldo + oF ...] and out[j*ldo + oR ...], dtype dt.  Both forms give the same values.
+void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const void* U, bool u_op, int64_t ldu, int K,
+                          const void* v, const void* vr, void* out, int64_t ldo, int64_t oF, int64_t oR);
 void launch_flow_dv(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v,
                     const void* w, void* gv);
 // Device int *d_out = floor(max |v|) + 1 over all pairs (saturating at 1<<20, NaN -> saturate).

@@ -81,6 +81,12 @@ struct Solver {
     bool implicit = false;
     double *Tb = nullptr, *GAs = nullptr, *GTs = nullptr, *ds = nullptr, *zt = nullptr, *zt_prev = nullptr;
     TX *AV, *TV, *u_op, *vin_n, *vin_m, *out_n, *out_n2, *nu, *yR, *yW, *flow_v, *flow_vr, *flow_tmp, *I;
+    // FP32 operators with flows: every column of V also in the operator precision (V32, its
+    // rounding, written where the column is formed), which the rebuild of Theta V's flow rows
+    // reads instead of the FP64 columns
+    bool col_op = false;
+    TX* V32 = nullptr;
+    TX* col_in(int j) { return col_op ? V32 + (int64_t)j * n : vin_n; }
     // flow on reduced frames: their geometry (owned by the plan), frames and flow
     int fscale = 1;
     Geom* gs = nullptr;
@@ -167,6 +173,8 @@ struct Solver {
         }
         AV = wsx("AV", (int64_t)Kcap * m);
         TV = wsx("TV", (int64_t)Kcap * R);
+        col_op = flow && std::is_same<TX, float>::value;
+        if (col_op) V32 = wsx("V32", (int64_t)Kcap * n);
         u_op = wsx("u_op", n);
         out_n2 = wsx("out_n2", n);
         nu = wsx("nu", R);
@@ -363,18 +371,19 @@ struct Solver {
         gemv_fused<double, double>(c, len, k, Q, len, h, -1.0, y, 1.0, x, nullptr, nullptr, sq);
     }
 
-    // H v_j, the row/column j of G_H, d_j = (H v_j)^T b and Theta v_j; vin_n already holds
+    // H v_j, the row/column j of G_H, d_j = (H v_j)^T b and Theta v_j; col_in(j) already holds
     // v_j in TX when have_vin.  For j < start_av, H v_j is the Golub-Kahan start's FP64 product
     // (rounded to TX) instead of a new application of H.
     void add_column(int j, bool have_vin, int start_av = 0) {
-        if (!have_vin) convert<double, TX>(c, n, V + (int64_t)j * n, vin_n);
+        TX* vj = col_in(j);
+        if (!have_vin) convert<double, TX>(c, n, V + (int64_t)j * n, vj);
         TX* avj = AV + (int64_t)j * m;
         if (j < start_av)
             convert<double, TX>(c, m, AVs + (int64_t)j * m, avj);
         else
-            A(vin_n, avj);
+            A(vj, avj);
         gram_row<TX>(c, m, j, AV, m, b, GAs, KLD, ds + j);
-        theta(vin_n, TV + (int64_t)j * R);
+        theta(vj, TV + (int64_t)j * R);
     }
 
     // The Gram matrices and d of the true basis from those of the stored columns, the
@@ -541,7 +550,8 @@ struct Solver {
                             launch_flow_radius(c, g, dt, flow_vr, rad_vr);
                         }
                     });
-                    launch_flow_fwd_cols(c, g, dt, p.interp, V, n, K, flow_v, p.use_reverse ? flow_vr : nullptr, TV, R,
+                    launch_flow_fwd_cols(c, g, dt, p.interp, col_op ? (const void*)V32 : (const void*)V, col_op, n, K,
+                                         flow_v, p.use_reverse ? flow_vr : nullptr, TV, R,
                                          oRF, oRR);
                     if (rep) rep->n_L += (int64_t)K * (p.use_reverse ? 2 : 1);
                     if (rep) rep->n_flow_updates++;
@@ -593,7 +603,7 @@ struct Solver {
             // the coefficients of u^(k+1), whatever is queued next
             const double* zt_k = zt;
             if (ahead) {
-                normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
+                normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, col_in(K));
                 add_column(K, true);
                 if (!nu_fresh) theta(u_op, nu);
                 weights(nu, w2, K + 1);
@@ -655,7 +665,7 @@ struct Solver {
                 break;
             }
             if (!ahead) {
-                normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, vin_n);
+                normalize2<TX>(c, n, r, scal + 7, scal + 14, V + (int64_t)K * n, col_in(K));
                 add_column(K, true);
             }
             ++K;
@@ -716,6 +726,11 @@ static void check_solve_capacity(Ctx& c, const Plan& P, const mmof_solve_params&
         grow += c.work_growth(t + "AV", es * K * m) + c.work_growth(t + "TV", es * K * R);
         for (const char* nm : {"u_op", "out_n", "out_n2", "vin_n"}) vecs += c.work_growth(t + nm, es * n);
         for (const char* nm : {"nu", "yR", "yW"}) vecs += c.work_growth(t + nm, es * R);
+        if (flow && es == sizeof(float)) {
+            // the FP32 copy of V's columns
+            per_col += es * n;
+            grow += c.work_growth(t + "V32", es * K * n);
+        }
     };
     if (f64) per_precision("solve_d_", sizeof(double));
     if (f32) per_precision("solve_f_", sizeof(float));
