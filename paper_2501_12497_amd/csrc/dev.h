@@ -130,4 +130,25 @@ __device__ __forceinline__ int mirror(int i, int n) {
     return i;
 }
 
+// The MM weight 1/sqrt(nu^2 + eps^2) (eps > 0) in FP64, the one formula of every weight path
+// (the buffer, the Gram, the residual's weighting and the Theta kernels that fuse it): the
+// hardware reciprocal square root (relative error below 2^-22) refined by two Newton steps
+// r <- r (3 - x r^2) / 2, each of which squares the relative error, so the result is within a
+// few ulp of the rounded value; a sum too large for the refinement takes the division.
+__device__ __forceinline__ double mm_weight(double a, double eps2) {
+    const double x = fma(a, a, eps2);
+    if (!(x < 1.0e300)) return 1.0 / sqrt(x);
+    const double h = 0.5 * x;
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(-h * r, r, 1.5);
+    r = r * fma(-h * r, r, 1.5);
+    return r;
+}
+
+// A row value weighted by the MM weight of its nu, rounded to the row type.
+template <class T>
+__device__ __forceinline__ T mm_weighted(T y, T nu, double eps2) {
+    return (T)((double)y * mm_weight((double)nu, eps2));
+}
+
 }  // namespace mmof

@@ -88,7 +88,8 @@ __device__ __forceinline__ T sample_at(const S* __restrict__ src, const SampleCe
 template <class T, int INTERP, int FTW, int FTH>
 __global__ __launch_bounds__(256) void k_flow_fwd(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ u, const T* __restrict__ v,
-                                                  T* __restrict__ r, int direction) {
+                                                  T* __restrict__ r, int direction, const T* __restrict__ nuw,
+                                                  T* __restrict__ mw, double eps2) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
     const int x = tl.x0 + (int)(threadIdx.x % FTW);
@@ -102,7 +103,9 @@ __global__ __launch_bounds__(256) void k_flow_fwd(const Tile* __restrict__ tiles
     const T vxx = vx[p], vyy = vx[np + p];
     const T* src = direction > 0 ? ut1 : ut;
     const T* sub = direction > 0 ? ut : ut1;
-    r[f.pair_off + p] = warp_sample<T, INTERP>(src, f.nx, f.ny, x, y, vxx, vyy) - sub[p];
+    const T val = warp_sample<T, INTERP>(src, f.nx, f.ny, x, y, vxx, vyy) - sub[p];
+    r[f.pair_off + p] = val;
+    if (mw) mw[f.pair_off + p] = mm_weighted(val, nuw[f.pair_off + p], eps2);
 }
 
 // Forward and (when vr is not null) reverse flow rows of Theta for K columns at once:
@@ -139,10 +142,13 @@ __global__ __launch_bounds__(256) void k_flow_fwd_cols(const Tile* __restrict__ 
 // offset); a row whose width is not a multiple of 4 ends with a thread of 1..3 pixels, whose
 // accesses go element by element.  The bilinear samples stay single loads.  Values equal those
 // of the scalar kernels.
+// mw (may be null; the scalar kernel too): the rows weighted by the MM weights of nuw
+// (RowWeighting).
 template <class T, int INTERP, int LW>
 __global__ __launch_bounds__(256) void k_flow_fwd4(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                    const T* __restrict__ u, const T* __restrict__ v,
-                                                   T* __restrict__ r, int direction) {
+                                                   T* __restrict__ r, int direction, const T* __restrict__ nuw,
+                                                   T* __restrict__ mw, double eps2) {
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
     const int x = tl.x0 + 4 * (int)(threadIdx.x % LW);
@@ -162,6 +168,13 @@ __global__ __launch_bounds__(256) void k_flow_fwd4(const Tile* __restrict__ tile
     for (int j = 0; j < 4; ++j)
         o.v[j] = warp_sample<T, INTERP>(src, f.nx, f.ny, x + j, y, vx.v[j], vy.v[j]) - sub.v[j];
     st4n(r + f.pair_off + p, o, nv);
+    if (mw) {
+        const Quad<T> nq = ld4n(nuw + f.pair_off + p, nv);
+        Quad<T> m;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m.v[j] = mm_weighted(o.v[j], nq.v[j], eps2);
+        st4n(mw + f.pair_off + p, m, nv);
+    }
 }
 
 template <class T, class S, int INTERP, int LW>
@@ -600,25 +613,29 @@ static auto flow_adj_kernel(int choice) {
 }
 
 void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r,
-                     int choice) {
+                     int choice, const RowWeighting* rw) {
     if (g.n_pairs == 0) return;
     if (choice < 0) choice = g.choice("flow_fwd", dt, 1);
     MMOF_CHECK(choice >= 0 && choice < kFlowCandidates, MMOF_ERR_INVALID, "flow tile candidate out of range");
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        ScopedTime st(&c, "flow_fwd", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
-        if (aligned_to(sizeof(T), {u, v, r})) {
+        // (with rw also nu read and the weighted rows written)
+        ScopedTime st(&c, "flow_fwd", (rw ? 7.0 : 5.0) * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
+        const T* nuw = rw ? (const T*)rw->nu_a : nullptr;
+        T* mw = rw ? (T*)rw->m_a : nullptr;
+        const double eps2 = rw ? rw->eps2 : 0.0;
+        if (aligned_to(sizeof(T), {u, v, r, nuw, mw})) {
             const Flow4Shape sh = kFlow4Shapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), true);
             auto k = interp == MMOF_INTERP_ROUND ? flow_fwd4_kernel<T, 1>(choice) : flow_fwd4_kernel<T, 0>(choice);
             hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(64 * sh.nw), 0, c.stream, tl.buf.as<Tile>(),
-                               g.dframes(), (const T*)u, (const T*)v, (T*)r, direction);
+                               g.dframes(), (const T*)u, (const T*)v, (T*)r, direction, nuw, mw, eps2);
         } else {
             const TileShape sh = kFlowShapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, true);
             auto k = interp == MMOF_INTERP_ROUND ? flow_fwd_kernel<T, 1>(choice) : flow_fwd_kernel<T, 0>(choice);
             hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<Tile>(), g.dframes(),
-                               (const T*)u, (const T*)v, (T*)r, direction);
+                               (const T*)u, (const T*)v, (T*)r, direction, nuw, mw, eps2);
         }
         MMOF_LAUNCH_CHECK();
     });

@@ -8,10 +8,13 @@ namespace mmof {
 
 // A GTW x GTH tile per workgroup of 256 threads; each thread owns RPT = GTW * GTH / 256
 // consecutive rows of one column, so the row below is loaded once and reused.
+// mx, my (may be null): gx and gy weighted by the MM weights of nux, nuy (RowWeighting).
 template <class T, int GTW, int GTH>
 __global__ __launch_bounds__(256) void k_grad_fwd(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                   const T* __restrict__ u, const T* __restrict__ wx,
-                                                  const T* __restrict__ wy, T* __restrict__ gx, T* __restrict__ gy) {
+                                                  const T* __restrict__ wy, T* __restrict__ gx, T* __restrict__ gy,
+                                                  const T* __restrict__ nux, const T* __restrict__ nuy,
+                                                  T* __restrict__ mx, T* __restrict__ my, double eps2) {
     constexpr int RPT = GTW * GTH / 256;
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
@@ -29,14 +32,18 @@ __global__ __launch_bounds__(256) void k_grad_fwd(const Tile* __restrict__ tiles
         if (x < nx - 1) {
             const int64_t o = f.gx_off + (int64_t)y * (nx - 1) + x;
             T d = uf[p + 1] - c;
-            gx[o] = wx ? wx[o] * d : d;
+            d = wx ? wx[o] * d : d;
+            gx[o] = d;
+            if (mx) mx[o] = mm_weighted(d, nux[o], eps2);
         }
         T below = T(0);
         if (y < ny - 1) {
             below = uf[p + nx];
             const int64_t o = f.gy_off + p;
             T d = below - c;
-            gy[o] = wy ? wy[o] * d : d;
+            d = wy ? wy[o] * d : d;
+            gy[o] = d;
+            if (my) my[o] = mm_weighted(d, nuy[o], eps2);
         }
         c = below;
     }
@@ -100,7 +107,17 @@ __global__ __launch_bounds__(256) void k_grad_adj(const Tile* __restrict__ tiles
 template <class T, int LW, int RPT>
 __global__ __launch_bounds__(256) void k_grad_fwd4(const Tile* __restrict__ tiles, const FrameInfo* __restrict__ fr,
                                                    const T* __restrict__ u, const T* __restrict__ wx,
-                                                   const T* __restrict__ wy, T* __restrict__ gx, T* __restrict__ gy) {
+                                                   const T* __restrict__ wy, T* __restrict__ gx, T* __restrict__ gy,
+                                                   const T* __restrict__ nux, const T* __restrict__ nuy,
+                                                   T* __restrict__ mx, T* __restrict__ my, double eps2) {
+    // the MM-weighted copies of four aligned values and of one value (mx, my may be null)
+    auto mw4 = [&](T* m, const T* nu, int64_t o, const Quad<T>& q) {
+        const Quad<T> nq = ld4(nu + o);
+        Quad<T> r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r.v[i] = mm_weighted(q.v[i], nq.v[i], eps2);
+        st4(m + o, r);
+    };
     const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const FrameInfo f = fr[tl.frame];
     const int lx = (int)(threadIdx.x % LW);
@@ -144,15 +161,24 @@ __global__ __launch_bounds__(256) void k_grad_fwd4(const Tile* __restrict__ tile
                 for (int i = 0; i < 4; ++i) g.v[i] = w.v[i] * g.v[i];
             }
             st4(gx + B + e0, g);
+            if (mx) mw4(mx, nux, B + e0, g);
         } else if (e0 < n_el) {  // the tail (fewer than 4 values)
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                if (e0 + i < n_el) gx[B + e0 + i] = wx ? wx[B + e0 + i] * g.v[i] : g.v[i];
+                if (e0 + i < n_el) {
+                    const T val = wx ? wx[B + e0 + i] * g.v[i] : g.v[i];
+                    gx[B + e0 + i] = val;
+                    if (mx) mx[B + e0 + i] = mm_weighted(val, nux[B + e0 + i], eps2);
+                }
         }
         if (lx == 0) {  // the head, before the first aligned element
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                if (i < t0 && i < n_el) gx[B + i] = wx ? wx[B + i] * d[i] : d[i];
+                if (i < t0 && i < n_el) {
+                    const T val = wx ? wx[B + i] * d[i] : d[i];
+                    gx[B + i] = val;
+                    if (mx) mx[B + i] = mm_weighted(val, nux[B + i], eps2);
+                }
         }
         Quad<T> below = zero4<T>();
         if (y < ny - 1) {
@@ -167,6 +193,7 @@ __global__ __launch_bounds__(256) void k_grad_fwd4(const Tile* __restrict__ tile
                 for (int j = 0; j < 4; ++j) d.v[j] = w.v[j] * d.v[j];
             }
             st4(gy + og, d);
+            if (my) mw4(my, nuy, og, d);
         }
         c = below;
     }
@@ -273,26 +300,34 @@ static auto grad_adj4_kernel(int choice) {
 }
 
 void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy,
-                     int choice) {
+                     int choice, const RowWeighting* rw) {
     if (choice < 0) choice = g.choice("grad_fwd", dt, 2);
     MMOF_CHECK(choice >= 0 && choice < kGradCandidates, MMOF_ERR_INVALID, "grad tile candidate out of range");
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
-        // u read, gx and gy written, weights read when given
-        const double bytes = sizeof(T) * ((double)g.n + (wx ? 2.0 : 1.0) * g.gx_len + (wy ? 2.0 : 1.0) * g.gy_len);
+        // u read, gx and gy written, weights read when given; with rw also nu read and the
+        // weighted rows written
+        const double per_row = (rw ? 3.0 : 1.0);
+        const double bytes = sizeof(T) * ((double)g.n + (per_row + (wx ? 1.0 : 0.0)) * g.gx_len +
+                                          (per_row + (wy ? 1.0 : 0.0)) * g.gy_len);
         ScopedTime st(&c, "grad_fwd", bytes, (wx ? 2.0 : 1.0) * g.gx_len + (wy ? 2.0 : 1.0) * g.gy_len);
-        if (g.vec4 && aligned_to(4 * sizeof(T), {u, wx, wy, gx, gy})) {
+        const T* nux = rw ? (const T*)rw->nu_a : nullptr;
+        const T* nuy = rw ? (const T*)rw->nu_b : nullptr;
+        T* mx = rw ? (T*)rw->m_a : nullptr;
+        T* my = rw ? (T*)rw->m_b : nullptr;
+        const double eps2 = rw ? rw->eps2 : 0.0;
+        if (g.vec4 && aligned_to(4 * sizeof(T), {u, wx, wy, gx, gy, nux, nuy, mx, my})) {
             const Grad4Shape sh = kGrad4Shapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw(), sh.th(), false);
             hipLaunchKernelGGL(grad_fwd4_kernel<T>(choice), dim3((unsigned)tl.count), dim3(64 * sh.nw), 0, c.stream,
                                tl.buf.as<Tile>(), g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx,
-                               (T*)gy);
+                               (T*)gy, nux, nuy, mx, my, eps2);
         } else {
             const TileShape sh = kGradShapes[choice];
             const TileList& tl = g.tile_list(c.stream, sh.tw, sh.th, false);
             hipLaunchKernelGGL(grad_fwd_kernel<T>(choice), dim3((unsigned)tl.count), dim3(256), 0, c.stream,
                                tl.buf.as<Tile>(), g.dframes(), (const T*)u, (const T*)wx, (const T*)wy, (T*)gx,
-                               (T*)gy);
+                               (T*)gy, nux, nuy, mx, my, eps2);
         }
         MMOF_LAUNCH_CHECK();
     });

@@ -75,21 +75,6 @@ __device__ __forceinline__ void dot_row2(const TX* __restrict__ X, int64_t ld, i
     }
 }
 
-// The MM weight 1/sqrt(nu^2 + eps^2) (eps > 0) in FP64, the one formula of every weight path
-// (the buffer, the Gram and the residual with weights formed from nu): the hardware reciprocal
-// square root (relative error below 2^-22) refined by two Newton steps r <- r (3 - x r^2) / 2,
-// each of which squares the relative error, so the result is within a few ulp of the rounded
-// value; a sum too large for the refinement takes the division.
-__device__ __forceinline__ double mm_weight(double a, double eps2) {
-    const double x = fma(a, a, eps2);
-    if (!(x < 1.0e300)) return 1.0 / sqrt(x);
-    const double h = 0.5 * x;
-    double r = __builtin_amdgcn_rsq(x);
-    r = r * fma(-h * r, r, 1.5);
-    r = r * fma(-h * r, r, 1.5);
-    return r;
-}
-
 // FP64 MM weights w2 = 1/sqrt(nu^2 + eps^2) of the rows of Theta.
 template <class TX>
 __global__ void k_mm_weights_f64(int64_t n, const TX* __restrict__ nu, double eps2, double* __restrict__ w) {

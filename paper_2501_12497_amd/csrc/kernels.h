@@ -14,15 +14,27 @@ extern const int kBlurCandidates, kGradCandidates, kFlowCandidates, kFlowAdjCand
 TileShape grad_tile(const Geom& g, int choice);
 TileShape flow_tile(const Geom& g, int choice);
 
-// Psi and Psi^T (eq. L); weights optional.
+// The MM weighting of Theta's rows fused into the kernel that forms them: besides its rows y, the
+// kernel writes m = y / sqrt(nu^2 + eps^2) (the weight in FP64, the product rounded to the row
+// type, as the separate weighting pass computes it), nu and m laid out like y.  a: the rows of the
+// first output (gx, or the flow rows), b: those of the second (gy).
+struct RowWeighting {
+    const void* nu_a = nullptr;
+    void* m_a = nullptr;
+    const void* nu_b = nullptr;
+    void* m_b = nullptr;
+    double eps2 = 0.0;
+};
+
+// Psi and Psi^T (eq. L); weights optional; rw: the MM weighting of the rows (may be null).
 void launch_grad_fwd(Ctx& c, Geom& g, int dt, const void* u, const void* wx, const void* wy, void* gx, void* gy,
-                     int choice = -1);
+                     int choice = -1, const RowWeighting* rw = nullptr);
 void launch_grad_adj(Ctx& c, Geom& g, int dt, const void* gx, const void* gy, const void* wx, const void* wy,
                      void* u, bool accumulate, int choice = -1);
 
 // L(v) = -M-bar (direction +1) / -M-bar' (direction -1) and relatives.
 void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r,
-                     int choice = -1);
+                     int choice = -1, const RowWeighting* rw = nullptr);
 void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const void* r, const void* v, void* u,
                      bool accumulate, const int32_t* d_radius /* device int: floor(max|v|)+1, or null */,
                      int choice = -1);

@@ -226,6 +226,35 @@ struct Solver {
         theta_flow(in, out);
         if (rep) rep->n_theta++;
     }
+    // theta(in, out) and, in the same kernels, its rows weighted by the MM weights of nu_
+    // (1/sqrt(nu^2 + eps^2)) into outw: the residual's W Theta u without a pass of its own
+    // (per-row weights from nu, no temporal-difference rows)
+    void theta_weighted(const TX* in, TX* out, const TX* nu_, TX* outw) {
+        const double eps2 = p.eps * p.eps;
+        RowWeighting gw;
+        gw.nu_a = nu_ + oGX;
+        gw.m_a = outw + oGX;
+        gw.nu_b = nu_ + oGY;
+        gw.m_b = outw + oGY;
+        gw.eps2 = eps2;
+        launch_grad_fwd(c, g, dt, in, nullptr, nullptr, out + oGX, out + oGY, -1, &gw);
+        if (flow) {
+            RowWeighting fw;
+            fw.nu_a = nu_ + oRF;
+            fw.m_a = outw + oRF;
+            fw.eps2 = eps2;
+            launch_flow_fwd(c, g, dt, +1, p.interp, in, flow_v, out + oRF, -1, &fw);
+            if (p.use_reverse) {
+                RowWeighting rw;
+                rw.nu_a = nu_ + oRR;
+                rw.m_a = outw + oRR;
+                rw.eps2 = eps2;
+                launch_flow_fwd(c, g, dt, -1, p.interp, in, flow_vr, out + oRR, -1, &rw);
+            }
+            if (rep) rep->n_L += p.use_reverse ? 2 : 1;
+        }
+        if (rep) rep->n_theta++;
+    }
     void thetaT(const TX* in, TX* out) {
         launch_grad_adj(c, g, dt, in + oGX, in + oGY, nullptr, nullptr, out, false);
         if (tdiff) launch_tdiff(c, g, dt, true, in + oTD, out, true);
@@ -580,11 +609,15 @@ struct Solver {
                        std::to_string(reinterpret_cast<uintptr_t>(wsrc));
                 replayable(key, [&] {
                     At(vin_m, out_n);
-                    theta(u_op, yR);
-                    if (wsrc)
-                        weight_mul_nu<TX>(c, R, wsrc, p.eps, yR, yW);
-                    else
-                        weight_mul<TX>(c, R, w2, yR, yW);
+                    if (wsrc && !tdiff) {
+                        theta_weighted(u_op, yR, wsrc, yW);
+                    } else {
+                        theta(u_op, yR);
+                        if (wsrc)
+                            weight_mul_nu<TX>(c, R, wsrc, p.eps, yR, yW);
+                        else
+                            weight_mul<TX>(c, R, w2, yR, yW);
+                    }
                     thetaT(yW, out_n2);
                     residual_combine<TX>(c, n, out_n, out_n2, res, r);
                 });
