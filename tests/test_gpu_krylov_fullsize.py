@@ -106,3 +106,36 @@ def test_cgs2_at_basis_length(B):
     assert np.abs(h2).max() <= 1e-13 * np.sqrt(sq)
     del Q, x
     torch.cuda.empty_cache()
+
+
+def test_block_dot_ragged_length_all_columns(B):
+    """A length just past 2^26 (odd): the inner products then use their largest number of row
+    chunks (8192) of 8194 rows with a short last chunk of odd length, and 21 columns take three
+    column groups (8, 8, 5) on the one-dimensional grid; every column is checked, and the
+    column combination at rows around the chunk seams and the end."""
+    import torch
+    n = N_PIX + 12345
+    k = 21
+    g = torch.Generator(device="cuda").manual_seed(11)
+    print(f"block dot ragged: {k} x {n} FP64", flush=True)
+    V = torch.randn((k, n), generator=g, device="cuda", dtype=torch.float64)
+    y = torch.randn(n, generator=g, device="cuda", dtype=torch.float64)
+    z = torch.randn(k, generator=g, device="cuda", dtype=torch.float64)
+    d = B.block_dot(V, y).cpu().numpy()
+    yh = y.cpu().numpy()
+    for j in range(k):
+        vj = V[j].cpu().numpy()
+        exp = float(np.dot(vj, yh))
+        assert abs(d[j] - exp) <= 1e-12 * float(np.dot(np.abs(vj), np.abs(yh))), j
+    u = B.block_combine(V, z)
+    chunk = 8194
+    seams = [c * chunk + o for c in (1, 4095, 8190, 8191) for o in (-1, 0, 1)]
+    rows = np.array(sorted(set(seams + [0, n // 2, n - 3, n - 2, n - 1])))
+    idx = torch.as_tensor(rows, device="cuda")
+    Vs = V[:, idx].cpu().numpy()
+    zh = z.cpu().numpy()
+    exp = zh @ Vs
+    got = u[idx].cpu().numpy()
+    assert np.all(np.abs(got - exp) <= 1e-13 * (np.abs(zh) @ np.abs(Vs)))
+    del V, y, u
+    torch.cuda.empty_cache()
