@@ -296,7 +296,9 @@ constexpr int ADJ_SLOTS = 4;
 template <class T, int INTERP, int ATX, int ATY>
 __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ tiles, const T* __restrict__ r,
                                                   const T* __restrict__ v, T* __restrict__ u, int direction,
-                                                  int accumulate, const int32_t* __restrict__ d_radius) {
+                                                  int accumulate, const int32_t* __restrict__ d_radius,
+                                                  const T* __restrict__ cx, const double* __restrict__ clam,
+                                                  double* __restrict__ cout) {
     constexpr int RPT = ATX * ATY / 256;
     constexpr int SMAX = (ATX + 2 * RMAX) * (ATY + 2 * RMAX);  // source window (raster rank < 2^16)
     constexpr int CW = ATX + 1, NC = (ATX + 1) * (ATY + 1);     // cells touching the tile
@@ -470,12 +472,19 @@ __global__ __launch_bounds__(256) void k_flow_adj(const AdjTile* __restrict__ ti
         }
     }
     if (!col_in) return;
+    // cout (may be null): instead of u, the residual cout = cx + lambda u (ResidualOut)
+    const double lam = cout ? clam[0] : 0.0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int qy = qy0 + k;
         if (qy >= ny) break;
         const T val = acc[k] + direct[k];
-        u[tl.off + (int64_t)qy * nx + qx] = accumulate ? old[k] + val : val;
+        const T out = accumulate ? old[k] + val : val;
+        const int64_t o = tl.off + (int64_t)qy * nx + qx;
+        if (cout)
+            cout[o] = (double)cx[o] + lam * (double)out;
+        else
+            u[o] = out;
     }
 }
 
@@ -705,7 +714,7 @@ void launch_flow_fwd_cols(Ctx& c, Geom& g, int dt, int interp, const void* Uv, b
 }
 
 void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const void* r, const void* v, void* u,
-                     bool accumulate, const int32_t* d_radius, int choice) {
+                     bool accumulate, const int32_t* d_radius, int choice, const ResidualOut* res) {
     int32_t* rad = const_cast<int32_t*>(d_radius);
     if (!rad) {
         rad = static_cast<int32_t*>(c.work("flow_radius", 256));
@@ -720,7 +729,9 @@ void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const v
         ScopedTime st(&c, "flow_adj", 5.0 * sizeof(T) * g.pair_px, 12.0 * g.pair_px);
         auto k = interp == MMOF_INTERP_ROUND ? flow_adj_kernel<T, 1>(choice) : flow_adj_kernel<T, 0>(choice);
         hipLaunchKernelGGL(k, dim3((unsigned)tl.count), dim3(256), 0, c.stream, tl.buf.as<AdjTile>(), (const T*)r,
-                           (const T*)v, (T*)u, direction, accumulate ? 1 : 0, rad);
+                           (const T*)v, (T*)u, direction, accumulate ? 1 : 0, rad,
+                           res ? (const T*)res->x : (const T*)nullptr, res ? res->lam : nullptr,
+                           res ? res->out : nullptr);
         MMOF_LAUNCH_CHECK();
     });
 }

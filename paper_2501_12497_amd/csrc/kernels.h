@@ -35,9 +35,18 @@ void launch_grad_adj(Ctx& c, Geom& g, int dt, const void* gx, const void* gy, co
 // L(v) = -M-bar (direction +1) / -M-bar' (direction -1) and relatives.
 void launch_flow_fwd(Ctx& c, Geom& g, int dt, int direction, int interp, const void* u, const void* v, void* r,
                      int choice = -1, const RowWeighting* rw = nullptr);
+// The residual formed where the last Theta^T kernel writes its output: instead of u, the kernel
+// writes out = x + lambda u in FP64 (x in the operator precision, lambda on the device), the
+// arithmetic of the separate combination pass.
+struct ResidualOut {
+    const void* x = nullptr;
+    const double* lam = nullptr;
+    double* out = nullptr;
+};
+// res (may be null): write the residual instead of u (ResidualOut).
 void launch_flow_adj(Ctx& c, Geom& g, int dt, int direction, int interp, const void* r, const void* v, void* u,
                      bool accumulate, const int32_t* d_radius /* device int: floor(max|v|)+1, or null */,
-                     int choice = -1);
+                     int choice = -1, const ResidualOut* res = nullptr);
 // Forward (v) and, when vr is not null, reverse (vr) flow rows of Theta for K columns U (FP64,
 // or in the operator precision of dt when u_op; leading dimension ldu) in one launch:
 // out[j*ldo + oF ...] and out[j*ldo + oR ...], dtype dt.  Both forms give the same values.

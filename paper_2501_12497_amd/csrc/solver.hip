@@ -255,15 +255,21 @@ struct Solver {
         }
         if (rep) rep->n_theta++;
     }
-    void thetaT(const TX* in, TX* out) {
+    // out = Theta^T in; with res (only when flows are on: the last flow adjoint forms it), the
+    // residual res->out = res->x + lambda out instead of out.  Returns whether it was formed.
+    bool thetaT(const TX* in, TX* out, const ResidualOut* res = nullptr) {
         launch_grad_adj(c, g, dt, in + oGX, in + oGY, nullptr, nullptr, out, false);
         if (tdiff) launch_tdiff(c, g, dt, true, in + oTD, out, true);
+        bool formed = false;
         if (flow) {
-            launch_flow_adj(c, g, dt, +1, p.interp, in + oRF, flow_v, out, true, rad_v);
-            if (p.use_reverse) launch_flow_adj(c, g, dt, -1, p.interp, in + oRR, flow_vr, out, true, rad_vr);
+            launch_flow_adj(c, g, dt, +1, p.interp, in + oRF, flow_v, out, true, rad_v, -1,
+                            p.use_reverse ? nullptr : res);
+            if (p.use_reverse) launch_flow_adj(c, g, dt, -1, p.interp, in + oRR, flow_vr, out, true, rad_vr, -1, res);
             if (rep) rep->n_L += p.use_reverse ? 2 : 1;
+            formed = res != nullptr;
         }
         if (rep) rep->n_thetaT++;
+        return formed;
     }
 
     // FP64 MM weights of the rows of Theta u: per row, then per group for IsoTV and GS.  Per-row
@@ -618,8 +624,11 @@ struct Solver {
                         else
                             weight_mul<TX>(c, R, w2, yR, yW);
                     }
-                    thetaT(yW, out_n2);
-                    residual_combine<TX>(c, n, out_n, out_n2, res, r);
+                    ResidualOut ro;
+                    ro.x = out_n;
+                    ro.lam = res;
+                    ro.out = r;
+                    if (!thetaT(yW, out_n2, &ro)) residual_combine<TX>(c, n, out_n, out_n2, res, r);
                 });
                 // 8. r against the basis, ||r'||^2
                 extend(K, scal + 7);
