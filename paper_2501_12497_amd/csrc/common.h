@@ -215,6 +215,7 @@ struct Plan {
     DeviceBuffer d_rays[4];         // ray tiles of the forward projector (angle groups 1, 2, 4, 8)
     DeviceBuffer d_tiles_a;         // pixel tiles of the back-projector
     DeviceBuffer d_tiles_b;         // 32x32 tiles of the frame transpose
+    bool tr_vec = false;            // every frame side and offset a multiple of 4 (vector transpose)
     int64_t n_rays[4] = {0, 0, 0, 0}, n_tiles_a = 0, n_tiles_b = 0;
     // fan beam: source-to-centre and source-to-detector distances, bin width (pixel units)
     double fan_dso = 0.0, fan_dsd = 0.0, fan_du = 0.0;

@@ -48,6 +48,42 @@ __global__ __launch_bounds__(256) void k_transpose_frames(const Tile* __restrict
     }
 }
 
+// The same transpose with 16-byte accesses, for stacks whose frame sides and offsets are all
+// multiples of 4 (Plan::tr_vec): a tile row is 32 / VEC vectors of VEC = 16 / sizeof(T) pixels,
+// and each thread reads one (FP32) or two (FP64) of them and writes as many of the transposed
+// tile.
+template <class T>
+__global__ __launch_bounds__(256) void k_transpose_frames4(const Tile* __restrict__ tiles,
+                                                           const RadonFrame* __restrict__ rf,
+                                                           const T* __restrict__ u, T* __restrict__ ut) {
+    constexpr int VEC = 16 / (int)sizeof(T);      // 4 FP32 or 2 FP64 pixels per access
+    constexpr int VPR = 32 / VEC;                  // vectors per tile row
+    typedef T VT __attribute__((ext_vector_type(VEC)));
+    __shared__ T s[32][33];
+    const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const RadonFrame f = rf[tl.frame];
+    for (int i = threadIdx.x; i < 32 * VPR; i += 256) {
+        const int r = i / VPR, c = VEC * (i % VPR);
+        const int y = tl.y0 + r, x = tl.x0 + c;
+        if (y < f.ny && x < f.nx) {   // (x < nx implies x + VEC - 1 < nx: nx is a multiple of 4)
+            const VT q = *reinterpret_cast<const VT*>(u + f.u_off + (int64_t)y * f.nx + x);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) s[r][c + e] = q[e];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 32 * VPR; i += 256) {
+        const int xr = i / VPR, c = VEC * (i % VPR);   // output row (x) and its first y
+        const int x = tl.x0 + xr, y = tl.y0 + c;
+        if (x < f.nx && y < f.ny) {
+            VT q;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q[e] = s[c + e][xr];
+            *reinterpret_cast<VT*>(ut + f.u_off + (int64_t)x * f.ny + y) = q;
+        }
+    }
+}
+
 // Sum over the (at most three) pixels of one row (the row starting at offset roff of the
 // frame img) with non-zero hat weight for a ray whose centre crosses the row at xs: weights 1 - |a| |x - xs| with |a| >= 1/sqrt(2), so the
 // pixels are floor(xs) - 1 .. floor(xs) + 1 when the fraction is below 1/2, else
@@ -364,10 +400,12 @@ void radon_plan_init(Ctx& c, Plan& p, const double* cs) {
     std::vector<RayTile> rays[4];  // angle groups of 1, 2, 4, 8
     std::vector<Tile> px, tr;
     int64_t sino = 0, trig = 0;
+    p.tr_vec = true;
     for (int64_t fi = 0; fi < g.n_frames; ++fi) {
         const FrameInfo& fr = g.frames[fi];
         // the projectors address pixels by 32-bit offsets within a frame
         MMOF_CHECK((int64_t)fr.ny * fr.nx < ((int64_t)1 << 31), MMOF_ERR_SHAPE, "frames must have fewer than 2^31 pixels");
+        if (fr.nx % 4 != 0 || fr.ny % 4 != 0 || fr.off % 4 != 0) p.tr_vec = false;
         RadonFrame r{};
         r.u_off = fr.off;
         r.sino_off = sino;
@@ -669,14 +707,24 @@ void fan_plan_init(Ctx& c, Plan& p) {
     MMOF_HIP(hipStreamSynchronize(c.stream));
 }
 
+// ut = the per-frame transpose of u (16-byte accesses when the stack allows them)
+template <class T>
+static void launch_transpose(Ctx& c, Plan& p, const T* u, T* ut) {
+    if (p.tr_vec && aligned_to(16, {u, ut}))
+        hipLaunchKernelGGL(k_transpose_frames4<T>, dim3((unsigned)p.n_tiles_b), dim3(256), 0, c.stream,
+                           p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), u, ut);
+    else
+        hipLaunchKernelGGL(k_transpose_frames<T>, dim3((unsigned)p.n_tiles_b), dim3(256), 0, c.stream,
+                           p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), u, ut);
+    MMOF_LAUNCH_CHECK();
+}
+
 void launch_fan_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b) {
     if (p.n_rays[2] == 0) return;
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         T* ut = static_cast<T*>(c.work("radon_transpose", sizeof(T) * p.n));
-        hipLaunchKernelGGL(k_transpose_frames<T>, dim3((unsigned)p.n_tiles_b), dim3(256), 0, c.stream,
-                           p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), (const T*)u, ut);
-        MMOF_LAUNCH_CHECK();
+        launch_transpose<T>(c, p, (const T*)u, ut);
         ScopedTime st(&c, "fan_fwd", (double)sizeof(T) * (p.n + p.m), 0.0);
         hipLaunchKernelGGL(k_fan_fwd<T>, dim3((unsigned)p.n_rays[2]), dim3(256), 0, c.stream,
                            p.d_rays[2].as<RayTile>(), p.d_rinfo.as<RadonFrame>(), p.d_fanrays.as<double4>(),
@@ -738,9 +786,7 @@ void launch_radon_fwd(Ctx& c, Plan& p, int dt, const void* u, void* b, int choic
     dispatch(dt, [&](auto z) {
         using T = decltype(z);
         T* ut = static_cast<T*>(c.work("radon_transpose", sizeof(T) * p.n));
-        hipLaunchKernelGGL(k_transpose_frames<T>, dim3((unsigned)p.n_tiles_b), dim3(256), 0, c.stream,
-                           p.d_tiles_b.as<Tile>(), p.d_rinfo.as<RadonFrame>(), (const T*)u, ut);
-        MMOF_LAUNCH_CHECK();
+        launch_transpose<T>(c, p, (const T*)u, ut);
         ScopedTime st(&c, "radon_fwd", (double)sizeof(T) * (p.n + p.m), p.radon_flops);
         auto k = choice == 0 ? k_radon_fwd<T, 1> : choice == 1 ? k_radon_fwd<T, 2> : choice == 2 ? k_radon_fwd<T, 4>
                                                                                                  : k_radon_fwd<T, 8>;
