@@ -103,6 +103,28 @@ def test_radon_forward_wide_frames(B, which, cand):
     assert_close(b, exp, tol, scale)
 
 
+@pytest.mark.parametrize("which", ["f64", "f32"])
+def test_radon_forward_frames_of_quarter_widths(B, which):
+    """Frames whose sides are multiples of 4 but not of 32 (100 x 68 and 36 x 132, offsets then
+    multiples of 4 too): the frame transpose takes its vector form on tiles the frame edges cut;
+    steep and flat angles, against the oracle element by element."""
+    import torch
+    dt, tol = (torch.float64, TOL64) if which == "f64" else (torch.float32, TOL32)
+    r = np.random.default_rng(15)
+    sizes = [(3, 100, 68), (2, 36, 132)]
+    us = [r.uniform(0.0, 1.0, (nt, ny, nx)) for nt, ny, nx in sizes]
+    base = np.array([0.0, 0.25, 0.5, 0.75]) * math.pi
+    angs = [np.stack([np.concatenate([base, r.uniform(0, math.pi, 3)]) for _ in range(s[0])]) for s in sizes]
+    nbins = [bins_for(100), bins_for(132)]
+    plan = B.plan_radon(B.Stack(sizes), [7, 7], nbins, np.concatenate([a.ravel() for a in angs]))
+    if dt == torch.float32:
+        us = [roundtrip32(u) for u in us]
+    b = host(B.apply_A(plan, dev(pack(us), dt)))
+    exp = pack([forward.radon_fwd(u, a, nb) for u, a, nb in zip(us, angs, nbins)])
+    scale = pack([forward.radon_fwd(np.abs(u), a, nb) for u, a, nb in zip(us, angs, nbins)])
+    assert_close(b, exp, tol, scale)
+
+
 def test_radon_adjoint_identity_fp64(B):
     import torch
     r = np.random.default_rng(12)
